@@ -1,0 +1,86 @@
+"""CPU oracle for one-ring neighbor finding -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It wraps ``oracle.c`` (the plain serial definition of
+Sec. 1 and Sec. 3.2.2 of the paper, one ordered set per vertex) through
+ctypes, and shares no code with the HIP library.
+
+``node_neighbors`` / ``elem_neighbors`` take a host int32 connectivity array
+``[n_elem, npe]``, the element type code (0 tri3, 1 tet4, 2 hex8) and the
+vertex count, and return ``(row_ptr, cols)`` as int32 numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_NPE = {0: 3, 1: 4, 2: 8}
+_EDGES_PER_ELEM = {0: 3, 1: 6, 2: 12}
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so next to it (plain gcc, -O2)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
+                        _SRC, "-o", tmp], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        for name in ("oracle_node_neighbors", "oracle_elem_neighbors"):
+            fn = getattr(lib, name)
+            fn.restype = ctypes.c_int64
+            fn.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+        _lib = lib
+    return _lib
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+_ERRORS = {-1: "invalid argument", -2: "vertex id out of range", -3: "capacity", -4: "out of memory"}
+
+
+def _run(fn_name, conn, etype, n_vert, cap_per_elem):
+    conn = np.ascontiguousarray(np.asarray(conn, dtype=np.int32))
+    npe = _NPE.get(int(etype))
+    if npe is None:
+        raise OracleError("invalid argument")
+    conn = conn.reshape(-1, npe)
+    n_elem = conn.shape[0]
+    cap = max(1, cap_per_elem * n_elem)
+    row_ptr = np.zeros(n_vert + 1, dtype=np.int32)
+    cols = np.empty(cap, dtype=np.int32)
+    r = getattr(_load(), fn_name)(conn.ctypes.data, n_elem, int(etype), int(n_vert),
+                                  row_ptr.ctypes.data, cols.ctypes.data, cap)
+    if r < 0:
+        raise OracleError(_ERRORS.get(int(r), str(r)))
+    return row_ptr, cols[:r].copy()
+
+
+def node_neighbors(conn, etype: int, n_vert: int):
+    """One-ring neighboring nodes of every vertex as (row_ptr, cols)."""
+    return _run("oracle_node_neighbors", conn, etype, n_vert, 2 * _EDGES_PER_ELEM.get(int(etype), 0))
+
+
+def elem_neighbors(conn, etype: int, n_vert: int):
+    """One-ring neighboring elements of every vertex as (row_ptr, cols)."""
+    return _run("oracle_elem_neighbors", conn, etype, n_vert, _NPE.get(int(etype), 0))

@@ -1,0 +1,208 @@
+"""Pins of the CPU oracle against values fixed by the paper's definition and by
+mathematics: hand-worked cases, brute force, a library route, closed forms,
+lattice rows and invariants.  CPU only."""
+import numpy as np
+import pytest
+
+from paper_1604_04689_amd import meshgen as mg
+from tests import pins
+
+
+def _eq(a, b):
+    return np.array_equal(np.asarray(a), np.asarray(b))
+
+
+@pytest.mark.parametrize("case", pins.read_golden(), ids=lambda c: c["name"])
+def test_golden_hand_cases(oracle_mod, case):
+    conn = case["conn"].reshape(-1, pins.NPE[case["etype"]])
+    nr, nc = oracle_mod.node_neighbors(conn, case["etype"], case["n_vert"])
+    er, ec = oracle_mod.elem_neighbors(conn, case["etype"], case["n_vert"])
+    assert _eq(nr, case["node_row_ptr"]) and _eq(nc, case["node_cols"])
+    assert _eq(er, case["elem_row_ptr"]) and _eq(ec, case["elem_cols"])
+
+
+def test_golden_cases_agree_with_brute_force():
+    # the fixtures themselves are re-derived by the independent brute force
+    for case in pins.read_golden():
+        conn = case["conn"].reshape(-1, pins.NPE[case["etype"]])
+        (nr, nc), (er, ec) = pins.brute_force(conn, case["etype"], case["n_vert"])
+        assert _eq(nr, case["node_row_ptr"]) and _eq(nc, case["node_cols"]), case["name"]
+        assert _eq(er, case["elem_row_ptr"]) and _eq(ec, case["elem_cols"]), case["name"]
+
+
+def test_hex_edge_pairs_from_geometry():
+    # the 12 cube edges: 4 per axis
+    pairs = pins.edge_pairs(2)
+    assert len(pairs) == 12
+    assert len(pins.edge_pairs(1)) == 6 and len(pins.edge_pairs(0)) == 3
+
+
+@pytest.mark.parametrize("etype", [0, 1, 2])
+@pytest.mark.parametrize("seed", range(6))
+def test_random_meshes_vs_brute_force(oracle_mod, etype, seed):
+    rng = np.random.default_rng(1000 + seed)
+    n_vert = int(rng.integers(1, 25))
+    n_elem = int(rng.integers(0, 30))
+    m = mg.random_mesh(n_elem, n_vert, etype, seed=seed)
+    (bnr, bnc), (ber, bec) = pins.brute_force(m.conn, etype, n_vert)
+    nr, nc = oracle_mod.node_neighbors(m.conn, etype, n_vert)
+    er, ec = oracle_mod.elem_neighbors(m.conn, etype, n_vert)
+    assert _eq(nr, bnr) and _eq(nc, bnc)
+    assert _eq(er, ber) and _eq(ec, bec)
+
+
+@pytest.mark.parametrize("etype", [0, 1, 2])
+@pytest.mark.parametrize("seed", range(4))
+def test_random_meshes_vs_scipy(oracle_mod, etype, seed):
+    rng = np.random.default_rng(2000 + seed)
+    n_vert = int(rng.integers(1, 3000))
+    n_elem = int(rng.integers(0, 6000))
+    m = mg.random_mesh(n_elem, n_vert, etype, seed=seed)
+    (snr, snc), (ser, sec) = pins.scipy_csr(m.conn, etype, n_vert)
+    nr, nc = oracle_mod.node_neighbors(m.conn, etype, n_vert)
+    er, ec = oracle_mod.elem_neighbors(m.conn, etype, n_vert)
+    assert _eq(nr, snr) and _eq(nc, snc)
+    assert _eq(er, ser) and _eq(ec, sec)
+
+
+def test_structured_meshes_vs_scipy(oracle_mod):
+    for m in (mg.tri_grid(40, "coin", 5), mg.kuhn_tet_grid(7, 6), mg.hex_grid(6, 7)):
+        (snr, snc), (ser, sec) = pins.scipy_csr(m.conn, m.etype, m.n_vert)
+        nr, nc = oracle_mod.node_neighbors(m.conn, m.etype, m.n_vert)
+        er, ec = oracle_mod.elem_neighbors(m.conn, m.etype, m.n_vert)
+        assert _eq(nr, snr) and _eq(nc, snc), m.name
+        assert _eq(er, ser) and _eq(ec, sec), m.name
+
+
+# ---- closed forms ----------------------------------------------------------
+
+def test_tri64_closed_forms(oracle_mod):
+    m = mg.tri64()
+    assert (m.n_elem, m.n_vert) == (7938, 4096)
+    nr, nc = oracle_mod.node_neighbors(m.conn, m.etype, m.n_vert)
+    er, ec = oracle_mod.elem_neighbors(m.conn, m.etype, m.n_vert)
+    assert nc.shape[0] == 2 * pins.tri_grid_edge_count(64) == 24066
+    assert ec.shape[0] == 3 * 7938 == 23814
+    nd = np.bincount(np.diff(nr))
+    ed = np.bincount(np.diff(er))
+    # interior 62^2 vertices: 6 and 6; edge vertices 4 and 3; the two corners
+    # on the diagonal 3 and 2; the two off-diagonal corners 2 and 1
+    assert dict((k, v) for k, v in enumerate(nd) if v) == {6: 3844, 4: 248, 3: 2, 2: 2}
+    assert dict((k, v) for k, v in enumerate(ed) if v) == {6: 3844, 3: 248, 2: 2, 1: 2}
+
+
+@pytest.mark.parametrize("n", [2, 3, 17, 96])
+def test_tri_main_lattice_rows(oracle_mod, n):
+    m = mg.tri_grid(n, "main", seed=n)
+    er = pins.lattice_node_csr(m.dims, pins.TRI_MAIN_STEPS, m.perm)
+    nr, nc = oracle_mod.node_neighbors(m.conn, m.etype, m.n_vert)
+    assert _eq(nr, er[0]) and _eq(nc, er[1])
+
+
+@pytest.mark.parametrize("m_cells", [1, 2, 5, 12])
+def test_kuhn_lattice_rows(oracle_mod, m_cells):
+    m = mg.kuhn_tet_grid(m_cells, seed=m_cells)
+    er = pins.lattice_node_csr(m.dims, pins.KUHN_STEPS, m.perm)
+    nr, nc = oracle_mod.node_neighbors(m.conn, m.etype, m.n_vert)
+    assert _eq(nr, er[0]) and _eq(nc, er[1])
+    assert nc.shape[0] == 2 * pins.kuhn_edge_count(m_cells)
+    er_, ec_ = oracle_mod.elem_neighbors(m.conn, m.etype, m.n_vert)
+    assert ec_.shape[0] == 24 * m_cells ** 3
+    # interior vertices: 14 node and 24 element neighbors
+    s = m_cells + 1
+    coords = np.stack(np.unravel_index(np.arange(s ** 3), (s, s, s)), 1)
+    interior = np.all((coords > 0) & (coords < m_cells), axis=1)
+    ids = m.perm[interior]
+    assert np.all(np.diff(nr)[ids] == 14)
+    assert np.all(np.diff(er_)[ids] == 24)
+
+
+@pytest.mark.parametrize("m_cells", [1, 3, 8])
+def test_hex_lattice_rows(oracle_mod, m_cells):
+    m = mg.hex_grid(m_cells, seed=m_cells)
+    er = pins.lattice_node_csr(m.dims, pins.HEX_STEPS, m.perm)
+    nr, nc = oracle_mod.node_neighbors(m.conn, m.etype, m.n_vert)
+    assert _eq(nr, er[0]) and _eq(nc, er[1])
+    assert nc.shape[0] == 2 * pins.hex_edge_count(m_cells)
+    _, ec = oracle_mod.elem_neighbors(m.conn, m.etype, m.n_vert)
+    assert ec.shape[0] == 8 * m_cells ** 3
+
+
+@pytest.mark.parametrize("n", [5, 64, 300])
+def test_coin_grid_euler_and_degrees(oracle_mod, n):
+    # a triangulated disk: V - E + F = 1, so node nnz = 2E = 2(V + F - 1);
+    # interior vertices have as many node as element neighbors, boundary
+    # vertices one more node neighbor than element neighbors
+    m = mg.tri_grid(n, "coin", seed=n)
+    nr, nc = oracle_mod.node_neighbors(m.conn, m.etype, m.n_vert)
+    er, ec = oracle_mod.elem_neighbors(m.conn, m.etype, m.n_vert)
+    assert nc.shape[0] == 2 * (m.n_vert + m.n_elem - 1)
+    coords = np.stack(np.unravel_index(np.arange(n * n), (n, n)), 1)
+    interior = np.all((coords > 0) & (coords < n - 1), axis=1)
+    dn = np.diff(nr)[m.perm]
+    de = np.diff(er)[m.perm]
+    assert np.all(dn[interior] == de[interior])
+    assert np.all((dn[interior] >= 4) & (dn[interior] <= 8))
+    assert np.all(dn[~interior] == de[~interior] + 1)
+
+
+# ---- invariants ------------------------------------------------------------
+
+@pytest.mark.parametrize("etype,maker", [(0, lambda: mg.tri_grid(33, "coin", 3)),
+                                         (1, lambda: mg.kuhn_tet_grid(5, 4)),
+                                         (2, lambda: mg.hex_grid(5, 5)),
+                                         (1, lambda: mg.random_mesh(500, 120, 1, 9))])
+def test_invariants(oracle_mod, etype, maker):
+    m = maker()
+    nr, nc = oracle_mod.node_neighbors(m.conn, etype, m.n_vert)
+    er, ec = oracle_mod.elem_neighbors(m.conn, etype, m.n_vert)
+    pins.check_csr_shape(nr, nc, m.n_vert)
+    pins.check_csr_shape(er, ec, m.n_vert)
+    assert pins.rows_strictly_increasing(nr, nc)
+    assert pins.rows_strictly_increasing(er, ec)
+    assert pins.is_symmetric(nr, nc)
+    rid = pins.row_ids(nr)
+    assert not np.any(rid == nc)  # no self pairs
+    # e in R(v)  <=>  v in conn[e]
+    rid_e = pins.row_ids(er)
+    a = set(zip(rid_e.tolist(), ec.tolist()))
+    b = set((int(v), e) for e in range(m.n_elem) for v in m.conn[e])
+    assert a == b
+    if etype in (0, 1):
+        # simplices: N(v) = union of the nodes of R(v), minus v
+        for v in range(0, m.n_vert, max(1, m.n_vert // 50)):
+            nb = set(m.conn[ec[er[v]:er[v + 1]]].ravel().tolist()) - {v}
+            assert nb == set(nc[nr[v]:nr[v + 1]].tolist())
+
+
+def test_vertex_permutation_equivariance(oracle_mod):
+    m = mg.random_mesh(400, 150, 1, 21)
+    pi = np.random.default_rng(5).permutation(m.n_vert).astype(np.int32)
+    nr, nc = oracle_mod.node_neighbors(m.conn, 1, m.n_vert)
+    pr, pc = oracle_mod.node_neighbors(pi[m.conn], 1, m.n_vert)
+    for v in range(m.n_vert):
+        got = pc[pr[pi[v]]:pr[pi[v] + 1]]
+        assert np.array_equal(got, np.sort(pi[nc[nr[v]:nr[v + 1]]]))
+
+
+def test_element_shuffle(oracle_mod):
+    m = mg.kuhn_tet_grid(4, 1)
+    sig = np.random.default_rng(6).permutation(m.n_elem)
+    nr, nc = oracle_mod.node_neighbors(m.conn, 1, m.n_vert)
+    sr, sc = oracle_mod.node_neighbors(m.conn[sig], 1, m.n_vert)
+    assert _eq(nr, sr) and _eq(nc, sc)
+    er, ec = oracle_mod.elem_neighbors(m.conn, 1, m.n_vert)
+    tr, tc = oracle_mod.elem_neighbors(m.conn[sig], 1, m.n_vert)
+    inv = np.argsort(sig)  # old row e is new row inv[e]
+    assert _eq(er, tr)
+    for v in range(m.n_vert):
+        assert np.array_equal(tc[tr[v]:tr[v + 1]], np.sort(inv[ec[er[v]:er[v + 1]]]))
+
+
+def test_errors(oracle_mod):
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.node_neighbors(np.array([[0, 1, 5]]), 0, 3)
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.elem_neighbors(np.array([[0, -1, 2]]), 0, 3)
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.node_neighbors(np.array([[0, 1, 2]]), 7, 3)
