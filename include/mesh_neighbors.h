@@ -1,0 +1,127 @@
+/*
+ * mesh_neighbors.h -- C ABI of the one-ring neighbor library (libmeshnbr.so).
+ *
+ * For every vertex of a mesh given as plain integer connectivity, the library
+ * finds its one-ring neighboring nodes (vertices joined to it by an element
+ * edge) and its one-ring neighboring elements (elements that contain it), as
+ * defined in Sec. 1 of Mei et al., "A Parallel Solution to Finding Nodal
+ * Neighbors in Generic Meshes", and returns each relation as a CSR matrix with
+ * ascending, duplicate-free rows.  The method follows Sec. 2: form integer
+ * pairs per element, sort them by their first entry, then derive counts and
+ * first indices per vertex by segmented reduction and scan.  Everything runs
+ * in HIP kernels on the device; inputs and outputs stay in device memory.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Ids are 0-based.  Element e is row e of the connectivity array, which is
+ *    int32, row-major [n_elem][nodes_per_element].
+ *  - Element types and their edges (pairs of node positions):
+ *      MESH_TRI3 (3 nodes): (0,1) (1,2) (2,0)
+ *      MESH_TET4 (4 nodes): all 6 pairs
+ *      MESH_HEX8 (8 nodes, VTK order: 0-1-2-3 bottom face, 4-7 the nodes
+ *                 above them): (0,1)(1,2)(2,3)(3,0)(4,5)(5,6)(6,7)(7,4)
+ *                 (0,4)(1,5)(2,6)(3,7); face and body diagonals are not edges.
+ *  - Output CSR: row_ptr is int32 [n_vert + 1], row_ptr[0] = 0, and the
+ *    neighbors of v are cols[row_ptr[v] .. row_ptr[v+1]) in ascending order.
+ *    A vertex is never its own neighbor; a repeated id inside one element
+ *    (a degenerate element) yields no self pair and lists that element once.
+ *    Vertices used by no element get empty rows.  nnz = row_ptr[n_vert].
+ *  - Every data pointer (conn, row_ptr, cols, workspace and the batched
+ *    descriptor arrays) is a DEVICE pointer owned by the caller; the library
+ *    allocates nothing and keeps no state between calls.  `stream` is a
+ *    hipStream_t (NULL = the null stream).  Calls are asynchronous and
+ *    stream-ordered; none synchronises the host except mesh_check.
+ *  - Argument errors are returned synchronously before anything is launched.
+ *    Data errors found on the device (a vertex id outside [0, n_vert), more
+ *    nnz than cols_capacity) are recorded in the workspace: the output is then
+ *    unspecified but every access stays in bounds, and mesh_check reports it.
+ *  - Two calls may run concurrently only with distinct workspaces.
+ */
+#ifndef MESH_NEIGHBORS_H
+#define MESH_NEIGHBORS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { MESH_TRI3 = 0, MESH_TET4 = 1, MESH_HEX8 = 2 } mesh_elem_type;
+
+typedef enum {
+    MESH_OK = 0,
+    MESH_ERR_INVALID_ARG = 1,      /* null pointer, negative size, ...          */
+    MESH_ERR_UNSUPPORTED_TYPE = 2, /* element type code not listed above        */
+    MESH_ERR_WORKSPACE = 3,        /* workspace smaller than the query says     */
+    MESH_ERR_CAPACITY = 4,         /* nnz exceeded cols_capacity (device check) */
+    MESH_ERR_OVERFLOW = 5,         /* sizes beyond the int32 / pair-count range */
+    MESH_ERR_INDEX_RANGE = 6,      /* a connectivity id outside [0, n_vert)     */
+    MESH_ERR_HIP = 7,              /* a HIP runtime call or launch failed        */
+    MESH_ERR_INTERNAL = 8          /* a device-side consistency guard tripped    */
+} mesh_status;
+
+/* ------------------------------------------------------------------------ */
+/* Neighboring nodes (Sec. 2.1.1, 2.2.1).                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Workspace size and a cols capacity that always suffices for
+ * mesh_node_neighbors on a mesh of n_elem elements of type etype over n_vert
+ * vertices.  The capacity is the number of directed edge pairs,
+ * 2 * edges_per_element * n_elem (every pair distinct in the worst case).
+ * Limits: n_vert <= 2^31 - 1; pairs <= 2^31 - 1 (else MESH_ERR_OVERFLOW). */
+mesh_status mesh_node_neighbors_query(int64_t n_elem, int32_t etype, int32_t n_vert,
+                                      size_t* workspace_bytes, int64_t* cols_capacity);
+
+/* One-ring neighboring nodes of every vertex.
+ *   conn           device int32 [n_elem * npe], read only
+ *   row_ptr        device int32 [n_vert + 1], written
+ *   cols           device int32 [cols_capacity], first nnz entries written
+ *   workspace      device scratch of >= the queried size (256-byte aligned);
+ *                  its first bytes carry the device error word that
+ *                  mesh_check reads, so keep it until checked.
+ * Pipeline (all on `stream`): per-element pair emission from the type's
+ * edge table as packed 64-bit keys (u << b) | w, b = bits of n_vert - 1,
+ * with per-digit histograms fused in; LSD radix sort of the keys; one pass
+ * that drops repeated keys, writes cols and scatters row starts. */
+mesh_status mesh_node_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
+                                int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
+                                void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Neighboring elements (Sec. 2.1.2, 2.2.2).                                */
+/* ------------------------------------------------------------------------ */
+
+/* Workspace size and sufficient cols capacity (npe * n_elem) for
+ * mesh_elem_neighbors.  Limits: n_elem * npe <= 2^31 - 1. */
+mesh_status mesh_elem_neighbors_query(int64_t n_elem, int32_t etype, int32_t n_vert,
+                                      size_t* workspace_bytes, int64_t* cols_capacity);
+
+/* One-ring neighboring elements of every vertex.  Same arguments as
+ * mesh_node_neighbors.  Pipeline: per-vertex counts of (vertex, element)
+ * pairs, exclusive scan to row_ptr, scatter of element ids into their rows,
+ * and an ascending sort of each row (a counting sort by vertex). */
+mesh_status mesh_elem_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
+                                int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
+                                void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics.                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* Synchronises `stream`, then returns the data error recorded in `workspace`
+ * by the last call that used it: MESH_OK, MESH_ERR_INDEX_RANGE,
+ * MESH_ERR_CAPACITY or MESH_ERR_INTERNAL (MESH_ERR_HIP if the sync fails). */
+mesh_status mesh_check(const void* workspace, void* stream);
+
+/* Static, human-readable name of a status code. */
+const char* mesh_status_string(mesh_status status);
+
+/* Library ABI version, (major << 16) | minor. */
+int32_t mesh_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MESH_NEIGHBORS_H */

@@ -1,0 +1,9 @@
+"""One-ring node and element neighbor lists of generic meshes on MI355X.
+
+The compute path is the HIP library ``libmeshnbr.so`` (C ABI in
+``include/mesh_neighbors.h``); this package holds its ctypes binding
+(``binding``), the in-tree build script (``build``) and seeded synthetic
+mesh generators (``meshgen``).
+"""
+from .binding import (HEX8, TET4, TRI3, MeshError, NeighborBuild, Status, elem_neighbors,  # noqa: F401
+                      lib, node_neighbors, query_elem, query_node, status_string)

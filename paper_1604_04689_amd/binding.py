@@ -1,0 +1,175 @@
+"""ctypes binding of libmeshnbr.so (include/mesh_neighbors.h).
+
+Argument marshalling only: every step of the neighbor pipelines runs in the
+library's HIP kernels.  PyTorch provides device memory and the stream.  If the
+library is missing this module raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import enum
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmeshnbr.so")
+
+TRI3, TET4, HEX8 = 0, 1, 2
+NODES_PER_ELEM = {TRI3: 3, TET4: 4, HEX8: 8}
+
+
+class Status(enum.IntEnum):
+    OK = 0
+    INVALID_ARG = 1
+    UNSUPPORTED_TYPE = 2
+    WORKSPACE = 3
+    CAPACITY = 4
+    OVERFLOW = 5
+    INDEX_RANGE = 6
+    HIP = 7
+    INTERNAL = 8
+
+
+class MeshError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = Status(status)
+        super().__init__(f"{where}: {status_string(status)} ({self.status.name})")
+
+
+_lib = None
+
+_c_i32, _c_i64, _c_sz, _c_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
+
+# name -> (restype, argtypes); mirrors include/mesh_neighbors.h
+SIGNATURES = {
+    "mesh_node_neighbors_query": (_c_i32, [_c_i64, _c_i32, _c_i32, ctypes.POINTER(_c_sz), ctypes.POINTER(_c_i64)]),
+    "mesh_node_neighbors": (_c_i32, [_c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64, _c_p, _c_sz, _c_p]),
+    "mesh_elem_neighbors_query": (_c_i32, [_c_i64, _c_i32, _c_i32, ctypes.POINTER(_c_sz), ctypes.POINTER(_c_i64)]),
+    "mesh_elem_neighbors": (_c_i32, [_c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64, _c_p, _c_sz, _c_p]),
+    "mesh_check": (_c_i32, [_c_p, _c_p]),
+    "mesh_status_string": (ctypes.c_char_p, [_c_i32]),
+    "mesh_abi_version": (_c_i32, []),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmeshnbr.so (built in-tree); raise if it is not there."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1604_04689_amd.build` "
+                               "(the HIP library is required; there is no CPU path)")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(h, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = h
+    return _lib
+
+
+def status_string(status) -> str:
+    return lib().mesh_status_string(int(status)).decode()
+
+
+def _query(kind, n_elem, etype, n_vert):
+    ws = _c_sz(0)
+    cap = _c_i64(0)
+    st = getattr(lib(), f"mesh_{kind}_neighbors_query")(int(n_elem), int(etype), int(n_vert),
+                                                       ctypes.byref(ws), ctypes.byref(cap))
+    if st != Status.OK:
+        raise MeshError(st, f"mesh_{kind}_neighbors_query")
+    return int(ws.value), int(cap.value)
+
+
+def query_node(n_elem, etype, n_vert):
+    """(workspace bytes, sufficient cols capacity) for the node relation."""
+    return _query("node", n_elem, etype, n_vert)
+
+
+def query_elem(n_elem, etype, n_vert):
+    """(workspace bytes, sufficient cols capacity) for the element relation."""
+    return _query("elem", n_elem, etype, n_vert)
+
+
+def _stream_handle(stream, device):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+class NeighborBuild:
+    """Device buffers for one relation ("node" or "elem") of one mesh shape.
+
+    Allocates the workspace and outputs once; ``launch`` enqueues the
+    pipeline on a stream without allocating or synchronising, ``result``
+    checks the device error word and returns ``(row_ptr, cols[:nnz])``.
+    """
+
+    def __init__(self, kind, n_elem, etype, n_vert, device="cuda", cols_capacity=None):
+        import torch
+
+        if kind not in ("node", "elem"):
+            raise ValueError(kind)
+        self.kind = kind
+        self.n_elem, self.etype, self.n_vert = int(n_elem), int(etype), int(n_vert)
+        self.device = torch.device(device)
+        ws_bytes, cap = _query(kind, n_elem, etype, n_vert)
+        self.cols_capacity = int(cap if cols_capacity is None else cols_capacity)
+        # 256-byte aligned workspace carved from a byte tensor
+        self._ws_raw = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        pad = (-self._ws_raw.data_ptr()) % 256
+        self.workspace = self._ws_raw[pad:pad + ws_bytes]
+        self.ws_bytes = ws_bytes
+        self.row_ptr = torch.empty(self.n_vert + 1, dtype=torch.int32, device=self.device)
+        self.cols = torch.empty(max(self.cols_capacity, 1), dtype=torch.int32, device=self.device)
+        self._fn = getattr(lib(), f"mesh_{kind}_neighbors")
+
+    def launch(self, conn, stream=None):
+        import torch
+
+        if conn.device != self.device or conn.dtype != torch.int32 or not conn.is_contiguous():
+            raise ValueError("conn must be a contiguous int32 tensor on the build's device")
+        npe = NODES_PER_ELEM.get(self.etype)
+        if npe is not None and conn.numel() != self.n_elem * npe:
+            raise ValueError(f"conn has {conn.numel()} ids, expected {self.n_elem} x {npe}")
+        st = self._fn(_ptr(conn), self.n_elem, self.etype, self.n_vert, _ptr(self.row_ptr),
+                      _ptr(self.cols) if self.cols_capacity > 0 else ctypes.c_void_p(0), self.cols_capacity,
+                      _ptr(self.workspace), self.ws_bytes, _stream_handle(stream, self.device))
+        if st != Status.OK:
+            raise MeshError(st, f"mesh_{self.kind}_neighbors")
+
+    def check(self, stream=None):
+        st = lib().mesh_check(_ptr(self.workspace), _stream_handle(stream, self.device))
+        if st != Status.OK:
+            raise MeshError(st, "mesh_check")
+
+    def result(self, stream=None):
+        self.check(stream)
+        nnz = int(self.row_ptr[-1].item())
+        return self.row_ptr, self.cols[:nnz]
+
+
+def _n_elem(conn, etype):
+    if conn.dim() == 2:
+        return conn.shape[0]
+    return conn.numel() // NODES_PER_ELEM.get(int(etype), 1)
+
+
+def node_neighbors(conn, etype, n_vert, stream=None):
+    """One-ring neighboring nodes of every vertex: (row_ptr, cols) on conn's device."""
+    b = NeighborBuild("node", _n_elem(conn, etype), etype, n_vert, conn.device)
+    b.launch(conn, stream)
+    return b.result(stream)
+
+
+def elem_neighbors(conn, etype, n_vert, stream=None):
+    """One-ring neighboring elements of every vertex: (row_ptr, cols) on conn's device."""
+    b = NeighborBuild("elem", _n_elem(conn, etype), etype, n_vert, conn.device)
+    b.launch(conn, stream)
+    return b.result(stream)

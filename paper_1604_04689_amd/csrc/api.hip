@@ -1,0 +1,136 @@
+// C ABI of the one-ring neighbor library: argument checks, workspace sizing
+// and dispatch to the node and element pipelines.  Declared in
+// include/mesh_neighbors.h.
+#include <climits>
+
+#include "../../include/mesh_neighbors.h"
+#include "common.hpp"
+#include "elements.hpp"
+#include "internal.hpp"
+
+namespace mnb {
+
+constexpr int FILL_BLOCK = 256;
+constexpr int FILL_GRID_MAX = 4096;
+
+__global__ __launch_bounds__(FILL_BLOCK) void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t value) {
+    for (int64_t i = (int64_t)blockIdx.x * FILL_BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * FILL_BLOCK)
+        p[i] = value;
+}
+
+static hipError_t fill_words(uint32_t* p, int64_t n, uint32_t value, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int grid = (int)tmin<int64_t>(ceil_div(n, FILL_BLOCK), FILL_GRID_MAX);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid), dim3(FILL_BLOCK), 0, s, p, n, value);
+    return hipGetLastError();
+}
+
+hipError_t zero_words(void* p, size_t bytes, hipStream_t s) {
+    return fill_words((uint32_t*)p, (int64_t)(bytes / 4), 0u, s);
+}
+
+hipError_t fill_i32(int32_t* p, int64_t n, int32_t value, hipStream_t s) {
+    return fill_words((uint32_t*)p, n, (uint32_t)value, s);
+}
+
+}  // namespace mnb
+
+using namespace mnb;
+
+static bool aligned(const void* p) { return ((uintptr_t)p % ALIGN) == 0; }
+
+static mesh_status check_sizes(int64_t n_elem, int32_t etype, int32_t n_vert) {
+    if (n_elem < 0 || n_vert < 0) return MESH_ERR_INVALID_ARG;
+    if (nodes_per_elem(etype) == 0) return MESH_ERR_UNSUPPORTED_TYPE;
+    return MESH_OK;
+}
+
+extern "C" {
+
+int32_t mesh_abi_version(void) { return (1 << 16) | 0; }
+
+const char* mesh_status_string(mesh_status s) {
+    switch (s) {
+        case MESH_OK: return "ok";
+        case MESH_ERR_INVALID_ARG: return "invalid argument";
+        case MESH_ERR_UNSUPPORTED_TYPE: return "unsupported element type";
+        case MESH_ERR_WORKSPACE: return "workspace too small or misaligned";
+        case MESH_ERR_CAPACITY: return "cols capacity too small";
+        case MESH_ERR_OVERFLOW: return "size beyond the supported range";
+        case MESH_ERR_INDEX_RANGE: return "vertex id outside [0, n_vert)";
+        case MESH_ERR_HIP: return "HIP runtime error";
+        case MESH_ERR_INTERNAL: return "internal device check failed";
+    }
+    return "unknown status";
+}
+
+mesh_status mesh_node_neighbors_query(int64_t n_elem, int32_t etype, int32_t n_vert, size_t* workspace_bytes,
+                                      int64_t* cols_capacity) {
+    mesh_status st = check_sizes(n_elem, etype, n_vert);
+    if (st != MESH_OK) return st;
+    if (!workspace_bytes || !cols_capacity) return MESH_ERR_INVALID_ARG;
+    if (n_elem > INT32_MAX / (2 * edges_per_elem(etype))) return MESH_ERR_OVERFLOW;
+    NodePlan p;
+    if (!plan_node(n_elem, etype, n_vert, &p)) return MESH_ERR_INVALID_ARG;
+    *workspace_bytes = p.total;
+    *cols_capacity = p.n_pairs;
+    return MESH_OK;
+}
+
+mesh_status mesh_node_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
+                                int32_t* row_ptr, int32_t* cols, int64_t cols_capacity, void* workspace,
+                                size_t workspace_bytes, void* stream) {
+    size_t need;
+    int64_t cap_hint;
+    mesh_status st = mesh_node_neighbors_query(n_elem, etype, n_vert, &need, &cap_hint);
+    if (st != MESH_OK) return st;
+    if (!row_ptr || !workspace || (n_elem > 0 && !conn) || cols_capacity < 0) return MESH_ERR_INVALID_ARG;
+    if (cols_capacity > 0 && !cols) return MESH_ERR_INVALID_ARG;
+    if (workspace_bytes < need || !aligned(workspace)) return MESH_ERR_WORKSPACE;
+    NodePlan p;
+    plan_node(n_elem, etype, n_vert, &p);
+    hipError_t e = run_node(p, conn, row_ptr, cols, cols_capacity, workspace, (hipStream_t)stream);
+    return e == hipSuccess ? MESH_OK : MESH_ERR_HIP;
+}
+
+mesh_status mesh_elem_neighbors_query(int64_t n_elem, int32_t etype, int32_t n_vert, size_t* workspace_bytes,
+                                      int64_t* cols_capacity) {
+    mesh_status st = check_sizes(n_elem, etype, n_vert);
+    if (st != MESH_OK) return st;
+    if (!workspace_bytes || !cols_capacity) return MESH_ERR_INVALID_ARG;
+    if (n_elem > INT32_MAX / nodes_per_elem(etype)) return MESH_ERR_OVERFLOW;
+    ElemPlan p;
+    if (!plan_elem(n_elem, etype, n_vert, &p)) return MESH_ERR_INVALID_ARG;
+    *workspace_bytes = p.total;
+    *cols_capacity = p.n_slots;
+    return MESH_OK;
+}
+
+mesh_status mesh_elem_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
+                                int32_t* row_ptr, int32_t* cols, int64_t cols_capacity, void* workspace,
+                                size_t workspace_bytes, void* stream) {
+    size_t need;
+    int64_t cap_hint;
+    mesh_status st = mesh_elem_neighbors_query(n_elem, etype, n_vert, &need, &cap_hint);
+    if (st != MESH_OK) return st;
+    if (!row_ptr || !workspace || (n_elem > 0 && !conn) || cols_capacity < 0) return MESH_ERR_INVALID_ARG;
+    if (cols_capacity > 0 && !cols) return MESH_ERR_INVALID_ARG;
+    if (workspace_bytes < need || !aligned(workspace)) return MESH_ERR_WORKSPACE;
+    ElemPlan p;
+    plan_elem(n_elem, etype, n_vert, &p);
+    hipError_t e = run_elem(p, conn, row_ptr, cols, cols_capacity, workspace, (hipStream_t)stream);
+    return e == hipSuccess ? MESH_OK : MESH_ERR_HIP;
+}
+
+mesh_status mesh_check(const void* workspace, void* stream) {
+    if (!workspace) return MESH_ERR_INVALID_ARG;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return MESH_ERR_HIP;
+    uint32_t err = 0;
+    if (hipMemcpy(&err, workspace, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) return MESH_ERR_HIP;
+    if (err & ERR_INTERNAL) return MESH_ERR_INTERNAL;
+    if (err & ERR_INDEX_RANGE) return MESH_ERR_INDEX_RANGE;
+    if (err & ERR_CAPACITY) return MESH_ERR_CAPACITY;
+    return MESH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// Device building blocks shared by the node and element pipelines: error
+// word, decoupled look-back status words, wave64 and block prefix sums.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mnb {
+
+constexpr int WAVE = 64;
+
+// Bits of the device error word (first word of every workspace).
+constexpr uint32_t ERR_INDEX_RANGE = 1u;  // a connectivity id outside [0, n_vert)
+constexpr uint32_t ERR_CAPACITY = 2u;     // more nnz than the cols capacity
+constexpr uint32_t ERR_INTERNAL = 4u;     // a look-back wait gave up / bad offset
+
+// Key value of a pair that is not an edge (self pair, bad id): all ones, so it
+// sorts after every real key on any digit split, and is dropped at the end.
+constexpr uint64_t KEY_NONE = ~0ull;
+
+// Workspace header: error word, tile tickets, counters (bytes).
+constexpr size_t HEADER_BYTES = 256;
+constexpr int HDR_ERR = 0;          // u32 index of the error word
+constexpr int HDR_TICKET0 = 4;      // u32 index of the first tile ticket
+constexpr int N_TICKETS = 16;
+constexpr int HDR_LONG_COUNT = 32;  // u32 index of the long-row counter
+
+// Decoupled look-back status word: 2 flag bits over a 62-bit value.
+constexpr uint64_t LB_AGG = 1ull << 62;  // value = this tile's own count
+constexpr uint64_t LB_INC = 2ull << 62;  // value = count of this and all earlier tiles
+constexpr uint64_t LB_FLAG = 3ull << 62;
+constexpr uint64_t LB_VAL = ~LB_FLAG;
+
+// A look-back wait polls at most this many times (about a second with the
+// sleep below) before it records ERR_INTERNAL and moves on, so every wave of
+// every kernel always terminates.
+constexpr uint32_t SPIN_LIMIT = 1u << 22;
+
+__device__ __forceinline__ uint64_t lb_load(const uint64_t* p) {
+    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void lb_store(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void set_error(uint32_t* err, uint32_t bit) {
+    atomicOr(err, bit);
+}
+
+// Exclusive prefix over the tiles before `tile` of one running count whose
+// status words sit `stride` apart (status[t * stride]).  The caller has
+// already published LB_AGG | agg for this tile (or LB_INC for tile 0).  Tiles
+// are handed out in launch order by an atomic ticket, so every earlier tile is
+// resident and the walk finishes.  Publishes LB_INC | (prefix + agg).
+__device__ __forceinline__ uint64_t lookback_prefix(uint64_t* status, int64_t stride, uint32_t tile,
+                                                    uint64_t agg, uint32_t* err) {
+    if (tile == 0) return 0;
+    uint64_t prefix = 0;
+    int64_t t = (int64_t)tile - 1;
+    uint32_t spins = 0;
+    while (t >= 0) {
+        uint64_t s = lb_load(status + t * stride);
+        uint64_t f = s & LB_FLAG;
+        if (f == 0) {
+            // give up after SPIN_LIMIT polls, or at once when another wait
+            // already gave up (so a failure cannot chain into long waits)
+            if (++spins > SPIN_LIMIT ||
+                ((spins & 1023u) == 0 &&
+                 (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_INTERNAL))) {
+                set_error(err, ERR_INTERNAL);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        prefix += s & LB_VAL;
+        if (f == LB_INC) break;
+        --t;
+    }
+    lb_store(status + (int64_t)tile * stride, LB_INC | (prefix + agg));
+    return prefix;
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_sum(T x) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        T y = __shfl_up(x, d, WAVE);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Exclusive prefix sum of one value per thread across the block, in thread
+// order; *total receives the block sum.  s_tmp needs BLOCK/64 entries.
+// Contains __syncthreads: every thread of the block must call it.
+template <int BLOCK, typename T>
+__device__ __forceinline__ T block_exclusive_sum(T v, T* s_tmp, T* total) {
+    constexpr int WAVES = BLOCK / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wid = threadIdx.x / WAVE;
+    T x = wave_inclusive_sum(v);
+    if (lane == WAVE - 1) s_tmp[wid] = x;
+    __syncthreads();
+    T before = 0, sum = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+        T t = s_tmp[w];
+        before += (w < wid) ? t : T(0);
+        sum += t;
+    }
+    __syncthreads();
+    *total = sum;
+    return before + x - v;
+}
+
+__host__ __device__ constexpr int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <typename T>
+__host__ __device__ constexpr T tmin(T a, T b) {
+    return a < b ? a : b;
+}
+
+}  // namespace mnb

@@ -1,0 +1,55 @@
+// Host-side interface between the C ABI and the two pipelines.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mnb {
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// ---- node pipeline ---------------------------------------------------------
+struct NodePlan {
+    int64_t n_elem = 0;
+    int32_t etype = 0;
+    int32_t n_vert = 0;
+    int64_t n_pairs = 0;      // 2 * edges per element * n_elem
+    uint32_t id_bits = 1;     // b: bits of a vertex id in the packed key
+    int n_pass = 0;           // radix passes over the 2b key bits
+    int64_t n_tiles = 0;      // radix tiles
+    int64_t n_utiles = 0;     // unique/CSR tiles
+    // workspace offsets (bytes)
+    size_t off_hist = 0, off_ulb = 0, off_lb0 = 0, off_lb1 = 0, off_keys0 = 0, off_keys1 = 0;
+    size_t zero_bytes = 0;    // bytes from 0 cleared at the start of a call
+    size_t total = 0;
+};
+
+bool plan_node(int64_t n_elem, int32_t etype, int32_t n_vert, NodePlan* p);
+hipError_t run_node(const NodePlan& p, const int32_t* conn, int32_t* row_ptr, int32_t* cols,
+                    int64_t cols_capacity, void* ws, hipStream_t stream);
+
+// ---- element pipeline --------------------------------------------------------
+struct ElemPlan {
+    int64_t n_elem = 0;
+    int32_t etype = 0;
+    int32_t n_vert = 0;
+    int64_t n_slots = 0;      // npe * n_elem
+    int64_t n_stiles = 0;     // scan tiles over the vertices
+    int64_t long_cap = 0;     // capacity of the long-row list
+    size_t off_cursor = 0, off_lb = 0, off_long = 0;
+    size_t zero_bytes = 0;
+    size_t total = 0;
+};
+
+bool plan_elem(int64_t n_elem, int32_t etype, int32_t n_vert, ElemPlan* p);
+hipError_t run_elem(const ElemPlan& p, const int32_t* conn, int32_t* row_ptr, int32_t* cols,
+                    int64_t cols_capacity, void* ws, hipStream_t stream);
+
+// Clears `bytes` (a multiple of 4) from `p` with a fill kernel (no memset
+// nodes, so the sequence can be captured into a graph).
+hipError_t zero_words(void* p, size_t bytes, hipStream_t stream);
+hipError_t fill_i32(int32_t* p, int64_t n, int32_t value, hipStream_t stream);
+
+}  // namespace mnb

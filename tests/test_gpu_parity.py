@@ -1,0 +1,191 @@
+"""Parity of the HIP pipelines (through the C ABI) with the CPU oracle.
+
+The relation is exact integer work with one canonical answer (ascending,
+duplicate-free rows), so every comparison is bit-exact: tolerance 0."""
+import numpy as np
+import pytest
+
+from paper_1604_04689_amd import meshgen as mg
+from tests import pins
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _nb():
+    import paper_1604_04689_amd as nb
+    return nb
+
+
+def gpu_csr(kind, conn, etype, n_vert, stream=None):
+    nb = _nb()
+    npe = pins.NPE[etype]
+    c = torch.as_tensor(np.ascontiguousarray(conn, dtype=np.int32).reshape(-1, npe)).to(DEV)
+    fn = nb.node_neighbors if kind == "node" else nb.elem_neighbors
+    row_ptr, cols = fn(c, etype, n_vert, stream=stream)
+    return row_ptr.cpu().numpy(), cols.cpu().numpy()
+
+
+def assert_same(got, want, what=""):
+    gr, gc = got
+    wr, wc = want
+    assert gr.shape == wr.shape, what
+    assert np.array_equal(gr, wr), f"{what}: row_ptr differs at {np.flatnonzero(gr != wr)[:10]}"
+    assert gc.shape == wc.shape, f"{what}: nnz {gc.shape[0]} vs {wc.shape[0]}"
+    assert np.array_equal(gc, wc), f"{what}: cols differ at {np.flatnonzero(gc != wc)[:10]}"
+
+
+def check_both(oracle_mod, conn, etype, n_vert, what=""):
+    print(f"[parity] {what} etype={etype} n_elem={np.asarray(conn).reshape(-1, pins.NPE[etype]).shape[0]} "
+          f"n_vert={n_vert}", flush=True)
+    assert_same(gpu_csr("node", conn, etype, n_vert), oracle_mod.node_neighbors(conn, etype, n_vert), what + " node")
+    assert_same(gpu_csr("elem", conn, etype, n_vert), oracle_mod.elem_neighbors(conn, etype, n_vert), what + " elem")
+
+
+@pytest.mark.parametrize("case", pins.read_golden(), ids=lambda c: c["name"])
+def test_golden(case):
+    conn = case["conn"].reshape(-1, pins.NPE[case["etype"]])
+    assert_same(gpu_csr("node", conn, case["etype"], case["n_vert"]), (case["node_row_ptr"], case["node_cols"]))
+    assert_same(gpu_csr("elem", conn, case["etype"], case["n_vert"]), (case["elem_row_ptr"], case["elem_cols"]))
+
+
+@pytest.mark.parametrize("etype", [0, 1, 2])
+@pytest.mark.parametrize("size", [(1, 1), (7, 5), (300, 90), (5000, 4000), (60000, 9000), (20000, 2 ** 20 + 7)])
+def test_random_meshes(oracle_mod, etype, size):
+    n_elem, n_vert = size
+    m = mg.random_mesh(n_elem, n_vert, etype, seed=n_elem + 7 * etype)
+    check_both(oracle_mod, m.conn, etype, n_vert, m.name)
+
+
+@pytest.mark.parametrize("maker", [lambda: mg.tri64(), lambda: mg.tri_grid(300, "coin", 3),
+                                   lambda: mg.kuhn_tet_grid(20, 4), lambda: mg.hex_grid(16, 5),
+                                   lambda: mg.tri_grid(2, "main", 1), lambda: mg.kuhn_tet_grid(1, 2),
+                                   lambda: mg.hex_grid(1, 3)],
+                         ids=["tri64", "tri300coin", "kuhn20", "hex16", "tri2", "kuhn1", "hex1"])
+def test_structured(oracle_mod, maker):
+    m = maker()
+    check_both(oracle_mod, m.conn, m.etype, m.n_vert, m.name)
+
+
+def test_large_ids_many_passes(oracle_mod):
+    # ids up to 2^25: 50 key bits, 7 radix passes
+    m = mg.random_mesh(30000, 2 ** 25 - 3, 1, seed=3)
+    check_both(oracle_mod, m.conn, 1, m.n_vert, "ids 2^25")
+
+
+def test_fans_long_element_rows(oracle_mod):
+    # vertex 0 lies in n triangles: element rows of 100 (long-row list),
+    # 5000 (LDS bitonic) and 9000 (in-place bitonic in global memory)
+    for n in (100, 5000, 9000):
+        rim = np.arange(1, n + 2, dtype=np.int32)
+        conn = np.stack([np.zeros(n, np.int32), rim[:-1], rim[1:]], 1)
+        conn = conn[np.random.default_rng(n).permutation(n)]
+        check_both(oracle_mod, conn, 0, n + 2, f"fan{n}")
+
+
+def test_degenerate_and_duplicate_elements(oracle_mod):
+    rng = np.random.default_rng(9)
+    conn = rng.integers(0, 6, size=(4000, 4)).astype(np.int32)  # many repeats per tet
+    conn[::7] = conn[1::7][: conn[::7].shape[0]]                   # duplicate rows
+    conn[::11, 1] = conn[::11, 0]                                   # explicit repeated ids
+    check_both(oracle_mod, conn, 1, 8, "degenerate")
+    check_both(oracle_mod, np.zeros((50, 3), np.int32), 0, 1, "all-self tri")
+
+
+def test_empty_and_no_vertices():
+    for kind in ("node", "elem"):
+        r, c = gpu_csr(kind, np.zeros((0, 3), np.int32), 0, 5)
+        assert r.tolist() == [0] * 6 and c.shape == (0,)
+        r, c = gpu_csr(kind, np.zeros((0, 4), np.int32), 1, 0)
+        assert r.tolist() == [0] and c.shape == (0,)
+
+
+def test_index_range_error():
+    nb = _nb()
+    for kind in ("node", "elem"):
+        with pytest.raises(nb.MeshError) as e:
+            gpu_csr(kind, np.array([[0, 1, 2], [1, 2, 9]], np.int32), 0, 4)
+        assert e.value.status == nb.Status.INDEX_RANGE
+        with pytest.raises(nb.MeshError) as e:
+            gpu_csr(kind, np.array([[0, -1, 2]], np.int32), 0, 4)
+        assert e.value.status == nb.Status.INDEX_RANGE
+
+
+def test_capacity_error():
+    nb = _nb()
+    m = mg.tri_grid(20, "main", 1)
+    for kind in ("node", "elem"):
+        b = nb.NeighborBuild(kind, m.n_elem, m.etype, m.n_vert, DEV, cols_capacity=100)
+        b.launch(torch.as_tensor(m.conn).to(DEV))
+        with pytest.raises(nb.MeshError) as e:
+            b.result()
+        assert e.value.status == nb.Status.CAPACITY
+
+
+def test_exact_capacity_is_enough(oracle_mod):
+    nb = _nb()
+    m = mg.kuhn_tet_grid(6, 2)
+    for kind, ref in (("node", oracle_mod.node_neighbors), ("elem", oracle_mod.elem_neighbors)):
+        want = ref(m.conn, m.etype, m.n_vert)
+        b = nb.NeighborBuild(kind, m.n_elem, m.etype, m.n_vert, DEV, cols_capacity=want[1].shape[0])
+        b.launch(torch.as_tensor(m.conn).to(DEV))
+        r, c = b.result()
+        assert_same((r.cpu().numpy(), c.cpu().numpy()), want, kind)
+
+
+def test_deterministic_and_workspace_reuse():
+    nb = _nb()
+    m = mg.kuhn_tet_grid(12, 8)
+    conn = torch.as_tensor(m.conn).to(DEV)
+    for kind in ("node", "elem"):
+        b = nb.NeighborBuild(kind, m.n_elem, m.etype, m.n_vert, DEV)
+        outs = []
+        for _ in range(3):  # the same workspace, reused without clearing
+            b.launch(conn)
+            r, c = b.result()
+            outs.append((r.cpu().numpy().copy(), c.cpu().numpy().copy()))
+        for o in outs[1:]:
+            assert_same(o, outs[0], kind)
+
+
+def test_side_stream(oracle_mod):
+    m = mg.hex_grid(9, 4)
+    s = torch.cuda.Stream(DEV)
+    with torch.cuda.stream(s):
+        got = gpu_csr("node", m.conn, m.etype, m.n_vert, stream=s)
+    assert_same(got, oracle_mod.node_neighbors(m.conn, m.etype, m.n_vert))
+
+
+# ---- full-size workloads ---------------------------------------------------
+
+@pytest.fixture(scope="module")
+def tri2048_mesh():
+    return mg.tri2048()
+
+
+@pytest.fixture(scope="module")
+def kuhn96_mesh():
+    return mg.kuhn96()
+
+
+@pytest.mark.slow
+def test_full_tri2048_vs_oracle(oracle_mod, tri2048_mesh):
+    m = tri2048_mesh
+    check_both(oracle_mod, m.conn, m.etype, m.n_vert, "tri2048 coin")
+
+
+@pytest.mark.slow
+def test_full_kuhn96_vs_oracle(oracle_mod, kuhn96_mesh):
+    m = kuhn96_mesh
+    check_both(oracle_mod, m.conn, m.etype, m.n_vert, "kuhn96")
+
+
+@pytest.mark.slow
+def test_full_kuhn96_lattice_rows(kuhn96_mesh):
+    # closed-form check without the oracle: every row from lattice offsets
+    m = kuhn96_mesh
+    want = pins.lattice_node_csr(m.dims, pins.KUHN_STEPS, m.perm)
+    assert_same(gpu_csr("node", m.conn, m.etype, m.n_vert), want, "kuhn96 lattice")
