@@ -120,6 +120,31 @@ const char* mesh_status_string(mesh_status status);
 /* Library ABI version, (major << 16) | minor. */
 int32_t mesh_abi_version(void);
 
+/* ------------------------------------------------------------------------ */
+/* Kernel timing (diagnostics, not part of the method).                     */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    char name[32];     /* kernel name, e.g. "radix_pass"               */
+    int64_t launches;  /* timed launches since the last read           */
+    double total_ms;   /* summed device duration of those launches     */
+    double min_ms;
+    double max_ms;
+} mesh_kernel_time;
+
+/* While enabled (process-wide), every kernel the library launches is
+ * bracketed by HIP events recorded by the launch itself on the launch's own
+ * stream (hipExtLaunchKernel), on the device current when the events were
+ * first created.  Up to 65536 launches are recorded between reads; later ones
+ * run untimed.  Always returns MESH_OK. */
+mesh_status mesh_timing_enable(int32_t enable);
+
+/* Waits for the recorded launches to finish, aggregates their durations per
+ * kernel name into out[0 .. min(n, max_entries)) and clears the record.
+ * Returns n, the number of distinct kernel names, or -1 if an event query
+ * failed. out may be NULL to only clear. */
+int32_t mesh_timing_read(mesh_kernel_time* out, int32_t max_entries);
+
 #ifdef __cplusplus
 }
 #endif

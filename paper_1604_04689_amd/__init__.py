@@ -6,4 +6,5 @@ The compute path is the HIP library ``libmeshnbr.so`` (C ABI in
 mesh generators (``meshgen``).
 """
 from .binding import (HEX8, TET4, TRI3, MeshError, NeighborBuild, Status, elem_neighbors,  # noqa: F401
-                      lib, node_neighbors, query_elem, query_node, status_string)
+                      lib, node_neighbors, query_elem, query_node, status_string, timing_enable,
+                      timing_read)

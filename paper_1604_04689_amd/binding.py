@@ -35,6 +35,11 @@ class MeshError(RuntimeError):
         super().__init__(f"{where}: {status_string(status)} ({self.status.name})")
 
 
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("min_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
+
+
 _lib = None
 
 _c_i32, _c_i64, _c_sz, _c_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
@@ -48,6 +53,8 @@ SIGNATURES = {
     "mesh_check": (_c_i32, [_c_p, _c_p]),
     "mesh_status_string": (ctypes.c_char_p, [_c_i32]),
     "mesh_abi_version": (_c_i32, []),
+    "mesh_timing_enable": (_c_i32, [_c_i32]),
+    "mesh_timing_read": (_c_i32, [ctypes.POINTER(KernelTime), _c_i32]),
 }
 
 
@@ -69,6 +76,21 @@ def lib() -> ctypes.CDLL:
 
 def status_string(status) -> str:
     return lib().mesh_status_string(int(status)).decode()
+
+
+def timing_enable(on: bool = True):
+    """Record HIP-event durations of every library kernel launched from now on."""
+    lib().mesh_timing_enable(1 if on else 0)
+
+
+def timing_read():
+    """{kernel name: (launches, total_ms, min_ms, max_ms)} since the last read (waits for them)."""
+    buf = (KernelTime * 64)()
+    n = lib().mesh_timing_read(buf, 64)
+    if n < 0:
+        raise RuntimeError("mesh_timing_read: event query failed")
+    return {buf[i].name.decode(): (int(buf[i].launches), buf[i].total_ms, buf[i].min_ms, buf[i].max_ms)
+            for i in range(min(n, 64))}
 
 
 def _query(kind, n_elem, etype, n_vert):

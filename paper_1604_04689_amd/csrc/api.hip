@@ -7,6 +7,7 @@
 #include "common.hpp"
 #include "elements.hpp"
 #include "internal.hpp"
+#include "launch.hpp"
 
 namespace mnb {
 
@@ -21,8 +22,7 @@ __global__ __launch_bounds__(FILL_BLOCK) void fill_u32_kernel(uint32_t* __restri
 static hipError_t fill_words(uint32_t* p, int64_t n, uint32_t value, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int grid = (int)tmin<int64_t>(ceil_div(n, FILL_BLOCK), FILL_GRID_MAX);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid), dim3(FILL_BLOCK), 0, s, p, n, value);
-    return hipGetLastError();
+    return launch("fill", fill_u32_kernel, dim3(grid), dim3(FILL_BLOCK), s, p, n, value);
 }
 
 hipError_t zero_words(void* p, size_t bytes, hipStream_t s) {

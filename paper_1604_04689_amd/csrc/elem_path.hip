@@ -17,6 +17,7 @@
 #include "common.hpp"
 #include "elements.hpp"
 #include "internal.hpp"
+#include "launch.hpp"
 
 namespace mnb {
 
@@ -262,16 +263,19 @@ bool plan_elem(int64_t n_elem, int32_t etype, int32_t n_vert, ElemPlan* p) {
 }
 
 template <int ET>
-static void launch_count_scatter(const ElemPlan& p, const int32_t* conn, int32_t* row_ptr, int32_t* cols,
-                                 int64_t cols_cap, uint32_t* cursor, uint64_t* lb, uint32_t* hdr, hipStream_t s) {
+static hipError_t launch_count_scatter(const ElemPlan& p, const int32_t* conn, int32_t* row_ptr, int32_t* cols,
+                                       int64_t cols_cap, uint32_t* cursor, uint64_t* lb, uint32_t* hdr,
+                                       hipStream_t s) {
     uint32_t* err = hdr + HDR_ERR;
-    const unsigned grid = (unsigned)ceil_div(p.n_slots, EC_BLOCK);
-    hipLaunchKernelGGL(elem_count_kernel<ET>, dim3(grid), dim3(EC_BLOCK), 0, s, conn, p.n_slots, p.n_vert, cursor,
-                       err);
-    hipLaunchKernelGGL(elem_scan_kernel, dim3((unsigned)p.n_stiles), dim3(SCAN_BLOCK), 0, s, cursor, p.n_vert, row_ptr,
-                       lb, hdr + HDR_TICKET0, err);
-    hipLaunchKernelGGL(elem_scatter_kernel<ET>, dim3(grid), dim3(EC_BLOCK), 0, s, conn, p.n_slots, p.n_vert, cursor,
-                       cols, cols_cap, err);
+    const dim3 grid((unsigned)ceil_div(p.n_slots, EC_BLOCK));
+    hipError_t e = launch("elem_count", elem_count_kernel<ET>, grid, dim3(EC_BLOCK), s, conn, p.n_slots, p.n_vert,
+                          cursor, err);
+    if (e != hipSuccess || p.n_vert == 0) return e;
+    e = launch("elem_scan", elem_scan_kernel, dim3((unsigned)p.n_stiles), dim3(SCAN_BLOCK), s, cursor, p.n_vert,
+               row_ptr, lb, hdr + HDR_TICKET0, err);
+    if (e != hipSuccess) return e;
+    return launch("elem_scatter", elem_scatter_kernel<ET>, grid, dim3(EC_BLOCK), s, conn, p.n_slots, p.n_vert,
+                  cursor, cols, cols_cap, err);
 }
 
 hipError_t run_elem(const ElemPlan& p, const int32_t* conn, int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
@@ -284,29 +288,19 @@ hipError_t run_elem(const ElemPlan& p, const int32_t* conn, int32_t* row_ptr, in
 
     hipError_t e = zero_words(ws, p.zero_bytes, s);
     if (e != hipSuccess) return e;
-    if (p.n_vert == 0) {
-        // no vertex: row_ptr = [0]; any element id is out of range
-        if (p.n_slots > 0) {
-            switch (p.etype) {
-                case TRI3: hipLaunchKernelGGL(elem_count_kernel<TRI3>, dim3((unsigned)ceil_div(p.n_slots, EC_BLOCK)), dim3(EC_BLOCK), 0, s, conn, p.n_slots, 0, cursor, hdr + HDR_ERR); break;
-                case TET4: hipLaunchKernelGGL(elem_count_kernel<TET4>, dim3((unsigned)ceil_div(p.n_slots, EC_BLOCK)), dim3(EC_BLOCK), 0, s, conn, p.n_slots, 0, cursor, hdr + HDR_ERR); break;
-                default: hipLaunchKernelGGL(elem_count_kernel<HEX8>, dim3((unsigned)ceil_div(p.n_slots, EC_BLOCK)), dim3(EC_BLOCK), 0, s, conn, p.n_slots, 0, cursor, hdr + HDR_ERR); break;
-            }
-        }
-        return fill_i32(row_ptr, 1, 0, s);
-    }
     if (p.n_slots == 0) return fill_i32(row_ptr, (int64_t)p.n_vert + 1, 0, s);
     switch (p.etype) {
-        case TRI3: launch_count_scatter<TRI3>(p, conn, row_ptr, cols, cols_capacity, cursor, lb, hdr, s); break;
-        case TET4: launch_count_scatter<TET4>(p, conn, row_ptr, cols, cols_capacity, cursor, lb, hdr, s); break;
-        default: launch_count_scatter<HEX8>(p, conn, row_ptr, cols, cols_capacity, cursor, lb, hdr, s); break;
+        case TRI3: e = launch_count_scatter<TRI3>(p, conn, row_ptr, cols, cols_capacity, cursor, lb, hdr, s); break;
+        case TET4: e = launch_count_scatter<TET4>(p, conn, row_ptr, cols, cols_capacity, cursor, lb, hdr, s); break;
+        default: e = launch_count_scatter<HEX8>(p, conn, row_ptr, cols, cols_capacity, cursor, lb, hdr, s); break;
     }
-    hipLaunchKernelGGL(elem_rowsort_kernel, dim3((unsigned)ceil_div(p.n_vert, RS_BLOCK)), dim3(RS_BLOCK), 0, s,
-                       row_ptr, p.n_vert, cols, cols_capacity, long_list, p.long_cap, hdr + HDR_LONG_COUNT,
-                       hdr + HDR_ERR);
-    hipLaunchKernelGGL(elem_longrows_kernel, dim3(LR_GRID), dim3(LR_BLOCK), 0, s, row_ptr, cols, cols_capacity,
-                       long_list, p.long_cap, hdr + HDR_LONG_COUNT);
-    return hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (p.n_vert == 0) return fill_i32(row_ptr, 1, 0, s);  // every id was out of range
+    e = launch("elem_rowsort", elem_rowsort_kernel, dim3((unsigned)ceil_div(p.n_vert, RS_BLOCK)), dim3(RS_BLOCK), s,
+               row_ptr, p.n_vert, cols, cols_capacity, long_list, p.long_cap, hdr + HDR_LONG_COUNT, hdr + HDR_ERR);
+    if (e != hipSuccess) return e;
+    return launch("elem_longrows", elem_longrows_kernel, dim3(LR_GRID), dim3(LR_BLOCK), s, row_ptr, cols,
+                  cols_capacity, long_list, p.long_cap, hdr + HDR_LONG_COUNT);
 }
 
 }  // namespace mnb

@@ -1,0 +1,44 @@
+// Kernel launch helper shared by the pipelines.  Every kernel of the library
+// goes through launch(): it converts the arguments to the kernel's parameter
+// types and, while kernel timing is enabled, brackets the dispatch with HIP
+// events taken by the launch itself (hipExtLaunchKernel), on the launch's own
+// stream, so per-kernel durations can be read back (mesh_timing_read).
+#pragma once
+
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <tuple>
+#include <utility>
+
+namespace mnb {
+
+bool timing_enabled();
+// Hands out an event pair for one timed launch; false when timing is off or
+// the record is full (the launch then runs untimed).
+bool timing_begin(hipEvent_t* start, hipEvent_t* stop);
+// Records that the pair brackets one launch of kernel `name`.
+void timing_commit(const char* name, hipEvent_t start, hipEvent_t stop);
+
+template <typename... P, typename... A>
+hipError_t launch(const char* name, void (*kernel)(P...), dim3 grid, dim3 block, hipStream_t stream, A&&... a) {
+    static_assert(sizeof...(P) == sizeof...(A), "argument count");
+    std::tuple<P...> vals(static_cast<P>(std::forward<A>(a))...);
+    void* args[sizeof...(P) > 0 ? sizeof...(P) : 1];
+    std::apply(
+        [&](auto&... x) {
+            int i = 0;
+            ((args[i++] = (void*)&x), ...);
+        },
+        vals);
+    if (grid.x == 0 || grid.y == 0 || grid.z == 0) return hipSuccess;
+    hipEvent_t e0, e1;
+    if (timing_enabled() && timing_begin(&e0, &e1)) {
+        hipError_t e = hipExtLaunchKernel((const void*)kernel, grid, block, args, 0, stream, e0, e1, 0);
+        if (e == hipSuccess) timing_commit(name, e0, e1);
+        return e;
+    }
+    return hipLaunchKernel((const void*)kernel, grid, block, args, 0, stream);
+}
+
+}  // namespace mnb

@@ -15,6 +15,7 @@
 #include "common.hpp"
 #include "elements.hpp"
 #include "internal.hpp"
+#include "launch.hpp"
 
 namespace mnb {
 
@@ -355,13 +356,13 @@ bool plan_node(int64_t n_elem, int32_t etype, int32_t n_vert, NodePlan* p) {
 }
 
 template <int ET>
-static void launch_emit(const NodePlan& p, const int32_t* conn, uint64_t* keys, uint32_t* hist, uint32_t* err,
-                        hipStream_t s) {
+static hipError_t launch_emit(const NodePlan& p, const int32_t* conn, uint64_t* keys, uint32_t* hist, uint32_t* err,
+                              hipStream_t s) {
     const int64_t tiles = ceil_div(p.n_elem, EMIT_BLOCK);
     const int grid = (int)tmin<int64_t>(tiles, EMIT_GRID_MAX);
     const uint32_t last_bits = 2 * p.id_bits - (uint32_t)(p.n_pass - 1) * RBITS;
-    hipLaunchKernelGGL(node_emit_kernel<ET>, dim3(grid), dim3(EMIT_BLOCK), 0, s, conn, p.n_elem, p.n_vert,
-                       p.id_bits, p.n_pass, last_bits, keys, hist, err);
+    return launch("node_emit", node_emit_kernel<ET>, dim3(grid), dim3(EMIT_BLOCK), s, conn, p.n_elem, p.n_vert,
+                  p.id_bits, p.n_pass, last_bits, keys, hist, err);
 }
 
 hipError_t run_node(const NodePlan& p, const int32_t* conn, int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
@@ -380,23 +381,24 @@ hipError_t run_node(const NodePlan& p, const int32_t* conn, int32_t* row_ptr, in
     if (p.n_pairs == 0) return fill_i32(row_ptr, (int64_t)p.n_vert + 1, 0, s);
 
     switch (p.etype) {
-        case TRI3: launch_emit<TRI3>(p, conn, kb[0], hist, err, s); break;
-        case TET4: launch_emit<TET4>(p, conn, kb[0], hist, err, s); break;
-        default: launch_emit<HEX8>(p, conn, kb[0], hist, err, s); break;
+        case TRI3: e = launch_emit<TRI3>(p, conn, kb[0], hist, err, s); break;
+        case TET4: e = launch_emit<TET4>(p, conn, kb[0], hist, err, s); break;
+        default: e = launch_emit<HEX8>(p, conn, kb[0], hist, err, s); break;
     }
+    if (e != hipSuccess) return e;
     const uint32_t total_bits = 2 * p.id_bits;
     for (int pass = 0; pass < p.n_pass; ++pass) {
         const uint32_t shift = (uint32_t)pass * RBITS;
         const uint32_t bits = tmin<uint32_t>(RBITS, total_bits - shift);
-        hipLaunchKernelGGL((radix_pass_kernel<SORT_BLOCK, SORT_ITEMS>), dim3((unsigned)p.n_tiles), dim3(SORT_BLOCK),
-                           0, s, kb[pass & 1], kb[(pass + 1) & 1], p.n_pairs, shift, bits, hist + pass * RADIX,
-                           lb[pass & 1], lb[(pass + 1) & 1], tickets + pass, err);
+        e = launch("radix_pass", radix_pass_kernel<SORT_BLOCK, SORT_ITEMS>, dim3((unsigned)p.n_tiles),
+                   dim3(SORT_BLOCK), s, kb[pass & 1], kb[(pass + 1) & 1], p.n_pairs, shift, bits,
+                   hist + pass * RADIX, lb[pass & 1], lb[(pass + 1) & 1], tickets + pass, err);
+        if (e != hipSuccess) return e;
     }
     const uint64_t* sorted = kb[p.n_pass & 1];
-    hipLaunchKernelGGL((unique_csr_kernel<UNIQ_BLOCK, UNIQ_ITEMS>), dim3((unsigned)p.n_utiles), dim3(UNIQ_BLOCK), 0,
-                       s, sorted, p.n_pairs, p.id_bits, p.n_vert, cols, cols_capacity, row_ptr, ulb,
-                       tickets + (N_TICKETS - 1), err);
-    return hipGetLastError();
+    return launch("unique_csr", unique_csr_kernel<UNIQ_BLOCK, UNIQ_ITEMS>, dim3((unsigned)p.n_utiles),
+                  dim3(UNIQ_BLOCK), s, sorted, p.n_pairs, p.id_bits, p.n_vert, cols, cols_capacity, row_ptr, ulb,
+                  tickets + (N_TICKETS - 1), err);
 }
 
 }  // namespace mnb
