@@ -57,22 +57,35 @@ def id_bits(n_vert):
     return b
 
 
-def model_bytes(m, nnz_node, nnz_elem):
-    """Algorithmic HBM bytes of the pipeline as run (bytes each kernel must
-    move at least once): node = conn + key write + p radix passes (read and
-    write) + unique read + cols + row_ptr; elem = two conn reads + cols
-    scatter + row-sort read/write + counts/scan/row_ptr."""
+def kernel_bytes(m, nnz_node, nnz_elem):
+    """Algorithmic HBM bytes per launch of every kernel of the two pipelines:
+    what the kernel must read and write at least once.  P = directed edge
+    pairs (2 x edges per element x F), Q = element pairs (nnz of the element
+    relation), conn = 4 x npe x F bytes."""
     f, v, k, npe = m.n_elem, m.n_vert, EDGES[m.etype], NPE[m.etype]
-    p_pairs = 2 * k * f
-    passes = -(-2 * id_bits(v) // 8)
-    node = 4 * npe * f + 8 * p_pairs + passes * 16 * p_pairs + 8 * p_pairs + 4 * nnz_node + 4 * (v + 1)
-    elem = 2 * 4 * npe * f + 4 * nnz_elem + 8 * nnz_elem + 12 * (v + 1)
-    return node, elem, passes
+    p_pairs, q_pairs = 2 * k * f, nnz_elem
+    conn = 4 * npe * f
+    return {
+        "node_hist": conn,                                  # read conn
+        "node_radix_first": conn + 8 * p_pairs,             # read conn, write keys
+        "node_radix": 16 * p_pairs,                         # read + write keys
+        "node_unique_csr": 8 * p_pairs + 4 * nnz_node + 4 * (v + 1),
+        "elem_hist": conn,
+        "elem_radix_first": conn + 8 * q_pairs,
+        "elem_radix": 16 * q_pairs,
+        "elem_csr": 8 * q_pairs + 4 * q_pairs + 4 * (v + 1),
+        "fill": 0,
+    }
+
+
+def passes(m):
+    b = id_bits(m.n_vert)
+    return -(-2 * b // 8), -(-b // 8)
 
 
 def radix_source_hash():
     h = hashlib.sha256()
-    for f in ("node_path.hip", "common.hpp", "launch.hpp"):
+    for f in ("radix.hpp", "common.hpp", "launch.hpp"):
         with open(os.path.join(ROOT, "paper_1604_04689_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -81,7 +94,7 @@ def radix_source_hash():
 def load_traffic(workload):
     """HBM bytes per radix_pass launch from the committed rocprofv3 counter
     summary, or None if absent or taken on different kernel source."""
-    path = os.path.join(PROFILES, f"radix_pass_{workload}_traffic.json")
+    path = os.path.join(PROFILES, f"node_radix_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -128,33 +141,38 @@ def run_workload(name, steps, warmup, torch, nb):
     elem.check(stream)
 
     sec = (t1 - t0) / steps
-    n_pairs = 2 * EDGES[m.etype] * m.n_elem
-    node_b, elem_b, passes = model_bytes(m, nnz_node, nnz_elem)
-    launches, total_ms, _, _ = kt["radix_pass"]
-    radix_ms = total_ms / launches
-    radix_bytes = 16 * n_pairs
-    node_kernels = ("node_emit", "radix_pass", "unique_csr")
-    node_ms = sum(v[1] for k, v in kt.items() if k in node_kernels) / steps
-    all_ms = sum(v[1] for v in kt.values()) / steps
+    kb = kernel_bytes(m, nnz_node, nnz_elem)
+    kernels = {}
+    model_total = 0
+    for k, (launches, total_ms, mn, mx) in sorted(kt.items()):
+        per = kb.get(k, 0)
+        avg_ms = total_ms / launches
+        model_total += per * launches / steps
+        kernels[k] = {"launches_per_step": launches / steps, "us_per_step": total_ms / steps * 1e3,
+                      "avg_us": avg_ms * 1e3, "bytes_per_launch": per,
+                      "GBs": per / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None}
+    node_p, elem_p = passes(m)
+    node_ms = sum(v[1] for k, v in kt.items() if k.startswith("node_")) / steps
+    elem_ms = sum(v[1] for k, v in kt.items() if k.startswith("elem_")) / steps
     res = {
         "workload": name,
         "n_elem": m.n_elem, "n_vert": m.n_vert, "etype": TYPE_NAME[m.etype],
-        "nnz_node": nnz_node, "nnz_elem": nnz_elem, "radix_passes": passes,
+        "nnz_node": nnz_node, "nnz_elem": nnz_elem, "radix_passes": {"node": node_p, "elem": elem_p},
         "ms_per_step": sec * 1e3,
         "elements_per_s": m.n_elem / sec,
-        "kernel_ms_per_step": {k: v[1] / steps for k, v in sorted(kt.items())},
-        "kernel_launches_per_step": {k: v[0] / steps for k, v in sorted(kt.items())},
-        "node_kernel_ms": node_ms, "elem_kernel_ms": all_ms - node_ms,
-        "model_bytes": {"node": node_b, "elem": elem_b},
-        "pipeline_model_GBs": (node_b + elem_b) / sec / 1e9,
-        "pipeline_frac_of_hbm": (node_b + elem_b) / sec / 1e9 / HBM_PEAK_GBS,
-        "radix_pass": {"avg_ms": radix_ms, "bytes_per_launch": radix_bytes,
-                       "GBs": radix_bytes / (radix_ms * 1e-3) / 1e9},
+        "node_kernel_ms": node_ms, "elem_kernel_ms": elem_ms,
+        "kernels": kernels,
+        "pipeline_model_bytes": model_total,
+        "pipeline_model_GBs": model_total / sec / 1e9,
+        "pipeline_frac_of_hbm": model_total / sec / 1e9 / HBM_PEAK_GBS,
+        "radix_pass": {"kernel": "node_radix", "avg_ms": kernels["node_radix"]["avg_us"] * 1e-3,
+                       "bytes_per_launch": kb["node_radix"], "GBs": kernels["node_radix"]["GBs"]},
     }
     log(f"[bench] {name}: {sec * 1e3:.3f} ms/step, {m.n_elem / sec / 1e9:.3f} G elem/s, "
-        f"radix {radix_ms * 1e3:.1f} us = {res['radix_pass']['GBs']:.0f} GB/s")
-    for k, v in sorted(kt.items()):
-        log(f"[bench]   {k:14s} {v[0] / steps:5.1f} launches  {v[1] / steps * 1e3:9.1f} us/step")
+        f"pipeline {res['pipeline_model_GBs']:.0f} GB/s of model bytes")
+    for k, v in kernels.items():
+        gbs = f"{v['GBs']:7.0f} GB/s" if v["GBs"] else ""
+        log(f"[bench]   {k:18s} {v['launches_per_step']:4.1f} x {v['avg_us']:8.1f} us = {v['us_per_step']:8.1f} us/step {gbs}")
     del node, elem, conn
     torch.cuda.empty_cache()
     return m, res
@@ -219,7 +237,7 @@ def main():
     traffic = load_traffic(args.workload)
     rp = main_res["radix_pass"]
     roofline = {"bound": "hbm", "achieved": rp["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": rp["GBs"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": "radix_pass",
+                "frac": rp["GBs"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": rp["kernel"],
                 "algorithmic_bytes_per_launch": rp["bytes_per_launch"], "avg_launch_ms": rp["avg_ms"]}
 
     cpu = None

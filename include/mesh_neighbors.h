@@ -28,7 +28,8 @@
  *    Vertices used by no element get empty rows.  nnz = row_ptr[n_vert].
  *  - Every data pointer (conn, row_ptr, cols, workspace and the batched
  *    descriptor arrays) is a DEVICE pointer owned by the caller; the library
- *    allocates nothing and keeps no state between calls.  `stream` is a
+ *    allocates nothing and keeps no per-call state between calls (the tile
+ *    shape and the timing switch below are process-wide settings).  `stream` is a
  *    hipStream_t (NULL = the null stream).  Calls are asynchronous and
  *    stream-ordered; none synchronises the host except mesh_check.
  *  - Argument errors are returned synchronously before anything is launched.
@@ -119,6 +120,20 @@ const char* mesh_status_string(mesh_status status);
 
 /* Library ABI version, (major << 16) | minor. */
 int32_t mesh_abi_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Tuning.                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Every radix pass of both pipelines uses one tile shape (threads per block x
+ * keys per thread) out of a fixed set built into the library.  The choice is
+ * process-wide and changes only speed, never results.  Shapes are numbered
+ * 0 .. mesh_radix_shape_count() - 1; mesh_set_radix_shape(-1) restores the
+ * default.  Returns MESH_ERR_INVALID_ARG for an unknown shape. */
+int32_t mesh_radix_shape_count(void);
+mesh_status mesh_radix_shape_info(int32_t shape, int32_t* block, int32_t* items);
+mesh_status mesh_set_radix_shape(int32_t shape);
+int32_t mesh_get_radix_shape(void);
 
 /* ------------------------------------------------------------------------ */
 /* Kernel timing (diagnostics, not part of the method).                     */

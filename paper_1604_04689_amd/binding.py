@@ -54,6 +54,10 @@ SIGNATURES = {
     "mesh_status_string": (ctypes.c_char_p, [_c_i32]),
     "mesh_abi_version": (_c_i32, []),
     "mesh_timing_enable": (_c_i32, [_c_i32]),
+    "mesh_radix_shape_count": (_c_i32, []),
+    "mesh_radix_shape_info": (_c_i32, [_c_i32, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]),
+    "mesh_set_radix_shape": (_c_i32, [_c_i32]),
+    "mesh_get_radix_shape": (_c_i32, []),
     "mesh_timing_read": (_c_i32, [ctypes.POINTER(KernelTime), _c_i32]),
 }
 
@@ -76,6 +80,27 @@ def lib() -> ctypes.CDLL:
 
 def status_string(status) -> str:
     return lib().mesh_status_string(int(status)).decode()
+
+
+def radix_shapes():
+    """[(threads per block, keys per thread)] of the radix tile shapes built in."""
+    out = []
+    for i in range(lib().mesh_radix_shape_count()):
+        b, it = _c_i32(0), _c_i32(0)
+        lib().mesh_radix_shape_info(i, ctypes.byref(b), ctypes.byref(it))
+        out.append((b.value, it.value))
+    return out
+
+
+def set_radix_shape(shape: int = -1):
+    """Select the radix tile shape for all later calls (-1 = default)."""
+    st = lib().mesh_set_radix_shape(int(shape))
+    if st != Status.OK:
+        raise MeshError(st, "mesh_set_radix_shape")
+
+
+def get_radix_shape() -> int:
+    return int(lib().mesh_get_radix_shape())
 
 
 def timing_enable(on: bool = True):

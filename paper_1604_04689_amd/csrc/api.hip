@@ -1,6 +1,7 @@
 // C ABI of the one-ring neighbor library: argument checks, workspace sizing
 // and dispatch to the node and element pipelines.  Declared in
 // include/mesh_neighbors.h.
+#include <atomic>
 #include <climits>
 
 #include "../../include/mesh_neighbors.h"
@@ -8,6 +9,7 @@
 #include "elements.hpp"
 #include "internal.hpp"
 #include "launch.hpp"
+#include "radix.hpp"
 
 namespace mnb {
 
@@ -32,6 +34,10 @@ hipError_t zero_words(void* p, size_t bytes, hipStream_t s) {
 hipError_t fill_i32(int32_t* p, int64_t n, int32_t value, hipStream_t s) {
     return fill_words((uint32_t*)p, n, (uint32_t)value, s);
 }
+
+static std::atomic<int> g_radix_shape{DEFAULT_RADIX_SHAPE};
+
+int radix_shape() { return g_radix_shape.load(std::memory_order_relaxed); }
 
 }  // namespace mnb
 
@@ -121,6 +127,23 @@ mesh_status mesh_elem_neighbors(const int32_t* conn, int64_t n_elem, int32_t ety
     hipError_t e = run_elem(p, conn, row_ptr, cols, cols_capacity, workspace, (hipStream_t)stream);
     return e == hipSuccess ? MESH_OK : MESH_ERR_HIP;
 }
+
+int32_t mesh_radix_shape_count(void) { return N_RADIX_SHAPES; }
+
+mesh_status mesh_radix_shape_info(int32_t shape, int32_t* block, int32_t* items) {
+    if (shape < 0 || shape >= N_RADIX_SHAPES || !block || !items) return MESH_ERR_INVALID_ARG;
+    *block = RADIX_SHAPES[shape].block;
+    *items = RADIX_SHAPES[shape].items;
+    return MESH_OK;
+}
+
+mesh_status mesh_set_radix_shape(int32_t shape) {
+    if (shape < -1 || shape >= N_RADIX_SHAPES) return MESH_ERR_INVALID_ARG;
+    g_radix_shape.store(shape < 0 ? DEFAULT_RADIX_SHAPE : shape, std::memory_order_relaxed);
+    return MESH_OK;
+}
+
+int32_t mesh_get_radix_shape(void) { return g_radix_shape.load(std::memory_order_relaxed); }
 
 mesh_status mesh_check(const void* workspace, void* stream) {
     if (!workspace) return MESH_ERR_INVALID_ARG;

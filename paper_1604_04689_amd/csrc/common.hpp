@@ -24,6 +24,7 @@ constexpr int HDR_ERR = 0;          // u32 index of the error word
 constexpr int HDR_TICKET0 = 4;      // u32 index of the first tile ticket
 constexpr int N_TICKETS = 16;
 constexpr int HDR_LONG_COUNT = 32;  // u32 index of the long-row counter
+constexpr int HDR_KEY_COUNT = 33;   // u32 index of a device-side key count
 
 // Decoupled look-back status word: 2 flag bits over a 62-bit value.
 constexpr uint64_t LB_AGG = 1ull << 62;  // value = this tile's own count
@@ -48,11 +49,22 @@ __device__ __forceinline__ void set_error(uint32_t* err, uint32_t bit) {
     atomicOr(err, bit);
 }
 
+__device__ __forceinline__ bool lookback_give_up(uint32_t spins, uint32_t* err) {
+    // give up after SPIN_LIMIT polls, or at once when another wait already
+    // gave up (so a failure cannot chain into long waits)
+    return spins > SPIN_LIMIT ||
+           ((spins & 1023u) == 0 && (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_INTERNAL));
+}
+
 // Exclusive prefix over the tiles before `tile` of one running count whose
-// status words sit `stride` apart (status[t * stride]).  The caller has
-// already published LB_AGG | agg for this tile (or LB_INC for tile 0).  Tiles
-// are handed out in launch order by an atomic ticket, so every earlier tile is
+// status words sit `stride` apart (status[t * stride]), walked by one thread.
+// The statuses of LB_BATCH predecessors are requested together, so one memory
+// round trip covers LB_BATCH steps of the walk.  The caller has already
+// published LB_AGG | agg for this tile (or LB_INC for tile 0).  Tiles are
+// handed out in launch order by an atomic ticket, so every earlier tile is
 // resident and the walk finishes.  Publishes LB_INC | (prefix + agg).
+constexpr int LB_BATCH = 4;
+
 __device__ __forceinline__ uint64_t lookback_prefix(uint64_t* status, int64_t stride, uint32_t tile,
                                                     uint64_t agg, uint32_t* err) {
     if (tile == 0) return 0;
@@ -60,25 +72,70 @@ __device__ __forceinline__ uint64_t lookback_prefix(uint64_t* status, int64_t st
     int64_t t = (int64_t)tile - 1;
     uint32_t spins = 0;
     while (t >= 0) {
-        uint64_t s = lb_load(status + t * stride);
-        uint64_t f = s & LB_FLAG;
-        if (f == 0) {
-            // give up after SPIN_LIMIT polls, or at once when another wait
-            // already gave up (so a failure cannot chain into long waits)
-            if (++spins > SPIN_LIMIT ||
-                ((spins & 1023u) == 0 &&
-                 (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_INTERNAL))) {
+        uint64_t s[LB_BATCH];
+#pragma unroll
+        for (int k = 0; k < LB_BATCH; ++k) s[k] = t - k >= 0 ? lb_load(status + (t - k) * stride) : LB_INC;
+        bool stalled = false, done = false;
+#pragma unroll
+        for (int k = 0; k < LB_BATCH; ++k) {
+            if (done || stalled) continue;
+            const uint64_t f = s[k] & LB_FLAG;
+            if (f == 0) {
+                stalled = true;  // resume the walk at this tile
+                continue;
+            }
+            prefix += s[k] & LB_VAL;
+            --t;
+            done = f == LB_INC || t < 0;
+        }
+        if (done) break;
+        if (stalled) {
+            if (lookback_give_up(++spins, err)) {
                 set_error(err, ERR_INTERNAL);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    lb_store(status + (int64_t)tile * stride, LB_INC | (prefix + agg));
+    return prefix;
+}
+
+// The same for a single running count, walked by a whole wave: lane l reads
+// the status of tile (t - l), the wave finds the nearest inclusive value with
+// a ballot and sums the window with a wave reduction.  Every lane of the wave
+// must call it; all lanes return the prefix, lane 0 publishes.
+__device__ __forceinline__ uint64_t wave_lookback_prefix(uint64_t* status, uint32_t tile, uint64_t agg,
+                                                         uint32_t* err) {
+    const int lane = __lane_id();
+    if (tile == 0) return 0;
+    uint64_t prefix = 0;
+    int64_t t = (int64_t)tile - 1;  // newest tile of the window
+    uint32_t spins = 0;
+    while (true) {
+        const int64_t mine = t - lane;
+        const uint64_t s = mine >= 0 ? lb_load(status + mine) : LB_INC;
+        const uint64_t f = s & LB_FLAG;
+        const uint64_t inc = __ballot(f == LB_INC);
+        const uint64_t none = __ballot(f == 0);
+        // lanes up to and including the first inclusive one must be ready
+        const uint64_t upto = inc ? ((inc & (~inc + 1)) << 1) - 1 : ~0ull;  // lanes 0..first INC
+        if (none & upto) {
+            if (lookback_give_up(++spins, err)) {
+                if (lane == 0) set_error(err, ERR_INTERNAL);
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        prefix += s & LB_VAL;
-        if (f == LB_INC) break;
-        --t;
+        uint64_t v = ((upto >> lane) & 1) ? (s & LB_VAL) : 0;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, WAVE);
+        prefix += v;
+        if (inc) break;
+        t -= WAVE;
     }
-    lb_store(status + (int64_t)tile * stride, LB_INC | (prefix + agg));
+    if (lane == 0) lb_store(status + tile, LB_INC | (prefix + agg));
     return prefix;
 }
 

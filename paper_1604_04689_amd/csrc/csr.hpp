@@ -1,0 +1,151 @@
+// Sorted keys -> CSR: the segmented reduction and scan of the paper
+// (Sec. 2.2.1: counts per vertex by segmented reduction, first indices by
+// segmented scan), done in one pass over the keys sorted ascending.
+#pragma once
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace mnb {
+
+constexpr int UNIQ_BLOCK = 256;
+constexpr int UNIQ_ITEMS = 16;
+constexpr int UNIQ_TILE = UNIQ_BLOCK * UNIQ_ITEMS;
+
+// ---------------------------------------------------------------------------
+// unique_csr over keys (hi << b) | lo sorted ascending, KEY_NONE last.  A key
+// is kept when it is not KEY_NONE and differs from its predecessor; kept keys
+// are compacted into cols (cols[i] = lo).  Where the high part (the vertex)
+// changes between neighbors in sorted order, the row starts of the vertices
+// in between are written, so empty rows get their offsets; the last real key
+// writes the tail up to row_ptr[n_vert] = nnz; with no real key at all the
+// first tile writes row_ptr = 0.  The key count is n, or *n_dev when given.
+// Wave w of a tile owns positions [w*64*ITEMS, (w+1)*64*ITEMS); compaction
+// offsets come from ballots, a scan over the waves and a look-back across
+// tiles (one wave walks 64 earlier tiles per step).
+// ---------------------------------------------------------------------------
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void unique_csr_kernel(const uint64_t* __restrict__ keys, int64_t n_host,
+                                                          const uint32_t* __restrict__ n_dev, uint32_t b,
+                                                          int32_t n_vert, int32_t* __restrict__ cols,
+                                                          int64_t cols_cap, int32_t* __restrict__ row_ptr,
+                                                          uint64_t* lookback, uint32_t* ticket, uint32_t* err) {
+    constexpr int WAVES = BLOCK / WAVE;
+    constexpr int TILE = BLOCK * ITEMS;
+    static_assert(ITEMS <= 32, "keep flags in one word");
+    __shared__ uint64_t s_keys[TILE + 2];  // [0] predecessor, [1..tile_n] tile, [tile_n+1] successor
+    __shared__ uint32_t s_wtot[WAVES];
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_prefix;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const int wid = tid / WAVE;
+    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const int64_t n = n_dev ? tmin<int64_t>(n_host, (int64_t)*n_dev) : n_host;
+    const uint32_t tile = s_tile;
+    const int64_t base = (int64_t)tile * TILE;
+    const int tile_n = (int)tmin<int64_t>(TILE, n - base);  // may be <= 0 when n is a device count
+    if (tile_n <= 0) {
+        // past the device key count: no later tile has keys either
+        if (tile == 0)
+            for (int64_t v = tid; v <= n_vert; v += BLOCK) row_ptr[v] = 0;
+        return;
+    }
+    const int wpos = wid * WAVE * ITEMS + lane;
+    {
+        uint64_t k[ITEMS];  // all loads in flight before the LDS stores
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int pos = wpos + j * WAVE;
+            k[j] = pos < tile_n ? keys[base + pos] : KEY_NONE;
+        }
+        uint64_t halo = KEY_NONE;
+        if (tid == 0 && base > 0) halo = keys[base - 1];
+        if (tid == 1 && base + tile_n < n) halo = keys[base + tile_n];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int pos = wpos + j * WAVE;
+            if (pos < tile_n) s_keys[1 + pos] = k[j];
+        }
+        if (tid == 0) s_keys[0] = halo;
+        if (tid == 1) s_keys[tile_n + 1] = halo;
+    }
+    __syncthreads();
+
+    uint32_t keep_bits = 0, wsum = 0;
+    uint32_t jcnt[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int pos = wpos + j * WAVE;
+        bool keep = false;
+        if (pos < tile_n) {
+            const uint64_t cur = s_keys[1 + pos];
+            keep = cur != KEY_NONE && (base + pos == 0 || cur != s_keys[pos]);
+        }
+        keep_bits |= (uint32_t)keep << j;
+        jcnt[j] = wsum;  // kept keys of this wave before item j
+        wsum += (uint32_t)__popcll(__ballot(keep));
+    }
+    if (lane == 0) s_wtot[wid] = wsum;
+    __syncthreads();
+    uint32_t woff = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+        const uint32_t t = s_wtot[w];
+        woff += w < wid ? t : 0u;
+        total += t;
+    }
+    if (wid == 0) {
+        if (lane == 0) lb_store(lookback + tile, (tile == 0 ? LB_INC : LB_AGG) | total);
+        const uint64_t before = wave_lookback_prefix(lookback, tile, total, err);
+        if (lane == 0) s_prefix = before;
+    }
+    __syncthreads();
+    const int64_t prefix = (int64_t)s_prefix + woff;
+    const uint64_t lt_mask = (1ull << lane) - 1;
+    const uint64_t lo_mask = b >= 64 ? ~0ull : (1ull << b) - 1;
+    bool cap_hit = false, bad = false;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int pos = wpos + j * WAVE;
+        const bool keep = (keep_bits >> j) & 1u;
+        const int64_t idx = prefix + jcnt[j] + __popcll(__ballot(keep) & lt_mask);
+        if (pos >= tile_n) continue;
+        const uint64_t cur = s_keys[1 + pos];
+        const int64_t gi = base + pos;
+        if (keep) {
+            if (idx < cols_cap) cols[idx] = (int32_t)(cur & lo_mask);
+            else cap_hit = true;
+        }
+        if (cur != KEY_NONE) {
+            const int64_t hi = (int64_t)(cur >> b);
+            if (hi >= n_vert) {  // only after a failed look-back left stale keys
+                bad = true;
+                continue;
+            }
+            const int64_t prev_hi = gi == 0 ? -1 : tmin<int64_t>((int64_t)(s_keys[pos] >> b), n_vert);
+            for (int64_t v = prev_hi + 1; v <= hi; ++v) row_ptr[v] = (int32_t)idx;
+            const uint64_t next = s_keys[pos + 2];
+            if (gi == n - 1 || next == KEY_NONE) {
+                const int32_t nnz = (int32_t)(idx + (keep ? 1 : 0));
+                for (int64_t v = hi + 1; v <= n_vert; ++v) row_ptr[v] = nnz;
+            }
+        } else if (gi == 0) {
+            for (int64_t v = 0; v <= n_vert; ++v) row_ptr[v] = 0;  // no real key at all
+        }
+    }
+    if (cap_hit) set_error(err, ERR_CAPACITY);
+    if (bad) set_error(err, ERR_INTERNAL);
+}
+
+// Tiles: ceil(n_host / UNIQ_TILE); the look-back array needs that many words.
+inline hipError_t launch_unique_csr(const char* name, const uint64_t* keys, int64_t n_host, const uint32_t* n_dev, uint32_t b,
+                                    int32_t n_vert, int32_t* cols, int64_t cols_cap, int32_t* row_ptr,
+                                    uint64_t* lookback, uint32_t* ticket, uint32_t* err, hipStream_t s) {
+    return launch(name, unique_csr_kernel<UNIQ_BLOCK, UNIQ_ITEMS>, dim3((unsigned)ceil_div(n_host, UNIQ_TILE)),
+                  dim3(UNIQ_BLOCK), s, keys, n_host, n_dev, b, n_vert, cols, cols_cap, row_ptr, lookback, ticket, err);
+}
+
+}  // namespace mnb

@@ -35,10 +35,12 @@ struct ElemPlan {
     int64_t n_elem = 0;
     int32_t etype = 0;
     int32_t n_vert = 0;
-    int64_t n_slots = 0;      // npe * n_elem
-    int64_t n_stiles = 0;     // scan tiles over the vertices
-    int64_t long_cap = 0;     // capacity of the long-row list
-    size_t off_cursor = 0, off_lb = 0, off_long = 0;
+    int64_t n_slots = 0;      // npe * n_elem (pairs before dropping repeats)
+    uint32_t id_bits = 1;     // bits of a vertex id
+    int n_pass = 0;           // radix passes over the vertex bits
+    int64_t n_tiles = 0;      // radix tiles (room for any tile shape)
+    int64_t n_utiles = 0;     // CSR tiles
+    size_t off_hist = 0, off_ulb = 0, off_lb0 = 0, off_lb1 = 0, off_keys0 = 0, off_keys1 = 0;
     size_t zero_bytes = 0;
     size_t total = 0;
 };

@@ -1,0 +1,204 @@
+// One stable LSD radix pass over 64-bit keys (8-bit digit), onesweep style:
+// tiles ranked in LDS, decoupled look-back across tiles, keys staged in digit
+// order in LDS and written out in coalesced runs.  The key source is a
+// template parameter, so the first pass of a pipeline can generate its keys
+// straight from the connectivity instead of reading an emitted key array.
+#pragma once
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace mnb {
+
+constexpr int RBITS = 8;
+constexpr int RADIX = 1 << RBITS;
+
+// Keys read from an array.  Every position holds a participating key.
+struct KeyArraySrc {
+    const uint64_t* __restrict__ keys;
+    static constexpr bool kSkipNone = false;
+    __device__ __forceinline__ uint64_t load(int64_t i) const { return keys[i]; }
+};
+
+// Tile shapes the library is built with: threads per block x keys per thread.
+// The LDS staging area is 8 * BLOCK * ITEMS bytes.
+struct RadixShape {
+    int block, items;
+};
+constexpr int N_RADIX_SHAPES = 5;
+constexpr RadixShape RADIX_SHAPES[N_RADIX_SHAPES] = {{512, 16}, {256, 32}, {512, 12}, {512, 24}, {1024, 8}};
+constexpr int DEFAULT_RADIX_SHAPE = 0;
+
+// ---------------------------------------------------------------------------
+// radix_pass: stable scatter of the keys by digit (key >> shift) & mask.
+//
+// Tile t (taken by atomic ticket, so every earlier tile is already resident)
+// holds BLOCK*ITEMS source positions.  Wave w owns a contiguous run of
+// 64*ITEMS positions, item j of lane l at offset j*64 + l, so (j, lane) order
+// is input order.
+//
+// Order of work inside a tile, chosen so that the serial chain through the
+// tiles (each tile's global offsets depend on all earlier tiles) is short:
+//  1. load the keys and count the tile's digits with LDS atomics;
+//  2. publish the tile's digit counts at once, then threads 0..255 walk back
+//     over earlier tiles (decoupled look-back) for their digit's offset while
+//     the other waves already rank their keys;
+//  3. rank: for each item, the lanes holding the same digit are found with one
+//     ballot per digit bit; the lowest such lane bumps the wave's private
+//     digit counter in LDS and the others take their rank from it; wave
+//     counts are then scanned in wave order (stability);
+//  4. stage the keys in LDS in digit order and write them to their global
+//     slots in coalesced runs.
+// Each tile also clears its status slots in `lookback_next` (null for the
+// last pass), the array the following pass uses.  `hist` is the global count
+// of every digit value over the participating keys of the whole pass.  When
+// Src::kSkipNone is set, KEY_NONE marks a position without a key.
+// ---------------------------------------------------------------------------
+template <int BLOCK, int ITEMS, class Src>
+__global__ __launch_bounds__(BLOCK) void radix_pass_kernel(Src src, uint64_t* __restrict__ out, int64_t n,
+                                                          uint32_t shift, uint32_t bits,
+                                                          const uint32_t* __restrict__ hist, uint64_t* lookback,
+                                                          uint64_t* lookback_next, uint32_t* ticket, uint32_t* err) {
+    static_assert(BLOCK >= RADIX, "one thread per digit");
+    constexpr int WAVES = BLOCK / WAVE;
+    constexpr int TILE = BLOCK * ITEMS;
+    __shared__ uint64_t s_keys[TILE];
+    __shared__ uint32_t s_whist[WAVES][RADIX];
+    __shared__ uint32_t s_cnt[RADIX];
+    __shared__ uint32_t s_tile_off[RADIX];
+    __shared__ int64_t s_glob[RADIX];
+    __shared__ uint32_t s_tmp[WAVES];
+    __shared__ uint32_t s_tile;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const int wid = tid / WAVE;
+    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+    for (int i = tid; i < WAVES * RADIX; i += BLOCK) (&s_whist[0][0])[i] = 0;
+    for (int i = tid; i < RADIX; i += BLOCK) s_cnt[i] = 0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const int64_t tile_base = (int64_t)tile * TILE;
+    const uint32_t dmask = (1u << bits) - 1;
+
+    // ---- 1. load (lanes of a wave read 64 consecutive positions), count ------
+    const int64_t wbase = tile_base + (int64_t)wid * WAVE * ITEMS + lane;
+    uint64_t key[ITEMS];
+    uint32_t valid_bits = 0;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int64_t idx = wbase + j * WAVE;
+        key[j] = idx < n ? src.load(idx) : KEY_NONE;
+        const bool valid = idx < n && !(Src::kSkipNone && key[j] == KEY_NONE);
+        valid_bits |= (uint32_t)valid << j;
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+        if ((valid_bits >> j) & 1u) atomicAdd(&s_cnt[(uint32_t)(key[j] >> shift) & dmask], 1u);
+    __syncthreads();
+
+    // ---- 2. publish, tile offsets, look-back ---------------------------------
+    const uint32_t tile_cnt = tid < RADIX ? s_cnt[tid] : 0u;
+    if (tid < RADIX) lb_store(lookback + (int64_t)tile * RADIX + tid, (tile == 0 ? LB_INC : LB_AGG) | tile_cnt);
+    uint32_t tile_total;
+    const uint32_t toff = block_exclusive_sum<BLOCK>(tile_cnt, s_tmp, &tile_total);
+    uint32_t hist_total;
+    const uint32_t gstart = block_exclusive_sum<BLOCK>(tid < RADIX ? hist[tid] : 0u, s_tmp, &hist_total);
+    if (tid < RADIX) {
+        s_tile_off[tid] = toff;
+        const uint64_t before = lookback_prefix(lookback + tid, RADIX, tile, tile_cnt, err);
+        s_glob[tid] = (int64_t)gstart + (int64_t)before - (int64_t)toff;
+        if (lookback_next) lookback_next[(int64_t)tile * RADIX + tid] = 0;  // slot of the next pass
+    }
+
+    // ---- 3. rank within the wave ---------------------------------------------
+    const uint64_t lt_mask = (1ull << lane) - 1;
+    uint32_t rank[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const bool valid = (valid_bits >> j) & 1u;
+        const uint32_t dg = (uint32_t)(key[j] >> shift) & dmask;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < RBITS; ++bit) {
+            const bool on = (dg >> bit) & 1u;
+            const uint64_t vote = __ballot(on);
+            peers &= on ? vote : ~vote;
+        }
+        const uint32_t below = __popcll(peers & lt_mask);
+        const int leader = __ffsll((unsigned long long)peers) - 1;
+        uint32_t base = 0;
+        if (valid && below == 0) {
+            base = s_whist[wid][dg];
+            s_whist[wid][dg] = base + (uint32_t)__popcll(peers);
+        }
+        base = __shfl(base, leader & (WAVE - 1), WAVE);
+        rank[j] = base + below;
+    }
+    __syncthreads();
+    if (tid < RADIX) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            const uint32_t c = s_whist[w][tid];
+            s_whist[w][tid] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+
+    // ---- 4. stage in digit order, then write out -------------------------------
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        if ((valid_bits >> j) & 1u) {
+            const uint32_t dg = (uint32_t)(key[j] >> shift) & dmask;
+            s_keys[s_tile_off[dg] + s_whist[wid][dg] + rank[j]] = key[j];
+        }
+    }
+    __syncthreads();
+    const int64_t limit = hist_total;  // participating keys of the pass = output size
+    bool bad = false;
+    for (int i = tid; i < (int)tile_total; i += BLOCK) {
+        const uint64_t k = s_keys[i];
+        const uint32_t dg = (uint32_t)(k >> shift) & dmask;
+        const int64_t dst = s_glob[dg] + i;
+        if ((uint64_t)dst < (uint64_t)limit) out[dst] = k;
+        else bad = true;
+    }
+    if (bad) set_error(err, ERR_INTERNAL);
+}
+
+template <int BLOCK, int ITEMS, class Src>
+hipError_t launch_radix_shape(const char* name, Src src, uint64_t* out, int64_t n, uint32_t shift, uint32_t bits, const uint32_t* hist,
+                              uint64_t* lb, uint64_t* lb_next, uint32_t* ticket, uint32_t* err, hipStream_t s) {
+    const int64_t tiles = ceil_div(n, (int64_t)BLOCK * ITEMS);
+    return launch(name, radix_pass_kernel<BLOCK, ITEMS, Src>, dim3((unsigned)tiles), dim3(BLOCK), s, src,
+                  out, n, shift, bits, hist, lb, lb_next, ticket, err);
+}
+
+// Launches one radix pass with tile shape RADIX_SHAPES[shape].  The look-back
+// arrays need room for ceil(n / min_radix_tile()) tiles.
+template <class Src>
+hipError_t launch_radix_pass(const char* name, int shape, Src src, uint64_t* out, int64_t n, uint32_t shift, uint32_t bits,
+                             const uint32_t* hist, uint64_t* lb, uint64_t* lb_next, uint32_t* ticket, uint32_t* err,
+                             hipStream_t s) {
+    switch (shape) {
+        case 1: return launch_radix_shape<256, 32>(name, src, out, n, shift, bits, hist, lb, lb_next, ticket, err, s);
+        case 2: return launch_radix_shape<512, 12>(name, src, out, n, shift, bits, hist, lb, lb_next, ticket, err, s);
+        case 3: return launch_radix_shape<512, 24>(name, src, out, n, shift, bits, hist, lb, lb_next, ticket, err, s);
+        case 4: return launch_radix_shape<1024, 8>(name, src, out, n, shift, bits, hist, lb, lb_next, ticket, err, s);
+        default: return launch_radix_shape<512, 16>(name, src, out, n, shift, bits, hist, lb, lb_next, ticket, err, s);
+    }
+}
+
+constexpr int min_radix_tile() {
+    int m = RADIX_SHAPES[0].block * RADIX_SHAPES[0].items;
+    for (int i = 1; i < N_RADIX_SHAPES; ++i)
+        if (RADIX_SHAPES[i].block * RADIX_SHAPES[i].items < m) m = RADIX_SHAPES[i].block * RADIX_SHAPES[i].items;
+    return m;
+}
+
+// Process-wide tile shape used by every radix pass (mesh_set_radix_shape).
+int radix_shape();
+
+}  // namespace mnb

@@ -189,3 +189,38 @@ def test_full_kuhn96_lattice_rows(kuhn96_mesh):
     m = kuhn96_mesh
     want = pins.lattice_node_csr(m.dims, pins.KUHN_STEPS, m.perm)
     assert_same(gpu_csr("node", m.conn, m.etype, m.n_vert), want, "kuhn96 lattice")
+
+
+def test_every_radix_shape_same_result(oracle_mod):
+    nb = _nb()
+    cases = [mg.kuhn_tet_grid(14, 3), mg.random_mesh(33333, 5000, 2, 4), mg.random_mesh(20001, 2 ** 25 - 3, 0, 5)]
+    try:
+        for shape in range(len(nb.radix_shapes())):
+            nb.set_radix_shape(shape)
+            for m in cases:
+                check_both(oracle_mod, m.conn, m.etype, m.n_vert, f"{m.name} shape {nb.radix_shapes()[shape]}")
+    finally:
+        nb.set_radix_shape(-1)
+
+
+@pytest.mark.slow
+def test_huge_vertex_count_sparse_use(oracle_mod):
+    # n_vert = 2^29 + 5: 60-bit node keys (8 radix passes); element buckets
+    # counted with global atomics (more than 2^14 buckets).  Expected CSR: the
+    # oracle on the used ids relabelled 0..k-1, expanded back.
+    n_vert = 2 ** 29 + 5
+    rng = np.random.default_rng(17)
+    used = np.unique(np.concatenate([rng.integers(0, n_vert, 3000), [0, n_vert - 1]]))
+    conn_local = rng.integers(0, used.shape[0], size=(4000, 4)).astype(np.int32)
+    conn = used[conn_local].astype(np.int32)
+    for kind, fn in (("node", oracle_mod.node_neighbors), ("elem", oracle_mod.elem_neighbors)):
+        lr, lc = fn(conn_local, 1, used.shape[0])
+        if kind == "node":
+            lc = used[lc].astype(np.int32)
+        counts = np.zeros(n_vert, dtype=np.int64)
+        counts[used] = np.diff(lr)
+        want_r = np.zeros(n_vert + 1, dtype=np.int64)
+        np.cumsum(counts, out=want_r[1:])
+        gr, gc = gpu_csr(kind, conn, 1, n_vert)
+        assert np.array_equal(gr.astype(np.int64), want_r), kind
+        assert np.array_equal(gc, lc), kind
