@@ -178,6 +178,109 @@ def run_workload(name, steps, warmup, torch, nb):
     return m, res
 
 
+def run_batched(steps, warmup, torch, nb, per_mesh_steps=2):
+    """512 mixed meshes: one batched launch sequence per relation vs 512
+    plain single-mesh calls per relation, on one stream."""
+    from paper_1604_04689_amd import meshgen as mg
+    t = time.time()
+    meshes = [s.build() for s in mg.batch_specs()]
+    log(f"[bench] batch512: {len(meshes)} meshes, F={sum(m.n_elem for m in meshes)} ({time.time() - t:.1f}s)")
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    desc = [(m.n_elem, m.etype, m.n_vert) for m in meshes]
+    conn = torch.as_tensor(nb.concat_conn([m.conn for m in meshes])).to(dev)
+    node = nb.BatchBuild("node", desc, dev)
+    elem = nb.BatchBuild("elem", desc, dev)
+    total_f = sum(m.n_elem for m in meshes)
+
+    def step():
+        node.launch(conn, stream)
+        elem.launch(conn, stream)
+
+    for _ in range(max(warmup, 1)):
+        step()
+    node.check(stream)
+    elem.check(stream)
+    nb.timing_read()
+    nb.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nb.timing_enable(False)
+    kt = nb.timing_read()
+    node.check(stream)
+    elem.check(stream)
+    batched = (t1 - t0) / steps
+    del node, elem
+
+    # the same meshes, one plain call per mesh and relation
+    conns = [torch.as_tensor(m.conn).to(dev) for m in meshes]
+    builds = [(nb.NeighborBuild("node", m.n_elem, m.etype, m.n_vert, dev),
+               nb.NeighborBuild("elem", m.n_elem, m.etype, m.n_vert, dev)) for m in meshes]
+
+    def step_each():
+        for c, (bn, be) in zip(conns, builds):
+            bn.launch(c, stream)
+            be.launch(c, stream)
+
+    step_each()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(per_mesh_steps):
+        step_each()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for bn, be in builds[:8]:
+        bn.check(stream)
+        be.check(stream)
+    per_mesh = (t1 - t0) / per_mesh_steps
+    del builds, conns
+    torch.cuda.empty_cache()
+    res = {"meshes": len(meshes), "n_elem": total_f,
+           "batched_ms_per_step": batched * 1e3, "batched_elements_per_s": total_f / batched,
+           "per_mesh_ms_per_step": per_mesh * 1e3, "per_mesh_elements_per_s": total_f / per_mesh,
+           "batched_over_per_mesh": per_mesh / batched,
+           "kernel_ms_per_step": {k: v[1] / steps for k, v in sorted(kt.items())}}
+    log(f"[bench] batch512: batched {batched * 1e3:.2f} ms/step ({total_f / batched / 1e9:.2f} G elem/s), "
+        f"per-mesh calls {per_mesh * 1e3:.2f} ms/step ({total_f / per_mesh / 1e9:.2f} G elem/s)")
+    return meshes, res
+
+
+def run_serving(meshes, capacity, torch, nb, n_req=600, warm=60, load=0.8, slots=4, max_batch=32,
+                budget=64 << 30):
+    """Poisson arrivals of requests drawn from the batch's meshes at an
+    offered load of `load` x the batched capacity (elements/s), admitted by a
+    device-memory budget for their buffers; continuous batching over `slots`
+    streams.  Inputs start in host memory (the upload is part of latency)."""
+    import numpy as np
+    from paper_1604_04689_amd import meshgen as mg
+    from paper_1604_04689_amd import serve
+    rng = np.random.default_rng(mg.BASE_SEED + 4)
+    pick = rng.integers(0, len(meshes), size=n_req + warm)
+    mean_f = float(np.mean([meshes[i].n_elem for i in pick]))
+    rate = load * capacity / mean_f
+    arr = mg.poisson_arrivals(n_req + warm, rate, seed=mg.BASE_SEED + 5)
+    reqs = [serve.Request(i, float(t), meshes[j].conn, meshes[j].etype, meshes[j].n_vert)
+            for i, (j, t) in enumerate(zip(pick, arr))]
+    srv = serve.Server(serve.GpuExecutor(slots), serve.RealClock(), n_slots=slots, budget_bytes=budget,
+                       max_batch=max_batch)
+    t0 = time.perf_counter()
+    done = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    summ = serve.latency_summary([r for r in done if r.rid >= warm])
+    summ.update({"offered_load": load, "offered_elements_per_s": rate * mean_f, "slots": slots,
+                 "max_batch": max_batch, "budget_bytes": budget, "batches": srv.batches,
+                 "mean_batch": float(np.mean(srv.batch_sizes)), "peak_reserved_bytes": srv.peak_in_use,
+                 "wall_s": wall, "warmup_requests": warm})
+    log(f"[bench] serve: {summ['requests']} requests at load {load}: p50 {summ['p50_ms']:.2f} ms, "
+        f"p99 {summ['p99_ms']:.2f} ms, {summ['elements_per_s'] / 1e9:.2f} G elem/s sustained, "
+        f"{srv.batches} batches")
+    return summ
+
+
 def cpu_baseline(m):
     import oracle
     t0 = time.perf_counter()
@@ -209,6 +312,8 @@ def main():
     ap.add_argument("--workload", default="tri2048", choices=sorted(WORKLOADS))
     ap.add_argument("--also", default="kuhn96", help="comma list of extra workloads reported beside ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-mesh batch and the serving stream")
+    ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (for counter scaling under rocprofv3)")
     args = ap.parse_args()
@@ -233,6 +338,12 @@ def main():
     others = {}
     for w in [x for x in args.also.split(",") if x and x != args.workload]:
         _, others[w] = run_workload(w, args.steps, args.warmup, torch, nb)
+
+    if not args.no_batch:
+        meshes, others["batch512"] = run_batched(max(3, args.steps // 4), 1, torch, nb)
+        others["serve"] = run_serving(meshes, others["batch512"]["batched_elements_per_s"], torch, nb,
+                                      n_req=args.serve_requests)
+        del meshes
 
     traffic = load_traffic(args.workload)
     rp = main_res["radix_pass"]

@@ -107,6 +107,56 @@ mesh_status mesh_elem_neighbors(const int32_t* conn, int64_t n_elem, int32_t ety
                                 void* workspace, size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Batches of independent meshes in one launch sequence.                    */
+/* ------------------------------------------------------------------------ */
+
+/* One mesh of a batch: a record in DEVICE memory, filled by the caller.  All
+ * meshes share one int32 connectivity array; the ids inside a mesh are local
+ * to it, in [0, n_vert).  Offsets are prefix sums over the meshes before it,
+ * in order: pair_off of 2 * edges_per_element * n_elem, slot_off of
+ * nodes_per_element * n_elem, vert_off of n_vert.  Meshes may mix types. */
+typedef struct {
+    int64_t conn_off;  /* index of the mesh's first id in the shared conn */
+    int64_t n_elem;
+    int64_t pair_off;  /* first directed edge pair of the mesh            */
+    int64_t slot_off;  /* first (node, element) slot of the mesh          */
+    int32_t vert_off;  /* first global vertex of the mesh                 */
+    int32_t n_vert;
+    int32_t etype;     /* mesh_elem_type                                  */
+    int32_t reserved;  /* 0                                               */
+} mesh_segment;
+
+/* Neighboring nodes of every vertex of every mesh of a batch.
+ *   segs         device mesh_segment [n_mesh]
+ *   total_pairs  sum of 2 * edges_per_element * n_elem (the pair_off end)
+ *   total_vert   sum of n_vert;  max_vert = largest n_vert of one mesh
+ *   row_ptr      device int32 [total_vert + 1]: one CSR over all vertices,
+ *                mesh m owning rows vert_off[m] .. vert_off[m] + n_vert[m]
+ *   cols         device int32 [cols_capacity]; entries are LOCAL vertex ids
+ * The slice row_ptr[vert_off .. vert_off + n_vert] - row_ptr[vert_off] with its
+ * cols equals mesh_node_neighbors on that mesh alone.  Keys are
+ * (vert_off + u) << bits(max_vert) | w, sorted by LSD radix passes over
+ * bits(total_vert) + bits(max_vert) bits.  Records inconsistent with
+ * total_pairs or with a mesh's own size raise MESH_ERR_INDEX_RANGE on the
+ * device; conn itself must cover every record (not checkable here). */
+mesh_status mesh_batch_node_neighbors_query(int32_t n_mesh, int64_t total_pairs, int32_t total_vert,
+                                            int32_t max_vert, size_t* workspace_bytes, int64_t* cols_capacity);
+mesh_status mesh_batch_node_neighbors(const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
+                                      int64_t total_pairs, int32_t total_vert, int32_t max_vert, int32_t* row_ptr,
+                                      int32_t* cols, int64_t cols_capacity, void* workspace, size_t workspace_bytes,
+                                      void* stream);
+
+/* Neighboring elements of every vertex of every mesh of a batch: as above,
+ * with total_slots = sum of nodes_per_element * n_elem; cols hold element
+ * ids LOCAL to the mesh.  Keys (vert_off + v) << 32 | e, sorted over
+ * bits(total_vert) bits. */
+mesh_status mesh_batch_elem_neighbors_query(int32_t n_mesh, int64_t total_slots, int32_t total_vert,
+                                            size_t* workspace_bytes, int64_t* cols_capacity);
+mesh_status mesh_batch_elem_neighbors(const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
+                                      int64_t total_slots, int32_t total_vert, int32_t* row_ptr, int32_t* cols,
+                                      int64_t cols_capacity, void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Diagnostics.                                                             */
 /* ------------------------------------------------------------------------ */
 

@@ -53,6 +53,14 @@ SIGNATURES = {
     "mesh_check": (_c_i32, [_c_p, _c_p]),
     "mesh_status_string": (ctypes.c_char_p, [_c_i32]),
     "mesh_abi_version": (_c_i32, []),
+    "mesh_batch_node_neighbors_query": (_c_i32, [_c_i32, _c_i64, _c_i32, _c_i32, ctypes.POINTER(_c_sz),
+                                                 ctypes.POINTER(_c_i64)]),
+    "mesh_batch_node_neighbors": (_c_i32, [_c_p, _c_p, _c_i32, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64, _c_p,
+                                           _c_sz, _c_p]),
+    "mesh_batch_elem_neighbors_query": (_c_i32, [_c_i32, _c_i64, _c_i32, ctypes.POINTER(_c_sz),
+                                                 ctypes.POINTER(_c_i64)]),
+    "mesh_batch_elem_neighbors": (_c_i32, [_c_p, _c_p, _c_i32, _c_i64, _c_i32, _c_p, _c_p, _c_i64, _c_p, _c_sz,
+                                           _c_p]),
     "mesh_timing_enable": (_c_i32, [_c_i32]),
     "mesh_radix_shape_count": (_c_i32, []),
     "mesh_radix_shape_info": (_c_i32, [_c_i32, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]),
@@ -220,3 +228,122 @@ def elem_neighbors(conn, etype, n_vert, stream=None):
     b = NeighborBuild("elem", _n_elem(conn, etype), etype, n_vert, conn.device)
     b.launch(conn, stream)
     return b.result(stream)
+
+
+# ---------------------------------------------------------------------------
+# Batches of meshes
+# ---------------------------------------------------------------------------
+
+EDGES_PER_ELEM = {TRI3: 3, TET4: 6, HEX8: 12}
+
+
+def segment_table(meshes):
+    """mesh_segment records (numpy structured array, 48 bytes each) for a
+    list of (n_elem, etype, n_vert), meshes laid out back to back in one
+    shared connectivity array, plus the totals (pairs, slots, vertices, ids)."""
+    import numpy as np
+
+    dt = np.dtype([("conn_off", "<i8"), ("n_elem", "<i8"), ("pair_off", "<i8"), ("slot_off", "<i8"),
+                   ("vert_off", "<i4"), ("n_vert", "<i4"), ("etype", "<i4"), ("reserved", "<i4")])
+    assert dt.itemsize == 48
+    seg = np.zeros(len(meshes), dtype=dt)
+    conn_off = pair_off = slot_off = vert_off = 0
+    for i, (n_elem, etype, n_vert) in enumerate(meshes):
+        npe, ne = NODES_PER_ELEM[int(etype)], EDGES_PER_ELEM[int(etype)]
+        seg[i] = (conn_off, n_elem, pair_off, slot_off, vert_off, n_vert, etype, 0)
+        conn_off += npe * n_elem
+        pair_off += 2 * ne * n_elem
+        slot_off += npe * n_elem
+        vert_off += n_vert
+    return seg, {"pairs": pair_off, "slots": slot_off, "vert": vert_off, "ids": conn_off,
+                 "max_vert": max([int(m[2]) for m in meshes], default=0)}
+
+
+class BatchBuild:
+    """Device buffers for one relation ("node" or "elem") of a batch of meshes.
+
+    ``meshes`` is a list of (n_elem, etype, n_vert); the connectivity passed to
+    ``launch`` is all meshes' int32 ids back to back, each mesh's ids local.
+    ``result`` gives the global CSR (cols in local ids); ``mesh_csr(m)`` the
+    slice of mesh m rebased to start at 0."""
+
+    def __init__(self, kind, meshes, device="cuda"):
+        import torch
+
+        if kind not in ("node", "elem"):
+            raise ValueError(kind)
+        self.kind = kind
+        self.device = torch.device(device)
+        seg, tot = segment_table(meshes)
+        self.seg_host = seg
+        self.totals = tot
+        self.n_mesh = len(meshes)
+        self.segs = torch.from_numpy(seg.view("u1")).to(self.device) if len(meshes) else \
+            torch.zeros(48, dtype=torch.uint8, device=self.device)
+        ws, cap = _c_sz(0), _c_i64(0)
+        if kind == "node":
+            st = lib().mesh_batch_node_neighbors_query(self.n_mesh, tot["pairs"], tot["vert"], tot["max_vert"],
+                                                       ctypes.byref(ws), ctypes.byref(cap))
+        else:
+            st = lib().mesh_batch_elem_neighbors_query(self.n_mesh, tot["slots"], tot["vert"], ctypes.byref(ws),
+                                                       ctypes.byref(cap))
+        if st != Status.OK:
+            raise MeshError(st, f"mesh_batch_{kind}_neighbors_query")
+        self.ws_bytes = int(ws.value)
+        self.cols_capacity = int(cap.value)
+        self._ws_raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        pad = (-self._ws_raw.data_ptr()) % 256
+        self.workspace = self._ws_raw[pad:pad + self.ws_bytes]
+        self.row_ptr = torch.empty(tot["vert"] + 1, dtype=torch.int32, device=self.device)
+        self.cols = torch.empty(max(self.cols_capacity, 1), dtype=torch.int32, device=self.device)
+
+    def launch(self, conn, stream=None):
+        import torch
+
+        if conn.device != self.device or conn.dtype != torch.int32 or not conn.is_contiguous():
+            raise ValueError("conn must be a contiguous int32 tensor on the build's device")
+        if conn.numel() != self.totals["ids"]:
+            raise ValueError(f"conn has {conn.numel()} ids, the segments cover {self.totals['ids']}")
+        t = self.totals
+        if self.kind == "node":
+            st = lib().mesh_batch_node_neighbors(_ptr(conn), _ptr(self.segs), self.n_mesh, t["pairs"], t["vert"],
+                                                 t["max_vert"], _ptr(self.row_ptr), _ptr(self.cols),
+                                                 self.cols_capacity, _ptr(self.workspace), self.ws_bytes,
+                                                 _stream_handle(stream, self.device))
+        else:
+            st = lib().mesh_batch_elem_neighbors(_ptr(conn), _ptr(self.segs), self.n_mesh, t["slots"], t["vert"],
+                                                 _ptr(self.row_ptr), _ptr(self.cols), self.cols_capacity,
+                                                 _ptr(self.workspace), self.ws_bytes,
+                                                 _stream_handle(stream, self.device))
+        if st != Status.OK:
+            raise MeshError(st, f"mesh_batch_{self.kind}_neighbors")
+
+    def check(self, stream=None):
+        st = lib().mesh_check(_ptr(self.workspace), _stream_handle(stream, self.device))
+        if st != Status.OK:
+            raise MeshError(st, "mesh_check")
+
+    def result(self, stream=None):
+        self.check(stream)
+        nnz = int(self.row_ptr[-1].item())
+        return self.row_ptr, self.cols[:nnz]
+
+    def mesh_csr(self, m, row_ptr_host=None):
+        """(row_ptr, cols) of mesh m alone, as device tensors, after result()."""
+        seg = self.seg_host[m]
+        v0, nv = int(seg["vert_off"]), int(seg["n_vert"])
+        rp = self.row_ptr[v0:v0 + nv + 1]
+        if row_ptr_host is not None:
+            a, b = int(row_ptr_host[v0]), int(row_ptr_host[v0 + nv])
+        else:
+            a, b = int(rp[0].item()), int(rp[-1].item())
+        return rp - a, self.cols[a:b]
+
+
+def concat_conn(conns):
+    """One int32 array holding the connectivities back to back (row-major)."""
+    import numpy as np
+
+    if not conns:
+        return np.zeros(0, dtype=np.int32)
+    return np.ascontiguousarray(np.concatenate([np.asarray(c, dtype=np.int32).ravel() for c in conns]))

@@ -128,6 +128,70 @@ mesh_status mesh_elem_neighbors(const int32_t* conn, int64_t n_elem, int32_t ety
     return e == hipSuccess ? MESH_OK : MESH_ERR_HIP;
 }
 
+mesh_status mesh_batch_node_neighbors_query(int32_t n_mesh, int64_t total_pairs, int32_t total_vert,
+                                            int32_t max_vert, size_t* workspace_bytes, int64_t* cols_capacity) {
+    if (n_mesh < 0 || total_pairs < 0 || total_vert < 0 || max_vert < 0 || max_vert > total_vert)
+        return MESH_ERR_INVALID_ARG;
+    if (!workspace_bytes || !cols_capacity) return MESH_ERR_INVALID_ARG;
+    if (total_pairs > INT32_MAX) return MESH_ERR_OVERFLOW;
+    BatchPlan p;
+    if (!plan_batch(total_pairs, batch_hi_bits(total_vert) + batch_node_lo_bits(max_vert), &p))
+        return MESH_ERR_OVERFLOW;
+    *workspace_bytes = p.total;
+    *cols_capacity = total_pairs;
+    return MESH_OK;
+}
+
+mesh_status mesh_batch_node_neighbors(const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
+                                      int64_t total_pairs, int32_t total_vert, int32_t max_vert, int32_t* row_ptr,
+                                      int32_t* cols, int64_t cols_capacity, void* workspace, size_t workspace_bytes,
+                                      void* stream) {
+    size_t need;
+    int64_t cap_hint;
+    mesh_status st = mesh_batch_node_neighbors_query(n_mesh, total_pairs, total_vert, max_vert, &need, &cap_hint);
+    if (st != MESH_OK) return st;
+    if (!row_ptr || !workspace || (total_pairs > 0 && (!conn || !segs)) || cols_capacity < 0)
+        return MESH_ERR_INVALID_ARG;
+    if (cols_capacity > 0 && !cols) return MESH_ERR_INVALID_ARG;
+    if (workspace_bytes < need || !aligned(workspace)) return MESH_ERR_WORKSPACE;
+    const uint32_t lo = batch_node_lo_bits(max_vert);
+    BatchPlan p;
+    plan_batch(total_pairs, batch_hi_bits(total_vert) + lo, &p);
+    hipError_t e = run_batch_node(p, conn, segs, n_mesh, lo, total_vert, row_ptr, cols, cols_capacity, workspace,
+                                  (hipStream_t)stream);
+    return e == hipSuccess ? MESH_OK : MESH_ERR_HIP;
+}
+
+mesh_status mesh_batch_elem_neighbors_query(int32_t n_mesh, int64_t total_slots, int32_t total_vert,
+                                            size_t* workspace_bytes, int64_t* cols_capacity) {
+    if (n_mesh < 0 || total_slots < 0 || total_vert < 0) return MESH_ERR_INVALID_ARG;
+    if (!workspace_bytes || !cols_capacity) return MESH_ERR_INVALID_ARG;
+    if (total_slots > INT32_MAX) return MESH_ERR_OVERFLOW;
+    BatchPlan p;
+    if (!plan_batch(total_slots, batch_hi_bits(total_vert), &p)) return MESH_ERR_OVERFLOW;
+    *workspace_bytes = p.total;
+    *cols_capacity = total_slots;
+    return MESH_OK;
+}
+
+mesh_status mesh_batch_elem_neighbors(const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
+                                      int64_t total_slots, int32_t total_vert, int32_t* row_ptr, int32_t* cols,
+                                      int64_t cols_capacity, void* workspace, size_t workspace_bytes, void* stream) {
+    size_t need;
+    int64_t cap_hint;
+    mesh_status st = mesh_batch_elem_neighbors_query(n_mesh, total_slots, total_vert, &need, &cap_hint);
+    if (st != MESH_OK) return st;
+    if (!row_ptr || !workspace || (total_slots > 0 && (!conn || !segs)) || cols_capacity < 0)
+        return MESH_ERR_INVALID_ARG;
+    if (cols_capacity > 0 && !cols) return MESH_ERR_INVALID_ARG;
+    if (workspace_bytes < need || !aligned(workspace)) return MESH_ERR_WORKSPACE;
+    BatchPlan p;
+    plan_batch(total_slots, batch_hi_bits(total_vert), &p);
+    hipError_t e = run_batch_elem(p, conn, segs, n_mesh, total_vert, row_ptr, cols, cols_capacity, workspace,
+                                  (hipStream_t)stream);
+    return e == hipSuccess ? MESH_OK : MESH_ERR_HIP;
+}
+
 int32_t mesh_radix_shape_count(void) { return N_RADIX_SHAPES; }
 
 mesh_status mesh_radix_shape_info(int32_t shape, int32_t* block, int32_t* items) {

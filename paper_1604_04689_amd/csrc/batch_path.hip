@@ -1,0 +1,273 @@
+// Batched neighbor build: many independent meshes, of mixed element types
+// and sizes, in one launch sequence.  Each mesh is described by a segment
+// record in device memory (mesh_segment); its connectivity holds local ids.
+// The keys carry the mesh's global vertex range:
+//   node relation:    (vert_off[m] + u) << lo_bits | w,   lo_bits = bits of the largest mesh
+//   element relation: (vert_off[m] + v) << 32 | e_local
+// so one sort and one CSR pass over all meshes give a global row_ptr over all
+// vertices whose per-mesh slice equals the single-mesh result, with cols in
+// local ids.  The steps are those of the single-mesh pipelines (Sec. 2.2.1,
+// 2.2.2): pair generation, LSD radix passes, unique/CSR.
+#include "../../include/mesh_neighbors.h"
+#include "common.hpp"
+#include "csr.hpp"
+#include "elements.hpp"
+#include "internal.hpp"
+#include "launch.hpp"
+#include "radix.hpp"
+
+namespace mnb {
+
+constexpr int BH_BLOCK = 256;
+constexpr int BH_GRID_MAX = 1024;
+constexpr int BH_UNROLL = 4;
+constexpr int B_MAX_PASS = 8;
+constexpr int TK_BCSR = 15;
+
+static_assert(sizeof(mesh_segment) == 48, "mesh_segment layout");
+
+// Largest m with offset(m) <= i over the segments (offsets non-decreasing).
+// `field` is the byte offset of the int64 offset inside mesh_segment.
+template <int FIELD>
+__device__ __forceinline__ int find_segment(const mesh_segment* __restrict__ segs, int n_mesh, int64_t i) {
+    int lo = 0, hi = n_mesh - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int64_t off = *(const int64_t*)((const char*)(segs + mid) + FIELD);
+        if (off <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void edge_positions(int32_t et, int k, int* a, int* b) {
+    if (et == TRI3) {
+        *a = Elem<TRI3>::A[k];
+        *b = Elem<TRI3>::B[k];
+    } else if (et == TET4) {
+        *a = Elem<TET4>::A[k];
+        *b = Elem<TET4>::B[k];
+    } else {
+        *a = Elem<HEX8>::A[k];
+        *b = Elem<HEX8>::B[k];
+    }
+}
+
+// Directed edge pair i of the batch (pairs of mesh m start at pair_off[m]).
+struct BatchNodePairSrc {
+    const int32_t* __restrict__ conn;
+    const mesh_segment* __restrict__ segs;
+    int32_t n_mesh;
+    uint32_t lo_bits;
+    static constexpr bool kSkipNone = false;
+
+    // key, or KEY_NONE; *bad is set when an id lies outside the mesh's range
+    // or the segment record is inconsistent (unknown type, pair beyond it).
+    __device__ __forceinline__ uint64_t make(int64_t i, bool* bad) const {
+        const int m = find_segment<offsetof(mesh_segment, pair_off)>(segs, n_mesh, i);
+        const mesh_segment& sg = segs[m];
+        const int32_t et = sg.etype;
+        const int ne = edges_per_elem(et), npe = nodes_per_elem(et);
+        const int64_t loc = i - sg.pair_off;
+        if (ne == 0 || loc < 0 || loc >= 2 * ne * sg.n_elem) {
+            *bad = true;
+            return KEY_NONE;
+        }
+        const int64_t e = loc / (2 * ne);
+        const int r = (int)(loc - e * 2 * ne);
+        int pa, pb;
+        edge_positions(et, r >> 1, &pa, &pb);
+        const int32_t* el = conn + sg.conn_off + e * npe;
+        const int32_t x = el[pa], y = el[pb];
+        const int32_t u = (r & 1) ? y : x;
+        const int32_t w = (r & 1) ? x : y;
+        const bool ok = (uint32_t)u < (uint32_t)sg.n_vert && (uint32_t)w < (uint32_t)sg.n_vert;
+        *bad = !ok;
+        if (!ok || u == w) return KEY_NONE;
+        return ((uint64_t)(uint32_t)(sg.vert_off + u) << lo_bits) | (uint64_t)(uint32_t)w;
+    }
+    __device__ __forceinline__ uint64_t load(int64_t i) const {
+        bool bad;
+        return make(i, &bad);
+    }
+};
+
+// (vertex, element) pair of connectivity slot s of the batch.
+struct BatchElemPairSrc {
+    const int32_t* __restrict__ conn;
+    const mesh_segment* __restrict__ segs;
+    int32_t n_mesh;
+    static constexpr bool kSkipNone = true;
+
+    __device__ __forceinline__ uint64_t make(int64_t s, bool* bad) const {
+        const int m = find_segment<offsetof(mesh_segment, slot_off)>(segs, n_mesh, s);
+        const mesh_segment& sg = segs[m];
+        const int npe = nodes_per_elem(sg.etype);
+        const int64_t loc = s - sg.slot_off;
+        if (npe == 0 || loc < 0 || loc >= npe * sg.n_elem) {
+            *bad = true;
+            return KEY_NONE;
+        }
+        const int32_t* el = conn + sg.conn_off;
+        const int32_t v = el[loc];
+        if ((uint32_t)v >= (uint32_t)sg.n_vert) {
+            *bad = true;
+            return KEY_NONE;
+        }
+        *bad = false;
+        const int64_t e = loc / npe;
+        const int j = (int)(loc - e * npe);
+        for (int jj = 0; jj < j; ++jj)
+            if (el[e * npe + jj] == v) return KEY_NONE;  // repeated id inside the element
+        return ((uint64_t)(uint32_t)(sg.vert_off + v) << 32) | (uint64_t)e;
+    }
+    __device__ __forceinline__ uint64_t load(int64_t s) const {
+        bool bad;
+        return make(s, &bad);
+    }
+};
+
+// Digit histograms (8-bit digits from bit shift0) of the keys a batch source
+// generates, the number of participating keys, and the data-error flag.
+template <class Src>
+__global__ __launch_bounds__(BH_BLOCK) void batch_hist_kernel(Src src, int64_t n, uint32_t shift0, int n_pass,
+                                                             uint32_t last_bits, uint32_t* __restrict__ hist,
+                                                             uint32_t* count, uint32_t* err) {
+    __shared__ uint32_t s_hist[B_MAX_PASS * RADIX];
+    __shared__ uint32_t s_keys;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_keys = 0;
+    for (int i = tid; i < n_pass * RADIX; i += BH_BLOCK) s_hist[i] = 0;
+    __syncthreads();
+    bool bad_seen = false;
+    uint32_t mine = 0;
+    const int64_t stride = (int64_t)gridDim.x * BH_BLOCK;
+    for (int64_t i0 = (int64_t)blockIdx.x * BH_BLOCK + tid; i0 < n; i0 += stride * BH_UNROLL) {
+        uint64_t k[BH_UNROLL];
+        bool take[BH_UNROLL];
+#pragma unroll
+        for (int u = 0; u < BH_UNROLL; ++u) {
+            const int64_t i = i0 + u * stride;
+            bool bad = false;
+            k[u] = i < n ? src.make(i, &bad) : KEY_NONE;
+            bad_seen |= bad;
+            take[u] = i < n && !(Src::kSkipNone && k[u] == KEY_NONE);
+        }
+#pragma unroll
+        for (int u = 0; u < BH_UNROLL; ++u) {
+            if (!take[u]) continue;
+            ++mine;
+            for (int p = 0; p < n_pass; ++p) {
+                const uint32_t mask = p == n_pass - 1 ? (1u << last_bits) - 1 : RADIX - 1;
+                atomicAdd(&s_hist[p * RADIX + ((uint32_t)(k[u] >> (shift0 + p * RBITS)) & mask)], 1u);
+            }
+        }
+    }
+    if (bad_seen) set_error(err, ERR_INDEX_RANGE);
+    if (mine) atomicAdd(&s_keys, mine);
+    __syncthreads();
+    if (tid == 0 && s_keys) atomicAdd(count, s_keys);
+    for (int i = tid; i < n_pass * RADIX; i += BH_BLOCK)
+        if (s_hist[i]) atomicAdd(&hist[i], s_hist[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+static uint32_t bits_for(int64_t n) {
+    uint32_t b = 1;
+    while (b < 31 && ((int64_t)1 << b) < n) ++b;
+    return b;
+}
+
+bool plan_batch(int64_t n_keys, uint32_t digit_bits, BatchPlan* p) {
+    if (n_keys < 0 || digit_bits == 0 || digit_bits > 62) return false;
+    p->n_keys = n_keys;
+    p->n_pass = (int)ceil_div(digit_bits, RBITS);
+    if (p->n_pass > B_MAX_PASS) return false;
+    p->digit_bits = digit_bits;
+    p->n_tiles = ceil_div(n_keys, min_radix_tile());
+    p->n_utiles = ceil_div(n_keys, UNIQ_TILE);
+    size_t off = HEADER_BYTES;
+    p->off_hist = off;
+    off += align_up(B_MAX_PASS * RADIX * sizeof(uint32_t));
+    p->off_ulb = off;
+    off += align_up((size_t)p->n_utiles * sizeof(uint64_t));
+    p->off_lb0 = off;
+    off += align_up((size_t)p->n_tiles * RADIX * sizeof(uint64_t));
+    p->zero_bytes = off;
+    p->off_lb1 = off;
+    off += p->n_pass > 1 ? align_up((size_t)p->n_tiles * RADIX * sizeof(uint64_t)) : 0;
+    p->off_keys0 = off;
+    off += align_up((size_t)n_keys * sizeof(uint64_t));
+    p->off_keys1 = off;
+    off += p->n_pass > 1 ? align_up((size_t)n_keys * sizeof(uint64_t)) : 0;
+    p->total = off;
+    return true;
+}
+
+uint32_t batch_node_lo_bits(int32_t max_vert) { return bits_for(max_vert); }
+uint32_t batch_hi_bits(int32_t total_vert) { return bits_for(total_vert); }
+
+template <class Src>
+static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, uint32_t shift0, uint32_t csr_lo_bits,
+                                 int32_t total_vert, int32_t* row_ptr, int32_t* cols, int64_t cols_cap, char* w,
+                                 hipStream_t s) {
+    uint32_t* hdr = (uint32_t*)w;
+    uint32_t* err = hdr + HDR_ERR;
+    uint32_t* count = hdr + HDR_KEY_COUNT;
+    uint32_t* hist = (uint32_t*)(w + p.off_hist);
+    uint64_t* ulb = (uint64_t*)(w + p.off_ulb);
+    uint64_t* lb[2] = {(uint64_t*)(w + p.off_lb0), (uint64_t*)(w + p.off_lb1)};
+    uint64_t* kb[2] = {(uint64_t*)(w + p.off_keys0), (uint64_t*)(w + p.off_keys1)};
+    const int shape = radix_shape();
+    const bool node = !Src::kSkipNone;
+
+    const int grid = (int)tmin<int64_t>(ceil_div(p.n_keys, BH_BLOCK), BH_GRID_MAX);
+    const uint32_t last_bits = p.digit_bits - (uint32_t)(p.n_pass - 1) * RBITS;
+    hipError_t e = launch(node ? "batch_node_hist" : "batch_elem_hist", batch_hist_kernel<Src>, dim3(grid),
+                          dim3(BH_BLOCK), s, src, p.n_keys, shift0, p.n_pass, last_bits, hist, count, err);
+    for (int q = 0; q < p.n_pass && e == hipSuccess; ++q) {
+        const uint32_t shift = shift0 + (uint32_t)q * RBITS;
+        const uint32_t bits = tmin<uint32_t>(RBITS, p.digit_bits - (uint32_t)q * RBITS);
+        uint64_t* out = kb[q & 1];
+        uint64_t* lb_next = q + 1 < p.n_pass ? lb[(q + 1) & 1] : nullptr;
+        if (q == 0)
+            e = launch_radix_pass(node ? "batch_node_radix_first" : "batch_elem_radix_first", shape, src, out,
+                                  p.n_keys, shift, bits, hist, lb[0], lb_next, hdr + HDR_TICKET0, err, s);
+        else if (node)
+            e = launch_radix_pass("batch_node_radix", shape, KeyArraySrc{kb[(q - 1) & 1]}, out, p.n_keys, shift,
+                                  bits, hist + q * RADIX, lb[q & 1], lb_next, hdr + HDR_TICKET0 + q, err, s);
+        else
+            e = launch_radix_pass("batch_elem_radix", shape, CountedKeySrc{kb[(q - 1) & 1], count}, out, p.n_keys,
+                                  shift, bits, hist + q * RADIX, lb[q & 1], lb_next, hdr + HDR_TICKET0 + q, err, s);
+    }
+    if (e != hipSuccess) return e;
+    (void)tag;
+    return launch_unique_csr(node ? "batch_node_csr" : "batch_elem_csr", kb[(p.n_pass - 1) & 1], p.n_keys,
+                             node ? (const uint32_t*)nullptr : count, csr_lo_bits, total_vert, cols, cols_cap,
+                             row_ptr, ulb, hdr + HDR_TICKET0 + TK_BCSR, err, s);
+}
+
+hipError_t run_batch_node(const BatchPlan& p, const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
+                          uint32_t lo_bits, int32_t total_vert, int32_t* row_ptr, int32_t* cols, int64_t cols_cap,
+                          void* ws, hipStream_t s) {
+    hipError_t e = zero_words(ws, p.zero_bytes, s);
+    if (e != hipSuccess) return e;
+    if (p.n_keys == 0 || n_mesh == 0) return fill_i32(row_ptr, (int64_t)total_vert + 1, 0, s);
+    return batch_pipeline(p, "node", BatchNodePairSrc{conn, segs, n_mesh, lo_bits}, 0u, lo_bits, total_vert, row_ptr,
+                          cols, cols_cap, (char*)ws, s);
+}
+
+hipError_t run_batch_elem(const BatchPlan& p, const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
+                          int32_t total_vert, int32_t* row_ptr, int32_t* cols, int64_t cols_cap, void* ws,
+                          hipStream_t s) {
+    hipError_t e = zero_words(ws, p.zero_bytes, s);
+    if (e != hipSuccess) return e;
+    if (p.n_keys == 0 || n_mesh == 0) return fill_i32(row_ptr, (int64_t)total_vert + 1, 0, s);
+    return batch_pipeline(p, "elem", BatchElemPairSrc{conn, segs, n_mesh}, 32u, 32u, total_vert, row_ptr, cols,
+                          cols_cap, (char*)ws, s);
+}
+
+}  // namespace mnb

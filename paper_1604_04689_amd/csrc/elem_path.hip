@@ -64,14 +64,6 @@ struct ElemPairSrc {
     }
 };
 
-// Keys in an array whose participating length is only known on the device.
-struct CountedKeySrc {
-    const uint64_t* __restrict__ keys;
-    const uint32_t* __restrict__ count;
-    static constexpr bool kSkipNone = true;
-    __device__ __forceinline__ uint64_t load(int64_t i) const { return i < (int64_t)*count ? keys[i] : KEY_NONE; }
-};
-
 // Histograms of the 8-bit digits of v over the pairs that take part, and
 // their number.  Raises ERR_INDEX_RANGE.
 template <int ET>

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/mesh_neighbors.h"
+
 namespace mnb {
 
 constexpr size_t ALIGN = 256;
@@ -48,6 +50,27 @@ struct ElemPlan {
 bool plan_elem(int64_t n_elem, int32_t etype, int32_t n_vert, ElemPlan* p);
 hipError_t run_elem(const ElemPlan& p, const int32_t* conn, int32_t* row_ptr, int32_t* cols,
                     int64_t cols_capacity, void* ws, hipStream_t stream);
+
+// ---- batched pipelines -------------------------------------------------------
+struct BatchPlan {
+    int64_t n_keys = 0;       // directed pairs (node) or connectivity slots (element)
+    uint32_t digit_bits = 0;  // key bits the radix passes cover
+    int n_pass = 0;
+    int64_t n_tiles = 0, n_utiles = 0;
+    size_t off_hist = 0, off_ulb = 0, off_lb0 = 0, off_lb1 = 0, off_keys0 = 0, off_keys1 = 0;
+    size_t zero_bytes = 0;
+    size_t total = 0;
+};
+
+bool plan_batch(int64_t n_keys, uint32_t digit_bits, BatchPlan* p);
+uint32_t batch_node_lo_bits(int32_t max_vert);
+uint32_t batch_hi_bits(int32_t total_vert);
+hipError_t run_batch_node(const BatchPlan& p, const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
+                          uint32_t lo_bits, int32_t total_vert, int32_t* row_ptr, int32_t* cols, int64_t cols_cap,
+                          void* ws, hipStream_t s);
+hipError_t run_batch_elem(const BatchPlan& p, const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
+                          int32_t total_vert, int32_t* row_ptr, int32_t* cols, int64_t cols_cap, void* ws,
+                          hipStream_t s);
 
 // Clears `bytes` (a multiple of 4) from `p` with a fill kernel (no memset
 // nodes, so the sequence can be captured into a graph).

@@ -20,6 +20,14 @@ struct KeyArraySrc {
     __device__ __forceinline__ uint64_t load(int64_t i) const { return keys[i]; }
 };
 
+// Keys in an array whose participating length is only known on the device.
+struct CountedKeySrc {
+    const uint64_t* __restrict__ keys;
+    const uint32_t* __restrict__ count;
+    static constexpr bool kSkipNone = true;
+    __device__ __forceinline__ uint64_t load(int64_t i) const { return i < (int64_t)*count ? keys[i] : KEY_NONE; }
+};
+
 // Tile shapes the library is built with: threads per block x keys per thread.
 // The LDS staging area is 8 * BLOCK * ITEMS bytes.
 struct RadixShape {

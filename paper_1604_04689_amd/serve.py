@@ -1,0 +1,270 @@
+"""Serving neighbor-build requests with continuous batching.
+
+Requests (one mesh each, both relations wanted) arrive over time.  The server
+keeps S execution slots (HIP streams).  Whenever a slot is free, the requests
+that have arrived and are waiting are admitted in arrival order while their
+reserved device memory fits the budget (the pair/key buffers dominate), and
+go out together as one batched launch on that slot; launches on different
+slots overlap on the device.  A request that arrives while others run waits
+only for the next free slot and for memory.  Results stay resident on the
+device until released; latency = completion - arrival.
+
+The executor is pluggable:
+
+* ``GpuExecutor`` runs each batch through the library's batched entry points
+  (``mesh_batch_node_neighbors`` / ``mesh_batch_elem_neighbors``) on its own
+  stream and detects completion with a HIP event;
+* ``FakeExecutor`` (tests) runs on the CPU with a simulated clock and
+  duration model, so admission and batching logic are testable without a GPU.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import heapq
+import math
+import time
+from typing import Callable, List, Optional
+
+import numpy as np
+
+from . import binding as _b
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds on the server clock
+    conn: np.ndarray        # int32 [n_elem, npe], local ids
+    etype: int
+    n_vert: int
+    reserve: int = 0        # device bytes reserved while in flight (set by the server)
+    admitted: float = math.nan
+    completed: float = math.nan
+
+    @property
+    def n_elem(self) -> int:
+        return int(self.conn.shape[0])
+
+    @property
+    def latency(self) -> float:
+        return self.completed - self.arrival
+
+
+def reserve_bytes(n_elem: int, etype: int, n_vert: int) -> int:
+    """Device bytes one request holds while in flight: both relations'
+    workspaces and outputs plus its connectivity (the library's own sizing)."""
+    ws_n, cap_n = _b.query_node(n_elem, etype, n_vert)
+    ws_e, cap_e = _b.query_elem(n_elem, etype, n_vert)
+    npe = _b.NODES_PER_ELEM[etype]
+    return ws_n + ws_e + 4 * (cap_n + cap_e) + 8 * (n_vert + 1) + 4 * npe * n_elem
+
+
+class BudgetError(ValueError):
+    pass
+
+
+@dataclasses.dataclass
+class BatchHandle:
+    slot: int
+    requests: List[Request]
+    payload: object = None
+
+
+class FakeExecutor:
+    """CPU stand-in: a batch 'runs' for t0 + elements * per_elem seconds of
+    simulated time, computed with the CPU oracle (tests only)."""
+
+    def __init__(self, clock, t0=1e-4, per_elem=1e-8, compute: Optional[Callable] = None):
+        self.clock = clock
+        self.t0, self.per_elem = t0, per_elem
+        self.compute = compute
+        self.finish = {}
+
+    def submit(self, batch: BatchHandle):
+        n = sum(r.n_elem for r in batch.requests)
+        self.finish[id(batch)] = self.clock.now() + self.t0 + n * self.per_elem
+        if self.compute is not None:
+            batch.payload = [self.compute(r) for r in batch.requests]
+
+    def done(self, batch: BatchHandle) -> bool:
+        return self.clock.now() >= self.finish[id(batch)]
+
+    def next_completion(self, batch: BatchHandle) -> float:
+        return self.finish[id(batch)]
+
+    def results(self, batch: BatchHandle):
+        return batch.payload
+
+    def release(self, batch: BatchHandle):
+        self.finish.pop(id(batch), None)
+
+
+class GpuExecutor:
+    """Runs each batch on its slot's stream through the batched C entry points."""
+
+    def __init__(self, n_slots: int, device="cuda:0", keep_results=False):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        self.streams = [torch.cuda.Stream(self.device) for _ in range(n_slots)]
+        self.keep = keep_results
+
+    def submit(self, batch: BatchHandle):
+        torch = self.torch
+        s = self.streams[batch.slot]
+        desc = [(r.n_elem, r.etype, r.n_vert) for r in batch.requests]
+        host = _b.concat_conn([r.conn for r in batch.requests])
+        with torch.cuda.stream(s):
+            pinned = torch.from_numpy(host).pin_memory() if host.size else torch.zeros(0, dtype=torch.int32)
+            conn = pinned.to(self.device, non_blocking=True)
+            node = _b.BatchBuild("node", desc, self.device)
+            elem = _b.BatchBuild("elem", desc, self.device)
+            node.launch(conn, s)
+            elem.launch(conn, s)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        batch.payload = {"node": node, "elem": elem, "event": ev, "conn": conn, "pinned": pinned}
+
+    def done(self, batch: BatchHandle) -> bool:
+        return batch.payload["event"].query()
+
+    def next_completion(self, batch: BatchHandle) -> float:
+        return math.nan
+
+    def results(self, batch: BatchHandle):
+        """Per request: ((node row_ptr, cols), (elem row_ptr, cols)) as host arrays."""
+        p = batch.payload
+        s = self.streams[batch.slot]
+        out = []
+        node_rp, node_cols = p["node"].result(s)
+        elem_rp, elem_cols = p["elem"].result(s)
+        nrp, ncol = node_rp.cpu().numpy(), node_cols.cpu().numpy()
+        erp, ecol = elem_rp.cpu().numpy(), elem_cols.cpu().numpy()
+        for seg in p["node"].seg_host:
+            v0, nv = int(seg["vert_off"]), int(seg["n_vert"])
+            a, b = int(nrp[v0]), int(nrp[v0 + nv])
+            c, d = int(erp[v0]), int(erp[v0 + nv])
+            out.append(((nrp[v0:v0 + nv + 1] - a, ncol[a:b]), (erp[v0:v0 + nv + 1] - c, ecol[c:d])))
+        return out
+
+    def check(self, batch: BatchHandle):
+        s = self.streams[batch.slot]
+        batch.payload["node"].check(s)
+        batch.payload["elem"].check(s)
+
+    def release(self, batch: BatchHandle):
+        batch.payload = None
+
+
+class RealClock:
+    def __init__(self):
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def wait_until(self, t: float):
+        while self.now() < t:
+            pass
+
+
+class SimClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def now(self) -> float:
+        return self.t
+
+    def wait_until(self, t: float):
+        self.t = max(self.t, t)
+
+
+class Server:
+    """Continuous batching over ``n_slots`` slots under ``budget_bytes``."""
+
+    def __init__(self, executor, clock, n_slots=4, budget_bytes=64 << 30, max_batch=64,
+                 on_complete: Optional[Callable] = None, reserve: Callable = reserve_bytes):
+        self.ex = executor
+        self.clock = clock
+        self.n_slots = n_slots
+        self.budget = budget_bytes
+        self.max_batch = max_batch
+        self.on_complete = on_complete
+        self.reserve = reserve
+        self.in_use = 0
+        self.peak_in_use = 0
+        self.batches = 0
+        self.batch_sizes = []
+        self.waiting = collections.deque()
+        self.running = {}  # slot -> BatchHandle
+
+    def _admit_into(self, slot: int) -> Optional[BatchHandle]:
+        now = self.clock.now()
+        take = []
+        while self.waiting and self.waiting[0].arrival <= now and len(take) < self.max_batch:
+            r = self.waiting[0]
+            if self.in_use + r.reserve > self.budget:
+                break  # FIFO: the head waits for memory, later ones wait behind it
+            self.waiting.popleft()
+            self.in_use += r.reserve
+            r.admitted = now
+            take.append(r)
+        if not take:
+            return None
+        self.peak_in_use = max(self.peak_in_use, self.in_use)
+        b = BatchHandle(slot, take)
+        self.ex.submit(b)
+        self.running[slot] = b
+        self.batches += 1
+        self.batch_sizes.append(len(take))
+        return b
+
+    def _retire(self, slot: int):
+        b = self.running.pop(slot)
+        now = self.clock.now()
+        for r in b.requests:
+            r.completed = now
+        if self.on_complete is not None:
+            self.on_complete(b, self.ex)
+        for r in b.requests:
+            self.in_use -= r.reserve
+        self.ex.release(b)
+
+    def run(self, requests: List[Request]) -> List[Request]:
+        """Serve the requests (sorted by arrival) to completion."""
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        for r in reqs:
+            r.reserve = self.reserve(r.n_elem, r.etype, r.n_vert)
+            if r.reserve > self.budget:
+                raise BudgetError(f"request {r.rid} needs {r.reserve} bytes, budget is {self.budget}")
+        self.waiting.extend(reqs)
+        while self.waiting or self.running:
+            progressed = False
+            for slot in list(self.running):
+                if self.ex.done(self.running[slot]):
+                    self._retire(slot)
+                    progressed = True
+            for slot in range(self.n_slots):
+                if slot not in self.running and self._admit_into(slot) is not None:
+                    progressed = True
+            if progressed:
+                continue
+            # nothing to do right now: advance to the next event
+            nxt = [self.ex.next_completion(b) for b in self.running.values()]
+            nxt = [t for t in nxt if not math.isnan(t)]
+            if self.waiting and self.waiting[0].arrival > self.clock.now():
+                nxt.append(self.waiting[0].arrival)
+            if nxt:
+                self.clock.wait_until(min(nxt))
+        return reqs
+
+
+def latency_summary(reqs: List[Request]):
+    lat = np.array([r.latency for r in reqs])
+    elems = sum(r.n_elem for r in reqs)
+    span = max(r.completed for r in reqs) - min(r.arrival for r in reqs)
+    return {"requests": len(reqs), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+            "elements": int(elems), "span_s": float(span), "elements_per_s": float(elems / span)}

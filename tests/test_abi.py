@@ -104,3 +104,25 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(RuntimeError, match="missing"):
         binding.lib()
+
+
+def test_segment_table_offsets():
+    seg, tot = binding.segment_table([(10, 0, 12), (0, 1, 5), (3, 2, 20), (7, 1, 9)])
+    assert seg.dtype.itemsize == 48
+    assert seg["conn_off"].tolist() == [0, 30, 30, 54]
+    assert seg["pair_off"].tolist() == [0, 60, 60, 132]
+    assert seg["slot_off"].tolist() == [0, 30, 30, 54]
+    assert seg["vert_off"].tolist() == [0, 12, 17, 37]
+    assert tot == {"pairs": 132 + 84, "slots": 54 + 28, "vert": 46, "ids": 82, "max_vert": 20}
+
+
+def test_batch_queries():
+    ws, cap = 0, 0
+    import ctypes
+    w, c = ctypes.c_size_t(0), ctypes.c_int64(0)
+    assert binding.lib().mesh_batch_node_neighbors_query(3, 1000, 500, 200, ctypes.byref(w), ctypes.byref(c)) == 0
+    assert c.value == 1000 and w.value >= 16 * 1000
+    assert binding.lib().mesh_batch_elem_neighbors_query(3, 800, 500, ctypes.byref(w), ctypes.byref(c)) == 0
+    assert c.value == 800
+    # max_vert above total_vert is inconsistent
+    assert binding.lib().mesh_batch_node_neighbors_query(3, 1000, 100, 200, ctypes.byref(w), ctypes.byref(c)) == 1

@@ -1,0 +1,36 @@
+"""Served results on the GPU equal the results of each mesh built alone."""
+import numpy as np
+import pytest
+
+from paper_1604_04689_amd import meshgen as mg
+from tests.test_serve import make_requests
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def test_served_equals_alone(oracle_mod):
+    from paper_1604_04689_amd import serve
+    reqs = make_requests(40, rate=20000.0, seed=11)
+    got = {}
+
+    def on_complete(batch, ex):
+        ex.check(batch)
+        for r, res in zip(batch.requests, ex.results(batch)):
+            got[r.rid] = res
+
+    clock = serve.RealClock()
+    srv = serve.Server(serve.GpuExecutor(3), clock, n_slots=3, budget_bytes=1 << 34, max_batch=8,
+                       on_complete=on_complete)
+    done = srv.run(reqs)
+    assert len(got) == len(reqs)
+    assert srv.batches < len(reqs)  # some batching happened
+    for r in reqs:
+        wn = oracle_mod.node_neighbors(r.conn, r.etype, r.n_vert)
+        we = oracle_mod.elem_neighbors(r.conn, r.etype, r.n_vert)
+        (gnr, gnc), (ger, gec) = got[r.rid]
+        assert np.array_equal(gnr, wn[0]) and np.array_equal(gnc, wn[1]), r.rid
+        assert np.array_equal(ger, we[0]) and np.array_equal(gec, we[1]), r.rid
+    s = serve.latency_summary(done)
+    print("served:", s, "batches:", srv.batches, flush=True)

@@ -1,0 +1,91 @@
+"""Continuous-batching server logic on the CPU (fake executor, simulated clock)."""
+import numpy as np
+import pytest
+
+from paper_1604_04689_amd import meshgen as mg
+from paper_1604_04689_amd import serve
+
+
+def make_requests(n, rate, seed=3, small=True):
+    specs = mg.batch_specs(n_mesh=n, seed=seed, tri_range=(4, 40) if small else (8, 512),
+                           cell_range=(1, 6) if small else (4, 48))
+    arr = mg.poisson_arrivals(n, rate, seed=seed + 1)
+    out = []
+    for i, (s, t) in enumerate(zip(specs, arr)):
+        m = s.build()
+        out.append(serve.Request(i, float(t), m.conn, m.etype, m.n_vert))
+    return out
+
+
+def run(reqs, **kw):
+    clock = serve.SimClock()
+    ex = serve.FakeExecutor(clock, t0=kw.pop("t0", 1e-4), per_elem=kw.pop("per_elem", 1e-8),
+                            compute=kw.pop("compute", None))
+    srv = serve.Server(ex, clock, **kw)
+    done = srv.run(reqs)
+    return srv, done
+
+
+def test_all_complete_in_order_and_within_budget():
+    reqs = make_requests(60, rate=2000.0)
+    budget = 3 * max(serve.reserve_bytes(r.n_elem, r.etype, r.n_vert) for r in reqs)
+    srv, done = run(reqs, n_slots=3, budget_bytes=budget, max_batch=8)
+    assert all(r.completed >= r.admitted >= r.arrival for r in done)
+    assert srv.peak_in_use <= budget
+    assert srv.in_use == 0
+    # admission is FIFO
+    adm = [r.admitted for r in sorted(done, key=lambda r: r.arrival)]
+    assert all(a <= b for a, b in zip(adm, adm[1:]))
+    assert max(srv.batch_sizes) <= 8
+
+
+def test_budget_makes_requests_wait():
+    reqs = make_requests(30, rate=1e6)  # all arrive at once
+    one = max(serve.reserve_bytes(r.n_elem, r.etype, r.n_vert) for r in reqs)
+    srv, done = run(reqs, n_slots=8, budget_bytes=one, max_batch=64)
+    # the budget holds about one large request: memory, not slots, gates admission
+    assert srv.peak_in_use <= one
+    assert srv.batches > 8  # more launches than slots: requests waited for memory
+    waits = [r.admitted - r.arrival for r in done]
+    assert max(waits) > 0
+
+
+def test_oversize_request_refused():
+    reqs = make_requests(5, rate=100.0)
+    with pytest.raises(serve.BudgetError):
+        run(reqs, budget_bytes=10)
+
+
+def test_continuous_admission_while_running():
+    # a long first batch; later arrivals start on other slots before it ends
+    reqs = make_requests(12, rate=50000.0)
+    srv, done = run(reqs, n_slots=4, budget_bytes=1 << 40, max_batch=1, per_elem=1e-6)
+    first = min(done, key=lambda r: r.arrival)
+    overlapped = [r for r in done if r is not first and r.admitted < first.completed]
+    assert overlapped, "no request was admitted while the first batch was running"
+
+
+def test_results_same_alone_and_in_mix(oracle_mod):
+    reqs = make_requests(25, rate=5000.0)
+    got = {}
+
+    def on_complete(batch, ex):
+        for r, res in zip(batch.requests, ex.results(batch)):
+            got[r.rid] = res
+
+    def compute(r):
+        return (oracle_mod.node_neighbors(r.conn, r.etype, r.n_vert),
+                oracle_mod.elem_neighbors(r.conn, r.etype, r.n_vert))
+
+    srv, done = run(reqs, n_slots=2, budget_bytes=1 << 40, max_batch=6, compute=compute, on_complete=on_complete)
+    for r in reqs:
+        alone = compute(r)
+        for k in range(2):
+            assert np.array_equal(got[r.rid][k][0], alone[k][0]) and np.array_equal(got[r.rid][k][1], alone[k][1])
+
+
+def test_latency_summary():
+    reqs = make_requests(20, rate=1000.0)
+    srv, done = run(reqs, n_slots=2, budget_bytes=1 << 40)
+    s = serve.latency_summary(done)
+    assert s["requests"] == 20 and s["p99_ms"] >= s["p50_ms"] >= 0 and s["elements_per_s"] > 0
