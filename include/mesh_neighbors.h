@@ -185,6 +185,19 @@ mesh_status mesh_radix_shape_info(int32_t shape, int32_t* block, int32_t* items)
 mesh_status mesh_set_radix_shape(int32_t shape);
 int32_t mesh_get_radix_shape(void);
 
+/* How mesh_node_neighbors (single mesh) orders its keys; results are the same
+ * either way.  Process-wide, default MESH_NODE_SORT_FULL_KEY.
+ *  FULL_KEY:     LSD radix passes over all 2b bits of (u << b) | w, then one
+ *                pass drops repeats and writes the CSR.
+ *  VERTEX_ROWS:  LSD radix passes over the bits of u only (the paper's sort by
+ *                the first array), then each row's neighbor ids are sorted and
+ *                deduplicated in LDS (rows over 256 pairs by a block each),
+ *                the distinct counts are scanned into row_ptr and the rows
+ *                gathered into cols.  Fewer full passes over the keys. */
+typedef enum { MESH_NODE_SORT_FULL_KEY = 0, MESH_NODE_SORT_VERTEX_ROWS = 1 } mesh_node_sort;
+mesh_status mesh_set_node_sort(int32_t mode);
+int32_t mesh_get_node_sort(void);
+
 /* ------------------------------------------------------------------------ */
 /* Kernel timing (diagnostics, not part of the method).                     */
 /* ------------------------------------------------------------------------ */

@@ -66,6 +66,8 @@ SIGNATURES = {
     "mesh_radix_shape_info": (_c_i32, [_c_i32, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]),
     "mesh_set_radix_shape": (_c_i32, [_c_i32]),
     "mesh_get_radix_shape": (_c_i32, []),
+    "mesh_set_node_sort": (_c_i32, [_c_i32]),
+    "mesh_get_node_sort": (_c_i32, []),
     "mesh_timing_read": (_c_i32, [ctypes.POINTER(KernelTime), _c_i32]),
 }
 
@@ -109,6 +111,20 @@ def set_radix_shape(shape: int = -1):
 
 def get_radix_shape() -> int:
     return int(lib().mesh_get_radix_shape())
+
+
+NODE_SORT_FULL_KEY, NODE_SORT_VERTEX_ROWS = 0, 1
+
+
+def set_node_sort(mode: int):
+    """Select the single-mesh node algorithm (results are identical)."""
+    st = lib().mesh_set_node_sort(int(mode))
+    if st != Status.OK:
+        raise MeshError(st, "mesh_set_node_sort")
+
+
+def get_node_sort() -> int:
+    return int(lib().mesh_get_node_sort())
 
 
 def timing_enable(on: bool = True):
@@ -265,7 +281,9 @@ class BatchBuild:
     ``meshes`` is a list of (n_elem, etype, n_vert); the connectivity passed to
     ``launch`` is all meshes' int32 ids back to back, each mesh's ids local.
     ``result`` gives the global CSR (cols in local ids); ``mesh_csr(m)`` the
-    slice of mesh m rebased to start at 0."""
+    slice of mesh m rebased to start at 0.  ``reset(meshes)`` re-targets the
+    build at another batch, reusing its device buffers when they are large
+    enough (they only grow)."""
 
     def __init__(self, kind, meshes, device="cuda"):
         import torch
@@ -274,28 +292,44 @@ class BatchBuild:
             raise ValueError(kind)
         self.kind = kind
         self.device = torch.device(device)
+        self._ws_raw = self._rp = self._cols = self._segs = None
+        self.reset(meshes)
+
+    def reset(self, meshes):
+        import torch
+
         seg, tot = segment_table(meshes)
         self.seg_host = seg
         self.totals = tot
         self.n_mesh = len(meshes)
-        self.segs = torch.from_numpy(seg.view("u1")).to(self.device) if len(meshes) else \
-            torch.zeros(48, dtype=torch.uint8, device=self.device)
         ws, cap = _c_sz(0), _c_i64(0)
-        if kind == "node":
+        if self.kind == "node":
             st = lib().mesh_batch_node_neighbors_query(self.n_mesh, tot["pairs"], tot["vert"], tot["max_vert"],
                                                        ctypes.byref(ws), ctypes.byref(cap))
         else:
             st = lib().mesh_batch_elem_neighbors_query(self.n_mesh, tot["slots"], tot["vert"], ctypes.byref(ws),
                                                        ctypes.byref(cap))
         if st != Status.OK:
-            raise MeshError(st, f"mesh_batch_{kind}_neighbors_query")
+            raise MeshError(st, f"mesh_batch_{self.kind}_neighbors_query")
         self.ws_bytes = int(ws.value)
         self.cols_capacity = int(cap.value)
-        self._ws_raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+
+        def grow(buf, n, dtype):
+            if buf is None or buf.numel() < n:
+                return torch.empty(max(n, 1), dtype=dtype, device=self.device)
+            return buf
+
+        self._ws_raw = grow(self._ws_raw, self.ws_bytes + 256, torch.uint8)
         pad = (-self._ws_raw.data_ptr()) % 256
         self.workspace = self._ws_raw[pad:pad + self.ws_bytes]
-        self.row_ptr = torch.empty(tot["vert"] + 1, dtype=torch.int32, device=self.device)
-        self.cols = torch.empty(max(self.cols_capacity, 1), dtype=torch.int32, device=self.device)
+        self._rp = grow(self._rp, tot["vert"] + 1, torch.int32)
+        self.row_ptr = self._rp[:tot["vert"] + 1]
+        self._cols = grow(self._cols, self.cols_capacity, torch.int32)
+        self.cols = self._cols
+        self._segs = grow(self._segs, 48 * max(len(meshes), 1), torch.uint8)
+        if len(meshes):
+            self._segs[:48 * len(meshes)].copy_(torch.from_numpy(seg.view("u1")), non_blocking=False)
+        self.segs = self._segs
 
     def launch(self, conn, stream=None):
         import torch

@@ -36,6 +36,9 @@ hipError_t fill_i32(int32_t* p, int64_t n, int32_t value, hipStream_t s) {
 }
 
 static std::atomic<int> g_radix_shape{DEFAULT_RADIX_SHAPE};
+static std::atomic<int> g_node_sort{0};
+
+int node_sort_mode() { return g_node_sort.load(std::memory_order_relaxed); }
 
 int radix_shape() { return g_radix_shape.load(std::memory_order_relaxed); }
 
@@ -208,6 +211,14 @@ mesh_status mesh_set_radix_shape(int32_t shape) {
 }
 
 int32_t mesh_get_radix_shape(void) { return g_radix_shape.load(std::memory_order_relaxed); }
+
+mesh_status mesh_set_node_sort(int32_t mode) {
+    if (mode != MESH_NODE_SORT_FULL_KEY && mode != MESH_NODE_SORT_VERTEX_ROWS) return MESH_ERR_INVALID_ARG;
+    g_node_sort.store(mode, std::memory_order_relaxed);
+    return MESH_OK;
+}
+
+int32_t mesh_get_node_sort(void) { return g_node_sort.load(std::memory_order_relaxed); }
 
 mesh_status mesh_check(const void* workspace, void* stream) {
     if (!workspace) return MESH_ERR_INVALID_ARG;

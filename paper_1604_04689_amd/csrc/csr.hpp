@@ -43,23 +43,26 @@ __global__ __launch_bounds__(BLOCK) void unique_csr_kernel(const uint64_t* __res
     const int wid = tid / WAVE;
     if (tid == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
-    const int64_t n = n_dev ? tmin<int64_t>(n_host, (int64_t)*n_dev) : n_host;
     const uint32_t tile = s_tile;
     const int64_t base = (int64_t)tile * TILE;
-    const int tile_n = (int)tmin<int64_t>(TILE, n - base);  // may be <= 0 when n is a device count
-    if (tile_n <= 0) {
-        // past the device key count: no later tile has keys either
-        if (tile == 0)
-            for (int64_t v = tid; v <= n_vert; v += BLOCK) row_ptr[v] = 0;
-        return;
-    }
     const int wpos = wid * WAVE * ITEMS + lane;
+    // keys are read up to the array length n_host, so the loads need not wait
+    // for the device count; only positions below the count take part
+    const int load_n = (int)tmin<int64_t>(TILE, n_host - base);
+    const int64_t n = n_dev ? tmin<int64_t>(n_host, (int64_t)*n_dev) : n_host;
+    const int tile_n = (int)tmin<int64_t>(TILE, n - base);  // may be <= 0 when n is a device count
     {
         uint64_t k[ITEMS];  // all loads in flight before the LDS stores
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const int pos = wpos + j * WAVE;
-            k[j] = pos < tile_n ? keys[base + pos] : KEY_NONE;
+            k[j] = pos < load_n ? keys[base + pos] : KEY_NONE;
+        }
+        if (tile_n <= 0) {
+            // past the device key count: no later tile has keys either
+            if (tile == 0)
+                for (int64_t v = tid; v <= n_vert; v += BLOCK) row_ptr[v] = 0;
+            return;
         }
         uint64_t halo = KEY_NONE;
         if (tid == 0 && base > 0) halo = keys[base - 1];
@@ -146,6 +149,60 @@ inline hipError_t launch_unique_csr(const char* name, const uint64_t* keys, int6
                                     uint64_t* lookback, uint32_t* ticket, uint32_t* err, hipStream_t s) {
     return launch(name, unique_csr_kernel<UNIQ_BLOCK, UNIQ_ITEMS>, dim3((unsigned)ceil_div(n_host, UNIQ_TILE)),
                   dim3(UNIQ_BLOCK), s, keys, n_host, n_dev, b, n_vert, cols, cols_cap, row_ptr, lookback, ticket, err);
+}
+
+// Exclusive scan of n int32 counts: out[i] = sum of in[0..i), out[n] = total.
+// Tiles by ticket, one wave-wide look-back per tile.
+constexpr int SCAN_BLOCK = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
+
+static __global__ __launch_bounds__(SCAN_BLOCK) void scan_i32_kernel(const int32_t* __restrict__ in, int64_t n,
+                                                             int32_t* __restrict__ out, uint64_t* lookback,
+                                                             uint32_t* ticket, uint32_t* err) {
+    constexpr int WAVES = SCAN_BLOCK / WAVE;
+    static_assert(SCAN_ITEMS * WAVES <= WAVE, "one wave scans the item/wave sums");
+    __shared__ uint32_t s_sum[SCAN_ITEMS * WAVES];
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_prefix;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
+    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const int64_t base = (int64_t)tile * SCAN_TILE;
+    uint32_t c[SCAN_ITEMS], ex[SCAN_ITEMS];
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const int64_t i = base + j * SCAN_BLOCK + wid * WAVE + lane;
+        c[j] = i < n ? (uint32_t)in[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const uint32_t incl = wave_inclusive_sum(c[j]);
+        ex[j] = incl - c[j];
+        if (lane == WAVE - 1) s_sum[j * WAVES + wid] = incl;
+    }
+    __syncthreads();
+    if (wid == 0) {
+        const uint32_t v = lane < SCAN_ITEMS * WAVES ? s_sum[lane] : 0u;
+        const uint32_t incl = wave_inclusive_sum(v);
+        if (lane < SCAN_ITEMS * WAVES) s_sum[lane] = incl - v;
+        const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+        if (lane == 0) lb_store(lookback + tile, (tile == 0 ? LB_INC : LB_AGG) | total);
+        const uint64_t before = wave_lookback_prefix(lookback, tile, total, err);
+        if (lane == 0) s_prefix = before;
+    }
+    __syncthreads();
+    const uint64_t prefix = s_prefix;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const int64_t i = base + j * SCAN_BLOCK + wid * WAVE + lane;
+        if (i < n) {
+            const uint64_t start = prefix + s_sum[j * WAVES + wid] + ex[j];
+            out[i] = (int32_t)start;
+            if (i == n - 1) out[n] = (int32_t)(start + c[j]);
+        }
+    }
 }
 
 }  // namespace mnb

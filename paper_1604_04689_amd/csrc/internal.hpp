@@ -19,11 +19,15 @@ struct NodePlan {
     int32_t n_vert = 0;
     int64_t n_pairs = 0;      // 2 * edges per element * n_elem
     uint32_t id_bits = 1;     // b: bits of a vertex id in the packed key
-    int n_pass = 0;           // radix passes over the 2b key bits
+    int n_pass = 0;           // radix passes over the 2b key bits (full-key mode)
+    uint32_t hi_bits = 1;     // vertex-rows mode: bits sorted above the low b bits
+    int n_pass_rows = 0;      // vertex-rows mode: radix passes
     int64_t n_tiles = 0;      // radix tiles
     int64_t n_utiles = 0;     // unique/CSR tiles
+    int64_t long_cap = 0;     // vertex-rows mode: capacity of the long-row list
     // workspace offsets (bytes)
     size_t off_hist = 0, off_ulb = 0, off_lb0 = 0, off_lb1 = 0, off_keys0 = 0, off_keys1 = 0;
+    size_t off_deg = 0, off_src = 0, off_long = 0;
     size_t zero_bytes = 0;    // bytes from 0 cleared at the start of a call
     size_t total = 0;
 };
@@ -71,6 +75,11 @@ hipError_t run_batch_node(const BatchPlan& p, const int32_t* conn, const mesh_se
 hipError_t run_batch_elem(const BatchPlan& p, const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
                           int32_t total_vert, int32_t* row_ptr, int32_t* cols, int64_t cols_cap, void* ws,
                           hipStream_t s);
+
+// Node algorithm (process-wide): 0 = LSD sort of the full key, then one
+// unique/CSR pass; 1 = LSD sort of the vertex bits only, then per-row sort
+// and deduplication in LDS, scan and gather.
+int node_sort_mode();
 
 // Clears `bytes` (a multiple of 4) from `p` with a fill kernel (no memset
 // nodes, so the sequence can be captured into a graph).

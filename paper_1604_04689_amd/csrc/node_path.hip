@@ -19,6 +19,7 @@
 #include "launch.hpp"
 #include "csr.hpp"
 #include "radix.hpp"
+#include "rows.hpp"
 
 namespace mnb {
 
@@ -75,9 +76,9 @@ struct NodePairSrc {
 // ---------------------------------------------------------------------------
 template <int ET>
 __global__ __launch_bounds__(EMIT_BLOCK) void node_hist_kernel(const int32_t* __restrict__ conn, int64_t n_elem,
-                                                              int32_t n_vert, uint32_t b, int n_pass,
-                                                              uint32_t last_bits, uint32_t* __restrict__ hist,
-                                                              uint32_t* err) {
+                                                              int32_t n_vert, uint32_t b, uint32_t shift0,
+                                                              int n_pass, uint32_t last_bits,
+                                                              uint32_t* __restrict__ hist, uint32_t* err) {
     using E = Elem<ET>;
     constexpr int NPE = E::NPE;
     __shared__ int32_t s_conn[EMIT_BLOCK * NPE];
@@ -121,8 +122,8 @@ __global__ __launch_bounds__(EMIT_BLOCK) void node_hist_kernel(const int32_t* __
                 const uint64_t k1 = edge ? ((uint64_t)w << b) | (uint64_t)u : KEY_NONE;
                 for (int p = 0; p < n_pass; ++p) {
                     const uint32_t mask = (p == n_pass - 1) ? ((1u << last_bits) - 1) : (RADIX - 1);
-                    atomicAdd(&s_hist[p * RADIX + ((uint32_t)(k0 >> (p * RBITS)) & mask)], 1u);
-                    atomicAdd(&s_hist[p * RADIX + ((uint32_t)(k1 >> (p * RBITS)) & mask)], 1u);
+                    atomicAdd(&s_hist[p * RADIX + ((uint32_t)(k0 >> (shift0 + p * RBITS)) & mask)], 1u);
+                    atomicAdd(&s_hist[p * RADIX + ((uint32_t)(k1 >> (shift0 + p * RBITS)) & mask)], 1u);
                 }
             }
         }
@@ -145,6 +146,12 @@ static uint32_t id_bits_for(int32_t n_vert) {
     return b;
 }
 
+static uint32_t bits_for_count(int64_t n) {  // smallest b >= 1 with 2^b >= n
+    uint32_t b = 1;
+    while (b < 31 && ((int64_t)1 << b) < n) ++b;
+    return b;
+}
+
 bool plan_node(int64_t n_elem, int32_t etype, int32_t n_vert, NodePlan* p) {
     const int ne = edges_per_elem(etype);
     if (ne == 0 || n_elem < 0 || n_vert < 0) return false;
@@ -154,22 +161,34 @@ bool plan_node(int64_t n_elem, int32_t etype, int32_t n_vert, NodePlan* p) {
     p->n_pairs = 2 * (int64_t)ne * n_elem;
     p->id_bits = id_bits_for(n_vert);
     p->n_pass = (int)ceil_div(2 * p->id_bits, RBITS);
+    // vertex-rows mode sorts the high part only; its bits leave the all-ones
+    // value free for KEY_NONE so that no real key ties with it
+    p->hi_bits = bits_for_count((int64_t)n_vert + 1);
+    p->n_pass_rows = (int)ceil_div(p->hi_bits, RBITS);
     p->n_tiles = ceil_div(p->n_pairs, min_radix_tile());  // look-back room for any tile shape
     p->n_utiles = ceil_div(p->n_pairs, UNIQ_TILE);
+    p->long_cap = p->n_pairs / (ROW_SHORT + 1) + 1;
     size_t off = HEADER_BYTES;
     p->off_hist = off;
     off += align_up(MAX_PASS * RADIX * sizeof(uint32_t));
     p->off_ulb = off;
-    off += align_up((size_t)p->n_utiles * sizeof(uint64_t));
+    off += align_up((size_t)tmin<int64_t>(p->n_utiles + ceil_div((int64_t)n_vert + 1, SCAN_TILE), INT64_MAX) *
+                    sizeof(uint64_t));
     p->off_lb0 = off;
     off += align_up((size_t)p->n_tiles * RADIX * sizeof(uint64_t));
-    p->zero_bytes = off;  // header, histograms, unique look-back, pass-0 look-back
+    p->zero_bytes = off;  // header, histograms, CSR/scan look-back, pass-0 look-back
     p->off_lb1 = off;
     off += align_up((size_t)p->n_tiles * RADIX * sizeof(uint64_t));
     p->off_keys0 = off;
     off += align_up((size_t)p->n_pairs * sizeof(uint64_t));
     p->off_keys1 = off;
     off += align_up((size_t)p->n_pairs * sizeof(uint64_t));
+    p->off_deg = off;  // vertex-rows mode: distinct neighbors per vertex
+    off += align_up((size_t)n_vert * sizeof(int32_t));
+    p->off_src = off;  // vertex-rows mode: first key index of each row
+    off += align_up((size_t)n_vert * sizeof(int64_t));
+    p->off_long = off;
+    off += align_up((size_t)p->long_cap * sizeof(int64_t));
     p->total = off;
     return true;
 }
@@ -185,17 +204,25 @@ static hipError_t node_pipeline(const NodePlan& p, const int32_t* conn, int32_t*
     uint64_t* lb[2] = {(uint64_t*)(w + p.off_lb0), (uint64_t*)(w + p.off_lb1)};
     uint64_t* kb[2] = {(uint64_t*)(w + p.off_keys0), (uint64_t*)(w + p.off_keys1)};
     const int shape = radix_shape();
+    const bool rows = node_sort_mode() == 1;
 
+    // full-key mode: passes over all 2b key bits; vertex-rows mode: over the
+    // hi_bits above the low b bits
+    const uint32_t shift0 = rows ? p.id_bits : 0;
+    const uint32_t sort_bits = rows ? p.hi_bits : 2 * p.id_bits;
+    const int n_pass = rows ? p.n_pass_rows : p.n_pass;
     const int grid = (int)tmin<int64_t>(ceil_div(p.n_elem, EMIT_BLOCK), EMIT_GRID_MAX);
-    const uint32_t total_bits = 2 * p.id_bits;
-    const uint32_t last_bits = total_bits - (uint32_t)(p.n_pass - 1) * RBITS;
-    hipError_t e = launch("node_hist", node_hist_kernel<ET>, dim3(grid), dim3(EMIT_BLOCK), s, conn, p.n_elem,
-                          p.n_vert, p.id_bits, p.n_pass, last_bits, hist, err);
-    for (int pass = 0; pass < p.n_pass && e == hipSuccess; ++pass) {
-        const uint32_t shift = (uint32_t)pass * RBITS;
-        const uint32_t bits = tmin<uint32_t>(RBITS, total_bits - shift);
+    const uint32_t last_bits = sort_bits - (uint32_t)(n_pass - 1) * RBITS;
+    hipError_t e = hipSuccess;
+    if (rows) e = fill_i32((int32_t*)(w + p.off_deg), p.n_vert, 0, s);
+    if (e == hipSuccess)
+        e = launch("node_hist", node_hist_kernel<ET>, dim3(grid), dim3(EMIT_BLOCK), s, conn, p.n_elem, p.n_vert,
+                   p.id_bits, shift0, n_pass, last_bits, hist, err);
+    for (int pass = 0; pass < n_pass && e == hipSuccess; ++pass) {
+        const uint32_t shift = shift0 + (uint32_t)pass * RBITS;
+        const uint32_t bits = tmin<uint32_t>(RBITS, sort_bits - (uint32_t)pass * RBITS);
         uint64_t* out = kb[pass & 1];
-        uint64_t* lb_next = pass + 1 < p.n_pass ? lb[(pass + 1) & 1] : nullptr;
+        uint64_t* lb_next = pass + 1 < n_pass ? lb[(pass + 1) & 1] : nullptr;
         if (pass == 0)
             e = launch_radix_pass("node_radix_first", shape, NodePairSrc<ET>{conn, p.n_vert, p.id_bits}, out,
                                   p.n_pairs, shift, bits, hist, lb[0], lb_next, tickets + 0, err, s);
@@ -204,9 +231,31 @@ static hipError_t node_pipeline(const NodePlan& p, const int32_t* conn, int32_t*
                                   bits, hist + pass * RADIX, lb[pass & 1], lb_next, tickets + pass, err, s);
     }
     if (e != hipSuccess) return e;
-    const uint64_t* sorted = kb[(p.n_pass - 1) & 1];
-    return launch_unique_csr("node_unique_csr", sorted, p.n_pairs, (const uint32_t*)nullptr, p.id_bits, p.n_vert, cols, cols_capacity,
-                             row_ptr, ulb, tickets + (N_TICKETS - 1), err, s);
+    const uint64_t* sorted = kb[(n_pass - 1) & 1];
+    if (!rows)
+        return launch_unique_csr("node_unique_csr", sorted, p.n_pairs, (const uint32_t*)nullptr, p.id_bits,
+                                 p.n_vert, cols, cols_capacity, row_ptr, ulb, tickets + (N_TICKETS - 1), err, s);
+    // vertex-rows mode: canonical rows into the free key buffer, then scan and gather
+    int32_t* deg = (int32_t*)(w + p.off_deg);
+    int64_t* src = (int64_t*)(w + p.off_src);
+    int64_t* long_list = (int64_t*)(w + p.off_long);
+    int32_t* temp = (int32_t*)kb[n_pass & 1];
+    e = launch("node_row_unique", row_unique_kernel, dim3((unsigned)ceil_div(p.n_pairs, ROW_TILE)), dim3(ROW_BLOCK),
+               s, sorted, p.n_pairs, p.id_bits, p.n_vert, deg, src, temp, long_list, p.long_cap,
+               hdr + HDR_LONG_COUNT, err);
+    if (e == hipSuccess)
+        e = launch("node_long_rows", long_rows_kernel, dim3(LONG_GRID), dim3(LONG_BLOCK), s, sorted, p.n_pairs,
+                   p.id_bits, p.n_vert, deg, src, temp, (const int64_t*)long_list, p.long_cap,
+                   (const uint32_t*)(hdr + HDR_LONG_COUNT), err);
+    if (e == hipSuccess)
+        e = launch("node_row_scan", scan_i32_kernel, dim3((unsigned)ceil_div((int64_t)p.n_vert, SCAN_TILE)),
+                   dim3(SCAN_BLOCK), s, (const int32_t*)deg, (int64_t)p.n_vert, row_ptr, ulb,
+                   tickets + (N_TICKETS - 2), err);
+    if (e == hipSuccess)
+        e = launch("node_row_gather", row_gather_kernel, dim3((unsigned)ceil_div((int64_t)p.n_vert, GATHER_BLOCK)),
+                   dim3(GATHER_BLOCK), s, (const int32_t*)row_ptr, (const int32_t*)deg, (const int64_t*)src,
+                   (const int32_t*)temp, p.n_vert, cols, cols_capacity, err);
+    return e;
 }
 
 hipError_t run_node(const NodePlan& p, const int32_t* conn, int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,

@@ -20,13 +20,24 @@ struct KeyArraySrc {
     __device__ __forceinline__ uint64_t load(int64_t i) const { return keys[i]; }
 };
 
-// Keys in an array whose participating length is only known on the device.
+// Keys in an array whose participating length is only known on the device:
+// positions at or past *count are not read (the kernel reads the count once
+// per tile, alongside the key loads).
 struct CountedKeySrc {
     const uint64_t* __restrict__ keys;
     const uint32_t* __restrict__ count;
     static constexpr bool kSkipNone = true;
-    __device__ __forceinline__ uint64_t load(int64_t i) const { return i < (int64_t)*count ? keys[i] : KEY_NONE; }
+    __device__ __forceinline__ uint64_t load(int64_t i) const { return keys[i]; }
 };
+
+template <class Src>
+__device__ __forceinline__ int64_t source_limit(const Src&, int64_t n) {
+    return n;
+}
+template <>
+__device__ __forceinline__ int64_t source_limit<CountedKeySrc>(const CountedKeySrc& s, int64_t n) {
+    return tmin<int64_t>(n, (int64_t)*s.count);
+}
 
 // Tile shapes the library is built with: threads per block x keys per thread.
 // The LDS staging area is 8 * BLOCK * ITEMS bytes.
@@ -91,13 +102,16 @@ __global__ __launch_bounds__(BLOCK) void radix_pass_kernel(Src src, uint64_t* __
 
     // ---- 1. load (lanes of a wave read 64 consecutive positions), count ------
     const int64_t wbase = tile_base + (int64_t)wid * WAVE * ITEMS + lane;
+    const int64_t limit_n = source_limit(src, n);
     uint64_t key[ITEMS];
     uint32_t valid_bits = 0;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int64_t idx = wbase + j * WAVE;
+        // positions in [limit_n, n) lie inside the source array; they are read
+        // but never take part, so the loads need not wait for the count
         key[j] = idx < n ? src.load(idx) : KEY_NONE;
-        const bool valid = idx < n && !(Src::kSkipNone && key[j] == KEY_NONE);
+        const bool valid = idx < limit_n && !(Src::kSkipNone && key[j] == KEY_NONE);
         valid_bits |= (uint32_t)valid << j;
     }
 #pragma unroll

@@ -101,31 +101,49 @@ class FakeExecutor:
 
 
 class GpuExecutor:
-    """Runs each batch on its slot's stream through the batched C entry points."""
+    """Runs each batch on its slot's stream through the batched C entry points.
 
-    def __init__(self, n_slots: int, device="cuda:0", keep_results=False):
+    Each slot keeps a pinned host staging buffer and its device buffers
+    (connectivity, workspaces, outputs) across batches; they only grow, so a
+    steady stream of requests allocates nothing after warm-up."""
+
+    def __init__(self, n_slots: int, device="cuda:0"):
         import torch
 
         self.torch = torch
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(self.device) for _ in range(n_slots)]
-        self.keep = keep_results
+        self.slot_state = [dict(pinned=None, conn=None, node=None, elem=None, event=None) for _ in range(n_slots)]
 
     def submit(self, batch: BatchHandle):
         torch = self.torch
+        st = self.slot_state[batch.slot]
         s = self.streams[batch.slot]
         desc = [(r.n_elem, r.etype, r.n_vert) for r in batch.requests]
-        host = _b.concat_conn([r.conn for r in batch.requests])
+        n_ids = sum(r.conn.size for r in batch.requests)
+        if st["pinned"] is None or st["pinned"].numel() < n_ids:
+            st["pinned"] = torch.empty(max(n_ids, 1), dtype=torch.int32, pin_memory=True)
+            st["conn"] = torch.empty(max(n_ids, 1), dtype=torch.int32, device=self.device)
+        host = st["pinned"].numpy()
+        at = 0
+        for r in batch.requests:
+            k = r.conn.size
+            host[at:at + k] = r.conn.reshape(-1)
+            at += k
         with torch.cuda.stream(s):
-            pinned = torch.from_numpy(host).pin_memory() if host.size else torch.zeros(0, dtype=torch.int32)
-            conn = pinned.to(self.device, non_blocking=True)
-            node = _b.BatchBuild("node", desc, self.device)
-            elem = _b.BatchBuild("elem", desc, self.device)
-            node.launch(conn, s)
-            elem.launch(conn, s)
+            conn = st["conn"][:n_ids]
+            conn.copy_(st["pinned"][:n_ids], non_blocking=True)
+            if st["node"] is None:
+                st["node"] = _b.BatchBuild("node", desc, self.device)
+                st["elem"] = _b.BatchBuild("elem", desc, self.device)
+            else:
+                st["node"].reset(desc)
+                st["elem"].reset(desc)
+            st["node"].launch(conn, s)
+            st["elem"].launch(conn, s)
             ev = torch.cuda.Event()
             ev.record(s)
-        batch.payload = {"node": node, "elem": elem, "event": ev, "conn": conn, "pinned": pinned}
+        batch.payload = {"node": st["node"], "elem": st["elem"], "event": ev}
 
     def done(self, batch: BatchHandle) -> bool:
         return batch.payload["event"].query()
