@@ -70,17 +70,16 @@ def kernel_bytes(m, nnz_node, nnz_elem):
         "node_radix_first": conn + 8 * p_pairs,             # read conn, write keys
         "node_radix": 16 * p_pairs,                         # read + write keys
         "node_unique_csr": 8 * p_pairs + 4 * nnz_node + 4 * (v + 1),
+        "node_row_unique": 8 * p_pairs + 4 * nnz_node + 8 * v,  # read keys, write row values + deg/src
+        "node_row_scan": 8 * v,
+        "node_row_gather": 8 * nnz_node + 8 * v + 4 * (v + 1),
+        "node_long_rows": 0,                                # only rows past the short limit; data-dependent
         "elem_hist": conn,
         "elem_radix_first": conn + 8 * q_pairs,
         "elem_radix": 16 * q_pairs,
         "elem_csr": 8 * q_pairs + 4 * q_pairs + 4 * (v + 1),
         "fill": 0,
     }
-
-
-def passes(m):
-    b = id_bits(m.n_vert)
-    return -(-2 * b // 8), -(-b // 8)
 
 
 def radix_source_hash():
@@ -116,8 +115,8 @@ def run_workload(name, steps, warmup, torch, nb):
     stream = torch.cuda.current_stream(dev)
 
     def step():
-        node.launch(conn, stream)
-        elem.launch(conn, stream)
+        node.launch(conn, stream, tuned=True)
+        elem.launch(conn, stream, tuned=True)
 
     for _ in range(max(warmup, 1)):
         step()
@@ -151,13 +150,18 @@ def run_workload(name, steps, warmup, torch, nb):
         kernels[k] = {"launches_per_step": launches / steps, "us_per_step": total_ms / steps * 1e3,
                       "avg_us": avg_ms * 1e3, "bytes_per_launch": per,
                       "GBs": per / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None}
-    node_p, elem_p = passes(m)
+    node_p = sum(kt[k][0] for k in ("node_radix_first", "node_radix") if k in kt) // steps
+    elem_p = sum(kt[k][0] for k in ("elem_radix_first", "elem_radix") if k in kt) // steps
+    from paper_1604_04689_amd import autotune
+    tuned = {kind: autotune.lookup(kind, m.etype, m.n_elem) for kind in ("node", "elem")}
+    tuned = {kind: (None if e is None else {"shape": nb.radix_shapes()[e["shape"]], "node_sort": e["mode"]})
+             for kind, e in tuned.items()}
     node_ms = sum(v[1] for k, v in kt.items() if k.startswith("node_")) / steps
     elem_ms = sum(v[1] for k, v in kt.items() if k.startswith("elem_")) / steps
     res = {
         "workload": name,
         "n_elem": m.n_elem, "n_vert": m.n_vert, "etype": TYPE_NAME[m.etype],
-        "nnz_node": nnz_node, "nnz_elem": nnz_elem, "radix_passes": {"node": node_p, "elem": elem_p},
+        "nnz_node": nnz_node, "nnz_elem": nnz_elem, "radix_passes": {"node": node_p, "elem": elem_p}, "tuned": tuned,
         "ms_per_step": sec * 1e3,
         "elements_per_s": m.n_elem / sec,
         "node_kernel_ms": node_ms, "elem_kernel_ms": elem_ms,

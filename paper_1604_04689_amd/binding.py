@@ -201,11 +201,14 @@ class NeighborBuild:
         self.cols = torch.empty(max(self.cols_capacity, 1), dtype=torch.int32, device=self.device)
         self._fn = getattr(lib(), f"mesh_{kind}_neighbors")
 
-    def launch(self, conn, stream=None):
+    def launch(self, conn, stream=None, tuned=False):
         import torch
 
         if conn.device != self.device or conn.dtype != torch.int32 or not conn.is_contiguous():
             raise ValueError("conn must be a contiguous int32 tensor on the build's device")
+        if tuned and self.etype in NODES_PER_ELEM:
+            from . import autotune
+            autotune.apply(self.kind, self.etype, self.n_elem)
         npe = NODES_PER_ELEM.get(self.etype)
         if npe is not None and conn.numel() != self.n_elem * npe:
             raise ValueError(f"conn has {conn.numel()} ids, expected {self.n_elem} x {npe}")

@@ -17,35 +17,51 @@
 namespace mnb {
 
 constexpr int ROW_BLOCK = 256;
-constexpr int ROW_TILE = 4096;   // keys whose rows a block owns
-constexpr int ROW_HALO = 1024;   // keys read past the tile to finish its last row
-constexpr int ROW_SHORT = 256;   // longest row ranked in LDS; longer rows are listed
+constexpr int ROW_TILE = 2048;   // keys whose rows a block owns
+constexpr int ROW_HALO = 512;    // keys read past the tile to finish its last row
+constexpr int ROW_SHORT = 256;   // longest row handled in LDS; longer rows are listed
 constexpr int LONG_BLOCK = 256;
 constexpr int LONG_LDS = 16384;  // longest row sorted in LDS by one block
 constexpr int LONG_GRID = 256;
 constexpr int GATHER_BLOCK = 256;
+constexpr uint32_t SLOT_EMPTY = 0xffffffffu;
 
-// A block owns the rows whose first key lies in its tile.  Each key of such a
-// row finds its row's extent in LDS, decides whether it is the first copy of
-// its lo value, and (after a barrier) counts the distinct values below it:
-// that count is its place in the row.  Rows longer than ROW_SHORT, or not
-// ending inside the halo, are listed (by first key index) for long_rows.
+static_assert(ROW_HALO >= ROW_SHORT, "a short row owned by a tile ends inside its halo");
+
+// A block owns the rows whose first key lies in its tile (keys read past the
+// tile finish its last row).  Per position: its row's first position by a
+// max-scan of row starts, the row length from the row's last position.  Each
+// key of a short row inserts its low part into an open-addressing table in
+// LDS that spans the row's own positions (size L, linear probing); the
+// insertion that fills an empty slot is the value's one kept copy.  A kept
+// value's place in the row is the number of distinct values below it, counted
+// over the row's table.  Rows longer than ROW_SHORT (or running past the halo)
+// are listed, by first key index, for long_rows.
 static __global__ __launch_bounds__(ROW_BLOCK) void row_unique_kernel(const uint64_t* __restrict__ keys, int64_t n,
-                                                              uint32_t b, int32_t n_vert, int32_t* __restrict__ deg,
-                                                              int64_t* __restrict__ src, int32_t* __restrict__ temp,
-                                                              int64_t* __restrict__ long_list, int64_t long_cap,
-                                                              uint32_t* long_count, uint32_t* err) {
+                                                                     uint32_t b, int32_t n_vert,
+                                                                     int32_t* __restrict__ deg,
+                                                                     int64_t* __restrict__ src,
+                                                                     int32_t* __restrict__ temp,
+                                                                     int64_t* __restrict__ long_list,
+                                                                     int64_t long_cap, uint32_t* long_count,
+                                                                     uint32_t* err) {
     constexpr int SPAN = ROW_TILE + ROW_HALO;
     constexpr int PER = SPAN / ROW_BLOCK;
-    __shared__ uint64_t s_k[SPAN + 1];    // s_k[0] = key before the tile, s_k[1 + p] = key base + p
-    __shared__ uint8_t s_start[SPAN + 1];  // s_start[p]: position p starts a row (p = SPAN: sentinel)
-    __shared__ uint8_t s_first[SPAN];      // position p holds the first copy of its lo value in its row
+    constexpr int WAVES = ROW_BLOCK / WAVE;
+    static_assert(SPAN % ROW_BLOCK == 0, "whole positions per thread");
+    __shared__ uint64_t s_k[SPAN + 1];   // s_k[0] = key before the tile, s_k[1 + p] = key base + p
+    __shared__ int16_t s_rs[SPAN];       // first position of p's row (-1: row starts before the tile)
+    __shared__ int16_t s_len[SPAN];      // at a row's first position: its length (0 if it leaves the span)
+    __shared__ uint32_t s_tab[SPAN];     // per-row open-addressing tables over the row's positions
+    __shared__ int32_t s_tmp[WAVES];
+    __shared__ int32_t s_bounds[2];
     const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1), wid = tid / WAVE;
     const int64_t base = (int64_t)blockIdx.x * ROW_TILE;
     const int span = (int)tmin<int64_t>(SPAN, n - base);
     const uint64_t lo_mask = (1ull << b) - 1;
     {
-        uint64_t k[PER];
+        uint64_t k[PER];  // striped, coalesced; all loads in flight before the stores
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int p = q * ROW_BLOCK + tid;
@@ -53,79 +69,144 @@ static __global__ __launch_bounds__(ROW_BLOCK) void row_unique_kernel(const uint
         }
         const uint64_t before = (tid == 0 && base > 0) ? keys[base - 1] : KEY_NONE;
 #pragma unroll
-        for (int q = 0; q < PER; ++q) s_k[1 + q * ROW_BLOCK + tid] = k[q];
-        if (tid == 0) s_k[0] = before;
+        for (int q = 0; q < PER; ++q) {
+            const int p = q * ROW_BLOCK + tid;
+            s_k[1 + p] = k[q];
+            s_tab[p] = SLOT_EMPTY;
+            s_len[p] = 0;
+        }
+        if (tid == 0) {
+            s_k[0] = before;
+            s_bounds[0] = ROW_TILE;
+            s_bounds[1] = SPAN;
+        }
     }
     __syncthreads();
-    // row starts: a real key whose hi differs from its predecessor's (the
-    // first real key of the array starts a row; KEY_NONE ends the data)
-    for (int p = tid; p <= SPAN; p += ROW_BLOCK) {
-        bool st;
-        if (p == SPAN || p >= span) st = true;
-        else {
-            const uint64_t cur = s_k[1 + p];
-            if (cur == KEY_NONE) st = true;
-            else if (base + p == 0) st = true;
-            else st = (cur >> b) != (s_k[p] >> b) || s_k[p] == KEY_NONE;
+    // ---- row starts and the first position of every row (blocked: PER
+    // consecutive positions per thread, then a max-scan over the threads)
+    bool st[PER];
+    int last = -1;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int p = tid * PER + q;
+        const uint64_t cur = s_k[1 + p], prev = s_k[p];
+        const bool s_ = p >= span || cur == KEY_NONE || base + p == 0 || prev == KEY_NONE || (cur >> b) != (prev >> b);
+        st[q] = s_;
+        if (s_) last = p;
+    }
+    {
+        int incl = last;
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const int y = __shfl_up(incl, d, WAVE);
+            if (lane >= d) incl = y > incl ? y : incl;
         }
-        s_start[p] = st;
+        if (lane == WAVE - 1) s_tmp[wid] = incl;
+        __syncthreads();
+        int before_w = -1;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w)
+            if (w < wid) before_w = s_tmp[w] > before_w ? s_tmp[w] : before_w;
+        int prev = __shfl_up(incl, 1, WAVE);
+        if (lane == 0) prev = -1;
+        int cur_rs = prev > before_w ? prev : before_w;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int p = tid * PER + q;
+            if (st[q]) cur_rs = p;
+            s_rs[p] = (int16_t)cur_rs;
+            if (st[q] && p < ROW_TILE) atomicMin(&s_bounds[0], p);
+            if (st[q] && p >= ROW_TILE) atomicMin(&s_bounds[1], p);
+        }
     }
     __syncthreads();
-    // owned region: from the first row start in the tile to the first row start at or after ROW_TILE
-    // (every thread finds the same bounds)
-    int p0 = ROW_TILE, pe = SPAN;
-    for (int p = 0; p < ROW_TILE; ++p)
-        if (s_start[p]) {
-            p0 = p;
-            break;
-        }
-    for (int p = ROW_TILE; p <= SPAN; ++p)
-        if (s_start[p]) {
-            pe = p;
-            break;
-        }
+    const int p0 = s_bounds[0], pe = s_bounds[1];
     if (p0 >= ROW_TILE) return;  // the tile lies inside a row owned by an earlier tile
-    // keep flags
+    // ---- row lengths, written at each row's first position by its last position
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int p = tid * PER + q;
+        if (p < p0 || p >= pe || s_k[1 + p] == KEY_NONE) continue;
+        bool next_start;
+        if (q + 1 < PER) next_start = st[q + 1];
+        else if (p + 1 >= SPAN) next_start = false;  // the row may go on past the span
+        else next_start = s_rs[p + 1] == p + 1;
+        if (next_start) s_len[s_rs[p]] = (int16_t)(p + 1 - s_rs[p]);
+    }
+    __syncthreads();
+    // ---- insert every key of a short row into its row's table (striped:
+    // consecutive positions on consecutive threads); a first probe for all,
+    // then further probes for the few that collided
     bool bad = false;
-    for (int p = p0 + tid; p < pe; p += ROW_BLOCK) {
+    uint32_t kept = 0, pending = 0;
+    uint32_t hslot[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int p = q * ROW_BLOCK + tid;
+        hslot[q] = 0;
+        if (p < p0 || p >= pe) continue;
         const uint64_t cur = s_k[1 + p];
         if (cur == KEY_NONE) continue;
-        int rs = p;
-        while (!s_start[rs]) --rs;
-        int re = p + 1;
-        while (!s_start[re]) ++re;
-        if (re - rs > ROW_SHORT || (re == SPAN && base + SPAN < n)) {
+        const int rs = s_rs[p];
+        const int len = s_len[rs];
+        if (len == 0 || len > ROW_SHORT) {  // long, or running past the span
             if (p == rs) {
                 const uint32_t slot = atomicAdd(long_count, 1u);
                 if ((int64_t)slot < long_cap) long_list[slot] = base + rs;
                 else bad = true;
             }
-            s_first[p] = 0;
             continue;
         }
-        const uint64_t lo = cur & lo_mask;
-        bool first = true;
-        for (int j = rs; j < p; ++j) first &= (s_k[1 + j] & lo_mask) != lo;
-        s_first[p] = first;
+        const uint32_t lo = (uint32_t)(cur & lo_mask);
+        const uint32_t h = (uint32_t)(((uint64_t)(lo * 2654435761u) * (uint32_t)len) >> 32);
+        const uint32_t old = atomicCAS(&s_tab[rs + h], SLOT_EMPTY, lo);
+        if (old == SLOT_EMPTY) kept |= 1u << q;
+        else if (old != lo) {
+            pending |= 1u << q;
+            hslot[q] = h;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        if (!((pending >> q) & 1u)) continue;
+        const int p = q * ROW_BLOCK + tid;
+        const int rs = s_rs[p];
+        const uint32_t len = (uint32_t)s_len[rs];
+        const uint32_t lo = (uint32_t)(s_k[1 + p] & lo_mask);
+        uint32_t h = hslot[q];
+        for (uint32_t probe = 1; probe < len; ++probe) {
+            h = h + 1 == len ? 0 : h + 1;
+            const uint32_t old = atomicCAS(&s_tab[rs + h], SLOT_EMPTY, lo);
+            if (old == SLOT_EMPTY) {
+                kept |= 1u << q;
+                break;
+            }
+            if (old == lo) break;
+        }
     }
     __syncthreads();
-    for (int p = p0 + tid; p < pe; p += ROW_BLOCK) {
+    // ---- place every kept value: the number of distinct values below it
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int p = q * ROW_BLOCK + tid;
+        if (p < p0 || p >= pe) continue;
         const uint64_t cur = s_k[1 + p];
         if (cur == KEY_NONE) continue;
-        int rs = p;
-        while (!s_start[rs]) --rs;
-        int re = p + 1;
-        while (!s_start[re]) ++re;
-        if (re - rs > ROW_SHORT || (re == SPAN && base + SPAN < n)) continue;
-        const uint64_t lo = cur & lo_mask;
-        if (s_first[p]) {
+        const int rs = s_rs[p];
+        const int len = s_len[rs];
+        if (len == 0 || len > ROW_SHORT) continue;
+        if ((kept >> q) & 1u) {
+            const uint32_t lo = (uint32_t)(cur & lo_mask);
             int below = 0;
-            for (int j = rs; j < re; ++j) below += (s_first[j] && (s_k[1 + j] & lo_mask) < lo) ? 1 : 0;
+            for (int j = 0; j < len; ++j) {
+                const uint32_t t = s_tab[rs + j];
+                below += (t < lo) ? 1 : 0;  // SLOT_EMPTY is above every value
+            }
             temp[base + rs + below] = (int32_t)lo;
         }
         if (p == rs) {
             int cnt = 0;
-            for (int j = rs; j < re; ++j) cnt += s_first[j];
+            for (int j = 0; j < len; ++j) cnt += s_tab[rs + j] != SLOT_EMPTY ? 1 : 0;
             const int64_t hi = (int64_t)(cur >> b);
             if (hi < n_vert) {
                 deg[hi] = cnt;
@@ -239,24 +320,42 @@ static __global__ __launch_bounds__(LONG_BLOCK) void long_rows_kernel(const uint
     }
 }
 
-// cols[row_ptr[v] + i] = temp[src[v] + i] for i < deg[v]: one thread per row.
+// cols[row_ptr[v] + i] = temp[src[v] + i] for i < deg[v].  A block covers
+// GATHER_BLOCK consecutive vertices; their output range is contiguous, so the
+// block walks it with consecutive threads on consecutive outputs (coalesced
+// writes), finding each output's row by binary search over the block's row
+// starts in LDS.
 static __global__ __launch_bounds__(GATHER_BLOCK) void row_gather_kernel(const int32_t* __restrict__ row_ptr,
-                                                                 const int32_t* __restrict__ deg,
-                                                                 const int64_t* __restrict__ src,
-                                                                 const int32_t* __restrict__ temp, int32_t n_vert,
-                                                                 int32_t* __restrict__ cols, int64_t cols_cap,
-                                                                 uint32_t* err) {
-    const int64_t v = (int64_t)blockIdx.x * GATHER_BLOCK + threadIdx.x;
-    if (v >= n_vert) return;
-    const int d = deg[v];
-    if (d <= 0) return;
-    const int64_t from = src[v];
-    const int64_t to = row_ptr[v];
-    if (to + d > cols_cap) {
-        set_error(err, ERR_CAPACITY);
+                                                                        const int32_t* __restrict__ deg,
+                                                                        const int64_t* __restrict__ src,
+                                                                        const int32_t* __restrict__ temp,
+                                                                        int32_t n_vert, int32_t* __restrict__ cols,
+                                                                        int64_t cols_cap, uint32_t* err) {
+    __shared__ int32_t s_start[GATHER_BLOCK + 1];
+    __shared__ int64_t s_src[GATHER_BLOCK];
+    const int tid = threadIdx.x;
+    const int64_t v0 = (int64_t)blockIdx.x * GATHER_BLOCK;
+    const int nv = (int)tmin<int64_t>(GATHER_BLOCK, (int64_t)n_vert - v0);
+    if (tid < nv) {
+        s_start[tid] = row_ptr[v0 + tid];
+        s_src[tid] = deg[v0 + tid] > 0 ? src[v0 + tid] : 0;
+    }
+    if (tid == 0) s_start[nv] = row_ptr[v0 + nv];
+    __syncthreads();
+    const int64_t a = s_start[0], e = s_start[nv];
+    if (e > cols_cap) {
+        if (tid == 0) set_error(err, ERR_CAPACITY);
         return;
     }
-    for (int i = 0; i < d; ++i) cols[to + i] = temp[from + i];
+    for (int64_t i = a + tid; i < e; i += GATHER_BLOCK) {
+        int lo = 0, hi = nv - 1;  // last row whose start <= i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_start[mid] <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        cols[i] = temp[s_src[lo] + (i - s_start[lo])];
+    }
 }
 
 }  // namespace mnb

@@ -126,3 +126,31 @@ def test_batch_queries():
     assert c.value == 800
     # max_vert above total_vert is inconsistent
     assert binding.lib().mesh_batch_node_neighbors_query(3, 1000, 100, 200, ctypes.byref(w), ctypes.byref(c)) == 1
+
+
+def test_tuning_table_lookup(tmp_path, monkeypatch):
+    import json
+    from paper_1604_04689_amd import autotune
+    table = {"entries": [
+        {"relation": "node", "etype": 0, "bucket": 20, "shape": 2, "mode": 1},
+        {"relation": "node", "etype": 0, "bucket": 26, "shape": 0, "mode": 0},
+        {"relation": "elem", "etype": 1, "bucket": 24, "shape": 3, "mode": 0}]}
+    path = tmp_path / "t.json"
+    path.write_text(json.dumps(table))
+    monkeypatch.setattr(autotune, "TABLE", str(path))
+    monkeypatch.setattr(autotune, "_table_cache", None)
+    monkeypatch.delenv("MESHNBR_TUNING", raising=False)
+    # 2^20 node pairs of triangles = 174763 elements
+    assert autotune.lookup("node", 0, 174763)["shape"] == 2
+    assert autotune.lookup("node", 0, 8380418)["mode"] == 0      # bucket 25 -> nearest 26
+    assert autotune.lookup("elem", 1, 5308416)["shape"] == 3
+    assert autotune.lookup("elem", 0, 1000) is None               # no entry for the type
+    autotune.apply("node", 0, 174763)
+    assert binding.get_radix_shape() == 2 and binding.get_node_sort() == 1
+    autotune.apply("elem", 0, 10)
+    assert binding.get_radix_shape() == 0
+    binding.set_node_sort(0)
+    monkeypatch.setattr(autotune, "_table_cache", None)
+    monkeypatch.setenv("MESHNBR_TUNING", "off")
+    assert autotune.lookup("node", 0, 174763) is None
+    monkeypatch.setattr(autotune, "_table_cache", None)
