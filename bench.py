@@ -103,6 +103,29 @@ def load_traffic(workload):
     return t.get("bytes_per_launch")
 
 
+def time_graph_replays(torch, graphs, builds, stream, steps):
+    """Seconds per step of replaying the captured graphs; checks that the
+    replays leave exactly the eager outputs in place."""
+    before = [(b.row_ptr.clone(), b.cols.clone()) for b in builds]
+    for g in graphs:
+        g.launch(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for g in graphs:
+            g.launch(stream)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    for b, (rp, cols) in zip(builds, before):
+        b.check(stream)
+        nnz = int(rp[-1].item())
+        if not (torch.equal(b.row_ptr, rp) and torch.equal(b.cols[:nnz], cols[:nnz])):
+            raise RuntimeError("graph replay differs from the eager result")
+    for g in graphs:
+        g.destroy()
+    return sec
+
+
 def run_workload(name, steps, warmup, torch, nb):
     log(f"[bench] generating {name} ...")
     t = time.time()
@@ -140,6 +163,8 @@ def run_workload(name, steps, warmup, torch, nb):
     elem.check(stream)
 
     sec = (t1 - t0) / steps
+    graph_sec = time_graph_replays(torch, [node.capture(conn, tuned=True), elem.capture(conn, tuned=True)],
+                                   [node, elem], stream, steps)
     kb = kernel_bytes(m, nnz_node, nnz_elem)
     kernels = {}
     model_total = 0
@@ -164,6 +189,7 @@ def run_workload(name, steps, warmup, torch, nb):
         "nnz_node": nnz_node, "nnz_elem": nnz_elem, "radix_passes": {"node": node_p, "elem": elem_p}, "tuned": tuned,
         "ms_per_step": sec * 1e3,
         "elements_per_s": m.n_elem / sec,
+        "graph_ms_per_step": graph_sec * 1e3,
         "node_kernel_ms": node_ms, "elem_kernel_ms": elem_ms,
         "kernels": kernels,
         "pipeline_model_bytes": model_total,
@@ -172,7 +198,8 @@ def run_workload(name, steps, warmup, torch, nb):
         "radix_pass": {"kernel": "node_radix", "avg_ms": kernels["node_radix"]["avg_us"] * 1e-3,
                        "bytes_per_launch": kb["node_radix"], "GBs": kernels["node_radix"]["GBs"]},
     }
-    log(f"[bench] {name}: {sec * 1e3:.3f} ms/step, {m.n_elem / sec / 1e9:.3f} G elem/s, "
+    log(f"[bench] {name}: {sec * 1e3:.3f} ms/step eager, {graph_sec * 1e3:.3f} ms/step graph replay, "
+        f"{m.n_elem / sec / 1e9:.3f} G elem/s, "
         f"pipeline {res['pipeline_model_GBs']:.0f} GB/s of model bytes")
     for k, v in kernels.items():
         gbs = f"{v['GBs']:7.0f} GB/s" if v["GBs"] else ""
@@ -218,6 +245,7 @@ def run_batched(steps, warmup, torch, nb, per_mesh_steps=2):
     node.check(stream)
     elem.check(stream)
     batched = (t1 - t0) / steps
+    batched_graph = time_graph_replays(torch, [node.capture(conn), elem.capture(conn)], [node, elem], stream, steps)
     del node, elem
 
     # the same meshes, one plain call per mesh and relation
@@ -245,6 +273,7 @@ def run_batched(steps, warmup, torch, nb, per_mesh_steps=2):
     torch.cuda.empty_cache()
     res = {"meshes": len(meshes), "n_elem": total_f,
            "batched_ms_per_step": batched * 1e3, "batched_elements_per_s": total_f / batched,
+           "batched_graph_ms_per_step": batched_graph * 1e3,
            "per_mesh_ms_per_step": per_mesh * 1e3, "per_mesh_elements_per_s": total_f / per_mesh,
            "batched_over_per_mesh": per_mesh / batched,
            "kernel_ms_per_step": {k: v[1] / steps for k, v in sorted(kt.items())}}

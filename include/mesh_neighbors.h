@@ -157,6 +157,48 @@ mesh_status mesh_batch_elem_neighbors(const int32_t* conn, const mesh_segment* s
                                       int64_t cols_capacity, void* workspace, size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* HIP graphs: one call's launch sequence, captured once, replayed cheaply. */
+/* ------------------------------------------------------------------------ */
+
+/* An instantiated HIP graph owned by the library (opaque). */
+typedef struct mesh_graph_s* mesh_graph;
+
+/* Each mesh_graph_* capture takes the arguments of the entry point of the
+ * same name (without the stream), validates them exactly as that entry point
+ * does (returning the same status), and records its whole launch sequence on
+ * a private stream into *graph.  Nothing runs at capture time.  The graph
+ * keeps the pointers and sizes it was captured with: every replay reads the
+ * buffers' contents at that time (conn, and segs for batches, may change
+ * between replays; their sizes may not) and rewrites the outputs and the
+ * workspace, so a replay returns what an eager call on the same contents
+ * returns, bit for bit.  The process-wide radix shape and node algorithm
+ * are fixed at capture.  The buffers must stay allocated while the graph
+ * lives.  Launches being captured are not timed.  Returns MESH_ERR_HIP if
+ * capture or instantiation fails; *graph is then NULL. */
+mesh_status mesh_graph_node_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
+                                      int32_t* row_ptr, int32_t* cols, int64_t cols_capacity, void* workspace,
+                                      size_t workspace_bytes, mesh_graph* graph);
+mesh_status mesh_graph_elem_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
+                                      int32_t* row_ptr, int32_t* cols, int64_t cols_capacity, void* workspace,
+                                      size_t workspace_bytes, mesh_graph* graph);
+mesh_status mesh_graph_batch_node_neighbors(const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
+                                            int64_t total_pairs, int32_t total_vert, int32_t max_vert,
+                                            int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
+                                            void* workspace, size_t workspace_bytes, mesh_graph* graph);
+mesh_status mesh_graph_batch_elem_neighbors(const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
+                                            int64_t total_slots, int32_t total_vert, int32_t* row_ptr,
+                                            int32_t* cols, int64_t cols_capacity, void* workspace,
+                                            size_t workspace_bytes, mesh_graph* graph);
+
+/* Enqueues one replay of `graph` on `stream` (asynchronous, like the eager
+ * calls; read errors with mesh_check on the captured workspace).  Replays of
+ * one graph on different streams must not overlap: they share its buffers. */
+mesh_status mesh_graph_launch(mesh_graph graph, void* stream);
+
+/* Frees the graph (NULL is accepted).  Replays already enqueued complete. */
+mesh_status mesh_graph_destroy(mesh_graph graph);
+
+/* ------------------------------------------------------------------------ */
 /* Diagnostics.                                                             */
 /* ------------------------------------------------------------------------ */
 

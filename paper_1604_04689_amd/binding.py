@@ -69,6 +69,16 @@ SIGNATURES = {
     "mesh_set_node_sort": (_c_i32, [_c_i32]),
     "mesh_get_node_sort": (_c_i32, []),
     "mesh_timing_read": (_c_i32, [ctypes.POINTER(KernelTime), _c_i32]),
+    "mesh_graph_node_neighbors": (_c_i32, [_c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64, _c_p, _c_sz,
+                                           ctypes.POINTER(_c_p)]),
+    "mesh_graph_elem_neighbors": (_c_i32, [_c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64, _c_p, _c_sz,
+                                           ctypes.POINTER(_c_p)]),
+    "mesh_graph_batch_node_neighbors": (_c_i32, [_c_p, _c_p, _c_i32, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64,
+                                                 _c_p, _c_sz, ctypes.POINTER(_c_p)]),
+    "mesh_graph_batch_elem_neighbors": (_c_i32, [_c_p, _c_p, _c_i32, _c_i64, _c_i32, _c_p, _c_p, _c_i64, _c_p,
+                                                 _c_sz, ctypes.POINTER(_c_p)]),
+    "mesh_graph_launch": (_c_i32, [_c_p, _c_p]),
+    "mesh_graph_destroy": (_c_i32, [_c_p]),
 }
 
 
@@ -228,6 +238,64 @@ class NeighborBuild:
         nnz = int(self.row_ptr[-1].item())
         return self.row_ptr, self.cols[:nnz]
 
+    def capture(self, conn, tuned=False):
+        """A Graph replaying ``launch(conn)`` on this build's buffers; conn's
+        contents may change between replays, its address and size may not."""
+        import torch
+
+        if conn.device != self.device or conn.dtype != torch.int32 or not conn.is_contiguous():
+            raise ValueError("conn must be a contiguous int32 tensor on the build's device")
+        if tuned and self.etype in NODES_PER_ELEM:
+            from . import autotune
+            autotune.apply(self.kind, self.etype, self.n_elem)
+        npe = NODES_PER_ELEM.get(self.etype)
+        if npe is not None and conn.numel() != self.n_elem * npe:
+            raise ValueError(f"conn has {conn.numel()} ids, expected {self.n_elem} x {npe}")
+        h = _c_p()
+        with _device_guard(self.device):
+            st = getattr(lib(), f"mesh_graph_{self.kind}_neighbors")(
+                _ptr(conn), self.n_elem, self.etype, self.n_vert, _ptr(self.row_ptr),
+                _ptr(self.cols) if self.cols_capacity > 0 else ctypes.c_void_p(0), self.cols_capacity,
+                _ptr(self.workspace), self.ws_bytes, ctypes.byref(h))
+        if st != Status.OK:
+            raise MeshError(st, f"mesh_graph_{self.kind}_neighbors")
+        return Graph(h, self.device, keep=(conn, self._ws_raw, self.row_ptr, self.cols))
+
+
+class Graph:
+    """An instantiated HIP graph of one call (see mesh_graph_* in the
+    header).  Holds references to the buffers it was captured on."""
+
+    def __init__(self, handle, device, keep=()):
+        self._h = handle
+        self.device = device
+        self._keep = keep
+
+    def launch(self, stream=None):
+        if not self._h:
+            raise ValueError("graph was destroyed")
+        st = lib().mesh_graph_launch(self._h, _stream_handle(stream, self.device))
+        if st != Status.OK:
+            raise MeshError(st, "mesh_graph_launch")
+
+    def destroy(self):
+        if self._h:
+            lib().mesh_graph_destroy(self._h)
+            self._h = None
+            self._keep = ()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def _device_guard(device):
+    import torch
+
+    return torch.cuda.device(device)
+
 
 def _n_elem(conn, etype):
     if conn.dim() == 2:
@@ -296,9 +364,15 @@ class BatchBuild:
         self.kind = kind
         self.device = torch.device(device)
         self._ws_raw = self._rp = self._cols = self._segs = None
+        self._seg_pinned = self._seg_event = None
         self.reset(meshes)
 
-    def reset(self, meshes):
+    def reset(self, meshes, stream=None):
+        """Re-target at another batch.  The segment table is uploaded
+        asynchronously on ``stream`` (default: the current stream), so reset
+        and launch must use the same stream."""
+        import contextlib
+
         import torch
 
         seg, tot = segment_table(meshes)
@@ -329,9 +403,20 @@ class BatchBuild:
         self.row_ptr = self._rp[:tot["vert"] + 1]
         self._cols = grow(self._cols, self.cols_capacity, torch.int32)
         self.cols = self._cols
-        self._segs = grow(self._segs, 48 * max(len(meshes), 1), torch.uint8)
-        if len(meshes):
-            self._segs[:48 * len(meshes)].copy_(torch.from_numpy(seg.view("u1")), non_blocking=False)
+        nbytes = 48 * len(meshes)
+        self._segs = grow(self._segs, max(nbytes, 1), torch.uint8)
+        if nbytes:
+            # the pinned staging buffer is rewritten only after its previous upload has completed
+            if self._seg_event is not None:
+                self._seg_event.synchronize()
+            if self._seg_pinned is None or self._seg_pinned.numel() < nbytes:
+                self._seg_pinned = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+            self._seg_pinned[:nbytes].numpy()[:] = seg.view("u1")
+            ctx = torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+            with ctx:
+                self._segs[:nbytes].copy_(self._seg_pinned[:nbytes], non_blocking=True)
+                self._seg_event = torch.cuda.Event()
+                self._seg_event.record()
         self.segs = self._segs
 
     def launch(self, conn, stream=None):
@@ -364,6 +449,34 @@ class BatchBuild:
         self.check(stream)
         nnz = int(self.row_ptr[-1].item())
         return self.row_ptr, self.cols[:nnz]
+
+    def capture(self, conn):
+        """A Graph replaying ``launch(conn)`` for the current batch layout
+        (totals fixed; conn and segment contents may change between replays
+        as long as the totals stay the same)."""
+        import torch
+
+        if conn.device != self.device or conn.dtype != torch.int32 or not conn.is_contiguous():
+            raise ValueError("conn must be a contiguous int32 tensor on the build's device")
+        if conn.numel() != self.totals["ids"]:
+            raise ValueError(f"conn has {conn.numel()} ids, the segments cover {self.totals['ids']}")
+        t = self.totals
+        h = _c_p()
+        with _device_guard(self.device):
+            if self.kind == "node":
+                st = lib().mesh_graph_batch_node_neighbors(_ptr(conn), _ptr(self.segs), self.n_mesh, t["pairs"],
+                                                           t["vert"], t["max_vert"], _ptr(self.row_ptr),
+                                                           _ptr(self.cols), self.cols_capacity, _ptr(self.workspace),
+                                                           self.ws_bytes, ctypes.byref(h))
+            else:
+                st = lib().mesh_graph_batch_elem_neighbors(_ptr(conn), _ptr(self.segs), self.n_mesh, t["slots"],
+                                                           t["vert"], _ptr(self.row_ptr), _ptr(self.cols),
+                                                           self.cols_capacity, _ptr(self.workspace), self.ws_bytes,
+                                                           ctypes.byref(h))
+        if st != Status.OK:
+            raise MeshError(st, f"mesh_graph_batch_{self.kind}_neighbors")
+        # the graph holds the buffers themselves: a later reset() may replace them
+        return Graph(h, self.device, keep=(conn, self._ws_raw, self._rp, self._cols, self._segs))
 
     def mesh_csr(self, m, row_ptr_host=None):
         """(row_ptr, cols) of mesh m alone, as device tensors, after result()."""

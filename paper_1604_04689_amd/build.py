@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmeshnbr.so")
-SOURCES = ["api.hip", "node_path.hip", "elem_path.hip", "batch_path.hip", "timing.hip"]
+SOURCES = ["api.hip", "node_path.hip", "elem_path.hip", "batch_path.hip", "graph.hip", "timing.hip"]
 ARCH = os.environ.get("MESHNBR_ARCH", "gfx950")
 
 

@@ -3,6 +3,7 @@
 // types and, while kernel timing is enabled, brackets the dispatch with HIP
 // events taken by the launch itself (hipExtLaunchKernel), on the launch's own
 // stream, so per-kernel durations can be read back (mesh_timing_read).
+// Launches into a stream that is being captured into a graph run untimed.
 #pragma once
 
 #include <hip/hip_ext.h>
@@ -33,7 +34,10 @@ hipError_t launch(const char* name, void (*kernel)(P...), dim3 grid, dim3 block,
         vals);
     if (grid.x == 0 || grid.y == 0 || grid.z == 0) return hipSuccess;
     hipEvent_t e0, e1;
-    if (timing_enabled() && timing_begin(&e0, &e1)) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    // launches recorded into a graph run untimed
+    if (timing_enabled() && hipStreamIsCapturing(stream, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone &&
+        timing_begin(&e0, &e1)) {
         hipError_t e = hipExtLaunchKernel((const void*)kernel, grid, block, args, 0, stream, e0, e1, 0);
         if (e == hipSuccess) timing_commit(name, e0, e1);
         return e;

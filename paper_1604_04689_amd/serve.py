@@ -107,13 +107,33 @@ class GpuExecutor:
     (connectivity, workspaces, outputs) across batches; they only grow, so a
     steady stream of requests allocates nothing after warm-up."""
 
-    def __init__(self, n_slots: int, device="cuda:0"):
+    COPY_CHUNK = 1 << 20  # ids per staging task
+
+    def __init__(self, n_slots: int, device="cuda:0", copy_threads: int = 8):
+        import concurrent.futures
+
         import torch
 
         self.torch = torch
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(self.device) for _ in range(n_slots)]
         self.slot_state = [dict(pinned=None, conn=None, node=None, elem=None, event=None) for _ in range(n_slots)]
+        # numpy releases the GIL for plain copies, so staging runs on several cores
+        self.pool = concurrent.futures.ThreadPoolExecutor(copy_threads) if copy_threads > 1 else None
+
+    def _stage(self, host, requests):
+        tasks, at = [], 0
+        for r in requests:
+            src = r.conn.reshape(-1)
+            for a in range(0, src.size, self.COPY_CHUNK):
+                b = min(a + self.COPY_CHUNK, src.size)
+                tasks.append((host[at + a:at + b], src[a:b]))
+            at += src.size
+        if self.pool is None or len(tasks) == 1:
+            for d, s in tasks:
+                np.copyto(d, s, casting="unsafe")
+        else:
+            list(self.pool.map(lambda t: np.copyto(t[0], t[1], casting="unsafe"), tasks))
 
     def submit(self, batch: BatchHandle):
         torch = self.torch
@@ -121,15 +141,12 @@ class GpuExecutor:
         s = self.streams[batch.slot]
         desc = [(r.n_elem, r.etype, r.n_vert) for r in batch.requests]
         n_ids = sum(r.conn.size for r in batch.requests)
+        # the slot is free, so its previous batch (and its upload) has completed
         if st["pinned"] is None or st["pinned"].numel() < n_ids:
             st["pinned"] = torch.empty(max(n_ids, 1), dtype=torch.int32, pin_memory=True)
-            st["conn"] = torch.empty(max(n_ids, 1), dtype=torch.int32, device=self.device)
-        host = st["pinned"].numpy()
-        at = 0
-        for r in batch.requests:
-            k = r.conn.size
-            host[at:at + k] = r.conn.reshape(-1)
-            at += k
+            with torch.cuda.stream(s):
+                st["conn"] = torch.empty(max(n_ids, 1), dtype=torch.int32, device=self.device)
+        self._stage(st["pinned"].numpy(), batch.requests)
         with torch.cuda.stream(s):
             conn = st["conn"][:n_ids]
             conn.copy_(st["pinned"][:n_ids], non_blocking=True)
@@ -137,8 +154,8 @@ class GpuExecutor:
                 st["node"] = _b.BatchBuild("node", desc, self.device)
                 st["elem"] = _b.BatchBuild("elem", desc, self.device)
             else:
-                st["node"].reset(desc)
-                st["elem"].reset(desc)
+                st["node"].reset(desc, s)
+                st["elem"].reset(desc, s)
             st["node"].launch(conn, s)
             st["elem"].launch(conn, s)
             ev = torch.cuda.Event()
