@@ -24,13 +24,15 @@ constexpr int BH_UNROLL = 4;
 constexpr int B_MAX_PASS = 8;
 constexpr int TK_BCSR = 15;
 
+constexpr int SEG_LUT_SHIFT = 10;
+constexpr int LUT_BLOCK = 256;
+
 static_assert(sizeof(mesh_segment) == 48, "mesh_segment layout");
 
-// Largest m with offset(m) <= i over the segments (offsets non-decreasing).
-// `field` is the byte offset of the int64 offset inside mesh_segment.
+// Largest m in [lo, hi] with offset(m) <= i (offsets non-decreasing).
+// `FIELD` is the byte offset of the int64 offset inside mesh_segment.
 template <int FIELD>
-__device__ __forceinline__ int find_segment(const mesh_segment* __restrict__ segs, int n_mesh, int64_t i) {
-    int lo = 0, hi = n_mesh - 1;
+__device__ __forceinline__ int find_segment(const mesh_segment* __restrict__ segs, int lo, int hi, int64_t i) {
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         const int64_t off = *(const int64_t*)((const char*)(segs + mid) + FIELD);
@@ -40,31 +42,50 @@ __device__ __forceinline__ int find_segment(const mesh_segment* __restrict__ seg
     return lo;
 }
 
-__device__ __forceinline__ void edge_positions(int32_t et, int k, int* a, int* b) {
-    if (et == TRI3) {
-        *a = Elem<TRI3>::A[k];
-        *b = Elem<TRI3>::B[k];
-    } else if (et == TET4) {
-        *a = Elem<TET4>::A[k];
-        *b = Elem<TET4>::B[k];
-    } else {
-        *a = Elem<HEX8>::A[k];
-        *b = Elem<HEX8>::B[k];
-    }
+// lut[t] = segment holding position min(t << SEG_LUT_SHIFT, n - 1), for
+// t < n_lut = ((n - 1) >> SEG_LUT_SHIFT) + 2.  Position i then lies in a
+// segment between lut[i >> SHIFT] and lut[(i >> SHIFT) + 1], usually the
+// first, so the per-key search is short.
+template <int FIELD>
+static __global__ __launch_bounds__(LUT_BLOCK) void segment_lut_kernel(const mesh_segment* __restrict__ segs,
+                                                                      int n_mesh, int64_t n, int32_t* __restrict__ lut,
+                                                                      int64_t n_lut) {
+    const int64_t t = (int64_t)blockIdx.x * LUT_BLOCK + threadIdx.x;
+    if (t >= n_lut) return;
+    const int64_t pos = tmin<int64_t>(t << SEG_LUT_SHIFT, n - 1);
+    lut[t] = find_segment<FIELD>(segs, 0, n_mesh - 1, pos);
+}
+
+template <int FIELD>
+__device__ __forceinline__ int lut_segment(const mesh_segment* __restrict__ segs, const int32_t* __restrict__ lut,
+                                           int64_t i) {
+    const int64_t t = i >> SEG_LUT_SHIFT;
+    return find_segment<FIELD>(segs, lut[t], lut[t + 1], i);
+}
+
+// Element, edge nodes and direction of local pair index loc of a mesh of
+// type ET (constant divisors).
+template <int ET>
+__device__ __forceinline__ void pair_of(uint32_t loc, uint32_t* e, int* pa, int* pb, int* dir) {
+    constexpr uint32_t KPE = 2 * Elem<ET>::NE;
+    *e = loc / KPE;
+    const int r = (int)(loc - *e * KPE);
+    edge_nodes<ET>(r >> 1, pa, pb);
+    *dir = r & 1;
 }
 
 // Directed edge pair i of the batch (pairs of mesh m start at pair_off[m]).
 struct BatchNodePairSrc {
     const int32_t* __restrict__ conn;
     const mesh_segment* __restrict__ segs;
-    int32_t n_mesh;
+    const int32_t* __restrict__ lut;
     uint32_t lo_bits;
     static constexpr bool kSkipNone = false;
 
     // key, or KEY_NONE; *bad is set when an id lies outside the mesh's range
     // or the segment record is inconsistent (unknown type, pair beyond it).
     __device__ __forceinline__ uint64_t make(int64_t i, bool* bad) const {
-        const int m = find_segment<offsetof(mesh_segment, pair_off)>(segs, n_mesh, i);
+        const int m = lut_segment<offsetof(mesh_segment, pair_off)>(segs, lut, i);
         const mesh_segment& sg = segs[m];
         const int32_t et = sg.etype;
         const int ne = edges_per_elem(et), npe = nodes_per_elem(et);
@@ -73,14 +94,15 @@ struct BatchNodePairSrc {
             *bad = true;
             return KEY_NONE;
         }
-        const int64_t e = loc / (2 * ne);
-        const int r = (int)(loc - e * 2 * ne);
-        int pa, pb;
-        edge_positions(et, r >> 1, &pa, &pb);
-        const int32_t* el = conn + sg.conn_off + e * npe;
+        uint32_t e;
+        int pa, pb, dir;
+        if (et == TRI3) pair_of<TRI3>((uint32_t)loc, &e, &pa, &pb, &dir);
+        else if (et == TET4) pair_of<TET4>((uint32_t)loc, &e, &pa, &pb, &dir);
+        else pair_of<HEX8>((uint32_t)loc, &e, &pa, &pb, &dir);
+        const int32_t* el = conn + sg.conn_off + (int64_t)e * npe;
         const int32_t x = el[pa], y = el[pb];
-        const int32_t u = (r & 1) ? y : x;
-        const int32_t w = (r & 1) ? x : y;
+        const int32_t u = dir ? y : x;
+        const int32_t w = dir ? x : y;
         const bool ok = (uint32_t)u < (uint32_t)sg.n_vert && (uint32_t)w < (uint32_t)sg.n_vert;
         *bad = !ok;
         if (!ok || u == w) return KEY_NONE;
@@ -96,11 +118,11 @@ struct BatchNodePairSrc {
 struct BatchElemPairSrc {
     const int32_t* __restrict__ conn;
     const mesh_segment* __restrict__ segs;
-    int32_t n_mesh;
+    const int32_t* __restrict__ lut;
     static constexpr bool kSkipNone = true;
 
     __device__ __forceinline__ uint64_t make(int64_t s, bool* bad) const {
-        const int m = find_segment<offsetof(mesh_segment, slot_off)>(segs, n_mesh, s);
+        const int m = lut_segment<offsetof(mesh_segment, slot_off)>(segs, lut, s);
         const mesh_segment& sg = segs[m];
         const int npe = nodes_per_elem(sg.etype);
         const int64_t loc = s - sg.slot_off;
@@ -115,10 +137,12 @@ struct BatchElemPairSrc {
             return KEY_NONE;
         }
         *bad = false;
-        const int64_t e = loc / npe;
-        const int j = (int)(loc - e * npe);
+        const uint32_t l32 = (uint32_t)loc;
+        const uint32_t e = npe == 3 ? l32 / 3u : npe == 4 ? l32 >> 2 : l32 >> 3;
+        const int j = (int)(l32 - e * (uint32_t)npe);
+        const int32_t* first = el + (int64_t)e * npe;
         for (int jj = 0; jj < j; ++jj)
-            if (el[e * npe + jj] == v) return KEY_NONE;  // repeated id inside the element
+            if (first[jj] == v) return KEY_NONE;  // repeated id inside the element
         return ((uint64_t)(uint32_t)(sg.vert_off + v) << 32) | (uint64_t)e;
     }
     __device__ __forceinline__ uint64_t load(int64_t s) const {
@@ -203,6 +227,9 @@ bool plan_batch(int64_t n_keys, uint32_t digit_bits, BatchPlan* p) {
     off += align_up((size_t)n_keys * sizeof(uint64_t));
     p->off_keys1 = off;
     off += p->n_pass > 1 ? align_up((size_t)n_keys * sizeof(uint64_t)) : 0;
+    p->n_lut = n_keys > 0 ? ((n_keys - 1) >> SEG_LUT_SHIFT) + 2 : 0;
+    p->off_lut = off;
+    off += align_up((size_t)p->n_lut * sizeof(int32_t));
     p->total = off;
     return true;
 }
@@ -213,7 +240,7 @@ uint32_t batch_hi_bits(int32_t total_vert) { return bits_for(total_vert); }
 template <class Src>
 static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, uint32_t shift0, uint32_t csr_lo_bits,
                                  int32_t total_vert, int32_t* row_ptr, int32_t* cols, int64_t cols_cap, char* w,
-                                 hipStream_t s) {
+                                 const mesh_segment* segs, int32_t n_mesh, hipStream_t s) {
     uint32_t* hdr = (uint32_t*)w;
     uint32_t* err = hdr + HDR_ERR;
     uint32_t* count = hdr + HDR_KEY_COUNT;
@@ -226,8 +253,15 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
 
     const int grid = (int)tmin<int64_t>(ceil_div(p.n_keys, BH_BLOCK), BH_GRID_MAX);
     const uint32_t last_bits = p.digit_bits - (uint32_t)(p.n_pass - 1) * RBITS;
-    hipError_t e = launch(node ? "batch_node_hist" : "batch_elem_hist", batch_hist_kernel<Src>, dim3(grid),
-                          dim3(BH_BLOCK), s, src, p.n_keys, shift0, p.n_pass, last_bits, hist, count, err);
+    const dim3 lut_grid((unsigned)ceil_div(p.n_lut, LUT_BLOCK));
+    hipError_t e =
+        node ? launch("batch_segment_lut", segment_lut_kernel<offsetof(mesh_segment, pair_off)>, lut_grid,
+                      dim3(LUT_BLOCK), s, segs, n_mesh, p.n_keys, (int32_t*)(w + p.off_lut), p.n_lut)
+             : launch("batch_segment_lut", segment_lut_kernel<offsetof(mesh_segment, slot_off)>, lut_grid,
+                      dim3(LUT_BLOCK), s, segs, n_mesh, p.n_keys, (int32_t*)(w + p.off_lut), p.n_lut);
+    if (e == hipSuccess)
+        e = launch(node ? "batch_node_hist" : "batch_elem_hist", batch_hist_kernel<Src>, dim3(grid), dim3(BH_BLOCK),
+                   s, src, p.n_keys, shift0, p.n_pass, last_bits, hist, count, err);
     for (int q = 0; q < p.n_pass && e == hipSuccess; ++q) {
         const uint32_t shift = shift0 + (uint32_t)q * RBITS;
         const uint32_t bits = tmin<uint32_t>(RBITS, p.digit_bits - (uint32_t)q * RBITS);
@@ -256,8 +290,9 @@ hipError_t run_batch_node(const BatchPlan& p, const int32_t* conn, const mesh_se
     hipError_t e = zero_words(ws, p.zero_bytes, s);
     if (e != hipSuccess) return e;
     if (p.n_keys == 0 || n_mesh == 0) return fill_i32(row_ptr, (int64_t)total_vert + 1, 0, s);
-    return batch_pipeline(p, "node", BatchNodePairSrc{conn, segs, n_mesh, lo_bits}, 0u, lo_bits, total_vert, row_ptr,
-                          cols, cols_cap, (char*)ws, s);
+    const int32_t* lut = (const int32_t*)((char*)ws + p.off_lut);
+    return batch_pipeline(p, "node", BatchNodePairSrc{conn, segs, lut, lo_bits}, 0u, lo_bits, total_vert, row_ptr,
+                          cols, cols_cap, (char*)ws, segs, n_mesh, s);
 }
 
 hipError_t run_batch_elem(const BatchPlan& p, const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
@@ -266,8 +301,9 @@ hipError_t run_batch_elem(const BatchPlan& p, const int32_t* conn, const mesh_se
     hipError_t e = zero_words(ws, p.zero_bytes, s);
     if (e != hipSuccess) return e;
     if (p.n_keys == 0 || n_mesh == 0) return fill_i32(row_ptr, (int64_t)total_vert + 1, 0, s);
-    return batch_pipeline(p, "elem", BatchElemPairSrc{conn, segs, n_mesh}, 32u, 32u, total_vert, row_ptr, cols,
-                          cols_cap, (char*)ws, s);
+    const int32_t* lut = (const int32_t*)((char*)ws + p.off_lut);
+    return batch_pipeline(p, "elem", BatchElemPairSrc{conn, segs, lut}, 32u, 32u, total_vert, row_ptr, cols,
+                          cols_cap, (char*)ws, segs, n_mesh, s);
 }
 
 }  // namespace mnb

@@ -38,11 +38,12 @@ constexpr int TK_CSR = 15;
 // The element holding slot s contains vertex v = conn[s] for the first time
 // (set semantics for degenerate elements: a repeated id counts once).
 template <int NPE>
-__device__ __forceinline__ bool first_occurrence(const int32_t* __restrict__ conn, int64_t e, int j, int32_t v) {
+__device__ __forceinline__ bool first_occurrence(const int32_t* __restrict__ conn, uint32_t e, int j, int32_t v) {
     bool first = true;
+    const int32_t* el = conn + (size_t)e * NPE;
 #pragma unroll
     for (int jj = 0; jj < NPE - 1; ++jj)
-        if (jj < j) first &= conn[e * NPE + jj] != v;
+        if (jj < j) first &= el[jj] != v;
     return first;
 }
 
@@ -57,8 +58,9 @@ struct ElemPairSrc {
         constexpr int NPE = Elem<ET>::NPE;
         const int32_t v = conn[s];
         if ((uint32_t)v >= (uint32_t)n_vert) return KEY_NONE;
-        const int64_t e = s / NPE;
-        const int j = (int)(s - e * NPE);
+        const uint32_t ss = (uint32_t)s;  // slot indices stay below 2^31
+        const uint32_t e = ss / NPE;
+        const int j = (int)(ss - e * NPE);
         if (!first_occurrence<NPE>(conn, e, j, v)) return KEY_NONE;
         return ((uint64_t)(uint32_t)v << 32) | (uint64_t)e;
     }
@@ -91,8 +93,8 @@ __global__ __launch_bounds__(HIST_BLOCK) void elem_hist_kernel(const int32_t* __
             v[u] = -1;
             if (s < n_slots) {
                 v[u] = conn[s];
-                const int64_t e = s / NPE;
-                take[u] = first_occurrence<NPE>(conn, e, (int)(s - e * NPE), v[u]);
+                const uint32_t e = (uint32_t)s / NPE;
+                take[u] = first_occurrence<NPE>(conn, e, (int)((uint32_t)s - e * NPE), v[u]);
             }
         }
 #pragma unroll

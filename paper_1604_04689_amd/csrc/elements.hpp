@@ -40,6 +40,22 @@ struct Elem<HEX8> {
     static constexpr int B[12] = {1, 2, 3, 0, 5, 6, 7, 4, 4, 5, 6, 7};
 };
 
+// The edge tables packed four bits per entry (entry k in bits 4k .. 4k+3),
+// so a runtime edge index selects its two nodes with one shift each.
+template <int N>
+constexpr uint64_t pack_nibbles(const int (&t)[N]) {
+    uint64_t r = 0;
+    for (int i = 0; i < N; ++i) r |= (uint64_t)t[i] << (4 * i);
+    return r;
+}
+
+template <int ET>
+__device__ __forceinline__ void edge_nodes(int k, int* a, int* b) {
+    constexpr uint64_t TA = pack_nibbles(Elem<ET>::A), TB = pack_nibbles(Elem<ET>::B);
+    *a = (int)((TA >> (4 * k)) & 15u);
+    *b = (int)((TB >> (4 * k)) & 15u);
+}
+
 __host__ __device__ inline int nodes_per_elem(int32_t et) {
     return et == TRI3 ? 3 : et == TET4 ? 4 : et == HEX8 ? 8 : 0;
 }

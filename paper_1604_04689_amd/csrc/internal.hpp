@@ -62,6 +62,8 @@ struct BatchPlan {
     int n_pass = 0;
     int64_t n_tiles = 0, n_utiles = 0;
     size_t off_hist = 0, off_ulb = 0, off_lb0 = 0, off_lb1 = 0, off_keys0 = 0, off_keys1 = 0;
+    int64_t n_lut = 0;      // segment lookup entries (one per 2^SEG_LUT_SHIFT keys, plus one)
+    size_t off_lut = 0;
     size_t zero_bytes = 0;
     size_t total = 0;
 };

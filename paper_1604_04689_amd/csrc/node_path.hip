@@ -40,18 +40,13 @@ template <int ET>
 __device__ __forceinline__ uint64_t node_pair_key(const int32_t* __restrict__ conn, int64_t i, int32_t n_vert,
                                                   uint32_t b) {
     using E = Elem<ET>;
-    constexpr int KPE = 2 * E::NE;
-    const int64_t e = i / KPE;
-    const int r = (int)(i - e * KPE);
-    const int k = r >> 1;
-    int pa = 0, pb = 0;
-#pragma unroll
-    for (int q = 0; q < E::NE; ++q)
-        if (q == k) {
-            pa = E::A[q];
-            pb = E::B[q];
-        }
-    const int32_t* el = conn + e * E::NPE;
+    constexpr uint32_t KPE = 2 * E::NE;
+    const uint32_t ii = (uint32_t)i;  // pair indices stay below 2^31
+    const uint32_t e = ii / KPE;
+    const int r = (int)(ii - e * KPE);
+    int pa, pb;
+    edge_nodes<ET>(r >> 1, &pa, &pb);
+    const int32_t* el = conn + (size_t)e * E::NPE;
     const int32_t x = el[pa], y = el[pb];
     const int32_t u = (r & 1) ? y : x;
     const int32_t w = (r & 1) ? x : y;

@@ -18,7 +18,7 @@ namespace mnb {
 
 constexpr int ROW_BLOCK = 256;
 constexpr int ROW_TILE = 2048;   // keys whose rows a block owns
-constexpr int ROW_HALO = 512;    // keys read past the tile to finish its last row
+constexpr int ROW_HALO = 256;    // keys read past the tile to finish its last row
 constexpr int ROW_SHORT = 256;   // longest row handled in LDS; longer rows are listed
 constexpr int LONG_BLOCK = 256;
 constexpr int LONG_LDS = 16384;  // longest row sorted in LDS by one block
@@ -29,14 +29,17 @@ constexpr uint32_t SLOT_EMPTY = 0xffffffffu;
 static_assert(ROW_HALO >= ROW_SHORT, "a short row owned by a tile ends inside its halo");
 
 // A block owns the rows whose first key lies in its tile (keys read past the
-// tile finish its last row).  Per position: its row's first position by a
-// max-scan of row starts, the row length from the row's last position.  Each
-// key of a short row inserts its low part into an open-addressing table in
-// LDS that spans the row's own positions (size L, linear probing); the
-// insertion that fills an empty slot is the value's one kept copy.  A kept
-// value's place in the row is the number of distinct values below it, counted
-// over the row's table.  Rows longer than ROW_SHORT (or running past the halo)
-// are listed, by first key index, for long_rows.
+// tile finish its last row).  Positions are striped over the block: chunk
+// c = q * WAVES + wave holds positions 64c .. 64c + 63, one per lane, so row
+// starts, row ends and prefix counts come from wave ballots plus one short
+// scan over the chunks.  Each key of a short row inserts its low part into an
+// open-addressing table in LDS that spans the row's own positions (size L,
+// linear probing); the insertion that fills an empty slot is the value's one
+// kept copy.  Kept copies are compacted in position order into a dense list,
+// where each row's distinct values are contiguous; a value's place in its row
+// is the number of the row's distinct values below it.  Rows longer than
+// ROW_SHORT (or running past the halo) are listed, by first key index, for
+// long_rows.
 static __global__ __launch_bounds__(ROW_BLOCK) void row_unique_kernel(const uint64_t* __restrict__ keys, int64_t n,
                                                                      uint32_t b, int32_t n_vert,
                                                                      int32_t* __restrict__ deg,
@@ -48,95 +51,95 @@ static __global__ __launch_bounds__(ROW_BLOCK) void row_unique_kernel(const uint
     constexpr int SPAN = ROW_TILE + ROW_HALO;
     constexpr int PER = SPAN / ROW_BLOCK;
     constexpr int WAVES = ROW_BLOCK / WAVE;
-    static_assert(SPAN % ROW_BLOCK == 0, "whole positions per thread");
-    __shared__ uint64_t s_k[SPAN + 1];   // s_k[0] = key before the tile, s_k[1 + p] = key base + p
-    __shared__ int16_t s_rs[SPAN];       // first position of p's row (-1: row starts before the tile)
-    __shared__ int16_t s_len[SPAN];      // at a row's first position: its length (0 if it leaves the span)
-    __shared__ uint32_t s_tab[SPAN];     // per-row open-addressing tables over the row's positions
-    __shared__ int32_t s_tmp[WAVES];
+    constexpr int CH = SPAN / WAVE;  // chunks of 64 positions
+    static_assert(SPAN % ROW_BLOCK == 0 && ROW_TILE % WAVE == 0, "whole chunks per thread and per tile");
+    static_assert(CH <= WAVE, "one wave scans the chunk summaries");
+    __shared__ int16_t s_rs[SPAN];        // first position of p's row (-1: row starts before the tile)
+    __shared__ int16_t s_len[SPAN];       // at a row's first position: its length (0 if it leaves the span)
+    // per-row open-addressing tables over the row's positions; once every
+    // insertion is done, the same words hold the kept values, dense, in
+    // position order
+    __shared__ uint32_t s_tab[SPAN];
+    uint32_t* const s_dval = s_tab;
+    __shared__ int16_t s_e[SPAN + 1];     // kept copies before position p
+    __shared__ uint64_t s_lastkey[CH];    // key at the last position of each chunk
+    __shared__ uint64_t s_startmask[CH];  // row-start flags of each chunk
+    __shared__ int32_t s_csum[CH + 1];    // per chunk: last row start, then kept count; scanned
     __shared__ int32_t s_bounds[2];
+    __shared__ uint64_t s_before;
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1), wid = tid / WAVE;
     const int64_t base = (int64_t)blockIdx.x * ROW_TILE;
     const int span = (int)tmin<int64_t>(SPAN, n - base);
     const uint64_t lo_mask = (1ull << b) - 1;
-    {
-        uint64_t k[PER];  // striped, coalesced; all loads in flight before the stores
+    const uint64_t lt_mask = (1ull << lane) - 1;
+    uint64_t k[PER];  // striped, coalesced; all loads in flight before the stores
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int p = q * ROW_BLOCK + tid;
-            k[q] = p < span ? keys[base + p] : KEY_NONE;
-        }
-        const uint64_t before = (tid == 0 && base > 0) ? keys[base - 1] : KEY_NONE;
+    for (int q = 0; q < PER; ++q) {
+        const int p = q * ROW_BLOCK + tid;
+        k[q] = p < span ? keys[base + p] : KEY_NONE;
+    }
+    if (tid == 0) {
+        s_before = base > 0 ? keys[base - 1] : KEY_NONE;
+        s_bounds[0] = ROW_TILE;
+        s_bounds[1] = SPAN;
+    }
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int p = q * ROW_BLOCK + tid;
-            s_k[1 + p] = k[q];
-            s_tab[p] = SLOT_EMPTY;
-            s_len[p] = 0;
-        }
-        if (tid == 0) {
-            s_k[0] = before;
-            s_bounds[0] = ROW_TILE;
-            s_bounds[1] = SPAN;
+    for (int q = 0; q < PER; ++q) {
+        const int p = q * ROW_BLOCK + tid;
+        if (lane == WAVE - 1) s_lastkey[q * WAVES + wid] = k[q];
+        s_tab[p] = SLOT_EMPTY;
+        s_len[p] = 0;
+    }
+    __syncthreads();
+    // ---- row starts: ballots per chunk, the tile's first owned start and the halo's first start
+    uint64_t smask[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int p = q * ROW_BLOCK + tid, c = q * WAVES + wid;
+        uint64_t prev = __shfl_up(k[q], 1, WAVE);
+        if (lane == 0) prev = c == 0 ? s_before : s_lastkey[c - 1];
+        const uint64_t cur = k[q];
+        const bool st = p >= span || cur == KEY_NONE || prev == KEY_NONE || (cur >> b) != (prev >> b);
+        smask[q] = __ballot(st);
+        if (lane == 0) {
+            s_startmask[c] = smask[q];
+            s_csum[c] = smask[q] ? c * WAVE + 63 - __clzll((long long)smask[q]) : -1;
+            if (smask[q]) atomicMin(&s_bounds[c * WAVE < ROW_TILE ? 0 : 1], c * WAVE + __ffsll((unsigned long long)smask[q]) - 1);
         }
     }
     __syncthreads();
-    // ---- row starts and the first position of every row (blocked: PER
-    // consecutive positions per thread, then a max-scan over the threads)
-    bool st[PER];
-    int last = -1;
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int p = tid * PER + q;
-        const uint64_t cur = s_k[1 + p], prev = s_k[p];
-        const bool s_ = p >= span || cur == KEY_NONE || base + p == 0 || prev == KEY_NONE || (cur >> b) != (prev >> b);
-        st[q] = s_;
-        if (s_) last = p;
-    }
-    {
-        int incl = last;
+    if (wid == 0) {  // exclusive max-scan of the chunks' last starts
+        int v = lane < CH ? s_csum[lane] : -1;
 #pragma unroll
         for (int d = 1; d < WAVE; d <<= 1) {
-            const int y = __shfl_up(incl, d, WAVE);
-            if (lane >= d) incl = y > incl ? y : incl;
+            const int y = __shfl_up(v, d, WAVE);
+            if (lane >= d) v = y > v ? y : v;
         }
-        if (lane == WAVE - 1) s_tmp[wid] = incl;
-        __syncthreads();
-        int before_w = -1;
-#pragma unroll
-        for (int w = 0; w < WAVES; ++w)
-            if (w < wid) before_w = s_tmp[w] > before_w ? s_tmp[w] : before_w;
-        int prev = __shfl_up(incl, 1, WAVE);
-        if (lane == 0) prev = -1;
-        int cur_rs = prev > before_w ? prev : before_w;
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int p = tid * PER + q;
-            if (st[q]) cur_rs = p;
-            s_rs[p] = (int16_t)cur_rs;
-            if (st[q] && p < ROW_TILE) atomicMin(&s_bounds[0], p);
-            if (st[q] && p >= ROW_TILE) atomicMin(&s_bounds[1], p);
-        }
+        int ex = __shfl_up(v, 1, WAVE);
+        if (lane == 0) ex = -1;
+        if (lane < CH) s_csum[lane] = ex;
     }
     __syncthreads();
     const int p0 = s_bounds[0], pe = s_bounds[1];
     if (p0 >= ROW_TILE) return;  // the tile lies inside a row owned by an earlier tile
-    // ---- row lengths, written at each row's first position by its last position
+    // ---- every position's row start; row lengths written at each row's
+    // first position by its last position
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int p = tid * PER + q;
-        if (p < p0 || p >= pe || s_k[1 + p] == KEY_NONE) continue;
+        const int p = q * ROW_BLOCK + tid, c = q * WAVES + wid;
+        const uint64_t upto = smask[q] & (lt_mask | (1ull << lane));
+        const int rs = upto ? c * WAVE + 63 - __clzll((long long)upto) : s_csum[c];
+        s_rs[p] = (int16_t)rs;
+        if (p < p0 || p >= pe || k[q] == KEY_NONE) continue;
         bool next_start;
-        if (q + 1 < PER) next_start = st[q + 1];
-        else if (p + 1 >= SPAN) next_start = false;  // the row may go on past the span
-        else next_start = s_rs[p + 1] == p + 1;
-        if (next_start) s_len[s_rs[p]] = (int16_t)(p + 1 - s_rs[p]);
+        if (lane < WAVE - 1) next_start = (smask[q] >> (lane + 1)) & 1ull;
+        else next_start = c + 1 < CH ? (s_startmask[c + 1] & 1ull) : false;  // past the span: unknown
+        if (next_start) s_len[rs] = (int16_t)(p + 1 - rs);
     }
     __syncthreads();
-    // ---- insert every key of a short row into its row's table (striped:
-    // consecutive positions on consecutive threads); a first probe for all,
-    // then further probes for the few that collided
+    // ---- insert every key of a short row into its row's table; a first
+    // probe for all, then further probes for the few that collided
     bool bad = false;
     uint32_t kept = 0, pending = 0;
     uint32_t hslot[PER];
@@ -144,9 +147,7 @@ static __global__ __launch_bounds__(ROW_BLOCK) void row_unique_kernel(const uint
     for (int q = 0; q < PER; ++q) {
         const int p = q * ROW_BLOCK + tid;
         hslot[q] = 0;
-        if (p < p0 || p >= pe) continue;
-        const uint64_t cur = s_k[1 + p];
-        if (cur == KEY_NONE) continue;
+        if (p < p0 || p >= pe || k[q] == KEY_NONE) continue;
         const int rs = s_rs[p];
         const int len = s_len[rs];
         if (len == 0 || len > ROW_SHORT) {  // long, or running past the span
@@ -157,7 +158,7 @@ static __global__ __launch_bounds__(ROW_BLOCK) void row_unique_kernel(const uint
             }
             continue;
         }
-        const uint32_t lo = (uint32_t)(cur & lo_mask);
+        const uint32_t lo = (uint32_t)(k[q] & lo_mask);
         const uint32_t h = (uint32_t)(((uint64_t)(lo * 2654435761u) * (uint32_t)len) >> 32);
         const uint32_t old = atomicCAS(&s_tab[rs + h], SLOT_EMPTY, lo);
         if (old == SLOT_EMPTY) kept |= 1u << q;
@@ -172,7 +173,7 @@ static __global__ __launch_bounds__(ROW_BLOCK) void row_unique_kernel(const uint
         const int p = q * ROW_BLOCK + tid;
         const int rs = s_rs[p];
         const uint32_t len = (uint32_t)s_len[rs];
-        const uint32_t lo = (uint32_t)(s_k[1 + p] & lo_mask);
+        const uint32_t lo = (uint32_t)(k[q] & lo_mask);
         uint32_t h = hslot[q];
         for (uint32_t probe = 1; probe < len; ++probe) {
             h = h + 1 == len ? 0 : h + 1;
@@ -184,32 +185,54 @@ static __global__ __launch_bounds__(ROW_BLOCK) void row_unique_kernel(const uint
             if (old == lo) break;
         }
     }
+    // ---- dense list of the kept values in position order
+    uint64_t kmask[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        kmask[q] = __ballot((kept >> q) & 1u);
+        if (lane == 0) s_csum[q * WAVES + wid] = __popcll(kmask[q]);
+    }
     __syncthreads();
-    // ---- place every kept value: the number of distinct values below it
+    if (wid == 0) {  // exclusive sum-scan of the chunks' kept counts
+        const int x = lane < CH ? s_csum[lane] : 0;
+        int v = x;
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const int y = __shfl_up(v, d, WAVE);
+            if (lane >= d) v += y;
+        }
+        if (lane < CH) s_csum[lane] = v - x;
+        if (lane == CH - 1) s_csum[CH] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int p = q * ROW_BLOCK + tid, c = q * WAVES + wid;
+        const int e = s_csum[c] + __popcll(kmask[q] & lt_mask);
+        s_e[p] = (int16_t)e;
+        if ((kept >> q) & 1u) s_dval[e] = (uint32_t)(k[q] & lo_mask);
+    }
+    if (tid == 0) s_e[SPAN] = (int16_t)s_csum[CH];
+    __syncthreads();
+    // ---- place every kept value; the row's first position records the row
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int p = q * ROW_BLOCK + tid;
-        if (p < p0 || p >= pe) continue;
-        const uint64_t cur = s_k[1 + p];
-        if (cur == KEY_NONE) continue;
+        if (p < p0 || p >= pe || k[q] == KEY_NONE) continue;
         const int rs = s_rs[p];
         const int len = s_len[rs];
         if (len == 0 || len > ROW_SHORT) continue;
+        const int ds = s_e[rs], u = s_e[rs + len] - ds;
         if ((kept >> q) & 1u) {
-            const uint32_t lo = (uint32_t)(cur & lo_mask);
+            const uint32_t lo = (uint32_t)(k[q] & lo_mask);
             int below = 0;
-            for (int j = 0; j < len; ++j) {
-                const uint32_t t = s_tab[rs + j];
-                below += (t < lo) ? 1 : 0;  // SLOT_EMPTY is above every value
-            }
+            for (int j = 0; j < u; ++j) below += s_dval[ds + j] < lo ? 1 : 0;
             temp[base + rs + below] = (int32_t)lo;
         }
         if (p == rs) {
-            int cnt = 0;
-            for (int j = 0; j < len; ++j) cnt += s_tab[rs + j] != SLOT_EMPTY ? 1 : 0;
-            const int64_t hi = (int64_t)(cur >> b);
+            const int64_t hi = (int64_t)(k[q] >> b);
             if (hi < n_vert) {
-                deg[hi] = cnt;
+                deg[hi] = u;
                 src[hi] = base + rs;
             } else {
                 bad = true;
