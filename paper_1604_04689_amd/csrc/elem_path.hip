@@ -26,7 +26,7 @@
 
 namespace mnb {
 
-constexpr int HIST_BLOCK = 256;
+constexpr int HIST_BLOCK = 512;
 constexpr int HIST_GRID_MAX = 1024;
 constexpr int HIST_UNROLL = 4;
 constexpr int MAX_EPASS = 4;  // 31 vertex bits
@@ -67,9 +67,11 @@ struct ElemPairSrc {
 };
 
 // Histograms of the 8-bit digits of v over the pairs that take part, and
-// their number.  Raises ERR_INDEX_RANGE.
+// their number.  A thread takes whole elements, HIST_UNROLL of them in
+// flight; a repeated id inside an element counts once.  Raises
+// ERR_INDEX_RANGE.
 template <int ET>
-__global__ __launch_bounds__(HIST_BLOCK) void elem_hist_kernel(const int32_t* __restrict__ conn, int64_t n_slots,
+__global__ __launch_bounds__(HIST_BLOCK) void elem_hist_kernel(const int32_t* __restrict__ conn, int64_t n_elem,
                                                               int32_t n_vert, int n_pass, uint32_t last_bits,
                                                               uint32_t* __restrict__ hist, uint32_t* pair_count,
                                                               uint32_t* err) {
@@ -83,32 +85,29 @@ __global__ __launch_bounds__(HIST_BLOCK) void elem_hist_kernel(const int32_t* __
     bool bad = false;
     uint32_t pairs = 0;
     const int64_t stride = (int64_t)gridDim.x * HIST_BLOCK;
-    for (int64_t s0 = (int64_t)blockIdx.x * HIST_BLOCK + tid; s0 < n_slots; s0 += stride * HIST_UNROLL) {
-        int32_t v[HIST_UNROLL];
-        bool take[HIST_UNROLL];
+    for (int64_t e0 = (int64_t)blockIdx.x * HIST_BLOCK + tid; e0 < n_elem; e0 += stride * HIST_UNROLL) {
+        int32_t id[HIST_UNROLL][NPE];
 #pragma unroll
         for (int u = 0; u < HIST_UNROLL; ++u) {  // all loads in flight first
-            const int64_t s = s0 + u * stride;
-            take[u] = false;
-            v[u] = -1;
-            if (s < n_slots) {
-                v[u] = conn[s];
-                const uint32_t e = (uint32_t)s / NPE;
-                take[u] = first_occurrence<NPE>(conn, e, (int)((uint32_t)s - e * NPE), v[u]);
-            }
+            const int64_t e = e0 + u * stride;
+            if (e < n_elem) load_elem_ids<ET>(conn, e, id[u]);
         }
 #pragma unroll
         for (int u = 0; u < HIST_UNROLL; ++u) {
-            if (s0 + u * stride >= n_slots) continue;
-            if ((uint32_t)v[u] >= (uint32_t)n_vert) {
-                bad = true;
-                continue;
-            }
-            if (!take[u]) continue;
-            ++pairs;
-            for (int p = 0; p < n_pass; ++p) {
-                const uint32_t mask = p == n_pass - 1 ? (1u << last_bits) - 1 : RADIX - 1;
-                atomicAdd(&s_hist[p * RADIX + (((uint32_t)v[u] >> (p * RBITS)) & mask)], 1u);
+            if (e0 + u * stride >= n_elem) continue;
+#pragma unroll
+            for (int j = 0; j < NPE; ++j) {
+                const int32_t v = id[u][j];
+                bool take = (uint32_t)v < (uint32_t)n_vert;
+                bad |= !take;
+#pragma unroll
+                for (int jj = 0; jj < j; ++jj) take &= id[u][jj] != v;
+                if (!take) continue;
+                ++pairs;
+                for (int p = 0; p < n_pass; ++p) {
+                    const uint32_t mask = p == n_pass - 1 ? (1u << last_bits) - 1 : RADIX - 1;
+                    atomicAdd(&s_hist[p * RADIX + (((uint32_t)v >> (p * RBITS)) & mask)], 1u);
+                }
             }
         }
     }
@@ -171,9 +170,9 @@ static hipError_t elem_pipeline(const ElemPlan& p, const int32_t* conn, int32_t*
     uint64_t* kb[2] = {(uint64_t*)(w + p.off_keys0), (uint64_t*)(w + p.off_keys1)};
     const int shape = radix_shape();
 
-    const int grid = (int)tmin<int64_t>(ceil_div(p.n_slots, HIST_BLOCK), HIST_GRID_MAX);
+    const int grid = (int)tmin<int64_t>(ceil_div(p.n_elem, HIST_BLOCK), HIST_GRID_MAX);
     const uint32_t last_bits = p.id_bits - (uint32_t)(p.n_pass - 1) * RBITS;
-    hipError_t e = launch("elem_hist", elem_hist_kernel<ET>, dim3(grid), dim3(HIST_BLOCK), s, conn, p.n_slots,
+    hipError_t e = launch("elem_hist", elem_hist_kernel<ET>, dim3(grid), dim3(HIST_BLOCK), s, conn, p.n_elem,
                           p.n_vert, p.n_pass, last_bits, hist, count, err);
     for (int q = 0; q < p.n_pass && e == hipSuccess; ++q) {
         const uint32_t shift = 32 + (uint32_t)q * RBITS;

@@ -56,6 +56,16 @@ __device__ __forceinline__ void edge_nodes(int k, int* a, int* b) {
     *b = (int)((TB >> (4 * k)) & 15u);
 }
 
+// The ids of element e, read by one thread (consecutive threads read
+// consecutive elements, so a wave's loads cover one contiguous span).
+template <int ET>
+__device__ __forceinline__ void load_elem_ids(const int32_t* __restrict__ conn, int64_t e,
+                                              int32_t (&id)[Elem<ET>::NPE]) {
+    const int32_t* el = conn + e * Elem<ET>::NPE;
+#pragma unroll
+    for (int j = 0; j < Elem<ET>::NPE; ++j) id[j] = el[j];
+}
+
 __host__ __device__ inline int nodes_per_elem(int32_t et) {
     return et == TRI3 ? 3 : et == TET4 ? 4 : et == HEX8 ? 8 : 0;
 }

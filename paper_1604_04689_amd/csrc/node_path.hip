@@ -25,8 +25,9 @@ namespace mnb {
 
 constexpr int MAX_PASS = 8;  // 2b <= 62 key bits
 
-constexpr int EMIT_BLOCK = 256;   // elements per histogram tile (one per thread)
-constexpr int EMIT_GRID_MAX = 1024;
+constexpr int NH_BLOCK = 512;
+constexpr int NH_UNROLL = 4;      // elements per thread in flight
+constexpr int NH_GRID_MAX = 1024;
 
 // ---------------------------------------------------------------------------
 // Directed edge pairs of the elements, generated on the fly from the
@@ -36,17 +37,12 @@ constexpr int EMIT_GRID_MAX = 1024;
 // or a pair touching an id outside [0, n_vert) yields KEY_NONE, which sorts
 // after every real key and is dropped by unique_csr.
 // ---------------------------------------------------------------------------
+// Key of directed pair r (edge r / 2, direction r % 2) of the element whose
+// ids start at el.
 template <int ET>
-__device__ __forceinline__ uint64_t node_pair_key(const int32_t* __restrict__ conn, int64_t i, int32_t n_vert,
-                                                  uint32_t b) {
-    using E = Elem<ET>;
-    constexpr uint32_t KPE = 2 * E::NE;
-    const uint32_t ii = (uint32_t)i;  // pair indices stay below 2^31
-    const uint32_t e = ii / KPE;
-    const int r = (int)(ii - e * KPE);
+__device__ __forceinline__ uint64_t elem_pair_key(const int32_t* el, int r, int32_t n_vert, uint32_t b) {
     int pa, pb;
     edge_nodes<ET>(r >> 1, &pa, &pb);
-    const int32_t* el = conn + (size_t)e * E::NPE;
     const int32_t x = el[pa], y = el[pb];
     const int32_t u = (r & 1) ? y : x;
     const int32_t w = (r & 1) ? x : y;
@@ -55,66 +51,101 @@ __device__ __forceinline__ uint64_t node_pair_key(const int32_t* __restrict__ co
 }
 
 template <int ET>
+__device__ __forceinline__ uint64_t node_pair_key(const int32_t* __restrict__ conn, int64_t i, int32_t n_vert,
+                                                  uint32_t b) {
+    constexpr uint32_t KPE = 2 * Elem<ET>::NE;
+    const uint32_t ii = (uint32_t)i;  // pair indices stay below 2^31
+    const uint32_t e = ii / KPE;
+    return elem_pair_key<ET>(conn + (size_t)e * Elem<ET>::NPE, (int)(ii - e * KPE), n_vert, b);
+}
+
+// Pair keys of the single-mesh node relation.  A radix tile first copies the
+// connectivity of the elements its pairs come from into LDS with coalesced
+// loads (stage), then builds every key from there (load_staged).
+template <int ET>
 struct NodePairSrc {
     const int32_t* __restrict__ conn;
     int32_t n_vert;
     uint32_t b;
     static constexpr bool kSkipNone = false;
+    static constexpr bool kStaged = true;
+    static constexpr uint32_t KPE = 2 * Elem<ET>::NE;
+    static constexpr int NPE = Elem<ET>::NPE;
+
     __device__ __forceinline__ uint64_t load(int64_t i) const { return node_pair_key<ET>(conn, i, n_vert, b); }
+
+    // ids of the tile's elements to s[0 ..): at most (TILE / KPE + 2) * NPE words
+    template <int BLOCK, int TILE>
+    __device__ __forceinline__ void stage(int64_t tile_base, int64_t n, int32_t* s, int tid) const {
+        constexpr int MAXC = (TILE / (int)KPE + 2) * NPE;
+        constexpr int PER = (MAXC + BLOCK - 1) / BLOCK;
+        static_assert(MAXC <= 2 * TILE, "staged ids fit the key staging area");
+        const uint32_t e0 = (uint32_t)tile_base / KPE;
+        const uint32_t e1 = ((uint32_t)tmin<int64_t>(tile_base + TILE, n) - 1u) / KPE;
+        const int cnt = (int)(e1 - e0 + 1u) * NPE;
+        const int32_t* src = conn + (size_t)e0 * NPE;
+        int32_t v[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = q * BLOCK + tid;
+            v[q] = i < cnt ? src[i] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = q * BLOCK + tid;
+            if (i < cnt) s[i] = v[q];
+        }
+    }
+    __device__ __forceinline__ uint64_t load_staged(int64_t i, int64_t tile_base, const int32_t* s) const {
+        const uint32_t ii = (uint32_t)i;
+        const uint32_t e = ii / KPE;
+        const uint32_t e0 = (uint32_t)tile_base / KPE;
+        return elem_pair_key<ET>(s + (e - e0) * NPE, (int)(ii - e * KPE), n_vert, b);
+    }
 };
 
 // ---------------------------------------------------------------------------
 // node_hist: the digit histograms of every radix pass over all pair keys,
 // read from the connectivity (the keys themselves are generated again by the
-// first radix pass).  Each block accumulates in LDS over the element tiles it
-// visits and flushes once with global atomics.  Raises ERR_INDEX_RANGE.
+// first radix pass).  A thread takes whole elements, HIST_UNROLL of them in
+// flight at once; each block accumulates in LDS and flushes once with global
+// atomics.  Raises ERR_INDEX_RANGE.
 // ---------------------------------------------------------------------------
 template <int ET>
-__global__ __launch_bounds__(EMIT_BLOCK) void node_hist_kernel(const int32_t* __restrict__ conn, int64_t n_elem,
-                                                              int32_t n_vert, uint32_t b, uint32_t shift0,
-                                                              int n_pass, uint32_t last_bits,
-                                                              uint32_t* __restrict__ hist, uint32_t* err) {
+__global__ __launch_bounds__(NH_BLOCK) void node_hist_kernel(const int32_t* __restrict__ conn, int64_t n_elem,
+                                                            int32_t n_vert, uint32_t b, uint32_t shift0, int n_pass,
+                                                            uint32_t last_bits, uint32_t* __restrict__ hist,
+                                                            uint32_t* err) {
     using E = Elem<ET>;
     constexpr int NPE = E::NPE;
-    __shared__ int32_t s_conn[EMIT_BLOCK * NPE];
     __shared__ uint32_t s_hist[MAX_PASS * RADIX];
-
     const int tid = threadIdx.x;
-    for (int i = tid; i < n_pass * RADIX; i += EMIT_BLOCK) s_hist[i] = 0;
+    for (int i = tid; i < n_pass * RADIX; i += NH_BLOCK) s_hist[i] = 0;
+    __syncthreads();
     bool bad_seen = false;
-
-    for (int64_t tile = blockIdx.x; tile * EMIT_BLOCK < n_elem; tile += gridDim.x) {
-        const int64_t e0 = tile * EMIT_BLOCK;
-        const int ne = (int)tmin<int64_t>(EMIT_BLOCK, n_elem - e0);
-        __syncthreads();  // previous tile consumed (and s_hist cleared)
-        const int32_t* src = conn + e0 * NPE;
-        int32_t x[NPE];  // all loads in flight before the LDS stores
+    const int64_t stride = (int64_t)gridDim.x * NH_BLOCK;
+    for (int64_t e0 = (int64_t)blockIdx.x * NH_BLOCK + tid; e0 < n_elem; e0 += stride * NH_UNROLL) {
+        int32_t id[NH_UNROLL][NPE];
 #pragma unroll
-        for (int q = 0; q < NPE; ++q) {
-            const int i = q * EMIT_BLOCK + tid;
-            x[q] = i < ne * NPE ? src[i] : 0;
+        for (int u = 0; u < NH_UNROLL; ++u) {  // all loads in flight first
+            const int64_t e = e0 + u * stride;
+            if (e < n_elem) load_elem_ids<ET>(conn, e, id[u]);
         }
 #pragma unroll
-        for (int q = 0; q < NPE; ++q) {
-            const int i = q * EMIT_BLOCK + tid;
-            if (i < ne * NPE) s_conn[i] = x[q];
-        }
-        __syncthreads();
-        if (tid < ne) {
-            int32_t id[NPE];
+        for (int u = 0; u < NH_UNROLL; ++u) {
+            if (e0 + u * stride >= n_elem) continue;
             bool ok[NPE];
 #pragma unroll
             for (int j = 0; j < NPE; ++j) {
-                id[j] = s_conn[tid * NPE + j];
-                ok[j] = (uint32_t)id[j] < (uint32_t)n_vert;
+                ok[j] = (uint32_t)id[u][j] < (uint32_t)n_vert;
                 bad_seen |= !ok[j];
             }
 #pragma unroll
             for (int k = 0; k < E::NE; ++k) {
-                const int32_t u = id[E::A[k]], w = id[E::B[k]];
-                const bool edge = ok[E::A[k]] && ok[E::B[k]] && u != w;
-                const uint64_t k0 = edge ? ((uint64_t)u << b) | (uint64_t)w : KEY_NONE;
-                const uint64_t k1 = edge ? ((uint64_t)w << b) | (uint64_t)u : KEY_NONE;
+                const int32_t x = id[u][E::A[k]], y = id[u][E::B[k]];
+                const bool edge = ok[E::A[k]] && ok[E::B[k]] && x != y;
+                const uint64_t k0 = edge ? ((uint64_t)x << b) | (uint64_t)y : KEY_NONE;
+                const uint64_t k1 = edge ? ((uint64_t)y << b) | (uint64_t)x : KEY_NONE;
                 for (int p = 0; p < n_pass; ++p) {
                     const uint32_t mask = (p == n_pass - 1) ? ((1u << last_bits) - 1) : (RADIX - 1);
                     atomicAdd(&s_hist[p * RADIX + ((uint32_t)(k0 >> (shift0 + p * RBITS)) & mask)], 1u);
@@ -125,7 +156,7 @@ __global__ __launch_bounds__(EMIT_BLOCK) void node_hist_kernel(const int32_t* __
     }
     if (bad_seen) set_error(err, ERR_INDEX_RANGE);
     __syncthreads();
-    for (int i = tid; i < n_pass * RADIX; i += EMIT_BLOCK) {
+    for (int i = tid; i < n_pass * RADIX; i += NH_BLOCK) {
         const uint32_t v = s_hist[i];
         if (v) atomicAdd(&hist[i], v);
     }
@@ -206,12 +237,12 @@ static hipError_t node_pipeline(const NodePlan& p, const int32_t* conn, int32_t*
     const uint32_t shift0 = rows ? p.id_bits : 0;
     const uint32_t sort_bits = rows ? p.hi_bits : 2 * p.id_bits;
     const int n_pass = rows ? p.n_pass_rows : p.n_pass;
-    const int grid = (int)tmin<int64_t>(ceil_div(p.n_elem, EMIT_BLOCK), EMIT_GRID_MAX);
+    const int grid = (int)tmin<int64_t>(ceil_div(p.n_elem, NH_BLOCK), NH_GRID_MAX);
     const uint32_t last_bits = sort_bits - (uint32_t)(n_pass - 1) * RBITS;
     hipError_t e = hipSuccess;
     if (rows) e = fill_i32((int32_t*)(w + p.off_deg), p.n_vert, 0, s);
     if (e == hipSuccess)
-        e = launch("node_hist", node_hist_kernel<ET>, dim3(grid), dim3(EMIT_BLOCK), s, conn, p.n_elem, p.n_vert,
+        e = launch("node_hist", node_hist_kernel<ET>, dim3(grid), dim3(NH_BLOCK), s, conn, p.n_elem, p.n_vert,
                    p.id_bits, shift0, n_pass, last_bits, hist, err);
     for (int pass = 0; pass < n_pass && e == hipSuccess; ++pass) {
         const uint32_t shift = shift0 + (uint32_t)pass * RBITS;

@@ -5,6 +5,8 @@
 // straight from the connectivity instead of reading an emitted key array.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -29,6 +31,13 @@ struct CountedKeySrc {
     static constexpr bool kSkipNone = true;
     __device__ __forceinline__ uint64_t load(int64_t i) const { return keys[i]; }
 };
+
+// Sources that define kStaged = true copy their tile's inputs into LDS first
+// (stage) and build keys from there (load_staged); see NodePairSrc.
+template <class S, class = void>
+struct is_staged : std::false_type {};
+template <class S>
+struct is_staged<S, std::void_t<decltype(S::kStaged)>> : std::bool_constant<S::kStaged> {};
 
 template <class Src>
 __device__ __forceinline__ int64_t source_limit(const Src&, int64_t n) {
@@ -105,14 +114,28 @@ __global__ __launch_bounds__(BLOCK) void radix_pass_kernel(Src src, uint64_t* __
     const int64_t limit_n = source_limit(src, n);
     uint64_t key[ITEMS];
     uint32_t valid_bits = 0;
+    if constexpr (is_staged<Src>::value) {
+        // the staging area is free until step 4
+        int32_t* s_stage = reinterpret_cast<int32_t*>(s_keys);
+        src.template stage<BLOCK, TILE>(tile_base, n, s_stage, tid);
+        __syncthreads();
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const int64_t idx = wbase + j * WAVE;
-        // positions in [limit_n, n) lie inside the source array; they are read
-        // but never take part, so the loads need not wait for the count
-        key[j] = idx < n ? src.load(idx) : KEY_NONE;
-        const bool valid = idx < limit_n && !(Src::kSkipNone && key[j] == KEY_NONE);
-        valid_bits |= (uint32_t)valid << j;
+        for (int j = 0; j < ITEMS; ++j) {
+            const int64_t idx = wbase + j * WAVE;
+            key[j] = idx < n ? src.load_staged(idx, tile_base, s_stage) : KEY_NONE;
+            const bool valid = idx < limit_n && !(Src::kSkipNone && key[j] == KEY_NONE);
+            valid_bits |= (uint32_t)valid << j;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int64_t idx = wbase + j * WAVE;
+            // positions in [limit_n, n) lie inside the source array; they are read
+            // but never take part, so the loads need not wait for the count
+            key[j] = idx < n ? src.load(idx) : KEY_NONE;
+            const bool valid = idx < limit_n && !(Src::kSkipNone && key[j] == KEY_NONE);
+            valid_bits |= (uint32_t)valid << j;
+        }
     }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j)
