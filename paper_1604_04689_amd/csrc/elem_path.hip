@@ -54,8 +54,46 @@ struct ElemPairSrc {
     const int32_t* __restrict__ conn;
     int32_t n_vert;
     static constexpr bool kSkipNone = true;
+    static constexpr bool kStaged = true;
+    static constexpr int NPE = Elem<ET>::NPE;
+
+    // ids of the tile's whole elements to s[0 ..): at most TILE + 2 * NPE words
+    template <int BLOCK, int TILE>
+    __device__ __forceinline__ void stage(int64_t tile_base, int64_t n, int32_t* s, int tid) const {
+        constexpr int MAXC = TILE + 2 * NPE;
+        constexpr int PER = (MAXC + BLOCK - 1) / BLOCK;
+        static_assert(MAXC <= 2 * TILE, "staged ids fit the key staging area");
+        const uint32_t e0 = (uint32_t)tile_base / NPE;
+        const uint32_t e1 = ((uint32_t)tmin<int64_t>(tile_base + TILE, n) - 1u) / NPE;
+        const int cnt = (int)(e1 - e0 + 1u) * NPE;
+        const int32_t* src = conn + (size_t)e0 * NPE;
+        int32_t v[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = q * BLOCK + tid;
+            v[q] = i < cnt ? src[i] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = q * BLOCK + tid;
+            if (i < cnt) s[i] = v[q];
+        }
+    }
+    __device__ __forceinline__ uint64_t load_staged(int64_t s, int64_t tile_base, const int32_t* st) const {
+        const uint32_t ss = (uint32_t)s;
+        const uint32_t e = ss / NPE;
+        const int32_t* el = st + (e - (uint32_t)tile_base / NPE) * NPE;
+        const int j = (int)(ss - e * NPE);
+        const int32_t v = el[j];
+        if ((uint32_t)v >= (uint32_t)n_vert) return KEY_NONE;
+        bool first = true;
+#pragma unroll
+        for (int jj = 0; jj < NPE - 1; ++jj)
+            if (jj < j) first &= el[jj] != v;
+        return first ? ((uint64_t)(uint32_t)v << 32) | (uint64_t)e : KEY_NONE;
+    }
+
     __device__ __forceinline__ uint64_t load(int64_t s) const {
-        constexpr int NPE = Elem<ET>::NPE;
         const int32_t v = conn[s];
         if ((uint32_t)v >= (uint32_t)n_vert) return KEY_NONE;
         const uint32_t ss = (uint32_t)s;  // slot indices stay below 2^31

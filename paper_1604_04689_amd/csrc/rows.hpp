@@ -2,8 +2,11 @@
 // only: keys (hi << b) | lo arrive grouped by hi (one group = one row, i.e.
 // one vertex), with the lo values of a row in any order and possibly
 // repeated.  For every row the distinct lo values are written ascending to
-// temp[start .. start + count) (start = index of the row's first key), with
-// deg[hi] = count and src[hi] = start.  A scan of deg then gives row_ptr and
+// temp[start .. start + count), with deg[hi] = count and src[hi] = start.  A
+// tile's rows are packed one after another from the index of its first owned
+// key (so its writes cover whole lines), within the tile's own key range;
+// in a tile that owns a long row every row (long ones included) starts at the
+// index of its own first key instead.  A scan of deg then gives row_ptr and
 // a gather moves each row to cols.  This is the paper's sort by the first
 // array (Sec. 2.2.1) followed by the duplicate-free, ascending rows of our
 // reading of the serial solution (Sec. 3.2.2).
@@ -66,6 +69,7 @@ static __global__ __launch_bounds__(ROW_BLOCK) void row_unique_kernel(const uint
     __shared__ uint64_t s_startmask[CH];  // row-start flags of each chunk
     __shared__ int32_t s_csum[CH + 1];    // per chunk: last row start, then kept count; scanned
     __shared__ int32_t s_bounds[2];
+    __shared__ int32_t s_haslong;
     __shared__ uint64_t s_before;
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1), wid = tid / WAVE;
@@ -83,6 +87,7 @@ static __global__ __launch_bounds__(ROW_BLOCK) void row_unique_kernel(const uint
         s_before = base > 0 ? keys[base - 1] : KEY_NONE;
         s_bounds[0] = ROW_TILE;
         s_bounds[1] = SPAN;
+        s_haslong = 0;
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -155,6 +160,7 @@ static __global__ __launch_bounds__(ROW_BLOCK) void row_unique_kernel(const uint
                 const uint32_t slot = atomicAdd(long_count, 1u);
                 if ((int64_t)slot < long_cap) long_list[slot] = base + rs;
                 else bad = true;
+                s_haslong = 1;
             }
             continue;
         }
@@ -214,7 +220,11 @@ static __global__ __launch_bounds__(ROW_BLOCK) void row_unique_kernel(const uint
     }
     if (tid == 0) s_e[SPAN] = (int16_t)s_csum[CH];
     __syncthreads();
-    // ---- place every kept value; the row's first position records the row
+    // ---- place every kept value; the row's first position records the row.
+    // Rows are packed from the tile's first owned key on, unless the tile
+    // owns a long row (whose output fills its own key range): then every row
+    // writes into its own key range.
+    const bool packed = s_haslong == 0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int p = q * ROW_BLOCK + tid;
@@ -227,13 +237,13 @@ static __global__ __launch_bounds__(ROW_BLOCK) void row_unique_kernel(const uint
             const uint32_t lo = (uint32_t)(k[q] & lo_mask);
             int below = 0;
             for (int j = 0; j < u; ++j) below += s_dval[ds + j] < lo ? 1 : 0;
-            temp[base + rs + below] = (int32_t)lo;
+            temp[base + (packed ? p0 + ds : rs) + below] = (int32_t)lo;
         }
         if (p == rs) {
             const int64_t hi = (int64_t)(k[q] >> b);
             if (hi < n_vert) {
                 deg[hi] = u;
-                src[hi] = base + rs;
+                src[hi] = base + (packed ? p0 + ds : rs);
             } else {
                 bad = true;
             }
