@@ -41,6 +41,9 @@ WORKLOADS = {
 }
 
 
+SERVE_OFFERED = 0.6e9  # elements/s offered to the serving stream (Poisson arrivals)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -225,8 +228,8 @@ def run_batched(steps, warmup, torch, nb, per_mesh_steps=2):
     total_f = sum(m.n_elem for m in meshes)
 
     def step():
-        node.launch(conn, stream)
-        elem.launch(conn, stream)
+        node.launch(conn, stream, tuned=True)
+        elem.launch(conn, stream, tuned=True)
 
     for _ in range(max(warmup, 1)):
         step()
@@ -245,7 +248,8 @@ def run_batched(steps, warmup, torch, nb, per_mesh_steps=2):
     node.check(stream)
     elem.check(stream)
     batched = (t1 - t0) / steps
-    batched_graph = time_graph_replays(torch, [node.capture(conn), elem.capture(conn)], [node, elem], stream, steps)
+    batched_graph = time_graph_replays(torch, [node.capture(conn, tuned=True), elem.capture(conn, tuned=True)],
+                                       [node, elem], stream, steps)
     del node, elem
 
     # the same meshes, one plain call per mesh and relation
@@ -255,8 +259,8 @@ def run_batched(steps, warmup, torch, nb, per_mesh_steps=2):
 
     def step_each():
         for c, (bn, be) in zip(conns, builds):
-            bn.launch(c, stream)
-            be.launch(c, stream)
+            bn.launch(c, stream, tuned=True)
+            be.launch(c, stream, tuned=True)
 
     step_each()
     torch.cuda.synchronize()
@@ -282,33 +286,41 @@ def run_batched(steps, warmup, torch, nb, per_mesh_steps=2):
     return meshes, res
 
 
-def run_serving(meshes, capacity, torch, nb, n_req=600, warm=60, load=0.8, slots=4, max_batch=32,
+def run_serving(meshes, torch, nb, rate_elems=None, n_req=600, warm=60, slots=4, max_batch=32,
                 budget=64 << 30):
-    """Poisson arrivals of requests drawn from the batch's meshes at an
-    offered load of `load` x the batched capacity (elements/s), admitted by a
-    device-memory budget for their buffers; continuous batching over `slots`
-    streams.  Inputs start in host memory (the upload is part of latency)."""
+    """Requests drawn from the batch's meshes, admitted by a device-memory
+    budget for their buffers, continuous batching over `slots` streams.
+    Inputs start in pageable host memory; staging and upload are part of
+    latency.  Arrivals are Poisson at `rate_elems` elements/s offered, or all
+    at t = 0 (saturation: sustained throughput) when rate_elems is None."""
     import numpy as np
     from paper_1604_04689_amd import meshgen as mg
     from paper_1604_04689_amd import serve
     rng = np.random.default_rng(mg.BASE_SEED + 4)
     pick = rng.integers(0, len(meshes), size=n_req + warm)
     mean_f = float(np.mean([meshes[i].n_elem for i in pick]))
-    rate = load * capacity / mean_f
-    arr = mg.poisson_arrivals(n_req + warm, rate, seed=mg.BASE_SEED + 5)
+    if rate_elems is None:
+        arr = np.zeros(n_req)
+    else:
+        arr = mg.poisson_arrivals(n_req, rate_elems / mean_f, seed=mg.BASE_SEED + 5)
+    ex = serve.GpuExecutor(slots)
+    # warm-up stream on the same executor (pinned staging blocks, device buffers), not measured
+    warm_reqs = [serve.Request(i, 0.0, meshes[j].conn, meshes[j].etype, meshes[j].n_vert)
+                 for i, j in enumerate(pick[n_req:])]
+    serve.Server(ex, serve.RealClock(), n_slots=slots, budget_bytes=budget, max_batch=max_batch).run(warm_reqs)
     reqs = [serve.Request(i, float(t), meshes[j].conn, meshes[j].etype, meshes[j].n_vert)
-            for i, (j, t) in enumerate(zip(pick, arr))]
-    srv = serve.Server(serve.GpuExecutor(slots), serve.RealClock(), n_slots=slots, budget_bytes=budget,
-                       max_batch=max_batch)
+            for i, (j, t) in enumerate(zip(pick[:n_req], arr))]
+    srv = serve.Server(ex, serve.RealClock(), n_slots=slots, budget_bytes=budget, max_batch=max_batch)
     t0 = time.perf_counter()
     done = srv.run(reqs)
     wall = time.perf_counter() - t0
-    summ = serve.latency_summary([r for r in done if r.rid >= warm])
-    summ.update({"offered_load": load, "offered_elements_per_s": rate * mean_f, "slots": slots,
-                 "max_batch": max_batch, "budget_bytes": budget, "batches": srv.batches,
+    summ = serve.latency_summary(done)
+    summ.update({"offered_elements_per_s": rate_elems, "arrivals": "poisson" if rate_elems else "all at t=0",
+                 "slots": slots, "max_batch": max_batch, "budget_bytes": budget, "batches": srv.batches,
                  "mean_batch": float(np.mean(srv.batch_sizes)), "peak_reserved_bytes": srv.peak_in_use,
                  "wall_s": wall, "warmup_requests": warm})
-    log(f"[bench] serve: {summ['requests']} requests at load {load}: p50 {summ['p50_ms']:.2f} ms, "
+    what = f"offered {rate_elems / 1e9:.2f} G elem/s" if rate_elems else "saturation"
+    log(f"[bench] serve ({what}): {summ['requests']} requests: p50 {summ['p50_ms']:.2f} ms, "
         f"p99 {summ['p99_ms']:.2f} ms, {summ['elements_per_s'] / 1e9:.2f} G elem/s sustained, "
         f"{srv.batches} batches")
     return summ
@@ -374,8 +386,8 @@ def main():
 
     if not args.no_batch:
         meshes, others["batch512"] = run_batched(max(3, args.steps // 4), 1, torch, nb)
-        others["serve"] = run_serving(meshes, others["batch512"]["batched_elements_per_s"], torch, nb,
-                                      n_req=args.serve_requests)
+        others["serve"] = run_serving(meshes, torch, nb, rate_elems=SERVE_OFFERED, n_req=args.serve_requests)
+        others["serve_saturation"] = run_serving(meshes, torch, nb, rate_elems=None, n_req=args.serve_requests)
         del meshes
 
     traffic = load_traffic(args.workload)

@@ -53,22 +53,30 @@ def load_table():
     return _table_cache
 
 
-def lookup(kind, etype, n_elem):
-    """The tuned entry for a call, or the nearest bucket of the same
-    relation and type, or None."""
+def _nearest(relation, etype, n_keys):
     table = load_table()
     if not table:
         return None
-    b = size_bucket(keys_of(kind, n_elem, etype))
+    b = size_bucket(n_keys)
     best = None
     for (rel, et, bk), e in table.items():
-        if rel == kind and et == etype and (best is None or abs(bk - b) < abs(best["bucket"] - b)):
+        if rel == relation and et == etype and (best is None or abs(bk - b) < abs(best["bucket"] - b)):
             best = e
     return best
 
 
-def apply(kind, etype, n_elem):
-    e = lookup(kind, etype, n_elem)
+def lookup(kind, etype, n_elem):
+    """The tuned entry for a single-mesh call, or the nearest bucket of the
+    same relation and type, or None."""
+    return _nearest(kind, etype, keys_of(kind, n_elem, etype))
+
+
+def lookup_batch(kind, n_keys):
+    """The tuned entry for a batch of n_keys pairs (node) or slots (element)."""
+    return _nearest("batch_" + kind, -1, n_keys)
+
+
+def _set(kind, e):
     if e is None:
         _b.set_radix_shape(-1)
         if kind == "node":
@@ -77,6 +85,14 @@ def apply(kind, etype, n_elem):
     _b.set_radix_shape(e["shape"])
     if kind == "node":
         _b.set_node_sort(e["mode"])
+
+
+def apply(kind, etype, n_elem):
+    _set(kind, lookup(kind, etype, n_elem))
+
+
+def apply_batch(kind, n_keys):
+    _set(kind, lookup_batch(kind, n_keys))
 
 
 def _digest(row_ptr, cols):
@@ -105,7 +121,52 @@ def time_config(torch, kind, mesh, conn, shape, mode, steps):
     return ms, digest
 
 
-def tune(meshes, steps=5, log=print):
+def time_batch_config(torch, kind, desc, conn, shape, mode, steps):
+    _b.set_radix_shape(shape)
+    if kind == "node":
+        _b.set_node_sort(mode)
+    build = _b.BatchBuild(kind, desc, conn.device)
+    build.launch(conn)
+    rp, cols = build.result()
+    digest = _digest(rp, cols)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        build.launch(conn)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    build.check()
+    del build
+    return ms, digest
+
+
+def tune_batches(torch, batches, steps=3, log=print):
+    entries = []
+    for name, meshes in batches:
+        desc = [(m.n_elem, m.etype, m.n_vert) for m in meshes]
+        conn = torch.as_tensor(_b.concat_conn([m.conn for m in meshes])).to("cuda:0")
+        seg, tot = _b.segment_table(desc)
+        for kind in ("node", "elem"):
+            modes = (0, 1) if kind == "node" else (0,)
+            results = []
+            for mode in modes:
+                for shape in range(len(_b.radix_shapes())):
+                    ms, dg = time_batch_config(torch, kind, desc, conn, shape, mode, steps)
+                    results.append((ms, shape, mode, dg))
+                    log(f"[tune] {name} batch {kind} shape {_b.radix_shapes()[shape]} mode {mode}: {ms:.3f} ms")
+            if len({r[3] for r in results}) != 1:
+                raise RuntimeError(f"configurations disagree on batch {name} {kind}: outputs differ")
+            ms, shape, mode, _ = min(results)
+            n_keys = tot["pairs"] if kind == "node" else tot["slots"]
+            entries.append({"relation": "batch_" + kind, "etype": -1, "bucket": size_bucket(n_keys),
+                            "shape": shape, "mode": mode, "ms": ms, "workload": name,
+                            "candidates": {f"shape{s}_mode{md}": round(t, 4) for t, s, md, _ in results}})
+        del conn
+        torch.cuda.empty_cache()
+    return entries
+
+
+def tune(meshes, steps=5, log=print, batches=()):
     import torch
 
     entries = []
@@ -128,6 +189,7 @@ def tune(meshes, steps=5, log=print):
                             "candidates": {f"shape{s}_mode{md}": round(t, 4) for t, s, md, _ in results}})
         del conn
         torch.cuda.empty_cache()
+    entries += tune_batches(torch, batches, log=log)
     _b.set_radix_shape(-1)
     _b.set_node_sort(_b.NODE_SORT_FULL_KEY)
     props = torch.cuda.get_device_properties(0)
@@ -143,11 +205,14 @@ def main():
     args = ap.parse_args()
     if args.quick:
         meshes = [mg.tri_grid(256, "coin", 1), mg.kuhn_tet_grid(16, 2), mg.hex_grid(16, 3)]
+        batches = [("batch64", [s.build() for s in mg.batch_specs(64, seed=7)])]
     else:
         meshes = [mg.tri_grid(256, "coin", 1), mg.tri_grid(1024, "coin", 2), mg.tri2048(),
                   mg.kuhn_tet_grid(24, 3), mg.kuhn_tet_grid(48, 4), mg.kuhn96(),
                   mg.hex_grid(24, 5), mg.hex_grid(64, 6)]
-    table = tune(meshes)
+        batches = [("batch64", [s.build() for s in mg.batch_specs(64, seed=7)]),
+                   ("batch512", [s.build() for s in mg.batch_specs()])]
+    table = tune(meshes, batches=batches)
     with open(args.out, "w") as fh:
         json.dump(table, fh, indent=1)
     print(f"wrote {args.out} with {len(table['entries'])} entries", flush=True)

@@ -324,10 +324,12 @@ def elem_neighbors(conn, etype, n_vert, stream=None):
 EDGES_PER_ELEM = {TRI3: 3, TET4: 6, HEX8: 12}
 
 
-def segment_table(meshes):
+def segment_table(meshes, conn_offs=None):
     """mesh_segment records (numpy structured array, 48 bytes each) for a
-    list of (n_elem, etype, n_vert), meshes laid out back to back in one
-    shared connectivity array, plus the totals (pairs, slots, vertices, ids)."""
+    list of (n_elem, etype, n_vert), plus the totals (pairs, slots, vertices,
+    ids).  The meshes' ids lie back to back in one shared connectivity array,
+    or, with ``conn_offs``, mesh m's ids start at index conn_offs[m] of it;
+    ``ids`` is then the end of the furthest mesh."""
     import numpy as np
 
     dt = np.dtype([("conn_off", "<i8"), ("n_elem", "<i8"), ("pair_off", "<i8"), ("slot_off", "<i8"),
@@ -335,14 +337,18 @@ def segment_table(meshes):
     assert dt.itemsize == 48
     seg = np.zeros(len(meshes), dtype=dt)
     conn_off = pair_off = slot_off = vert_off = 0
+    ids_end = 0
     for i, (n_elem, etype, n_vert) in enumerate(meshes):
         npe, ne = NODES_PER_ELEM[int(etype)], EDGES_PER_ELEM[int(etype)]
+        if conn_offs is not None:
+            conn_off = int(conn_offs[i])
         seg[i] = (conn_off, n_elem, pair_off, slot_off, vert_off, n_vert, etype, 0)
         conn_off += npe * n_elem
+        ids_end = max(ids_end, conn_off)
         pair_off += 2 * ne * n_elem
         slot_off += npe * n_elem
         vert_off += n_vert
-    return seg, {"pairs": pair_off, "slots": slot_off, "vert": vert_off, "ids": conn_off,
+    return seg, {"pairs": pair_off, "slots": slot_off, "vert": vert_off, "ids": ids_end,
                  "max_vert": max([int(m[2]) for m in meshes], default=0)}
 
 
@@ -356,7 +362,7 @@ class BatchBuild:
     build at another batch, reusing its device buffers when they are large
     enough (they only grow)."""
 
-    def __init__(self, kind, meshes, device="cuda"):
+    def __init__(self, kind, meshes, device="cuda", conn_offs=None):
         import torch
 
         if kind not in ("node", "elem"):
@@ -365,17 +371,19 @@ class BatchBuild:
         self.device = torch.device(device)
         self._ws_raw = self._rp = self._cols = self._segs = None
         self._seg_pinned = self._seg_event = None
-        self.reset(meshes)
+        self.reset(meshes, conn_offs=conn_offs)
 
-    def reset(self, meshes, stream=None):
+    def reset(self, meshes, stream=None, conn_offs=None):
         """Re-target at another batch.  The segment table is uploaded
         asynchronously on ``stream`` (default: the current stream), so reset
-        and launch must use the same stream."""
+        and launch must use the same stream.  ``conn_offs`` places each mesh's
+        ids in the connectivity passed to launch (default: back to back)."""
         import contextlib
 
         import torch
 
-        seg, tot = segment_table(meshes)
+        seg, tot = segment_table(meshes, conn_offs)
+        self.custom_offsets = conn_offs is not None
         self.seg_host = seg
         self.totals = tot
         self.n_mesh = len(meshes)
@@ -419,13 +427,15 @@ class BatchBuild:
                 self._seg_event.record()
         self.segs = self._segs
 
-    def launch(self, conn, stream=None):
+    def launch(self, conn, stream=None, tuned=False):
         import torch
 
         if conn.device != self.device or conn.dtype != torch.int32 or not conn.is_contiguous():
             raise ValueError("conn must be a contiguous int32 tensor on the build's device")
-        if conn.numel() != self.totals["ids"]:
-            raise ValueError(f"conn has {conn.numel()} ids, the segments cover {self.totals['ids']}")
+        if tuned:
+            from . import autotune
+            autotune.apply_batch(self.kind, self.totals["pairs"] if self.kind == "node" else self.totals["slots"])
+        self._check_conn(conn)
         t = self.totals
         if self.kind == "node":
             st = lib().mesh_batch_node_neighbors(_ptr(conn), _ptr(self.segs), self.n_mesh, t["pairs"], t["vert"],
@@ -440,6 +450,11 @@ class BatchBuild:
         if st != Status.OK:
             raise MeshError(st, f"mesh_batch_{self.kind}_neighbors")
 
+    def _check_conn(self, conn):
+        need = self.totals["ids"]
+        if (conn.numel() < need) if self.custom_offsets else (conn.numel() != need):
+            raise ValueError(f"conn has {conn.numel()} ids, the segments cover {need}")
+
     def check(self, stream=None):
         st = lib().mesh_check(_ptr(self.workspace), _stream_handle(stream, self.device))
         if st != Status.OK:
@@ -450,7 +465,7 @@ class BatchBuild:
         nnz = int(self.row_ptr[-1].item())
         return self.row_ptr, self.cols[:nnz]
 
-    def capture(self, conn):
+    def capture(self, conn, tuned=False):
         """A Graph replaying ``launch(conn)`` for the current batch layout
         (totals fixed; conn and segment contents may change between replays
         as long as the totals stay the same)."""
@@ -458,8 +473,10 @@ class BatchBuild:
 
         if conn.device != self.device or conn.dtype != torch.int32 or not conn.is_contiguous():
             raise ValueError("conn must be a contiguous int32 tensor on the build's device")
-        if conn.numel() != self.totals["ids"]:
-            raise ValueError(f"conn has {conn.numel()} ids, the segments cover {self.totals['ids']}")
+        if tuned:
+            from . import autotune
+            autotune.apply_batch(self.kind, self.totals["pairs"] if self.kind == "node" else self.totals["slots"])
+        self._check_conn(conn)
         t = self.totals
         h = _c_p()
         with _device_guard(self.device):

@@ -15,6 +15,7 @@
 #include "internal.hpp"
 #include "launch.hpp"
 #include "radix.hpp"
+#include "rows.hpp"
 
 namespace mnb {
 
@@ -205,19 +206,23 @@ static uint32_t bits_for(int64_t n) {
     return b;
 }
 
-bool plan_batch(int64_t n_keys, uint32_t digit_bits, BatchPlan* p) {
-    if (n_keys < 0 || digit_bits == 0 || digit_bits > 62) return false;
+bool plan_batch(int64_t n_keys, uint32_t digit_bits, int32_t rows_vert, BatchPlan* p) {
+    if (n_keys < 0 || digit_bits == 0 || digit_bits > 62 || rows_vert < 0) return false;
     p->n_keys = n_keys;
     p->n_pass = (int)ceil_div(digit_bits, RBITS);
     if (p->n_pass > B_MAX_PASS) return false;
     p->digit_bits = digit_bits;
     p->n_tiles = ceil_div(n_keys, min_radix_tile());
     p->n_utiles = ceil_div(n_keys, UNIQ_TILE);
+    p->rows_vert = rows_vert;
+    p->long_cap = rows_vert > 0 ? n_keys / (ROW_SHORT + 1) + 1 : 0;
+    const int64_t scan_tiles = rows_vert > 0 ? ceil_div((int64_t)rows_vert + 1, SCAN_TILE) : 0;
+    const bool two_bufs = p->n_pass > 1 || rows_vert > 0;  // the rows stage writes into the free key buffer
     size_t off = HEADER_BYTES;
     p->off_hist = off;
     off += align_up(B_MAX_PASS * RADIX * sizeof(uint32_t));
-    p->off_ulb = off;
-    off += align_up((size_t)p->n_utiles * sizeof(uint64_t));
+    p->off_ulb = off;  // CSR look-back, or the rows stage's scan look-back
+    off += align_up((size_t)(p->n_utiles > scan_tiles ? p->n_utiles : scan_tiles) * sizeof(uint64_t));
     p->off_lb0 = off;
     off += align_up((size_t)p->n_tiles * RADIX * sizeof(uint64_t));
     p->zero_bytes = off;
@@ -226,7 +231,13 @@ bool plan_batch(int64_t n_keys, uint32_t digit_bits, BatchPlan* p) {
     p->off_keys0 = off;
     off += align_up((size_t)n_keys * sizeof(uint64_t));
     p->off_keys1 = off;
-    off += p->n_pass > 1 ? align_up((size_t)n_keys * sizeof(uint64_t)) : 0;
+    off += two_bufs ? align_up((size_t)n_keys * sizeof(uint64_t)) : 0;
+    p->off_deg = off;
+    off += align_up((size_t)rows_vert * sizeof(int32_t));
+    p->off_src = off;
+    off += align_up((size_t)rows_vert * sizeof(int64_t));
+    p->off_long = off;
+    off += align_up((size_t)p->long_cap * sizeof(int64_t));
     p->n_lut = n_keys > 0 ? ((n_keys - 1) >> SEG_LUT_SHIFT) + 2 : 0;
     p->off_lut = off;
     off += align_up((size_t)p->n_lut * sizeof(int32_t));
@@ -240,7 +251,7 @@ uint32_t batch_hi_bits(int32_t total_vert) { return bits_for(total_vert); }
 template <class Src>
 static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, uint32_t shift0, uint32_t csr_lo_bits,
                                  int32_t total_vert, int32_t* row_ptr, int32_t* cols, int64_t cols_cap, char* w,
-                                 const mesh_segment* segs, int32_t n_mesh, hipStream_t s) {
+                                 const mesh_segment* segs, int32_t n_mesh, bool rows, hipStream_t s) {
     uint32_t* hdr = (uint32_t*)w;
     uint32_t* err = hdr + HDR_ERR;
     uint32_t* count = hdr + HDR_KEY_COUNT;
@@ -279,6 +290,12 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
     }
     if (e != hipSuccess) return e;
     (void)tag;
+    if (rows) {
+        RowsStage r{kb[(p.n_pass - 1) & 1], p.n_keys, csr_lo_bits, total_vert, (int32_t*)(w + p.off_deg),
+                    (int64_t*)(w + p.off_src), (int32_t*)kb[p.n_pass & 1], (int64_t*)(w + p.off_long), p.long_cap,
+                    hdr + HDR_LONG_COUNT, ulb, hdr + HDR_TICKET0 + TK_BCSR, err};
+        return launch_rows_stage(true, r, row_ptr, cols, cols_cap, s);
+    }
     return launch_unique_csr(node ? "batch_node_csr" : "batch_elem_csr", kb[(p.n_pass - 1) & 1], p.n_keys,
                              node ? (const uint32_t*)nullptr : count, csr_lo_bits, total_vert, cols, cols_cap,
                              row_ptr, ulb, hdr + HDR_TICKET0 + TK_BCSR, err, s);
@@ -291,8 +308,19 @@ hipError_t run_batch_node(const BatchPlan& p, const int32_t* conn, const mesh_se
     if (e != hipSuccess) return e;
     if (p.n_keys == 0 || n_mesh == 0) return fill_i32(row_ptr, (int64_t)total_vert + 1, 0, s);
     const int32_t* lut = (const int32_t*)((char*)ws + p.off_lut);
+    if (node_sort_mode() == 1) {
+        // vertex-rows: radix passes over the global-vertex bits only (the
+        // all-ones value stays free for KEY_NONE), then per-row dedup
+        BatchPlan q = p;
+        q.digit_bits = bits_for((int64_t)total_vert + 1);
+        q.n_pass = (int)ceil_div(q.digit_bits, RBITS);
+        e = fill_i32((int32_t*)((char*)ws + p.off_deg), total_vert, 0, s);
+        if (e != hipSuccess) return e;
+        return batch_pipeline(q, "node", BatchNodePairSrc{conn, segs, lut, lo_bits}, lo_bits, lo_bits, total_vert,
+                              row_ptr, cols, cols_cap, (char*)ws, segs, n_mesh, true, s);
+    }
     return batch_pipeline(p, "node", BatchNodePairSrc{conn, segs, lut, lo_bits}, 0u, lo_bits, total_vert, row_ptr,
-                          cols, cols_cap, (char*)ws, segs, n_mesh, s);
+                          cols, cols_cap, (char*)ws, segs, n_mesh, false, s);
 }
 
 hipError_t run_batch_elem(const BatchPlan& p, const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
@@ -303,7 +331,7 @@ hipError_t run_batch_elem(const BatchPlan& p, const int32_t* conn, const mesh_se
     if (p.n_keys == 0 || n_mesh == 0) return fill_i32(row_ptr, (int64_t)total_vert + 1, 0, s);
     const int32_t* lut = (const int32_t*)((char*)ws + p.off_lut);
     return batch_pipeline(p, "elem", BatchElemPairSrc{conn, segs, lut}, 32u, 32u, total_vert, row_ptr, cols,
-                          cols_cap, (char*)ws, segs, n_mesh, s);
+                          cols_cap, (char*)ws, segs, n_mesh, false, s);
 }
 
 }  // namespace mnb

@@ -64,11 +64,14 @@ struct BatchPlan {
     size_t off_hist = 0, off_ulb = 0, off_lb0 = 0, off_lb1 = 0, off_keys0 = 0, off_keys1 = 0;
     int64_t n_lut = 0;      // segment lookup entries (one per 2^SEG_LUT_SHIFT keys, plus one)
     size_t off_lut = 0;
+    int32_t rows_vert = 0;  // node relation: vertices of the vertex-rows stage (0: no such stage)
+    int64_t long_cap = 0;
+    size_t off_deg = 0, off_src = 0, off_long = 0;
     size_t zero_bytes = 0;
     size_t total = 0;
 };
 
-bool plan_batch(int64_t n_keys, uint32_t digit_bits, BatchPlan* p);
+bool plan_batch(int64_t n_keys, uint32_t digit_bits, int32_t rows_vert, BatchPlan* p);
 uint32_t batch_node_lo_bits(int32_t max_vert);
 uint32_t batch_hi_bits(int32_t total_vert);
 hipError_t run_batch_node(const BatchPlan& p, const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,

@@ -262,26 +262,10 @@ static hipError_t node_pipeline(const NodePlan& p, const int32_t* conn, int32_t*
         return launch_unique_csr("node_unique_csr", sorted, p.n_pairs, (const uint32_t*)nullptr, p.id_bits,
                                  p.n_vert, cols, cols_capacity, row_ptr, ulb, tickets + (N_TICKETS - 1), err, s);
     // vertex-rows mode: canonical rows into the free key buffer, then scan and gather
-    int32_t* deg = (int32_t*)(w + p.off_deg);
-    int64_t* src = (int64_t*)(w + p.off_src);
-    int64_t* long_list = (int64_t*)(w + p.off_long);
-    int32_t* temp = (int32_t*)kb[n_pass & 1];
-    e = launch("node_row_unique", row_unique_kernel, dim3((unsigned)ceil_div(p.n_pairs, ROW_TILE)), dim3(ROW_BLOCK),
-               s, sorted, p.n_pairs, p.id_bits, p.n_vert, deg, src, temp, long_list, p.long_cap,
-               hdr + HDR_LONG_COUNT, err);
-    if (e == hipSuccess)
-        e = launch("node_long_rows", long_rows_kernel, dim3(LONG_GRID), dim3(LONG_BLOCK), s, sorted, p.n_pairs,
-                   p.id_bits, p.n_vert, deg, src, temp, (const int64_t*)long_list, p.long_cap,
-                   (const uint32_t*)(hdr + HDR_LONG_COUNT), err);
-    if (e == hipSuccess)
-        e = launch("node_row_scan", scan_i32_kernel, dim3((unsigned)ceil_div((int64_t)p.n_vert, SCAN_TILE)),
-                   dim3(SCAN_BLOCK), s, (const int32_t*)deg, (int64_t)p.n_vert, row_ptr, ulb,
-                   tickets + (N_TICKETS - 2), err);
-    if (e == hipSuccess)
-        e = launch("node_row_gather", row_gather_kernel, dim3((unsigned)ceil_div((int64_t)p.n_vert, GATHER_BLOCK)),
-                   dim3(GATHER_BLOCK), s, (const int32_t*)row_ptr, (const int32_t*)deg, (const int64_t*)src,
-                   (const int32_t*)temp, p.n_vert, cols, cols_capacity, err);
-    return e;
+    RowsStage r{sorted, p.n_pairs, p.id_bits, p.n_vert, (int32_t*)(w + p.off_deg), (int64_t*)(w + p.off_src),
+                (int32_t*)kb[n_pass & 1], (int64_t*)(w + p.off_long), p.long_cap, hdr + HDR_LONG_COUNT,
+                ulb, tickets + (N_TICKETS - 2), err};
+    return launch_rows_stage(false, r, row_ptr, cols, cols_capacity, s);
 }
 
 hipError_t run_node(const NodePlan& p, const int32_t* conn, int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,

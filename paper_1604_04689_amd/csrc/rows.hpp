@@ -15,6 +15,7 @@
 #include <climits>
 
 #include "common.hpp"
+#include "csr.hpp"
 #include "launch.hpp"
 
 namespace mnb {
@@ -389,6 +390,48 @@ static __global__ __launch_bounds__(GATHER_BLOCK) void row_gather_kernel(const i
         }
         cols[i] = temp[s_src[lo] + (i - s_start[lo])];
     }
+}
+
+// The vertex-rows stage after the radix passes over the high key bits:
+// row dedup, long rows, scan of the distinct counts into row_ptr, gather into
+// cols.  `deg` must be zero on entry and `*long_count` zero; `temp` needs n
+// words; `scan_lb` room for ceil((n_vert + 1) / SCAN_TILE) zeroed look-back
+// slots.  Kernel names carry `tag` ("node" or "batch_node").
+struct RowsStage {
+    const uint64_t* sorted;
+    int64_t n;
+    uint32_t b;  // low bits of a key (the neighbor id)
+    int32_t n_vert;
+    int32_t* deg;
+    int64_t* src;
+    int32_t* temp;
+    int64_t* long_list;
+    int64_t long_cap;
+    uint32_t* long_count;
+    uint64_t* scan_lb;
+    uint32_t* scan_ticket;
+    uint32_t* err;
+};
+
+static inline hipError_t launch_rows_stage(bool batch, const RowsStage& r, int32_t* row_ptr, int32_t* cols,
+                                           int64_t cols_cap, hipStream_t s) {
+    hipError_t e = launch(batch ? "batch_node_row_unique" : "node_row_unique", row_unique_kernel,
+                          dim3((unsigned)ceil_div(r.n, ROW_TILE)), dim3(ROW_BLOCK), s, r.sorted, r.n, r.b, r.n_vert,
+                          r.deg, r.src, r.temp, r.long_list, r.long_cap, r.long_count, r.err);
+    if (e == hipSuccess)
+        e = launch(batch ? "batch_node_long_rows" : "node_long_rows", long_rows_kernel, dim3(LONG_GRID),
+                   dim3(LONG_BLOCK), s, r.sorted, r.n, r.b, r.n_vert, r.deg, r.src, r.temp,
+                   (const int64_t*)r.long_list, r.long_cap, (const uint32_t*)r.long_count, r.err);
+    if (e == hipSuccess)
+        e = launch(batch ? "batch_node_row_scan" : "node_row_scan", scan_i32_kernel,
+                   dim3((unsigned)ceil_div((int64_t)r.n_vert, SCAN_TILE)), dim3(SCAN_BLOCK), s, (const int32_t*)r.deg,
+                   (int64_t)r.n_vert, row_ptr, r.scan_lb, r.scan_ticket, r.err);
+    if (e == hipSuccess)
+        e = launch(batch ? "batch_node_row_gather" : "node_row_gather", row_gather_kernel,
+                   dim3((unsigned)ceil_div((int64_t)r.n_vert, GATHER_BLOCK)), dim3(GATHER_BLOCK), s,
+                   (const int32_t*)row_ptr, (const int32_t*)r.deg, (const int64_t*)r.src, (const int32_t*)r.temp,
+                   r.n_vert, cols, cols_cap, r.err);
+    return e;
 }
 
 }  // namespace mnb

@@ -11,9 +11,10 @@ device until released; latency = completion - arrival.
 
 The executor is pluggable:
 
-* ``GpuExecutor`` runs each batch through the library's batched entry points
-  (``mesh_batch_node_neighbors`` / ``mesh_batch_elem_neighbors``) on its own
-  stream and detects completion with a HIP event;
+* ``GpuExecutor`` uploads each request into a device arena when it arrives,
+  runs each batch through the library's batched entry points
+  (``mesh_batch_node_neighbors`` / ``mesh_batch_elem_neighbors``) on its
+  slot's stream and detects completion with a HIP event;
 * ``FakeExecutor`` (tests) runs on the CPU with a simulated clock and
   duration model, so admission and batching logic are testable without a GPU.
 """
@@ -41,6 +42,7 @@ class Request:
     reserve: int = 0        # device bytes reserved while in flight (set by the server)
     admitted: float = math.nan
     completed: float = math.nan
+    prep: object = None     # executor state once the upload has started
 
     @property
     def n_elem(self) -> int:
@@ -100,16 +102,57 @@ class FakeExecutor:
         self.finish.pop(id(batch), None)
 
 
+class Arena:
+    """First-fit allocator of index ranges in one device connectivity buffer
+    (host-side bookkeeping only)."""
+
+    def __init__(self, capacity: int, align: int = 64):
+        self.capacity, self.align = int(capacity), align
+        self.free = [(0, self.capacity)]  # sorted, disjoint (start, length)
+        self.used = {}
+
+    def alloc(self, n: int) -> Optional[int]:
+        n = max(int(n), 1)
+        n = (n + self.align - 1) // self.align * self.align
+        for i, (a, ln) in enumerate(self.free):
+            if ln >= n:
+                if ln == n:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (a + n, ln - n)
+                self.used[a] = n
+                return a
+        return None
+
+    def release(self, a: int):
+        n = self.used.pop(a)
+        i = 0
+        while i < len(self.free) and self.free[i][0] < a:
+            i += 1
+        self.free.insert(i, (a, n))
+        # merge with the neighbours
+        if i + 1 < len(self.free) and a + n == self.free[i + 1][0]:
+            self.free[i] = (a, n + self.free[i + 1][1])
+            self.free.pop(i + 1)
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == self.free[i][0]:
+            self.free[i - 1] = (self.free[i - 1][0], self.free[i - 1][1] + self.free[i][1])
+            self.free.pop(i)
+
+    def in_use(self) -> int:
+        return sum(self.used.values())
+
+
 class GpuExecutor:
     """Runs each batch on its slot's stream through the batched C entry points.
 
-    Each slot keeps a pinned host staging buffer and its device buffers
-    (connectivity, workspaces, outputs) across batches; they only grow, so a
-    steady stream of requests allocates nothing after warm-up."""
+    A request's connectivity is staged into pinned memory by a worker thread
+    and uploaded into a device arena on a separate upload stream as soon as
+    it arrives (``prepare``), overlapping the batches already running.  A
+    batch then only writes its segment records (which point into the arena)
+    and launches; its slot stream waits for its requests' uploads.  Each slot
+    keeps its device buffers across batches (they only grow)."""
 
-    COPY_CHUNK = 1 << 20  # ids per staging task
-
-    def __init__(self, n_slots: int, device="cuda:0", copy_threads: int = 8):
+    def __init__(self, n_slots: int, device="cuda:0", copy_threads: int = 8, arena_ids: int = 1 << 30):
         import concurrent.futures
 
         import torch
@@ -117,47 +160,54 @@ class GpuExecutor:
         self.torch = torch
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(self.device) for _ in range(n_slots)]
-        self.slot_state = [dict(pinned=None, conn=None, node=None, elem=None, event=None) for _ in range(n_slots)]
+        self.upload = torch.cuda.Stream(self.device)
+        self.slot_state = [dict(node=None, elem=None) for _ in range(n_slots)]
+        self.arena = Arena(arena_ids)
+        self.arena_buf = torch.empty(arena_ids, dtype=torch.int32, device=self.device)
         # numpy releases the GIL for plain copies, so staging runs on several cores
-        self.pool = concurrent.futures.ThreadPoolExecutor(copy_threads) if copy_threads > 1 else None
+        self.pool = concurrent.futures.ThreadPoolExecutor(max(copy_threads, 1))
 
-    def _stage(self, host, requests):
-        tasks, at = [], 0
-        for r in requests:
-            src = r.conn.reshape(-1)
-            for a in range(0, src.size, self.COPY_CHUNK):
-                b = min(a + self.COPY_CHUNK, src.size)
-                tasks.append((host[at + a:at + b], src[a:b]))
-            at += src.size
-        if self.pool is None or len(tasks) == 1:
-            for d, s in tasks:
-                np.copyto(d, s, casting="unsafe")
-        else:
-            list(self.pool.map(lambda t: np.copyto(t[0], t[1], casting="unsafe"), tasks))
+    def _stage_upload(self, conn: np.ndarray, off: int):
+        torch = self.torch
+        flat = conn.reshape(-1)
+        pinned = torch.empty(flat.size, dtype=torch.int32, pin_memory=True)
+        np.copyto(pinned.numpy(), flat, casting="unsafe")
+        with torch.cuda.stream(self.upload):
+            # the pinned block is reused only after this copy (host allocator events)
+            self.arena_buf[off:off + flat.size].copy_(pinned, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.upload)
+        return ev
+
+    def prepare(self, r: Request) -> bool:
+        """Start staging and uploading r; False if the arena is full now."""
+        if r.conn.size > self.arena.capacity:
+            raise BudgetError(f"request {r.rid} has {r.conn.size} ids, the arena holds {self.arena.capacity}")
+        off = self.arena.alloc(r.conn.size)
+        if off is None:
+            return False
+        r.prep = (off, self.pool.submit(self._stage_upload, r.conn, off))
+        return True
 
     def submit(self, batch: BatchHandle):
         torch = self.torch
         st = self.slot_state[batch.slot]
         s = self.streams[batch.slot]
         desc = [(r.n_elem, r.etype, r.n_vert) for r in batch.requests]
-        n_ids = sum(r.conn.size for r in batch.requests)
-        # the slot is free, so its previous batch (and its upload) has completed
-        if st["pinned"] is None or st["pinned"].numel() < n_ids:
-            st["pinned"] = torch.empty(max(n_ids, 1), dtype=torch.int32, pin_memory=True)
-            with torch.cuda.stream(s):
-                st["conn"] = torch.empty(max(n_ids, 1), dtype=torch.int32, device=self.device)
-        self._stage(st["pinned"].numpy(), batch.requests)
+        offs = []
+        for r in batch.requests:
+            off, fut = r.prep  # admitted only once its upload has started
+            s.wait_event(fut.result())
+            offs.append(off)
         with torch.cuda.stream(s):
-            conn = st["conn"][:n_ids]
-            conn.copy_(st["pinned"][:n_ids], non_blocking=True)
             if st["node"] is None:
-                st["node"] = _b.BatchBuild("node", desc, self.device)
-                st["elem"] = _b.BatchBuild("elem", desc, self.device)
+                st["node"] = _b.BatchBuild("node", desc, self.device, conn_offs=offs)
+                st["elem"] = _b.BatchBuild("elem", desc, self.device, conn_offs=offs)
             else:
-                st["node"].reset(desc, s)
-                st["elem"].reset(desc, s)
-            st["node"].launch(conn, s)
-            st["elem"].launch(conn, s)
+                st["node"].reset(desc, s, conn_offs=offs)
+                st["elem"].reset(desc, s, conn_offs=offs)
+            st["node"].launch(self.arena_buf, s, tuned=True)
+            st["elem"].launch(self.arena_buf, s, tuned=True)
             ev = torch.cuda.Event()
             ev.record(s)
         batch.payload = {"node": st["node"], "elem": st["elem"], "event": ev}
@@ -190,6 +240,11 @@ class GpuExecutor:
         batch.payload["elem"].check(s)
 
     def release(self, batch: BatchHandle):
+        # the batch has completed, so the arena ranges it read are free again
+        for r in batch.requests:
+            if getattr(r, "prep", None) is not None:
+                self.arena.release(r.prep[0])
+                r.prep = None
         batch.payload = None
 
 
@@ -220,7 +275,7 @@ class Server:
     """Continuous batching over ``n_slots`` slots under ``budget_bytes``."""
 
     def __init__(self, executor, clock, n_slots=4, budget_bytes=64 << 30, max_batch=64,
-                 on_complete: Optional[Callable] = None, reserve: Callable = reserve_bytes):
+                 on_complete: Optional[Callable] = None, reserve: Callable = reserve_bytes, max_staged=64):
         self.ex = executor
         self.clock = clock
         self.n_slots = n_slots
@@ -228,6 +283,8 @@ class Server:
         self.max_batch = max_batch
         self.on_complete = on_complete
         self.reserve = reserve
+        self.max_staged = max_staged  # uploads started ahead of admission, at most
+        self.admitted = 0
         self.in_use = 0
         self.peak_in_use = 0
         self.batches = 0
@@ -238,13 +295,17 @@ class Server:
     def _admit_into(self, slot: int) -> Optional[BatchHandle]:
         now = self.clock.now()
         take = []
+        staged = hasattr(self.ex, "prepare")
         while self.waiting and self.waiting[0].arrival <= now and len(take) < self.max_batch:
             r = self.waiting[0]
             if self.in_use + r.reserve > self.budget:
                 break  # FIFO: the head waits for memory, later ones wait behind it
+            if staged and r.prep is None:
+                break  # its upload has not started (connectivity arena full)
             self.waiting.popleft()
             self.in_use += r.reserve
             r.admitted = now
+            self.admitted += 1
             take.append(r)
         if not take:
             return None
@@ -275,8 +336,18 @@ class Server:
             if r.reserve > self.budget:
                 raise BudgetError(f"request {r.rid} needs {r.reserve} bytes, budget is {self.budget}")
         self.waiting.extend(reqs)
+        prepare = getattr(self.ex, "prepare", None)
+        next_prep = 0  # requests are prepared in arrival order as they arrive
+        first = self.admitted
         while self.waiting or self.running:
             progressed = False
+            if prepare is not None:
+                now = self.clock.now()
+                while (next_prep < len(reqs) and reqs[next_prep].arrival <= now
+                       and next_prep - (self.admitted - first) < self.max_staged):
+                    if not prepare(reqs[next_prep]):
+                        break  # arena full: retry once a batch has released its ranges
+                    next_prep += 1
             for slot in list(self.running):
                 if self.ex.done(self.running[slot]):
                     self._retire(slot)

@@ -18,6 +18,15 @@ def _nb():
     return nb
 
 
+@pytest.fixture(autouse=True, params=[0, 1], ids=["full_key", "vertex_rows"])
+def node_sort(request):
+    """Every batch test runs under both node algorithms (process-wide)."""
+    nb = _nb()
+    nb.set_node_sort(request.param)
+    yield request.param
+    nb.set_node_sort(0)
+
+
 def run_batch(meshes):
     nb = _nb()
     desc = [(m.n_elem, m.etype, m.n_vert) for m in meshes]
@@ -64,6 +73,14 @@ def test_mixed_random_batch(oracle_mod):
 def test_structured_small_batch(oracle_mod):
     specs = mg.batch_specs(n_mesh=48, seed=5, tri_range=(4, 60), cell_range=(1, 9))
     meshes = [s.build() for s in specs]
+    got = run_batch(meshes)
+    check_slices(oracle_mod, meshes, got)
+
+
+def test_batch_with_long_rows(oracle_mod):
+    # few vertices, many elements: rows of hundreds to thousands of pairs
+    meshes = [mg.random_mesh(3000, 40, 1, seed=51), mg.tri_grid(30, "coin", 52),
+              mg.random_mesh(9000, 7, 2, seed=53), mg.random_mesh(400, 300, 0, seed=54)]
     got = run_batch(meshes)
     check_slices(oracle_mod, meshes, got)
 

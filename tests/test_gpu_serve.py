@@ -34,3 +34,29 @@ def test_served_equals_alone(oracle_mod):
         assert np.array_equal(ger, we[0]) and np.array_equal(gec, we[1]), r.rid
     s = serve.latency_summary(done)
     print("served:", s, "batches:", srv.batches, flush=True)
+
+
+def test_served_with_small_arena(oracle_mod):
+    """A connectivity arena that holds only two requests at a time: uploads
+    wait for batches to release their ranges, results stay exact."""
+    from paper_1604_04689_amd import serve
+    reqs = make_requests(16, rate=50000.0, seed=12)
+    biggest = max(r.conn.size for r in reqs)
+    got = {}
+
+    def on_complete(batch, ex):
+        ex.check(batch)
+        for r, res in zip(batch.requests, ex.results(batch)):
+            got[r.rid] = res
+
+    ex = serve.GpuExecutor(2, arena_ids=2 * (biggest + 64))
+    srv = serve.Server(ex, serve.RealClock(), n_slots=2, budget_bytes=1 << 34, max_batch=8,
+                       on_complete=on_complete)
+    srv.run(reqs)
+    assert len(got) == len(reqs) and ex.arena.in_use() == 0
+    for r in reqs:
+        wn = oracle_mod.node_neighbors(r.conn, r.etype, r.n_vert)
+        we = oracle_mod.elem_neighbors(r.conn, r.etype, r.n_vert)
+        (gnr, gnc), (ger, gec) = got[r.rid]
+        assert np.array_equal(gnr, wn[0]) and np.array_equal(gnc, wn[1]), r.rid
+        assert np.array_equal(ger, we[0]) and np.array_equal(gec, we[1]), r.rid

@@ -89,3 +89,53 @@ def test_latency_summary():
     srv, done = run(reqs, n_slots=2, budget_bytes=1 << 40)
     s = serve.latency_summary(done)
     assert s["requests"] == 20 and s["p99_ms"] >= s["p50_ms"] >= 0 and s["elements_per_s"] > 0
+
+
+def test_arena_first_fit_and_merge():
+    a = serve.Arena(1024, align=64)
+    x = a.alloc(100)   # 128
+    y = a.alloc(64)
+    z = a.alloc(500)   # 512
+    assert (x, y, z) == (0, 128, 192)
+    assert a.alloc(400) is None           # 1024 - 704 = 320 left
+    a.release(y)
+    assert a.alloc(64) == 128             # first fit reuses the hole
+    a.release(x)
+    a.release(128)
+    assert a.free[0] == (0, 192)          # holes merged
+    a.release(z)
+    assert a.free == [(0, 1024)] and a.in_use() == 0
+    assert a.alloc(1024) == 0 and a.alloc(1) is None
+
+
+def test_staged_executor_admits_only_prepared():
+    """An executor with a prepare step: a request whose upload cannot start
+    (arena full) waits, and later requests wait behind it (FIFO)."""
+    clock = serve.SimClock()
+
+    class Staged(serve.FakeExecutor):
+        def __init__(self, clock):
+            super().__init__(clock, t0=1.0, per_elem=0.0)
+            self.room = 1
+
+        def prepare(self, r):
+            if self.room == 0:
+                return False
+            self.room -= 1
+            r.prep = ("slot", r.rid)
+            return True
+
+        def release(self, batch):
+            for r in batch.requests:
+                r.prep = None
+                self.room += 1
+            super().release(batch)
+
+    ex = Staged(clock)
+    conn = np.zeros((4, 3), dtype=np.int32)
+    reqs = [serve.Request(i, 0.0, conn, 0, 3) for i in range(3)]
+    srv = serve.Server(ex, clock, n_slots=4, budget_bytes=1 << 40, max_batch=8, reserve=lambda *a: 1)
+    done = srv.run(reqs)
+    # one arena room: the requests run one at a time, one second each
+    assert sorted(r.completed for r in done) == [1.0, 2.0, 3.0]
+    assert srv.batches == 3
