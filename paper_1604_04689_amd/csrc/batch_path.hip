@@ -21,12 +21,13 @@ namespace mnb {
 
 constexpr int BH_BLOCK = 256;
 constexpr int BH_GRID_MAX = 1024;
-constexpr int BH_UNROLL = 4;
 constexpr int B_MAX_PASS = 8;
 constexpr int TK_BCSR = 15;
 
 constexpr int SEG_LUT_SHIFT = 10;
 constexpr int LUT_BLOCK = 256;
+constexpr int STAGE_HDR = 8;  // int32 header words before the staged ids
+constexpr int BH_ITEMS = 16;  // keys per thread per histogram tile
 
 static_assert(sizeof(mesh_segment) == 48, "mesh_segment layout");
 
@@ -113,6 +114,84 @@ struct BatchNodePairSrc {
         bool bad;
         return make(i, &bad);
     }
+
+    // ---- staged path: a tile whose keys all lie in one mesh copies that
+    // mesh's element ids into LDS once (coalesced) and builds its keys there;
+    // other tiles use make().  Header words: [0] 1 if staged, [1] type,
+    // [2] n_vert, [3] vert_off, [4] first staged element, [6..7] pair_off.
+    static constexpr bool kStaged = true;
+    template <int TILE>
+    static constexpr int stage_words() { return STAGE_HDR + TILE / 2 + 16; }
+
+    template <int BLOCK, int TILE>
+    __device__ __forceinline__ void stage(int64_t tile_base, int64_t n, int32_t* s, int tid) const {
+        static_assert(stage_words<TILE>() <= 2 * TILE, "staged ids fit the key staging area");
+        constexpr int PER = (stage_words<TILE>() - STAGE_HDR + BLOCK - 1) / BLOCK;
+        const int64_t last = tmin<int64_t>(tile_base + TILE, n) - 1;
+        const int m0 = lut_segment<offsetof(mesh_segment, pair_off)>(segs, lut, tile_base);
+        const int m1 = lut_segment<offsetof(mesh_segment, pair_off)>(segs, lut, last);
+        const mesh_segment& sg = segs[m0];
+        const int kpe = 2 * edges_per_elem(sg.etype), npe = nodes_per_elem(sg.etype);
+        const bool one = m0 == m1 && kpe > 0 && tile_base >= sg.pair_off && last < sg.pair_off + kpe * sg.n_elem;
+        if (!one) {
+            if (tid == 0) s[0] = 0;
+            return;
+        }
+        const uint32_t e0 = (uint32_t)((tile_base - sg.pair_off) / kpe);
+        const uint32_t e1 = (uint32_t)((last - sg.pair_off) / kpe);
+        const int cnt = (int)(e1 - e0 + 1u) * npe;  // <= (TILE / 6 + 2) * 3 words
+        const int32_t* src = conn + sg.conn_off + (int64_t)e0 * npe;
+        int32_t* ids = s + STAGE_HDR;
+        int32_t v[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = q * BLOCK + tid;
+            v[q] = i < cnt ? src[i] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = q * BLOCK + tid;
+            if (i < cnt) ids[i] = v[q];
+        }
+        if (tid == 0) {
+            s[0] = 1;
+            s[1] = sg.etype;
+            s[2] = sg.n_vert;
+            s[3] = sg.vert_off;
+            s[4] = (int32_t)e0;
+            *(int64_t*)(s + 6) = sg.pair_off;
+        }
+    }
+
+    __device__ __forceinline__ uint64_t load_staged(int64_t i, int64_t tile_base, const int32_t* s, bool* bad) const {
+        if (s[0] == 0) return make(i, bad);
+        const int32_t et = s[1], nv = s[2];
+        const uint32_t loc = (uint32_t)(i - *(const int64_t*)(s + 6));
+        uint32_t e;
+        int pa, pb, dir, npe;
+        if (et == TRI3) {
+            pair_of<TRI3>(loc, &e, &pa, &pb, &dir);
+            npe = 3;
+        } else if (et == TET4) {
+            pair_of<TET4>(loc, &e, &pa, &pb, &dir);
+            npe = 4;
+        } else {
+            pair_of<HEX8>(loc, &e, &pa, &pb, &dir);
+            npe = 8;
+        }
+        const int32_t* el = s + STAGE_HDR + (e - (uint32_t)s[4]) * npe;
+        const int32_t x = el[pa], y = el[pb];
+        const int32_t u = dir ? y : x;
+        const int32_t w = dir ? x : y;
+        const bool ok = (uint32_t)u < (uint32_t)nv && (uint32_t)w < (uint32_t)nv;
+        *bad = !ok;
+        if (!ok || u == w) return KEY_NONE;
+        return ((uint64_t)(uint32_t)(s[3] + u) << lo_bits) | (uint64_t)(uint32_t)w;
+    }
+    __device__ __forceinline__ uint64_t load_staged(int64_t i, int64_t tile_base, const int32_t* s) const {
+        bool bad;
+        return load_staged(i, tile_base, s, &bad);
+    }
 };
 
 // (vertex, element) pair of connectivity slot s of the batch.
@@ -150,41 +229,108 @@ struct BatchElemPairSrc {
         bool bad;
         return make(s, &bad);
     }
+
+    // staged path as for BatchNodePairSrc; header [6..7] holds slot_off
+    static constexpr bool kStaged = true;
+    template <int TILE>
+    static constexpr int stage_words() { return STAGE_HDR + TILE + 16; }
+
+    template <int BLOCK, int TILE>
+    __device__ __forceinline__ void stage(int64_t tile_base, int64_t n, int32_t* st, int tid) const {
+        static_assert(stage_words<TILE>() <= 2 * TILE, "staged ids fit the key staging area");
+        constexpr int PER = (stage_words<TILE>() - STAGE_HDR + BLOCK - 1) / BLOCK;
+        const int64_t last = tmin<int64_t>(tile_base + TILE, n) - 1;
+        const int m0 = lut_segment<offsetof(mesh_segment, slot_off)>(segs, lut, tile_base);
+        const int m1 = lut_segment<offsetof(mesh_segment, slot_off)>(segs, lut, last);
+        const mesh_segment& sg = segs[m0];
+        const int npe = nodes_per_elem(sg.etype);
+        const bool one = m0 == m1 && npe > 0 && tile_base >= sg.slot_off && last < sg.slot_off + npe * sg.n_elem;
+        if (!one) {
+            if (tid == 0) st[0] = 0;
+            return;
+        }
+        const uint32_t e0 = (uint32_t)((tile_base - sg.slot_off) / npe);
+        const uint32_t e1 = (uint32_t)((last - sg.slot_off) / npe);
+        const int cnt = (int)(e1 - e0 + 1u) * npe;  // <= TILE + 2 * npe words
+        const int32_t* src = conn + sg.conn_off + (int64_t)e0 * npe;
+        int32_t* ids = st + STAGE_HDR;
+        int32_t v[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = q * BLOCK + tid;
+            v[q] = i < cnt ? src[i] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = q * BLOCK + tid;
+            if (i < cnt) ids[i] = v[q];
+        }
+        if (tid == 0) {
+            st[0] = 1;
+            st[1] = npe;
+            st[2] = sg.n_vert;
+            st[3] = sg.vert_off;
+            st[4] = (int32_t)e0;
+            *(int64_t*)(st + 6) = sg.slot_off;
+        }
+    }
+
+    __device__ __forceinline__ uint64_t load_staged(int64_t s, int64_t tile_base, const int32_t* st, bool* bad) const {
+        if (st[0] == 0) return make(s, bad);
+        const int npe = st[1];
+        const uint32_t loc = (uint32_t)(s - *(const int64_t*)(st + 6));
+        const uint32_t e = npe == 3 ? loc / 3u : npe == 4 ? loc >> 2 : loc >> 3;
+        const int j = (int)(loc - e * (uint32_t)npe);
+        const int32_t* el = st + STAGE_HDR + (e - (uint32_t)st[4]) * npe;
+        const int32_t v = el[j];
+        if ((uint32_t)v >= (uint32_t)st[2]) {
+            *bad = true;
+            return KEY_NONE;
+        }
+        *bad = false;
+        for (int jj = 0; jj < j; ++jj)
+            if (el[jj] == v) return KEY_NONE;  // repeated id inside the element
+        return ((uint64_t)(uint32_t)(st[3] + v) << 32) | (uint64_t)e;
+    }
+    __device__ __forceinline__ uint64_t load_staged(int64_t s, int64_t tile_base, const int32_t* st) const {
+        bool bad;
+        return load_staged(s, tile_base, st, &bad);
+    }
 };
 
 // Digit histograms (8-bit digits from bit shift0) of the keys a batch source
-// generates, the number of participating keys, and the data-error flag.
+// generates, the number of participating keys, and the data-error flag.  A
+// block takes tiles of BH_BLOCK x BH_ITEMS consecutive keys, staged as in the
+// first radix pass.
 template <class Src>
 __global__ __launch_bounds__(BH_BLOCK) void batch_hist_kernel(Src src, int64_t n, uint32_t shift0, int n_pass,
                                                              uint32_t last_bits, uint32_t* __restrict__ hist,
                                                              uint32_t* count, uint32_t* err) {
+    constexpr int TILE = BH_BLOCK * BH_ITEMS;
+    __shared__ __align__(16) int32_t s_stage[Src::template stage_words<TILE>()];  // header holds an int64
     __shared__ uint32_t s_hist[B_MAX_PASS * RADIX];
     __shared__ uint32_t s_keys;
     const int tid = threadIdx.x;
     if (tid == 0) s_keys = 0;
     for (int i = tid; i < n_pass * RADIX; i += BH_BLOCK) s_hist[i] = 0;
-    __syncthreads();
     bool bad_seen = false;
     uint32_t mine = 0;
-    const int64_t stride = (int64_t)gridDim.x * BH_BLOCK;
-    for (int64_t i0 = (int64_t)blockIdx.x * BH_BLOCK + tid; i0 < n; i0 += stride * BH_UNROLL) {
-        uint64_t k[BH_UNROLL];
-        bool take[BH_UNROLL];
-#pragma unroll
-        for (int u = 0; u < BH_UNROLL; ++u) {
-            const int64_t i = i0 + u * stride;
+    for (int64_t t0 = (int64_t)blockIdx.x * TILE; t0 < n; t0 += (int64_t)gridDim.x * TILE) {
+        __syncthreads();  // the previous tile's staged ids are consumed
+        src.template stage<BH_BLOCK, TILE>(t0, n, s_stage, tid);
+        __syncthreads();
+#pragma unroll 4
+        for (int j = 0; j < BH_ITEMS; ++j) {
+            const int64_t i = t0 + (int64_t)j * BH_BLOCK + tid;
+            if (i >= n) break;
             bool bad = false;
-            k[u] = i < n ? src.make(i, &bad) : KEY_NONE;
+            const uint64_t k = src.load_staged(i, t0, s_stage, &bad);
             bad_seen |= bad;
-            take[u] = i < n && !(Src::kSkipNone && k[u] == KEY_NONE);
-        }
-#pragma unroll
-        for (int u = 0; u < BH_UNROLL; ++u) {
-            if (!take[u]) continue;
+            if (Src::kSkipNone && k == KEY_NONE) continue;
             ++mine;
             for (int p = 0; p < n_pass; ++p) {
                 const uint32_t mask = p == n_pass - 1 ? (1u << last_bits) - 1 : RADIX - 1;
-                atomicAdd(&s_hist[p * RADIX + ((uint32_t)(k[u] >> (shift0 + p * RBITS)) & mask)], 1u);
+                atomicAdd(&s_hist[p * RADIX + ((uint32_t)(k >> (shift0 + p * RBITS)) & mask)], 1u);
             }
         }
     }
@@ -262,7 +408,7 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
     const int shape = radix_shape();
     const bool node = !Src::kSkipNone;
 
-    const int grid = (int)tmin<int64_t>(ceil_div(p.n_keys, BH_BLOCK), BH_GRID_MAX);
+    const int grid = (int)tmin<int64_t>(ceil_div(p.n_keys, (int64_t)BH_BLOCK * BH_ITEMS), BH_GRID_MAX);
     const uint32_t last_bits = p.digit_bits - (uint32_t)(p.n_pass - 1) * RBITS;
     const dim3 lut_grid((unsigned)ceil_div(p.n_lut, LUT_BLOCK));
     hipError_t e =
