@@ -19,7 +19,7 @@
 
 namespace mnb {
 
-constexpr int BH_BLOCK = 256;
+constexpr int BH_BLOCK = 512;
 constexpr int BH_GRID_MAX = 1024;
 constexpr int B_MAX_PASS = 8;
 constexpr int TK_BCSR = 15;
@@ -27,7 +27,6 @@ constexpr int TK_BCSR = 15;
 constexpr int SEG_LUT_SHIFT = 10;
 constexpr int LUT_BLOCK = 256;
 constexpr int STAGE_HDR = 8;  // int32 header words before the staged ids
-constexpr int BH_ITEMS = 16;  // keys per thread per histogram tile
 
 static_assert(sizeof(mesh_segment) == 48, "mesh_segment layout");
 
@@ -65,6 +64,51 @@ __device__ __forceinline__ int lut_segment(const mesh_segment* __restrict__ segs
     return find_segment<FIELD>(segs, lut[t], lut[t + 1], i);
 }
 
+// Per radix tile (TILE consecutive keys): the mesh all of its keys lie in,
+// or etype = -1 if they span several meshes.  Built once per call so that a
+// tile reads one record, not a chain of lookups, before staging its ids.
+struct TileRec {
+    int32_t etype;     // -1: keys of several meshes (the tile takes the per-key path)
+    int32_t n_vert;
+    int32_t vert_off;
+    uint32_t e0;       // first element of the tile, local to its mesh
+    int32_t cnt;       // ids to stage: whole elements e0 .. e1
+    int32_t reserved;
+    int64_t off;       // pair_off (node) or slot_off (element) of the mesh
+    int64_t ids;       // index in conn of the first staged id
+    int64_t reserved2;
+};
+static_assert(sizeof(TileRec) == 48, "TileRec layout");
+
+template <bool NODE>
+static __global__ __launch_bounds__(LUT_BLOCK) void tile_table_kernel(const mesh_segment* __restrict__ segs,
+                                                                     const int32_t* __restrict__ lut, int64_t n,
+                                                                     int64_t tile, TileRec* __restrict__ recs,
+                                                                     int64_t n_tiles) {
+    constexpr int FIELD = NODE ? (int)offsetof(mesh_segment, pair_off) : (int)offsetof(mesh_segment, slot_off);
+    const int64_t t = (int64_t)blockIdx.x * LUT_BLOCK + threadIdx.x;
+    if (t >= n_tiles) return;
+    const int64_t base = t * tile, last = tmin<int64_t>(base + tile, n) - 1;
+    const int m0 = lut_segment<FIELD>(segs, lut, base), m1 = lut_segment<FIELD>(segs, lut, last);
+    const mesh_segment& sg = segs[m0];
+    const int npe = nodes_per_elem(sg.etype);
+    const int per = NODE ? 2 * edges_per_elem(sg.etype) : npe;  // keys per element
+    const int64_t off = NODE ? sg.pair_off : sg.slot_off;
+    TileRec r{};
+    r.etype = -1;
+    if (m0 == m1 && per > 0 && base >= off && last < off + per * sg.n_elem) {
+        const uint32_t e0 = (uint32_t)((base - off) / per), e1 = (uint32_t)((last - off) / per);
+        r.etype = sg.etype;
+        r.n_vert = sg.n_vert;
+        r.vert_off = sg.vert_off;
+        r.e0 = e0;
+        r.cnt = (int32_t)(e1 - e0 + 1u) * npe;
+        r.off = off;
+        r.ids = sg.conn_off + (int64_t)e0 * npe;
+    }
+    recs[t] = r;
+}
+
 // Element, edge nodes and direction of local pair index loc of a mesh of
 // type ET (constant divisors).
 template <int ET>
@@ -81,6 +125,7 @@ struct BatchNodePairSrc {
     const int32_t* __restrict__ conn;
     const mesh_segment* __restrict__ segs;
     const int32_t* __restrict__ lut;
+    const TileRec* __restrict__ tiles;  // built for the tile size of the launch
     uint32_t lo_bits;
     static constexpr bool kSkipNone = false;
 
@@ -127,39 +172,31 @@ struct BatchNodePairSrc {
     __device__ __forceinline__ void stage(int64_t tile_base, int64_t n, int32_t* s, int tid) const {
         static_assert(stage_words<TILE>() <= 2 * TILE, "staged ids fit the key staging area");
         constexpr int PER = (stage_words<TILE>() - STAGE_HDR + BLOCK - 1) / BLOCK;
-        const int64_t last = tmin<int64_t>(tile_base + TILE, n) - 1;
-        const int m0 = lut_segment<offsetof(mesh_segment, pair_off)>(segs, lut, tile_base);
-        const int m1 = lut_segment<offsetof(mesh_segment, pair_off)>(segs, lut, last);
-        const mesh_segment& sg = segs[m0];
-        const int kpe = 2 * edges_per_elem(sg.etype), npe = nodes_per_elem(sg.etype);
-        const bool one = m0 == m1 && kpe > 0 && tile_base >= sg.pair_off && last < sg.pair_off + kpe * sg.n_elem;
-        if (!one) {
+        const TileRec r = tiles[tile_base / TILE];
+        if (r.etype < 0) {
             if (tid == 0) s[0] = 0;
             return;
         }
-        const uint32_t e0 = (uint32_t)((tile_base - sg.pair_off) / kpe);
-        const uint32_t e1 = (uint32_t)((last - sg.pair_off) / kpe);
-        const int cnt = (int)(e1 - e0 + 1u) * npe;  // <= (TILE / 6 + 2) * 3 words
-        const int32_t* src = conn + sg.conn_off + (int64_t)e0 * npe;
+        const int32_t* src = conn + r.ids;  // r.cnt <= (TILE / 6 + 2) * 3 words
         int32_t* ids = s + STAGE_HDR;
         int32_t v[PER];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int i = q * BLOCK + tid;
-            v[q] = i < cnt ? src[i] : 0;
+            v[q] = i < r.cnt ? src[i] : 0;
         }
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int i = q * BLOCK + tid;
-            if (i < cnt) ids[i] = v[q];
+            if (i < r.cnt) ids[i] = v[q];
         }
         if (tid == 0) {
             s[0] = 1;
-            s[1] = sg.etype;
-            s[2] = sg.n_vert;
-            s[3] = sg.vert_off;
-            s[4] = (int32_t)e0;
-            *(int64_t*)(s + 6) = sg.pair_off;
+            s[1] = r.etype;
+            s[2] = r.n_vert;
+            s[3] = r.vert_off;
+            s[4] = (int32_t)r.e0;
+            *(int64_t*)(s + 6) = r.off;
         }
     }
 
@@ -199,6 +236,7 @@ struct BatchElemPairSrc {
     const int32_t* __restrict__ conn;
     const mesh_segment* __restrict__ segs;
     const int32_t* __restrict__ lut;
+    const TileRec* __restrict__ tiles;  // built for the tile size of the launch
     static constexpr bool kSkipNone = true;
 
     __device__ __forceinline__ uint64_t make(int64_t s, bool* bad) const {
@@ -239,39 +277,31 @@ struct BatchElemPairSrc {
     __device__ __forceinline__ void stage(int64_t tile_base, int64_t n, int32_t* st, int tid) const {
         static_assert(stage_words<TILE>() <= 2 * TILE, "staged ids fit the key staging area");
         constexpr int PER = (stage_words<TILE>() - STAGE_HDR + BLOCK - 1) / BLOCK;
-        const int64_t last = tmin<int64_t>(tile_base + TILE, n) - 1;
-        const int m0 = lut_segment<offsetof(mesh_segment, slot_off)>(segs, lut, tile_base);
-        const int m1 = lut_segment<offsetof(mesh_segment, slot_off)>(segs, lut, last);
-        const mesh_segment& sg = segs[m0];
-        const int npe = nodes_per_elem(sg.etype);
-        const bool one = m0 == m1 && npe > 0 && tile_base >= sg.slot_off && last < sg.slot_off + npe * sg.n_elem;
-        if (!one) {
+        const TileRec r = tiles[tile_base / TILE];
+        if (r.etype < 0) {
             if (tid == 0) st[0] = 0;
             return;
         }
-        const uint32_t e0 = (uint32_t)((tile_base - sg.slot_off) / npe);
-        const uint32_t e1 = (uint32_t)((last - sg.slot_off) / npe);
-        const int cnt = (int)(e1 - e0 + 1u) * npe;  // <= TILE + 2 * npe words
-        const int32_t* src = conn + sg.conn_off + (int64_t)e0 * npe;
+        const int32_t* src = conn + r.ids;  // r.cnt <= TILE + 2 * npe words
         int32_t* ids = st + STAGE_HDR;
         int32_t v[PER];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int i = q * BLOCK + tid;
-            v[q] = i < cnt ? src[i] : 0;
+            v[q] = i < r.cnt ? src[i] : 0;
         }
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int i = q * BLOCK + tid;
-            if (i < cnt) ids[i] = v[q];
+            if (i < r.cnt) ids[i] = v[q];
         }
         if (tid == 0) {
             st[0] = 1;
-            st[1] = npe;
-            st[2] = sg.n_vert;
-            st[3] = sg.vert_off;
-            st[4] = (int32_t)e0;
-            *(int64_t*)(st + 6) = sg.slot_off;
+            st[1] = nodes_per_elem(r.etype);
+            st[2] = r.n_vert;
+            st[3] = r.vert_off;
+            st[4] = (int32_t)r.e0;
+            *(int64_t*)(st + 6) = r.off;
         }
     }
 
@@ -300,13 +330,13 @@ struct BatchElemPairSrc {
 
 // Digit histograms (8-bit digits from bit shift0) of the keys a batch source
 // generates, the number of participating keys, and the data-error flag.  A
-// block takes tiles of BH_BLOCK x BH_ITEMS consecutive keys, staged as in the
-// first radix pass.
-template <class Src>
+// block takes tiles of BH_BLOCK x ITEMS consecutive keys (the tile size of
+// the radix passes, so both use one tile table), staged as in the first pass.
+template <class Src, int ITEMS>
 __global__ __launch_bounds__(BH_BLOCK) void batch_hist_kernel(Src src, int64_t n, uint32_t shift0, int n_pass,
                                                              uint32_t last_bits, uint32_t* __restrict__ hist,
                                                              uint32_t* count, uint32_t* err) {
-    constexpr int TILE = BH_BLOCK * BH_ITEMS;
+    constexpr int TILE = BH_BLOCK * ITEMS;
     __shared__ __align__(16) int32_t s_stage[Src::template stage_words<TILE>()];  // header holds an int64
     __shared__ uint32_t s_hist[B_MAX_PASS * RADIX];
     __shared__ uint32_t s_keys;
@@ -320,7 +350,7 @@ __global__ __launch_bounds__(BH_BLOCK) void batch_hist_kernel(Src src, int64_t n
         src.template stage<BH_BLOCK, TILE>(t0, n, s_stage, tid);
         __syncthreads();
 #pragma unroll 4
-        for (int j = 0; j < BH_ITEMS; ++j) {
+        for (int j = 0; j < ITEMS; ++j) {
             const int64_t i = t0 + (int64_t)j * BH_BLOCK + tid;
             if (i >= n) break;
             bool bad = false;
@@ -387,6 +417,8 @@ bool plan_batch(int64_t n_keys, uint32_t digit_bits, int32_t rows_vert, BatchPla
     p->n_lut = n_keys > 0 ? ((n_keys - 1) >> SEG_LUT_SHIFT) + 2 : 0;
     p->off_lut = off;
     off += align_up((size_t)p->n_lut * sizeof(int32_t));
+    p->off_tiles = off;  // room for the smallest tile shape
+    off += align_up((size_t)p->n_tiles * sizeof(TileRec));
     p->total = off;
     return true;
 }
@@ -408,7 +440,10 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
     const int shape = radix_shape();
     const bool node = !Src::kSkipNone;
 
-    const int grid = (int)tmin<int64_t>(ceil_div(p.n_keys, (int64_t)BH_BLOCK * BH_ITEMS), BH_GRID_MAX);
+    const RadixShape sh = RADIX_SHAPES[shape >= 0 && shape < N_RADIX_SHAPES ? shape : DEFAULT_RADIX_SHAPE];
+    const int64_t tile = (int64_t)sh.block * sh.items;  // the tile launch_radix_pass uses for `shape`
+    const int64_t n_tiles = ceil_div(p.n_keys, tile);
+    const int grid = (int)tmin<int64_t>(n_tiles, BH_GRID_MAX);
     const uint32_t last_bits = p.digit_bits - (uint32_t)(p.n_pass - 1) * RBITS;
     const dim3 lut_grid((unsigned)ceil_div(p.n_lut, LUT_BLOCK));
     hipError_t e =
@@ -417,8 +452,22 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
              : launch("batch_segment_lut", segment_lut_kernel<offsetof(mesh_segment, slot_off)>, lut_grid,
                       dim3(LUT_BLOCK), s, segs, n_mesh, p.n_keys, (int32_t*)(w + p.off_lut), p.n_lut);
     if (e == hipSuccess)
-        e = launch(node ? "batch_node_hist" : "batch_elem_hist", batch_hist_kernel<Src>, dim3(grid), dim3(BH_BLOCK),
-                   s, src, p.n_keys, shift0, p.n_pass, last_bits, hist, count, err);
+        e = launch("batch_tile_table", tile_table_kernel<!Src::kSkipNone>, dim3((unsigned)ceil_div(n_tiles, LUT_BLOCK)),
+                   dim3(LUT_BLOCK), s, segs, (const int32_t*)(w + p.off_lut), p.n_keys, tile, (TileRec*)(w + p.off_tiles),
+                   n_tiles);
+    const char* hname = node ? "batch_node_hist" : "batch_elem_hist";
+    if (e == hipSuccess) {
+        const dim3 g(grid), b(BH_BLOCK);
+        if (tile == 6144)
+            e = launch(hname, batch_hist_kernel<Src, 12>, g, b, s, src, p.n_keys, shift0, p.n_pass, last_bits, hist,
+                       count, err);
+        else if (tile == 12288)
+            e = launch(hname, batch_hist_kernel<Src, 24>, g, b, s, src, p.n_keys, shift0, p.n_pass, last_bits, hist,
+                       count, err);
+        else
+            e = launch(hname, batch_hist_kernel<Src, 16>, g, b, s, src, p.n_keys, shift0, p.n_pass, last_bits, hist,
+                       count, err);
+    }
     for (int q = 0; q < p.n_pass && e == hipSuccess; ++q) {
         const uint32_t shift = shift0 + (uint32_t)q * RBITS;
         const uint32_t bits = tmin<uint32_t>(RBITS, p.digit_bits - (uint32_t)q * RBITS);
@@ -454,6 +503,7 @@ hipError_t run_batch_node(const BatchPlan& p, const int32_t* conn, const mesh_se
     if (e != hipSuccess) return e;
     if (p.n_keys == 0 || n_mesh == 0) return fill_i32(row_ptr, (int64_t)total_vert + 1, 0, s);
     const int32_t* lut = (const int32_t*)((char*)ws + p.off_lut);
+    const TileRec* tiles = (const TileRec*)((char*)ws + p.off_tiles);
     if (node_sort_mode() == 1) {
         // vertex-rows: radix passes over the global-vertex bits only (the
         // all-ones value stays free for KEY_NONE), then per-row dedup
@@ -462,10 +512,10 @@ hipError_t run_batch_node(const BatchPlan& p, const int32_t* conn, const mesh_se
         q.n_pass = (int)ceil_div(q.digit_bits, RBITS);
         e = fill_i32((int32_t*)((char*)ws + p.off_deg), total_vert, 0, s);
         if (e != hipSuccess) return e;
-        return batch_pipeline(q, "node", BatchNodePairSrc{conn, segs, lut, lo_bits}, lo_bits, lo_bits, total_vert,
+        return batch_pipeline(q, "node", BatchNodePairSrc{conn, segs, lut, tiles, lo_bits}, lo_bits, lo_bits, total_vert,
                               row_ptr, cols, cols_cap, (char*)ws, segs, n_mesh, true, s);
     }
-    return batch_pipeline(p, "node", BatchNodePairSrc{conn, segs, lut, lo_bits}, 0u, lo_bits, total_vert, row_ptr,
+    return batch_pipeline(p, "node", BatchNodePairSrc{conn, segs, lut, tiles, lo_bits}, 0u, lo_bits, total_vert, row_ptr,
                           cols, cols_cap, (char*)ws, segs, n_mesh, false, s);
 }
 
@@ -476,7 +526,8 @@ hipError_t run_batch_elem(const BatchPlan& p, const int32_t* conn, const mesh_se
     if (e != hipSuccess) return e;
     if (p.n_keys == 0 || n_mesh == 0) return fill_i32(row_ptr, (int64_t)total_vert + 1, 0, s);
     const int32_t* lut = (const int32_t*)((char*)ws + p.off_lut);
-    return batch_pipeline(p, "elem", BatchElemPairSrc{conn, segs, lut}, 32u, 32u, total_vert, row_ptr, cols,
+    const TileRec* tiles = (const TileRec*)((char*)ws + p.off_tiles);
+    return batch_pipeline(p, "elem", BatchElemPairSrc{conn, segs, lut, tiles}, 32u, 32u, total_vert, row_ptr, cols,
                           cols_cap, (char*)ws, segs, n_mesh, false, s);
 }
 

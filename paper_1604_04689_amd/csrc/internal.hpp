@@ -64,6 +64,7 @@ struct BatchPlan {
     size_t off_hist = 0, off_ulb = 0, off_lb0 = 0, off_lb1 = 0, off_keys0 = 0, off_keys1 = 0;
     int64_t n_lut = 0;      // segment lookup entries (one per 2^SEG_LUT_SHIFT keys, plus one)
     size_t off_lut = 0;
+    size_t off_tiles = 0;   // one record per radix tile
     int32_t rows_vert = 0;  // node relation: vertices of the vertex-rows stage (0: no such stage)
     int64_t long_cap = 0;
     size_t off_deg = 0, off_src = 0, off_long = 0;
