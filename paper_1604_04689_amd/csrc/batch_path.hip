@@ -20,6 +20,7 @@
 namespace mnb {
 
 constexpr int BH_BLOCK = 512;
+constexpr int BH_COPIES = 8;  // per-lane copies of each histogram counter
 constexpr int BH_GRID_MAX = 1024;
 constexpr int B_MAX_PASS = 8;
 constexpr int TK_BCSR = 15;
@@ -334,15 +335,20 @@ struct BatchElemPairSrc {
 // the radix passes, so both use one tile table), staged as in the first pass.
 template <class Src, int ITEMS>
 __global__ __launch_bounds__(BH_BLOCK) void batch_hist_kernel(Src src, int64_t n, uint32_t shift0, int n_pass,
-                                                             uint32_t last_bits, uint32_t* __restrict__ hist,
-                                                             uint32_t* count, uint32_t* err) {
+                                                             uint32_t last_bits, uint32_t copies,
+                                                             uint32_t* __restrict__ hist, uint32_t* count,
+                                                             uint32_t* err) {
     constexpr int TILE = BH_BLOCK * ITEMS;
     __shared__ __align__(16) int32_t s_stage[Src::template stage_words<TILE>()];  // header holds an int64
-    __shared__ uint32_t s_hist[B_MAX_PASS * RADIX];
+    // `copies` (a power of two) copies of every counter, picked by lane: the
+    // keys of one small mesh share their high digits, and lanes adding to one
+    // address serialise.  Dynamic LDS of n_pass * RADIX * copies words.
+    extern __shared__ uint32_t s_hist[];
     __shared__ uint32_t s_keys;
     const int tid = threadIdx.x;
+    const uint32_t copy = (uint32_t)tid & (copies - 1);
     if (tid == 0) s_keys = 0;
-    for (int i = tid; i < n_pass * RADIX; i += BH_BLOCK) s_hist[i] = 0;
+    for (int i = tid; i < n_pass * RADIX * (int)copies; i += BH_BLOCK) s_hist[i] = 0;
     bool bad_seen = false;
     uint32_t mine = 0;
     for (int64_t t0 = (int64_t)blockIdx.x * TILE; t0 < n; t0 += (int64_t)gridDim.x * TILE) {
@@ -360,7 +366,8 @@ __global__ __launch_bounds__(BH_BLOCK) void batch_hist_kernel(Src src, int64_t n
             ++mine;
             for (int p = 0; p < n_pass; ++p) {
                 const uint32_t mask = p == n_pass - 1 ? (1u << last_bits) - 1 : RADIX - 1;
-                atomicAdd(&s_hist[p * RADIX + ((uint32_t)(k >> (shift0 + p * RBITS)) & mask)], 1u);
+                const uint32_t d = p * RADIX + ((uint32_t)(k >> (shift0 + p * RBITS)) & mask);
+                atomicAdd(&s_hist[d * copies + copy], 1u);
             }
         }
     }
@@ -368,8 +375,11 @@ __global__ __launch_bounds__(BH_BLOCK) void batch_hist_kernel(Src src, int64_t n
     if (mine) atomicAdd(&s_keys, mine);
     __syncthreads();
     if (tid == 0 && s_keys) atomicAdd(count, s_keys);
-    for (int i = tid; i < n_pass * RADIX; i += BH_BLOCK)
-        if (s_hist[i]) atomicAdd(&hist[i], s_hist[i]);
+    for (int i = tid; i < n_pass * RADIX; i += BH_BLOCK) {
+        uint32_t v = 0;
+        for (uint32_t c = 0; c < copies; ++c) v += s_hist[i * copies + c];
+        if (v) atomicAdd(&hist[i], v);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -458,15 +468,18 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
     const char* hname = node ? "batch_node_hist" : "batch_elem_hist";
     if (e == hipSuccess) {
         const dim3 g(grid), b(BH_BLOCK);
+        // at most 32 KB of counters: 8 copies up to 4 passes, 4 beyond
+        const uint32_t copies = p.n_pass <= 4 ? BH_COPIES : BH_COPIES / 2;
+        const size_t shm = (size_t)p.n_pass * RADIX * copies * sizeof(uint32_t);
         if (tile == 6144)
-            e = launch(hname, batch_hist_kernel<Src, 12>, g, b, s, src, p.n_keys, shift0, p.n_pass, last_bits, hist,
-                       count, err);
+            e = launch_shm(hname, batch_hist_kernel<Src, 12>, g, b, shm, s, src, p.n_keys, shift0, p.n_pass, last_bits,
+                           copies, hist, count, err);
         else if (tile == 12288)
-            e = launch(hname, batch_hist_kernel<Src, 24>, g, b, s, src, p.n_keys, shift0, p.n_pass, last_bits, hist,
-                       count, err);
+            e = launch_shm(hname, batch_hist_kernel<Src, 24>, g, b, shm, s, src, p.n_keys, shift0, p.n_pass, last_bits,
+                           copies, hist, count, err);
         else
-            e = launch(hname, batch_hist_kernel<Src, 16>, g, b, s, src, p.n_keys, shift0, p.n_pass, last_bits, hist,
-                       count, err);
+            e = launch_shm(hname, batch_hist_kernel<Src, 16>, g, b, shm, s, src, p.n_keys, shift0, p.n_pass, last_bits,
+                           copies, hist, count, err);
     }
     for (int q = 0; q < p.n_pass && e == hipSuccess; ++q) {
         const uint32_t shift = shift0 + (uint32_t)q * RBITS;

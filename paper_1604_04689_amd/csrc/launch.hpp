@@ -21,8 +21,19 @@ bool timing_begin(hipEvent_t* start, hipEvent_t* stop);
 // Records that the pair brackets one launch of kernel `name`.
 void timing_commit(const char* name, hipEvent_t start, hipEvent_t stop);
 
+// As launch(), with `shm` bytes of dynamic LDS.
+template <typename... P, typename... A>
+hipError_t launch_shm(const char* name, void (*kernel)(P...), dim3 grid, dim3 block, size_t shm, hipStream_t stream,
+                      A&&... a);
+
 template <typename... P, typename... A>
 hipError_t launch(const char* name, void (*kernel)(P...), dim3 grid, dim3 block, hipStream_t stream, A&&... a) {
+    return launch_shm(name, kernel, grid, block, 0, stream, std::forward<A>(a)...);
+}
+
+template <typename... P, typename... A>
+hipError_t launch_shm(const char* name, void (*kernel)(P...), dim3 grid, dim3 block, size_t shm, hipStream_t stream,
+                      A&&... a) {
     static_assert(sizeof...(P) == sizeof...(A), "argument count");
     std::tuple<P...> vals(static_cast<P>(std::forward<A>(a))...);
     void* args[sizeof...(P) > 0 ? sizeof...(P) : 1];
@@ -38,11 +49,11 @@ hipError_t launch(const char* name, void (*kernel)(P...), dim3 grid, dim3 block,
     // launches recorded into a graph run untimed
     if (timing_enabled() && hipStreamIsCapturing(stream, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone &&
         timing_begin(&e0, &e1)) {
-        hipError_t e = hipExtLaunchKernel((const void*)kernel, grid, block, args, 0, stream, e0, e1, 0);
+        hipError_t e = hipExtLaunchKernel((const void*)kernel, grid, block, args, shm, stream, e0, e1, 0);
         if (e == hipSuccess) timing_commit(name, e0, e1);
         return e;
     }
-    return hipLaunchKernel((const void*)kernel, grid, block, args, 0, stream);
+    return hipLaunchKernel((const void*)kernel, grid, block, args, shm, stream);
 }
 
 }  // namespace mnb
