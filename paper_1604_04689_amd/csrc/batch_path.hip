@@ -201,34 +201,50 @@ struct BatchNodePairSrc {
         }
     }
 
-    __device__ __forceinline__ uint64_t load_staged(int64_t i, int64_t tile_base, const int32_t* s, bool* bad) const {
-        if (s[0] == 0) return make(i, bad);
-        const int32_t et = s[1], nv = s[2];
-        const uint32_t loc = (uint32_t)(i - *(const int64_t*)(s + 6));
+    // the tile's header, read once (wave-uniform values)
+    struct Header {
+        int32_t etype, n_vert, vert_off;
+        uint32_t e0;
+        int64_t off;
+    };
+    __device__ __forceinline__ bool staged(const int32_t* s) const {
+        return __builtin_amdgcn_readfirstlane(s[0]) != 0;
+    }
+    __device__ __forceinline__ Header header(const int32_t* s) const {
+        const int64_t off = *(const int64_t*)(s + 6);
+        return {__builtin_amdgcn_readfirstlane(s[1]), __builtin_amdgcn_readfirstlane(s[2]),
+                __builtin_amdgcn_readfirstlane(s[3]), (uint32_t)__builtin_amdgcn_readfirstlane(s[4]),
+                (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(off >> 32)) << 32) |
+                          (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)off))};
+    }
+    __device__ __forceinline__ uint64_t load_staged(const Header& h, int64_t i, int64_t tile_base, const int32_t* s,
+                                                    bool* bad) const {
+        const uint32_t loc = (uint32_t)(i - h.off);
         uint32_t e;
         int pa, pb, dir, npe;
-        if (et == TRI3) {
+        if (h.etype == TRI3) {
             pair_of<TRI3>(loc, &e, &pa, &pb, &dir);
             npe = 3;
-        } else if (et == TET4) {
+        } else if (h.etype == TET4) {
             pair_of<TET4>(loc, &e, &pa, &pb, &dir);
             npe = 4;
         } else {
             pair_of<HEX8>(loc, &e, &pa, &pb, &dir);
             npe = 8;
         }
-        const int32_t* el = s + STAGE_HDR + (e - (uint32_t)s[4]) * npe;
+        const int32_t* el = s + STAGE_HDR + (e - h.e0) * npe;
         const int32_t x = el[pa], y = el[pb];
         const int32_t u = dir ? y : x;
         const int32_t w = dir ? x : y;
-        const bool ok = (uint32_t)u < (uint32_t)nv && (uint32_t)w < (uint32_t)nv;
+        const bool ok = (uint32_t)u < (uint32_t)h.n_vert && (uint32_t)w < (uint32_t)h.n_vert;
         *bad = !ok;
         if (!ok || u == w) return KEY_NONE;
-        return ((uint64_t)(uint32_t)(s[3] + u) << lo_bits) | (uint64_t)(uint32_t)w;
+        return ((uint64_t)(uint32_t)(h.vert_off + u) << lo_bits) | (uint64_t)(uint32_t)w;
     }
-    __device__ __forceinline__ uint64_t load_staged(int64_t i, int64_t tile_base, const int32_t* s) const {
+    __device__ __forceinline__ uint64_t load_staged(const Header& h, int64_t i, int64_t tile_base,
+                                                    const int32_t* s) const {
         bool bad;
-        return load_staged(i, tile_base, s, &bad);
+        return load_staged(h, i, tile_base, s, &bad);
     }
 };
 
@@ -306,26 +322,42 @@ struct BatchElemPairSrc {
         }
     }
 
-    __device__ __forceinline__ uint64_t load_staged(int64_t s, int64_t tile_base, const int32_t* st, bool* bad) const {
-        if (st[0] == 0) return make(s, bad);
-        const int npe = st[1];
-        const uint32_t loc = (uint32_t)(s - *(const int64_t*)(st + 6));
+    struct Header {
+        int32_t npe, n_vert, vert_off;
+        uint32_t e0;
+        int64_t off;
+    };
+    __device__ __forceinline__ bool staged(const int32_t* st) const {
+        return __builtin_amdgcn_readfirstlane(st[0]) != 0;
+    }
+    __device__ __forceinline__ Header header(const int32_t* st) const {
+        const int64_t off = *(const int64_t*)(st + 6);
+        return {__builtin_amdgcn_readfirstlane(st[1]), __builtin_amdgcn_readfirstlane(st[2]),
+                __builtin_amdgcn_readfirstlane(st[3]), (uint32_t)__builtin_amdgcn_readfirstlane(st[4]),
+                (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(off >> 32)) << 32) |
+                          (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)off))};
+    }
+    __device__ __forceinline__ uint64_t load_staged(const Header& h, int64_t s, int64_t tile_base, const int32_t* st,
+                                                    bool* bad) const {
+        const int npe = h.npe;
+        const uint32_t loc = (uint32_t)(s - h.off);
         const uint32_t e = npe == 3 ? loc / 3u : npe == 4 ? loc >> 2 : loc >> 3;
         const int j = (int)(loc - e * (uint32_t)npe);
-        const int32_t* el = st + STAGE_HDR + (e - (uint32_t)st[4]) * npe;
+        const int32_t* el = st + STAGE_HDR + (e - h.e0) * npe;
         const int32_t v = el[j];
-        if ((uint32_t)v >= (uint32_t)st[2]) {
+        if ((uint32_t)v >= (uint32_t)h.n_vert) {
             *bad = true;
             return KEY_NONE;
         }
         *bad = false;
         for (int jj = 0; jj < j; ++jj)
             if (el[jj] == v) return KEY_NONE;  // repeated id inside the element
-        return ((uint64_t)(uint32_t)(st[3] + v) << 32) | (uint64_t)e;
+        return ((uint64_t)(uint32_t)(h.vert_off + v) << 32) | (uint64_t)e;
     }
-    __device__ __forceinline__ uint64_t load_staged(int64_t s, int64_t tile_base, const int32_t* st) const {
+    __device__ __forceinline__ uint64_t load_staged(const Header& h, int64_t s, int64_t tile_base,
+                                                    const int32_t* st) const {
         bool bad;
-        return load_staged(s, tile_base, st, &bad);
+        return load_staged(h, s, tile_base, st, &bad);
     }
 };
 
@@ -355,12 +387,14 @@ __global__ __launch_bounds__(BH_BLOCK) void batch_hist_kernel(Src src, int64_t n
         __syncthreads();  // the previous tile's staged ids are consumed
         src.template stage<BH_BLOCK, TILE>(t0, n, s_stage, tid);
         __syncthreads();
+        const bool staged = src.staged(s_stage);
+        const auto hdr = src.header(s_stage);  // meaningful only when staged
 #pragma unroll 4
         for (int j = 0; j < ITEMS; ++j) {
             const int64_t i = t0 + (int64_t)j * BH_BLOCK + tid;
             if (i >= n) break;
             bool bad = false;
-            const uint64_t k = src.load_staged(i, t0, s_stage, &bad);
+            const uint64_t k = staged ? src.load_staged(hdr, i, t0, s_stage, &bad) : src.make(i, &bad);
             bad_seen |= bad;
             if (Src::kSkipNone && k == KEY_NONE) continue;
             ++mine;

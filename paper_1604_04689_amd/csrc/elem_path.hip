@@ -79,7 +79,10 @@ struct ElemPairSrc {
             if (i < cnt) s[i] = v[q];
         }
     }
-    __device__ __forceinline__ uint64_t load_staged(int64_t s, int64_t tile_base, const int32_t* st) const {
+    struct Header {};
+    __device__ __forceinline__ bool staged(const int32_t*) const { return true; }
+    __device__ __forceinline__ Header header(const int32_t*) const { return {}; }
+    __device__ __forceinline__ uint64_t load_staged(Header, int64_t s, int64_t tile_base, const int32_t* st) const {
         const uint32_t ss = (uint32_t)s;
         const uint32_t e = ss / NPE;
         const int32_t* el = st + (e - (uint32_t)tile_base / NPE) * NPE;

@@ -96,7 +96,10 @@ struct NodePairSrc {
             if (i < cnt) s[i] = v[q];
         }
     }
-    __device__ __forceinline__ uint64_t load_staged(int64_t i, int64_t tile_base, const int32_t* s) const {
+    struct Header {};
+    __device__ __forceinline__ bool staged(const int32_t*) const { return true; }
+    __device__ __forceinline__ Header header(const int32_t*) const { return {}; }
+    __device__ __forceinline__ uint64_t load_staged(Header, int64_t i, int64_t tile_base, const int32_t* s) const {
         const uint32_t ii = (uint32_t)i;
         const uint32_t e = ii / KPE;
         const uint32_t e0 = (uint32_t)tile_base / KPE;

@@ -33,7 +33,9 @@ struct CountedKeySrc {
 };
 
 // Sources that define kStaged = true copy their tile's inputs into LDS first
-// (stage) and build keys from there (load_staged); see NodePairSrc.
+// (stage); if staged(s) says the tile was staged (the same for the whole
+// block), its keys are built from there with the tile's header read once
+// (header, load_staged), else with load(); see NodePairSrc.
 template <class S, class = void>
 struct is_staged : std::false_type {};
 template <class S>
@@ -114,19 +116,25 @@ __global__ __launch_bounds__(BLOCK) void radix_pass_kernel(Src src, uint64_t* __
     const int64_t limit_n = source_limit(src, n);
     uint64_t key[ITEMS];
     uint32_t valid_bits = 0;
+    bool direct = true;
     if constexpr (is_staged<Src>::value) {
         // the staging area is free until step 4
         int32_t* s_stage = reinterpret_cast<int32_t*>(s_keys);
         src.template stage<BLOCK, TILE>(tile_base, n, s_stage, tid);
         __syncthreads();
+        if (src.staged(s_stage)) {
+            direct = false;
+            const auto hdr = src.header(s_stage);
 #pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const int64_t idx = wbase + j * WAVE;
-            key[j] = idx < n ? src.load_staged(idx, tile_base, s_stage) : KEY_NONE;
-            const bool valid = idx < limit_n && !(Src::kSkipNone && key[j] == KEY_NONE);
-            valid_bits |= (uint32_t)valid << j;
+            for (int j = 0; j < ITEMS; ++j) {
+                const int64_t idx = wbase + j * WAVE;
+                key[j] = idx < n ? src.load_staged(hdr, idx, tile_base, s_stage) : KEY_NONE;
+                const bool valid = idx < limit_n && !(Src::kSkipNone && key[j] == KEY_NONE);
+                valid_bits |= (uint32_t)valid << j;
+            }
         }
-    } else {
+    }
+    if (direct) {
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const int64_t idx = wbase + j * WAVE;
