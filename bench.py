@@ -129,6 +129,38 @@ def time_graph_replays(torch, graphs, builds, stream, steps):
     return sec
 
 
+def time_two_streams(torch, node, elem, conn, stream, steps):
+    """Seconds per step with the two relations on two streams (they are
+    independent, so their radix passes overlap); outputs checked against the
+    sequential ones."""
+    side = torch.cuda.Stream(conn.device)
+    before = [(b.row_ptr.clone(), b.cols.clone()) for b in (node, elem)]
+
+    def step():
+        ev = torch.cuda.Event()
+        ev.record(stream)
+        side.wait_event(ev)
+        node.launch(conn, stream, tuned=True)
+        elem.launch(conn, side, tuned=True)
+        back = torch.cuda.Event()
+        back.record(side)
+        stream.wait_event(back)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    for b, (rp, cols) in zip((node, elem), before):
+        b.check(stream)
+        nnz = int(rp[-1].item())
+        if not (torch.equal(b.row_ptr, rp) and torch.equal(b.cols[:nnz], cols[:nnz])):
+            raise RuntimeError("two-stream step differs from the sequential result")
+    return sec
+
+
 def run_workload(name, steps, warmup, torch, nb):
     log(f"[bench] generating {name} ...")
     t = time.time()
@@ -168,6 +200,7 @@ def run_workload(name, steps, warmup, torch, nb):
     sec = (t1 - t0) / steps
     graph_sec = time_graph_replays(torch, [node.capture(conn, tuned=True), elem.capture(conn, tuned=True)],
                                    [node, elem], stream, steps)
+    two_sec = time_two_streams(torch, node, elem, conn, stream, steps)
     kb = kernel_bytes(m, nnz_node, nnz_elem)
     kernels = {}
     model_total = 0
@@ -193,6 +226,8 @@ def run_workload(name, steps, warmup, torch, nb):
         "ms_per_step": sec * 1e3,
         "elements_per_s": m.n_elem / sec,
         "graph_ms_per_step": graph_sec * 1e3,
+        "two_streams_ms_per_step": two_sec * 1e3,
+        "two_streams_elements_per_s": m.n_elem / two_sec,
         "node_kernel_ms": node_ms, "elem_kernel_ms": elem_ms,
         "kernels": kernels,
         "pipeline_model_bytes": model_total,
@@ -202,6 +237,7 @@ def run_workload(name, steps, warmup, torch, nb):
                        "bytes_per_launch": kb["node_radix"], "GBs": kernels["node_radix"]["GBs"]},
     }
     log(f"[bench] {name}: {sec * 1e3:.3f} ms/step eager, {graph_sec * 1e3:.3f} ms/step graph replay, "
+        f"{two_sec * 1e3:.3f} ms/step on two streams, "
         f"{m.n_elem / sec / 1e9:.3f} G elem/s, "
         f"pipeline {res['pipeline_model_GBs']:.0f} GB/s of model bytes")
     for k, v in kernels.items():
