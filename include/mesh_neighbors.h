@@ -227,16 +227,28 @@ mesh_status mesh_radix_shape_info(int32_t shape, int32_t* block, int32_t* items)
 mesh_status mesh_set_radix_shape(int32_t shape);
 int32_t mesh_get_radix_shape(void);
 
-/* How mesh_node_neighbors (single mesh) orders its keys; results are the same
- * either way.  Process-wide, default MESH_NODE_SORT_FULL_KEY.
+/* How the node relation orders its keys; results are the same either way.
+ * Process-wide, default MESH_NODE_SORT_FULL_KEY.  The batched node entry
+ * points use VERTEX_ROWS when EDGE_ROWS is set.
  *  FULL_KEY:     LSD radix passes over all 2b bits of (u << b) | w, then one
  *                pass drops repeats and writes the CSR.
  *  VERTEX_ROWS:  LSD radix passes over the bits of u only (the paper's sort by
  *                the first array), then each row's neighbor ids are sorted and
  *                deduplicated in LDS (rows over 256 pairs by a block each),
  *                the distinct counts are scanned into row_ptr and the rows
- *                gathered into cols.  Fewer full passes over the keys. */
-typedef enum { MESH_NODE_SORT_FULL_KEY = 0, MESH_NODE_SORT_VERTEX_ROWS = 1 } mesh_node_sort;
+ *                gathered into cols.  Fewer full passes over the keys.
+ *  EDGE_ROWS:    every element edge once, as (min << b) | max, sorted by min
+ *                and deduplicated per row as in VERTEX_ROWS: each vertex's
+ *                higher neighbours and the unique edges; those edges
+ *                transposed to (max << b) | min and sorted by max give each
+ *                vertex's lower neighbours; a row is its lower neighbours
+ *                followed by its higher ones.  Half the keys of VERTEX_ROWS in
+ *                the first sort. */
+typedef enum {
+    MESH_NODE_SORT_FULL_KEY = 0,
+    MESH_NODE_SORT_VERTEX_ROWS = 1,
+    MESH_NODE_SORT_EDGE_ROWS = 2
+} mesh_node_sort;
 mesh_status mesh_set_node_sort(int32_t mode);
 int32_t mesh_get_node_sort(void);
 

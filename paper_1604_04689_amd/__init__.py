@@ -9,4 +9,4 @@ from .binding import (HEX8, TET4, TRI3, MeshError, NeighborBuild, Status, elem_n
                       lib, node_neighbors, query_elem, query_node, status_string, timing_enable,
                       timing_read, radix_shapes, set_radix_shape, get_radix_shape,
                       BatchBuild, segment_table, concat_conn, set_node_sort, get_node_sort,
-                      NODE_SORT_FULL_KEY, NODE_SORT_VERTEX_ROWS, Graph)
+                      NODE_SORT_FULL_KEY, NODE_SORT_VERTEX_ROWS, NODE_SORT_EDGE_ROWS, Graph)

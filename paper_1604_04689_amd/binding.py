@@ -123,11 +123,12 @@ def get_radix_shape() -> int:
     return int(lib().mesh_get_radix_shape())
 
 
-NODE_SORT_FULL_KEY, NODE_SORT_VERTEX_ROWS = 0, 1
+NODE_SORT_FULL_KEY, NODE_SORT_VERTEX_ROWS, NODE_SORT_EDGE_ROWS = 0, 1, 2
 
 
 def set_node_sort(mode: int):
-    """Select the single-mesh node algorithm (results are identical)."""
+    """Select the node algorithm (results are identical; batches use vertex-rows
+    when edge-rows is set)."""
     st = lib().mesh_set_node_sort(int(mode))
     if st != Status.OK:
         raise MeshError(st, "mesh_set_node_sort")

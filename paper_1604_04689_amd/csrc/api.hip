@@ -213,7 +213,8 @@ mesh_status mesh_set_radix_shape(int32_t shape) {
 int32_t mesh_get_radix_shape(void) { return g_radix_shape.load(std::memory_order_relaxed); }
 
 mesh_status mesh_set_node_sort(int32_t mode) {
-    if (mode != MESH_NODE_SORT_FULL_KEY && mode != MESH_NODE_SORT_VERTEX_ROWS) return MESH_ERR_INVALID_ARG;
+    if (mode != MESH_NODE_SORT_FULL_KEY && mode != MESH_NODE_SORT_VERTEX_ROWS && mode != MESH_NODE_SORT_EDGE_ROWS)
+        return MESH_ERR_INVALID_ARG;
     g_node_sort.store(mode, std::memory_order_relaxed);
     return MESH_OK;
 }

@@ -551,7 +551,7 @@ hipError_t run_batch_node(const BatchPlan& p, const int32_t* conn, const mesh_se
     if (p.n_keys == 0 || n_mesh == 0) return fill_i32(row_ptr, (int64_t)total_vert + 1, 0, s);
     const int32_t* lut = (const int32_t*)((char*)ws + p.off_lut);
     const TileRec* tiles = (const TileRec*)((char*)ws + p.off_tiles);
-    if (node_sort_mode() == 1) {
+    if (node_sort_mode() != 0) {  // vertex-rows (also when edge-rows is set)
         // vertex-rows: radix passes over the global-vertex bits only (the
         // all-ones value stays free for KEY_NONE), then per-row dedup
         BatchPlan q = p;

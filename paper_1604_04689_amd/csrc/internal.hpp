@@ -28,6 +28,9 @@ struct NodePlan {
     // workspace offsets (bytes)
     size_t off_hist = 0, off_ulb = 0, off_lb0 = 0, off_lb1 = 0, off_keys0 = 0, off_keys1 = 0;
     size_t off_deg = 0, off_src = 0, off_long = 0;
+    int64_t n_edges = 0;      // edge-rows mode: canonical keys (one per element edge)
+    size_t off_hist2 = 0;     // edge-rows mode: digit histograms of the transposed edges
+    size_t off_up = 0, off_low = 0;  // edge-rows mode: starts of higher and lower neighbours
     size_t zero_bytes = 0;    // bytes from 0 cleared at the start of a call
     size_t total = 0;
 };

@@ -18,6 +18,7 @@
 #include "internal.hpp"
 #include "launch.hpp"
 #include "csr.hpp"
+#include "edges.hpp"
 #include "radix.hpp"
 #include "rows.hpp"
 
@@ -50,29 +51,51 @@ __device__ __forceinline__ uint64_t elem_pair_key(const int32_t* el, int r, int3
     return edge ? ((uint64_t)u << b) | (uint64_t)w : KEY_NONE;
 }
 
+// Canonical key of edge k of the element whose ids start at el: the edge once,
+// (min << b) | max, for the edge-rows algorithm.
 template <int ET>
+__device__ __forceinline__ uint64_t elem_canon_key(const int32_t* el, int k, int32_t n_vert, uint32_t b) {
+    int pa, pb;
+    edge_nodes<ET>(k, &pa, &pb);
+    const int32_t x = el[pa], y = el[pb];
+    const bool edge = (uint32_t)x < (uint32_t)n_vert && (uint32_t)y < (uint32_t)n_vert && x != y;
+    const uint32_t lo = (uint32_t)(x < y ? x : y), hi = (uint32_t)(x < y ? y : x);
+    return edge ? ((uint64_t)lo << b) | (uint64_t)hi : KEY_NONE;
+}
+
+// Key i of the node relation: directed pairs (2 per edge), or with CANON the
+// edges once each.
+template <int ET, bool CANON>
+__device__ __forceinline__ uint64_t node_key_at(const int32_t* el, int r, int32_t n_vert, uint32_t b) {
+    if constexpr (CANON) return elem_canon_key<ET>(el, r, n_vert, b);
+    else return elem_pair_key<ET>(el, r, n_vert, b);
+}
+
+template <int ET, bool CANON>
 __device__ __forceinline__ uint64_t node_pair_key(const int32_t* __restrict__ conn, int64_t i, int32_t n_vert,
                                                   uint32_t b) {
-    constexpr uint32_t KPE = 2 * Elem<ET>::NE;
+    constexpr uint32_t KPE = (CANON ? 1 : 2) * Elem<ET>::NE;
     const uint32_t ii = (uint32_t)i;  // pair indices stay below 2^31
     const uint32_t e = ii / KPE;
-    return elem_pair_key<ET>(conn + (size_t)e * Elem<ET>::NPE, (int)(ii - e * KPE), n_vert, b);
+    return node_key_at<ET, CANON>(conn + (size_t)e * Elem<ET>::NPE, (int)(ii - e * KPE), n_vert, b);
 }
 
 // Pair keys of the single-mesh node relation.  A radix tile first copies the
 // connectivity of the elements its pairs come from into LDS with coalesced
 // loads (stage), then builds every key from there (load_staged).
-template <int ET>
+template <int ET, bool CANON = false>
 struct NodePairSrc {
     const int32_t* __restrict__ conn;
     int32_t n_vert;
     uint32_t b;
     static constexpr bool kSkipNone = false;
     static constexpr bool kStaged = true;
-    static constexpr uint32_t KPE = 2 * Elem<ET>::NE;
+    static constexpr uint32_t KPE = (CANON ? 1 : 2) * Elem<ET>::NE;  // keys per element
     static constexpr int NPE = Elem<ET>::NPE;
 
-    __device__ __forceinline__ uint64_t load(int64_t i) const { return node_pair_key<ET>(conn, i, n_vert, b); }
+    __device__ __forceinline__ uint64_t load(int64_t i) const {
+        return node_pair_key<ET, CANON>(conn, i, n_vert, b);
+    }
 
     // ids of the tile's elements to s[0 ..): at most (TILE / KPE + 2) * NPE words
     template <int BLOCK, int TILE>
@@ -103,7 +126,7 @@ struct NodePairSrc {
         const uint32_t ii = (uint32_t)i;
         const uint32_t e = ii / KPE;
         const uint32_t e0 = (uint32_t)tile_base / KPE;
-        return elem_pair_key<ET>(s + (e - e0) * NPE, (int)(ii - e * KPE), n_vert, b);
+        return node_key_at<ET, CANON>(s + (e - e0) * NPE, (int)(ii - e * KPE), n_vert, b);
     }
 };
 
@@ -114,7 +137,7 @@ struct NodePairSrc {
 // flight at once; each block accumulates in LDS and flushes once with global
 // atomics.  Raises ERR_INDEX_RANGE.
 // ---------------------------------------------------------------------------
-template <int ET>
+template <int ET, bool CANON>
 __global__ __launch_bounds__(NH_BLOCK) void node_hist_kernel(const int32_t* __restrict__ conn, int64_t n_elem,
                                                             int32_t n_vert, uint32_t b, uint32_t shift0, int n_pass,
                                                             uint32_t last_bits, uint32_t* __restrict__ hist,
@@ -147,12 +170,14 @@ __global__ __launch_bounds__(NH_BLOCK) void node_hist_kernel(const int32_t* __re
             for (int k = 0; k < E::NE; ++k) {
                 const int32_t x = id[u][E::A[k]], y = id[u][E::B[k]];
                 const bool edge = ok[E::A[k]] && ok[E::B[k]] && x != y;
-                const uint64_t k0 = edge ? ((uint64_t)x << b) | (uint64_t)y : KEY_NONE;
+                const int32_t lo = x < y ? x : y, hi = x < y ? y : x;
+                const uint64_t k0 = !edge ? KEY_NONE
+                                          : CANON ? ((uint64_t)lo << b) | (uint64_t)hi : ((uint64_t)x << b) | (uint64_t)y;
                 const uint64_t k1 = edge ? ((uint64_t)y << b) | (uint64_t)x : KEY_NONE;
                 for (int p = 0; p < n_pass; ++p) {
                     const uint32_t mask = (p == n_pass - 1) ? ((1u << last_bits) - 1) : (RADIX - 1);
                     atomicAdd(&s_hist[p * RADIX + ((uint32_t)(k0 >> (shift0 + p * RBITS)) & mask)], 1u);
-                    atomicAdd(&s_hist[p * RADIX + ((uint32_t)(k1 >> (shift0 + p * RBITS)) & mask)], 1u);
+                    if (!CANON) atomicAdd(&s_hist[p * RADIX + ((uint32_t)(k1 >> (shift0 + p * RBITS)) & mask)], 1u);
                 }
             }
         }
@@ -197,9 +222,12 @@ bool plan_node(int64_t n_elem, int32_t etype, int32_t n_vert, NodePlan* p) {
     p->n_tiles = ceil_div(p->n_pairs, min_radix_tile());  // look-back room for any tile shape
     p->n_utiles = ceil_div(p->n_pairs, UNIQ_TILE);
     p->long_cap = p->n_pairs / (ROW_SHORT + 1) + 1;
+    p->n_edges = (int64_t)ne * n_elem;
     size_t off = HEADER_BYTES;
     p->off_hist = off;
     off += align_up(MAX_PASS * RADIX * sizeof(uint32_t));
+    p->off_hist2 = off;
+    off += align_up(MAX_KH_PASS * RADIX * sizeof(uint32_t));
     p->off_ulb = off;
     off += align_up((size_t)tmin<int64_t>(p->n_utiles + ceil_div((int64_t)n_vert + 1, SCAN_TILE), INT64_MAX) *
                     sizeof(uint64_t));
@@ -218,6 +246,10 @@ bool plan_node(int64_t n_elem, int32_t etype, int32_t n_vert, NodePlan* p) {
     off += align_up((size_t)n_vert * sizeof(int64_t));
     p->off_long = off;
     off += align_up((size_t)p->long_cap * sizeof(int64_t));
+    p->off_up = off;
+    off += align_up(((size_t)n_vert + 1) * sizeof(int32_t));
+    p->off_low = off;
+    off += align_up(((size_t)n_vert + 1) * sizeof(int32_t));
     p->total = off;
     return true;
 }
@@ -233,42 +265,91 @@ static hipError_t node_pipeline(const NodePlan& p, const int32_t* conn, int32_t*
     uint64_t* lb[2] = {(uint64_t*)(w + p.off_lb0), (uint64_t*)(w + p.off_lb1)};
     uint64_t* kb[2] = {(uint64_t*)(w + p.off_keys0), (uint64_t*)(w + p.off_keys1)};
     const int shape = radix_shape();
-    const bool rows = node_sort_mode() == 1;
+    const int mode = node_sort_mode();
+    const bool rows = mode == 1, edges = mode == 2;
 
-    // full-key mode: passes over all 2b key bits; vertex-rows mode: over the
-    // hi_bits above the low b bits
-    const uint32_t shift0 = rows ? p.id_bits : 0;
-    const uint32_t sort_bits = rows ? p.hi_bits : 2 * p.id_bits;
-    const int n_pass = rows ? p.n_pass_rows : p.n_pass;
+    // full-key mode: passes over all 2b key bits; vertex-rows and edge-rows
+    // modes: over the hi_bits above the low b bits.  Edge-rows sorts one
+    // canonical key per element edge instead of two directed pairs.
+    const uint32_t shift0 = rows || edges ? p.id_bits : 0;
+    const uint32_t sort_bits = rows || edges ? p.hi_bits : 2 * p.id_bits;
+    const int n_pass = rows || edges ? p.n_pass_rows : p.n_pass;
+    const int64_t n_keys = edges ? p.n_edges : p.n_pairs;
     const int grid = (int)tmin<int64_t>(ceil_div(p.n_elem, NH_BLOCK), NH_GRID_MAX);
     const uint32_t last_bits = sort_bits - (uint32_t)(n_pass - 1) * RBITS;
     hipError_t e = hipSuccess;
-    if (rows) e = fill_i32((int32_t*)(w + p.off_deg), p.n_vert, 0, s);
+    if (rows || edges) e = fill_i32((int32_t*)(w + p.off_deg), p.n_vert, 0, s);
     if (e == hipSuccess)
-        e = launch("node_hist", node_hist_kernel<ET>, dim3(grid), dim3(NH_BLOCK), s, conn, p.n_elem, p.n_vert,
-                   p.id_bits, shift0, n_pass, last_bits, hist, err);
+        e = edges ? launch("node_hist", node_hist_kernel<ET, true>, dim3(grid), dim3(NH_BLOCK), s, conn, p.n_elem,
+                           p.n_vert, p.id_bits, shift0, n_pass, last_bits, hist, err)
+                  : launch("node_hist", node_hist_kernel<ET, false>, dim3(grid), dim3(NH_BLOCK), s, conn, p.n_elem,
+                           p.n_vert, p.id_bits, shift0, n_pass, last_bits, hist, err);
+    if (e != hipSuccess) return e;
+    if ((rows || edges) && p.n_vert == 0) return fill_i32(row_ptr, 1, 0, s);  // every id is out of range
     for (int pass = 0; pass < n_pass && e == hipSuccess; ++pass) {
         const uint32_t shift = shift0 + (uint32_t)pass * RBITS;
         const uint32_t bits = tmin<uint32_t>(RBITS, sort_bits - (uint32_t)pass * RBITS);
         uint64_t* out = kb[pass & 1];
-        uint64_t* lb_next = pass + 1 < n_pass ? lb[(pass + 1) & 1] : nullptr;
+        // edge-rows: the last pass also clears the look-back slots of the
+        // first pass over the transposed edges
+        uint64_t* lb_next = pass + 1 < n_pass || edges ? lb[(pass + 1) & 1] : nullptr;
         if (pass == 0)
-            e = launch_radix_pass("node_radix_first", shape, NodePairSrc<ET>{conn, p.n_vert, p.id_bits}, out,
-                                  p.n_pairs, shift, bits, hist, lb[0], lb_next, tickets + 0, err, s);
+            e = edges ? launch_radix_pass("node_radix_first", shape, NodePairSrc<ET, true>{conn, p.n_vert, p.id_bits},
+                                          out, n_keys, shift, bits, hist, lb[0], lb_next, tickets + 0, err, s)
+                      : launch_radix_pass("node_radix_first", shape, NodePairSrc<ET, false>{conn, p.n_vert, p.id_bits},
+                                          out, n_keys, shift, bits, hist, lb[0], lb_next, tickets + 0, err, s);
         else
-            e = launch_radix_pass("node_radix", shape, KeyArraySrc{kb[(pass - 1) & 1]}, out, p.n_pairs, shift,
-                                  bits, hist + pass * RADIX, lb[pass & 1], lb_next, tickets + pass, err, s);
+            e = launch_radix_pass("node_radix", shape, KeyArraySrc{kb[(pass - 1) & 1]}, out, n_keys, shift, bits,
+                                  hist + pass * RADIX, lb[pass & 1], lb_next, tickets + pass, err, s);
     }
     if (e != hipSuccess) return e;
     const uint64_t* sorted = kb[(n_pass - 1) & 1];
-    if (!rows)
+    if (!rows && !edges)
         return launch_unique_csr("node_unique_csr", sorted, p.n_pairs, (const uint32_t*)nullptr, p.id_bits,
                                  p.n_vert, cols, cols_capacity, row_ptr, ulb, tickets + (N_TICKETS - 1), err, s);
     // vertex-rows mode: canonical rows into the free key buffer, then scan and gather
-    RowsStage r{sorted, p.n_pairs, p.id_bits, p.n_vert, (int32_t*)(w + p.off_deg), (int64_t*)(w + p.off_src),
+    RowsStage r{sorted, n_keys, p.id_bits, p.n_vert, (int32_t*)(w + p.off_deg), (int64_t*)(w + p.off_src),
                 (int32_t*)kb[n_pass & 1], (int64_t*)(w + p.off_long), p.long_cap, hdr + HDR_LONG_COUNT,
                 ulb, tickets + (N_TICKETS - 2), err};
-    return launch_rows_stage(false, r, row_ptr, cols, cols_capacity, s);
+    if (rows) return launch_rows_stage(false, r, row_ptr, cols, cols_capacity, s);
+
+    // edge-rows mode: the rows stage over the canonical keys gives each
+    // vertex's higher neighbours; their scan is up_ptr (up_ptr[V] = E)
+    int32_t* up_ptr = (int32_t*)(w + p.off_up);
+    int32_t* low_ptr = (int32_t*)(w + p.off_low);
+    e = launch_rows_dedup(r, up_ptr, s);
+    if (e != hipSuccess) return e;
+    // transposed edges (w << b) | v: ping-pong halves of the sorted buffer (free
+    // now); w alone after the row values in the other buffer
+    uint64_t* tk[2] = {kb[(n_pass - 1) & 1], kb[(n_pass - 1) & 1] + p.n_edges};
+    int32_t* up_cols = (int32_t*)kb[n_pass & 1] + p.n_edges;
+    const int32_t* E = up_ptr + p.n_vert;
+    const unsigned vgrid = (unsigned)ceil_div((int64_t)p.n_vert, EDGE_BLOCK);
+    uint32_t* hist2 = (uint32_t*)(w + p.off_hist2);
+    e = launch("node_edge_transpose", edge_transpose_kernel, dim3(vgrid), dim3(EDGE_BLOCK), s, (const int32_t*)up_ptr,
+               (const int32_t*)r.deg, (const int64_t*)r.src, (const int32_t*)r.temp, p.n_vert, p.id_bits, tk[0],
+               up_cols);
+    if (e == hipSuccess)
+        e = launch("node_edge_hist", key_hist_kernel,
+                   dim3((unsigned)tmin<int64_t>(ceil_div(p.n_edges, KH_BLOCK), KH_GRID_MAX)), dim3(KH_BLOCK), s,
+                   (const uint64_t*)tk[0], E, p.id_bits, n_pass, last_bits, hist2);
+    for (int q = 0; q < n_pass && e == hipSuccess; ++q) {
+        const uint32_t shift = p.id_bits + (uint32_t)q * RBITS;
+        const uint32_t bits = tmin<uint32_t>(RBITS, p.hi_bits - (uint32_t)q * RBITS);
+        const int l = (n_pass + q) & 1;  // look-back array, cleared by the previous pass
+        uint64_t* lb_next = q + 1 < n_pass ? lb[l ^ 1] : nullptr;
+        e = launch_radix_pass("node_edge_radix", shape, CountedKeySrc{tk[q & 1], (const uint32_t*)E}, tk[(q + 1) & 1],
+                              p.n_edges, shift, bits, hist2 + q * RADIX, lb[l], lb_next, tickets + 8 + q, err, s);
+    }
+    if (e == hipSuccess)
+        e = launch("node_edge_low_ptr", low_ptr_kernel,
+                   dim3((unsigned)tmin<int64_t>(ceil_div(p.n_edges, LOWPTR_BLOCK) + 1, 4096)), dim3(LOWPTR_BLOCK), s,
+                   (const uint64_t*)tk[n_pass & 1], p.n_edges, E, p.id_bits, p.n_vert, low_ptr);
+    if (e == hipSuccess)
+        e = launch("node_edge_merge", edge_merge_kernel, dim3(vgrid), dim3(EDGE_BLOCK), s, (const int32_t*)low_ptr,
+                   (const int32_t*)up_ptr, (const uint64_t*)tk[n_pass & 1], (const int32_t*)up_cols, p.n_vert,
+                   p.id_bits, row_ptr, cols, cols_capacity, err);
+    return e;
 }
 
 hipError_t run_node(const NodePlan& p, const int32_t* conn, int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,

@@ -114,6 +114,11 @@ __global__ __launch_bounds__(BLOCK) void radix_pass_kernel(Src src, uint64_t* __
     // ---- 1. load (lanes of a wave read 64 consecutive positions), count ------
     const int64_t wbase = tile_base + (int64_t)wid * WAVE * ITEMS + lane;
     const int64_t limit_n = source_limit(src, n);
+    // A tile wholly past the participating keys (a device-side count below n)
+    // has nothing to place, and every later tile is past them too, so no tile
+    // ever looks back at it: it leaves at once (its status and next-pass slots
+    // are never read).
+    if (tile_base >= limit_n) return;
     uint64_t key[ITEMS];
     uint32_t valid_bits = 0;
     bool direct = true;

@@ -413,8 +413,9 @@ struct RowsStage {
     uint32_t* err;
 };
 
-static inline hipError_t launch_rows_stage(bool batch, const RowsStage& r, int32_t* row_ptr, int32_t* cols,
-                                           int64_t cols_cap, hipStream_t s) {
+// Row dedup, long rows, and the scan of the distinct counts into row_ptr
+// (n_vert + 1 entries).
+static inline hipError_t launch_rows_dedup(const RowsStage& r, int32_t* row_ptr, hipStream_t s, bool batch = false) {
     hipError_t e = launch(batch ? "batch_node_row_unique" : "node_row_unique", row_unique_kernel,
                           dim3((unsigned)ceil_div(r.n, ROW_TILE)), dim3(ROW_BLOCK), s, r.sorted, r.n, r.b, r.n_vert,
                           r.deg, r.src, r.temp, r.long_list, r.long_cap, r.long_count, r.err);
@@ -426,6 +427,12 @@ static inline hipError_t launch_rows_stage(bool batch, const RowsStage& r, int32
         e = launch(batch ? "batch_node_row_scan" : "node_row_scan", scan_i32_kernel,
                    dim3((unsigned)ceil_div((int64_t)r.n_vert, SCAN_TILE)), dim3(SCAN_BLOCK), s, (const int32_t*)r.deg,
                    (int64_t)r.n_vert, row_ptr, r.scan_lb, r.scan_ticket, r.err);
+    return e;
+}
+
+static inline hipError_t launch_rows_stage(bool batch, const RowsStage& r, int32_t* row_ptr, int32_t* cols,
+                                           int64_t cols_cap, hipStream_t s) {
+    hipError_t e = launch_rows_dedup(r, row_ptr, s, batch);
     if (e == hipSuccess)
         e = launch(batch ? "batch_node_row_gather" : "node_row_gather", row_gather_kernel,
                    dim3((unsigned)ceil_div((int64_t)r.n_vert, GATHER_BLOCK)), dim3(GATHER_BLOCK), s,

@@ -36,7 +36,7 @@ def _same_size_variants(kind_of_mesh):
     return mg.hex_grid(18, 15), mg.hex_grid(18, 16)
 
 
-@pytest.mark.parametrize("kind,mode", [("node", 0), ("node", 1), ("elem", 0)])
+@pytest.mark.parametrize("kind,mode", [("node", 0), ("node", 1), ("node", 2), ("elem", 0)])
 @pytest.mark.parametrize("family", ["tri", "tet", "hex"])
 def test_single_mesh_graph_replays(oracle_mod, kind, mode, family):
     nb = _nb()

@@ -1,5 +1,7 @@
-"""The vertex-rows node algorithm (sort by the vertex bits only, then per-row
-sort and deduplication) gives bit-identical results to the oracle."""
+"""The row-based node algorithms give bit-identical results to the oracle:
+vertex-rows (sort by the vertex bits only, then per-row sort and
+deduplication) and edge-rows (each edge once by its lower vertex, then
+transposed by its higher vertex)."""
 import numpy as np
 import pytest
 
@@ -12,10 +14,11 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture
-def rows_mode():
+@pytest.fixture(params=[1, 2], ids=["vertex_rows", "edge_rows"])
+def rows_mode(request):
+    """Every test of this file runs under both row-based node algorithms."""
     import paper_1604_04689_amd as nb
-    nb.set_node_sort(nb.NODE_SORT_VERTEX_ROWS)
+    nb.set_node_sort(request.param)
     yield nb
     nb.set_node_sort(nb.NODE_SORT_FULL_KEY)
 
