@@ -60,23 +60,32 @@ def id_bits(n_vert):
     return b
 
 
-def kernel_bytes(m, nnz_node, nnz_elem):
+def kernel_bytes(m, nnz_node, nnz_elem, node_sort):
     """Algorithmic HBM bytes per launch of every kernel of the two pipelines:
     what the kernel must read and write at least once.  P = directed edge
     pairs (2 x edges per element x F), Q = element pairs (nnz of the element
-    relation), conn = 4 x npe x F bytes."""
+    relation), U = node nnz, V = vertices, conn = 4 x npe x F bytes.  The node
+    sort passes move K keys: P, or with the edge-rows algorithm the k x F
+    canonical edge keys; E = U / 2 unique edges."""
     f, v, k, npe = m.n_elem, m.n_vert, EDGES[m.etype], NPE[m.etype]
-    p_pairs, q_pairs = 2 * k * f, nnz_elem
+    p_pairs, q_pairs, u = 2 * k * f, nnz_elem, nnz_node
+    keys = k * f if node_sort == 2 else p_pairs
+    e = u // 2
     conn = 4 * npe * f
     return {
         "node_hist": conn,                                  # read conn
-        "node_radix_first": conn + 8 * p_pairs,             # read conn, write keys
-        "node_radix": 16 * p_pairs,                         # read + write keys
-        "node_unique_csr": 8 * p_pairs + 4 * nnz_node + 4 * (v + 1),
-        "node_row_unique": 8 * p_pairs + 4 * nnz_node + 8 * v,  # read keys, write row values + deg/src
+        "node_radix_first": conn + 8 * keys,                # read conn, write keys
+        "node_radix": 16 * keys,                            # read + write keys
+        "node_unique_csr": 8 * keys + 4 * u + 4 * (v + 1),
+        "node_row_unique": 8 * keys + 4 * (e if node_sort == 2 else u) + 12 * v,  # keys in; row values + deg/src out
         "node_row_scan": 8 * v,
-        "node_row_gather": 8 * nnz_node + 8 * v + 4 * (v + 1),
+        "node_row_gather": 8 * u + 12 * v + 4 * (v + 1),
         "node_long_rows": 0,                                # only rows past the short limit; data-dependent
+        "node_edge_transpose": 4 * e + 12 * v + 12 * e,     # row values, up_ptr/deg/src in; keys + ids out
+        "node_edge_hist": 8 * e,
+        "node_edge_radix": 16 * e,
+        "node_edge_low_ptr": 8 * e + 4 * (v + 1),
+        "node_edge_merge": 12 * e + 8 * (v + 1) + 4 * u + 4 * (v + 1),
         "elem_hist": conn,
         "elem_radix_first": conn + 8 * q_pairs,
         "elem_radix": 16 * q_pairs,
@@ -93,15 +102,16 @@ def radix_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload):
-    """HBM bytes per radix_pass launch from the committed rocprofv3 counter
-    summary, or None if absent or taken on different kernel source."""
+def load_traffic(workload, node_sort):
+    """HBM bytes per node_radix launch from the committed rocprofv3 counter
+    summary, or None if absent, taken on different kernel source, or with a
+    different node algorithm (which changes the keys per launch)."""
     path = os.path.join(PROFILES, f"node_radix_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("source_sha") != radix_source_hash():
+    if t.get("source_sha") != radix_source_hash() or t.get("node_sort") != node_sort:
         return None
     return t.get("bytes_per_launch")
 
@@ -201,7 +211,12 @@ def run_workload(name, steps, warmup, torch, nb):
     graph_sec = time_graph_replays(torch, [node.capture(conn, tuned=True), elem.capture(conn, tuned=True)],
                                    [node, elem], stream, steps)
     two_sec = time_two_streams(torch, node, elem, conn, stream, steps)
-    kb = kernel_bytes(m, nnz_node, nnz_elem)
+    from paper_1604_04689_amd import autotune
+    tuned = {kind: autotune.lookup(kind, m.etype, m.n_elem) for kind in ("node", "elem")}
+    node_sort = tuned["node"]["mode"] if tuned["node"] else 0
+    tuned = {kind: (None if e is None else {"shape": nb.radix_shapes()[e["shape"]], "node_sort": e["mode"]})
+             for kind, e in tuned.items()}
+    kb = kernel_bytes(m, nnz_node, nnz_elem, node_sort)
     kernels = {}
     model_total = 0
     for k, (launches, total_ms, mn, mx) in sorted(kt.items()):
@@ -213,10 +228,6 @@ def run_workload(name, steps, warmup, torch, nb):
                       "GBs": per / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None}
     node_p = sum(kt[k][0] for k in ("node_radix_first", "node_radix") if k in kt) // steps
     elem_p = sum(kt[k][0] for k in ("elem_radix_first", "elem_radix") if k in kt) // steps
-    from paper_1604_04689_amd import autotune
-    tuned = {kind: autotune.lookup(kind, m.etype, m.n_elem) for kind in ("node", "elem")}
-    tuned = {kind: (None if e is None else {"shape": nb.radix_shapes()[e["shape"]], "node_sort": e["mode"]})
-             for kind, e in tuned.items()}
     node_ms = sum(v[1] for k, v in kt.items() if k.startswith("node_")) / steps
     elem_ms = sum(v[1] for k, v in kt.items() if k.startswith("elem_")) / steps
     res = {
@@ -426,7 +437,7 @@ def main():
         others["serve_saturation"] = run_serving(meshes, torch, nb, rate_elems=None, n_req=args.serve_requests)
         del meshes
 
-    traffic = load_traffic(args.workload)
+    traffic = load_traffic(args.workload, (main_res["tuned"]["node"] or {}).get("node_sort", 0))
     rp = main_res["radix_pass"]
     roofline = {"bound": "hbm", "achieved": rp["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": rp["GBs"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": rp["kernel"],

@@ -3,7 +3,8 @@
 Every choice it makes changes speed only, never results: the radix tile
 shape (threads per block x keys per thread, which also sets the number of
 tiles in flight per CU) and, for the node relation, the algorithm (LSD sort
-of the full key, or sort by the vertex bits plus per-row deduplication).
+of the full key; sort by the vertex bits plus per-row deduplication; or each
+edge once by its lower vertex, deduplicated per row, then transposed).
 For each workload it times every combination on the GPU, checks that all of
 them produce byte-identical CSR output, and records the fastest per
 (relation, element type, size bucket) in ``tuning.json`` next to this file.
@@ -174,7 +175,7 @@ def tune(meshes, steps=5, log=print, batches=()):
     for m in meshes:
         conn = torch.as_tensor(m.conn).to(dev)
         for kind in ("node", "elem"):
-            modes = (0, 1) if kind == "node" else (0,)
+            modes = (0, 1, 2) if kind == "node" else (0,)
             results = []
             for mode in modes:
                 for shape in range(len(_b.radix_shapes())):
