@@ -227,9 +227,8 @@ mesh_status mesh_radix_shape_info(int32_t shape, int32_t* block, int32_t* items)
 mesh_status mesh_set_radix_shape(int32_t shape);
 int32_t mesh_get_radix_shape(void);
 
-/* How the node relation orders its keys; results are the same either way.
- * Process-wide, default MESH_NODE_SORT_FULL_KEY.  The batched node entry
- * points use VERTEX_ROWS when EDGE_ROWS is set.
+/* How the node relation (single meshes and batches) orders its keys; results
+ * are the same either way.  Process-wide, default MESH_NODE_SORT_FULL_KEY.
  *  FULL_KEY:     LSD radix passes over all 2b bits of (u << b) | w, then one
  *                pass drops repeats and writes the CSR.
  *  VERTEX_ROWS:  LSD radix passes over the bits of u only (the paper's sort by

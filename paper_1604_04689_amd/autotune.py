@@ -148,7 +148,7 @@ def tune_batches(torch, batches, steps=3, log=print):
         conn = torch.as_tensor(_b.concat_conn([m.conn for m in meshes])).to("cuda:0")
         seg, tot = _b.segment_table(desc)
         for kind in ("node", "elem"):
-            modes = (0, 1) if kind == "node" else (0,)
+            modes = (0, 1, 2) if kind == "node" else (0,)
             results = []
             for mode in modes:
                 for shape in range(len(_b.radix_shapes())):

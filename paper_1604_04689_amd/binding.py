@@ -127,8 +127,8 @@ NODE_SORT_FULL_KEY, NODE_SORT_VERTEX_ROWS, NODE_SORT_EDGE_ROWS = 0, 1, 2
 
 
 def set_node_sort(mode: int):
-    """Select the node algorithm (results are identical; batches use vertex-rows
-    when edge-rows is set)."""
+    """Select the node algorithm of single meshes and batches (results are
+    identical)."""
     st = lib().mesh_set_node_sort(int(mode))
     if st != Status.OK:
         raise MeshError(st, "mesh_set_node_sort")

@@ -15,6 +15,7 @@
 #include "internal.hpp"
 #include "launch.hpp"
 #include "radix.hpp"
+#include "edges.hpp"
 #include "rows.hpp"
 
 namespace mnb {
@@ -81,20 +82,23 @@ struct TileRec {
 };
 static_assert(sizeof(TileRec) == 48, "TileRec layout");
 
-template <bool NODE>
+// KIND: 0 element slots, 1 directed pairs, 2 canonical edges (keys of which
+// are looked up in the pair table at twice their index).
+template <int KIND>
 static __global__ __launch_bounds__(LUT_BLOCK) void tile_table_kernel(const mesh_segment* __restrict__ segs,
                                                                      const int32_t* __restrict__ lut, int64_t n,
                                                                      int64_t tile, TileRec* __restrict__ recs,
                                                                      int64_t n_tiles) {
-    constexpr int FIELD = NODE ? (int)offsetof(mesh_segment, pair_off) : (int)offsetof(mesh_segment, slot_off);
+    constexpr int FIELD = KIND ? (int)offsetof(mesh_segment, pair_off) : (int)offsetof(mesh_segment, slot_off);
+    constexpr int SCALE = KIND == 2 ? 2 : 1;
     const int64_t t = (int64_t)blockIdx.x * LUT_BLOCK + threadIdx.x;
     if (t >= n_tiles) return;
     const int64_t base = t * tile, last = tmin<int64_t>(base + tile, n) - 1;
-    const int m0 = lut_segment<FIELD>(segs, lut, base), m1 = lut_segment<FIELD>(segs, lut, last);
+    const int m0 = lut_segment<FIELD>(segs, lut, base * SCALE), m1 = lut_segment<FIELD>(segs, lut, last * SCALE);
     const mesh_segment& sg = segs[m0];
     const int npe = nodes_per_elem(sg.etype);
-    const int per = NODE ? 2 * edges_per_elem(sg.etype) : npe;  // keys per element
-    const int64_t off = NODE ? sg.pair_off : sg.slot_off;
+    const int per = KIND == 2 ? edges_per_elem(sg.etype) : KIND == 1 ? 2 * edges_per_elem(sg.etype) : npe;
+    const int64_t off = KIND ? sg.pair_off / SCALE : sg.slot_off;  // first key of the mesh
     TileRec r{};
     r.etype = -1;
     if (m0 == m1 && per > 0 && base >= off && last < off + per * sg.n_elem) {
@@ -121,40 +125,67 @@ __device__ __forceinline__ void pair_of(uint32_t loc, uint32_t* e, int* pa, int*
     *dir = r & 1;
 }
 
-// Directed edge pair i of the batch (pairs of mesh m start at pair_off[m]).
-struct BatchNodePairSrc {
+// Node key i of the batch: directed edge pair i (the pairs of mesh m start at
+// pair_off[m]), or with CANON edge i once (mesh m's edges start at
+// pair_off[m] / 2, every pair count being even) as the canonical key
+// ((vert_off + min) << lo_bits) | max.
+template <bool CANON>
+struct BatchNodeKeySrc {
     const int32_t* __restrict__ conn;
     const mesh_segment* __restrict__ segs;
-    const int32_t* __restrict__ lut;
+    const int32_t* __restrict__ lut;  // over pair positions
     const TileRec* __restrict__ tiles;  // built for the tile size of the launch
     uint32_t lo_bits;
     static constexpr bool kSkipNone = false;
+    static constexpr int PAIR_SCALE = CANON ? 2 : 1;  // pair positions per key
+    static constexpr int TABLE_KIND = CANON ? 2 : 1;  // tile_table_kernel<KIND>
+
+    template <int ET>
+    __device__ __forceinline__ static void locate(uint32_t loc, uint32_t* e, int* pa, int* pb, int* dir) {
+        if constexpr (CANON) {
+            constexpr uint32_t NE = Elem<ET>::NE;
+            *e = loc / NE;
+            edge_nodes<ET>((int)(loc - *e * NE), pa, pb);
+            *dir = 0;
+        } else {
+            pair_of<ET>(loc, e, pa, pb, dir);
+        }
+    }
+    __device__ __forceinline__ uint64_t key_of(int32_t x, int32_t y, int dir, int32_t n_vert, int32_t vert_off,
+                                               bool* bad) const {
+        const bool ok = (uint32_t)x < (uint32_t)n_vert && (uint32_t)y < (uint32_t)n_vert;
+        *bad = !ok;
+        if (!ok || x == y) return KEY_NONE;
+        int32_t u, w;
+        if (CANON) {
+            u = x < y ? x : y;
+            w = x < y ? y : x;
+        } else {
+            u = dir ? y : x;
+            w = dir ? x : y;
+        }
+        return ((uint64_t)(uint32_t)(vert_off + u) << lo_bits) | (uint64_t)(uint32_t)w;
+    }
 
     // key, or KEY_NONE; *bad is set when an id lies outside the mesh's range
-    // or the segment record is inconsistent (unknown type, pair beyond it).
+    // or the segment record is inconsistent (unknown type, key beyond it).
     __device__ __forceinline__ uint64_t make(int64_t i, bool* bad) const {
-        const int m = lut_segment<offsetof(mesh_segment, pair_off)>(segs, lut, i);
+        const int m = lut_segment<offsetof(mesh_segment, pair_off)>(segs, lut, i * PAIR_SCALE);
         const mesh_segment& sg = segs[m];
         const int32_t et = sg.etype;
         const int ne = edges_per_elem(et), npe = nodes_per_elem(et);
-        const int64_t loc = i - sg.pair_off;
-        if (ne == 0 || loc < 0 || loc >= 2 * ne * sg.n_elem) {
+        const int64_t loc = i - sg.pair_off / PAIR_SCALE;
+        if (ne == 0 || loc < 0 || loc >= 2 * ne / PAIR_SCALE * sg.n_elem) {
             *bad = true;
             return KEY_NONE;
         }
         uint32_t e;
         int pa, pb, dir;
-        if (et == TRI3) pair_of<TRI3>((uint32_t)loc, &e, &pa, &pb, &dir);
-        else if (et == TET4) pair_of<TET4>((uint32_t)loc, &e, &pa, &pb, &dir);
-        else pair_of<HEX8>((uint32_t)loc, &e, &pa, &pb, &dir);
+        if (et == TRI3) locate<TRI3>((uint32_t)loc, &e, &pa, &pb, &dir);
+        else if (et == TET4) locate<TET4>((uint32_t)loc, &e, &pa, &pb, &dir);
+        else locate<HEX8>((uint32_t)loc, &e, &pa, &pb, &dir);
         const int32_t* el = conn + sg.conn_off + (int64_t)e * npe;
-        const int32_t x = el[pa], y = el[pb];
-        const int32_t u = dir ? y : x;
-        const int32_t w = dir ? x : y;
-        const bool ok = (uint32_t)u < (uint32_t)sg.n_vert && (uint32_t)w < (uint32_t)sg.n_vert;
-        *bad = !ok;
-        if (!ok || u == w) return KEY_NONE;
-        return ((uint64_t)(uint32_t)(sg.vert_off + u) << lo_bits) | (uint64_t)(uint32_t)w;
+        return key_of(el[pa], el[pb], dir, sg.n_vert, sg.vert_off, bad);
     }
     __device__ __forceinline__ uint64_t load(int64_t i) const {
         bool bad;
@@ -164,10 +195,11 @@ struct BatchNodePairSrc {
     // ---- staged path: a tile whose keys all lie in one mesh copies that
     // mesh's element ids into LDS once (coalesced) and builds its keys there;
     // other tiles use make().  Header words: [0] 1 if staged, [1] type,
-    // [2] n_vert, [3] vert_off, [4] first staged element, [6..7] pair_off.
+    // [2] n_vert, [3] vert_off, [4] first staged element, [6..7] key offset
+    // of the mesh.
     static constexpr bool kStaged = true;
     template <int TILE>
-    static constexpr int stage_words() { return STAGE_HDR + TILE / 2 + 16; }
+    static constexpr int stage_words() { return STAGE_HDR + (CANON ? TILE : TILE / 2) + 16; }
 
     template <int BLOCK, int TILE>
     __device__ __forceinline__ void stage(int64_t tile_base, int64_t n, int32_t* s, int tid) const {
@@ -178,7 +210,7 @@ struct BatchNodePairSrc {
             if (tid == 0) s[0] = 0;
             return;
         }
-        const int32_t* src = conn + r.ids;  // r.cnt <= (TILE / 6 + 2) * 3 words
+        const int32_t* src = conn + r.ids;  // r.cnt <= stage_words - STAGE_HDR words
         int32_t* ids = s + STAGE_HDR;
         int32_t v[PER];
 #pragma unroll
@@ -223,23 +255,17 @@ struct BatchNodePairSrc {
         uint32_t e;
         int pa, pb, dir, npe;
         if (h.etype == TRI3) {
-            pair_of<TRI3>(loc, &e, &pa, &pb, &dir);
+            locate<TRI3>(loc, &e, &pa, &pb, &dir);
             npe = 3;
         } else if (h.etype == TET4) {
-            pair_of<TET4>(loc, &e, &pa, &pb, &dir);
+            locate<TET4>(loc, &e, &pa, &pb, &dir);
             npe = 4;
         } else {
-            pair_of<HEX8>(loc, &e, &pa, &pb, &dir);
+            locate<HEX8>(loc, &e, &pa, &pb, &dir);
             npe = 8;
         }
         const int32_t* el = s + STAGE_HDR + (e - h.e0) * npe;
-        const int32_t x = el[pa], y = el[pb];
-        const int32_t u = dir ? y : x;
-        const int32_t w = dir ? x : y;
-        const bool ok = (uint32_t)u < (uint32_t)h.n_vert && (uint32_t)w < (uint32_t)h.n_vert;
-        *bad = !ok;
-        if (!ok || u == w) return KEY_NONE;
-        return ((uint64_t)(uint32_t)(h.vert_off + u) << lo_bits) | (uint64_t)(uint32_t)w;
+        return key_of(el[pa], el[pb], dir, h.n_vert, h.vert_off, bad);
     }
     __device__ __forceinline__ uint64_t load_staged(const Header& h, int64_t i, int64_t tile_base,
                                                     const int32_t* s) const {
@@ -247,6 +273,8 @@ struct BatchNodePairSrc {
         return load_staged(h, i, tile_base, s, &bad);
     }
 };
+using BatchNodePairSrc = BatchNodeKeySrc<false>;
+using BatchEdgeSrc = BatchNodeKeySrc<true>;
 
 // (vertex, element) pair of connectivity slot s of the batch.
 struct BatchElemPairSrc {
@@ -255,6 +283,7 @@ struct BatchElemPairSrc {
     const int32_t* __restrict__ lut;
     const TileRec* __restrict__ tiles;  // built for the tile size of the launch
     static constexpr bool kSkipNone = true;
+    static constexpr int TABLE_KIND = 0;  // tile_table_kernel<KIND>
 
     __device__ __forceinline__ uint64_t make(int64_t s, bool* bad) const {
         const int m = lut_segment<offsetof(mesh_segment, slot_off)>(segs, lut, s);
@@ -441,6 +470,8 @@ bool plan_batch(int64_t n_keys, uint32_t digit_bits, int32_t rows_vert, BatchPla
     size_t off = HEADER_BYTES;
     p->off_hist = off;
     off += align_up(B_MAX_PASS * RADIX * sizeof(uint32_t));
+    p->off_hist2 = off;  // edge-rows: histograms of the transposed edges
+    off += rows_vert > 0 ? align_up(MAX_KH_PASS * RADIX * sizeof(uint32_t)) : 0;
     p->off_ulb = off;  // CSR look-back, or the rows stage's scan look-back
     off += align_up((size_t)(p->n_utiles > scan_tiles ? p->n_utiles : scan_tiles) * sizeof(uint64_t));
     p->off_lb0 = off;
@@ -458,6 +489,10 @@ bool plan_batch(int64_t n_keys, uint32_t digit_bits, int32_t rows_vert, BatchPla
     off += align_up((size_t)rows_vert * sizeof(int64_t));
     p->off_long = off;
     off += align_up((size_t)p->long_cap * sizeof(int64_t));
+    p->off_up = off;
+    off += rows_vert > 0 ? align_up(((size_t)rows_vert + 1) * sizeof(int32_t)) : 0;
+    p->off_low = off;
+    off += rows_vert > 0 ? align_up(((size_t)rows_vert + 1) * sizeof(int32_t)) : 0;
     p->n_lut = n_keys > 0 ? ((n_keys - 1) >> SEG_LUT_SHIFT) + 2 : 0;
     p->off_lut = off;
     off += align_up((size_t)p->n_lut * sizeof(int32_t));
@@ -473,7 +508,9 @@ uint32_t batch_hi_bits(int32_t total_vert) { return bits_for(total_vert); }
 template <class Src>
 static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, uint32_t shift0, uint32_t csr_lo_bits,
                                  int32_t total_vert, int32_t* row_ptr, int32_t* cols, int64_t cols_cap, char* w,
-                                 const mesh_segment* segs, int32_t n_mesh, bool rows, hipStream_t s) {
+                                 const mesh_segment* segs, int32_t n_mesh, int rows, hipStream_t s) {
+    // rows: 0 unique + CSR, 1 vertex-rows stage, 2 edge-rows (src gives
+    // canonical edge keys; p.n_keys is the number of edges)
     uint32_t* hdr = (uint32_t*)w;
     uint32_t* err = hdr + HDR_ERR;
     uint32_t* count = hdr + HDR_KEY_COUNT;
@@ -490,13 +527,15 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
     const int grid = (int)tmin<int64_t>(n_tiles, BH_GRID_MAX);
     const uint32_t last_bits = p.digit_bits - (uint32_t)(p.n_pass - 1) * RBITS;
     const dim3 lut_grid((unsigned)ceil_div(p.n_lut, LUT_BLOCK));
+    const int64_t lut_n = rows == 2 ? 2 * p.n_keys : p.n_keys;  // the table is over pair positions
     hipError_t e =
         node ? launch("batch_segment_lut", segment_lut_kernel<offsetof(mesh_segment, pair_off)>, lut_grid,
-                      dim3(LUT_BLOCK), s, segs, n_mesh, p.n_keys, (int32_t*)(w + p.off_lut), p.n_lut)
+                      dim3(LUT_BLOCK), s, segs, n_mesh, lut_n, (int32_t*)(w + p.off_lut), p.n_lut)
              : launch("batch_segment_lut", segment_lut_kernel<offsetof(mesh_segment, slot_off)>, lut_grid,
                       dim3(LUT_BLOCK), s, segs, n_mesh, p.n_keys, (int32_t*)(w + p.off_lut), p.n_lut);
     if (e == hipSuccess)
-        e = launch("batch_tile_table", tile_table_kernel<!Src::kSkipNone>, dim3((unsigned)ceil_div(n_tiles, LUT_BLOCK)),
+        e = launch("batch_tile_table", tile_table_kernel<Src::TABLE_KIND>,
+                   dim3((unsigned)ceil_div(n_tiles, LUT_BLOCK)),
                    dim3(LUT_BLOCK), s, segs, (const int32_t*)(w + p.off_lut), p.n_keys, tile, (TileRec*)(w + p.off_tiles),
                    n_tiles);
     const char* hname = node ? "batch_node_hist" : "batch_elem_hist";
@@ -519,7 +558,7 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
         const uint32_t shift = shift0 + (uint32_t)q * RBITS;
         const uint32_t bits = tmin<uint32_t>(RBITS, p.digit_bits - (uint32_t)q * RBITS);
         uint64_t* out = kb[q & 1];
-        uint64_t* lb_next = q + 1 < p.n_pass ? lb[(q + 1) & 1] : nullptr;
+        uint64_t* lb_next = q + 1 < p.n_pass || rows == 2 ? lb[(q + 1) & 1] : nullptr;
         if (q == 0)
             e = launch_radix_pass(node ? "batch_node_radix_first" : "batch_elem_radix_first", shape, src, out,
                                   p.n_keys, shift, bits, hist, lb[0], lb_next, hdr + HDR_TICKET0, err, s);
@@ -536,7 +575,17 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
         RowsStage r{kb[(p.n_pass - 1) & 1], p.n_keys, csr_lo_bits, total_vert, (int32_t*)(w + p.off_deg),
                     (int64_t*)(w + p.off_src), (int32_t*)kb[p.n_pass & 1], (int64_t*)(w + p.off_long), p.long_cap,
                     hdr + HDR_LONG_COUNT, ulb, hdr + HDR_TICKET0 + TK_BCSR, err};
-        return launch_rows_stage(true, r, row_ptr, cols, cols_cap, s);
+        if (rows == 1) return launch_rows_stage(true, r, row_ptr, cols, cols_cap, s);
+        // edge-rows: each vertex's higher neighbours and their scan, then the
+        // transposed edges; the key buffers hold 2 x n_keys keys (pairs)
+        int32_t* up_ptr = (int32_t*)(w + p.off_up);
+        e = launch_rows_dedup(r, up_ptr, s, true);
+        if (e != hipSuccess) return e;
+        EdgeStage g{up_ptr, r.deg, r.src, r.temp, total_vert, csr_lo_bits, segs, n_mesh, p.n_keys,
+                    {kb[(p.n_pass - 1) & 1], kb[(p.n_pass - 1) & 1] + p.n_keys}, (int32_t*)kb[p.n_pass & 1] + p.n_keys,
+                    (uint32_t*)(w + p.off_hist2), {lb[0], lb[1]}, p.n_pass & 1, hdr + HDR_TICKET0 + 8, shape,
+                    p.n_pass, p.digit_bits, (int32_t*)(w + p.off_low), err};
+        return launch_edge_stage(g, row_ptr, cols, cols_cap, s);
     }
     return launch_unique_csr(node ? "batch_node_csr" : "batch_elem_csr", kb[(p.n_pass - 1) & 1], p.n_keys,
                              node ? (const uint32_t*)nullptr : count, csr_lo_bits, total_vert, cols, cols_cap,
@@ -551,19 +600,24 @@ hipError_t run_batch_node(const BatchPlan& p, const int32_t* conn, const mesh_se
     if (p.n_keys == 0 || n_mesh == 0) return fill_i32(row_ptr, (int64_t)total_vert + 1, 0, s);
     const int32_t* lut = (const int32_t*)((char*)ws + p.off_lut);
     const TileRec* tiles = (const TileRec*)((char*)ws + p.off_tiles);
-    if (node_sort_mode() != 0) {  // vertex-rows (also when edge-rows is set)
-        // vertex-rows: radix passes over the global-vertex bits only (the
-        // all-ones value stays free for KEY_NONE), then per-row dedup
+    const int mode = node_sort_mode();
+    if (mode != 0) {
+        // vertex-rows and edge-rows: radix passes over the global-vertex bits
+        // only (the all-ones value stays free for KEY_NONE), then per-row dedup
         BatchPlan q = p;
         q.digit_bits = bits_for((int64_t)total_vert + 1);
         q.n_pass = (int)ceil_div(q.digit_bits, RBITS);
         e = fill_i32((int32_t*)((char*)ws + p.off_deg), total_vert, 0, s);
         if (e != hipSuccess) return e;
-        return batch_pipeline(q, "node", BatchNodePairSrc{conn, segs, lut, tiles, lo_bits}, lo_bits, lo_bits, total_vert,
-                              row_ptr, cols, cols_cap, (char*)ws, segs, n_mesh, true, s);
+        if (mode == 1)
+            return batch_pipeline(q, "node", BatchNodePairSrc{conn, segs, lut, tiles, lo_bits}, lo_bits, lo_bits,
+                                  total_vert, row_ptr, cols, cols_cap, (char*)ws, segs, n_mesh, 1, s);
+        q.n_keys = p.n_keys / 2;  // one canonical key per edge
+        return batch_pipeline(q, "node", BatchEdgeSrc{conn, segs, lut, tiles, lo_bits}, lo_bits, lo_bits, total_vert,
+                              row_ptr, cols, cols_cap, (char*)ws, segs, n_mesh, 2, s);
     }
     return batch_pipeline(p, "node", BatchNodePairSrc{conn, segs, lut, tiles, lo_bits}, 0u, lo_bits, total_vert, row_ptr,
-                          cols, cols_cap, (char*)ws, segs, n_mesh, false, s);
+                          cols, cols_cap, (char*)ws, segs, n_mesh, 0, s);
 }
 
 hipError_t run_batch_elem(const BatchPlan& p, const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
@@ -575,7 +629,7 @@ hipError_t run_batch_elem(const BatchPlan& p, const int32_t* conn, const mesh_se
     const int32_t* lut = (const int32_t*)((char*)ws + p.off_lut);
     const TileRec* tiles = (const TileRec*)((char*)ws + p.off_tiles);
     return batch_pipeline(p, "elem", BatchElemPairSrc{conn, segs, lut, tiles}, 32u, 32u, total_vert, row_ptr, cols,
-                          cols_cap, (char*)ws, segs, n_mesh, false, s);
+                          cols_cap, (char*)ws, segs, n_mesh, 0, s);
 }
 
 }  // namespace mnb

@@ -14,6 +14,7 @@
 // once instead of twice.
 #pragma once
 
+#include "../../include/mesh_neighbors.h"
 #include "common.hpp"
 #include "launch.hpp"
 #include "radix.hpp"
@@ -26,21 +27,42 @@ constexpr int KH_GRID_MAX = 1024;
 constexpr int LOWPTR_BLOCK = 256;
 constexpr int MAX_KH_PASS = 4;  // 31 vertex bits
 
+// With BATCH, row vertices are global (vert_off[m] + local) and neighbour
+// ids local to the mesh: the transposed key is then
+// ((vert_off + w) << b) | (v - vert_off), the mesh of v found among the
+// segment records (vert_off non-decreasing; a vertex with rows belongs to a
+// mesh with vertices).
+template <bool BATCH>
 static __global__ __launch_bounds__(EDGE_BLOCK) void edge_transpose_kernel(const int32_t* __restrict__ up_ptr,
                                                                          const int32_t* __restrict__ deg,
                                                                          const int64_t* __restrict__ src,
                                                                          const int32_t* __restrict__ temp,
                                                                          int32_t n_vert, uint32_t b,
+                                                                         const mesh_segment* __restrict__ segs,
+                                                                         int32_t n_mesh,
                                                                          uint64_t* __restrict__ tkeys,
                                                                          int32_t* __restrict__ up_cols) {
     __shared__ int32_t s_start[EDGE_BLOCK + 1];
     __shared__ int64_t s_src[EDGE_BLOCK];
+    __shared__ int32_t s_voff[EDGE_BLOCK];
     const int tid = threadIdx.x;
     const int64_t v0 = (int64_t)blockIdx.x * EDGE_BLOCK;
     const int nv = (int)tmin<int64_t>(EDGE_BLOCK, (int64_t)n_vert - v0);
     if (tid < nv) {
         s_start[tid] = up_ptr[v0 + tid];
         s_src[tid] = deg[v0 + tid] > 0 ? src[v0 + tid] : 0;
+        int32_t voff = 0;
+        if (BATCH) {  // largest m with vert_off[m] <= v
+            const int64_t v = v0 + tid;
+            int lo = 0, hi = n_mesh - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (segs[mid].vert_off <= v) lo = mid;
+                else hi = mid - 1;
+            }
+            voff = segs[lo].vert_off;
+        }
+        s_voff[tid] = voff;
     }
     if (tid == 0) s_start[nv] = up_ptr[v0 + nv];
     __syncthreads();
@@ -53,7 +75,8 @@ static __global__ __launch_bounds__(EDGE_BLOCK) void edge_transpose_kernel(const
             else hi = mid - 1;
         }
         const int32_t w = temp[s_src[lo] + (i - s_start[lo])];
-        tkeys[i] = ((uint64_t)(uint32_t)w << b) | (uint64_t)(v0 + lo);
+        const int32_t voff = s_voff[lo];
+        tkeys[i] = ((uint64_t)(uint32_t)(voff + w) << b) | (uint64_t)(v0 + lo - voff);
         up_cols[i] = w;
     }
 }
@@ -158,6 +181,69 @@ static __global__ __launch_bounds__(EDGE_BLOCK) void edge_merge_kernel(const int
         const int o = (int)(i - s_start[lo]);
         cols[i] = o < s_nlow[lo] ? (int32_t)(tsorted[s_low[lo] + o] & lo_mask) : up_cols[s_up[lo] + (o - s_nlow[lo])];
     }
+}
+
+// Everything after the rows stage of the edge-rows algorithm.  up_ptr holds
+// the scan of the higher-neighbour counts (up_ptr[n_vert] = E); keys[2] are
+// two buffers of n_edges keys each (the transposed edges ping-pong between
+// them), up_cols n_edges ints, hist2 zeroed, lb[l0] cleared for n_edges keys
+// and lb[l0 ^ 1] for later clearing; tickets[0 .. n_pass) zero.
+struct EdgeStage {
+    const int32_t* up_ptr;
+    const int32_t* deg;
+    const int64_t* src;
+    const int32_t* temp;
+    int32_t n_vert;
+    uint32_t b;
+    const mesh_segment* segs;  // batches (null for one mesh)
+    int32_t n_mesh;
+    int64_t n_edges;
+    uint64_t* keys[2];
+    int32_t* up_cols;
+    uint32_t* hist2;
+    uint64_t* lb[2];
+    int l0;
+    uint32_t* tickets;
+    int shape, n_pass;
+    uint32_t hi_bits;
+    int32_t* low_ptr;
+    uint32_t* err;
+};
+
+static inline hipError_t launch_edge_stage(const EdgeStage& g, int32_t* row_ptr, int32_t* cols, int64_t cols_cap,
+                                           hipStream_t s) {
+    const bool batch = g.segs != nullptr;
+    const int32_t* E = g.up_ptr + g.n_vert;
+    const unsigned vgrid = (unsigned)ceil_div((int64_t)g.n_vert, EDGE_BLOCK);
+    const uint32_t last_bits = g.hi_bits - (uint32_t)(g.n_pass - 1) * RBITS;
+    hipError_t e =
+        batch ? launch("batch_node_edge_transpose", edge_transpose_kernel<true>, dim3(vgrid), dim3(EDGE_BLOCK), s,
+                       g.up_ptr, g.deg, g.src, g.temp, g.n_vert, g.b, g.segs, g.n_mesh, g.keys[0], g.up_cols)
+              : launch("node_edge_transpose", edge_transpose_kernel<false>, dim3(vgrid), dim3(EDGE_BLOCK), s,
+                       g.up_ptr, g.deg, g.src, g.temp, g.n_vert, g.b, g.segs, g.n_mesh, g.keys[0], g.up_cols);
+    if (e == hipSuccess)
+        e = launch(batch ? "batch_node_edge_hist" : "node_edge_hist", key_hist_kernel,
+                   dim3((unsigned)tmin<int64_t>(ceil_div(g.n_edges, KH_BLOCK), KH_GRID_MAX)), dim3(KH_BLOCK), s,
+                   (const uint64_t*)g.keys[0], E, g.b, g.n_pass, last_bits, g.hist2);
+    for (int q = 0; q < g.n_pass && e == hipSuccess; ++q) {
+        const uint32_t shift = g.b + (uint32_t)q * RBITS;
+        const uint32_t bits = tmin<uint32_t>(RBITS, g.hi_bits - (uint32_t)q * RBITS);
+        const int l = g.l0 ^ (q & 1);  // look-back array, cleared by the previous pass
+        uint64_t* lb_next = q + 1 < g.n_pass ? g.lb[l ^ 1] : nullptr;
+        e = launch_radix_pass(batch ? "batch_node_edge_radix" : "node_edge_radix", g.shape,
+                              CountedKeySrc{g.keys[q & 1], (const uint32_t*)E}, g.keys[(q + 1) & 1], g.n_edges, shift,
+                              bits, g.hist2 + q * RADIX, g.lb[l], lb_next, g.tickets + q, g.err, s);
+    }
+    const uint64_t* sorted = g.keys[g.n_pass & 1];
+    if (e == hipSuccess)
+        e = launch(batch ? "batch_node_edge_low_ptr" : "node_edge_low_ptr", low_ptr_kernel,
+                   dim3((unsigned)tmin<int64_t>(ceil_div(g.n_edges, LOWPTR_BLOCK) + 1, 4096)), dim3(LOWPTR_BLOCK), s,
+                   sorted, g.n_edges, E, g.b, g.n_vert, g.low_ptr);
+    if (e == hipSuccess)
+        e = launch(batch ? "batch_node_edge_merge" : "node_edge_merge", edge_merge_kernel, dim3(vgrid),
+                   dim3(EDGE_BLOCK), s, (const int32_t*)g.low_ptr, g.up_ptr, sorted, (const int32_t*)g.up_cols,
+                   g.n_vert, g.b, row_ptr, cols, cols_cap, g.err);
+    return e;
 }
 
 }  // namespace mnb

@@ -71,6 +71,7 @@ struct BatchPlan {
     int32_t rows_vert = 0;  // node relation: vertices of the vertex-rows stage (0: no such stage)
     int64_t long_cap = 0;
     size_t off_deg = 0, off_src = 0, off_long = 0;
+    size_t off_hist2 = 0, off_up = 0, off_low = 0;  // node relation, edge-rows algorithm
     size_t zero_bytes = 0;
     size_t total = 0;
 };

@@ -321,34 +321,11 @@ static hipError_t node_pipeline(const NodePlan& p, const int32_t* conn, int32_t*
     if (e != hipSuccess) return e;
     // transposed edges (w << b) | v: ping-pong halves of the sorted buffer (free
     // now); w alone after the row values in the other buffer
-    uint64_t* tk[2] = {kb[(n_pass - 1) & 1], kb[(n_pass - 1) & 1] + p.n_edges};
-    int32_t* up_cols = (int32_t*)kb[n_pass & 1] + p.n_edges;
-    const int32_t* E = up_ptr + p.n_vert;
-    const unsigned vgrid = (unsigned)ceil_div((int64_t)p.n_vert, EDGE_BLOCK);
-    uint32_t* hist2 = (uint32_t*)(w + p.off_hist2);
-    e = launch("node_edge_transpose", edge_transpose_kernel, dim3(vgrid), dim3(EDGE_BLOCK), s, (const int32_t*)up_ptr,
-               (const int32_t*)r.deg, (const int64_t*)r.src, (const int32_t*)r.temp, p.n_vert, p.id_bits, tk[0],
-               up_cols);
-    if (e == hipSuccess)
-        e = launch("node_edge_hist", key_hist_kernel,
-                   dim3((unsigned)tmin<int64_t>(ceil_div(p.n_edges, KH_BLOCK), KH_GRID_MAX)), dim3(KH_BLOCK), s,
-                   (const uint64_t*)tk[0], E, p.id_bits, n_pass, last_bits, hist2);
-    for (int q = 0; q < n_pass && e == hipSuccess; ++q) {
-        const uint32_t shift = p.id_bits + (uint32_t)q * RBITS;
-        const uint32_t bits = tmin<uint32_t>(RBITS, p.hi_bits - (uint32_t)q * RBITS);
-        const int l = (n_pass + q) & 1;  // look-back array, cleared by the previous pass
-        uint64_t* lb_next = q + 1 < n_pass ? lb[l ^ 1] : nullptr;
-        e = launch_radix_pass("node_edge_radix", shape, CountedKeySrc{tk[q & 1], (const uint32_t*)E}, tk[(q + 1) & 1],
-                              p.n_edges, shift, bits, hist2 + q * RADIX, lb[l], lb_next, tickets + 8 + q, err, s);
-    }
-    if (e == hipSuccess)
-        e = launch("node_edge_low_ptr", low_ptr_kernel,
-                   dim3((unsigned)tmin<int64_t>(ceil_div(p.n_edges, LOWPTR_BLOCK) + 1, 4096)), dim3(LOWPTR_BLOCK), s,
-                   (const uint64_t*)tk[n_pass & 1], p.n_edges, E, p.id_bits, p.n_vert, low_ptr);
-    if (e == hipSuccess)
-        e = launch("node_edge_merge", edge_merge_kernel, dim3(vgrid), dim3(EDGE_BLOCK), s, (const int32_t*)low_ptr,
-                   (const int32_t*)up_ptr, (const uint64_t*)tk[n_pass & 1], (const int32_t*)up_cols, p.n_vert,
-                   p.id_bits, row_ptr, cols, cols_capacity, err);
+    EdgeStage g{up_ptr, r.deg, r.src, r.temp, p.n_vert, p.id_bits, nullptr, 0, p.n_edges,
+                {kb[(n_pass - 1) & 1], kb[(n_pass - 1) & 1] + p.n_edges}, (int32_t*)kb[n_pass & 1] + p.n_edges,
+                (uint32_t*)(w + p.off_hist2), {lb[0], lb[1]}, n_pass & 1, tickets + 8, shape, n_pass, p.hi_bits,
+                low_ptr, err};
+    e = launch_edge_stage(g, row_ptr, cols, cols_capacity, s);
     return e;
 }
 

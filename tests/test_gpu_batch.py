@@ -18,9 +18,9 @@ def _nb():
     return nb
 
 
-@pytest.fixture(autouse=True, params=[0, 1], ids=["full_key", "vertex_rows"])
+@pytest.fixture(autouse=True, params=[0, 1, 2], ids=["full_key", "vertex_rows", "edge_rows"])
 def node_sort(request):
-    """Every batch test runs under both node algorithms (process-wide)."""
+    """Every batch test runs under every node algorithm (process-wide)."""
     nb = _nb()
     nb.set_node_sort(request.param)
     yield request.param
