@@ -66,12 +66,18 @@ def kernel_bytes(m, nnz_node, nnz_elem, node_sort):
     pairs (2 x edges per element x F), Q = element pairs (nnz of the element
     relation), U = node nnz, V = vertices, conn = 4 x npe x F bytes.  The node
     sort passes move K keys: P, or with the edge-rows algorithm the k x F
-    canonical edge keys; E = U / 2 unique edges."""
+    canonical edge keys; E = U / 2 unique edges.  The element sort's last
+    pass reads keys and writes cols and the row starts instead of keys, so
+    elem_radix is the mean over its middle passes and that last one."""
     f, v, k, npe = m.n_elem, m.n_vert, EDGES[m.etype], NPE[m.etype]
     p_pairs, q_pairs, u = 2 * k * f, nnz_elem, nnz_node
     keys = k * f if node_sort == 2 else p_pairs
     e = u // 2
     conn = 4 * npe * f
+    id_bits = max(1, (v - 1).bit_length())
+    elem_passes = (id_bits + 7) // 8
+    csr_out = 4 * q_pairs + 4 * (v + 1)                      # cols and row starts
+    later = [16 * q_pairs] * (elem_passes - 2) + [8 * q_pairs + csr_out]
     return {
         "node_hist": conn,                                  # read conn
         "node_radix_first": conn + 8 * keys,                # read conn, write keys
@@ -87,9 +93,9 @@ def kernel_bytes(m, nnz_node, nnz_elem, node_sort):
         "node_edge_low_ptr": 8 * e + 4 * (v + 1),
         "node_edge_merge": 12 * e + 8 * (v + 1) + 4 * u + 4 * (v + 1),
         "elem_hist": conn,
-        "elem_radix_first": conn + 8 * q_pairs,
-        "elem_radix": 16 * q_pairs,
-        "elem_csr": 8 * q_pairs + 4 * q_pairs + 4 * (v + 1),
+        "elem_radix_first": conn + (8 * q_pairs if elem_passes > 1 else csr_out),
+        "elem_radix": sum(later) // len(later) if elem_passes > 1 else 0,
+        "elem_row_fill": 4 * (v + 1),                       # block minima, then the fill: each reads row_ptr
         "fill": 0,
     }
 

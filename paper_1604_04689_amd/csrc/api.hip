@@ -138,7 +138,7 @@ mesh_status mesh_batch_node_neighbors_query(int32_t n_mesh, int64_t total_pairs,
     if (!workspace_bytes || !cols_capacity) return MESH_ERR_INVALID_ARG;
     if (total_pairs > INT32_MAX) return MESH_ERR_OVERFLOW;
     BatchPlan p;
-    if (!plan_batch(total_pairs, batch_hi_bits(total_vert) + batch_node_lo_bits(max_vert), total_vert, &p))
+    if (!plan_batch(total_pairs, batch_hi_bits(total_vert) + batch_node_lo_bits(max_vert), total_vert, total_vert, &p))
         return MESH_ERR_OVERFLOW;
     *workspace_bytes = p.total;
     *cols_capacity = total_pairs;
@@ -159,7 +159,7 @@ mesh_status mesh_batch_node_neighbors(const int32_t* conn, const mesh_segment* s
     if (workspace_bytes < need || !aligned(workspace)) return MESH_ERR_WORKSPACE;
     const uint32_t lo = batch_node_lo_bits(max_vert);
     BatchPlan p;
-    plan_batch(total_pairs, batch_hi_bits(total_vert) + lo, total_vert, &p);
+    plan_batch(total_pairs, batch_hi_bits(total_vert) + lo, total_vert, total_vert, &p);
     hipError_t e = run_batch_node(p, conn, segs, n_mesh, lo, total_vert, row_ptr, cols, cols_capacity, workspace,
                                   (hipStream_t)stream);
     return e == hipSuccess ? MESH_OK : MESH_ERR_HIP;
@@ -171,7 +171,7 @@ mesh_status mesh_batch_elem_neighbors_query(int32_t n_mesh, int64_t total_slots,
     if (!workspace_bytes || !cols_capacity) return MESH_ERR_INVALID_ARG;
     if (total_slots > INT32_MAX) return MESH_ERR_OVERFLOW;
     BatchPlan p;
-    if (!plan_batch(total_slots, batch_hi_bits(total_vert), 0, &p)) return MESH_ERR_OVERFLOW;
+    if (!plan_batch(total_slots, batch_hi_bits(total_vert), 0, total_vert, &p)) return MESH_ERR_OVERFLOW;
     *workspace_bytes = p.total;
     *cols_capacity = total_slots;
     return MESH_OK;
@@ -189,7 +189,7 @@ mesh_status mesh_batch_elem_neighbors(const int32_t* conn, const mesh_segment* s
     if (cols_capacity > 0 && !cols) return MESH_ERR_INVALID_ARG;
     if (workspace_bytes < need || !aligned(workspace)) return MESH_ERR_WORKSPACE;
     BatchPlan p;
-    plan_batch(total_slots, batch_hi_bits(total_vert), 0, &p);
+    plan_batch(total_slots, batch_hi_bits(total_vert), 0, total_vert, &p);
     hipError_t e = run_batch_elem(p, conn, segs, n_mesh, total_vert, row_ptr, cols, cols_capacity, workspace,
                                   (hipStream_t)stream);
     return e == hipSuccess ? MESH_OK : MESH_ERR_HIP;

@@ -455,8 +455,8 @@ static uint32_t bits_for(int64_t n) {
     return b;
 }
 
-bool plan_batch(int64_t n_keys, uint32_t digit_bits, int32_t rows_vert, BatchPlan* p) {
-    if (n_keys < 0 || digit_bits == 0 || digit_bits > 62 || rows_vert < 0) return false;
+bool plan_batch(int64_t n_keys, uint32_t digit_bits, int32_t rows_vert, int32_t total_vert, BatchPlan* p) {
+    if (n_keys < 0 || digit_bits == 0 || digit_bits > 62 || rows_vert < 0 || total_vert < 0) return false;
     p->n_keys = n_keys;
     p->n_pass = (int)ceil_div(digit_bits, RBITS);
     if (p->n_pass > B_MAX_PASS) return false;
@@ -489,6 +489,8 @@ bool plan_batch(int64_t n_keys, uint32_t digit_bits, int32_t rows_vert, BatchPla
     off += align_up((size_t)rows_vert * sizeof(int64_t));
     p->off_long = off;
     off += align_up((size_t)p->long_cap * sizeof(int64_t));
+    p->off_bmin = off;
+    off += align_up((size_t)ceil_div((int64_t)total_vert + 1, (int64_t)RF_TILE) * sizeof(int32_t));
     p->off_up = off;
     off += rows_vert > 0 ? align_up(((size_t)rows_vert + 1) * sizeof(int32_t)) : 0;
     p->off_low = off;
@@ -554,22 +556,34 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
             e = launch_shm(hname, batch_hist_kernel<Src, 16>, g, b, shm, s, src, p.n_keys, shift0, p.n_pass, last_bits,
                            copies, hist, count, err);
     }
+    // element relation: the last pass writes cols and offers row starts
+    const CsrOut csr{cols, row_ptr, cols ? cols_cap : 0, 32u, 0xffffffffull};
+    if (!node && e == hipSuccess) e = fill_i32(row_ptr, (int64_t)total_vert + 1, INT32_MAX, s);
     for (int q = 0; q < p.n_pass && e == hipSuccess; ++q) {
         const uint32_t shift = shift0 + (uint32_t)q * RBITS;
         const uint32_t bits = tmin<uint32_t>(RBITS, p.digit_bits - (uint32_t)q * RBITS);
         uint64_t* out = kb[q & 1];
         uint64_t* lb_next = q + 1 < p.n_pass || rows == 2 ? lb[(q + 1) & 1] : nullptr;
-        if (q == 0)
+        const bool last_elem = !node && q + 1 == p.n_pass;
+        if (q == 0 && last_elem)
+            e = launch_radix_pass("batch_elem_radix_first", shape, src, csr, p.n_keys, shift, bits, hist, lb[0],
+                                  lb_next, hdr + HDR_TICKET0, err, s);
+        else if (q == 0)
             e = launch_radix_pass(node ? "batch_node_radix_first" : "batch_elem_radix_first", shape, src, out,
                                   p.n_keys, shift, bits, hist, lb[0], lb_next, hdr + HDR_TICKET0, err, s);
         else if (node)
             e = launch_radix_pass("batch_node_radix", shape, KeyArraySrc{kb[(q - 1) & 1]}, out, p.n_keys, shift,
                                   bits, hist + q * RADIX, lb[q & 1], lb_next, hdr + HDR_TICKET0 + q, err, s);
+        else if (last_elem)
+            e = launch_radix_pass("batch_elem_radix", shape, CountedKeySrc{kb[(q - 1) & 1], count}, csr, p.n_keys,
+                                  shift, bits, hist + q * RADIX, lb[q & 1], lb_next, hdr + HDR_TICKET0 + q, err, s);
         else
             e = launch_radix_pass("batch_elem_radix", shape, CountedKeySrc{kb[(q - 1) & 1], count}, out, p.n_keys,
                                   shift, bits, hist + q * RADIX, lb[q & 1], lb_next, hdr + HDR_TICKET0 + q, err, s);
     }
     if (e != hipSuccess) return e;
+    if (!node)
+        return launch_rowptr_fill("batch_elem_row_fill", row_ptr, total_vert, count, (int32_t*)(w + p.off_bmin), s);
     (void)tag;
     if (rows) {
         RowsStage r{kb[(p.n_pass - 1) & 1], p.n_keys, csr_lo_bits, total_vert, (int32_t*)(w + p.off_deg),
@@ -587,9 +601,9 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
                     p.n_pass, p.digit_bits, (int32_t*)(w + p.off_low), err};
         return launch_edge_stage(g, row_ptr, cols, cols_cap, s);
     }
-    return launch_unique_csr(node ? "batch_node_csr" : "batch_elem_csr", kb[(p.n_pass - 1) & 1], p.n_keys,
-                             node ? (const uint32_t*)nullptr : count, csr_lo_bits, total_vert, cols, cols_cap,
-                             row_ptr, ulb, hdr + HDR_TICKET0 + TK_BCSR, err, s);
+    return launch_unique_csr("batch_node_csr", kb[(p.n_pass - 1) & 1], p.n_keys, (const uint32_t*)nullptr,
+                             csr_lo_bits, total_vert, cols, cols_cap, row_ptr, ulb, hdr + HDR_TICKET0 + TK_BCSR, err,
+                             s);
 }
 
 hipError_t run_batch_node(const BatchPlan& p, const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,

@@ -206,3 +206,101 @@ static __global__ __launch_bounds__(SCAN_BLOCK) void scan_i32_kernel(const int32
 }
 
 }  // namespace mnb
+
+namespace mnb {
+
+// Row starts after a CsrOut pass: row_ptr[v] holds the first slot of vertex
+// v's row, or INT32_MAX for a vertex without keys.  Such a vertex's row is
+// empty and starts where the next non-empty row starts, so row_ptr becomes
+// its suffix minimum, with row_ptr[n] = *count.  Two launches: block minima,
+// then the fill (a block takes the minimum of the later blocks' minima, then
+// the suffix minimum of its own entries).
+constexpr int RF_BLOCK = 256;
+constexpr int RF_ITEMS = 16;
+constexpr int RF_TILE = RF_BLOCK * RF_ITEMS;
+
+static __global__ __launch_bounds__(RF_BLOCK) void rowptr_blockmin_kernel(int32_t* __restrict__ row_ptr, int64_t n,
+                                                                         const uint32_t* __restrict__ count,
+                                                                         int32_t* __restrict__ block_min) {
+    __shared__ int32_t s_min[RF_BLOCK / WAVE];
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
+    const int64_t base = (int64_t)blockIdx.x * RF_TILE;
+    int32_t m = INT32_MAX;
+#pragma unroll
+    for (int j = 0; j < RF_ITEMS; ++j) {
+        const int64_t i = base + j * RF_BLOCK + tid;
+        if (i < n) m = min(m, row_ptr[i]);
+        else if (i == n) {
+            const int32_t c = (int32_t)*count;
+            row_ptr[n] = c;  // only this block reads entry n
+            m = min(m, c);
+        }
+    }
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) m = min(m, __shfl_xor(m, d, WAVE));
+    if (lane == 0) s_min[wid] = m;
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < RF_BLOCK / WAVE; ++w) m = min(m, s_min[w]);
+        block_min[blockIdx.x] = m;
+    }
+}
+
+static __global__ __launch_bounds__(RF_BLOCK) void rowptr_fill_kernel(int32_t* __restrict__ row_ptr, int64_t n,
+                                                                      const int32_t* __restrict__ block_min,
+                                                                      int64_t n_blocks) {
+    __shared__ int32_t s_red[RF_BLOCK / WAVE];
+    __shared__ int32_t s_after[RF_BLOCK / WAVE];  // minimum over each wave's entries
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
+    // minimum over the later blocks (entry n lives in the last block)
+    int32_t later = INT32_MAX;
+    for (int64_t b = (int64_t)blockIdx.x + 1 + tid; b < n_blocks; b += RF_BLOCK) later = min(later, block_min[b]);
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) later = min(later, __shfl_xor(later, d, WAVE));
+    if (lane == 0) s_red[wid] = later;
+    // this thread's entries, RF_ITEMS consecutive ones
+    const int64_t first = (int64_t)blockIdx.x * RF_TILE + (int64_t)tid * RF_ITEMS;
+    int32_t v[RF_ITEMS];
+    int32_t mine = INT32_MAX;
+#pragma unroll
+    for (int j = 0; j < RF_ITEMS; ++j) {
+        const int64_t i = first + j;
+        v[j] = i <= n ? row_ptr[i] : INT32_MAX;
+        mine = min(mine, v[j]);
+    }
+    // suffix minimum over the later lanes of the wave, then the later waves
+    int32_t suf = mine;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const int32_t y = __shfl_down(suf, d, WAVE);
+        if (lane + d < WAVE) suf = min(suf, y);
+    }
+    int32_t after = __shfl_down(suf, 1, WAVE);  // exclusive
+    if (lane == WAVE - 1) after = INT32_MAX;
+    if (lane == 0) s_after[wid] = suf;  // the whole wave's minimum
+    __syncthreads();
+    for (int w = 0; w < RF_BLOCK / WAVE; ++w) later = min(later, s_red[w]);
+    int32_t carry = min(later, after);
+    for (int w = wid + 1; w < RF_BLOCK / WAVE; ++w) carry = min(carry, s_after[w]);
+#pragma unroll
+    for (int j = RF_ITEMS - 1; j >= 0; --j) {
+        const int64_t i = first + j;
+        const int32_t r = min(v[j], carry);
+        if (i < n && r != v[j]) row_ptr[i] = r;
+        carry = r;
+    }
+}
+
+// Launches the two fix-up kernels; block_min needs ceil((n + 1) / RF_TILE) ints.
+static inline hipError_t launch_rowptr_fill(const char* tag, int32_t* row_ptr, int64_t n, const uint32_t* count,
+                                            int32_t* block_min, hipStream_t s) {
+    const int64_t blocks = ceil_div(n + 1, (int64_t)RF_TILE);
+    hipError_t e = launch(tag, rowptr_blockmin_kernel, dim3((unsigned)blocks), dim3(RF_BLOCK), s, row_ptr, n, count,
+                          block_min);
+    if (e == hipSuccess)
+        e = launch(tag, rowptr_fill_kernel, dim3((unsigned)blocks), dim3(RF_BLOCK), s, row_ptr, n,
+                   (const int32_t*)block_min, blocks);
+    return e;
+}
+
+}  // namespace mnb

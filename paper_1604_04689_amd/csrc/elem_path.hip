@@ -33,7 +33,6 @@ constexpr int MAX_EPASS = 4;  // 31 vertex bits
 
 // Ticket slots in the workspace header.
 constexpr int TK_PASS0 = 0;  // passes 0..3
-constexpr int TK_CSR = 15;
 
 // The element holding slot s contains vertex v = conn[s] for the first time
 // (set semantics for degenerate elements: a repeated id counts once).
@@ -180,21 +179,20 @@ bool plan_elem(int64_t n_elem, int32_t etype, int32_t n_vert, ElemPlan* p) {
     p->id_bits = id_bits_of(n_vert);
     p->n_pass = (int)ceil_div(p->id_bits, RBITS);
     p->n_tiles = ceil_div(p->n_slots, min_radix_tile());
-    p->n_utiles = ceil_div(p->n_slots, UNIQ_TILE);
     size_t off = HEADER_BYTES;
     p->off_hist = off;
     off += align_up(MAX_EPASS * RADIX * sizeof(uint32_t));
-    p->off_ulb = off;
-    off += align_up((size_t)p->n_utiles * sizeof(uint64_t));
     p->off_lb0 = off;
     off += align_up((size_t)p->n_tiles * RADIX * sizeof(uint64_t));
-    p->zero_bytes = off;  // header, histograms, CSR look-back, pass-0 look-back
+    p->zero_bytes = off;  // header, histograms, pass-0 look-back
     p->off_lb1 = off;
     off += p->n_pass > 1 ? align_up((size_t)p->n_tiles * RADIX * sizeof(uint64_t)) : 0;
     p->off_keys0 = off;
     off += align_up((size_t)p->n_slots * sizeof(uint64_t));
     p->off_keys1 = off;
     off += p->n_pass > 1 ? align_up((size_t)p->n_slots * sizeof(uint64_t)) : 0;
+    p->off_bmin = off;
+    off += align_up((size_t)ceil_div((int64_t)n_vert + 1, (int64_t)RF_TILE) * sizeof(int32_t));
     p->total = off;
     return true;
 }
@@ -206,31 +204,39 @@ static hipError_t elem_pipeline(const ElemPlan& p, const int32_t* conn, int32_t*
     uint32_t* err = hdr + HDR_ERR;
     uint32_t* count = hdr + HDR_KEY_COUNT;
     uint32_t* hist = (uint32_t*)(w + p.off_hist);
-    uint64_t* ulb = (uint64_t*)(w + p.off_ulb);
     uint64_t* lb[2] = {(uint64_t*)(w + p.off_lb0), (uint64_t*)(w + p.off_lb1)};
     uint64_t* kb[2] = {(uint64_t*)(w + p.off_keys0), (uint64_t*)(w + p.off_keys1)};
     const int shape = radix_shape();
 
     const int grid = (int)tmin<int64_t>(ceil_div(p.n_elem, HIST_BLOCK), HIST_GRID_MAX);
     const uint32_t last_bits = p.id_bits - (uint32_t)(p.n_pass - 1) * RBITS;
-    hipError_t e = launch("elem_hist", elem_hist_kernel<ET>, dim3(grid), dim3(HIST_BLOCK), s, conn, p.n_elem,
-                          p.n_vert, p.n_pass, last_bits, hist, count, err);
+    // the last pass (CsrOut) offers every row start: unset entries hold INT32_MAX
+    hipError_t e = fill_i32(row_ptr, (int64_t)p.n_vert + 1, INT32_MAX, s);
+    if (e == hipSuccess)
+        e = launch("elem_hist", elem_hist_kernel<ET>, dim3(grid), dim3(HIST_BLOCK), s, conn, p.n_elem, p.n_vert,
+                   p.n_pass, last_bits, hist, count, err);
+    const CsrOut csr{cols, row_ptr, cols ? cols_cap : 0, 32u, 0xffffffffull};
     for (int q = 0; q < p.n_pass && e == hipSuccess; ++q) {
         const uint32_t shift = 32 + (uint32_t)q * RBITS;
         const uint32_t bits = tmin<uint32_t>(RBITS, p.id_bits - (uint32_t)q * RBITS);
+        const bool last = q + 1 == p.n_pass;
         uint64_t* out = kb[q & 1];
-        uint64_t* lb_next = q + 1 < p.n_pass ? lb[(q + 1) & 1] : nullptr;
-        if (q == 0)
-            e = launch_radix_pass("elem_radix_first", shape, ElemPairSrc<ET>{conn, p.n_vert}, out, p.n_slots, shift,
-                                  bits, hist, lb[0], lb_next, hdr + HDR_TICKET0 + TK_PASS0, err, s);
-        else
-            e = launch_radix_pass("elem_radix", shape, CountedKeySrc{kb[(q - 1) & 1], count}, out, p.n_slots, shift,
-                                  bits, hist + q * RADIX, lb[q & 1], lb_next, hdr + HDR_TICKET0 + TK_PASS0 + q, err,
-                                  s);
+        uint64_t* lb_next = last ? nullptr : lb[(q + 1) & 1];
+        const ElemPairSrc<ET> first{conn, p.n_vert};
+        const CountedKeySrc later{kb[(q - 1) & 1], count};
+        uint32_t* ticket = hdr + HDR_TICKET0 + TK_PASS0 + q;
+        const uint32_t* hq = hist + q * RADIX;
+        if (q == 0 && last) e = launch_radix_pass("elem_radix_first", shape, first, csr, p.n_slots, shift, bits, hq,
+                                                  lb[0], lb_next, ticket, err, s);
+        else if (q == 0) e = launch_radix_pass("elem_radix_first", shape, first, out, p.n_slots, shift, bits, hq,
+                                               lb[0], lb_next, ticket, err, s);
+        else if (last) e = launch_radix_pass("elem_radix", shape, later, csr, p.n_slots, shift, bits, hq, lb[q & 1],
+                                             lb_next, ticket, err, s);
+        else e = launch_radix_pass("elem_radix", shape, later, out, p.n_slots, shift, bits, hq, lb[q & 1], lb_next,
+                                   ticket, err, s);
     }
     if (e != hipSuccess) return e;
-    return launch_unique_csr("elem_csr", kb[(p.n_pass - 1) & 1], p.n_slots, count, 32u, p.n_vert, cols, cols_cap, row_ptr, ulb,
-                             hdr + HDR_TICKET0 + TK_CSR, err, s);
+    return launch_rowptr_fill("elem_row_fill", row_ptr, p.n_vert, count, (int32_t*)(w + p.off_bmin), s);
 }
 
 hipError_t run_elem(const ElemPlan& p, const int32_t* conn, int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,

@@ -48,8 +48,8 @@ struct ElemPlan {
     uint32_t id_bits = 1;     // bits of a vertex id
     int n_pass = 0;           // radix passes over the vertex bits
     int64_t n_tiles = 0;      // radix tiles (room for any tile shape)
-    int64_t n_utiles = 0;     // CSR tiles
-    size_t off_hist = 0, off_ulb = 0, off_lb0 = 0, off_lb1 = 0, off_keys0 = 0, off_keys1 = 0;
+    size_t off_hist = 0, off_lb0 = 0, off_lb1 = 0, off_keys0 = 0, off_keys1 = 0;
+    size_t off_bmin = 0;      // block minima of the row-start fill
     size_t zero_bytes = 0;
     size_t total = 0;
 };
@@ -72,11 +72,12 @@ struct BatchPlan {
     int64_t long_cap = 0;
     size_t off_deg = 0, off_src = 0, off_long = 0;
     size_t off_hist2 = 0, off_up = 0, off_low = 0;  // node relation, edge-rows algorithm
+    size_t off_bmin = 0;    // element relation: block minima of the row-start fill
     size_t zero_bytes = 0;
     size_t total = 0;
 };
 
-bool plan_batch(int64_t n_keys, uint32_t digit_bits, int32_t rows_vert, BatchPlan* p);
+bool plan_batch(int64_t n_keys, uint32_t digit_bits, int32_t rows_vert, int32_t total_vert, BatchPlan* p);
 uint32_t batch_node_lo_bits(int32_t max_vert);
 uint32_t batch_hi_bits(int32_t total_vert);
 hipError_t run_batch_node(const BatchPlan& p, const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
@@ -88,7 +89,9 @@ hipError_t run_batch_elem(const BatchPlan& p, const int32_t* conn, const mesh_se
 
 // Node algorithm (process-wide): 0 = LSD sort of the full key, then one
 // unique/CSR pass; 1 = LSD sort of the vertex bits only, then per-row sort
-// and deduplication in LDS, scan and gather.
+// and deduplication in LDS, scan and gather; 2 = each element edge once,
+// keyed by its lower vertex, rows deduplicated, the unique edges transposed
+// and sorted by their higher vertex, both halves merged per row.
 int node_sort_mode();
 
 // Clears `bytes` (a multiple of 4) from `p` with a fill kernel (no memset

@@ -41,6 +41,40 @@ struct is_staged : std::false_type {};
 template <class S>
 struct is_staged<S, std::void_t<decltype(S::kStaged)>> : std::bool_constant<S::kStaged> {};
 
+// Output of a pass.  KeyOut writes every key to its slot.  CsrOut, for the
+// last pass of a sort by the bits above vshift (stable, so each row comes out
+// in input order), writes the low part of each key to cols and the start of
+// every row to row_ptr with atomicMin: a key starts a row where the high part
+// changes inside a tile's run of one digit, and the first key of a run may
+// start one (its predecessor lies in another tile), so it offers its slot and
+// the smallest offer wins.  Every row-start write is the atomic: plain stores
+// mixed with atomics on the same lines cost several times more than either.
+// row_ptr must hold INT32_MAX beforehand; rows with no keys are filled in by
+// rowptr_fill afterwards.
+struct KeyOut {
+    uint64_t* __restrict__ out;
+    __device__ __forceinline__ bool put(uint64_t k, int64_t dst, int, int, const uint64_t*) const {
+        out[dst] = k;
+        return true;
+    }
+};
+
+struct CsrOut {
+    int32_t* __restrict__ cols;
+    int32_t* row_ptr;
+    int64_t cols_cap;
+    uint32_t vshift;
+    uint64_t lo_mask;
+    // false: no room in cols (capacity error)
+    __device__ __forceinline__ bool put(uint64_t k, int64_t dst, int i, int run_first, const uint64_t* s_keys) const {
+        if (dst >= cols_cap) return false;
+        cols[dst] = (int32_t)(k & lo_mask);
+        const uint64_t v = k >> vshift;
+        if (i == run_first || v != (s_keys[i - 1] >> vshift)) atomicMin(&row_ptr[v], (int32_t)dst);
+        return true;
+    }
+};
+
 template <class Src>
 __device__ __forceinline__ int64_t source_limit(const Src&, int64_t n) {
     return n;
@@ -84,8 +118,8 @@ constexpr int DEFAULT_RADIX_SHAPE = 0;
 // of every digit value over the participating keys of the whole pass.  When
 // Src::kSkipNone is set, KEY_NONE marks a position without a key.
 // ---------------------------------------------------------------------------
-template <int BLOCK, int ITEMS, class Src>
-__global__ __launch_bounds__(BLOCK) void radix_pass_kernel(Src src, uint64_t* __restrict__ out, int64_t n,
+template <int BLOCK, int ITEMS, class Src, class Out>
+__global__ __launch_bounds__(BLOCK) void radix_pass_kernel(Src src, Out out, int64_t n,
                                                           uint32_t shift, uint32_t bits,
                                                           const uint32_t* __restrict__ hist, uint64_t* lookback,
                                                           uint64_t* lookback_next, uint32_t* ticket, uint32_t* err) {
@@ -215,29 +249,30 @@ __global__ __launch_bounds__(BLOCK) void radix_pass_kernel(Src src, uint64_t* __
     }
     __syncthreads();
     const int64_t limit = hist_total;  // participating keys of the pass = output size
-    bool bad = false;
+    bool bad = false, full = false;
     for (int i = tid; i < (int)tile_total; i += BLOCK) {
         const uint64_t k = s_keys[i];
         const uint32_t dg = (uint32_t)(k >> shift) & dmask;
         const int64_t dst = s_glob[dg] + i;
-        if ((uint64_t)dst < (uint64_t)limit) out[dst] = k;
+        if ((uint64_t)dst < (uint64_t)limit) full |= !out.put(k, dst, i, (int)s_tile_off[dg], s_keys);
         else bad = true;
     }
     if (bad) set_error(err, ERR_INTERNAL);
+    if (full) set_error(err, ERR_CAPACITY);
 }
 
-template <int BLOCK, int ITEMS, class Src>
-hipError_t launch_radix_shape(const char* name, Src src, uint64_t* out, int64_t n, uint32_t shift, uint32_t bits, const uint32_t* hist,
+template <int BLOCK, int ITEMS, class Src, class Out>
+hipError_t launch_radix_shape(const char* name, Src src, Out out, int64_t n, uint32_t shift, uint32_t bits, const uint32_t* hist,
                               uint64_t* lb, uint64_t* lb_next, uint32_t* ticket, uint32_t* err, hipStream_t s) {
     const int64_t tiles = ceil_div(n, (int64_t)BLOCK * ITEMS);
-    return launch(name, radix_pass_kernel<BLOCK, ITEMS, Src>, dim3((unsigned)tiles), dim3(BLOCK), s, src,
+    return launch(name, radix_pass_kernel<BLOCK, ITEMS, Src, Out>, dim3((unsigned)tiles), dim3(BLOCK), s, src,
                   out, n, shift, bits, hist, lb, lb_next, ticket, err);
 }
 
 // Launches one radix pass with tile shape RADIX_SHAPES[shape].  The look-back
 // arrays need room for ceil(n / min_radix_tile()) tiles.
-template <class Src>
-hipError_t launch_radix_pass(const char* name, int shape, Src src, uint64_t* out, int64_t n, uint32_t shift, uint32_t bits,
+template <class Src, class Out>
+hipError_t launch_radix_pass(const char* name, int shape, Src src, Out out, int64_t n, uint32_t shift, uint32_t bits,
                              const uint32_t* hist, uint64_t* lb, uint64_t* lb_next, uint32_t* ticket, uint32_t* err,
                              hipStream_t s) {
     switch (shape) {
@@ -247,6 +282,13 @@ hipError_t launch_radix_pass(const char* name, int shape, Src src, uint64_t* out
         case 4: return launch_radix_shape<1024, 8>(name, src, out, n, shift, bits, hist, lb, lb_next, ticket, err, s);
         default: return launch_radix_shape<512, 16>(name, src, out, n, shift, bits, hist, lb, lb_next, ticket, err, s);
     }
+}
+
+template <class Src>
+hipError_t launch_radix_pass(const char* name, int shape, Src src, uint64_t* out, int64_t n, uint32_t shift,
+                             uint32_t bits, const uint32_t* hist, uint64_t* lb, uint64_t* lb_next, uint32_t* ticket,
+                             uint32_t* err, hipStream_t s) {
+    return launch_radix_pass(name, shape, src, KeyOut{out}, n, shift, bits, hist, lb, lb_next, ticket, err, s);
 }
 
 constexpr int min_radix_tile() {
