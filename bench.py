@@ -78,6 +78,9 @@ def kernel_bytes(m, nnz_node, nnz_elem, node_sort):
     elem_passes = (id_bits + 7) // 8
     csr_out = 4 * q_pairs + 4 * (v + 1)                      # cols and row starts
     later = [16 * q_pairs] * (elem_passes - 2) + [8 * q_pairs + csr_out]
+    # edge passes sort the E transposed edges by their higher vertex (id_bits);
+    # the last one writes the lower neighbours and their group starts
+    edge_passes = [16 * e] * (elem_passes - 1) + [8 * e + 4 * e + 4 * (v + 1)]
     return {
         "node_hist": conn,                                  # read conn
         "node_radix_first": conn + 8 * keys,                # read conn, write keys
@@ -89,9 +92,9 @@ def kernel_bytes(m, nnz_node, nnz_elem, node_sort):
         "node_long_rows": 0,                                # only rows past the short limit; data-dependent
         "node_edge_transpose": 4 * e + 12 * v + 12 * e,     # row values, up_ptr/deg/src in; keys + ids out
         "node_edge_hist": 8 * e,
-        "node_edge_radix": 16 * e,
-        "node_edge_low_ptr": 8 * e + 4 * (v + 1),
-        "node_edge_merge": 12 * e + 8 * (v + 1) + 4 * u + 4 * (v + 1),
+        "node_edge_radix": sum(edge_passes) // len(edge_passes),
+        "node_edge_low_fill": 4 * (v + 1),
+        "node_edge_merge": 8 * e + 8 * (v + 1) + 4 * u + 4 * (v + 1),
         "elem_hist": conn,
         "elem_radix_first": conn + (8 * q_pairs if elem_passes > 1 else csr_out),
         "elem_radix": sum(later) // len(later) if elem_passes > 1 else 0,

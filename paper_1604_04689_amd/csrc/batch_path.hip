@@ -598,7 +598,7 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
         EdgeStage g{up_ptr, r.deg, r.src, r.temp, total_vert, csr_lo_bits, segs, n_mesh, p.n_keys,
                     {kb[(p.n_pass - 1) & 1], kb[(p.n_pass - 1) & 1] + p.n_keys}, (int32_t*)kb[p.n_pass & 1] + p.n_keys,
                     (uint32_t*)(w + p.off_hist2), {lb[0], lb[1]}, p.n_pass & 1, hdr + HDR_TICKET0 + 8, shape,
-                    p.n_pass, p.digit_bits, (int32_t*)(w + p.off_low), err};
+                    p.n_pass, p.digit_bits, (int32_t*)(w + p.off_low), (int32_t*)(w + p.off_bmin), err};
         return launch_edge_stage(g, row_ptr, cols, cols_cap, s);
     }
     return launch_unique_csr("batch_node_csr", kb[(p.n_pass - 1) & 1], p.n_keys, (const uint32_t*)nullptr,

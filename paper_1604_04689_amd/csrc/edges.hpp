@@ -17,6 +17,7 @@
 #include "../../include/mesh_neighbors.h"
 #include "common.hpp"
 #include "launch.hpp"
+#include "csr.hpp"
 #include "radix.hpp"
 
 namespace mnb {
@@ -24,7 +25,6 @@ namespace mnb {
 constexpr int EDGE_BLOCK = 256;  // vertices per block in transpose and merge
 constexpr int KH_BLOCK = 512;
 constexpr int KH_GRID_MAX = 1024;
-constexpr int LOWPTR_BLOCK = 256;
 constexpr int MAX_KH_PASS = 4;  // 31 vertex bits
 
 // With BATCH, row vertices are global (vert_off[m] + local) and neighbour
@@ -110,37 +110,14 @@ static __global__ __launch_bounds__(KH_BLOCK) void key_hist_kernel(const uint64_
         if (s_hist[i]) atomicAdd(&hist[i], s_hist[i]);
 }
 
-// low_ptr[v] = first index of the keys (sorted by hi = key >> b) whose hi is
-// at least v, for v in [0, n_vert]; the keys are keys[0 .. *count).  A
-// position where hi changes writes the entries of the vertices it passes.
-static __global__ __launch_bounds__(LOWPTR_BLOCK) void low_ptr_kernel(const uint64_t* __restrict__ keys,
-                                                                     int64_t n_cap, const int32_t* __restrict__ count,
-                                                                     uint32_t b, int32_t n_vert,
-                                                                     int32_t* __restrict__ low_ptr) {
-    const int64_t n = *count;
-    const int64_t stride = (int64_t)gridDim.x * LOWPTR_BLOCK;
-    const int64_t gid = (int64_t)blockIdx.x * LOWPTR_BLOCK + threadIdx.x;
-    if (n == 0) {  // no edges: every group is empty
-        for (int64_t v = gid; v <= n_vert; v += stride) low_ptr[v] = 0;
-        return;
-    }
-    for (int64_t i = gid; i < n && i < n_cap; i += stride) {
-        const int64_t w = (int64_t)(keys[i] >> b);
-        const int64_t prev = i > 0 ? (int64_t)(keys[i - 1] >> b) : -1;
-        if (w != prev)
-            for (int64_t v = prev + 1; v <= w && v <= n_vert; ++v) low_ptr[v] = (int32_t)i;
-        if (i == n - 1)
-            for (int64_t v = w + 1; v <= n_vert; ++v) low_ptr[v] = (int32_t)n;
-    }
-}
-
-// row_ptr and cols of the node relation from the lower groups (sorted
-// transposed keys) and the higher rows (up_cols).
+// row_ptr and cols of the node relation from the lower groups (low_cols,
+// each vertex's lower neighbours from low_ptr[v]) and the higher rows (up_cols
+// from up_ptr[v]).
 static __global__ __launch_bounds__(EDGE_BLOCK) void edge_merge_kernel(const int32_t* __restrict__ low_ptr,
                                                                      const int32_t* __restrict__ up_ptr,
-                                                                     const uint64_t* __restrict__ tsorted,
+                                                                     const int32_t* __restrict__ low_cols,
                                                                      const int32_t* __restrict__ up_cols,
-                                                                     int32_t n_vert, uint32_t b,
+                                                                     int32_t n_vert,
                                                                      int32_t* __restrict__ row_ptr,
                                                                      int32_t* __restrict__ cols, int64_t cols_cap,
                                                                      uint32_t* err) {
@@ -170,7 +147,6 @@ static __global__ __launch_bounds__(EDGE_BLOCK) void edge_merge_kernel(const int
         if (tid == 0) set_error(err, ERR_CAPACITY);
         return;
     }
-    const uint64_t lo_mask = (1ull << b) - 1;
     for (int64_t i = a + tid; i < e; i += EDGE_BLOCK) {
         int lo = 0, hi = nv - 1;  // last row whose start <= i
         while (lo < hi) {
@@ -179,7 +155,7 @@ static __global__ __launch_bounds__(EDGE_BLOCK) void edge_merge_kernel(const int
             else hi = mid - 1;
         }
         const int o = (int)(i - s_start[lo]);
-        cols[i] = o < s_nlow[lo] ? (int32_t)(tsorted[s_low[lo] + o] & lo_mask) : up_cols[s_up[lo] + (o - s_nlow[lo])];
+        cols[i] = o < s_nlow[lo] ? low_cols[s_low[lo] + o] : up_cols[s_up[lo] + (o - s_nlow[lo])];
     }
 }
 
@@ -187,12 +163,15 @@ static __global__ __launch_bounds__(EDGE_BLOCK) void edge_merge_kernel(const int
 // the scan of the higher-neighbour counts (up_ptr[n_vert] = E); keys[2] are
 // two buffers of n_edges keys each (the transposed edges ping-pong between
 // them), up_cols n_edges ints, hist2 zeroed, lb[l0] cleared for n_edges keys
-// and lb[l0 ^ 1] for later clearing; tickets[0 .. n_pass) zero.
+// and lb[l0 ^ 1] for later clearing; tickets[0 .. n_pass) zero.  temp (the
+// row values, dead once transposed) takes the lower neighbours, written by
+// the last pass with their group starts in low_ptr (n_vert + 1 ints);
+// block_min holds ceil((n_vert + 1) / RF_TILE) ints.
 struct EdgeStage {
     const int32_t* up_ptr;
     const int32_t* deg;
     const int64_t* src;
-    const int32_t* temp;
+    int32_t* temp;
     int32_t n_vert;
     uint32_t b;
     const mesh_segment* segs;  // batches (null for one mesh)
@@ -207,6 +186,7 @@ struct EdgeStage {
     int shape, n_pass;
     uint32_t hi_bits;
     int32_t* low_ptr;
+    int32_t* block_min;
     uint32_t* err;
 };
 
@@ -225,24 +205,30 @@ static inline hipError_t launch_edge_stage(const EdgeStage& g, int32_t* row_ptr,
         e = launch(batch ? "batch_node_edge_hist" : "node_edge_hist", key_hist_kernel,
                    dim3((unsigned)tmin<int64_t>(ceil_div(g.n_edges, KH_BLOCK), KH_GRID_MAX)), dim3(KH_BLOCK), s,
                    (const uint64_t*)g.keys[0], E, g.b, g.n_pass, last_bits, g.hist2);
+    if (e == hipSuccess) e = fill_i32(g.low_ptr, (int64_t)g.n_vert + 1, INT32_MAX, s);
+    // the last pass writes the lower neighbours (low bits) and offers the
+    // start of each vertex's group
+    const CsrOut low{g.temp, g.low_ptr, g.n_edges, g.b, (1ull << g.b) - 1};
+    const char* rname = batch ? "batch_node_edge_radix" : "node_edge_radix";
     for (int q = 0; q < g.n_pass && e == hipSuccess; ++q) {
         const uint32_t shift = g.b + (uint32_t)q * RBITS;
         const uint32_t bits = tmin<uint32_t>(RBITS, g.hi_bits - (uint32_t)q * RBITS);
         const int l = g.l0 ^ (q & 1);  // look-back array, cleared by the previous pass
-        uint64_t* lb_next = q + 1 < g.n_pass ? g.lb[l ^ 1] : nullptr;
-        e = launch_radix_pass(batch ? "batch_node_edge_radix" : "node_edge_radix", g.shape,
-                              CountedKeySrc{g.keys[q & 1], (const uint32_t*)E}, g.keys[(q + 1) & 1], g.n_edges, shift,
-                              bits, g.hist2 + q * RADIX, g.lb[l], lb_next, g.tickets + q, g.err, s);
+        const CountedKeySrc src{g.keys[q & 1], (const uint32_t*)E};
+        if (q + 1 < g.n_pass)
+            e = launch_radix_pass(rname, g.shape, src, g.keys[(q + 1) & 1], g.n_edges, shift, bits,
+                                  g.hist2 + q * RADIX, g.lb[l], g.lb[l ^ 1], g.tickets + q, g.err, s);
+        else
+            e = launch_radix_pass(rname, g.shape, src, low, g.n_edges, shift, bits, g.hist2 + q * RADIX, g.lb[l],
+                                  nullptr, g.tickets + q, g.err, s);
     }
-    const uint64_t* sorted = g.keys[g.n_pass & 1];
     if (e == hipSuccess)
-        e = launch(batch ? "batch_node_edge_low_ptr" : "node_edge_low_ptr", low_ptr_kernel,
-                   dim3((unsigned)tmin<int64_t>(ceil_div(g.n_edges, LOWPTR_BLOCK) + 1, 4096)), dim3(LOWPTR_BLOCK), s,
-                   sorted, g.n_edges, E, g.b, g.n_vert, g.low_ptr);
+        e = launch_rowptr_fill(batch ? "batch_node_edge_low_fill" : "node_edge_low_fill", g.low_ptr, g.n_vert,
+                               (const uint32_t*)E, g.block_min, s);
     if (e == hipSuccess)
         e = launch(batch ? "batch_node_edge_merge" : "node_edge_merge", edge_merge_kernel, dim3(vgrid),
-                   dim3(EDGE_BLOCK), s, (const int32_t*)g.low_ptr, g.up_ptr, sorted, (const int32_t*)g.up_cols,
-                   g.n_vert, g.b, row_ptr, cols, cols_cap, g.err);
+                   dim3(EDGE_BLOCK), s, (const int32_t*)g.low_ptr, g.up_ptr, (const int32_t*)g.temp,
+                   (const int32_t*)g.up_cols, g.n_vert, row_ptr, cols, cols_cap, g.err);
     return e;
 }
 

@@ -31,6 +31,7 @@ struct NodePlan {
     int64_t n_edges = 0;      // edge-rows mode: canonical keys (one per element edge)
     size_t off_hist2 = 0;     // edge-rows mode: digit histograms of the transposed edges
     size_t off_up = 0, off_low = 0;  // edge-rows mode: starts of higher and lower neighbours
+    size_t off_bmin = 0;      // edge-rows mode: block minima of the lower-group fill
     size_t zero_bytes = 0;    // bytes from 0 cleared at the start of a call
     size_t total = 0;
 };
@@ -72,7 +73,7 @@ struct BatchPlan {
     int64_t long_cap = 0;
     size_t off_deg = 0, off_src = 0, off_long = 0;
     size_t off_hist2 = 0, off_up = 0, off_low = 0;  // node relation, edge-rows algorithm
-    size_t off_bmin = 0;    // element relation: block minima of the row-start fill
+    size_t off_bmin = 0;    // block minima of a row-start fill (element rows, lower groups)
     size_t zero_bytes = 0;
     size_t total = 0;
 };

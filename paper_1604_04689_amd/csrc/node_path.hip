@@ -250,6 +250,8 @@ bool plan_node(int64_t n_elem, int32_t etype, int32_t n_vert, NodePlan* p) {
     off += align_up(((size_t)n_vert + 1) * sizeof(int32_t));
     p->off_low = off;
     off += align_up(((size_t)n_vert + 1) * sizeof(int32_t));
+    p->off_bmin = off;  // edge-rows mode: block minima of the lower-group fill
+    off += align_up((size_t)ceil_div((int64_t)n_vert + 1, (int64_t)RF_TILE) * sizeof(int32_t));
     p->total = off;
     return true;
 }
@@ -324,7 +326,7 @@ static hipError_t node_pipeline(const NodePlan& p, const int32_t* conn, int32_t*
     EdgeStage g{up_ptr, r.deg, r.src, r.temp, p.n_vert, p.id_bits, nullptr, 0, p.n_edges,
                 {kb[(n_pass - 1) & 1], kb[(n_pass - 1) & 1] + p.n_edges}, (int32_t*)kb[n_pass & 1] + p.n_edges,
                 (uint32_t*)(w + p.off_hist2), {lb[0], lb[1]}, n_pass & 1, tickets + 8, shape, n_pass, p.hi_bits,
-                low_ptr, err};
+                low_ptr, (int32_t*)(w + p.off_bmin), err};
     e = launch_edge_stage(g, row_ptr, cols, cols_capacity, s);
     return e;
 }
