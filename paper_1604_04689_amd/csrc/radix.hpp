@@ -118,11 +118,21 @@ constexpr int DEFAULT_RADIX_SHAPE = 0;
 // of every digit value over the participating keys of the whole pass.  When
 // Src::kSkipNone is set, KEY_NONE marks a position without a key.
 // ---------------------------------------------------------------------------
+// Waves per SIMD when as many blocks share a CU as its 160 KB of LDS allow:
+// the register budget the kernel is compiled for (more registers than that
+// would leave a block's worth of LDS idle).
+constexpr int radix_waves_per_eu(int block, int items) {
+    const int lds = 8 * block * items + (block / WAVE) * RADIX * 4 + 4 * RADIX * 4 + 256;
+    int blocks = (160 * 1024) / lds;
+    if (blocks < 1) blocks = 1;
+    const int w = blocks * (block / WAVE) / 4;
+    return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
 template <int BLOCK, int ITEMS, class Src, class Out>
-__global__ __launch_bounds__(BLOCK) void radix_pass_kernel(Src src, Out out, int64_t n,
-                                                          uint32_t shift, uint32_t bits,
-                                                          const uint32_t* __restrict__ hist, uint64_t* lookback,
-                                                          uint64_t* lookback_next, uint32_t* ticket, uint32_t* err) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(radix_waves_per_eu(BLOCK, ITEMS))))
+void radix_pass_kernel(Src src, Out out, int64_t n, uint32_t shift, uint32_t bits, const uint32_t* __restrict__ hist,
+                       uint64_t* lookback, uint64_t* lookback_next, uint32_t* ticket, uint32_t* err) {
     static_assert(BLOCK >= RADIX, "one thread per digit");
     constexpr int WAVES = BLOCK / WAVE;
     constexpr int TILE = BLOCK * ITEMS;
@@ -204,19 +214,34 @@ __global__ __launch_bounds__(BLOCK) void radix_pass_kernel(Src src, Out out, int
     }
 
     // ---- 3. rank within the wave ---------------------------------------------
+    // peers = valid lanes whose digit equals this lane's, kept as two 32-bit
+    // halves: per digit bit, m is all ones where the bit is set, and a lane
+    // keeps the voters that agree with it, peers &= ~(vote ^ m), one
+    // three-input bitwise instruction per half.  Every lane of a digit holds
+    // the same peers, so all of them read the wave's counter and store the
+    // same new value: no leader, no branch, and the items' rank chains can
+    // overlap.  (Invalid lanes carry a digit in range and store what their
+    // digit's valid lanes store, or the unchanged count.)
     const uint64_t lt_mask = (1ull << lane) - 1;
-    uint32_t rank[ITEMS];
+    // ranks are below TILE <= 2^16: two per register
+    static_assert(TILE <= 65536, "16-bit ranks");
+    uint32_t rank2[(ITEMS + 1) / 2] = {};
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const bool valid = (valid_bits >> j) & 1u;
         const uint32_t dg = (uint32_t)(key[j] >> shift) & dmask;
-        uint64_t peers = __ballot(valid);
+        const uint64_t vv = __ballot(valid);
+        uint32_t plo = (uint32_t)vv, phi = (uint32_t)(vv >> 32);
 #pragma unroll
         for (int bit = 0; bit < RBITS; ++bit) {
-            const bool on = (dg >> bit) & 1u;
-            const uint64_t vote = __ballot(on);
-            peers &= on ? vote : ~vote;
+            uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int32_t)dg, bit, 1);
+            asm("" : "+v"(m));  // keeps the vote a compare of m itself
+            const uint64_t vote = __ballot(m != 0);
+            plo &= ~((uint32_t)vote ^ m);
+            phi &= ~((uint32_t)(vote >> 32) ^ m);
+            asm("" : "+v"(plo), "+v"(phi));  // one three-input op per half
         }
+        const uint64_t peers = ((uint64_t)phi << 32) | plo;
         const uint32_t below = __popcll(peers & lt_mask);
         const int leader = __ffsll((unsigned long long)peers) - 1;
         uint32_t base = 0;
@@ -225,7 +250,7 @@ __global__ __launch_bounds__(BLOCK) void radix_pass_kernel(Src src, Out out, int
             s_whist[wid][dg] = base + (uint32_t)__popcll(peers);
         }
         base = __shfl(base, leader & (WAVE - 1), WAVE);
-        rank[j] = base + below;
+        rank2[j / 2] |= (base + below) << (16 * (j & 1));
     }
     __syncthreads();
     if (tid < RADIX) {
@@ -244,7 +269,8 @@ __global__ __launch_bounds__(BLOCK) void radix_pass_kernel(Src src, Out out, int
     for (int j = 0; j < ITEMS; ++j) {
         if ((valid_bits >> j) & 1u) {
             const uint32_t dg = (uint32_t)(key[j] >> shift) & dmask;
-            s_keys[s_tile_off[dg] + s_whist[wid][dg] + rank[j]] = key[j];
+            const uint32_t rank = (rank2[j / 2] >> (16 * (j & 1))) & 0xffffu;
+            s_keys[s_tile_off[dg] + s_whist[wid][dg] + rank] = key[j];
         }
     }
     __syncthreads();
