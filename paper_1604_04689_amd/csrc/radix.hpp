@@ -147,6 +147,12 @@ void radix_pass_kernel(Src src, Out out, int64_t n, uint32_t shift, uint32_t bit
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
     const int wid = tid / WAVE;
+    // With a device-side count below n, only the first ceil(count / TILE)
+    // blocks take tickets, so those tickets are exactly the tiles that hold
+    // keys; the other blocks leave before touching the ticket counter (a
+    // single-address atomic that every block would otherwise queue on).
+    const int64_t limit_n = source_limit(src, n);
+    if ((int64_t)blockIdx.x * TILE >= limit_n) return;
     if (tid == 0) s_tile = atomicAdd(ticket, 1u);
     for (int i = tid; i < WAVES * RADIX; i += BLOCK) (&s_whist[0][0])[i] = 0;
     for (int i = tid; i < RADIX; i += BLOCK) s_cnt[i] = 0;
@@ -157,11 +163,8 @@ void radix_pass_kernel(Src src, Out out, int64_t n, uint32_t shift, uint32_t bit
 
     // ---- 1. load (lanes of a wave read 64 consecutive positions), count ------
     const int64_t wbase = tile_base + (int64_t)wid * WAVE * ITEMS + lane;
-    const int64_t limit_n = source_limit(src, n);
-    // A tile wholly past the participating keys (a device-side count below n)
-    // has nothing to place, and every later tile is past them too, so no tile
-    // ever looks back at it: it leaves at once (its status and next-pass slots
-    // are never read).
+    // (No ticket reaches past the participating keys: see above.  A tile past
+    // them would have nothing to place, and no tile would ever look back at it.)
     if (tile_base >= limit_n) return;
     uint64_t key[ITEMS];
     uint32_t valid_bits = 0;
