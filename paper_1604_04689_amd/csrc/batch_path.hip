@@ -66,52 +66,132 @@ __device__ __forceinline__ int lut_segment(const mesh_segment* __restrict__ segs
     return find_segment<FIELD>(segs, lut[t], lut[t + 1], i);
 }
 
-// Per radix tile (TILE consecutive keys): the mesh all of its keys lie in,
-// or etype = -1 if they span several meshes.  Built once per call so that a
-// tile reads one record, not a chain of lookups, before staging its ids.
+// Per radix tile (TILE consecutive keys): the mesh all of its keys lie in;
+// or, for a tile across at most MAX_TILE_SEGS meshes whose ids and keys are
+// contiguous (as the offsets of a packed batch are), those meshes; else
+// etype = -1 (the per-key path).  Built once per call so that a tile reads
+// one record, not a chain of lookups, before staging its ids.
+constexpr int TILE_MULTI = -2;
+constexpr int MAX_TILE_SEGS = 8;
+constexpr int SEG_WORDS = 8;  // staged record of one mesh of a TILE_MULTI tile
 struct TileRec {
-    int32_t etype;     // -1: keys of several meshes (the tile takes the per-key path)
+    int32_t etype;     // >= 0 one mesh; TILE_MULTI several; -1 per-key path
     int32_t n_vert;
     int32_t vert_off;
-    uint32_t e0;       // first element of the tile, local to its mesh
-    int32_t cnt;       // ids to stage: whole elements e0 .. e1
-    int32_t reserved;
-    int64_t off;       // pair_off (node) or slot_off (element) of the mesh
+    uint32_t e0;       // first element of the tile, local to its (first) mesh
+    int32_t cnt;       // ids to stage: whole elements from e0 to the tile's last
+    int32_t m0;        // TILE_MULTI: first mesh
+    int64_t off;       // key offset of the mesh (one mesh)
     int64_t ids;       // index in conn of the first staged id
-    int64_t reserved2;
+    int32_t n_seg;     // TILE_MULTI: meshes
+    int32_t reserved;
 };
 static_assert(sizeof(TileRec) == 48, "TileRec layout");
 
 // KIND: 0 element slots, 1 directed pairs, 2 canonical edges (keys of which
-// are looked up in the pair table at twice their index).
+// are looked up in the pair table at twice their index).  ids_cap: the most
+// ids the source's staging area holds.
+template <int KIND>
+__device__ __forceinline__ int64_t seg_key_off(const mesh_segment& sg) {
+    return KIND == 2 ? sg.pair_off / 2 : KIND == 1 ? sg.pair_off : sg.slot_off;
+}
+template <int KIND>
+__device__ __forceinline__ int seg_keys_per_elem(int32_t et) {
+    return KIND == 2 ? edges_per_elem(et) : KIND == 1 ? 2 * edges_per_elem(et) : nodes_per_elem(et);
+}
+
 template <int KIND>
 static __global__ __launch_bounds__(LUT_BLOCK) void tile_table_kernel(const mesh_segment* __restrict__ segs,
                                                                      const int32_t* __restrict__ lut, int64_t n,
                                                                      int64_t tile, TileRec* __restrict__ recs,
-                                                                     int64_t n_tiles) {
+                                                                     int64_t n_tiles, int32_t ids_cap) {
     constexpr int FIELD = KIND ? (int)offsetof(mesh_segment, pair_off) : (int)offsetof(mesh_segment, slot_off);
     constexpr int SCALE = KIND == 2 ? 2 : 1;
     const int64_t t = (int64_t)blockIdx.x * LUT_BLOCK + threadIdx.x;
     if (t >= n_tiles) return;
     const int64_t base = t * tile, last = tmin<int64_t>(base + tile, n) - 1;
     const int m0 = lut_segment<FIELD>(segs, lut, base * SCALE), m1 = lut_segment<FIELD>(segs, lut, last * SCALE);
-    const mesh_segment& sg = segs[m0];
-    const int npe = nodes_per_elem(sg.etype);
-    const int per = KIND == 2 ? edges_per_elem(sg.etype) : KIND == 1 ? 2 * edges_per_elem(sg.etype) : npe;
-    const int64_t off = KIND ? sg.pair_off / SCALE : sg.slot_off;  // first key of the mesh
     TileRec r{};
     r.etype = -1;
-    if (m0 == m1 && per > 0 && base >= off && last < off + per * sg.n_elem) {
-        const uint32_t e0 = (uint32_t)((base - off) / per), e1 = (uint32_t)((last - off) / per);
-        r.etype = sg.etype;
-        r.n_vert = sg.n_vert;
-        r.vert_off = sg.vert_off;
-        r.e0 = e0;
-        r.cnt = (int32_t)(e1 - e0 + 1u) * npe;
-        r.off = off;
-        r.ids = sg.conn_off + (int64_t)e0 * npe;
+    const mesh_segment& sg = segs[m0];
+    const int per0 = seg_keys_per_elem<KIND>(sg.etype);
+    const int64_t off0 = seg_key_off<KIND>(sg);  // first key of the mesh
+    if (per0 == 0 || base < off0 || base >= off0 + per0 * sg.n_elem) {
+        recs[t] = r;  // inconsistent records: the per-key path reports them
+        return;
+    }
+    const uint32_t e0 = (uint32_t)((base - off0) / per0);
+    if (m0 == m1) {
+        if (last < off0 + per0 * sg.n_elem) {
+            const uint32_t e1 = (uint32_t)((last - off0) / per0);
+            r.etype = sg.etype;
+            r.n_vert = sg.n_vert;
+            r.vert_off = sg.vert_off;
+            r.e0 = e0;
+            r.cnt = (int32_t)(e1 - e0 + 1u) * nodes_per_elem(sg.etype);
+            r.off = off0;
+            r.ids = sg.conn_off + (int64_t)e0 * nodes_per_elem(sg.etype);
+        }
+    } else if (m1 - m0 < MAX_TILE_SEGS) {
+        bool ok = true;
+        for (int m = m0; m < m1 && ok; ++m) {
+            const mesh_segment& a = segs[m];
+            const mesh_segment& b = segs[m + 1];
+            const int per = seg_keys_per_elem<KIND>(a.etype);
+            ok = (per > 0 || a.n_elem == 0) && seg_key_off<KIND>(a) + per * a.n_elem == seg_key_off<KIND>(b) &&
+                 a.conn_off + (int64_t)nodes_per_elem(a.etype) * a.n_elem == b.conn_off;
+        }
+        const mesh_segment& sl = segs[m1];
+        const int per1 = seg_keys_per_elem<KIND>(sl.etype);
+        const int64_t off1 = seg_key_off<KIND>(sl);
+        ok = ok && per1 > 0 && last >= off1 && last < off1 + per1 * sl.n_elem;
+        if (ok) {
+            const int64_t ids0 = sg.conn_off + (int64_t)e0 * nodes_per_elem(sg.etype);
+            const int64_t ids1 = sl.conn_off + ((last - off1) / per1 + 1) * nodes_per_elem(sl.etype);
+            if (ids1 - ids0 <= ids_cap) {
+                r.etype = TILE_MULTI;
+                r.e0 = e0;
+                r.cnt = (int32_t)(ids1 - ids0);
+                r.m0 = m0;
+                r.n_seg = m1 - m0 + 1;
+                r.ids = ids0;
+            }
+        }
     }
     recs[t] = r;
+}
+
+// Stages a TILE_MULTI tile's mesh records (SEG_WORDS words each, after the
+// ids area): type, n_vert, vert_off, npe, first id relative to the staged
+// ids, key offset (two words).
+template <int KIND>
+__device__ __forceinline__ void stage_seg_records(const mesh_segment* __restrict__ segs, const TileRec& r,
+                                                  int32_t* rec, int tid) {
+    if (tid < r.n_seg) {
+        const mesh_segment& sg = segs[r.m0 + tid];
+        int32_t* q = rec + tid * SEG_WORDS;
+        q[0] = sg.etype;
+        q[1] = sg.n_vert;
+        q[2] = sg.vert_off;
+        q[3] = nodes_per_elem(sg.etype);
+        q[4] = (int32_t)(sg.conn_off - r.ids);
+        const int64_t ko = seg_key_off<KIND>(sg);
+        q[6] = (int32_t)ko;
+        q[7] = (int32_t)(ko >> 32);
+    }
+}
+
+// The record of a TILE_MULTI tile's mesh that holds key i (the last one
+// whose key offset is at most i; empty meshes share their successor's).
+__device__ __forceinline__ const int32_t* find_seg_record(const int32_t* rec, int n_seg, int64_t i) {
+    int k = 0;
+#pragma unroll
+    for (int kk = 1; kk < MAX_TILE_SEGS; ++kk) {
+        const int32_t* q = rec + kk * SEG_WORDS;
+        const int64_t ko = (int64_t)(((uint64_t)(uint32_t)q[7] << 32) | (uint32_t)q[6]);
+        if (kk < n_seg && ko <= i) k = kk;
+    }
+    return rec + k * SEG_WORDS;
 }
 
 // Element, edge nodes and direction of local pair index loc of a mesh of
@@ -192,25 +272,27 @@ struct BatchNodeKeySrc {
         return make(i, &bad);
     }
 
-    // ---- staged path: a tile whose keys all lie in one mesh copies that
-    // mesh's element ids into LDS once (coalesced) and builds its keys there;
-    // other tiles use make().  Header words: [0] 1 if staged, [1] type,
-    // [2] n_vert, [3] vert_off, [4] first staged element, [6..7] key offset
-    // of the mesh.
+    // ---- staged path: a tile whose keys all lie in one mesh, or in a few
+    // contiguous ones, copies their element ids into LDS once (coalesced) and
+    // builds its keys there; other tiles use make().  Header words: [0] 1 one
+    // mesh, 2 several, 0 not staged; [1] type (one mesh) or mesh count;
+    // [2] n_vert, [3] vert_off, [4] first staged element, [6..7] key offset of
+    // the mesh.  Several meshes: their records follow the ids area.
     static constexpr bool kStaged = true;
+    static constexpr int ids_cap(int tile) { return (CANON ? tile : tile / 2) + 16; }
     template <int TILE>
-    static constexpr int stage_words() { return STAGE_HDR + (CANON ? TILE : TILE / 2) + 16; }
+    static constexpr int stage_words() { return STAGE_HDR + ids_cap(TILE) + MAX_TILE_SEGS * SEG_WORDS; }
 
     template <int BLOCK, int TILE>
     __device__ __forceinline__ void stage(int64_t tile_base, int64_t n, int32_t* s, int tid) const {
         static_assert(stage_words<TILE>() <= 2 * TILE, "staged ids fit the key staging area");
-        constexpr int PER = (stage_words<TILE>() - STAGE_HDR + BLOCK - 1) / BLOCK;
+        constexpr int PER = (ids_cap(TILE) + BLOCK - 1) / BLOCK;
         const TileRec r = tiles[tile_base / TILE];
-        if (r.etype < 0) {
+        if (r.etype == -1) {
             if (tid == 0) s[0] = 0;
             return;
         }
-        const int32_t* src = conn + r.ids;  // r.cnt <= stage_words - STAGE_HDR words
+        const int32_t* src = conn + r.ids;  // r.cnt <= ids_cap words
         int32_t* ids = s + STAGE_HDR;
         int32_t v[PER];
 #pragma unroll
@@ -223,7 +305,14 @@ struct BatchNodeKeySrc {
             const int i = q * BLOCK + tid;
             if (i < r.cnt) ids[i] = v[q];
         }
-        if (tid == 0) {
+        if (r.etype == TILE_MULTI) {
+            stage_seg_records<TABLE_KIND>(segs, r, ids + ids_cap(TILE), tid);
+            if (tid == 0) {
+                s[0] = 2;
+                s[1] = r.n_seg;
+                s[2] = STAGE_HDR + ids_cap(TILE);  // where the records start
+            }
+        } else if (tid == 0) {
             s[0] = 1;
             s[1] = r.etype;
             s[2] = r.n_vert;
@@ -233,9 +322,10 @@ struct BatchNodeKeySrc {
         }
     }
 
-    // the tile's header, read once (wave-uniform values)
+    // the tile's header, read once (wave-uniform values); for several meshes
+    // etype holds their count and n_vert the word offset of their records
     struct Header {
-        int32_t etype, n_vert, vert_off;
+        int32_t multi, etype, n_vert, vert_off;
         uint32_t e0;
         int64_t off;
     };
@@ -244,28 +334,38 @@ struct BatchNodeKeySrc {
     }
     __device__ __forceinline__ Header header(const int32_t* s) const {
         const int64_t off = *(const int64_t*)(s + 6);
-        return {__builtin_amdgcn_readfirstlane(s[1]), __builtin_amdgcn_readfirstlane(s[2]),
-                __builtin_amdgcn_readfirstlane(s[3]), (uint32_t)__builtin_amdgcn_readfirstlane(s[4]),
+        return {__builtin_amdgcn_readfirstlane(s[0]) == 2, __builtin_amdgcn_readfirstlane(s[1]),
+                __builtin_amdgcn_readfirstlane(s[2]), __builtin_amdgcn_readfirstlane(s[3]),
+                (uint32_t)__builtin_amdgcn_readfirstlane(s[4]),
                 (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(off >> 32)) << 32) |
                           (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)off))};
     }
+    // rel: staged position of the mesh's element 0 (negative when the
+    // staged ids start past it); element e sits at rel + e * NPE >= 0
+    template <int ET>
+    __device__ __forceinline__ uint64_t staged_key(const int32_t* ids, int32_t rel, uint32_t loc, int32_t n_vert,
+                                                   int32_t vert_off, bool* bad) const {
+        uint32_t e;
+        int pa, pb, dir;
+        locate<ET>(loc, &e, &pa, &pb, &dir);
+        const int32_t* el = ids + (rel + (int32_t)e * Elem<ET>::NPE);
+        return key_of(el[pa], el[pb], dir, n_vert, vert_off, bad);
+    }
     __device__ __forceinline__ uint64_t load_staged(const Header& h, int64_t i, int64_t tile_base, const int32_t* s,
                                                     bool* bad) const {
-        const uint32_t loc = (uint32_t)(i - h.off);
-        uint32_t e;
-        int pa, pb, dir, npe;
-        if (h.etype == TRI3) {
-            locate<TRI3>(loc, &e, &pa, &pb, &dir);
-            npe = 3;
-        } else if (h.etype == TET4) {
-            locate<TET4>(loc, &e, &pa, &pb, &dir);
-            npe = 4;
-        } else {
-            locate<HEX8>(loc, &e, &pa, &pb, &dir);
-            npe = 8;
+        const int32_t* ids = s + STAGE_HDR;
+        if (h.multi) {
+            const int32_t* q = find_seg_record(s + h.n_vert, h.etype, i);
+            const uint32_t loc = (uint32_t)(i - (int64_t)(((uint64_t)(uint32_t)q[7] << 32) | (uint32_t)q[6]));
+            if (q[0] == TRI3) return staged_key<TRI3>(ids, q[4], loc, q[1], q[2], bad);
+            if (q[0] == TET4) return staged_key<TET4>(ids, q[4], loc, q[1], q[2], bad);
+            return staged_key<HEX8>(ids, q[4], loc, q[1], q[2], bad);
         }
-        const int32_t* el = s + STAGE_HDR + (e - h.e0) * npe;
-        return key_of(el[pa], el[pb], dir, h.n_vert, h.vert_off, bad);
+        const uint32_t loc = (uint32_t)(i - h.off);
+        const int32_t e0 = (int32_t)h.e0;  // staged ids start at element e0
+        if (h.etype == TRI3) return staged_key<TRI3>(ids, -3 * e0, loc, h.n_vert, h.vert_off, bad);
+        if (h.etype == TET4) return staged_key<TET4>(ids, -4 * e0, loc, h.n_vert, h.vert_off, bad);
+        return staged_key<HEX8>(ids, -8 * e0, loc, h.n_vert, h.vert_off, bad);
     }
     __device__ __forceinline__ uint64_t load_staged(const Header& h, int64_t i, int64_t tile_base,
                                                     const int32_t* s) const {
@@ -314,21 +414,24 @@ struct BatchElemPairSrc {
         return make(s, &bad);
     }
 
-    // staged path as for BatchNodePairSrc; header [6..7] holds slot_off
+    // staged path as for BatchNodeKeySrc: slot i of a mesh is its conn entry
+    // i, so the staged ids are the tile's slots plus the rest of its first
+    // and last elements (for the repeat check); header [1] holds npe.
     static constexpr bool kStaged = true;
+    static constexpr int ids_cap(int tile) { return tile + 16; }
     template <int TILE>
-    static constexpr int stage_words() { return STAGE_HDR + TILE + 16; }
+    static constexpr int stage_words() { return STAGE_HDR + ids_cap(TILE) + MAX_TILE_SEGS * SEG_WORDS; }
 
     template <int BLOCK, int TILE>
     __device__ __forceinline__ void stage(int64_t tile_base, int64_t n, int32_t* st, int tid) const {
         static_assert(stage_words<TILE>() <= 2 * TILE, "staged ids fit the key staging area");
-        constexpr int PER = (stage_words<TILE>() - STAGE_HDR + BLOCK - 1) / BLOCK;
+        constexpr int PER = (ids_cap(TILE) + BLOCK - 1) / BLOCK;
         const TileRec r = tiles[tile_base / TILE];
-        if (r.etype < 0) {
+        if (r.etype == -1) {
             if (tid == 0) st[0] = 0;
             return;
         }
-        const int32_t* src = conn + r.ids;  // r.cnt <= TILE + 2 * npe words
+        const int32_t* src = conn + r.ids;  // r.cnt <= ids_cap words
         int32_t* ids = st + STAGE_HDR;
         int32_t v[PER];
 #pragma unroll
@@ -341,7 +444,14 @@ struct BatchElemPairSrc {
             const int i = q * BLOCK + tid;
             if (i < r.cnt) ids[i] = v[q];
         }
-        if (tid == 0) {
+        if (r.etype == TILE_MULTI) {
+            stage_seg_records<TABLE_KIND>(segs, r, ids + ids_cap(TILE), tid);
+            if (tid == 0) {
+                st[0] = 2;
+                st[1] = r.n_seg;
+                st[2] = STAGE_HDR + ids_cap(TILE);  // where the records start
+            }
+        } else if (tid == 0) {
             st[0] = 1;
             st[1] = nodes_per_elem(r.etype);
             st[2] = r.n_vert;
@@ -351,8 +461,10 @@ struct BatchElemPairSrc {
         }
     }
 
+    // for several meshes, npe holds their count and n_vert the word offset
+    // of their records
     struct Header {
-        int32_t npe, n_vert, vert_off;
+        int32_t multi, npe, n_vert, vert_off;
         uint32_t e0;
         int64_t off;
     };
@@ -361,27 +473,44 @@ struct BatchElemPairSrc {
     }
     __device__ __forceinline__ Header header(const int32_t* st) const {
         const int64_t off = *(const int64_t*)(st + 6);
-        return {__builtin_amdgcn_readfirstlane(st[1]), __builtin_amdgcn_readfirstlane(st[2]),
-                __builtin_amdgcn_readfirstlane(st[3]), (uint32_t)__builtin_amdgcn_readfirstlane(st[4]),
+        return {__builtin_amdgcn_readfirstlane(st[0]) == 2, __builtin_amdgcn_readfirstlane(st[1]),
+                __builtin_amdgcn_readfirstlane(st[2]), __builtin_amdgcn_readfirstlane(st[3]),
+                (uint32_t)__builtin_amdgcn_readfirstlane(st[4]),
                 (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(off >> 32)) << 32) |
                           (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)off))};
     }
-    __device__ __forceinline__ uint64_t load_staged(const Header& h, int64_t s, int64_t tile_base, const int32_t* st,
-                                                    bool* bad) const {
-        const int npe = h.npe;
-        const uint32_t loc = (uint32_t)(s - h.off);
+    // key of local slot loc of a mesh whose element 0 is staged at rel
+    // (negative when the staged ids start past it)
+    __device__ __forceinline__ static uint64_t staged_key(const int32_t* ids, int32_t rel, int npe, uint32_t loc,
+                                                          int32_t n_vert, int32_t vert_off, bool* bad) {
         const uint32_t e = npe == 3 ? loc / 3u : npe == 4 ? loc >> 2 : loc >> 3;
         const int j = (int)(loc - e * (uint32_t)npe);
-        const int32_t* el = st + STAGE_HDR + (e - h.e0) * npe;
+        const int32_t* el = ids + (rel + (int32_t)e * npe);
         const int32_t v = el[j];
-        if ((uint32_t)v >= (uint32_t)h.n_vert) {
+        if ((uint32_t)v >= (uint32_t)n_vert) {
             *bad = true;
             return KEY_NONE;
         }
         *bad = false;
-        for (int jj = 0; jj < j; ++jj)
-            if (el[jj] == v) return KEY_NONE;  // repeated id inside the element
-        return ((uint64_t)(uint32_t)(h.vert_off + v) << 32) | (uint64_t)e;
+        // a repeated id inside the element counts once: compare with the
+        // element's earlier ids (all reads issued together, up to seven)
+        bool first = true;
+#pragma unroll
+        for (int jj = 0; jj < 7; ++jj) {
+            const int32_t w = el[jj < j ? jj : 0];
+            first &= jj >= j || w != v;
+        }
+        return first ? ((uint64_t)(uint32_t)(vert_off + v) << 32) | (uint64_t)e : KEY_NONE;
+    }
+    __device__ __forceinline__ uint64_t load_staged(const Header& h, int64_t s, int64_t tile_base, const int32_t* st,
+                                                    bool* bad) const {
+        const int32_t* ids = st + STAGE_HDR;
+        if (h.multi) {
+            const int32_t* q = find_seg_record(st + h.n_vert, h.npe, s);
+            const uint32_t loc = (uint32_t)(s - (int64_t)(((uint64_t)(uint32_t)q[7] << 32) | (uint32_t)q[6]));
+            return staged_key(ids, q[4], q[3], loc, q[1], q[2], bad);
+        }
+        return staged_key(ids, -h.npe * (int32_t)h.e0, h.npe, (uint32_t)(s - h.off), h.n_vert, h.vert_off, bad);
     }
     __device__ __forceinline__ uint64_t load_staged(const Header& h, int64_t s, int64_t tile_base,
                                                     const int32_t* st) const {
@@ -539,7 +668,7 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
         e = launch("batch_tile_table", tile_table_kernel<Src::TABLE_KIND>,
                    dim3((unsigned)ceil_div(n_tiles, LUT_BLOCK)),
                    dim3(LUT_BLOCK), s, segs, (const int32_t*)(w + p.off_lut), p.n_keys, tile, (TileRec*)(w + p.off_tiles),
-                   n_tiles);
+                   n_tiles, (int32_t)Src::ids_cap((int)tile));
     const char* hname = node ? "batch_node_hist" : "batch_elem_hist";
     if (e == hipSuccess) {
         const dim3 g(grid), b(BH_BLOCK);

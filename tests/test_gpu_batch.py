@@ -85,6 +85,43 @@ def test_batch_with_long_rows(oracle_mod):
     check_slices(oracle_mod, meshes, got)
 
 
+def test_batch_with_gapped_and_reordered_conn(oracle_mod):
+    """Meshes placed in the connectivity with gaps and out of order: tiles
+    across meshes whose ids are not contiguous must take the per-key path,
+    the contiguous ones the staged path, and both give the oracle's rows."""
+    nb = _nb()
+    rng = np.random.default_rng(91)
+    meshes = [mg.random_mesh(int(rng.integers(50, 1500)), int(rng.integers(20, 600)), i % 3, seed=300 + i)
+              for i in range(30)]
+    # layout: meshes back to back except a few gaps, and meshes 10..12 stored in reverse order
+    order = list(range(30))
+    order[10:13] = [12, 11, 10]
+    offs = [0] * 30
+    pos = 0
+    parts = []
+    for j, i in enumerate(order):
+        if j % 7 == 3:  # a gap of junk ids
+            parts.append(np.full(5, 2 ** 30, dtype=np.int32))
+            pos += 5
+        offs[i] = pos
+        parts.append(meshes[i].conn.reshape(-1))
+        pos += meshes[i].conn.size
+    conn = torch.as_tensor(np.concatenate(parts).astype(np.int32)).to(DEV)
+    desc = [(m.n_elem, m.etype, m.n_vert) for m in meshes]
+    got = {}
+    for kind in ("node", "elem"):
+        b = nb.BatchBuild(kind, desc, DEV, conn_offs=offs)
+        b.launch(conn)
+        rp, cols = b.result()
+        rp_h, cols_h = rp.cpu().numpy(), cols.cpu().numpy()
+        got[kind] = []
+        for seg in b.seg_host:
+            v0, nv = int(seg["vert_off"]), int(seg["n_vert"])
+            a, c = int(rp_h[v0]), int(rp_h[v0 + nv])
+            got[kind].append((rp_h[v0:v0 + nv + 1] - a, cols_h[a:c]))
+    check_slices(oracle_mod, meshes, got)
+
+
 def test_single_mesh_batch_equals_single_call(oracle_mod):
     m = mg.kuhn_tet_grid(9, 3)
     got = run_batch([m])
