@@ -681,6 +681,9 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
         else if (tile == 12288)
             e = launch_shm(hname, batch_hist_kernel<Src, 24>, g, b, shm, s, src, p.n_keys, shift0, p.n_pass, last_bits,
                            copies, hist, count, err);
+        else if (tile == 4096)
+            e = launch_shm(hname, batch_hist_kernel<Src, 8>, g, b, shm, s, src, p.n_keys, shift0, p.n_pass, last_bits,
+                           copies, hist, count, err);
         else
             e = launch_shm(hname, batch_hist_kernel<Src, 16>, g, b, shm, s, src, p.n_keys, shift0, p.n_pass, last_bits,
                            copies, hist, count, err);

@@ -89,8 +89,9 @@ __device__ __forceinline__ int64_t source_limit<CountedKeySrc>(const CountedKeyS
 struct RadixShape {
     int block, items;
 };
-constexpr int N_RADIX_SHAPES = 5;
-constexpr RadixShape RADIX_SHAPES[N_RADIX_SHAPES] = {{512, 16}, {256, 32}, {512, 12}, {512, 24}, {1024, 8}};
+constexpr int N_RADIX_SHAPES = 7;
+constexpr RadixShape RADIX_SHAPES[N_RADIX_SHAPES] = {{512, 16}, {256, 32}, {512, 12}, {512, 24},
+                                                     {1024, 8}, {512, 8},  {256, 16}};
 constexpr int DEFAULT_RADIX_SHAPE = 0;
 
 // ---------------------------------------------------------------------------
@@ -309,6 +310,8 @@ hipError_t launch_radix_pass(const char* name, int shape, Src src, Out out, int6
         case 2: return launch_radix_shape<512, 12>(name, src, out, n, shift, bits, hist, lb, lb_next, ticket, err, s);
         case 3: return launch_radix_shape<512, 24>(name, src, out, n, shift, bits, hist, lb, lb_next, ticket, err, s);
         case 4: return launch_radix_shape<1024, 8>(name, src, out, n, shift, bits, hist, lb, lb_next, ticket, err, s);
+        case 5: return launch_radix_shape<512, 8>(name, src, out, n, shift, bits, hist, lb, lb_next, ticket, err, s);
+        case 6: return launch_radix_shape<256, 16>(name, src, out, n, shift, bits, hist, lb, lb_next, ticket, err, s);
         default: return launch_radix_shape<512, 16>(name, src, out, n, shift, bits, hist, lb, lb_next, ticket, err, s);
     }
 }
