@@ -145,14 +145,18 @@ class Arena:
 class GpuExecutor:
     """Runs each batch on its slot's stream through the batched C entry points.
 
-    A request's connectivity is staged into pinned memory by a worker thread
-    and uploaded into a device arena on a separate upload stream as soon as
-    it arrives (``prepare``), overlapping the batches already running.  A
-    batch then only writes its segment records (which point into the arena)
-    and launches; its slot stream waits for its requests' uploads.  Each slot
-    keeps its device buffers across batches (they only grow)."""
+    The device connectivity arena has a pinned host twin with the same
+    offsets.  When a request arrives (``prepare``) it gets an arena range, and
+    a worker thread copies its connectivity into the twin range (numpy, no
+    GIL held).  The main thread then uploads finished copies oldest first,
+    merging requests that are adjacent in the arena into one copy, on a
+    separate upload stream, so uploads overlap the batches already running.
+    A batch only writes its segment records (which point into the arena) and
+    launches; its slot stream waits for its requests' uploads.  A range is
+    free again once its batch has completed.  Each slot keeps its device
+    buffers across batches (they only grow)."""
 
-    def __init__(self, n_slots: int, device="cuda:0", copy_threads: int = 8, arena_ids: int = 1 << 30):
+    def __init__(self, n_slots: int, device="cuda:0", copy_threads: int = 8, arena_ids: int = 1 << 28):
         import concurrent.futures
 
         import torch
@@ -164,20 +168,44 @@ class GpuExecutor:
         self.slot_state = [dict(node=None, elem=None) for _ in range(n_slots)]
         self.arena = Arena(arena_ids)
         self.arena_buf = torch.empty(arena_ids, dtype=torch.int32, device=self.device)
-        # numpy releases the GIL for plain copies, so staging runs on several cores
+        self.pin = torch.empty(arena_ids, dtype=torch.int32, pin_memory=True)
+        self.pin_np = self.pin.numpy()
+        self.staging = collections.deque()  # prepared, upload not yet issued, in prepare order
         self.pool = concurrent.futures.ThreadPoolExecutor(max(copy_threads, 1))
 
-    def _stage_upload(self, conn: np.ndarray, off: int):
-        torch = self.torch
+    def _copy_in(self, conn: np.ndarray, off: int):
         flat = conn.reshape(-1)
-        pinned = torch.empty(flat.size, dtype=torch.int32, pin_memory=True)
-        np.copyto(pinned.numpy(), flat, casting="unsafe")
+        np.copyto(self.pin_np[off:off + flat.size], flat, casting="unsafe")
+
+    def _flush(self, until: Optional[Request] = None):
+        """Upload the staged requests whose host copies are done, oldest first;
+        with ``until``, first wait for the copies up to that request."""
+        runs, flushed = [], []
+        while self.staging:
+            r = self.staging[0]
+            off, fut, _ = r.prep
+            if until is None and not fut.done():
+                break
+            fut.result()  # waits for `until` and its elders; re-raises a failed copy
+            self.staging.popleft()
+            end = off + self.arena.used[off]  # the range's padding travels along, harmlessly
+            if runs and runs[-1][1] == off:
+                runs[-1][1] = end
+            else:
+                runs.append([off, end])
+            flushed.append(r)
+            if r is until:
+                until = None
+        if not flushed:
+            return
+        torch = self.torch
         with torch.cuda.stream(self.upload):
-            # the pinned block is reused only after this copy (host allocator events)
-            self.arena_buf[off:off + flat.size].copy_(pinned, non_blocking=True)
+            for a, b in runs:
+                self.arena_buf[a:b].copy_(self.pin[a:b], non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(self.upload)
-        return ev
+        for r in flushed:
+            r.prep[2] = ev
 
     def prepare(self, r: Request) -> bool:
         """Start staging and uploading r; False if the arena is full now."""
@@ -186,7 +214,9 @@ class GpuExecutor:
         off = self.arena.alloc(r.conn.size)
         if off is None:
             return False
-        r.prep = (off, self.pool.submit(self._stage_upload, r.conn, off))
+        r.prep = [off, self.pool.submit(self._copy_in, r.conn, off), None]  # range, host copy, upload event
+        self.staging.append(r)
+        self._flush()
         return True
 
     def submit(self, batch: BatchHandle):
@@ -196,9 +226,10 @@ class GpuExecutor:
         desc = [(r.n_elem, r.etype, r.n_vert) for r in batch.requests]
         offs = []
         for r in batch.requests:
-            off, fut = r.prep  # admitted only once its upload has started
-            s.wait_event(fut.result())
-            offs.append(off)
+            if r.prep[2] is None:
+                self._flush(until=r)
+            s.wait_event(r.prep[2])
+            offs.append(r.prep[0])
         with torch.cuda.stream(s):
             if st["node"] is None:
                 st["node"] = _b.BatchBuild("node", desc, self.device, conn_offs=offs)
