@@ -372,6 +372,46 @@ struct BatchNodeKeySrc {
         bool bad;
         return load_staged(h, i, tile_base, s, &bad);
     }
+
+    // Histogram path: the keys of a tile inside one mesh, whole elements per
+    // thread with their ids read once from conn; add(key) for each key whose
+    // position lies in [lo, hi).  False if the tile is not inside one mesh.
+    template <int ET, int BLOCK, class Add>
+    __device__ __forceinline__ void elem_keys(const TileRec& r, int64_t lo, int64_t hi, int tid, Add& add,
+                                              bool& bad) const {
+        using E = Elem<ET>;
+        constexpr int PER = CANON ? E::NE : 2 * E::NE;
+        const int n_el = r.cnt / E::NPE;
+        const int32_t* ids = conn + r.ids;
+#pragma unroll 2
+        for (int q = tid; q < n_el; q += BLOCK) {
+            int32_t id[E::NPE];
+#pragma unroll
+            for (int j = 0; j < E::NPE; ++j) id[j] = ids[(int64_t)q * E::NPE + j];
+            const int64_t pos0 = r.off + ((int64_t)r.e0 + q) * PER;
+#pragma unroll
+            for (int k = 0; k < E::NE; ++k) {
+#pragma unroll
+                for (int dir = 0; dir < (CANON ? 1 : 2); ++dir) {
+                    const int64_t pos = pos0 + (CANON ? k : 2 * k + dir);
+                    if (pos < lo || pos >= hi) continue;
+                    bool b;
+                    add(key_of(id[E::A[k]], id[E::B[k]], dir, r.n_vert, r.vert_off, &b));
+                    bad |= b;
+                }
+            }
+        }
+    }
+    template <int BLOCK, int TILE, class Add>
+    __device__ __forceinline__ bool hist_tile(int64_t t0, int64_t n, int tid, Add& add, bool& bad) const {
+        const TileRec r = tiles[t0 / TILE];
+        if (r.etype < 0) return false;
+        const int64_t hi = tmin<int64_t>(t0 + TILE, n);
+        if (r.etype == TRI3) elem_keys<TRI3, BLOCK>(r, t0, hi, tid, add, bad);
+        else if (r.etype == TET4) elem_keys<TET4, BLOCK>(r, t0, hi, tid, add, bad);
+        else elem_keys<HEX8, BLOCK>(r, t0, hi, tid, add, bad);
+        return true;
+    }
 };
 using BatchNodePairSrc = BatchNodeKeySrc<false>;
 using BatchEdgeSrc = BatchNodeKeySrc<true>;
@@ -517,6 +557,48 @@ struct BatchElemPairSrc {
         bool bad;
         return load_staged(h, s, tile_base, st, &bad);
     }
+
+    // Histogram path as for BatchNodeKeySrc: slots of whole elements per
+    // thread, a repeated id inside an element counted once.
+    template <int NPE, int BLOCK, class Add>
+    __device__ __forceinline__ void elem_keys(const TileRec& r, int64_t lo, int64_t hi, int tid, Add& add,
+                                              bool& bad) const {
+        const int n_el = r.cnt / NPE;
+        const int32_t* ids = conn + r.ids;
+#pragma unroll 2
+        for (int q = tid; q < n_el; q += BLOCK) {
+            int32_t id[NPE];
+#pragma unroll
+            for (int j = 0; j < NPE; ++j) id[j] = ids[(int64_t)q * NPE + j];
+            const uint32_t e = r.e0 + (uint32_t)q;
+            const int64_t pos0 = r.off + (int64_t)e * NPE;
+#pragma unroll
+            for (int j = 0; j < NPE; ++j) {
+                const int64_t pos = pos0 + j;
+                if (pos < lo || pos >= hi) continue;
+                const int32_t v = id[j];
+                if ((uint32_t)v >= (uint32_t)r.n_vert) {
+                    bad = true;
+                    continue;
+                }
+                bool first = true;
+#pragma unroll
+                for (int jj = 0; jj < NPE - 1; ++jj)
+                    if (jj < j) first &= id[jj] != v;
+                if (first) add(((uint64_t)(uint32_t)(r.vert_off + v) << 32) | (uint64_t)e);
+            }
+        }
+    }
+    template <int BLOCK, int TILE, class Add>
+    __device__ __forceinline__ bool hist_tile(int64_t t0, int64_t n, int tid, Add& add, bool& bad) const {
+        const TileRec r = tiles[t0 / TILE];
+        if (r.etype < 0) return false;
+        const int64_t hi = tmin<int64_t>(t0 + TILE, n);
+        if (r.etype == TRI3) elem_keys<3, BLOCK>(r, t0, hi, tid, add, bad);
+        else if (r.etype == TET4) elem_keys<4, BLOCK>(r, t0, hi, tid, add, bad);
+        else elem_keys<8, BLOCK>(r, t0, hi, tid, add, bad);
+        return true;
+    }
 };
 
 // Digit histograms (8-bit digits from bit shift0) of the keys a batch source
@@ -541,7 +623,18 @@ __global__ __launch_bounds__(BH_BLOCK) void batch_hist_kernel(Src src, int64_t n
     for (int i = tid; i < n_pass * RADIX * (int)copies; i += BH_BLOCK) s_hist[i] = 0;
     bool bad_seen = false;
     uint32_t mine = 0;
+    auto add = [&](uint64_t k) {
+        ++mine;
+        for (int p = 0; p < n_pass; ++p) {
+            const uint32_t mask = p == n_pass - 1 ? (1u << last_bits) - 1 : RADIX - 1;
+            const uint32_t d = p * RADIX + ((uint32_t)(k >> (shift0 + p * RBITS)) & mask);
+            atomicAdd(&s_hist[d * copies + copy], 1u);
+        }
+    };
+    __syncthreads();  // counters cleared
     for (int64_t t0 = (int64_t)blockIdx.x * TILE; t0 < n; t0 += (int64_t)gridDim.x * TILE) {
+        // a tile inside one mesh: whole elements per thread straight from conn
+        if (src.template hist_tile<BH_BLOCK, TILE>(t0, n, tid, add, bad_seen)) continue;
         __syncthreads();  // the previous tile's staged ids are consumed
         src.template stage<BH_BLOCK, TILE>(t0, n, s_stage, tid);
         __syncthreads();
@@ -555,12 +648,7 @@ __global__ __launch_bounds__(BH_BLOCK) void batch_hist_kernel(Src src, int64_t n
             const uint64_t k = staged ? src.load_staged(hdr, i, t0, s_stage, &bad) : src.make(i, &bad);
             bad_seen |= bad;
             if (Src::kSkipNone && k == KEY_NONE) continue;
-            ++mine;
-            for (int p = 0; p < n_pass; ++p) {
-                const uint32_t mask = p == n_pass - 1 ? (1u << last_bits) - 1 : RADIX - 1;
-                const uint32_t d = p * RADIX + ((uint32_t)(k >> (shift0 + p * RBITS)) & mask);
-                atomicAdd(&s_hist[d * copies + copy], 1u);
-            }
+            add(k);
         }
     }
     if (bad_seen) set_error(err, ERR_INDEX_RANGE);
