@@ -122,6 +122,26 @@ def test_batch_with_gapped_and_reordered_conn(oracle_mod):
     check_slices(oracle_mod, meshes, got)
 
 
+def test_batch_every_radix_shape_same_result(oracle_mod):
+    """Every tile shape (each has its own tile table and histogram tiling)
+    gives the same bytes as the default one, and the oracle's rows."""
+    nb = _nb()
+    specs = mg.batch_specs(n_mesh=24, seed=11, tri_range=(4, 90), cell_range=(1, 12))
+    meshes = [s.build() for s in specs]
+    ref = run_batch(meshes)
+    check_slices(oracle_mod, meshes, ref)
+    try:
+        for shape in range(1, len(nb.radix_shapes())):
+            nb.set_radix_shape(shape)
+            got = run_batch(meshes)
+            for kind in ("node", "elem"):
+                for i in range(len(meshes)):
+                    assert np.array_equal(got[kind][i][0], ref[kind][i][0]), (shape, kind, i)
+                    assert np.array_equal(got[kind][i][1], ref[kind][i][1]), (shape, kind, i)
+    finally:
+        nb.set_radix_shape(0)
+
+
 def test_single_mesh_batch_equals_single_call(oracle_mod):
     m = mg.kuhn_tet_grid(9, 3)
     got = run_batch([m])
