@@ -32,16 +32,33 @@ constexpr uint64_t LB_INC = 2ull << 62;  // value = count of this and all earlie
 constexpr uint64_t LB_FLAG = 3ull << 62;
 constexpr uint64_t LB_VAL = ~LB_FLAG;
 
+// The radix passes' status words come in two widths: 32 bits (2 flag bits
+// over a 30-bit count) for passes over fewer than LB32_MAX_KEYS keys, which
+// halves the look-back traffic, and 64 bits beyond.
+template <class W>
+struct LbWord;
+template <>
+struct LbWord<uint64_t> {
+    static constexpr uint64_t AGG = LB_AGG, INC = LB_INC, FLAG = LB_FLAG, VAL = LB_VAL;
+};
+template <>
+struct LbWord<uint32_t> {
+    static constexpr uint32_t AGG = 1u << 30, INC = 2u << 30, FLAG = 3u << 30, VAL = ~(3u << 30);
+};
+constexpr int64_t LB32_MAX_KEYS = (int64_t)1 << 30;
+
 // A look-back wait polls at most this many times (about a second with the
 // sleep below) before it records ERR_INTERNAL and moves on, so every wave of
 // every kernel always terminates.
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
 
-__device__ __forceinline__ uint64_t lb_load(const uint64_t* p) {
-    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+template <class W>
+__device__ __forceinline__ W lb_load(const W* p) {
+    return __hip_atomic_load(const_cast<W*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void lb_store(uint64_t* p, uint64_t v) {
+template <class W>
+__device__ __forceinline__ void lb_store(W* p, W v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -65,28 +82,30 @@ __device__ __forceinline__ bool lookback_give_up(uint32_t spins, uint32_t* err) 
 // resident and the walk finishes.  Publishes LB_INC | (prefix + agg).
 constexpr int LB_BATCH = 4;
 
-__device__ __forceinline__ uint64_t lookback_prefix(uint64_t* status, int64_t stride, uint32_t tile,
-                                                    uint64_t agg, uint32_t* err) {
+template <class W>
+__device__ __forceinline__ uint64_t lookback_prefix(W* status, int64_t stride, uint32_t tile, uint64_t agg,
+                                                    uint32_t* err) {
+    using L = LbWord<W>;
     if (tile == 0) return 0;
     uint64_t prefix = 0;
     int64_t t = (int64_t)tile - 1;
     uint32_t spins = 0;
     while (t >= 0) {
-        uint64_t s[LB_BATCH];
+        W s[LB_BATCH];
 #pragma unroll
-        for (int k = 0; k < LB_BATCH; ++k) s[k] = t - k >= 0 ? lb_load(status + (t - k) * stride) : LB_INC;
+        for (int k = 0; k < LB_BATCH; ++k) s[k] = t - k >= 0 ? lb_load(status + (t - k) * stride) : L::INC;
         bool stalled = false, done = false;
 #pragma unroll
         for (int k = 0; k < LB_BATCH; ++k) {
             if (done || stalled) continue;
-            const uint64_t f = s[k] & LB_FLAG;
+            const W f = s[k] & L::FLAG;
             if (f == 0) {
                 stalled = true;  // resume the walk at this tile
                 continue;
             }
-            prefix += s[k] & LB_VAL;
+            prefix += s[k] & L::VAL;
             --t;
-            done = f == LB_INC || t < 0;
+            done = f == L::INC || t < 0;
         }
         if (done) break;
         if (stalled) {
@@ -97,7 +116,7 @@ __device__ __forceinline__ uint64_t lookback_prefix(uint64_t* status, int64_t st
             __builtin_amdgcn_s_sleep(1);
         }
     }
-    lb_store(status + (int64_t)tile * stride, LB_INC | (prefix + agg));
+    lb_store(status + (int64_t)tile * stride, (W)(L::INC | (W)(prefix + agg)));
     return prefix;
 }
 

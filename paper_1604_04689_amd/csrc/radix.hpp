@@ -130,10 +130,10 @@ constexpr int radix_waves_per_eu(int block, int items) {
     return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
-template <int BLOCK, int ITEMS, class Src, class Out>
+template <int BLOCK, int ITEMS, class Src, class Out, class W>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(radix_waves_per_eu(BLOCK, ITEMS))))
 void radix_pass_kernel(Src src, Out out, int64_t n, uint32_t shift, uint32_t bits, const uint32_t* __restrict__ hist,
-                       uint64_t* lookback, uint64_t* lookback_next, uint32_t* ticket, uint32_t* err) {
+                       W* lookback, W* lookback_next, uint32_t* ticket, uint32_t* err) {
     static_assert(BLOCK >= RADIX, "one thread per digit");
     constexpr int WAVES = BLOCK / WAVE;
     constexpr int TILE = BLOCK * ITEMS;
@@ -205,7 +205,8 @@ void radix_pass_kernel(Src src, Out out, int64_t n, uint32_t shift, uint32_t bit
 
     // ---- 2. publish, tile offsets, look-back ---------------------------------
     const uint32_t tile_cnt = tid < RADIX ? s_cnt[tid] : 0u;
-    if (tid < RADIX) lb_store(lookback + (int64_t)tile * RADIX + tid, (tile == 0 ? LB_INC : LB_AGG) | tile_cnt);
+    if (tid < RADIX)
+        lb_store(lookback + (int64_t)tile * RADIX + tid, (W)((tile == 0 ? LbWord<W>::INC : LbWord<W>::AGG) | tile_cnt));
     uint32_t tile_total;
     const uint32_t toff = block_exclusive_sum<BLOCK>(tile_cnt, s_tmp, &tile_total);
     uint32_t hist_total;
@@ -214,7 +215,7 @@ void radix_pass_kernel(Src src, Out out, int64_t n, uint32_t shift, uint32_t bit
         s_tile_off[tid] = toff;
         const uint64_t before = lookback_prefix(lookback + tid, RADIX, tile, tile_cnt, err);
         s_glob[tid] = (int64_t)gstart + (int64_t)before - (int64_t)toff;
-        if (lookback_next) lookback_next[(int64_t)tile * RADIX + tid] = 0;  // slot of the next pass
+        if (lookback_next) lookback_next[(int64_t)tile * RADIX + tid] = 0;  // slot of the next pass (same width)
     }
 
     // ---- 3. rank within the wave ---------------------------------------------
@@ -291,12 +292,12 @@ void radix_pass_kernel(Src src, Out out, int64_t n, uint32_t shift, uint32_t bit
     if (full) set_error(err, ERR_CAPACITY);
 }
 
-template <int BLOCK, int ITEMS, class Src, class Out>
+template <int BLOCK, int ITEMS, class Src, class Out, class W = uint32_t>
 hipError_t launch_radix_shape(const char* name, Src src, Out out, int64_t n, uint32_t shift, uint32_t bits, const uint32_t* hist,
                               uint64_t* lb, uint64_t* lb_next, uint32_t* ticket, uint32_t* err, hipStream_t s) {
     const int64_t tiles = ceil_div(n, (int64_t)BLOCK * ITEMS);
-    return launch(name, radix_pass_kernel<BLOCK, ITEMS, Src, Out>, dim3((unsigned)tiles), dim3(BLOCK), s, src,
-                  out, n, shift, bits, hist, lb, lb_next, ticket, err);
+    return launch(name, radix_pass_kernel<BLOCK, ITEMS, Src, Out, W>, dim3((unsigned)tiles), dim3(BLOCK), s, src,
+                  out, n, shift, bits, hist, reinterpret_cast<W*>(lb), reinterpret_cast<W*>(lb_next), ticket, err);
 }
 
 // Launches one radix pass with tile shape RADIX_SHAPES[shape].  The look-back
@@ -305,6 +306,13 @@ template <class Src, class Out>
 hipError_t launch_radix_pass(const char* name, int shape, Src src, Out out, int64_t n, uint32_t shift, uint32_t bits,
                              const uint32_t* hist, uint64_t* lb, uint64_t* lb_next, uint32_t* ticket, uint32_t* err,
                              hipStream_t s) {
+    // The status arrays hold 64-bit words; passes over fewer than
+    // LB32_MAX_KEYS keys use them as 32-bit words (every pass of one
+    // pipeline has the same n, so a pass and the next agree on the width of
+    // the slots they hand over).  Larger passes take the default tile shape.
+    if (n >= LB32_MAX_KEYS)
+        return launch_radix_shape<512, 16, Src, Out, uint64_t>(name, src, out, n, shift, bits, hist, lb, lb_next,
+                                                               ticket, err, s);
     switch (shape) {
         case 1: return launch_radix_shape<256, 32>(name, src, out, n, shift, bits, hist, lb, lb_next, ticket, err, s);
         case 2: return launch_radix_shape<512, 12>(name, src, out, n, shift, bits, hist, lb, lb_next, ticket, err, s);
