@@ -205,9 +205,10 @@ def test_every_radix_shape_same_result(oracle_mod):
 
 @pytest.mark.slow
 def test_huge_vertex_count_sparse_use(oracle_mod):
-    # n_vert = 2^29 + 5: 60-bit node keys (8 radix passes); element buckets
-    # counted with global atomics (more than 2^14 buckets).  Expected CSR: the
-    # oracle on the used ids relabelled 0..k-1, expanded back.
+    # n_vert = 2^29 + 5: 60-bit node keys (8 radix passes); the element
+    # relation sorts 30 vertex bits (4 passes) over mostly empty rows.
+    # Expected CSR: the oracle on the used ids relabelled 0..k-1, expanded
+    # back.
     n_vert = 2 ** 29 + 5
     rng = np.random.default_rng(17)
     used = np.unique(np.concatenate([rng.integers(0, n_vert, 3000), [0, n_vert - 1]]))
@@ -224,3 +225,25 @@ def test_huge_vertex_count_sparse_use(oracle_mod):
         gr, gc = gpu_csr(kind, conn, 1, n_vert)
         assert np.array_equal(gr.astype(np.int64), want_r), kind
         assert np.array_equal(gc, lc), kind
+
+
+@pytest.mark.slow
+def test_elem_past_2_30_slots_wide_status_words():
+    """At 2^30 keys or more a radix pass keeps 64-bit look-back words (below,
+    32-bit ones with a 30-bit count).  360 M copies of one triangle give
+    1.08 G element slots with a closed-form answer: each of the three
+    vertices lists every element, in order."""
+    nb = _nb()
+    f = 360_000_000
+    assert 3 * f >= 2 ** 30
+    conn = torch.tensor([0, 1, 2], dtype=torch.int32, device=DEV).repeat(f)
+    rp, cols = nb.elem_neighbors(conn, 0, 3)
+    del conn
+    assert rp.cpu().tolist() == [0, f, 2 * f, 3 * f]
+    want = torch.arange(f, dtype=torch.int32, device=DEV)
+    try:
+        for v in range(3):
+            assert torch.equal(cols[v * f:(v + 1) * f], want), v
+    finally:
+        del rp, cols, want
+        torch.cuda.empty_cache()
