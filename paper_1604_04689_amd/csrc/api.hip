@@ -35,6 +35,39 @@ hipError_t fill_i32(int32_t* p, int64_t n, int32_t value, hipStream_t s) {
     return fill_words((uint32_t*)p, n, (uint32_t)value, s);
 }
 
+// Up to MAX_FILL_REGIONS regions, each with its own value, in one launch.
+struct FillSet {
+    uint32_t* p[MAX_FILL_REGIONS];
+    int64_t end[MAX_FILL_REGIONS];  // running word counts
+    uint32_t value[MAX_FILL_REGIONS];
+    int count;
+};
+
+__global__ __launch_bounds__(FILL_BLOCK) void fill_set_kernel(FillSet f) {
+    const int64_t total = f.end[f.count - 1];
+    for (int64_t i = (int64_t)blockIdx.x * FILL_BLOCK + threadIdx.x; i < total; i += (int64_t)gridDim.x * FILL_BLOCK) {
+        int k = 0;
+        while (i >= f.end[k]) ++k;
+        f.p[k][i - (k ? f.end[k - 1] : 0)] = f.value[k];
+    }
+}
+
+hipError_t fill_regions(const FillRegion* r, int count, hipStream_t s) {
+    FillSet f{};
+    int64_t total = 0;
+    for (int i = 0; i < count && i < MAX_FILL_REGIONS; ++i) {
+        if (r[i].n_words <= 0) continue;
+        f.p[f.count] = (uint32_t*)r[i].p;
+        total += r[i].n_words;
+        f.end[f.count] = total;
+        f.value[f.count] = r[i].value;
+        ++f.count;
+    }
+    if (f.count == 0) return hipSuccess;
+    const int grid = (int)tmin<int64_t>(ceil_div(total, FILL_BLOCK), FILL_GRID_MAX);
+    return launch("fill", fill_set_kernel, dim3(grid), dim3(FILL_BLOCK), s, f);
+}
+
 static std::atomic<int> g_radix_shape{DEFAULT_RADIX_SHAPE};
 static std::atomic<int> g_node_sort{0};
 

@@ -777,8 +777,7 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
                            copies, hist, count, err);
     }
     // element relation: the last pass writes cols and offers row starts
-    const CsrOut csr{cols, row_ptr, cols ? cols_cap : 0, 32u, 0xffffffffull};
-    if (!node && e == hipSuccess) e = fill_i32(row_ptr, (int64_t)total_vert + 1, INT32_MAX, s);
+    const CsrOut csr{cols, row_ptr, cols ? cols_cap : 0, 32u, 0xffffffffull};  // row_ptr set to INT32_MAX by the caller
     for (int q = 0; q < p.n_pass && e == hipSuccess; ++q) {
         const uint32_t shift = shift0 + (uint32_t)q * RBITS;
         const uint32_t bits = tmin<uint32_t>(RBITS, p.digit_bits - (uint32_t)q * RBITS);
@@ -829,20 +828,24 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
 hipError_t run_batch_node(const BatchPlan& p, const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
                           uint32_t lo_bits, int32_t total_vert, int32_t* row_ptr, int32_t* cols, int64_t cols_cap,
                           void* ws, hipStream_t s) {
-    hipError_t e = zero_words(ws, p.zero_bytes, s);
+    const int mode = node_sort_mode();
+    const bool empty = p.n_keys == 0 || n_mesh == 0;
+    char* w = (char*)ws;
+    FillRegion fill[3] = {{ws, (int64_t)(p.zero_bytes / 4), 0u}};
+    int n_fill = 1;
+    if (!empty && mode != 0) fill[n_fill++] = {w + p.off_deg, total_vert, 0u};
+    if (!empty && mode == 2) fill[n_fill++] = {w + p.off_low, (int64_t)total_vert + 1, (uint32_t)INT32_MAX};
+    hipError_t e = fill_regions(fill, n_fill, s);
     if (e != hipSuccess) return e;
-    if (p.n_keys == 0 || n_mesh == 0) return fill_i32(row_ptr, (int64_t)total_vert + 1, 0, s);
+    if (empty) return fill_i32(row_ptr, (int64_t)total_vert + 1, 0, s);
     const int32_t* lut = (const int32_t*)((char*)ws + p.off_lut);
     const TileRec* tiles = (const TileRec*)((char*)ws + p.off_tiles);
-    const int mode = node_sort_mode();
     if (mode != 0) {
         // vertex-rows and edge-rows: radix passes over the global-vertex bits
         // only (the all-ones value stays free for KEY_NONE), then per-row dedup
         BatchPlan q = p;
         q.digit_bits = bits_for((int64_t)total_vert + 1);
         q.n_pass = (int)ceil_div(q.digit_bits, RBITS);
-        e = fill_i32((int32_t*)((char*)ws + p.off_deg), total_vert, 0, s);
-        if (e != hipSuccess) return e;
         if (mode == 1)
             return batch_pipeline(q, "node", BatchNodePairSrc{conn, segs, lut, tiles, lo_bits}, lo_bits, lo_bits,
                                   total_vert, row_ptr, cols, cols_cap, (char*)ws, segs, n_mesh, 1, s);
@@ -857,9 +860,11 @@ hipError_t run_batch_node(const BatchPlan& p, const int32_t* conn, const mesh_se
 hipError_t run_batch_elem(const BatchPlan& p, const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
                           int32_t total_vert, int32_t* row_ptr, int32_t* cols, int64_t cols_cap, void* ws,
                           hipStream_t s) {
-    hipError_t e = zero_words(ws, p.zero_bytes, s);
-    if (e != hipSuccess) return e;
-    if (p.n_keys == 0 || n_mesh == 0) return fill_i32(row_ptr, (int64_t)total_vert + 1, 0, s);
+    const bool empty = p.n_keys == 0 || n_mesh == 0;
+    const FillRegion fill[2] = {{ws, (int64_t)(p.zero_bytes / 4), 0u},
+                                {row_ptr, (int64_t)total_vert + 1, empty ? 0u : (uint32_t)INT32_MAX}};
+    hipError_t e = fill_regions(fill, 2, s);
+    if (e != hipSuccess || empty) return e;
     const int32_t* lut = (const int32_t*)((char*)ws + p.off_lut);
     const TileRec* tiles = (const TileRec*)((char*)ws + p.off_tiles);
     return batch_pipeline(p, "elem", BatchElemPairSrc{conn, segs, lut, tiles}, 32u, 32u, total_vert, row_ptr, cols,

@@ -165,8 +165,8 @@ static __global__ __launch_bounds__(EDGE_BLOCK) void edge_merge_kernel(const int
 // them), up_cols n_edges ints, hist2 zeroed, lb[l0] cleared for n_edges keys
 // and lb[l0 ^ 1] for later clearing; tickets[0 .. n_pass) zero.  temp (the
 // row values, dead once transposed) takes the lower neighbours, written by
-// the last pass with their group starts in low_ptr (n_vert + 1 ints);
-// block_min holds ceil((n_vert + 1) / RF_TILE) ints.
+// the last pass with their group starts in low_ptr (n_vert + 1 ints, set to
+// INT32_MAX by the caller); block_min holds ceil((n_vert + 1) / RF_TILE) ints.
 struct EdgeStage {
     const int32_t* up_ptr;
     const int32_t* deg;
@@ -205,7 +205,6 @@ static inline hipError_t launch_edge_stage(const EdgeStage& g, int32_t* row_ptr,
         e = launch(batch ? "batch_node_edge_hist" : "node_edge_hist", key_hist_kernel,
                    dim3((unsigned)tmin<int64_t>(ceil_div(g.n_edges, KH_BLOCK), KH_GRID_MAX)), dim3(KH_BLOCK), s,
                    (const uint64_t*)g.keys[0], E, g.b, g.n_pass, last_bits, g.hist2);
-    if (e == hipSuccess) e = fill_i32(g.low_ptr, (int64_t)g.n_vert + 1, INT32_MAX, s);
     // the last pass writes the lower neighbours (low bits) and offers the
     // start of each vertex's group
     const CsrOut low{g.temp, g.low_ptr, g.n_edges, g.b, (1ull << g.b) - 1};

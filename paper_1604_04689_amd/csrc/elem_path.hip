@@ -210,10 +210,9 @@ static hipError_t elem_pipeline(const ElemPlan& p, const int32_t* conn, int32_t*
 
     const int grid = (int)tmin<int64_t>(ceil_div(p.n_elem, HIST_BLOCK), HIST_GRID_MAX);
     const uint32_t last_bits = p.id_bits - (uint32_t)(p.n_pass - 1) * RBITS;
-    // the last pass (CsrOut) offers every row start: unset entries hold INT32_MAX
-    hipError_t e = fill_i32(row_ptr, (int64_t)p.n_vert + 1, INT32_MAX, s);
-    if (e == hipSuccess)
-        e = launch("elem_hist", elem_hist_kernel<ET>, dim3(grid), dim3(HIST_BLOCK), s, conn, p.n_elem, p.n_vert,
+    // the last pass (CsrOut) offers every row start: unset entries hold
+    // INT32_MAX (set by the caller)
+    hipError_t e = launch("elem_hist", elem_hist_kernel<ET>, dim3(grid), dim3(HIST_BLOCK), s, conn, p.n_elem, p.n_vert,
                    p.n_pass, last_bits, hist, count, err);
     const CsrOut csr{cols, row_ptr, cols ? cols_cap : 0, 32u, 0xffffffffull};
     for (int q = 0; q < p.n_pass && e == hipSuccess; ++q) {
@@ -241,9 +240,10 @@ static hipError_t elem_pipeline(const ElemPlan& p, const int32_t* conn, int32_t*
 
 hipError_t run_elem(const ElemPlan& p, const int32_t* conn, int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
                     void* ws, hipStream_t s) {
-    hipError_t e = zero_words(ws, p.zero_bytes, s);
-    if (e != hipSuccess) return e;
-    if (p.n_slots == 0) return fill_i32(row_ptr, (int64_t)p.n_vert + 1, 0, s);
+    const FillRegion fill[2] = {{ws, (int64_t)(p.zero_bytes / 4), 0u},
+                                {row_ptr, (int64_t)p.n_vert + 1, p.n_slots == 0 ? 0u : (uint32_t)INT32_MAX}};
+    hipError_t e = fill_regions(fill, 2, s);
+    if (e != hipSuccess || p.n_slots == 0) return e;
     switch (p.etype) {
         case TRI3: return elem_pipeline<TRI3>(p, conn, row_ptr, cols, cols_capacity, (char*)ws, s);
         case TET4: return elem_pipeline<TET4>(p, conn, row_ptr, cols, cols_capacity, (char*)ws, s);

@@ -100,4 +100,13 @@ int node_sort_mode();
 hipError_t zero_words(void* p, size_t bytes, hipStream_t stream);
 hipError_t fill_i32(int32_t* p, int64_t n, int32_t value, hipStream_t stream);
 
+// Several fills (32-bit words, each region its own value) in one launch.
+constexpr int MAX_FILL_REGIONS = 3;
+struct FillRegion {
+    void* p;
+    int64_t n_words;
+    uint32_t value;
+};
+hipError_t fill_regions(const FillRegion* r, int count, hipStream_t stream);
+
 }  // namespace mnb

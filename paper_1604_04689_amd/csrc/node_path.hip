@@ -257,7 +257,7 @@ bool plan_node(int64_t n_elem, int32_t etype, int32_t n_vert, NodePlan* p) {
 }
 
 template <int ET>
-static hipError_t node_pipeline(const NodePlan& p, const int32_t* conn, int32_t* row_ptr, int32_t* cols,
+static hipError_t node_pipeline(const NodePlan& p, int mode, const int32_t* conn, int32_t* row_ptr, int32_t* cols,
                                 int64_t cols_capacity, char* w, hipStream_t s) {
     uint32_t* hdr = (uint32_t*)w;
     uint32_t* err = hdr + HDR_ERR;
@@ -267,7 +267,6 @@ static hipError_t node_pipeline(const NodePlan& p, const int32_t* conn, int32_t*
     uint64_t* lb[2] = {(uint64_t*)(w + p.off_lb0), (uint64_t*)(w + p.off_lb1)};
     uint64_t* kb[2] = {(uint64_t*)(w + p.off_keys0), (uint64_t*)(w + p.off_keys1)};
     const int shape = radix_shape();
-    const int mode = node_sort_mode();
     const bool rows = mode == 1, edges = mode == 2;
 
     // full-key mode: passes over all 2b key bits; vertex-rows and edge-rows
@@ -279,10 +278,9 @@ static hipError_t node_pipeline(const NodePlan& p, const int32_t* conn, int32_t*
     const int64_t n_keys = edges ? p.n_edges : p.n_pairs;
     const int grid = (int)tmin<int64_t>(ceil_div(p.n_elem, NH_BLOCK), NH_GRID_MAX);
     const uint32_t last_bits = sort_bits - (uint32_t)(n_pass - 1) * RBITS;
-    hipError_t e = hipSuccess;
-    if (rows || edges) e = fill_i32((int32_t*)(w + p.off_deg), p.n_vert, 0, s);
-    if (e == hipSuccess)
-        e = edges ? launch("node_hist", node_hist_kernel<ET, true>, dim3(grid), dim3(NH_BLOCK), s, conn, p.n_elem,
+    // (the caller has cleared the row degrees and, for edge-rows, set the
+    // lower-group starts to INT32_MAX, with the workspace header)
+    hipError_t e = edges ? launch("node_hist", node_hist_kernel<ET, true>, dim3(grid), dim3(NH_BLOCK), s, conn, p.n_elem,
                            p.n_vert, p.id_bits, shift0, n_pass, last_bits, hist, err)
                   : launch("node_hist", node_hist_kernel<ET, false>, dim3(grid), dim3(NH_BLOCK), s, conn, p.n_elem,
                            p.n_vert, p.id_bits, shift0, n_pass, last_bits, hist, err);
@@ -333,13 +331,19 @@ static hipError_t node_pipeline(const NodePlan& p, const int32_t* conn, int32_t*
 
 hipError_t run_node(const NodePlan& p, const int32_t* conn, int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
                     void* ws, hipStream_t s) {
-    hipError_t e = zero_words(ws, p.zero_bytes, s);
+    const int mode = node_sort_mode();
+    char* w = (char*)ws;
+    FillRegion fill[3] = {{ws, (int64_t)(p.zero_bytes / 4), 0u}};
+    int n_fill = 1;
+    if (p.n_pairs > 0 && mode != 0) fill[n_fill++] = {w + p.off_deg, p.n_vert, 0u};
+    if (p.n_pairs > 0 && mode == 2) fill[n_fill++] = {w + p.off_low, (int64_t)p.n_vert + 1, (uint32_t)INT32_MAX};
+    hipError_t e = fill_regions(fill, n_fill, s);
     if (e != hipSuccess) return e;
     if (p.n_pairs == 0) return fill_i32(row_ptr, (int64_t)p.n_vert + 1, 0, s);
     switch (p.etype) {
-        case TRI3: return node_pipeline<TRI3>(p, conn, row_ptr, cols, cols_capacity, (char*)ws, s);
-        case TET4: return node_pipeline<TET4>(p, conn, row_ptr, cols, cols_capacity, (char*)ws, s);
-        default: return node_pipeline<HEX8>(p, conn, row_ptr, cols, cols_capacity, (char*)ws, s);
+        case TRI3: return node_pipeline<TRI3>(p, mode, conn, row_ptr, cols, cols_capacity, w, s);
+        case TET4: return node_pipeline<TET4>(p, mode, conn, row_ptr, cols, cols_capacity, w, s);
+        default: return node_pipeline<HEX8>(p, mode, conn, row_ptr, cols, cols_capacity, w, s);
     }
 }
 
