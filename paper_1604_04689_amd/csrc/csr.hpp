@@ -153,7 +153,7 @@ inline hipError_t launch_unique_csr(const char* name, const uint64_t* keys, int6
 
 // Exclusive scan of n int32 counts: out[i] = sum of in[0..i), out[n] = total.
 // Tiles by ticket, one wave-wide look-back per tile.
-constexpr int SCAN_BLOCK = 256;
+constexpr int SCAN_BLOCK = 1024;
 constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
 
@@ -161,8 +161,9 @@ static __global__ __launch_bounds__(SCAN_BLOCK) void scan_i32_kernel(const int32
                                                              int32_t* __restrict__ out, uint64_t* lookback,
                                                              uint32_t* ticket, uint32_t* err) {
     constexpr int WAVES = SCAN_BLOCK / WAVE;
-    static_assert(SCAN_ITEMS * WAVES <= WAVE, "one wave scans the item/wave sums");
-    __shared__ uint32_t s_sum[SCAN_ITEMS * WAVES];
+    constexpr int PARTS = SCAN_ITEMS * WAVES;  // one sum per (item, wave), in element order
+    static_assert(PARTS % WAVE == 0, "the partial sums fill whole waves");
+    __shared__ uint32_t s_sum[PARTS];
     __shared__ uint32_t s_tile;
     __shared__ uint64_t s_prefix;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
@@ -184,11 +185,17 @@ static __global__ __launch_bounds__(SCAN_BLOCK) void scan_i32_kernel(const int32
     }
     __syncthreads();
     if (wid == 0) {
-        const uint32_t v = lane < SCAN_ITEMS * WAVES ? s_sum[lane] : 0u;
-        const uint32_t incl = wave_inclusive_sum(v);
-        if (lane < SCAN_ITEMS * WAVES) s_sum[lane] = incl - v;
-        const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
-        if (lane == 0) lb_store(lookback + tile, (tile == 0 ? LB_INC : LB_AGG) | total);
+        // exclusive scan of the partial sums, 64 at a time with a carry (a
+        // large tile keeps the look-back walks short: they are latency-bound)
+        uint32_t total = 0;
+#pragma unroll
+        for (int c = 0; c < PARTS / WAVE; ++c) {
+            const uint32_t v = s_sum[c * WAVE + lane];
+            const uint32_t incl = wave_inclusive_sum(v);
+            s_sum[c * WAVE + lane] = total + incl - v;
+            total += __shfl(incl, WAVE - 1, WAVE);
+        }
+        if (lane == 0) lb_store(lookback + tile, (tile == 0 ? LB_INC : LB_AGG) | (uint64_t)total);
         const uint64_t before = wave_lookback_prefix(lookback, tile, total, err);
         if (lane == 0) s_prefix = before;
     }
