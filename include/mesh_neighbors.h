@@ -219,7 +219,8 @@ int32_t mesh_abi_version(void);
 
 /* Every radix pass of both pipelines uses one tile shape (threads per block x
  * keys per thread) out of a fixed set built into the library.  The choice is
- * process-wide and changes only speed, never results.  Shapes are numbered
+ * process-wide and changes only speed, never results (passes over 2^30 keys
+ * or more always take the default shape).  Shapes are numbered
  * 0 .. mesh_radix_shape_count() - 1; mesh_set_radix_shape(-1) restores the
  * default.  Returns MESH_ERR_INVALID_ARG for an unknown shape. */
 int32_t mesh_radix_shape_count(void);
