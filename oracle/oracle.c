@@ -19,9 +19,13 @@
  *     element yields no self pair) and an element is listed once per vertex;
  *   - neighboring nodes of a non-simplex element are those joined by one of
  *     its edges: 3 for a triangle, all 6 pairs of a tetrahedron, the 12 edges
- *     of a VTK-ordered hexahedron (the paper demonstrates triangles only,
- *     Sec. 2.2, and claims the method applies to arbitrary meshes);
- *   - ids are 0-based, element id = row of the connectivity array.
+ *     of a VTK-ordered hexahedron, the 4 sides of a quadrilateral, the 9 edges
+ *     of a wedge, the 8 edges of a pyramid (the paper demonstrates triangles
+ *     only, Sec. 2.2, and claims the method applies to arbitrary meshes,
+ *     Sec. 2.2 and Sec. 4); a mesh may mix element types, each element
+ *     contributing the edges of its own type;
+ *   - ids are 0-based, element id = row of the connectivity array (for a
+ *     mixed mesh, the element's index in its list of types).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -33,12 +37,22 @@ static const int TET_EDGES[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 
 /* VTK hexahedron: bottom ring 0-1-2-3, top ring 4-5-6-7, verticals i-(i+4). */
 static const int HEX_EDGES[12][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}, {4, 5}, {5, 6},
                                      {6, 7}, {7, 4}, {0, 4}, {1, 5}, {2, 6}, {3, 7}};
+/* Quadrilateral: the four sides 0-1-2-3 (no diagonals). */
+static const int QUAD_EDGES[4][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}};
+/* VTK wedge: triangle 0-1-2, triangle 3-4-5 above it, verticals i-(i+3). */
+static const int WEDGE_EDGES[9][2] = {{0, 1}, {1, 2}, {2, 0}, {3, 4}, {4, 5},
+                                      {5, 3}, {0, 3}, {1, 4}, {2, 5}};
+/* VTK pyramid: base ring 0-1-2-3, apex 4 joined to every base node. */
+static const int PYR_EDGES[8][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}, {0, 4}, {1, 4}, {2, 4}, {3, 4}};
 
 static int type_info(int32_t etype, int* npe, int* n_edges, const int (**edges)[2]) {
     switch (etype) {
         case 0: *npe = 3; *n_edges = 3; *edges = TRI_EDGES; return 0;
         case 1: *npe = 4; *n_edges = 6; *edges = TET_EDGES; return 0;
         case 2: *npe = 8; *n_edges = 12; *edges = HEX_EDGES; return 0;
+        case 3: *npe = 4; *n_edges = 4; *edges = QUAD_EDGES; return 0;
+        case 4: *npe = 6; *n_edges = 9; *edges = WEDGE_EDGES; return 0;
+        case 5: *npe = 5; *n_edges = 8; *edges = PYR_EDGES; return 0;
         default: return -1;
     }
 }
@@ -99,6 +113,26 @@ static int64_t emit_csr(const ordered_set* sets, int32_t n_vert, int32_t* row_pt
  *   -3    cols_cap too small (or nnz beyond int32)
  *   -4    out of host memory */
 
+/* The node pairs of one element: both endpoints of every edge of its type
+ * go into each other's set, except a self pair (Sec. 1; Sec. 2.1.1).
+ * Returns 0, or -4 when out of memory. */
+static int insert_element_nodes(ordered_set* sets, const int32_t* el, int n_edges, const int (*edges)[2]) {
+    for (int k = 0; k < n_edges; ++k) {
+        int32_t u = el[edges[k][0]], w = el[edges[k][1]];
+        if (u == w) continue; /* no self pair */
+        if (set_insert(&sets[u], w) || set_insert(&sets[w], u)) return -4;
+    }
+    return 0;
+}
+
+/* The element into the set of each of its nodes (Sec. 1; Sec. 2.1.2). */
+static int insert_element_elem(ordered_set* sets, const int32_t* el, int npe, int32_t e) {
+    for (int j = 0; j < npe; ++j) {
+        if (set_insert(&sets[el[j]], e)) return -4;
+    }
+    return 0;
+}
+
 /* One-ring neighboring nodes of every vertex (Sec. 1; Sec. 2.1.1). */
 int64_t oracle_node_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
                               int32_t* row_ptr, int32_t* cols, int64_t cols_cap) {
@@ -111,14 +145,9 @@ int64_t oracle_node_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype
     ordered_set* sets = (ordered_set*)calloc((size_t)n_vert + 1, sizeof(ordered_set));
     if (!sets) return -4;
     for (int64_t e = 0; e < n_elem; ++e) {
-        const int32_t* el = conn + e * npe;
-        for (int k = 0; k < n_edges; ++k) {
-            int32_t u = el[edges[k][0]], w = el[edges[k][1]];
-            if (u == w) continue; /* no self pair */
-            if (set_insert(&sets[u], w) || set_insert(&sets[w], u)) {
-                free_sets(sets, n_vert);
-                return -4;
-            }
+        if (insert_element_nodes(sets, conn + e * npe, n_edges, edges)) {
+            free_sets(sets, n_vert);
+            return -4;
         }
     }
     int64_t r = emit_csr(sets, n_vert, row_ptr, cols, cols_cap);
@@ -139,15 +168,60 @@ int64_t oracle_elem_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype
     ordered_set* sets = (ordered_set*)calloc((size_t)n_vert + 1, sizeof(ordered_set));
     if (!sets) return -4;
     for (int64_t e = 0; e < n_elem; ++e) {
-        const int32_t* el = conn + e * npe;
-        for (int j = 0; j < npe; ++j) {
-            if (set_insert(&sets[el[j]], (int32_t)e)) {
-                free_sets(sets, n_vert);
-                return -4;
-            }
+        if (insert_element_elem(sets, conn + e * npe, npe, (int32_t)e)) {
+            free_sets(sets, n_vert);
+            return -4;
         }
     }
     int64_t r = emit_csr(sets, n_vert, row_ptr, cols, cols_cap);
     free_sets(sets, n_vert);
     return r;
+}
+
+/* Meshes whose elements carry their own types: element e has type etypes[e]
+ * and ids conn[elem_off[e] .. elem_off[e+1]).  relation 0: neighboring nodes,
+ * 1: neighboring elements.  Beyond the codes above, -5: an element whose
+ * offsets do not span its type's node count. */
+static int64_t mixed_relation(int relation, const int32_t* conn, const int64_t* elem_off, const int32_t* etypes,
+                              int64_t n_elem, int32_t n_vert, int32_t* row_ptr, int32_t* cols, int64_t cols_cap) {
+    if (n_elem < 0 || n_vert < 0 || n_elem > INT32_MAX || !row_ptr || (n_elem > 0 && (!elem_off || !etypes)))
+        return -1;
+    if (n_elem > 0 && elem_off[0] != 0) return -5;
+    for (int64_t e = 0; e < n_elem; ++e) {
+        int npe, n_edges;
+        const int(*edges)[2];
+        if (type_info(etypes[e], &npe, &n_edges, &edges) != 0) return -1;
+        if (elem_off[e + 1] - elem_off[e] != npe) return -5;
+    }
+    for (int64_t i = 0; i < (n_elem > 0 ? elem_off[n_elem] : 0); ++i)
+        if (conn[i] < 0 || conn[i] >= n_vert) return -2;
+    ordered_set* sets = (ordered_set*)calloc((size_t)n_vert + 1, sizeof(ordered_set));
+    if (!sets) return -4;
+    for (int64_t e = 0; e < n_elem; ++e) {
+        int npe, n_edges;
+        const int(*edges)[2];
+        type_info(etypes[e], &npe, &n_edges, &edges);
+        const int32_t* el = conn + elem_off[e];
+        int fail = relation == 0 ? insert_element_nodes(sets, el, n_edges, edges)
+                                 : insert_element_elem(sets, el, npe, (int32_t)e);
+        if (fail) {
+            free_sets(sets, n_vert);
+            return -4;
+        }
+    }
+    int64_t r = emit_csr(sets, n_vert, row_ptr, cols, cols_cap);
+    free_sets(sets, n_vert);
+    return r;
+}
+
+int64_t oracle_mixed_node_neighbors(const int32_t* conn, const int64_t* elem_off, const int32_t* etypes,
+                                    int64_t n_elem, int32_t n_vert, int32_t* row_ptr, int32_t* cols,
+                                    int64_t cols_cap) {
+    return mixed_relation(0, conn, elem_off, etypes, n_elem, n_vert, row_ptr, cols, cols_cap);
+}
+
+int64_t oracle_mixed_elem_neighbors(const int32_t* conn, const int64_t* elem_off, const int32_t* etypes,
+                                    int64_t n_elem, int32_t n_vert, int32_t* row_ptr, int32_t* cols,
+                                    int64_t cols_cap) {
+    return mixed_relation(1, conn, elem_off, etypes, n_elem, n_vert, row_ptr, cols, cols_cap);
 }

@@ -7,12 +7,18 @@ consume its arrays.  Every generator returns int32 connectivity, row-major
 permutation and element rows shuffled by a second seeded permutation, so that
 every radix digit of a neighbor key is uniform and every scatter is random.
 
-Element types (node order matters only for the hexahedron):
+Element types (VTK node orders):
 
 * ``TRI3`` (0): 3 nodes.
 * ``TET4`` (1): 4 nodes.
-* ``HEX8`` (2): 8 nodes in VTK order, nodes 0-3 the bottom face counter-
-  clockwise and nodes 4-7 the top face above them.
+* ``HEX8`` (2): 8 nodes, nodes 0-3 the bottom face counter-clockwise and
+  nodes 4-7 the top face above them.
+* ``QUAD4`` (3): 4 nodes around the face.
+* ``WEDGE6`` (4): triangle 0-1-2 and triangle 3-4-5 above it.
+* ``PYRAMID5`` (5): quadrilateral base 0-1-2-3 and apex 4.
+
+Meshes with several element types (``MixedMesh``) hold every element's ids
+back to back with one type code per element.
 
 The paper measures on scanned triangle surfaces (Stanford 3D Scanning
 Repository, GIT Large Geometry Models Archive; Sec. 3.1, Table 1).  Those
@@ -26,9 +32,9 @@ import math
 
 import numpy as np
 
-TRI3, TET4, HEX8 = 0, 1, 2
-NODES_PER_ELEM = {TRI3: 3, TET4: 4, HEX8: 8}
-TYPE_NAMES = {TRI3: "tri3", TET4: "tet4", HEX8: "hex8"}
+TRI3, TET4, HEX8, QUAD4, WEDGE6, PYRAMID5 = 0, 1, 2, 3, 4, 5
+NODES_PER_ELEM = {TRI3: 3, TET4: 4, HEX8: 8, QUAD4: 4, WEDGE6: 6, PYRAMID5: 5}
+TYPE_NAMES = {TRI3: "tri3", TET4: "tet4", HEX8: "hex8", QUAD4: "quad4", WEDGE6: "wedge6", PYRAMID5: "pyramid5"}
 
 BASE_SEED = 160404689
 
@@ -168,6 +174,156 @@ def hex_grid(m: int, seed: int = BASE_SEED, relabel=True, shuffle=True) -> Mesh:
     conn = np.stack([corner[c] for c in vtk], 1)
     s = m + 1
     return _finish(conn, HEX8, s ** 3, (s, s, s), rng, f"hex{m}", relabel, shuffle)
+
+
+def quad_grid(n: int, seed: int = BASE_SEED, relabel=True, shuffle=True) -> Mesh:
+    """Quadrilateral grid of ``n x n`` vertices (lattice id ``i*n + j``), one
+    quad per cell with its nodes around the cell."""
+    if n < 2:
+        raise ValueError("quad_grid needs n >= 2")
+    rng = np.random.default_rng(seed)
+    i, j = np.meshgrid(np.arange(n - 1), np.arange(n - 1), indexing="ij")
+    i, j = i.ravel(), j.ravel()
+    conn = np.stack([i * n + j, (i + 1) * n + j, (i + 1) * n + j + 1, i * n + j + 1], 1)
+    return _finish(conn, QUAD4, n * n, (n, n), rng, f"quad{n}", relabel, shuffle)
+
+
+def wedge_grid(n: int, layers: int, seed: int = BASE_SEED, relabel=True, shuffle=True) -> Mesh:
+    """The ``n x n`` vertex main-diagonal triangle grid extruded through
+    ``layers`` layers: lattice vertex (i, j, k) has id ``(i*n + j)*(layers+1) + k``
+    and every triangle of every layer is a wedge, its lower triangle first."""
+    if n < 2 or layers < 1:
+        raise ValueError("wedge_grid needs n >= 2 and layers >= 1")
+    rng = np.random.default_rng(seed)
+    i, j, k = np.meshgrid(np.arange(n - 1), np.arange(n - 1), np.arange(layers), indexing="ij")
+    i, j, k = i.ravel(), j.ravel(), k.ravel()
+    L = layers + 1
+
+    def vid(a, b, c):
+        return (a * n + b) * L + c
+
+    tris = [((0, 0), (0, 1), (1, 1)), ((0, 0), (1, 1), (1, 0))]
+    wedges = []
+    for t in tris:
+        lower = [vid(i + di, j + dj, k) for di, dj in t]
+        upper = [vid(i + di, j + dj, k + 1) for di, dj in t]
+        wedges.append(np.stack(lower + upper, 1))
+    conn = np.stack(wedges, 1).reshape(-1, 6)
+    return _finish(conn, WEDGE6, n * n * L, (n, n, L), rng, f"wedge{n}x{layers}", relabel, shuffle)
+
+
+# the 6 faces of a cell as quadrilaterals around the face, seen so that the
+# pyramid's base and the cell centre give a VTK pyramid
+_CELL_FACES = [
+    [(0, 0, 0), (0, 1, 0), (1, 1, 0), (1, 0, 0)],
+    [(0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)],
+    [(0, 0, 0), (1, 0, 0), (1, 0, 1), (0, 0, 1)],
+    [(0, 1, 0), (0, 1, 1), (1, 1, 1), (1, 1, 0)],
+    [(0, 0, 0), (0, 0, 1), (0, 1, 1), (0, 1, 0)],
+    [(1, 0, 0), (1, 1, 0), (1, 1, 1), (1, 0, 1)],
+]
+
+
+def pyramid_grid(m: int, seed: int = BASE_SEED, relabel=True, shuffle=True) -> Mesh:
+    """Cube of ``m^3`` cells, each cut into 6 pyramids: one per face, the
+    face as base and a vertex at the cell centre as apex.  Lattice corners
+    come first (as in ``hex_grid``), then the m^3 cell centres."""
+    if m < 1:
+        raise ValueError("pyramid_grid needs m >= 1")
+    rng = np.random.default_rng(seed)
+    corner = _cube_vertex_ids(m)
+    s = m + 1
+    centre = s ** 3 + np.arange(m ** 3)
+    pyrs = [np.stack([corner[c] for c in face] + [centre], 1) for face in _CELL_FACES]
+    conn = np.stack(pyrs, 1).reshape(-1, 5)
+    return _finish(conn, PYRAMID5, s ** 3 + m ** 3, (s ** 3 + m ** 3,), rng, f"pyramid{m}", relabel, shuffle)
+
+
+@dataclasses.dataclass
+class MixedMesh:
+    """A mesh whose elements carry their own types: ``conn`` int32 holds
+    every element's ids back to back, ``etypes`` uint8 one code per element."""
+
+    conn: np.ndarray
+    etypes: np.ndarray
+    n_vert: int
+    name: str = ""
+
+    @property
+    def n_elem(self) -> int:
+        return int(self.etypes.shape[0])
+
+    def elem_off(self):
+        npe = np.array([NODES_PER_ELEM[t] for t in range(6)], dtype=np.int64)[self.etypes.astype(np.int64)]
+        off = np.zeros(self.n_elem + 1, dtype=np.int64)
+        np.cumsum(npe, out=off[1:])
+        return off
+
+
+def _kuhn_cell_tets(corner_of):
+    out = []
+    for order in [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]:
+        p = [0, 0, 0]
+        path = [corner_of(tuple(p))]
+        for ax in order:
+            p[ax] = 1
+            path.append(corner_of(tuple(p)))
+        out.append(path)
+    return out
+
+
+def hybrid_grid(m: int, seed: int = BASE_SEED, relabel=True, shuffle=True) -> MixedMesh:
+    """Cube of ``m^3`` cells, each (by a seeded draw) one hexahedron, two
+    wedges (cut along the plane through its (0,0,z)-(1,1,z) diagonals), six
+    pyramids to a centre vertex, or six Kuhn tetrahedra.  Vertices: the
+    lattice corners, then one centre per cell (used only by pyramid cells).
+    Element order shuffled, vertex ids relabelled."""
+    if m < 1:
+        raise ValueError("hybrid_grid needs m >= 1")
+    rng = np.random.default_rng(seed)
+    s = m + 1
+    kinds = rng.integers(0, 4, size=m ** 3)
+    elems, types = [], []
+    vtk_hex = [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)]
+    cell = 0
+    for x in range(m):
+        for y in range(m):
+            for z in range(m):
+                def corner(c):
+                    return ((x + c[0]) * s + (y + c[1])) * s + (z + c[2])
+                kind = int(kinds[cell])
+                if kind == 0:
+                    elems.append([corner(c) for c in vtk_hex])
+                    types.append(HEX8)
+                elif kind == 1:
+                    for tri in (((0, 0), (1, 0), (1, 1)), ((0, 0), (1, 1), (0, 1))):
+                        elems.append([corner((a, b, 0)) for a, b in tri] + [corner((a, b, 1)) for a, b in tri])
+                        types.append(WEDGE6)
+                elif kind == 2:
+                    for face in _CELL_FACES:
+                        elems.append([corner(c) for c in face] + [s ** 3 + cell])
+                        types.append(PYRAMID5)
+                else:
+                    for t in _kuhn_cell_tets(corner):
+                        elems.append(t)
+                        types.append(TET4)
+                cell += 1
+    n_vert = s ** 3 + m ** 3
+    perm = rng.permutation(n_vert) if relabel else np.arange(n_vert)
+    order = rng.permutation(len(elems)) if shuffle else np.arange(len(elems))
+    conn = np.concatenate([perm[np.asarray(elems[e])] for e in order]).astype(np.int32)
+    etypes = np.asarray(types, dtype=np.uint8)[order]
+    return MixedMesh(conn=np.ascontiguousarray(conn), etypes=etypes, n_vert=n_vert, name=f"hybrid{m}")
+
+
+def random_mixed(n_elem: int, n_vert: int, seed: int, types=(0, 1, 2, 3, 4, 5)) -> MixedMesh:
+    """Random element types (from ``types``) with ids uniform in [0, n_vert):
+    degenerate and duplicate elements and unused vertices all occur."""
+    rng = np.random.default_rng(seed)
+    etypes = np.asarray(types, dtype=np.uint8)[rng.integers(0, len(types), size=n_elem)]
+    n_ids = int(sum(NODES_PER_ELEM[int(t)] for t in etypes))
+    conn = rng.integers(0, max(n_vert, 1), size=n_ids).astype(np.int32)
+    return MixedMesh(conn=conn, etypes=etypes, n_vert=int(n_vert), name=f"mixed{n_elem}x{n_vert}")
 
 
 def random_mesh(n_elem: int, n_vert: int, etype: int, seed: int) -> Mesh:

@@ -21,21 +21,60 @@ import numpy as np
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
-NPE = {0: 3, 1: 4, 2: 8}
+NPE = {0: 3, 1: 4, 2: 8, 3: 4, 4: 6, 5: 5}
 
+# Reference cells (VTK node orders) as coordinates.
+REF_COORDS = {
+    0: [(0, 0), (1, 0), (0, 1)],
+    1: [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)],
+    2: [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)],
+    3: [(0, 0), (1, 0), (1, 1), (0, 1)],
+    4: [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (0, 1, 1)],
+    5: [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0.5, 0.5, 1)],
+}
 # VTK hexahedron corner coordinates (unit cube).
-_HEX_CORNERS = [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)]
+_HEX_CORNERS = REF_COORDS[2]
+
+
+def hull_edges(coords):
+    """Edges of the convex polytope with the given corners, from geometry
+    alone.  In the plane: a pair is an edge when every other corner lies on
+    one side of the line through it.  In space: a facet is a plane through
+    three corners with every corner on one side (or on it); a pair is an edge
+    when two different facets contain it."""
+    x = np.asarray(coords, dtype=np.float64)
+    n, d = x.shape
+    out = []
+    if d == 2:
+        for a, b in itertools.combinations(range(n), 2):
+            t = x[b] - x[a]
+            side = [t[0] * (x[c] - x[a])[1] - t[1] * (x[c] - x[a])[0] for c in range(n) if c not in (a, b)]
+            if all(v > 1e-12 for v in side) or all(v < -1e-12 for v in side):
+                out.append((a, b))
+        return out
+    facets = set()
+    for tri in itertools.combinations(range(n), 3):
+        nrm = np.cross(x[tri[1]] - x[tri[0]], x[tri[2]] - x[tri[0]])
+        if np.linalg.norm(nrm) < 1e-12:
+            continue
+        h = (x - x[tri[0]]) @ nrm
+        if np.all(h <= 1e-12) or np.all(h >= -1e-12):
+            facets.add(frozenset(int(i) for i in np.flatnonzero(np.abs(h) <= 1e-12)))
+    for a, b in itertools.combinations(range(n), 2):
+        if sum(1 for f in facets if a in f and b in f) >= 2:
+            out.append((a, b))
+    return out
 
 
 def edge_pairs(etype: int):
-    """Node-position pairs joined by an element edge, derived from geometry.
+    """Node-position pairs joined by an element edge, derived from the
+    reference cell's geometry (its convex hull), not from a table."""
+    return hull_edges(REF_COORDS[etype])
 
-    Simplices: every pair of nodes.  Hexahedron: corner pairs that differ in
-    exactly one coordinate of the unit cube (the 12 edges).
-    """
-    npe = NPE[etype]
-    if etype in (0, 1):
-        return list(itertools.combinations(range(npe), 2))
+
+def hex_edges_by_axis():
+    """The cube's edges a second way: corner pairs that differ in exactly one
+    coordinate."""
     out = []
     for a, b in itertools.combinations(range(8), 2):
         if sum(x != y for x, y in zip(_HEX_CORNERS[a], _HEX_CORNERS[b])) == 1:
@@ -69,6 +108,63 @@ def brute_force(conn, etype, n_vert):
         node_rows.append(sorted(nb))
         elem_rows.append(sorted(el))
     return _to_csr(node_rows), _to_csr(elem_rows)
+
+
+def _mixed_elements(conn, etypes):
+    conn = np.asarray(conn).ravel().tolist()
+    out, at = [], 0
+    for t in np.asarray(etypes).ravel().tolist():
+        out.append((int(t), conn[at:at + NPE[int(t)]]))
+        at += NPE[int(t)]
+    assert at == len(conn)
+    return out
+
+
+def brute_force_mixed(conn, etypes, n_vert):
+    """(node_csr, elem_csr) of a mesh with one type per element, by scanning
+    all elements for each vertex, each with its own type's edges."""
+    elems = _mixed_elements(conn, etypes)
+    pairs = {t: edge_pairs(t) for t in NPE}
+    node_rows, elem_rows = [], []
+    for v in range(n_vert):
+        nb, el = set(), set()
+        for e, (t, row) in enumerate(elems):
+            if v in row:
+                el.add(e)
+            for i, j in pairs[t]:
+                if row[i] == v and row[j] != v:
+                    nb.add(row[j])
+                if row[j] == v and row[i] != v:
+                    nb.add(row[i])
+        node_rows.append(sorted(nb))
+        elem_rows.append(sorted(el))
+    return _to_csr(node_rows), _to_csr(elem_rows)
+
+
+def scipy_mixed(conn, etypes, n_vert):
+    """(node_csr, elem_csr) of a mixed mesh by sparse assembly."""
+    import scipy.sparse as sp
+
+    elems = _mixed_elements(conn, etypes)
+    u, w, vv, ee = [], [], [], []
+    for e, (t, row) in enumerate(elems):
+        for i, j in edge_pairs(t):
+            u.append(row[i])
+            w.append(row[j])
+        vv += row
+        ee += [e] * len(row)
+    a = sp.coo_matrix((np.ones(len(u)), (np.asarray(u, dtype=np.int64), np.asarray(w, dtype=np.int64))),
+                      shape=(n_vert, n_vert)).tocsr()
+    a = (a + a.T).tocsr()
+    a.setdiag(0)
+    a.eliminate_zeros()
+    a.sort_indices()
+    b = sp.coo_matrix((np.ones(len(vv)), (np.asarray(vv, dtype=np.int64), np.asarray(ee, dtype=np.int64))),
+                      shape=(n_vert, len(elems))).tocsr()
+    b.sum_duplicates()
+    b.sort_indices()
+    return ((a.indptr.astype(np.int32), a.indices.astype(np.int32)),
+            (b.indptr.astype(np.int32), b.indices.astype(np.int32)))
 
 
 def scipy_csr(conn, etype, n_vert):
@@ -105,6 +201,8 @@ def scipy_csr(conn, etype, n_vert):
 TRI_MAIN_STEPS = [(1, 0), (0, 1), (1, 1)]          # grid edges plus main diagonal
 KUHN_STEPS = [s for s in itertools.product((0, 1), repeat=3) if any(s)]
 HEX_STEPS = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+QUAD_STEPS = [(1, 0), (0, 1)]
+WEDGE_STEPS = [(1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 1)]  # main-diagonal triangles, extruded
 
 
 def lattice_node_csr(dims, steps, perm):

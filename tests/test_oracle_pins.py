@@ -30,14 +30,69 @@ def test_golden_cases_agree_with_brute_force():
         assert _eq(er, case["elem_row_ptr"]) and _eq(ec, case["elem_cols"]), case["name"]
 
 
-def test_hex_edge_pairs_from_geometry():
-    # the 12 cube edges: 4 per axis
-    pairs = pins.edge_pairs(2)
-    assert len(pairs) == 12
-    assert len(pins.edge_pairs(1)) == 6 and len(pins.edge_pairs(0)) == 3
+def test_edge_pairs_from_geometry():
+    # edges of each reference cell's convex hull: triangle 3, tetrahedron 6,
+    # cube 12 (also: corner pairs differing in one coordinate), square 4,
+    # wedge 9, pyramid 8
+    assert [len(pins.edge_pairs(t)) for t in range(6)] == [3, 6, 12, 4, 9, 8]
+    assert sorted(pins.edge_pairs(2)) == sorted(pins.hex_edges_by_axis())
+    assert (0, 2) not in pins.edge_pairs(3) and (1, 3) not in pins.edge_pairs(3)  # no quad diagonals
+    assert all(4 in e for e in pins.edge_pairs(5) if 4 in e) and sum(4 in e for e in pins.edge_pairs(5)) == 4
 
 
-@pytest.mark.parametrize("etype", [0, 1, 2])
+@pytest.mark.parametrize("case", pins.read_golden("mixed_cases.txt"), ids=lambda c: c["name"])
+def test_mixed_hand_cases(oracle_mod, case):
+    nr, nc = oracle_mod.mixed_node_neighbors(case["conn"], case["etypes"], case["n_vert"])
+    er, ec = oracle_mod.mixed_elem_neighbors(case["conn"], case["etypes"], case["n_vert"])
+    assert _eq(nr, case["node_row_ptr"]) and _eq(nc, case["node_cols"])
+    assert _eq(er, case["elem_row_ptr"]) and _eq(ec, case["elem_cols"])
+    (bnr, bnc), (ber, bec) = pins.brute_force_mixed(case["conn"], case["etypes"], case["n_vert"])
+    assert _eq(bnr, case["node_row_ptr"]) and _eq(bnc, case["node_cols"])
+    assert _eq(ber, case["elem_row_ptr"]) and _eq(bec, case["elem_cols"])
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_mixed_vs_brute_force_and_scipy(oracle_mod, seed):
+    rng = np.random.default_rng(3000 + seed)
+    m = mg.random_mixed(int(rng.integers(0, 40)), int(rng.integers(1, 25)), seed)
+    want = pins.brute_force_mixed(m.conn, m.etypes, m.n_vert)
+    got = (oracle_mod.mixed_node_neighbors(m.conn, m.etypes, m.n_vert),
+           oracle_mod.mixed_elem_neighbors(m.conn, m.etypes, m.n_vert))
+    for (a, b), (c, d) in zip(got, want):
+        assert _eq(a, c) and _eq(b, d)
+    big = mg.random_mixed(int(rng.integers(100, 5000)), int(rng.integers(10, 3000)), seed + 50)
+    want = pins.scipy_mixed(big.conn, big.etypes, big.n_vert)
+    got = (oracle_mod.mixed_node_neighbors(big.conn, big.etypes, big.n_vert),
+           oracle_mod.mixed_elem_neighbors(big.conn, big.etypes, big.n_vert))
+    for (a, b), (c, d) in zip(got, want):
+        assert _eq(a, c) and _eq(b, d)
+
+
+def test_mixed_of_one_type_is_the_uniform_relation(oracle_mod):
+    for et in range(6):
+        m = mg.random_mesh(300, 80, et, seed=40 + et)
+        types = np.full(m.n_elem, et)
+        assert all(_eq(a, b) for a, b in zip(oracle_mod.mixed_node_neighbors(m.conn, types, m.n_vert),
+                                              oracle_mod.node_neighbors(m.conn, et, m.n_vert)))
+        assert all(_eq(a, b) for a, b in zip(oracle_mod.mixed_elem_neighbors(m.conn, types, m.n_vert),
+                                              oracle_mod.elem_neighbors(m.conn, et, m.n_vert)))
+
+
+def test_hybrid_grid_vs_scipy_and_invariants(oracle_mod):
+    m = mg.hybrid_grid(6, seed=8)
+    nr, nc = oracle_mod.mixed_node_neighbors(m.conn, m.etypes, m.n_vert)
+    er, ec = oracle_mod.mixed_elem_neighbors(m.conn, m.etypes, m.n_vert)
+    (snr, snc), (ser, sec) = pins.scipy_mixed(m.conn, m.etypes, m.n_vert)
+    assert _eq(nr, snr) and _eq(nc, snc) and _eq(er, ser) and _eq(ec, sec)
+    assert pins.is_symmetric(nr, nc) and pins.rows_strictly_increasing(nr, nc)
+    assert ec.shape[0] == m.conn.shape[0]  # no degenerate elements: one entry per slot
+    off = m.elem_off()
+    rid_e = pins.row_ids(er)
+    assert set(zip(rid_e.tolist(), ec.tolist())) == {
+        (int(v), e) for e in range(m.n_elem) for v in m.conn[off[e]:off[e + 1]]}
+
+
+@pytest.mark.parametrize("etype", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("seed", range(6))
 def test_random_meshes_vs_brute_force(oracle_mod, etype, seed):
     rng = np.random.default_rng(1000 + seed)
@@ -51,7 +106,7 @@ def test_random_meshes_vs_brute_force(oracle_mod, etype, seed):
     assert _eq(er, ber) and _eq(ec, bec)
 
 
-@pytest.mark.parametrize("etype", [0, 1, 2])
+@pytest.mark.parametrize("etype", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("seed", range(4))
 def test_random_meshes_vs_scipy(oracle_mod, etype, seed):
     rng = np.random.default_rng(2000 + seed)
@@ -66,7 +121,8 @@ def test_random_meshes_vs_scipy(oracle_mod, etype, seed):
 
 
 def test_structured_meshes_vs_scipy(oracle_mod):
-    for m in (mg.tri_grid(40, "coin", 5), mg.kuhn_tet_grid(7, 6), mg.hex_grid(6, 7)):
+    for m in (mg.tri_grid(40, "coin", 5), mg.kuhn_tet_grid(7, 6), mg.hex_grid(6, 7), mg.quad_grid(30, 8),
+              mg.wedge_grid(12, 5, 9), mg.pyramid_grid(5, 10)):
         (snr, snc), (ser, sec) = pins.scipy_csr(m.conn, m.etype, m.n_vert)
         nr, nc = oracle_mod.node_neighbors(m.conn, m.etype, m.n_vert)
         er, ec = oracle_mod.elem_neighbors(m.conn, m.etype, m.n_vert)
@@ -128,6 +184,47 @@ def test_hex_lattice_rows(oracle_mod, m_cells):
     assert ec.shape[0] == 8 * m_cells ** 3
 
 
+@pytest.mark.parametrize("n", [2, 3, 20])
+def test_quad_lattice_rows(oracle_mod, n):
+    m = mg.quad_grid(n, seed=n)
+    er = pins.lattice_node_csr(m.dims, pins.QUAD_STEPS, m.perm)
+    nr, nc = oracle_mod.node_neighbors(m.conn, m.etype, m.n_vert)
+    assert _eq(nr, er[0]) and _eq(nc, er[1])
+    assert nc.shape[0] == 2 * 2 * n * (n - 1)
+    _, ec = oracle_mod.elem_neighbors(m.conn, m.etype, m.n_vert)
+    assert ec.shape[0] == 4 * (n - 1) ** 2
+
+
+@pytest.mark.parametrize("n,layers", [(2, 1), (5, 3), (16, 4)])
+def test_wedge_lattice_rows(oracle_mod, n, layers):
+    # the main-diagonal triangle grid's edges in every layer plus the
+    # verticals; the quadrilateral faces' diagonals are not edges
+    m = mg.wedge_grid(n, layers, seed=n + layers)
+    er = pins.lattice_node_csr(m.dims, pins.WEDGE_STEPS, m.perm)
+    nr, nc = oracle_mod.node_neighbors(m.conn, m.etype, m.n_vert)
+    assert _eq(nr, er[0]) and _eq(nc, er[1])
+    assert nc.shape[0] == 2 * ((layers + 1) * pins.tri_grid_edge_count(n) + n * n * layers)
+
+
+@pytest.mark.parametrize("m_cells", [1, 3, 7])
+def test_pyramid_grid_closed_forms(oracle_mod, m_cells):
+    # every lattice edge of the cube grid, plus each cell centre joined to its
+    # 8 corners; an interior corner has 6 lattice and 8 centre neighbours and
+    # lies in 3 pyramids of each of its 8 cells; a centre has 8 neighbours
+    # and 6 pyramids
+    m = mg.pyramid_grid(m_cells, seed=m_cells)
+    s = m_cells + 1
+    nr, nc = oracle_mod.node_neighbors(m.conn, m.etype, m.n_vert)
+    er, ec = oracle_mod.elem_neighbors(m.conn, m.etype, m.n_vert)
+    assert nc.shape[0] == 2 * (pins.hex_edge_count(m_cells) + 8 * m_cells ** 3)
+    assert ec.shape[0] == 5 * 6 * m_cells ** 3
+    coords = np.stack(np.unravel_index(np.arange(s ** 3), (s, s, s)), 1)
+    interior = m.perm[:s ** 3][np.all((coords > 0) & (coords < m_cells), axis=1)]
+    centres = m.perm[s ** 3:]
+    assert np.all(np.diff(nr)[interior] == 14) and np.all(np.diff(er)[interior] == 24)
+    assert np.all(np.diff(nr)[centres] == 8) and np.all(np.diff(er)[centres] == 6)
+
+
 @pytest.mark.parametrize("n", [5, 64, 300])
 def test_coin_grid_euler_and_degrees(oracle_mod, n):
     # a triangulated disk: V - E + F = 1, so node nnz = 2E = 2(V + F - 1);
@@ -151,6 +248,9 @@ def test_coin_grid_euler_and_degrees(oracle_mod, n):
 @pytest.mark.parametrize("etype,maker", [(0, lambda: mg.tri_grid(33, "coin", 3)),
                                          (1, lambda: mg.kuhn_tet_grid(5, 4)),
                                          (2, lambda: mg.hex_grid(5, 5)),
+                                         (3, lambda: mg.quad_grid(20, 6)),
+                                         (4, lambda: mg.wedge_grid(9, 3, 7)),
+                                         (5, lambda: mg.pyramid_grid(4, 8)),
                                          (1, lambda: mg.random_mesh(500, 120, 1, 9))])
 def test_invariants(oracle_mod, etype, maker):
     m = maker()
@@ -206,3 +306,7 @@ def test_errors(oracle_mod):
         oracle_mod.elem_neighbors(np.array([[0, -1, 2]]), 0, 3)
     with pytest.raises(oracle_mod.OracleError):
         oracle_mod.node_neighbors(np.array([[0, 1, 2]]), 7, 3)
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.mixed_node_neighbors(np.array([0, 1, 2, 3]), [0], 4)  # 4 ids for one triangle
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.mixed_elem_neighbors(np.array([0, 1, 9]), [0], 4)
