@@ -1,16 +1,21 @@
 #!/usr/bin/env python3
 """Throughput of the one-ring node + element neighbor CSR build on one GPU.
 
-A step is one pass of the whole hot path over one mesh: the node pipeline
-(pair emission, LSD radix sort, unique/CSR) and the element pipeline
-(counting sort by vertex, row sort), both on one stream, inputs resident in
-device memory.  Prints ONE JSON line on stdout; progress goes to stderr.
+A step is one pass of the whole hot path over one mesh: one mesh_neighbors
+call building both relations (the element relation's counting sort of
+(vertex, element) pairs by vertex, and the node relation, under the tuned
+node algorithm), on one stream, inputs resident in device memory.  Prints ONE
+JSON line on stdout; progress goes to stderr.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--workload tri2048]
 
 The headline workload is a 2048 x 2048-vertex triangle surface with coin-flip
-diagonals (8,380,418 triangles); the 96^3-cell Kuhn tetrahedral cube is
-measured beside it.  Inputs are synthetic (seeded generators).
+diagonals (8,380,418 triangles); beside it: the 96^3-cell Kuhn tetrahedral
+cube, the 64 x 64 triangle grid (microseconds), the node algorithms compared
+on both big meshes, the 512-mesh batch (one batched call vs 512 plain calls
+vs 512 graph replays) and the served request stream at offered loads of 0.5,
+0.8 and 0.95 of its measured capacity.  Inputs are synthetic (seeded
+generators).
 """
 from __future__ import annotations
 
@@ -18,6 +23,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -26,9 +32,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "elements/s for node+elem one-ring CSR build (HBM GB/s); batched vs per-mesh"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
-EDGES = {0: 3, 1: 6, 2: 12}
-NPE = {0: 3, 1: 4, 2: 8}
-TYPE_NAME = {0: "tri3", 1: "tet4", 2: "hex8"}
+EDGES = {0: 3, 1: 6, 2: 12, 3: 4, 4: 9, 5: 8}
+NPE = {0: 3, 1: 4, 2: 8, 3: 4, 4: 6, 5: 5}
+TYPE_NAME = {0: "tri3", 1: "tet4", 2: "hex8", 3: "quad4", 4: "wedge6", 5: "pyramid5"}
+SORT_NAME = {0: "full_key", 1: "vertex_rows", 2: "edge_rows", 3: "elem_rows"}
 PROFILES = os.path.join(ROOT, "profiles")
 
 WORKLOADS = {
@@ -40,8 +47,7 @@ WORKLOADS = {
               "ids permuted, rows shuffled"),
 }
 
-
-SERVE_OFFERED = 0.6e9  # elements/s offered to the serving stream (Poisson arrivals)
+SERVE_RHO = (0.5, 0.8, 0.95)
 
 
 def log(*a):
@@ -61,146 +67,149 @@ def id_bits(n_vert):
 
 
 def kernel_bytes(m, nnz_node, nnz_elem, node_sort):
-    """Algorithmic HBM bytes per launch of every kernel of the two pipelines:
-    what the kernel must read and write at least once.  P = directed edge
-    pairs (2 x edges per element x F), Q = element pairs (nnz of the element
-    relation), U = node nnz, V = vertices, conn = 4 x npe x F bytes.  The node
-    sort passes move K keys: P, or with the edge-rows algorithm the k x F
-    canonical edge keys; E = U / 2 unique edges.  The element sort's last
-    pass reads keys and writes cols and the row starts instead of keys, so
-    elem_radix is the mean over its middle passes and that last one."""
+    """Algorithmic HBM bytes per launch of every kernel of a step: what the
+    kernel must read and write at least once.  P = directed edge pairs
+    (2 x edges per element x F), Q = element pairs (nnz of the element
+    relation), U = node nnz, V = vertices, conn = 4 x npe x F bytes.  The
+    element sort's last pass reads keys and writes cols and the row starts
+    instead of keys, so elem_radix is the mean over its middle passes and that
+    last one.  node_erows (rows gathered through the element relation) reads
+    the element CSR and conn once and writes the node CSR."""
     f, v, k, npe = m.n_elem, m.n_vert, EDGES[m.etype], NPE[m.etype]
     p_pairs, q_pairs, u = 2 * k * f, nnz_elem, nnz_node
     keys = k * f if node_sort == 2 else p_pairs
     e = u // 2
     conn = 4 * npe * f
-    id_bits = max(1, (v - 1).bit_length())
-    elem_passes = (id_bits + 7) // 8
+    elem_passes = (id_bits(v) + 7) // 8
     csr_out = 4 * q_pairs + 4 * (v + 1)                      # cols and row starts
     later = [16 * q_pairs] * (elem_passes - 2) + [8 * q_pairs + csr_out]
-    # edge passes sort the E transposed edges by their higher vertex (id_bits);
-    # the last one writes the lower neighbours and their group starts
     edge_passes = [16 * e] * (elem_passes - 1) + [8 * e + 4 * e + 4 * (v + 1)]
     return {
-        "node_hist": conn,                                  # read conn
-        "node_radix_first": conn + 8 * keys,                # read conn, write keys
-        "node_radix": 16 * keys,                            # read + write keys
+        "node_hist": conn,
+        "node_radix_first": conn + 8 * keys,
+        "node_radix": 16 * keys,
         "node_unique_csr": 8 * keys + 4 * u + 4 * (v + 1),
-        "node_row_unique": 8 * keys + 4 * (e if node_sort == 2 else u) + 12 * v,  # keys in; row values + deg/src out
+        "node_row_unique": 8 * keys + 4 * (e if node_sort == 2 else u) + 12 * v,
         "node_row_scan": 8 * v,
         "node_row_gather": 8 * u + 12 * v + 4 * (v + 1),
         "node_long_rows": 0,                                # only rows past the short limit; data-dependent
-        "node_edge_transpose": 4 * e + 12 * v + 12 * e,     # row values, up_ptr/deg/src in; keys + ids out
+        "node_edge_transpose": 4 * e + 12 * v + 12 * e,
         "node_edge_hist": 8 * e,
         "node_edge_radix": sum(edge_passes) // len(edge_passes),
         "node_edge_low_fill": 4 * (v + 1),
         "node_edge_merge": 8 * e + 8 * (v + 1) + 4 * u + 4 * (v + 1),
+        "node_erows_prep": 4 * (v + 1),                     # element row starts in; tile table (small) out
+        "node_erows_long": 0,                               # long rows only; data-dependent
+        "node_erows": 4 * (v + 1) + 4 * q_pairs + conn + 4 * (v + 1) + 4 * u,
         "elem_hist": conn,
         "elem_radix_first": conn + (8 * q_pairs if elem_passes > 1 else csr_out),
         "elem_radix": sum(later) // len(later) if elem_passes > 1 else 0,
-        "elem_row_fill": 4 * (v + 1),                       # block minima, then the fill: each reads row_ptr
+        "elem_row_fill": 4 * (v + 1),
         "fill": 0,
     }
 
 
-def radix_source_hash():
+def source_hash():
+    """Hash of every kernel source: a traffic record taken on other source is stale."""
     h = hashlib.sha256()
-    for f in ("radix.hpp", "common.hpp", "launch.hpp"):
-        with open(os.path.join(ROOT, "paper_1604_04689_amd", "csrc", f), "rb") as fh:
+    csrc = os.path.join(ROOT, "paper_1604_04689_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload, node_sort):
-    """HBM bytes per node_radix launch from the committed rocprofv3 counter
-    summary, or None if absent, taken on different kernel source, or with a
-    different node algorithm (which changes the keys per launch)."""
-    path = os.path.join(PROFILES, f"node_radix_{workload}_traffic.json")
+def load_traffic(kernel, workload, node_sort):
+    """Measured HBM bytes per launch of `kernel` from the committed rocprofv3
+    counter summary, or None if absent or taken on other source or with
+    another node algorithm."""
+    path = os.path.join(PROFILES, f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("source_sha") != radix_source_hash() or t.get("node_sort") != node_sort:
+    if t.get("source_sha") != source_hash() or t.get("node_sort") != node_sort:
         return None
     return t.get("bytes_per_launch")
 
 
-def time_graph_replays(torch, graphs, builds, stream, steps):
-    """Seconds per step of replaying the captured graphs; checks that the
-    replays leave exactly the eager outputs in place."""
-    before = [(b.row_ptr.clone(), b.cols.clone()) for b in builds]
-    for g in graphs:
-        g.launch(stream)
+def _sync_time(torch, fn, steps):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        for g in graphs:
-            g.launch(stream)
+        fn()
     torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / steps
-    for b, (rp, cols) in zip(builds, before):
-        b.check(stream)
-        nnz = int(rp[-1].item())
-        if not (torch.equal(b.row_ptr, rp) and torch.equal(b.cols[:nnz], cols[:nnz])):
-            raise RuntimeError("graph replay differs from the eager result")
-    for g in graphs:
-        g.destroy()
+    return (time.perf_counter() - t0) / steps
+
+
+def _snapshot(build):
+    outs = [build.row_ptr, build.cols] + ([build.elem_row_ptr, build.elem_cols] if build.kind == "both" else [])
+    return [t.clone() for t in outs]
+
+
+def _same_as(build, snap):
+    outs = [build.row_ptr, build.cols] + ([build.elem_row_ptr, build.elem_cols] if build.kind == "both" else [])
+    return all(a.shape == b.shape and bool((a == b).all()) for a, b in zip(outs, snap))
+
+
+def time_graph(torch, build, conn, stream, steps):
+    """Seconds per step of replaying a captured graph of the call; the
+    replays must leave exactly the eager outputs."""
+    before = _snapshot(build)
+    g = build.capture(conn)
+    g.launch(stream)
+    sec = _sync_time(torch, lambda: g.launch(stream), steps)
+    build.check(stream)
+    if not _same_as(build, before):
+        raise RuntimeError("graph replay differs from the eager result")
+    g.destroy()
     return sec
 
 
-def time_two_streams(torch, node, elem, conn, stream, steps):
-    """Seconds per step with the two relations on two streams (they are
-    independent, so their radix passes overlap); outputs checked against the
-    sequential ones."""
-    side = torch.cuda.Stream(conn.device)
-    before = [(b.row_ptr.clone(), b.cols.clone()) for b in (node, elem)]
+def time_e2e(torch, nb, m, build, steps):
+    """Seconds per step including the upload of conn from pinned host memory
+    and the download of both CSRs into pinned host memory (context for a
+    caller whose mesh lives on the host)."""
+    dev = build.device
+    host_conn = torch.as_tensor(m.conn).pin_memory()
+    conn = torch.empty(host_conn.shape, dtype=torch.int32, device=dev)
+    outs = [build.row_ptr, build.cols, build.elem_row_ptr, build.elem_cols]
+    host_out = [torch.empty(o.shape, dtype=o.dtype).pin_memory() for o in outs]
+    stream = torch.cuda.current_stream(dev)
 
     def step():
-        ev = torch.cuda.Event()
-        ev.record(stream)
-        side.wait_event(ev)
-        node.launch(conn, stream, tuned=True)
-        elem.launch(conn, side, tuned=True)
-        back = torch.cuda.Event()
-        back.record(side)
-        stream.wait_event(back)
+        conn.copy_(host_conn, non_blocking=True)
+        build.launch(conn, stream)
+        for h, o in zip(host_out, outs):
+            h.copy_(o, non_blocking=True)
 
     step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / steps
-    for b, (rp, cols) in zip((node, elem), before):
-        b.check(stream)
-        nnz = int(rp[-1].item())
-        if not (torch.equal(b.row_ptr, rp) and torch.equal(b.cols[:nnz], cols[:nnz])):
-            raise RuntimeError("two-stream step differs from the sequential result")
-    return sec
+    sec = _sync_time(torch, step, steps)
+    build.check(stream)
+    bytes_moved = host_conn.numel() * 4 + sum(o.numel() * 4 for o in outs)
+    return sec, bytes_moved
 
 
-def run_workload(name, steps, warmup, torch, nb):
+def run_workload(name, steps, warmup, torch, nb, compare_sorts=True, e2e=True):
     log(f"[bench] generating {name} ...")
     t = time.time()
     m = make_mesh(name)
     log(f"[bench] {name}: F={m.n_elem} V={m.n_vert} ({time.time() - t:.1f}s)")
     dev = torch.device("cuda:0")
     conn = torch.as_tensor(m.conn).to(dev)
-    node = nb.NeighborBuild("node", m.n_elem, m.etype, m.n_vert, dev)
-    elem = nb.NeighborBuild("elem", m.n_elem, m.etype, m.n_vert, dev)
+    build = nb.NeighborBuild("both", m.n_elem, m.etype, m.n_vert, dev, options="tuned")
+    opts = build.options.as_dict()
+    node_sort = opts["node_sort"] if opts["node_sort"] >= 0 else 3
     stream = torch.cuda.current_stream(dev)
 
     def step():
-        node.launch(conn, stream, tuned=True)
-        elem.launch(conn, stream, tuned=True)
+        build.launch(conn, stream)
 
     for _ in range(max(warmup, 1)):
         step()
-    node.check(stream)
-    elem.check(stream)
-    nnz_node = int(node.row_ptr[-1].item())
-    nnz_elem = int(elem.row_ptr[-1].item())
+    build.check(stream)
+    nnz_node = int(build.row_ptr[-1].item())
+    nnz_elem = int(build.elem_row_ptr[-1].item())
     torch.cuda.synchronize()
 
     nb.timing_read()  # clear
@@ -213,18 +222,10 @@ def run_workload(name, steps, warmup, torch, nb):
     t1 = time.perf_counter()
     nb.timing_enable(False)
     kt = nb.timing_read()
-    node.check(stream)
-    elem.check(stream)
-
+    build.check(stream)
     sec = (t1 - t0) / steps
-    graph_sec = time_graph_replays(torch, [node.capture(conn, tuned=True), elem.capture(conn, tuned=True)],
-                                   [node, elem], stream, steps)
-    two_sec = time_two_streams(torch, node, elem, conn, stream, steps)
-    from paper_1604_04689_amd import autotune
-    tuned = {kind: autotune.lookup(kind, m.etype, m.n_elem) for kind in ("node", "elem")}
-    node_sort = tuned["node"]["mode"] if tuned["node"] else 0
-    tuned = {kind: (None if e is None else {"shape": nb.radix_shapes()[e["shape"]], "node_sort": e["mode"]})
-             for kind, e in tuned.items()}
+
+    graph_sec = time_graph(torch, build, conn, stream, steps)
     kb = kernel_bytes(m, nnz_node, nnz_elem, node_sort)
     kernels = {}
     model_total = 0
@@ -234,43 +235,87 @@ def run_workload(name, steps, warmup, torch, nb):
         model_total += per * launches / steps
         kernels[k] = {"launches_per_step": launches / steps, "us_per_step": total_ms / steps * 1e3,
                       "avg_us": avg_ms * 1e3, "bytes_per_launch": per,
-                      "GBs": per / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None}
-    node_p = sum(kt[k][0] for k in ("node_radix_first", "node_radix") if k in kt) // steps
-    elem_p = sum(kt[k][0] for k in ("elem_radix_first", "elem_radix") if k in kt) // steps
-    node_ms = sum(v[1] for k, v in kt.items() if k.startswith("node_")) / steps
-    elem_ms = sum(v[1] for k, v in kt.items() if k.startswith("elem_")) / steps
+                      "GBs": per / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 and per else None}
+    modeled = {k: v for k, v in kernels.items() if v["bytes_per_launch"]}
+    dom = max(modeled, key=lambda k: modeled[k]["us_per_step"])
     res = {
         "workload": name,
         "n_elem": m.n_elem, "n_vert": m.n_vert, "etype": TYPE_NAME[m.etype],
-        "nnz_node": nnz_node, "nnz_elem": nnz_elem, "radix_passes": {"node": node_p, "elem": elem_p}, "tuned": tuned,
+        "nnz_node": nnz_node, "nnz_elem": nnz_elem,
+        "options": {**opts, "node_sort_name": SORT_NAME[node_sort],
+                    "radix_shape": nb.radix_shapes()[opts["radix_shape"]] if opts["radix_shape"] >= 0 else None},
+        "radix_passes_elem": sum(kt[k][0] for k in ("elem_radix_first", "elem_radix") if k in kt) // steps,
         "ms_per_step": sec * 1e3,
         "elements_per_s": m.n_elem / sec,
         "graph_ms_per_step": graph_sec * 1e3,
-        "two_streams_ms_per_step": two_sec * 1e3,
-        "two_streams_elements_per_s": m.n_elem / two_sec,
-        "node_kernel_ms": node_ms, "elem_kernel_ms": elem_ms,
+        "graph_elements_per_s": m.n_elem / graph_sec,
+        "node_kernel_ms": sum(v[1] for k, v in kt.items() if k.startswith("node_")) / steps,
+        "elem_kernel_ms": sum(v[1] for k, v in kt.items() if k.startswith("elem_")) / steps,
         "kernels": kernels,
         "pipeline_model_bytes": model_total,
         "pipeline_model_GBs": model_total / sec / 1e9,
         "pipeline_frac_of_hbm": model_total / sec / 1e9 / HBM_PEAK_GBS,
-        "radix_pass": {"kernel": "node_radix", "avg_ms": kernels["node_radix"]["avg_us"] * 1e-3,
-                       "bytes_per_launch": kb["node_radix"], "GBs": kernels["node_radix"]["GBs"]},
+        "dominant_kernel": {"kernel": dom, "avg_ms": kernels[dom]["avg_us"] * 1e-3,
+                            "bytes_per_launch": kernels[dom]["bytes_per_launch"], "GBs": kernels[dom]["GBs"],
+                            "us_per_step": kernels[dom]["us_per_step"]},
     }
     log(f"[bench] {name}: {sec * 1e3:.3f} ms/step eager, {graph_sec * 1e3:.3f} ms/step graph replay, "
-        f"{two_sec * 1e3:.3f} ms/step on two streams, "
-        f"{m.n_elem / sec / 1e9:.3f} G elem/s, "
+        f"{m.n_elem / sec / 1e9:.3f} G elem/s ({SORT_NAME[node_sort]}), "
         f"pipeline {res['pipeline_model_GBs']:.0f} GB/s of model bytes")
     for k, v in kernels.items():
         gbs = f"{v['GBs']:7.0f} GB/s" if v["GBs"] else ""
-        log(f"[bench]   {k:18s} {v['launches_per_step']:4.1f} x {v['avg_us']:8.1f} us = {v['us_per_step']:8.1f} us/step {gbs}")
-    del node, elem, conn
+        log(f"[bench]   {k:22s} {v['launches_per_step']:4.1f} x {v['avg_us']:8.1f} us = {v['us_per_step']:8.1f} us/step {gbs}")
+
+    if compare_sorts:
+        # every node algorithm on the same mesh, the call building both
+        # relations (default tile shape); outputs compared byte for byte
+        ref = _snapshot(build)
+        by_sort = {}
+        for ns in (0, 1, 2, 3):
+            b = nb.NeighborBuild("both", m.n_elem, m.etype, m.n_vert, dev, options={"node_sort": ns})
+            b.launch(conn, stream)
+            b.check(stream)
+            if not _same_as(b, ref):
+                raise RuntimeError(f"node algorithm {SORT_NAME[ns]} differs from the tuned result")
+            s = _sync_time(torch, lambda: b.launch(conn, stream), max(3, steps // 2))
+            by_sort[SORT_NAME[ns]] = {"ms_per_step": s * 1e3, "elements_per_s": m.n_elem / s,
+                                      "workspace_bytes": b.ws_bytes}
+            log(f"[bench] {name} {SORT_NAME[ns]:12s}: {s * 1e3:.3f} ms/step, workspace {b.ws_bytes / 1e6:.0f} MB")
+            del b
+            torch.cuda.empty_cache()
+        res["by_node_sort"] = by_sort
+    if e2e:
+        s, nbytes = time_e2e(torch, nb, m, build, max(3, steps // 2))
+        res["with_transfers"] = {"ms_per_step": s * 1e3, "elements_per_s": m.n_elem / s, "pcie_bytes": nbytes,
+                                 "note": "conn uploaded from pinned host memory and both CSRs downloaded to "
+                                         "pinned host memory inside each step (context only)"}
+        log(f"[bench] {name} with H2D/D2H: {s * 1e3:.3f} ms/step ({nbytes / 1e6:.0f} MB over PCIe)")
+    del build, conn
     torch.cuda.empty_cache()
     return m, res
 
 
+def run_tiny(torch, nb, steps=200):
+    """The 64 x 64 grid: microseconds per step, eager and graph replay."""
+    m = make_mesh("tri64")
+    dev = torch.device("cuda:0")
+    conn = torch.as_tensor(m.conn).to(dev)
+    b = nb.NeighborBuild("both", m.n_elem, m.etype, m.n_vert, dev, options="tuned")
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(10):
+        b.launch(conn, stream)
+    b.check(stream)
+    sec = _sync_time(torch, lambda: b.launch(conn, stream), steps)
+    gsec = time_graph(torch, b, conn, stream, steps)
+    log(f"[bench] tri64: {sec * 1e6:.1f} us/step eager, {gsec * 1e6:.1f} us/step graph replay")
+    return {"workload": WORKLOADS["tri64"], "us_per_step": sec * 1e6, "graph_us_per_step": gsec * 1e6,
+            "elements_per_s": m.n_elem / sec, "graph_elements_per_s": m.n_elem / gsec,
+            "options": b.options.as_dict()}
+
+
 def run_batched(steps, warmup, torch, nb, per_mesh_steps=2):
-    """512 mixed meshes: one batched launch sequence per relation vs 512
-    plain single-mesh calls per relation, on one stream."""
+    """512 mixed meshes: one batched call (both relations) vs 512 plain
+    single-mesh calls vs 512 graph replays, on one stream."""
     from paper_1604_04689_amd import meshgen as mg
     t = time.time()
     meshes = [s.build() for s in mg.batch_specs()]
@@ -279,76 +324,70 @@ def run_batched(steps, warmup, torch, nb, per_mesh_steps=2):
     stream = torch.cuda.current_stream(dev)
     desc = [(m.n_elem, m.etype, m.n_vert) for m in meshes]
     conn = torch.as_tensor(nb.concat_conn([m.conn for m in meshes])).to(dev)
-    node = nb.BatchBuild("node", desc, dev)
-    elem = nb.BatchBuild("elem", desc, dev)
+    build = nb.BatchBuild("both", desc, dev, options="tuned")
     total_f = sum(m.n_elem for m in meshes)
 
-    def step():
-        node.launch(conn, stream, tuned=True)
-        elem.launch(conn, stream, tuned=True)
-
     for _ in range(max(warmup, 1)):
-        step()
-    node.check(stream)
-    elem.check(stream)
+        build.launch(conn, stream)
+    build.check(stream)
     nb.timing_read()
     nb.timing_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    batched = _sync_time(torch, lambda: build.launch(conn, stream), steps)
     nb.timing_enable(False)
     kt = nb.timing_read()
-    node.check(stream)
-    elem.check(stream)
-    batched = (t1 - t0) / steps
-    batched_graph = time_graph_replays(torch, [node.capture(conn, tuned=True), elem.capture(conn, tuned=True)],
-                                       [node, elem], stream, steps)
-    del node, elem
+    build.check(stream)
+    batched_graph = time_graph(torch, build, conn, stream, steps)
+    opts = build.options.as_dict()
+    del build
+    torch.cuda.empty_cache()
 
-    # the same meshes, one plain call per mesh and relation
+    # the same meshes, one plain call per mesh building both relations
     conns = [torch.as_tensor(m.conn).to(dev) for m in meshes]
-    builds = [(nb.NeighborBuild("node", m.n_elem, m.etype, m.n_vert, dev),
-               nb.NeighborBuild("elem", m.n_elem, m.etype, m.n_vert, dev)) for m in meshes]
+    builds = [nb.NeighborBuild("both", m.n_elem, m.etype, m.n_vert, dev, options="tuned") for m in meshes]
 
     def step_each():
-        for c, (bn, be) in zip(conns, builds):
-            bn.launch(c, stream, tuned=True)
-            be.launch(c, stream, tuned=True)
+        for c, b in zip(conns, builds):
+            b.launch(c, stream)
 
     step_each()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(per_mesh_steps):
-        step_each()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for bn, be in builds[:8]:
-        bn.check(stream)
-        be.check(stream)
-    per_mesh = (t1 - t0) / per_mesh_steps
-    del builds, conns
+    per_mesh = _sync_time(torch, step_each, per_mesh_steps)
+    for b in builds[:8]:
+        b.check(stream)
+    graphs = [b.capture(c) for b, c in zip(builds, conns)]
+
+    def replay_each():
+        for g in graphs:
+            g.launch(stream)
+
+    replay_each()
+    per_mesh_graph = _sync_time(torch, replay_each, per_mesh_steps)
+    for b in builds[:8]:
+        b.check(stream)
+    for g in graphs:
+        g.destroy()
+    del builds, conns, graphs
     torch.cuda.empty_cache()
-    res = {"meshes": len(meshes), "n_elem": total_f,
+    res = {"meshes": len(meshes), "n_elem": total_f, "options": opts,
            "batched_ms_per_step": batched * 1e3, "batched_elements_per_s": total_f / batched,
            "batched_graph_ms_per_step": batched_graph * 1e3,
            "per_mesh_ms_per_step": per_mesh * 1e3, "per_mesh_elements_per_s": total_f / per_mesh,
+           "per_mesh_graph_ms_per_step": per_mesh_graph * 1e3,
            "batched_over_per_mesh": per_mesh / batched,
+           "batched_over_per_mesh_graph": per_mesh_graph / batched,
            "kernel_ms_per_step": {k: v[1] / steps for k, v in sorted(kt.items())}}
     log(f"[bench] batch512: batched {batched * 1e3:.2f} ms/step ({total_f / batched / 1e9:.2f} G elem/s), "
-        f"per-mesh calls {per_mesh * 1e3:.2f} ms/step ({total_f / per_mesh / 1e9:.2f} G elem/s)")
+        f"per-mesh calls {per_mesh * 1e3:.2f} ms/step, per-mesh graph replays {per_mesh_graph * 1e3:.2f} ms/step")
     return meshes, res
 
 
-def run_serving(meshes, torch, nb, rate_elems=None, n_req=600, warm=60, slots=4, max_batch=32,
+def run_serving(meshes, torch, nb, rate_elems=None, n_req=5000, warm=500, slots=4, max_batch=64,
                 budget=64 << 30):
     """Requests drawn from the batch's meshes, admitted by a device-memory
-    budget for their buffers, continuous batching over `slots` streams.
-    Inputs start in pageable host memory; staging and upload are part of
-    latency.  Arrivals are Poisson at `rate_elems` elements/s offered, or all
-    at t = 0 (saturation: sustained throughput) when rate_elems is None."""
+    budget, continuous batching over `slots` streams.  Inputs start in
+    pageable host memory; staging and upload are part of latency.  Arrivals
+    are Poisson at `rate_elems` elements/s offered, or all at t = 0
+    (saturation: sustained throughput) when rate_elems is None.  Every
+    retired batch's device error word is checked; any error fails the run."""
     import numpy as np
     from paper_1604_04689_amd import meshgen as mg
     from paper_1604_04689_amd import serve
@@ -356,25 +395,27 @@ def run_serving(meshes, torch, nb, rate_elems=None, n_req=600, warm=60, slots=4,
     pick = rng.integers(0, len(meshes), size=n_req + warm)
     mean_f = float(np.mean([meshes[i].n_elem for i in pick]))
     if rate_elems is None:
-        arr = np.zeros(n_req)
+        arr = np.zeros(n_req + warm)
     else:
-        arr = mg.poisson_arrivals(n_req, rate_elems / mean_f, seed=mg.BASE_SEED + 5)
+        arr = mg.poisson_arrivals(n_req + warm, rate_elems / mean_f, seed=mg.BASE_SEED + 5)
     ex = serve.GpuExecutor(slots)
-    # warm-up stream on the same executor (pinned staging blocks, device buffers), not measured
-    warm_reqs = [serve.Request(i, 0.0, meshes[j].conn, meshes[j].etype, meshes[j].n_vert)
-                 for i, j in enumerate(pick[n_req:])]
-    serve.Server(ex, serve.RealClock(), n_slots=slots, budget_bytes=budget, max_batch=max_batch).run(warm_reqs)
+
+    def on_complete(batch, executor):
+        executor.check(batch)  # raises MeshError on any device error
+
     reqs = [serve.Request(i, float(t), meshes[j].conn, meshes[j].etype, meshes[j].n_vert)
-            for i, (j, t) in enumerate(zip(pick[:n_req], arr))]
-    srv = serve.Server(ex, serve.RealClock(), n_slots=slots, budget_bytes=budget, max_batch=max_batch)
+            for i, (j, t) in enumerate(zip(pick, arr))]
+    srv = serve.Server(ex, serve.RealClock(), n_slots=slots, budget_bytes=budget, max_batch=max_batch,
+                       on_complete=on_complete)
     t0 = time.perf_counter()
     done = srv.run(reqs)
     wall = time.perf_counter() - t0
-    summ = serve.latency_summary(done)
+    measured = sorted(done, key=lambda r: r.rid)[warm:]  # the first `warm` arrivals are warm-up
+    summ = serve.latency_summary(measured)
     summ.update({"offered_elements_per_s": rate_elems, "arrivals": "poisson" if rate_elems else "all at t=0",
                  "slots": slots, "max_batch": max_batch, "budget_bytes": budget, "batches": srv.batches,
                  "mean_batch": float(np.mean(srv.batch_sizes)), "peak_reserved_bytes": srv.peak_in_use,
-                 "wall_s": wall, "warmup_requests": warm})
+                 "wall_s": wall, "warmup_requests": warm, "errors_checked": True})
     what = f"offered {rate_elems / 1e9:.2f} G elem/s" if rate_elems else "saturation"
     log(f"[bench] serve ({what}): {summ['requests']} requests: p50 {summ['p50_ms']:.2f} ms, "
         f"p99 {summ['p99_ms']:.2f} ms, {summ['elements_per_s'] / 1e9:.2f} G elem/s sustained, "
@@ -382,16 +423,40 @@ def run_serving(meshes, torch, nb, rate_elems=None, n_req=600, warm=60, slots=4,
     return summ
 
 
+def _host_cpu():
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return os.cpu_count(), model
+
+
 def cpu_baseline(m):
+    """The oracle on the headline mesh: single thread (the oracle as it
+    stands), and the all-cores variant (threads own vertex ranges)."""
     import oracle
     t0 = time.perf_counter()
     oracle.node_neighbors(m.conn, m.etype, m.n_vert)
     t1 = time.perf_counter()
     oracle.elem_neighbors(m.conn, m.etype, m.n_vert)
     t2 = time.perf_counter()
-    return {"value": m.n_elem / (t2 - t0), "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"the full {m.n_elem}-element mesh, node then element relation, one pass, single thread "
-                      f"(node {t1 - t0:.2f} s + elem {t2 - t1:.2f} s)"}
+    nproc, model = _host_cpu()
+    out = {"value": m.n_elem / (t2 - t0), "unit": "elements/s", "cores": 1, "kind": "oracle",
+           "sample": f"the full {m.n_elem}-element mesh, node then element relation, one pass, single thread "
+                     f"(node {t1 - t0:.2f} s + elem {t2 - t1:.2f} s)",
+           "host": {"nproc": nproc, "cpu_model": model}}
+    threads = max(1, min(nproc or 1, 64))
+    t0 = time.perf_counter()
+    oracle.node_neighbors_mt(m.conn, m.etype, m.n_vert, threads)
+    oracle.elem_neighbors_mt(m.conn, m.etype, m.n_vert, threads)
+    t1 = time.perf_counter()
+    out["all_cores"] = {"value": m.n_elem / (t1 - t0), "unit": "elements/s", "cores": threads,
+                        "sample": "the same mesh, each thread owning a vertex range and scanning every element"}
+    return out
 
 
 def copy_calibration(torch, gib=2):
@@ -414,7 +479,9 @@ def main():
     ap.add_argument("--also", default="kuhn96", help="comma list of extra workloads reported beside ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-mesh batch and the serving stream")
-    ap.add_argument("--serve-requests", type=int, default=600)
+    ap.add_argument("--no-compare", action="store_true", help="skip the node-algorithm comparison")
+    ap.add_argument("--serve-requests", type=int, default=5000)
+    ap.add_argument("--serve-warmup", type=int, default=500)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (for counter scaling under rocprofv3)")
     args = ap.parse_args()
@@ -435,28 +502,38 @@ def main():
     if args.copy_calibration:
         copy_calibration(torch)
 
-    m, main_res = run_workload(args.workload, args.steps, args.warmup, torch, nb)
+    m, main_res = run_workload(args.workload, args.steps, args.warmup, torch, nb, compare_sorts=not args.no_compare)
     others = {}
     for w in [x for x in args.also.split(",") if x and x != args.workload]:
-        _, others[w] = run_workload(w, args.steps, args.warmup, torch, nb)
+        _, others[w] = run_workload(w, args.steps, args.warmup, torch, nb, compare_sorts=not args.no_compare)
+    others["tri64"] = run_tiny(torch, nb)
 
     if not args.no_batch:
         meshes, others["batch512"] = run_batched(max(3, args.steps // 4), 1, torch, nb)
-        others["serve"] = run_serving(meshes, torch, nb, rate_elems=SERVE_OFFERED, n_req=args.serve_requests)
-        others["serve_saturation"] = run_serving(meshes, torch, nb, rate_elems=None, n_req=args.serve_requests)
+        sat = run_serving(meshes, torch, nb, rate_elems=None, n_req=args.serve_requests, warm=args.serve_warmup)
+        others["serve_saturation"] = sat
+        capacity = sat["elements_per_s"]
+        others["serve"] = {f"rho_{rho}": run_serving(meshes, torch, nb, rate_elems=rho * capacity,
+                                                     n_req=args.serve_requests, warm=args.serve_warmup)
+                           for rho in SERVE_RHO}
+        others["serve"]["capacity_elements_per_s"] = capacity
+        others["serve"]["capacity_note"] = ("capacity = the sustained rate of the served path at saturation "
+                                            "(uploads from host memory included); offered load = rho x capacity")
         del meshes
 
-    traffic = load_traffic(args.workload, (main_res["tuned"]["node"] or {}).get("node_sort", 0))
-    rp = main_res["radix_pass"]
-    roofline = {"bound": "hbm", "achieved": rp["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": rp["GBs"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": rp["kernel"],
-                "algorithmic_bytes_per_launch": rp["bytes_per_launch"], "avg_launch_ms": rp["avg_ms"]}
+    dom = main_res["dominant_kernel"]
+    traffic = load_traffic(dom["kernel"], args.workload, main_res["options"]["node_sort"])
+    roofline = {"bound": "hbm", "achieved": dom["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dom["GBs"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom["kernel"],
+                "algorithmic_bytes_per_launch": dom["bytes_per_launch"], "avg_launch_ms": dom["avg_ms"],
+                "pipeline_frac": main_res["pipeline_frac_of_hbm"]}
 
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle ...")
         cpu = cpu_baseline(m)
-        log(f"[bench] oracle: {cpu['value']:.3e} elements/s ({cpu['sample']})")
+        log(f"[bench] oracle: {cpu['value']:.3e} elements/s ({cpu['sample']}); all cores: "
+            f"{cpu['all_cores']['value']:.3e} elements/s on {cpu['all_cores']['cores']} threads")
 
     out = {
         "metric": METRIC,
@@ -469,7 +546,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64",
+        "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "n_elem": m.n_elem, "n_vert": m.n_vert,
                    "etype": TYPE_NAME[m.etype], "parallelism": "single GPU"},

@@ -14,29 +14,40 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  *  - Ids are 0-based.  Element e is row e of the connectivity array, which is
- *    int32, row-major [n_elem][nodes_per_element].
- *  - Element types and their edges (pairs of node positions):
- *      MESH_TRI3 (3 nodes): (0,1) (1,2) (2,0)
- *      MESH_TET4 (4 nodes): all 6 pairs
- *      MESH_HEX8 (8 nodes, VTK order: 0-1-2-3 bottom face, 4-7 the nodes
- *                 above them): (0,1)(1,2)(2,3)(3,0)(4,5)(5,6)(6,7)(7,4)
- *                 (0,4)(1,5)(2,6)(3,7); face and body diagonals are not edges.
+ *    int32, row-major [n_elem][nodes_per_element] (for a mesh of one element
+ *    type), or, for a mixed mesh, element e's ids are
+ *    conn[elem_off[e] .. elem_off[e+1]).
+ *  - Element types and their edges (pairs of node positions).  Node orders
+ *    are those of VTK; the paper shows triangles and states that the method
+ *    applies to meshes of any element type (Sec. 2.2, Sec. 4):
+ *      MESH_TRI3     (3 nodes): (0,1) (1,2) (2,0)
+ *      MESH_TET4     (4 nodes): all 6 pairs
+ *      MESH_HEX8     (8 nodes, 0-1-2-3 bottom face, 4-7 the nodes above them):
+ *                    (0,1)(1,2)(2,3)(3,0)(4,5)(5,6)(6,7)(7,4)(0,4)(1,5)(2,6)(3,7)
+ *      MESH_QUAD4    (4 nodes around the face): (0,1)(1,2)(2,3)(3,0)
+ *      MESH_WEDGE6   (6 nodes, triangle 0-1-2 and triangle 3-4-5 above it):
+ *                    (0,1)(1,2)(2,0)(3,4)(4,5)(5,3)(0,3)(1,4)(2,5)
+ *      MESH_PYRAMID5 (5 nodes, base 0-1-2-3 and apex 4):
+ *                    (0,1)(1,2)(2,3)(3,0)(0,4)(1,4)(2,4)(3,4)
+ *    Face and body diagonals are not edges.
  *  - Output CSR: row_ptr is int32 [n_vert + 1], row_ptr[0] = 0, and the
  *    neighbors of v are cols[row_ptr[v] .. row_ptr[v+1]) in ascending order.
  *    A vertex is never its own neighbor; a repeated id inside one element
  *    (a degenerate element) yields no self pair and lists that element once.
  *    Vertices used by no element get empty rows.  nnz = row_ptr[n_vert].
- *  - Every data pointer (conn, row_ptr, cols, workspace and the batched
- *    descriptor arrays) is a DEVICE pointer owned by the caller; the library
- *    allocates nothing and keeps no per-call state between calls (the tile
- *    shape and the timing switch below are process-wide settings).  `stream` is a
- *    hipStream_t (NULL = the null stream).  Calls are asynchronous and
- *    stream-ordered; none synchronises the host except mesh_check.
+ *  - Every data pointer (conn, row_ptr, cols, workspace, the batched and
+ *    mixed descriptor arrays) is a DEVICE pointer owned by the caller; the
+ *    library allocates nothing and keeps no state between calls.  `opts`
+ *    (host pointer, may be NULL) selects speed-only choices for that call
+ *    alone.  `stream` is a hipStream_t (NULL = the null stream).  Calls are
+ *    asynchronous and stream-ordered; none synchronises the host except
+ *    mesh_check.
  *  - Argument errors are returned synchronously before anything is launched.
  *    Data errors found on the device (a vertex id outside [0, n_vert), more
  *    nnz than cols_capacity) are recorded in the workspace: the output is then
  *    unspecified but every access stays in bounds, and mesh_check reports it.
- *  - Two calls may run concurrently only with distinct workspaces.
+ *  - Calls are thread-safe; two calls may run concurrently only with
+ *    distinct workspaces and outputs.
  */
 #ifndef MESH_NEIGHBORS_H
 #define MESH_NEIGHBORS_H
@@ -48,19 +59,69 @@
 extern "C" {
 #endif
 
-typedef enum { MESH_TRI3 = 0, MESH_TET4 = 1, MESH_HEX8 = 2 } mesh_elem_type;
+typedef enum {
+    MESH_TRI3 = 0,
+    MESH_TET4 = 1,
+    MESH_HEX8 = 2,
+    MESH_QUAD4 = 3,
+    MESH_WEDGE6 = 4,
+    MESH_PYRAMID5 = 5
+} mesh_elem_type;
 
 typedef enum {
     MESH_OK = 0,
-    MESH_ERR_INVALID_ARG = 1,      /* null pointer, negative size, ...          */
-    MESH_ERR_UNSUPPORTED_TYPE = 2, /* element type code not listed above        */
-    MESH_ERR_WORKSPACE = 3,        /* workspace smaller than the query says     */
-    MESH_ERR_CAPACITY = 4,         /* nnz exceeded cols_capacity (device check) */
-    MESH_ERR_OVERFLOW = 5,         /* sizes beyond the int32 / pair-count range */
-    MESH_ERR_INDEX_RANGE = 6,      /* a connectivity id outside [0, n_vert)     */
-    MESH_ERR_HIP = 7,              /* a HIP runtime call or launch failed        */
-    MESH_ERR_INTERNAL = 8          /* a device-side consistency guard tripped    */
+    MESH_ERR_INVALID_ARG = 1,      /* null pointer, negative size, bad option  */
+    MESH_ERR_UNSUPPORTED_TYPE = 2, /* element type code not listed above       */
+    MESH_ERR_WORKSPACE = 3,        /* workspace smaller than the query says    */
+    MESH_ERR_CAPACITY = 4,         /* nnz exceeded cols_capacity (device check)*/
+    MESH_ERR_OVERFLOW = 5,         /* sizes beyond the int32 / pair-count range*/
+    MESH_ERR_INDEX_RANGE = 6,      /* a connectivity id outside [0, n_vert)    */
+    MESH_ERR_HIP = 7,              /* a HIP runtime call or launch failed       */
+    MESH_ERR_INTERNAL = 8          /* a device-side consistency guard tripped   */
 } mesh_status;
+
+/* ------------------------------------------------------------------------ */
+/* Per-call options: speed only, never results.                             */
+/* ------------------------------------------------------------------------ */
+
+/* How the node relation orders its pairs.  All give the same bytes.
+ *  FULL_KEY:     directed pairs packed as (u << b) | w, b = bits of n_vert - 1,
+ *                LSD radix passes over all 2b bits, then one pass drops
+ *                repeats and writes the CSR.
+ *  VERTEX_ROWS:  the same pairs sorted by the bits of u only (the paper's sort
+ *                by the first array, Sec. 2.2.1), then each row's neighbor ids
+ *                deduplicated and ordered in LDS (rows over 256 pairs by a
+ *                block each), counts scanned into row_ptr, rows gathered.
+ *  EDGE_ROWS:    every element edge once, (min << b) | max, sorted by min and
+ *                deduplicated per row as in VERTEX_ROWS (each vertex's higher
+ *                neighbors and the unique edges); those edges transposed and
+ *                sorted by max give each vertex's lower neighbors; a row is its
+ *                lower neighbors followed by its higher ones.
+ *  ELEM_ROWS:    the element relation first (the counting sort of (v, e) pairs
+ *                by v, Sec. 2.2.2); row v of the node relation is then the
+ *                set of edge-neighbors of v over the elements of its element
+ *                row, gathered into LDS, deduplicated and ordered there (rows
+ *                over the LDS limit by a block each from global memory).  Only
+ *                the element pairs are sorted. */
+typedef enum {
+    MESH_NODE_SORT_FULL_KEY = 0,
+    MESH_NODE_SORT_VERTEX_ROWS = 1,
+    MESH_NODE_SORT_EDGE_ROWS = 2,
+    MESH_NODE_SORT_ELEM_ROWS = 3
+} mesh_node_sort;
+
+/* Fields set to -1 take the library default (a rule built into the library,
+ * the same for every call of the same sizes).  The workspace size depends on
+ * the options: query and call with the same options. */
+typedef struct {
+    int32_t node_sort;    /* mesh_node_sort, or -1                               */
+    int32_t radix_shape;  /* radix tile shape 0 .. mesh_radix_shape_count()-1, or -1 */
+    int32_t digit_bits;   /* radix digit width: 8 or 11 bits per pass, or -1      */
+    int32_t reserved[5];  /* 0                                                    */
+} mesh_options;
+
+/* Options with every field set to -1 (the library defaults). */
+mesh_options mesh_default_options(void);
 
 /* ------------------------------------------------------------------------ */
 /* Neighboring nodes (Sec. 2.1.1, 2.2.1).                                   */
@@ -68,25 +129,23 @@ typedef enum {
 
 /* Workspace size and a cols capacity that always suffices for
  * mesh_node_neighbors on a mesh of n_elem elements of type etype over n_vert
- * vertices.  The capacity is the number of directed edge pairs,
+ * vertices, under `opts`.  The capacity is the number of directed edge pairs,
  * 2 * edges_per_element * n_elem (every pair distinct in the worst case).
  * Limits: n_vert <= 2^31 - 1; pairs <= 2^31 - 1 (else MESH_ERR_OVERFLOW). */
-mesh_status mesh_node_neighbors_query(int64_t n_elem, int32_t etype, int32_t n_vert,
+mesh_status mesh_node_neighbors_query(int64_t n_elem, int32_t etype, int32_t n_vert, const mesh_options* opts,
                                       size_t* workspace_bytes, int64_t* cols_capacity);
 
 /* One-ring neighboring nodes of every vertex.
  *   conn           device int32 [n_elem * npe], read only
  *   row_ptr        device int32 [n_vert + 1], written
  *   cols           device int32 [cols_capacity], first nnz entries written
+ *   opts           host, may be NULL (defaults)
  *   workspace      device scratch of >= the queried size (256-byte aligned);
  *                  its first bytes carry the device error word that
  *                  mesh_check reads, so keep it until checked.
- * Pipeline (all on `stream`): per-element pair emission from the type's
- * edge table as packed 64-bit keys (u << b) | w, b = bits of n_vert - 1,
- * with per-digit histograms fused in; LSD radix sort of the keys; one pass
- * that drops repeated keys, writes cols and scatters row starts. */
+ * The pipeline is the one opts->node_sort names (see mesh_node_sort). */
 mesh_status mesh_node_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
-                                int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
+                                int32_t* row_ptr, int32_t* cols, int64_t cols_capacity, const mesh_options* opts,
                                 void* workspace, size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
@@ -95,16 +154,62 @@ mesh_status mesh_node_neighbors(const int32_t* conn, int64_t n_elem, int32_t ety
 
 /* Workspace size and sufficient cols capacity (npe * n_elem) for
  * mesh_elem_neighbors.  Limits: n_elem * npe <= 2^31 - 1. */
-mesh_status mesh_elem_neighbors_query(int64_t n_elem, int32_t etype, int32_t n_vert,
+mesh_status mesh_elem_neighbors_query(int64_t n_elem, int32_t etype, int32_t n_vert, const mesh_options* opts,
                                       size_t* workspace_bytes, int64_t* cols_capacity);
 
 /* One-ring neighboring elements of every vertex.  Same arguments as
- * mesh_node_neighbors.  Pipeline: per-vertex counts of (vertex, element)
- * pairs, exclusive scan to row_ptr, scatter of element ids into their rows,
- * and an ascending sort of each row (a counting sort by vertex). */
+ * mesh_node_neighbors.  Pipeline: one (v, e) pair per node slot of every
+ * element (the first occurrence of an id inside its element), sorted by v
+ * with stable LSD counting-sort passes over the digits of v, the first pass
+ * reading the connectivity itself; pairs enter in element order, so each row
+ * comes out ascending.  The last pass writes cols and offers every row start
+ * to row_ptr with an atomic minimum; empty rows take the next row's start. */
 mesh_status mesh_elem_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
-                                int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
+                                int32_t* row_ptr, int32_t* cols, int64_t cols_capacity, const mesh_options* opts,
                                 void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Both relations in one call.                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Workspace size and both cols capacities for mesh_neighbors. */
+mesh_status mesh_neighbors_query(int64_t n_elem, int32_t etype, int32_t n_vert, const mesh_options* opts,
+                                 size_t* workspace_bytes, int64_t* node_cols_capacity,
+                                 int64_t* elem_cols_capacity);
+
+/* The node and element relations of one mesh.  Output arguments as for the
+ * two single-relation calls.  Under MESH_NODE_SORT_ELEM_ROWS the node
+ * relation is derived from the element relation just written (so the element
+ * pairs are sorted once for both); otherwise the two pipelines run one after
+ * the other in the one workspace. */
+mesh_status mesh_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
+                           int32_t* node_row_ptr, int32_t* node_cols, int64_t node_cols_capacity,
+                           int32_t* elem_row_ptr, int32_t* elem_cols, int64_t elem_cols_capacity,
+                           const mesh_options* opts, void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Meshes with several element types.                                       */
+/* ------------------------------------------------------------------------ */
+
+/* A mesh whose elements have their own types: element e has type etypes[e]
+ * (uint8, a mesh_elem_type) and ids conn[elem_off[e] .. elem_off[e+1]),
+ * elem_off int32 [n_elem + 1] with elem_off[0] = 0 and
+ * elem_off[e+1] - elem_off[e] = nodes of etypes[e].  n_ids = elem_off[n_elem]
+ * (the slot count) and n_pairs = sum of 2 * edges of each element's type are
+ * given by the caller for sizing.  Both relations are built; the node
+ * relation always takes the ELEM_ROWS algorithm (opts->node_sort must be -1
+ * or MESH_NODE_SORT_ELEM_ROWS).  An element whose type code is unknown or
+ * whose offsets disagree with its type raises MESH_ERR_INDEX_RANGE on the
+ * device and contributes nothing.  Limits: n_ids, n_pairs <= 2^31 - 1. */
+mesh_status mesh_mixed_neighbors_query(int64_t n_elem, int64_t n_ids, int64_t n_pairs, int32_t n_vert,
+                                       const mesh_options* opts, size_t* workspace_bytes,
+                                       int64_t* node_cols_capacity, int64_t* elem_cols_capacity);
+mesh_status mesh_mixed_neighbors(const int32_t* conn, const int32_t* elem_off, const uint8_t* etypes,
+                                 int64_t n_elem, int64_t n_ids, int64_t n_pairs, int32_t n_vert,
+                                 int32_t* node_row_ptr, int32_t* node_cols, int64_t node_cols_capacity,
+                                 int32_t* elem_row_ptr, int32_t* elem_cols, int64_t elem_cols_capacity,
+                                 const mesh_options* opts, void* workspace, size_t workspace_bytes,
+                                 void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Batches of independent meshes in one launch sequence.                    */
@@ -114,7 +219,8 @@ mesh_status mesh_elem_neighbors(const int32_t* conn, int64_t n_elem, int32_t ety
  * meshes share one int32 connectivity array; the ids inside a mesh are local
  * to it, in [0, n_vert).  Offsets are prefix sums over the meshes before it,
  * in order: pair_off of 2 * edges_per_element * n_elem, slot_off of
- * nodes_per_element * n_elem, vert_off of n_vert.  Meshes may mix types. */
+ * nodes_per_element * n_elem, vert_off of n_vert (so the meshes' vertex
+ * ranges tile [0, total_vert) in order).  Meshes may mix types. */
 typedef struct {
     int64_t conn_off;  /* index of the mesh's first id in the shared conn */
     int64_t n_elem;
@@ -129,32 +235,49 @@ typedef struct {
 /* Neighboring nodes of every vertex of every mesh of a batch.
  *   segs         device mesh_segment [n_mesh]
  *   total_pairs  sum of 2 * edges_per_element * n_elem (the pair_off end)
+ *   total_slots  sum of nodes_per_element * n_elem (the slot_off end)
  *   total_vert   sum of n_vert;  max_vert = largest n_vert of one mesh
  *   row_ptr      device int32 [total_vert + 1]: one CSR over all vertices,
  *                mesh m owning rows vert_off[m] .. vert_off[m] + n_vert[m]
  *   cols         device int32 [cols_capacity]; entries are LOCAL vertex ids
  * The slice row_ptr[vert_off .. vert_off + n_vert] - row_ptr[vert_off] with its
- * cols equals mesh_node_neighbors on that mesh alone.  Keys are
- * (vert_off + u) << bits(max_vert) | w, sorted by LSD radix passes over
- * bits(total_vert) + bits(max_vert) bits.  Records inconsistent with
- * total_pairs or with a mesh's own size raise MESH_ERR_INDEX_RANGE on the
- * device; conn itself must cover every record (not checkable here). */
-mesh_status mesh_batch_node_neighbors_query(int32_t n_mesh, int64_t total_pairs, int32_t total_vert,
-                                            int32_t max_vert, size_t* workspace_bytes, int64_t* cols_capacity);
+ * cols equals mesh_node_neighbors on that mesh alone.  Keys carry the global
+ * vertex vert_off + u.  A record inconsistent with total_pairs, total_vert
+ * or its own size (a key or vertex range outside the batch, an unknown type)
+ * raises MESH_ERR_INDEX_RANGE on the device, and its pairs are dropped;
+ * conn itself must cover every record (not checkable here). */
+mesh_status mesh_batch_node_neighbors_query(int32_t n_mesh, int64_t total_pairs, int64_t total_slots,
+                                            int32_t total_vert, int32_t max_vert, const mesh_options* opts,
+                                            size_t* workspace_bytes, int64_t* cols_capacity);
 mesh_status mesh_batch_node_neighbors(const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
-                                      int64_t total_pairs, int32_t total_vert, int32_t max_vert, int32_t* row_ptr,
-                                      int32_t* cols, int64_t cols_capacity, void* workspace, size_t workspace_bytes,
+                                      int64_t total_pairs, int64_t total_slots, int32_t total_vert, int32_t max_vert,
+                                      int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
+                                      const mesh_options* opts, void* workspace, size_t workspace_bytes,
                                       void* stream);
 
 /* Neighboring elements of every vertex of every mesh of a batch: as above,
  * with total_slots = sum of nodes_per_element * n_elem; cols hold element
- * ids LOCAL to the mesh.  Keys (vert_off + v) << 32 | e, sorted over
- * bits(total_vert) bits. */
+ * ids LOCAL to the mesh.  Keys (vert_off + v) << 32 | e, sorted over the bits
+ * of total_vert - 1. */
 mesh_status mesh_batch_elem_neighbors_query(int32_t n_mesh, int64_t total_slots, int32_t total_vert,
-                                            size_t* workspace_bytes, int64_t* cols_capacity);
+                                            const mesh_options* opts, size_t* workspace_bytes,
+                                            int64_t* cols_capacity);
 mesh_status mesh_batch_elem_neighbors(const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
                                       int64_t total_slots, int32_t total_vert, int32_t* row_ptr, int32_t* cols,
-                                      int64_t cols_capacity, void* workspace, size_t workspace_bytes, void* stream);
+                                      int64_t cols_capacity, const mesh_options* opts, void* workspace,
+                                      size_t workspace_bytes, void* stream);
+
+/* Both relations of a batch in one call (as mesh_neighbors for one mesh). */
+mesh_status mesh_batch_neighbors_query(int32_t n_mesh, int64_t total_pairs, int64_t total_slots,
+                                       int32_t total_vert, int32_t max_vert, const mesh_options* opts,
+                                       size_t* workspace_bytes, int64_t* node_cols_capacity,
+                                       int64_t* elem_cols_capacity);
+mesh_status mesh_batch_neighbors(const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
+                                 int64_t total_pairs, int64_t total_slots, int32_t total_vert, int32_t max_vert,
+                                 int32_t* node_row_ptr, int32_t* node_cols, int64_t node_cols_capacity,
+                                 int32_t* elem_row_ptr, int32_t* elem_cols, int64_t elem_cols_capacity,
+                                 const mesh_options* opts, void* workspace, size_t workspace_bytes,
+                                 void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* HIP graphs: one call's launch sequence, captured once, replayed cheaply. */
@@ -167,28 +290,41 @@ typedef struct mesh_graph_s* mesh_graph;
  * same name (without the stream), validates them exactly as that entry point
  * does (returning the same status), and records its whole launch sequence on
  * a private stream into *graph.  Nothing runs at capture time.  The graph
- * keeps the pointers and sizes it was captured with: every replay reads the
- * buffers' contents at that time (conn, and segs for batches, may change
- * between replays; their sizes may not) and rewrites the outputs and the
- * workspace, so a replay returns what an eager call on the same contents
- * returns, bit for bit.  The process-wide radix shape and node algorithm
- * are fixed at capture.  The buffers must stay allocated while the graph
+ * keeps the pointers, sizes and options it was captured with: every replay
+ * reads the buffers' contents at that time (conn, and segs for batches, may
+ * change between replays; their sizes may not) and rewrites the outputs and
+ * the workspace, so a replay returns what an eager call on the same contents
+ * returns, bit for bit.  The buffers must stay allocated while the graph
  * lives.  Launches being captured are not timed.  Returns MESH_ERR_HIP if
  * capture or instantiation fails; *graph is then NULL. */
 mesh_status mesh_graph_node_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
-                                      int32_t* row_ptr, int32_t* cols, int64_t cols_capacity, void* workspace,
-                                      size_t workspace_bytes, mesh_graph* graph);
+                                      int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
+                                      const mesh_options* opts, void* workspace, size_t workspace_bytes,
+                                      mesh_graph* graph);
 mesh_status mesh_graph_elem_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
-                                      int32_t* row_ptr, int32_t* cols, int64_t cols_capacity, void* workspace,
-                                      size_t workspace_bytes, mesh_graph* graph);
+                                      int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
+                                      const mesh_options* opts, void* workspace, size_t workspace_bytes,
+                                      mesh_graph* graph);
+mesh_status mesh_graph_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
+                                 int32_t* node_row_ptr, int32_t* node_cols, int64_t node_cols_capacity,
+                                 int32_t* elem_row_ptr, int32_t* elem_cols, int64_t elem_cols_capacity,
+                                 const mesh_options* opts, void* workspace, size_t workspace_bytes,
+                                 mesh_graph* graph);
 mesh_status mesh_graph_batch_node_neighbors(const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
-                                            int64_t total_pairs, int32_t total_vert, int32_t max_vert,
-                                            int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
-                                            void* workspace, size_t workspace_bytes, mesh_graph* graph);
+                                            int64_t total_pairs, int64_t total_slots, int32_t total_vert,
+                                            int32_t max_vert, int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
+                                            const mesh_options* opts, void* workspace, size_t workspace_bytes,
+                                            mesh_graph* graph);
+mesh_status mesh_graph_batch_neighbors(const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
+                                       int64_t total_pairs, int64_t total_slots, int32_t total_vert, int32_t max_vert,
+                                       int32_t* node_row_ptr, int32_t* node_cols, int64_t node_cols_capacity,
+                                       int32_t* elem_row_ptr, int32_t* elem_cols, int64_t elem_cols_capacity,
+                                       const mesh_options* opts, void* workspace, size_t workspace_bytes,
+                                       mesh_graph* graph);
 mesh_status mesh_graph_batch_elem_neighbors(const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
                                             int64_t total_slots, int32_t total_vert, int32_t* row_ptr,
-                                            int32_t* cols, int64_t cols_capacity, void* workspace,
-                                            size_t workspace_bytes, mesh_graph* graph);
+                                            int32_t* cols, int64_t cols_capacity, const mesh_options* opts,
+                                            void* workspace, size_t workspace_bytes, mesh_graph* graph);
 
 /* Enqueues one replay of `graph` on `stream` (asynchronous, like the eager
  * calls; read errors with mesh_check on the captured workspace).  Replays of
@@ -214,43 +350,23 @@ const char* mesh_status_string(mesh_status status);
 int32_t mesh_abi_version(void);
 
 /* ------------------------------------------------------------------------ */
-/* Tuning.                                                                  */
+/* Tuning information.                                                      */
 /* ------------------------------------------------------------------------ */
 
-/* Every radix pass of both pipelines uses one tile shape (threads per block x
- * keys per thread) out of a fixed set built into the library.  The choice is
- * process-wide and changes only speed, never results (passes over 2^30 keys
- * or more always take the default shape).  Shapes are numbered
- * 0 .. mesh_radix_shape_count() - 1; mesh_set_radix_shape(-1) restores the
- * default.  Returns MESH_ERR_INVALID_ARG for an unknown shape. */
+/* The radix tile shapes built into the library (threads per block x keys per
+ * thread), numbered 0 .. mesh_radix_shape_count() - 1, for
+ * mesh_options.radix_shape.  Returns MESH_ERR_INVALID_ARG for an unknown
+ * shape. */
 int32_t mesh_radix_shape_count(void);
 mesh_status mesh_radix_shape_info(int32_t shape, int32_t* block, int32_t* items);
-mesh_status mesh_set_radix_shape(int32_t shape);
-int32_t mesh_get_radix_shape(void);
 
-/* How the node relation (single meshes and batches) orders its keys; results
- * are the same either way.  Process-wide, default MESH_NODE_SORT_FULL_KEY.
- *  FULL_KEY:     LSD radix passes over all 2b bits of (u << b) | w, then one
- *                pass drops repeats and writes the CSR.
- *  VERTEX_ROWS:  LSD radix passes over the bits of u only (the paper's sort by
- *                the first array), then each row's neighbor ids are sorted and
- *                deduplicated in LDS (rows over 256 pairs by a block each),
- *                the distinct counts are scanned into row_ptr and the rows
- *                gathered into cols.  Fewer full passes over the keys.
- *  EDGE_ROWS:    every element edge once, as (min << b) | max, sorted by min
- *                and deduplicated per row as in VERTEX_ROWS: each vertex's
- *                higher neighbours and the unique edges; those edges
- *                transposed to (max << b) | min and sorted by max give each
- *                vertex's lower neighbours; a row is its lower neighbours
- *                followed by its higher ones.  Half the keys of VERTEX_ROWS in
- *                the first sort. */
-typedef enum {
-    MESH_NODE_SORT_FULL_KEY = 0,
-    MESH_NODE_SORT_VERTEX_ROWS = 1,
-    MESH_NODE_SORT_EDGE_ROWS = 2
-} mesh_node_sort;
-mesh_status mesh_set_node_sort(int32_t mode);
-int32_t mesh_get_node_sort(void);
+/* The tile shape (block x items) and digit width that a radix pass over
+ * n_keys keys actually launches with when the options ask for `shape` and
+ * `digit_bits` (-1 for defaults): passes over 2^30 keys or more, and digit
+ * widths that have no such shape, take the default shape of that width.
+ * Every table sized by tiles of a pass uses this same shape. */
+mesh_status mesh_radix_launch_shape(int32_t shape, int32_t digit_bits, int64_t n_keys, int32_t* block,
+                                    int32_t* items, int32_t* bits);
 
 /* ------------------------------------------------------------------------ */
 /* Kernel timing (diagnostics, not part of the method).                     */
@@ -264,11 +380,11 @@ typedef struct {
     double max_ms;
 } mesh_kernel_time;
 
-/* While enabled (process-wide), every kernel the library launches is
- * bracketed by HIP events recorded by the launch itself on the launch's own
- * stream (hipExtLaunchKernel), on the device current when the events were
- * first created.  Up to 65536 launches are recorded between reads; later ones
- * run untimed.  Always returns MESH_OK. */
+/* While enabled (a process-wide diagnostics switch that changes no result),
+ * every kernel the library launches is bracketed by HIP events recorded by
+ * the launch itself on the launch's own stream (hipExtLaunchKernel), on the
+ * device current when the events were first created.  Up to 65536 launches
+ * are recorded between reads; later ones run untimed.  Always MESH_OK. */
 mesh_status mesh_timing_enable(int32_t enable);
 
 /* Waits for the recorded launches to finish, aggregates their durations per

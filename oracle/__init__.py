@@ -33,7 +33,7 @@ def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so next to it (plain gcc, -O2)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.run(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
+        subprocess.run(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC", "-pthread",
                         _SRC, "-o", tmp], check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -49,6 +49,11 @@ def _load():
             fn = getattr(lib, name)
             fn.restype = ctypes.c_int64
             fn.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+        for name in ("oracle_node_neighbors_mt", "oracle_elem_neighbors_mt"):
+            fn = getattr(lib, name)
+            fn.restype = ctypes.c_int64
+            fn.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int,
                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
         for name in ("oracle_mixed_node_neighbors", "oracle_mixed_elem_neighbors"):
             fn = getattr(lib, name)
@@ -121,3 +126,30 @@ def mixed_node_neighbors(conn, etypes, n_vert: int):
 def mixed_elem_neighbors(conn, etypes, n_vert: int):
     """Neighboring elements of a mesh with one type code per element."""
     return _run_mixed("oracle_mixed_elem_neighbors", conn, etypes, n_vert, lambda t: _NPE.get(t, 0))
+
+
+def _run_mt(fn_name, conn, etype, n_vert, threads, cap_per_elem):
+    conn = np.ascontiguousarray(np.asarray(conn, dtype=np.int32))
+    npe = _NPE.get(int(etype))
+    if npe is None:
+        raise OracleError("invalid argument")
+    conn = conn.reshape(-1, npe)
+    cap = max(1, cap_per_elem * conn.shape[0])
+    row_ptr = np.zeros(n_vert + 1, dtype=np.int32)
+    cols = np.empty(cap, dtype=np.int32)
+    r = getattr(_load(), fn_name)(conn.ctypes.data, conn.shape[0], int(etype), int(n_vert), int(threads),
+                                  row_ptr.ctypes.data, cols.ctypes.data, cap)
+    if r < 0:
+        raise OracleError(_ERRORS.get(int(r), str(r)))
+    return row_ptr, cols[:r].copy()
+
+
+def node_neighbors_mt(conn, etype: int, n_vert: int, threads: int):
+    """node_neighbors on `threads` threads, each owning a vertex range (the
+    all-cores CPU baseline); the same result."""
+    return _run_mt("oracle_node_neighbors_mt", conn, etype, n_vert, threads, 2 * _EDGES_PER_ELEM.get(int(etype), 0))
+
+
+def elem_neighbors_mt(conn, etype: int, n_vert: int, threads: int):
+    """elem_neighbors on `threads` threads, each owning a vertex range."""
+    return _run_mt("oracle_elem_neighbors_mt", conn, etype, n_vert, threads, _NPE.get(int(etype), 0))

@@ -27,6 +27,7 @@
  *   - ids are 0-based, element id = row of the connectivity array (for a
  *     mixed mesh, the element's index in its list of types).
  */
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -224,4 +225,100 @@ int64_t oracle_mixed_elem_neighbors(const int32_t* conn, const int64_t* elem_off
                                     int64_t n_elem, int32_t n_vert, int32_t* row_ptr, int32_t* cols,
                                     int64_t cols_cap) {
     return mixed_relation(1, conn, elem_off, etypes, n_elem, n_vert, row_ptr, cols, cols_cap);
+}
+
+/* ---- all-cores variant (for the CPU baseline) ------------------------------
+ * The same definition with T threads: thread t owns the vertices
+ * [t V / T, (t+1) V / T), scans every element and inserts only into the sets
+ * of the vertices it owns, so no set is shared.  Rows are then concatenated
+ * in vertex order. */
+typedef struct {
+    int relation; /* 0 nodes, 1 elements */
+    const int32_t* conn;
+    int64_t n_elem;
+    int npe, n_edges;
+    const int (*edges)[2];
+    int32_t v0, v1;
+    ordered_set* sets; /* sets[v] for v in [v0, v1) */
+    int status;
+} mt_job;
+
+static void* mt_worker(void* arg) {
+    mt_job* j = (mt_job*)arg;
+    for (int64_t e = 0; e < j->n_elem && !j->status; ++e) {
+        const int32_t* el = j->conn + e * j->npe;
+        if (j->relation == 0) {
+            for (int k = 0; k < j->n_edges; ++k) {
+                int32_t u = el[j->edges[k][0]], w = el[j->edges[k][1]];
+                if (u == w) continue;
+                if (u >= j->v0 && u < j->v1 && set_insert(&j->sets[u], w)) j->status = -4;
+                if (w >= j->v0 && w < j->v1 && set_insert(&j->sets[w], u)) j->status = -4;
+            }
+        } else {
+            for (int q = 0; q < j->npe; ++q) {
+                int32_t v = el[q];
+                if (v >= j->v0 && v < j->v1 && set_insert(&j->sets[v], (int32_t)e)) j->status = -4;
+            }
+        }
+    }
+    return NULL;
+}
+
+static int64_t relation_mt(int relation, const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
+                           int n_threads, int32_t* row_ptr, int32_t* cols, int64_t cols_cap) {
+    int npe, n_edges;
+    const int(*edges)[2];
+    if (type_info(etype, &npe, &n_edges, &edges) != 0) return -1;
+    if (n_elem < 0 || n_vert < 0 || n_elem > INT32_MAX || (n_elem > 0 && !conn) || !row_ptr || n_threads < 1)
+        return -1;
+    for (int64_t i = 0; i < n_elem * npe; ++i)
+        if (conn[i] < 0 || conn[i] >= n_vert) return -2;
+    ordered_set* sets = (ordered_set*)calloc((size_t)n_vert + 1, sizeof(ordered_set));
+    mt_job* jobs = (mt_job*)calloc((size_t)n_threads, sizeof(mt_job));
+    pthread_t* th = (pthread_t*)calloc((size_t)n_threads, sizeof(pthread_t));
+    if (!sets || !jobs || !th) {
+        free(sets);
+        free(jobs);
+        free(th);
+        return -4;
+    }
+    int started = 0;
+    for (int t = 0; t < n_threads; ++t) {
+        mt_job* j = &jobs[t];
+        j->relation = relation;
+        j->conn = conn;
+        j->n_elem = n_elem;
+        j->npe = npe;
+        j->n_edges = n_edges;
+        j->edges = edges;
+        j->v0 = (int32_t)((int64_t)n_vert * t / n_threads);
+        j->v1 = (int32_t)((int64_t)n_vert * (t + 1) / n_threads);
+        j->sets = sets;
+        if (pthread_create(&th[t], NULL, mt_worker, j) != 0) {
+            j->status = -4;
+            break;
+        }
+        ++started;
+    }
+    int64_t r = 0;
+    for (int t = 0; t < started; ++t) {
+        pthread_join(th[t], NULL);
+        if (jobs[t].status) r = jobs[t].status;
+    }
+    if (started < n_threads) r = -4;
+    if (r == 0) r = emit_csr(sets, n_vert, row_ptr, cols, cols_cap);
+    free_sets(sets, n_vert);
+    free(jobs);
+    free(th);
+    return r;
+}
+
+int64_t oracle_node_neighbors_mt(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert, int n_threads,
+                                 int32_t* row_ptr, int32_t* cols, int64_t cols_cap) {
+    return relation_mt(0, conn, n_elem, etype, n_vert, n_threads, row_ptr, cols, cols_cap);
+}
+
+int64_t oracle_elem_neighbors_mt(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert, int n_threads,
+                                 int32_t* row_ptr, int32_t* cols, int64_t cols_cap) {
+    return relation_mt(1, conn, n_elem, etype, n_vert, n_threads, row_ptr, cols, cols_cap);
 }

@@ -1,16 +1,21 @@
 """Autotuner for the library's speed-only choices.
 
-Every choice it makes changes speed only, never results: the radix tile
-shape (threads per block x keys per thread, which also sets the number of
-tiles in flight per CU) and, for the node relation, the algorithm (LSD sort
-of the full key; sort by the vertex bits plus per-row deduplication; or each
-edge once by its lower vertex, deduplicated per row, then transposed).
-For each workload it times every combination on the GPU, checks that all of
-them produce byte-identical CSR output, and records the fastest per
-(relation, element type, size bucket) in ``tuning.json`` next to this file.
-``NeighborBuild.launch(..., tuned=True)`` applies the table before the
-launch; without ``tuned`` the process-wide settings are left as they are
-(set ``MESHNBR_TUNING=off`` to ignore the table).
+Every choice it makes changes speed only, never results: the node algorithm
+(LSD sort of the full key; sort by the vertex bits plus per-row
+deduplication; each edge once by its lower vertex, deduplicated per row, then
+transposed; or rows gathered through the element relation), the radix tile
+shape (threads per block x keys per thread, which also sets the waves per
+block and, through the LDS a tile needs, the blocks and so waves per CU) and
+the radix digit width.  For each workload it times every combination on the
+GPU, checks that all of them produce byte-identical CSR output, and records
+the fastest per (relation, element type, size bucket) in ``tuning.json`` next
+to this file.
+
+The table is read once and never written by a running program; a build asks
+for its options with ``options_for`` / ``batch_options_for`` and passes them
+to each call (``mesh_options``), so nothing process-wide changes.  A size
+more than two buckets away from every entry of its relation and type gets the
+library defaults.  Set ``MESHNBR_TUNING=off`` to ignore the table.
 
     python -m paper_1604_04689_amd.autotune [--quick]
 """
@@ -27,6 +32,11 @@ from . import binding as _b
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tuning.json")
+MAX_BUCKET_GAP = 2
+# the tile shapes the tuner times (the others never won a sweep over all of
+# them on MI355X; they stay selectable through mesh_options)
+TUNED_SHAPES = (0, 2, 4, 5)
+DIGIT_WIDTHS = (8,)
 
 
 def size_bucket(n_keys: int) -> int:
@@ -35,8 +45,10 @@ def size_bucket(n_keys: int) -> int:
 
 
 def keys_of(kind, n_elem, etype):
-    npe = _b.NODES_PER_ELEM[etype]
-    return 2 * _b.EDGES_PER_ELEM[etype] * n_elem if kind == "node" else npe * n_elem
+    """Pairs (node relation, both relations) or slots (element relation)."""
+    if kind == "elem":
+        return _b.NODES_PER_ELEM[etype] * n_elem
+    return 2 * _b.EDGES_PER_ELEM[etype] * n_elem
 
 
 _table_cache = None
@@ -55,62 +67,51 @@ def load_table():
 
 
 def _nearest(relation, etype, n_keys):
-    table = load_table()
-    if not table:
-        return None
     b = size_bucket(n_keys)
     best = None
-    for (rel, et, bk), e in table.items():
-        if rel == relation and et == etype and (best is None or abs(bk - b) < abs(best["bucket"] - b)):
+    for (rel, et, bk), e in load_table().items():
+        if rel == relation and et == etype and abs(bk - b) <= MAX_BUCKET_GAP and (
+                best is None or abs(bk - b) < abs(best["bucket"] - b)):
             best = e
     return best
 
 
-def lookup(kind, etype, n_elem):
-    """The tuned entry for a single-mesh call, or the nearest bucket of the
-    same relation and type, or None."""
-    return _nearest(kind, etype, keys_of(kind, n_elem, etype))
-
-
-def lookup_batch(kind, n_keys):
-    """The tuned entry for a batch of n_keys pairs (node) or slots (element)."""
-    return _nearest("batch_" + kind, -1, n_keys)
-
-
-def _set(kind, e):
+def _as_options(e, kind):
     if e is None:
-        _b.set_radix_shape(-1)
-        if kind == "node":
-            _b.set_node_sort(_b.NODE_SORT_FULL_KEY)
-        return
-    _b.set_radix_shape(e["shape"])
-    if kind == "node":
-        _b.set_node_sort(e["mode"])
+        return None
+    o = {"radix_shape": e["radix_shape"], "digit_bits": e.get("digit_bits", -1)}
+    if kind != "elem":
+        o["node_sort"] = e["node_sort"]
+    return o
 
 
-def apply(kind, etype, n_elem):
-    _set(kind, lookup(kind, etype, n_elem))
+def options_for(kind, etype, n_elem):
+    """mesh_options (as a dict) for a single-mesh call of relation kind
+    ("node", "elem" or "both"), or None for the library defaults."""
+    return _as_options(_nearest(kind, etype, keys_of(kind, n_elem, etype)), kind)
 
 
-def apply_batch(kind, n_keys):
-    _set(kind, lookup_batch(kind, n_keys))
+def batch_options_for(kind, pairs, slots):
+    """mesh_options (as a dict) for a batch of `pairs` directed pairs and
+    `slots` node slots, or None."""
+    return _as_options(_nearest("batch_" + kind, -1, slots if kind == "elem" else pairs), kind)
 
 
-def _digest(row_ptr, cols):
+def _digest(out):
     h = hashlib.sha256()
-    h.update(row_ptr.cpu().numpy().tobytes())
-    h.update(cols.cpu().numpy().tobytes())
+    if isinstance(out[0], tuple):
+        for rp, cols in out:
+            h.update(rp.cpu().numpy().tobytes())
+            h.update(cols.cpu().numpy().tobytes())
+    else:
+        h.update(out[0].cpu().numpy().tobytes())
+        h.update(out[1].cpu().numpy().tobytes())
     return h.hexdigest()
 
 
-def time_config(torch, kind, mesh, conn, shape, mode, steps):
-    _b.set_radix_shape(shape)
-    if kind == "node":
-        _b.set_node_sort(mode)
-    build = _b.NeighborBuild(kind, mesh.n_elem, mesh.etype, mesh.n_vert, conn.device)
+def _time(torch, build, conn, steps):
     build.launch(conn)
-    rp, cols = build.result()
-    digest = _digest(rp, cols)
+    digest = _digest(build.result())
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -118,53 +119,23 @@ def time_config(torch, kind, mesh, conn, shape, mode, steps):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / steps * 1e3
     build.check()
-    del build
     return ms, digest
 
 
-def time_batch_config(torch, kind, desc, conn, shape, mode, steps):
-    _b.set_radix_shape(shape)
-    if kind == "node":
-        _b.set_node_sort(mode)
-    build = _b.BatchBuild(kind, desc, conn.device)
-    build.launch(conn)
-    rp, cols = build.result()
-    digest = _digest(rp, cols)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        build.launch(conn)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) / steps * 1e3
-    build.check()
-    del build
-    return ms, digest
+def candidates(kind):
+    modes = (0, 1, 2, 3) if kind != "elem" else (-1,)
+    return [{"node_sort": m, "radix_shape": s, "digit_bits": d} for m in modes for s in TUNED_SHAPES
+            for d in DIGIT_WIDTHS]
 
 
-def tune_batches(torch, batches, steps=3, log=print):
-    entries = []
-    for name, meshes in batches:
-        desc = [(m.n_elem, m.etype, m.n_vert) for m in meshes]
-        conn = torch.as_tensor(_b.concat_conn([m.conn for m in meshes])).to("cuda:0")
-        seg, tot = _b.segment_table(desc)
-        for kind in ("node", "elem"):
-            modes = (0, 1, 2) if kind == "node" else (0,)
-            results = []
-            for mode in modes:
-                for shape in range(len(_b.radix_shapes())):
-                    ms, dg = time_batch_config(torch, kind, desc, conn, shape, mode, steps)
-                    results.append((ms, shape, mode, dg))
-                    log(f"[tune] {name} batch {kind} shape {_b.radix_shapes()[shape]} mode {mode}: {ms:.3f} ms")
-            if len({r[3] for r in results}) != 1:
-                raise RuntimeError(f"configurations disagree on batch {name} {kind}: outputs differ")
-            ms, shape, mode, _ = min(results)
-            n_keys = tot["pairs"] if kind == "node" else tot["slots"]
-            entries.append({"relation": "batch_" + kind, "etype": -1, "bucket": size_bucket(n_keys),
-                            "shape": shape, "mode": mode, "ms": ms, "workload": name,
-                            "candidates": {f"shape{s}_mode{md}": round(t, 4) for t, s, md, _ in results}})
-        del conn
-        torch.cuda.empty_cache()
-    return entries
+def _entry(relation, etype, n_keys, results, workload):
+    if len({r[2] for r in results}) != 1:
+        raise RuntimeError(f"configurations disagree on {workload} {relation}: outputs differ")
+    ms, opts, _ = min(results, key=lambda r: r[0])
+    return {"relation": relation, "etype": etype, "bucket": size_bucket(n_keys), **opts, "ms": ms,
+            "workload": workload,
+            "candidates": {f"ns{o['node_sort']}_shape{o['radix_shape']}_d{o['digit_bits']}": round(t, 4)
+                           for t, o, _ in results}}
 
 
 def tune(meshes, steps=5, log=print, batches=()):
@@ -174,25 +145,33 @@ def tune(meshes, steps=5, log=print, batches=()):
     dev = torch.device("cuda:0")
     for m in meshes:
         conn = torch.as_tensor(m.conn).to(dev)
-        for kind in ("node", "elem"):
-            modes = (0, 1, 2) if kind == "node" else (0,)
+        for kind in ("node", "elem", "both"):
             results = []
-            for mode in modes:
-                for shape in range(len(_b.radix_shapes())):
-                    ms, dg = time_config(torch, kind, m, conn, shape, mode, steps)
-                    results.append((ms, shape, mode, dg))
-                    log(f"[tune] {m.name} {kind} shape {_b.radix_shapes()[shape]} mode {mode}: {ms:.3f} ms")
-            if len({r[3] for r in results}) != 1:
-                raise RuntimeError(f"configurations disagree on {m.name} {kind}: outputs differ")
-            ms, shape, mode, _ = min(results)
-            entries.append({"relation": kind, "etype": m.etype, "bucket": size_bucket(keys_of(kind, m.n_elem, m.etype)),
-                            "shape": shape, "mode": mode, "ms": ms, "workload": m.name,
-                            "candidates": {f"shape{s}_mode{md}": round(t, 4) for t, s, md, _ in results}})
+            for o in candidates(kind):
+                b = _b.NeighborBuild(kind, m.n_elem, m.etype, m.n_vert, dev, options=o)
+                ms, dg = _time(torch, b, conn, steps)
+                del b
+                results.append((ms, o, dg))
+                log(f"[tune] {m.name} {kind} {o}: {ms:.3f} ms")
+            entries.append(_entry(kind, m.etype, keys_of(kind, m.n_elem, m.etype), results, m.name))
         del conn
         torch.cuda.empty_cache()
-    entries += tune_batches(torch, batches, log=log)
-    _b.set_radix_shape(-1)
-    _b.set_node_sort(_b.NODE_SORT_FULL_KEY)
+    for name, meshes_b in batches:
+        desc = [(x.n_elem, x.etype, x.n_vert) for x in meshes_b]
+        conn = torch.as_tensor(_b.concat_conn([x.conn for x in meshes_b])).to(dev)
+        _, tot = _b.segment_table(desc)
+        for kind in ("node", "elem", "both"):
+            results = []
+            for o in candidates(kind):
+                b = _b.BatchBuild(kind, desc, dev, options=o)
+                ms, dg = _time(torch, b, conn, max(2, steps // 2))
+                del b
+                results.append((ms, o, dg))
+                log(f"[tune] {name} batch {kind} {o}: {ms:.3f} ms")
+            entries.append(_entry("batch_" + kind, -1, tot["slots"] if kind == "elem" else tot["pairs"], results,
+                                  name))
+        del conn
+        torch.cuda.empty_cache()
     props = torch.cuda.get_device_properties(0)
     return {"device": getattr(props, "gcnArchName", props.name), "shapes": _b.radix_shapes(), "entries": entries}
 
@@ -208,7 +187,7 @@ def main():
         meshes = [mg.tri_grid(256, "coin", 1), mg.kuhn_tet_grid(16, 2), mg.hex_grid(16, 3)]
         batches = [("batch64", [s.build() for s in mg.batch_specs(64, seed=7)])]
     else:
-        meshes = [mg.tri_grid(256, "coin", 1), mg.tri_grid(1024, "coin", 2), mg.tri2048(),
+        meshes = [mg.tri64(), mg.tri_grid(256, "coin", 1), mg.tri_grid(1024, "coin", 2), mg.tri2048(),
                   mg.kuhn_tet_grid(24, 3), mg.kuhn_tet_grid(48, 4), mg.kuhn96(),
                   mg.hex_grid(24, 5), mg.hex_grid(64, 6)]
         batches = [("batch64", [s.build() for s in mg.batch_specs(64, seed=7)]),

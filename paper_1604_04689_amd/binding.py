@@ -13,8 +13,9 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmeshnbr.so")
 
-TRI3, TET4, HEX8 = 0, 1, 2
-NODES_PER_ELEM = {TRI3: 3, TET4: 4, HEX8: 8}
+TRI3, TET4, HEX8, QUAD4, WEDGE6, PYRAMID5 = 0, 1, 2, 3, 4, 5
+NODES_PER_ELEM = {TRI3: 3, TET4: 4, HEX8: 8, QUAD4: 4, WEDGE6: 6, PYRAMID5: 5}
+EDGES_PER_ELEM = {TRI3: 3, TET4: 6, HEX8: 12, QUAD4: 4, WEDGE6: 9, PYRAMID5: 8}
 
 
 class Status(enum.IntEnum):
@@ -40,45 +41,81 @@ class KernelTime(ctypes.Structure):
                 ("min_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
 
 
+NODE_SORT_FULL_KEY, NODE_SORT_VERTEX_ROWS, NODE_SORT_EDGE_ROWS, NODE_SORT_ELEM_ROWS = 0, 1, 2, 3
+NODE_SORT_NAMES = {0: "full_key", 1: "vertex_rows", 2: "edge_rows", 3: "elem_rows"}
+
+
+class Options(ctypes.Structure):
+    """mesh_options: per-call speed-only choices (-1 = library default)."""
+    _fields_ = [("node_sort", ctypes.c_int32), ("radix_shape", ctypes.c_int32), ("digit_bits", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+    def as_dict(self):
+        return {"node_sort": int(self.node_sort), "radix_shape": int(self.radix_shape),
+                "digit_bits": int(self.digit_bits)}
+
+
+def make_options(options=None) -> Options:
+    """Options from None (defaults), an Options, or a dict with any of
+    node_sort, radix_shape, digit_bits."""
+    if isinstance(options, Options):
+        return options
+    o = Options(-1, -1, -1)
+    for k, v in (options or {}).items():
+        if k not in ("node_sort", "radix_shape", "digit_bits"):
+            raise ValueError(f"unknown option {k}")
+        setattr(o, k, -1 if v is None else int(v))
+    return o
+
+
 _lib = None
 
 _c_i32, _c_i64, _c_sz, _c_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
+_P_SZ, _P_I64, _P_I32, _P_P = (ctypes.POINTER(_c_sz), ctypes.POINTER(_c_i64), ctypes.POINTER(_c_i32),
+                               ctypes.POINTER(_c_p))
+_P_OPT = ctypes.POINTER(Options)
 
 # name -> (restype, argtypes); mirrors include/mesh_neighbors.h
+_ONE = [_c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64, _P_OPT, _c_p, _c_sz]
+_BOTH = [_c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64, _c_p, _c_p, _c_i64, _P_OPT, _c_p, _c_sz]
+_BNODE = [_c_p, _c_p, _c_i32, _c_i64, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64, _P_OPT, _c_p, _c_sz]
+_BELEM = [_c_p, _c_p, _c_i32, _c_i64, _c_i32, _c_p, _c_p, _c_i64, _P_OPT, _c_p, _c_sz]
+_BBOTH = [_c_p, _c_p, _c_i32, _c_i64, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64, _c_p, _c_p, _c_i64, _P_OPT,
+          _c_p, _c_sz]
 SIGNATURES = {
-    "mesh_node_neighbors_query": (_c_i32, [_c_i64, _c_i32, _c_i32, ctypes.POINTER(_c_sz), ctypes.POINTER(_c_i64)]),
-    "mesh_node_neighbors": (_c_i32, [_c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64, _c_p, _c_sz, _c_p]),
-    "mesh_elem_neighbors_query": (_c_i32, [_c_i64, _c_i32, _c_i32, ctypes.POINTER(_c_sz), ctypes.POINTER(_c_i64)]),
-    "mesh_elem_neighbors": (_c_i32, [_c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64, _c_p, _c_sz, _c_p]),
+    "mesh_default_options": (Options, []),
+    "mesh_node_neighbors_query": (_c_i32, [_c_i64, _c_i32, _c_i32, _P_OPT, _P_SZ, _P_I64]),
+    "mesh_node_neighbors": (_c_i32, _ONE + [_c_p]),
+    "mesh_elem_neighbors_query": (_c_i32, [_c_i64, _c_i32, _c_i32, _P_OPT, _P_SZ, _P_I64]),
+    "mesh_elem_neighbors": (_c_i32, _ONE + [_c_p]),
+    "mesh_neighbors_query": (_c_i32, [_c_i64, _c_i32, _c_i32, _P_OPT, _P_SZ, _P_I64, _P_I64]),
+    "mesh_neighbors": (_c_i32, _BOTH + [_c_p]),
+    "mesh_mixed_neighbors_query": (_c_i32, [_c_i64, _c_i64, _c_i64, _c_i32, _P_OPT, _P_SZ, _P_I64, _P_I64]),
+    "mesh_mixed_neighbors": (_c_i32, [_c_p, _c_p, _c_p, _c_i64, _c_i64, _c_i64, _c_i32, _c_p, _c_p, _c_i64, _c_p,
+                                      _c_p, _c_i64, _P_OPT, _c_p, _c_sz, _c_p]),
+    "mesh_batch_node_neighbors_query": (_c_i32, [_c_i32, _c_i64, _c_i64, _c_i32, _c_i32, _P_OPT, _P_SZ, _P_I64]),
+    "mesh_batch_node_neighbors": (_c_i32, _BNODE + [_c_p]),
+    "mesh_batch_elem_neighbors_query": (_c_i32, [_c_i32, _c_i64, _c_i32, _P_OPT, _P_SZ, _P_I64]),
+    "mesh_batch_elem_neighbors": (_c_i32, _BELEM + [_c_p]),
+    "mesh_batch_neighbors_query": (_c_i32, [_c_i32, _c_i64, _c_i64, _c_i32, _c_i32, _P_OPT, _P_SZ, _P_I64,
+                                            _P_I64]),
+    "mesh_batch_neighbors": (_c_i32, _BBOTH + [_c_p]),
+    "mesh_graph_node_neighbors": (_c_i32, _ONE + [_P_P]),
+    "mesh_graph_elem_neighbors": (_c_i32, _ONE + [_P_P]),
+    "mesh_graph_neighbors": (_c_i32, _BOTH + [_P_P]),
+    "mesh_graph_batch_node_neighbors": (_c_i32, _BNODE + [_P_P]),
+    "mesh_graph_batch_elem_neighbors": (_c_i32, _BELEM + [_P_P]),
+    "mesh_graph_batch_neighbors": (_c_i32, _BBOTH + [_P_P]),
+    "mesh_graph_launch": (_c_i32, [_c_p, _c_p]),
+    "mesh_graph_destroy": (_c_i32, [_c_p]),
     "mesh_check": (_c_i32, [_c_p, _c_p]),
     "mesh_status_string": (ctypes.c_char_p, [_c_i32]),
     "mesh_abi_version": (_c_i32, []),
-    "mesh_batch_node_neighbors_query": (_c_i32, [_c_i32, _c_i64, _c_i32, _c_i32, ctypes.POINTER(_c_sz),
-                                                 ctypes.POINTER(_c_i64)]),
-    "mesh_batch_node_neighbors": (_c_i32, [_c_p, _c_p, _c_i32, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64, _c_p,
-                                           _c_sz, _c_p]),
-    "mesh_batch_elem_neighbors_query": (_c_i32, [_c_i32, _c_i64, _c_i32, ctypes.POINTER(_c_sz),
-                                                 ctypes.POINTER(_c_i64)]),
-    "mesh_batch_elem_neighbors": (_c_i32, [_c_p, _c_p, _c_i32, _c_i64, _c_i32, _c_p, _c_p, _c_i64, _c_p, _c_sz,
-                                           _c_p]),
-    "mesh_timing_enable": (_c_i32, [_c_i32]),
     "mesh_radix_shape_count": (_c_i32, []),
-    "mesh_radix_shape_info": (_c_i32, [_c_i32, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]),
-    "mesh_set_radix_shape": (_c_i32, [_c_i32]),
-    "mesh_get_radix_shape": (_c_i32, []),
-    "mesh_set_node_sort": (_c_i32, [_c_i32]),
-    "mesh_get_node_sort": (_c_i32, []),
+    "mesh_radix_shape_info": (_c_i32, [_c_i32, _P_I32, _P_I32]),
+    "mesh_radix_launch_shape": (_c_i32, [_c_i32, _c_i32, _c_i64, _P_I32, _P_I32, _P_I32]),
+    "mesh_timing_enable": (_c_i32, [_c_i32]),
     "mesh_timing_read": (_c_i32, [ctypes.POINTER(KernelTime), _c_i32]),
-    "mesh_graph_node_neighbors": (_c_i32, [_c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64, _c_p, _c_sz,
-                                           ctypes.POINTER(_c_p)]),
-    "mesh_graph_elem_neighbors": (_c_i32, [_c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64, _c_p, _c_sz,
-                                           ctypes.POINTER(_c_p)]),
-    "mesh_graph_batch_node_neighbors": (_c_i32, [_c_p, _c_p, _c_i32, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64,
-                                                 _c_p, _c_sz, ctypes.POINTER(_c_p)]),
-    "mesh_graph_batch_elem_neighbors": (_c_i32, [_c_p, _c_p, _c_i32, _c_i64, _c_i32, _c_p, _c_p, _c_i64, _c_p,
-                                                 _c_sz, ctypes.POINTER(_c_p)]),
-    "mesh_graph_launch": (_c_i32, [_c_p, _c_p]),
-    "mesh_graph_destroy": (_c_i32, [_c_p]),
 }
 
 
@@ -112,30 +149,15 @@ def radix_shapes():
     return out
 
 
-def set_radix_shape(shape: int = -1):
-    """Select the radix tile shape for all later calls (-1 = default)."""
-    st = lib().mesh_set_radix_shape(int(shape))
+def radix_launch_shape(shape, digit_bits, n_keys):
+    """(block, items, digit bits) a pass over n_keys keys launches with when
+    the options ask for `shape` and `digit_bits` (-1: defaults)."""
+    b, it, bits = _c_i32(0), _c_i32(0), _c_i32(0)
+    st = lib().mesh_radix_launch_shape(int(shape), int(digit_bits), int(n_keys), ctypes.byref(b), ctypes.byref(it),
+                                       ctypes.byref(bits))
     if st != Status.OK:
-        raise MeshError(st, "mesh_set_radix_shape")
-
-
-def get_radix_shape() -> int:
-    return int(lib().mesh_get_radix_shape())
-
-
-NODE_SORT_FULL_KEY, NODE_SORT_VERTEX_ROWS, NODE_SORT_EDGE_ROWS = 0, 1, 2
-
-
-def set_node_sort(mode: int):
-    """Select the node algorithm of single meshes and batches (results are
-    identical)."""
-    st = lib().mesh_set_node_sort(int(mode))
-    if st != Status.OK:
-        raise MeshError(st, "mesh_set_node_sort")
-
-
-def get_node_sort() -> int:
-    return int(lib().mesh_get_node_sort())
+        raise MeshError(st, "mesh_radix_launch_shape")
+    return b.value, it.value, bits.value
 
 
 def timing_enable(on: bool = True):
@@ -153,24 +175,34 @@ def timing_read():
             for i in range(min(n, 64))}
 
 
-def _query(kind, n_elem, etype, n_vert):
-    ws = _c_sz(0)
-    cap = _c_i64(0)
-    st = getattr(lib(), f"mesh_{kind}_neighbors_query")(int(n_elem), int(etype), int(n_vert),
-                                                       ctypes.byref(ws), ctypes.byref(cap))
+def _check(st, where):
     if st != Status.OK:
-        raise MeshError(st, f"mesh_{kind}_neighbors_query")
+        raise MeshError(st, where)
+
+
+def query(kind, n_elem, etype, n_vert, options=None):
+    """(workspace bytes, cols capacity) for kind "node" or "elem", or
+    (workspace bytes, node capacity, elem capacity) for "both"."""
+    o = make_options(options)
+    ws, cap, cap2 = _c_sz(0), _c_i64(0), _c_i64(0)
+    if kind == "both":
+        _check(lib().mesh_neighbors_query(int(n_elem), int(etype), int(n_vert), ctypes.byref(o), ctypes.byref(ws),
+                                          ctypes.byref(cap), ctypes.byref(cap2)), "mesh_neighbors_query")
+        return int(ws.value), int(cap.value), int(cap2.value)
+    fn = getattr(lib(), f"mesh_{kind}_neighbors_query")
+    _check(fn(int(n_elem), int(etype), int(n_vert), ctypes.byref(o), ctypes.byref(ws), ctypes.byref(cap)),
+           f"mesh_{kind}_neighbors_query")
     return int(ws.value), int(cap.value)
 
 
-def query_node(n_elem, etype, n_vert):
+def query_node(n_elem, etype, n_vert, options=None):
     """(workspace bytes, sufficient cols capacity) for the node relation."""
-    return _query("node", n_elem, etype, n_vert)
+    return query("node", n_elem, etype, n_vert, options)
 
 
-def query_elem(n_elem, etype, n_vert):
+def query_elem(n_elem, etype, n_vert, options=None):
     """(workspace bytes, sufficient cols capacity) for the element relation."""
-    return _query("elem", n_elem, etype, n_vert)
+    return query("elem", n_elem, etype, n_vert, options)
 
 
 def _stream_handle(stream, device):
@@ -185,82 +217,110 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
 
 
-class NeighborBuild:
-    """Device buffers for one relation ("node" or "elem") of one mesh shape.
+def _workspace(torch, nbytes, device, old=None):
+    """A 256-byte aligned byte view of at least nbytes (reusing `old`'s
+    storage when it is large enough): (raw tensor, aligned view)."""
+    raw = old if old is not None and old.numel() >= nbytes + 256 else \
+        torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    pad = (-raw.data_ptr()) % 256
+    return raw, raw[pad:pad + nbytes]
 
-    Allocates the workspace and outputs once; ``launch`` enqueues the
-    pipeline on a stream without allocating or synchronising, ``result``
-    checks the device error word and returns ``(row_ptr, cols[:nnz])``.
+
+def _resolve(kind, etype, n_elem, options):
+    """Options for a build: "tuned" looks them up in the tuning table."""
+    if isinstance(options, str):
+        if options != "tuned":
+            raise ValueError(options)
+        from . import autotune
+        return make_options(autotune.options_for(kind, etype, n_elem))
+    return make_options(options)
+
+
+def _check_conn(torch, conn, device):
+    if conn.device != device or conn.dtype != torch.int32 or not conn.is_contiguous():
+        raise ValueError("conn must be a contiguous int32 tensor on the build's device")
+
+
+class NeighborBuild:
+    """Device buffers for one mesh shape and one relation: kind "node",
+    "elem", or "both" (one call building both).
+
+    The options (None: library defaults; a dict; "tuned": from the tuning
+    table) are fixed here, since the workspace size depends on them.
+    ``launch`` enqueues the pipeline on a stream without allocating or
+    synchronising; ``result`` checks the device error word and returns
+    ``(row_ptr, cols[:nnz])`` (for "both": ``((node row_ptr, cols), (elem
+    row_ptr, cols))``).
     """
 
-    def __init__(self, kind, n_elem, etype, n_vert, device="cuda", cols_capacity=None):
+    def __init__(self, kind, n_elem, etype, n_vert, device="cuda", cols_capacity=None, options=None):
         import torch
 
-        if kind not in ("node", "elem"):
+        if kind not in ("node", "elem", "both"):
             raise ValueError(kind)
         self.kind = kind
         self.n_elem, self.etype, self.n_vert = int(n_elem), int(etype), int(n_vert)
         self.device = torch.device(device)
-        ws_bytes, cap = _query(kind, n_elem, etype, n_vert)
-        self.cols_capacity = int(cap if cols_capacity is None else cols_capacity)
-        # 256-byte aligned workspace carved from a byte tensor
-        self._ws_raw = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=self.device)
-        pad = (-self._ws_raw.data_ptr()) % 256
-        self.workspace = self._ws_raw[pad:pad + ws_bytes]
+        self.options = _resolve(kind, etype, n_elem, options)
+        q = query(kind, n_elem, etype, n_vert, self.options)
+        ws_bytes = q[0]
+        self.cols_capacity = int(q[1] if cols_capacity is None else cols_capacity)
+        self._ws_raw, self.workspace = _workspace(torch, ws_bytes, self.device)
         self.ws_bytes = ws_bytes
         self.row_ptr = torch.empty(self.n_vert + 1, dtype=torch.int32, device=self.device)
         self.cols = torch.empty(max(self.cols_capacity, 1), dtype=torch.int32, device=self.device)
-        self._fn = getattr(lib(), f"mesh_{kind}_neighbors")
+        if kind == "both":
+            self.elem_capacity = int(q[2])
+            self.elem_row_ptr = torch.empty(self.n_vert + 1, dtype=torch.int32, device=self.device)
+            self.elem_cols = torch.empty(max(self.elem_capacity, 1), dtype=torch.int32, device=self.device)
 
-    def launch(self, conn, stream=None, tuned=False):
+    def _args(self, conn):
+        a = [_ptr(conn), self.n_elem, self.etype, self.n_vert, _ptr(self.row_ptr),
+             _ptr(self.cols) if self.cols_capacity > 0 else ctypes.c_void_p(0), self.cols_capacity]
+        if self.kind == "both":
+            a += [_ptr(self.elem_row_ptr), _ptr(self.elem_cols) if self.elem_capacity > 0 else ctypes.c_void_p(0),
+                  self.elem_capacity]
+        return a + [ctypes.byref(self.options), _ptr(self.workspace), self.ws_bytes]
+
+    def _name(self, prefix="mesh_"):
+        return prefix + ("neighbors" if self.kind == "both" else f"{self.kind}_neighbors")
+
+    def _validate(self, conn):
         import torch
 
-        if conn.device != self.device or conn.dtype != torch.int32 or not conn.is_contiguous():
-            raise ValueError("conn must be a contiguous int32 tensor on the build's device")
-        if tuned and self.etype in NODES_PER_ELEM:
-            from . import autotune
-            autotune.apply(self.kind, self.etype, self.n_elem)
+        _check_conn(torch, conn, self.device)
         npe = NODES_PER_ELEM.get(self.etype)
         if npe is not None and conn.numel() != self.n_elem * npe:
             raise ValueError(f"conn has {conn.numel()} ids, expected {self.n_elem} x {npe}")
-        st = self._fn(_ptr(conn), self.n_elem, self.etype, self.n_vert, _ptr(self.row_ptr),
-                      _ptr(self.cols) if self.cols_capacity > 0 else ctypes.c_void_p(0), self.cols_capacity,
-                      _ptr(self.workspace), self.ws_bytes, _stream_handle(stream, self.device))
-        if st != Status.OK:
-            raise MeshError(st, f"mesh_{self.kind}_neighbors")
+
+    def launch(self, conn, stream=None):
+        self._validate(conn)
+        name = self._name()
+        _check(getattr(lib(), name)(*self._args(conn), _stream_handle(stream, self.device)), name)
 
     def check(self, stream=None):
-        st = lib().mesh_check(_ptr(self.workspace), _stream_handle(stream, self.device))
-        if st != Status.OK:
-            raise MeshError(st, "mesh_check")
+        _check(lib().mesh_check(_ptr(self.workspace), _stream_handle(stream, self.device)), "mesh_check")
 
     def result(self, stream=None):
         self.check(stream)
         nnz = int(self.row_ptr[-1].item())
+        if self.kind == "both":
+            enz = int(self.elem_row_ptr[-1].item())
+            return (self.row_ptr, self.cols[:nnz]), (self.elem_row_ptr, self.elem_cols[:enz])
         return self.row_ptr, self.cols[:nnz]
 
-    def capture(self, conn, tuned=False):
+    def capture(self, conn):
         """A Graph replaying ``launch(conn)`` on this build's buffers; conn's
         contents may change between replays, its address and size may not."""
-        import torch
-
-        if conn.device != self.device or conn.dtype != torch.int32 or not conn.is_contiguous():
-            raise ValueError("conn must be a contiguous int32 tensor on the build's device")
-        if tuned and self.etype in NODES_PER_ELEM:
-            from . import autotune
-            autotune.apply(self.kind, self.etype, self.n_elem)
-        npe = NODES_PER_ELEM.get(self.etype)
-        if npe is not None and conn.numel() != self.n_elem * npe:
-            raise ValueError(f"conn has {conn.numel()} ids, expected {self.n_elem} x {npe}")
+        self._validate(conn)
         h = _c_p()
+        name = self._name("mesh_graph_")
         with _device_guard(self.device):
-            st = getattr(lib(), f"mesh_graph_{self.kind}_neighbors")(
-                _ptr(conn), self.n_elem, self.etype, self.n_vert, _ptr(self.row_ptr),
-                _ptr(self.cols) if self.cols_capacity > 0 else ctypes.c_void_p(0), self.cols_capacity,
-                _ptr(self.workspace), self.ws_bytes, ctypes.byref(h))
-        if st != Status.OK:
-            raise MeshError(st, f"mesh_graph_{self.kind}_neighbors")
-        return Graph(h, self.device, keep=(conn, self._ws_raw, self.row_ptr, self.cols))
+            st = getattr(lib(), name)(*self._args(conn), ctypes.byref(h))
+        _check(st, name)
+        keep = (conn, self._ws_raw, self.row_ptr, self.cols) + (
+            (self.elem_row_ptr, self.elem_cols) if self.kind == "both" else ())
+        return Graph(h, self.device, keep=keep)
 
 
 class Graph:
@@ -275,9 +335,7 @@ class Graph:
     def launch(self, stream=None):
         if not self._h:
             raise ValueError("graph was destroyed")
-        st = lib().mesh_graph_launch(self._h, _stream_handle(stream, self.device))
-        if st != Status.OK:
-            raise MeshError(st, "mesh_graph_launch")
+        _check(lib().mesh_graph_launch(self._h, _stream_handle(stream, self.device)), "mesh_graph_launch")
 
     def destroy(self):
         if self._h:
@@ -304,26 +362,106 @@ def _n_elem(conn, etype):
     return conn.numel() // NODES_PER_ELEM.get(int(etype), 1)
 
 
-def node_neighbors(conn, etype, n_vert, stream=None):
+def node_neighbors(conn, etype, n_vert, stream=None, options=None):
     """One-ring neighboring nodes of every vertex: (row_ptr, cols) on conn's device."""
-    b = NeighborBuild("node", _n_elem(conn, etype), etype, n_vert, conn.device)
+    b = NeighborBuild("node", _n_elem(conn, etype), etype, n_vert, conn.device, options=options)
     b.launch(conn, stream)
     return b.result(stream)
 
 
-def elem_neighbors(conn, etype, n_vert, stream=None):
+def elem_neighbors(conn, etype, n_vert, stream=None, options=None):
     """One-ring neighboring elements of every vertex: (row_ptr, cols) on conn's device."""
-    b = NeighborBuild("elem", _n_elem(conn, etype), etype, n_vert, conn.device)
+    b = NeighborBuild("elem", _n_elem(conn, etype), etype, n_vert, conn.device, options=options)
     b.launch(conn, stream)
+    return b.result(stream)
+
+
+def neighbors(conn, etype, n_vert, stream=None, options=None):
+    """Both relations in one call: ((node row_ptr, cols), (elem row_ptr, cols))."""
+    b = NeighborBuild("both", _n_elem(conn, etype), etype, n_vert, conn.device, options=options)
+    b.launch(conn, stream)
+    return b.result(stream)
+
+
+# ---------------------------------------------------------------------------
+# Meshes of several element types
+# ---------------------------------------------------------------------------
+
+def mixed_layout(etypes):
+    """(elem_off int32 [n+1], n_ids, n_pairs) of elements of the given types,
+    their ids back to back."""
+    import numpy as np
+
+    et = np.asarray(etypes, dtype=np.int64)
+    npe = np.array([NODES_PER_ELEM[t] for t in range(6)], dtype=np.int64)[et]
+    nedge = np.array([EDGES_PER_ELEM[t] for t in range(6)], dtype=np.int64)[et]
+    off = np.zeros(et.size + 1, dtype=np.int64)
+    np.cumsum(npe, out=off[1:])
+    return off.astype(np.int32), int(off[-1]), int(2 * nedge.sum())
+
+
+class MixedBuild:
+    """Both relations of a mesh whose elements carry their own types
+    (mesh_mixed_neighbors).  The node relation takes the ELEM_ROWS algorithm."""
+
+    def __init__(self, n_elem, n_ids, n_pairs, n_vert, device="cuda", options=None):
+        import torch
+
+        self.n_elem, self.n_ids, self.n_pairs, self.n_vert = int(n_elem), int(n_ids), int(n_pairs), int(n_vert)
+        self.device = torch.device(device)
+        self.options = make_options(options)
+        ws, c1, c2 = _c_sz(0), _c_i64(0), _c_i64(0)
+        _check(lib().mesh_mixed_neighbors_query(self.n_elem, self.n_ids, self.n_pairs, self.n_vert,
+                                                ctypes.byref(self.options), ctypes.byref(ws), ctypes.byref(c1),
+                                                ctypes.byref(c2)), "mesh_mixed_neighbors_query")
+        self.ws_bytes = int(ws.value)
+        self.node_capacity, self.elem_capacity = int(c1.value), int(c2.value)
+        self._ws_raw, self.workspace = _workspace(torch, self.ws_bytes, self.device)
+        self.row_ptr = torch.empty(self.n_vert + 1, dtype=torch.int32, device=self.device)
+        self.cols = torch.empty(max(self.node_capacity, 1), dtype=torch.int32, device=self.device)
+        self.elem_row_ptr = torch.empty(self.n_vert + 1, dtype=torch.int32, device=self.device)
+        self.elem_cols = torch.empty(max(self.elem_capacity, 1), dtype=torch.int32, device=self.device)
+
+    def launch(self, conn, elem_off, etypes, stream=None):
+        import torch
+
+        _check_conn(torch, conn, self.device)
+        _check_conn(torch, elem_off, self.device)
+        if etypes.device != self.device or etypes.dtype != torch.uint8 or not etypes.is_contiguous():
+            raise ValueError("etypes must be a contiguous uint8 tensor on the build's device")
+        if elem_off.numel() != self.n_elem + 1 or etypes.numel() != self.n_elem or conn.numel() < self.n_ids:
+            raise ValueError("elem_off, etypes or conn do not match the build's sizes")
+        _check(lib().mesh_mixed_neighbors(
+            _ptr(conn), _ptr(elem_off), _ptr(etypes), self.n_elem, self.n_ids, self.n_pairs, self.n_vert,
+            _ptr(self.row_ptr), _ptr(self.cols) if self.node_capacity > 0 else ctypes.c_void_p(0),
+            self.node_capacity, _ptr(self.elem_row_ptr),
+            _ptr(self.elem_cols) if self.elem_capacity > 0 else ctypes.c_void_p(0), self.elem_capacity,
+            ctypes.byref(self.options), _ptr(self.workspace), self.ws_bytes, _stream_handle(stream, self.device)),
+            "mesh_mixed_neighbors")
+
+    def check(self, stream=None):
+        _check(lib().mesh_check(_ptr(self.workspace), _stream_handle(stream, self.device)), "mesh_check")
+
+    def result(self, stream=None):
+        self.check(stream)
+        nnz, enz = int(self.row_ptr[-1].item()), int(self.elem_row_ptr[-1].item())
+        return (self.row_ptr, self.cols[:nnz]), (self.elem_row_ptr, self.elem_cols[:enz])
+
+
+def mixed_neighbors(conn, etypes, n_vert, stream=None, options=None):
+    """Both relations of a mixed mesh given as flat int32 ids (device tensor)
+    and per-element type codes (device uint8 tensor)."""
+    import torch
+
+    elem_off, n_ids, n_pairs = mixed_layout(etypes.cpu().numpy())
+    b = MixedBuild(etypes.numel(), n_ids, n_pairs, n_vert, conn.device, options=options)
+    b.launch(conn, torch.as_tensor(elem_off).to(conn.device), etypes, stream)
     return b.result(stream)
 
 
 # ---------------------------------------------------------------------------
 # Batches of meshes
 # ---------------------------------------------------------------------------
-
-EDGES_PER_ELEM = {TRI3: 3, TET4: 6, HEX8: 12}
-
 
 def segment_table(meshes, conn_offs=None):
     """mesh_segment records (numpy structured array, 48 bytes each) for a
@@ -354,23 +492,29 @@ def segment_table(meshes, conn_offs=None):
 
 
 class BatchBuild:
-    """Device buffers for one relation ("node" or "elem") of a batch of meshes.
+    """Device buffers for one relation ("node", "elem" or "both") of a batch
+    of meshes.
 
     ``meshes`` is a list of (n_elem, etype, n_vert); the connectivity passed to
     ``launch`` is all meshes' int32 ids back to back, each mesh's ids local.
     ``result`` gives the global CSR (cols in local ids); ``mesh_csr(m)`` the
     slice of mesh m rebased to start at 0.  ``reset(meshes)`` re-targets the
     build at another batch, reusing its device buffers when they are large
-    enough (they only grow)."""
+    enough (they only grow).  Options are fixed at construction ("tuned":
+    from the tuning table's batch entries)."""
 
-    def __init__(self, kind, meshes, device="cuda", conn_offs=None):
+    def __init__(self, kind, meshes, device="cuda", conn_offs=None, options=None):
         import torch
 
-        if kind not in ("node", "elem"):
+        if kind not in ("node", "elem", "both"):
             raise ValueError(kind)
         self.kind = kind
         self.device = torch.device(device)
-        self._ws_raw = self._rp = self._cols = self._segs = None
+        self._tuned = isinstance(options, str)
+        if self._tuned and options != "tuned":
+            raise ValueError(options)
+        self._options_arg = None if self._tuned else make_options(options)
+        self._ws_raw = self._rp = self._cols = self._erp = self._ecols = self._segs = None
         self._seg_pinned = self._seg_event = None
         self.reset(meshes, conn_offs=conn_offs)
 
@@ -388,15 +532,24 @@ class BatchBuild:
         self.seg_host = seg
         self.totals = tot
         self.n_mesh = len(meshes)
-        ws, cap = _c_sz(0), _c_i64(0)
-        if self.kind == "node":
-            st = lib().mesh_batch_node_neighbors_query(self.n_mesh, tot["pairs"], tot["vert"], tot["max_vert"],
-                                                       ctypes.byref(ws), ctypes.byref(cap))
+        if self._tuned:
+            from . import autotune
+            self.options = make_options(autotune.batch_options_for(self.kind, tot["pairs"], tot["slots"]))
         else:
-            st = lib().mesh_batch_elem_neighbors_query(self.n_mesh, tot["slots"], tot["vert"], ctypes.byref(ws),
-                                                       ctypes.byref(cap))
-        if st != Status.OK:
-            raise MeshError(st, f"mesh_batch_{self.kind}_neighbors_query")
+            self.options = self._options_arg
+        ws, cap, cap2 = _c_sz(0), _c_i64(0), _c_i64(0)
+        o = ctypes.byref(self.options)
+        if self.kind == "node":
+            _check(lib().mesh_batch_node_neighbors_query(self.n_mesh, tot["pairs"], tot["slots"], tot["vert"],
+                                                         tot["max_vert"], o, ctypes.byref(ws), ctypes.byref(cap)),
+                   "mesh_batch_node_neighbors_query")
+        elif self.kind == "elem":
+            _check(lib().mesh_batch_elem_neighbors_query(self.n_mesh, tot["slots"], tot["vert"], o, ctypes.byref(ws),
+                                                         ctypes.byref(cap)), "mesh_batch_elem_neighbors_query")
+        else:
+            _check(lib().mesh_batch_neighbors_query(self.n_mesh, tot["pairs"], tot["slots"], tot["vert"],
+                                                    tot["max_vert"], o, ctypes.byref(ws), ctypes.byref(cap),
+                                                    ctypes.byref(cap2)), "mesh_batch_neighbors_query")
         self.ws_bytes = int(ws.value)
         self.cols_capacity = int(cap.value)
 
@@ -405,13 +558,17 @@ class BatchBuild:
                 return torch.empty(max(n, 1), dtype=dtype, device=self.device)
             return buf
 
-        self._ws_raw = grow(self._ws_raw, self.ws_bytes + 256, torch.uint8)
-        pad = (-self._ws_raw.data_ptr()) % 256
-        self.workspace = self._ws_raw[pad:pad + self.ws_bytes]
+        self._ws_raw, self.workspace = _workspace(torch, self.ws_bytes, self.device, self._ws_raw)
         self._rp = grow(self._rp, tot["vert"] + 1, torch.int32)
         self.row_ptr = self._rp[:tot["vert"] + 1]
         self._cols = grow(self._cols, self.cols_capacity, torch.int32)
         self.cols = self._cols
+        if self.kind == "both":
+            self.elem_capacity = int(cap2.value)
+            self._erp = grow(self._erp, tot["vert"] + 1, torch.int32)
+            self.elem_row_ptr = self._erp[:tot["vert"] + 1]
+            self._ecols = grow(self._ecols, self.elem_capacity, torch.int32)
+            self.elem_cols = self._ecols
         nbytes = 48 * len(meshes)
         self._segs = grow(self._segs, max(nbytes, 1), torch.uint8)
         if nbytes:
@@ -428,28 +585,30 @@ class BatchBuild:
                 self._seg_event.record()
         self.segs = self._segs
 
-    def launch(self, conn, stream=None, tuned=False):
-        import torch
-
-        if conn.device != self.device or conn.dtype != torch.int32 or not conn.is_contiguous():
-            raise ValueError("conn must be a contiguous int32 tensor on the build's device")
-        if tuned:
-            from . import autotune
-            autotune.apply_batch(self.kind, self.totals["pairs"] if self.kind == "node" else self.totals["slots"])
-        self._check_conn(conn)
+    def _args(self, conn):
         t = self.totals
         if self.kind == "node":
-            st = lib().mesh_batch_node_neighbors(_ptr(conn), _ptr(self.segs), self.n_mesh, t["pairs"], t["vert"],
-                                                 t["max_vert"], _ptr(self.row_ptr), _ptr(self.cols),
-                                                 self.cols_capacity, _ptr(self.workspace), self.ws_bytes,
-                                                 _stream_handle(stream, self.device))
+            a = [_ptr(conn), _ptr(self.segs), self.n_mesh, t["pairs"], t["slots"], t["vert"], t["max_vert"],
+                 _ptr(self.row_ptr), _ptr(self.cols), self.cols_capacity]
+        elif self.kind == "elem":
+            a = [_ptr(conn), _ptr(self.segs), self.n_mesh, t["slots"], t["vert"], _ptr(self.row_ptr),
+                 _ptr(self.cols), self.cols_capacity]
         else:
-            st = lib().mesh_batch_elem_neighbors(_ptr(conn), _ptr(self.segs), self.n_mesh, t["slots"], t["vert"],
-                                                 _ptr(self.row_ptr), _ptr(self.cols), self.cols_capacity,
-                                                 _ptr(self.workspace), self.ws_bytes,
-                                                 _stream_handle(stream, self.device))
-        if st != Status.OK:
-            raise MeshError(st, f"mesh_batch_{self.kind}_neighbors")
+            a = [_ptr(conn), _ptr(self.segs), self.n_mesh, t["pairs"], t["slots"], t["vert"], t["max_vert"],
+                 _ptr(self.row_ptr), _ptr(self.cols), self.cols_capacity, _ptr(self.elem_row_ptr),
+                 _ptr(self.elem_cols), self.elem_capacity]
+        return a + [ctypes.byref(self.options), _ptr(self.workspace), self.ws_bytes]
+
+    def _name(self, prefix="mesh_batch_"):
+        return prefix + ("neighbors" if self.kind == "both" else f"{self.kind}_neighbors")
+
+    def launch(self, conn, stream=None):
+        import torch
+
+        _check_conn(torch, conn, self.device)
+        self._check_conn(conn)
+        name = self._name()
+        _check(getattr(lib(), name)(*self._args(conn), _stream_handle(stream, self.device)), name)
 
     def _check_conn(self, conn):
         need = self.totals["ids"]
@@ -457,55 +616,46 @@ class BatchBuild:
             raise ValueError(f"conn has {conn.numel()} ids, the segments cover {need}")
 
     def check(self, stream=None):
-        st = lib().mesh_check(_ptr(self.workspace), _stream_handle(stream, self.device))
-        if st != Status.OK:
-            raise MeshError(st, "mesh_check")
+        _check(lib().mesh_check(_ptr(self.workspace), _stream_handle(stream, self.device)), "mesh_check")
 
     def result(self, stream=None):
         self.check(stream)
         nnz = int(self.row_ptr[-1].item())
+        if self.kind == "both":
+            enz = int(self.elem_row_ptr[-1].item())
+            return (self.row_ptr, self.cols[:nnz]), (self.elem_row_ptr, self.elem_cols[:enz])
         return self.row_ptr, self.cols[:nnz]
 
-    def capture(self, conn, tuned=False):
+    def capture(self, conn):
         """A Graph replaying ``launch(conn)`` for the current batch layout
         (totals fixed; conn and segment contents may change between replays
         as long as the totals stay the same)."""
         import torch
 
-        if conn.device != self.device or conn.dtype != torch.int32 or not conn.is_contiguous():
-            raise ValueError("conn must be a contiguous int32 tensor on the build's device")
-        if tuned:
-            from . import autotune
-            autotune.apply_batch(self.kind, self.totals["pairs"] if self.kind == "node" else self.totals["slots"])
+        _check_conn(torch, conn, self.device)
         self._check_conn(conn)
-        t = self.totals
         h = _c_p()
+        name = self._name("mesh_graph_batch_")
         with _device_guard(self.device):
-            if self.kind == "node":
-                st = lib().mesh_graph_batch_node_neighbors(_ptr(conn), _ptr(self.segs), self.n_mesh, t["pairs"],
-                                                           t["vert"], t["max_vert"], _ptr(self.row_ptr),
-                                                           _ptr(self.cols), self.cols_capacity, _ptr(self.workspace),
-                                                           self.ws_bytes, ctypes.byref(h))
-            else:
-                st = lib().mesh_graph_batch_elem_neighbors(_ptr(conn), _ptr(self.segs), self.n_mesh, t["slots"],
-                                                           t["vert"], _ptr(self.row_ptr), _ptr(self.cols),
-                                                           self.cols_capacity, _ptr(self.workspace), self.ws_bytes,
-                                                           ctypes.byref(h))
-        if st != Status.OK:
-            raise MeshError(st, f"mesh_graph_batch_{self.kind}_neighbors")
+            st = getattr(lib(), name)(*self._args(conn), ctypes.byref(h))
+        _check(st, name)
         # the graph holds the buffers themselves: a later reset() may replace them
-        return Graph(h, self.device, keep=(conn, self._ws_raw, self._rp, self._cols, self._segs))
+        return Graph(h, self.device, keep=(conn, self._ws_raw, self._rp, self._cols, self._erp, self._ecols,
+                                           self._segs))
 
-    def mesh_csr(self, m, row_ptr_host=None):
-        """(row_ptr, cols) of mesh m alone, as device tensors, after result()."""
+    def mesh_csr(self, m, row_ptr_host=None, relation="node"):
+        """(row_ptr, cols) of mesh m alone, as device tensors, after result()
+        (relation "elem" for the element CSR of a "both" build)."""
+        rp_all, cols_all = ((self.elem_row_ptr, self.elem_cols) if relation == "elem" and self.kind == "both"
+                            else (self.row_ptr, self.cols))
         seg = self.seg_host[m]
         v0, nv = int(seg["vert_off"]), int(seg["n_vert"])
-        rp = self.row_ptr[v0:v0 + nv + 1]
+        rp = rp_all[v0:v0 + nv + 1]
         if row_ptr_host is not None:
             a, b = int(row_ptr_host[v0]), int(row_ptr_host[v0 + nv])
         else:
             a, b = int(rp[0].item()), int(rp[-1].item())
-        return rp - a, self.cols[a:b]
+        return rp - a, cols_all[a:b]
 
 
 def concat_conn(conns):

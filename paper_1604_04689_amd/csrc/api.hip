@@ -1,7 +1,6 @@
 // C ABI of the one-ring neighbor library: argument checks, workspace sizing
 // and dispatch to the node and element pipelines.  Declared in
 // include/mesh_neighbors.h.
-#include <atomic>
 #include <climits>
 
 #include "../../include/mesh_neighbors.h"
@@ -68,12 +67,36 @@ hipError_t fill_regions(const FillRegion* r, int count, hipStream_t s) {
     return launch("fill", fill_set_kernel, dim3(grid), dim3(FILL_BLOCK), s, f);
 }
 
-static std::atomic<int> g_radix_shape{DEFAULT_RADIX_SHAPE};
-static std::atomic<int> g_node_sort{0};
+bool resolve_options(const mesh_options* o, Opts* out) {
+    Opts r;
+    if (o) {
+        if (o->node_sort < -1 || o->node_sort > NS_ELEM_ROWS) return false;
+        if (o->radix_shape < -1 || o->radix_shape >= N_RADIX_SHAPES) return false;
+        if (o->digit_bits != -1 && o->digit_bits != 8) return false;
+        if (o->node_sort >= 0) r.node_sort = o->node_sort;
+        if (o->radix_shape >= 0) r.shape = o->radix_shape;
+    }
+    *out = r;
+    return true;
+}
 
-int node_sort_mode() { return g_node_sort.load(std::memory_order_relaxed); }
+uint32_t bits_for_count(int64_t n) {
+    uint32_t b = 1;
+    while (b < 62 && ((int64_t)1 << b) < n) ++b;
+    return b;
+}
 
-int radix_shape() { return g_radix_shape.load(std::memory_order_relaxed); }
+uint32_t id_bits_for(int32_t n_vert) { return bits_for_count(n_vert); }
+
+PassPlan plan_passes(uint32_t bits, int) {
+    PassPlan pp;
+    pp.n_pass = (int)ceil_div(bits, RBITS);
+    for (int q = 0; q < pp.n_pass && q < 8; ++q) {
+        pp.shift[q] = (uint32_t)q * RBITS;
+        pp.width[q] = tmin<uint32_t>(RBITS, bits - (uint32_t)q * RBITS);
+    }
+    return pp;
+}
 
 }  // namespace mnb
 
@@ -87,9 +110,56 @@ static mesh_status check_sizes(int64_t n_elem, int32_t etype, int32_t n_vert) {
     return MESH_OK;
 }
 
+// Output pointers of one relation: row_ptr always, cols when the capacity is
+// positive.
+static bool outputs_ok(const int32_t* row_ptr, const int32_t* cols, int64_t cap) {
+    return row_ptr && cap >= 0 && (cap == 0 || cols);
+}
+
+static mesh_status workspace_ok(const void* ws, size_t bytes, size_t need) {
+    if (!ws) return MESH_ERR_INVALID_ARG;
+    return bytes < need || !aligned(ws) ? MESH_ERR_WORKSPACE : MESH_OK;
+}
+
+// Plans of one single-mesh call (both relations planned; node-only and
+// element-only calls use one of them).
+struct SinglePlans {
+    Opts o;
+    NodePlan node;
+    ElemPlan elem;
+};
+
+enum Relations { REL_NODE = 1, REL_ELEM = 2, REL_BOTH = 3 };
+
+static mesh_status plan_single(int64_t n_elem, int32_t etype, int32_t n_vert, const mesh_options* opts,
+                               int relations, bool node_internal_elem, SinglePlans* sp) {
+    mesh_status st = check_sizes(n_elem, etype, n_vert);
+    if (st != MESH_OK) return st;
+    if (!resolve_options(opts, &sp->o)) return MESH_ERR_INVALID_ARG;
+    // the relation's keys below 2^31: directed pairs for the node relation
+    // (the larger count), node slots for the element relation alone
+    if ((relations & REL_NODE) && n_elem > INT32_MAX / (2 * edges_per_elem(etype))) return MESH_ERR_OVERFLOW;
+    if (n_elem > INT32_MAX / nodes_per_elem(etype)) return MESH_ERR_OVERFLOW;
+    if ((relations & REL_NODE) && !plan_node(n_elem, etype, n_vert, sp->o, node_internal_elem, &sp->node))
+        return MESH_ERR_INVALID_ARG;
+    if (!plan_elem(n_elem, etype, n_vert, sp->o, &sp->elem)) return MESH_ERR_INVALID_ARG;
+    return MESH_OK;
+}
+
+static mesh_status hip_status(hipError_t e) { return e == hipSuccess ? MESH_OK : MESH_ERR_HIP; }
+
 extern "C" {
 
-int32_t mesh_abi_version(void) { return (1 << 16) | 0; }
+int32_t mesh_abi_version(void) { return (2 << 16) | 0; }
+
+mesh_options mesh_default_options(void) {
+    mesh_options o;
+    o.node_sort = -1;
+    o.radix_shape = -1;
+    o.digit_bits = -1;
+    for (int i = 0; i < 5; ++i) o.reserved[i] = 0;
+    return o;
+}
 
 const char* mesh_status_string(mesh_status s) {
     switch (s) {
@@ -106,105 +176,206 @@ const char* mesh_status_string(mesh_status s) {
     return "unknown status";
 }
 
-mesh_status mesh_node_neighbors_query(int64_t n_elem, int32_t etype, int32_t n_vert, size_t* workspace_bytes,
-                                      int64_t* cols_capacity) {
-    mesh_status st = check_sizes(n_elem, etype, n_vert);
-    if (st != MESH_OK) return st;
+// ---- single meshes ------------------------------------------------------------
+
+mesh_status mesh_node_neighbors_query(int64_t n_elem, int32_t etype, int32_t n_vert, const mesh_options* opts,
+                                      size_t* workspace_bytes, int64_t* cols_capacity) {
     if (!workspace_bytes || !cols_capacity) return MESH_ERR_INVALID_ARG;
-    if (n_elem > INT32_MAX / (2 * edges_per_elem(etype))) return MESH_ERR_OVERFLOW;
-    NodePlan p;
-    if (!plan_node(n_elem, etype, n_vert, &p)) return MESH_ERR_INVALID_ARG;
-    *workspace_bytes = p.total;
-    *cols_capacity = p.n_pairs;
+    SinglePlans sp;
+    mesh_status st = plan_single(n_elem, etype, n_vert, opts, REL_NODE, true, &sp);
+    if (st != MESH_OK) return st;
+    *workspace_bytes = sp.node.total;
+    *cols_capacity = sp.node.n_pairs;
     return MESH_OK;
 }
 
 mesh_status mesh_node_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
-                                int32_t* row_ptr, int32_t* cols, int64_t cols_capacity, void* workspace,
-                                size_t workspace_bytes, void* stream) {
-    size_t need;
-    int64_t cap_hint;
-    mesh_status st = mesh_node_neighbors_query(n_elem, etype, n_vert, &need, &cap_hint);
+                                int32_t* row_ptr, int32_t* cols, int64_t cols_capacity, const mesh_options* opts,
+                                void* workspace, size_t workspace_bytes, void* stream) {
+    SinglePlans sp;
+    mesh_status st = plan_single(n_elem, etype, n_vert, opts, REL_NODE, true, &sp);
     if (st != MESH_OK) return st;
-    if (!row_ptr || !workspace || (n_elem > 0 && !conn) || cols_capacity < 0) return MESH_ERR_INVALID_ARG;
-    if (cols_capacity > 0 && !cols) return MESH_ERR_INVALID_ARG;
-    if (workspace_bytes < need || !aligned(workspace)) return MESH_ERR_WORKSPACE;
-    NodePlan p;
-    plan_node(n_elem, etype, n_vert, &p);
-    hipError_t e = run_node(p, conn, row_ptr, cols, cols_capacity, workspace, (hipStream_t)stream);
-    return e == hipSuccess ? MESH_OK : MESH_ERR_HIP;
+    if ((n_elem > 0 && !conn) || !outputs_ok(row_ptr, cols, cols_capacity)) return MESH_ERR_INVALID_ARG;
+    st = workspace_ok(workspace, workspace_bytes, sp.node.total);
+    if (st != MESH_OK) return st;
+    return hip_status(run_node(sp.node, conn, row_ptr, cols, cols_capacity, workspace, (hipStream_t)stream));
 }
 
-mesh_status mesh_elem_neighbors_query(int64_t n_elem, int32_t etype, int32_t n_vert, size_t* workspace_bytes,
-                                      int64_t* cols_capacity) {
-    mesh_status st = check_sizes(n_elem, etype, n_vert);
-    if (st != MESH_OK) return st;
+mesh_status mesh_elem_neighbors_query(int64_t n_elem, int32_t etype, int32_t n_vert, const mesh_options* opts,
+                                      size_t* workspace_bytes, int64_t* cols_capacity) {
     if (!workspace_bytes || !cols_capacity) return MESH_ERR_INVALID_ARG;
-    if (n_elem > INT32_MAX / nodes_per_elem(etype)) return MESH_ERR_OVERFLOW;
-    ElemPlan p;
-    if (!plan_elem(n_elem, etype, n_vert, &p)) return MESH_ERR_INVALID_ARG;
-    *workspace_bytes = p.total;
-    *cols_capacity = p.n_slots;
+    SinglePlans sp;
+    mesh_status st = plan_single(n_elem, etype, n_vert, opts, REL_ELEM, true, &sp);
+    if (st != MESH_OK) return st;
+    *workspace_bytes = sp.elem.total;
+    *cols_capacity = sp.elem.n_slots;
     return MESH_OK;
 }
 
 mesh_status mesh_elem_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
-                                int32_t* row_ptr, int32_t* cols, int64_t cols_capacity, void* workspace,
-                                size_t workspace_bytes, void* stream) {
-    size_t need;
-    int64_t cap_hint;
-    mesh_status st = mesh_elem_neighbors_query(n_elem, etype, n_vert, &need, &cap_hint);
+                                int32_t* row_ptr, int32_t* cols, int64_t cols_capacity, const mesh_options* opts,
+                                void* workspace, size_t workspace_bytes, void* stream) {
+    SinglePlans sp;
+    mesh_status st = plan_single(n_elem, etype, n_vert, opts, REL_ELEM, true, &sp);
     if (st != MESH_OK) return st;
-    if (!row_ptr || !workspace || (n_elem > 0 && !conn) || cols_capacity < 0) return MESH_ERR_INVALID_ARG;
-    if (cols_capacity > 0 && !cols) return MESH_ERR_INVALID_ARG;
-    if (workspace_bytes < need || !aligned(workspace)) return MESH_ERR_WORKSPACE;
-    ElemPlan p;
-    plan_elem(n_elem, etype, n_vert, &p);
-    hipError_t e = run_elem(p, conn, row_ptr, cols, cols_capacity, workspace, (hipStream_t)stream);
-    return e == hipSuccess ? MESH_OK : MESH_ERR_HIP;
+    if ((n_elem > 0 && !conn) || !outputs_ok(row_ptr, cols, cols_capacity)) return MESH_ERR_INVALID_ARG;
+    st = workspace_ok(workspace, workspace_bytes, sp.elem.total);
+    if (st != MESH_OK) return st;
+    return hip_status(run_elem(sp.elem, conn, row_ptr, cols, cols_capacity, workspace, (hipStream_t)stream));
 }
 
-mesh_status mesh_batch_node_neighbors_query(int32_t n_mesh, int64_t total_pairs, int32_t total_vert,
-                                            int32_t max_vert, size_t* workspace_bytes, int64_t* cols_capacity) {
-    if (n_mesh < 0 || total_pairs < 0 || total_vert < 0 || max_vert < 0 || max_vert > total_vert)
+// Both relations: under ELEM_ROWS the node plan already holds the element
+// sort (the element CSR goes to the caller's outputs); otherwise the two
+// pipelines share one workspace, one after the other.
+static size_t both_bytes(const SinglePlans& sp) {
+    if (sp.node.mode == NS_ELEM_ROWS) return sp.node.total;
+    return sp.node.total > sp.elem.total ? sp.node.total : sp.elem.total;
+}
+
+mesh_status mesh_neighbors_query(int64_t n_elem, int32_t etype, int32_t n_vert, const mesh_options* opts,
+                                 size_t* workspace_bytes, int64_t* node_cols_capacity,
+                                 int64_t* elem_cols_capacity) {
+    if (!workspace_bytes || !node_cols_capacity || !elem_cols_capacity) return MESH_ERR_INVALID_ARG;
+    SinglePlans sp;
+    mesh_status st = plan_single(n_elem, etype, n_vert, opts, REL_BOTH, false, &sp);
+    if (st != MESH_OK) return st;
+    *workspace_bytes = both_bytes(sp);
+    *node_cols_capacity = sp.node.n_pairs;
+    *elem_cols_capacity = sp.elem.n_slots;
+    return MESH_OK;
+}
+
+mesh_status mesh_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
+                           int32_t* node_row_ptr, int32_t* node_cols, int64_t node_cols_capacity,
+                           int32_t* elem_row_ptr, int32_t* elem_cols, int64_t elem_cols_capacity,
+                           const mesh_options* opts, void* workspace, size_t workspace_bytes, void* stream) {
+    SinglePlans sp;
+    mesh_status st = plan_single(n_elem, etype, n_vert, opts, REL_BOTH, false, &sp);
+    if (st != MESH_OK) return st;
+    if ((n_elem > 0 && !conn) || !outputs_ok(node_row_ptr, node_cols, node_cols_capacity) ||
+        !outputs_ok(elem_row_ptr, elem_cols, elem_cols_capacity))
         return MESH_ERR_INVALID_ARG;
-    if (!workspace_bytes || !cols_capacity) return MESH_ERR_INVALID_ARG;
-    if (total_pairs > INT32_MAX) return MESH_ERR_OVERFLOW;
-    BatchPlan p;
-    if (!plan_batch(total_pairs, batch_hi_bits(total_vert) + batch_node_lo_bits(max_vert), total_vert, total_vert, &p))
-        return MESH_ERR_OVERFLOW;
+    st = workspace_ok(workspace, workspace_bytes, both_bytes(sp));
+    if (st != MESH_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (sp.node.mode == NS_ELEM_ROWS)
+        return hip_status(run_node(sp.node, conn, node_row_ptr, node_cols, node_cols_capacity, workspace, s, false,
+                                   elem_row_ptr, elem_cols, elem_cols_capacity));
+    hipError_t e = run_elem(sp.elem, conn, elem_row_ptr, elem_cols, elem_cols_capacity, workspace, s);
+    if (e == hipSuccess)
+        e = run_node(sp.node, conn, node_row_ptr, node_cols, node_cols_capacity, workspace, s, /*keep_err=*/true);
+    return hip_status(e);
+}
+
+// ---- meshes of several element types -------------------------------------------
+
+static mesh_status plan_mixed_call(int64_t n_elem, int64_t n_ids, int64_t n_pairs, int32_t n_vert,
+                                   const mesh_options* opts, MixedPlan* p) {
+    if (n_elem < 0 || n_ids < 0 || n_pairs < 0 || n_vert < 0) return MESH_ERR_INVALID_ARG;
+    Opts o;
+    if (!resolve_options(opts, &o) || o.node_sort != NS_ELEM_ROWS) return MESH_ERR_INVALID_ARG;
+    if (n_ids > INT32_MAX || n_pairs > INT32_MAX || n_elem > INT32_MAX) return MESH_ERR_OVERFLOW;
+    if (!plan_mixed(n_elem, n_ids, n_pairs, n_vert, o, p)) return MESH_ERR_INVALID_ARG;
+    return MESH_OK;
+}
+
+mesh_status mesh_mixed_neighbors_query(int64_t n_elem, int64_t n_ids, int64_t n_pairs, int32_t n_vert,
+                                       const mesh_options* opts, size_t* workspace_bytes,
+                                       int64_t* node_cols_capacity, int64_t* elem_cols_capacity) {
+    if (!workspace_bytes || !node_cols_capacity || !elem_cols_capacity) return MESH_ERR_INVALID_ARG;
+    MixedPlan p;
+    mesh_status st = plan_mixed_call(n_elem, n_ids, n_pairs, n_vert, opts, &p);
+    if (st != MESH_OK) return st;
     *workspace_bytes = p.total;
+    *node_cols_capacity = n_pairs;
+    *elem_cols_capacity = n_ids;
+    return MESH_OK;
+}
+
+mesh_status mesh_mixed_neighbors(const int32_t* conn, const int32_t* elem_off, const uint8_t* etypes,
+                                 int64_t n_elem, int64_t n_ids, int64_t n_pairs, int32_t n_vert,
+                                 int32_t* node_row_ptr, int32_t* node_cols, int64_t node_cols_capacity,
+                                 int32_t* elem_row_ptr, int32_t* elem_cols, int64_t elem_cols_capacity,
+                                 const mesh_options* opts, void* workspace, size_t workspace_bytes, void* stream) {
+    MixedPlan p;
+    mesh_status st = plan_mixed_call(n_elem, n_ids, n_pairs, n_vert, opts, &p);
+    if (st != MESH_OK) return st;
+    if ((n_elem > 0 && (!elem_off || !etypes)) || (n_ids > 0 && !conn) ||
+        !outputs_ok(node_row_ptr, node_cols, node_cols_capacity) ||
+        !outputs_ok(elem_row_ptr, elem_cols, elem_cols_capacity))
+        return MESH_ERR_INVALID_ARG;
+    st = workspace_ok(workspace, workspace_bytes, p.total);
+    if (st != MESH_OK) return st;
+    return hip_status(run_mixed(p, conn, elem_off, etypes, node_row_ptr, node_cols, node_cols_capacity, elem_row_ptr,
+                                elem_cols, elem_cols_capacity, workspace, (hipStream_t)stream));
+}
+
+// ---- batches ----------------------------------------------------------------------
+
+static mesh_status batch_sizes_ok(int32_t n_mesh, int64_t total_pairs, int64_t total_slots, int32_t total_vert,
+                                  int32_t max_vert) {
+    if (n_mesh < 0 || total_pairs < 0 || total_slots < 0 || total_vert < 0 || max_vert < 0 || max_vert > total_vert)
+        return MESH_ERR_INVALID_ARG;
+    if (total_pairs > INT32_MAX || total_slots > INT32_MAX) return MESH_ERR_OVERFLOW;
+    return MESH_OK;
+}
+
+struct BatchPlans {
+    Opts o;
+    BatchNodePlan node;
+    BatchPlan elem;
+};
+
+static mesh_status plan_batch_call(int32_t n_mesh, int64_t total_pairs, int64_t total_slots, int32_t total_vert,
+                                   int32_t max_vert, const mesh_options* opts, bool node_internal_elem,
+                                   BatchPlans* bp) {
+    mesh_status st = batch_sizes_ok(n_mesh, total_pairs, total_slots, total_vert, max_vert);
+    if (st != MESH_OK) return st;
+    if (!resolve_options(opts, &bp->o)) return MESH_ERR_INVALID_ARG;
+    if (!plan_batch_node(total_pairs, total_slots, total_vert, max_vert, bp->o, node_internal_elem, &bp->node))
+        return MESH_ERR_OVERFLOW;
+    if (!plan_batch_elem(total_slots, total_vert, bp->o, &bp->elem)) return MESH_ERR_OVERFLOW;
+    return MESH_OK;
+}
+
+mesh_status mesh_batch_node_neighbors_query(int32_t n_mesh, int64_t total_pairs, int64_t total_slots,
+                                            int32_t total_vert, int32_t max_vert, const mesh_options* opts,
+                                            size_t* workspace_bytes, int64_t* cols_capacity) {
+    if (!workspace_bytes || !cols_capacity) return MESH_ERR_INVALID_ARG;
+    BatchPlans bp;
+    mesh_status st = plan_batch_call(n_mesh, total_pairs, total_slots, total_vert, max_vert, opts, true, &bp);
+    if (st != MESH_OK) return st;
+    *workspace_bytes = bp.node.total;
     *cols_capacity = total_pairs;
     return MESH_OK;
 }
 
 mesh_status mesh_batch_node_neighbors(const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
-                                      int64_t total_pairs, int32_t total_vert, int32_t max_vert, int32_t* row_ptr,
-                                      int32_t* cols, int64_t cols_capacity, void* workspace, size_t workspace_bytes,
+                                      int64_t total_pairs, int64_t total_slots, int32_t total_vert, int32_t max_vert,
+                                      int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
+                                      const mesh_options* opts, void* workspace, size_t workspace_bytes,
                                       void* stream) {
-    size_t need;
-    int64_t cap_hint;
-    mesh_status st = mesh_batch_node_neighbors_query(n_mesh, total_pairs, total_vert, max_vert, &need, &cap_hint);
+    BatchPlans bp;
+    mesh_status st = plan_batch_call(n_mesh, total_pairs, total_slots, total_vert, max_vert, opts, true, &bp);
     if (st != MESH_OK) return st;
-    if (!row_ptr || !workspace || (total_pairs > 0 && (!conn || !segs)) || cols_capacity < 0)
+    if (((total_pairs > 0 || total_slots > 0) && (!conn || !segs)) || !outputs_ok(row_ptr, cols, cols_capacity))
         return MESH_ERR_INVALID_ARG;
-    if (cols_capacity > 0 && !cols) return MESH_ERR_INVALID_ARG;
-    if (workspace_bytes < need || !aligned(workspace)) return MESH_ERR_WORKSPACE;
-    const uint32_t lo = batch_node_lo_bits(max_vert);
-    BatchPlan p;
-    plan_batch(total_pairs, batch_hi_bits(total_vert) + lo, total_vert, total_vert, &p);
-    hipError_t e = run_batch_node(p, conn, segs, n_mesh, lo, total_vert, row_ptr, cols, cols_capacity, workspace,
-                                  (hipStream_t)stream);
-    return e == hipSuccess ? MESH_OK : MESH_ERR_HIP;
+    st = workspace_ok(workspace, workspace_bytes, bp.node.total);
+    if (st != MESH_OK) return st;
+    return hip_status(run_batch_node(bp.node, conn, segs, n_mesh, batch_node_lo_bits(max_vert), total_vert, row_ptr,
+                                     cols, cols_capacity, workspace, (hipStream_t)stream));
 }
 
 mesh_status mesh_batch_elem_neighbors_query(int32_t n_mesh, int64_t total_slots, int32_t total_vert,
-                                            size_t* workspace_bytes, int64_t* cols_capacity) {
-    if (n_mesh < 0 || total_slots < 0 || total_vert < 0) return MESH_ERR_INVALID_ARG;
+                                            const mesh_options* opts, size_t* workspace_bytes,
+                                            int64_t* cols_capacity) {
     if (!workspace_bytes || !cols_capacity) return MESH_ERR_INVALID_ARG;
-    if (total_slots > INT32_MAX) return MESH_ERR_OVERFLOW;
+    mesh_status st = batch_sizes_ok(n_mesh, 0, total_slots, total_vert, 0);
+    if (st != MESH_OK) return st;
+    Opts o;
+    if (!resolve_options(opts, &o)) return MESH_ERR_INVALID_ARG;
     BatchPlan p;
-    if (!plan_batch(total_slots, batch_hi_bits(total_vert), 0, total_vert, &p)) return MESH_ERR_OVERFLOW;
+    if (!plan_batch_elem(total_slots, total_vert, o, &p)) return MESH_ERR_OVERFLOW;
     *workspace_bytes = p.total;
     *cols_capacity = total_slots;
     return MESH_OK;
@@ -212,21 +383,70 @@ mesh_status mesh_batch_elem_neighbors_query(int32_t n_mesh, int64_t total_slots,
 
 mesh_status mesh_batch_elem_neighbors(const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
                                       int64_t total_slots, int32_t total_vert, int32_t* row_ptr, int32_t* cols,
-                                      int64_t cols_capacity, void* workspace, size_t workspace_bytes, void* stream) {
-    size_t need;
-    int64_t cap_hint;
-    mesh_status st = mesh_batch_elem_neighbors_query(n_mesh, total_slots, total_vert, &need, &cap_hint);
+                                      int64_t cols_capacity, const mesh_options* opts, void* workspace,
+                                      size_t workspace_bytes, void* stream) {
+    mesh_status st = batch_sizes_ok(n_mesh, 0, total_slots, total_vert, 0);
     if (st != MESH_OK) return st;
-    if (!row_ptr || !workspace || (total_slots > 0 && (!conn || !segs)) || cols_capacity < 0)
-        return MESH_ERR_INVALID_ARG;
-    if (cols_capacity > 0 && !cols) return MESH_ERR_INVALID_ARG;
-    if (workspace_bytes < need || !aligned(workspace)) return MESH_ERR_WORKSPACE;
+    Opts o;
+    if (!resolve_options(opts, &o)) return MESH_ERR_INVALID_ARG;
     BatchPlan p;
-    plan_batch(total_slots, batch_hi_bits(total_vert), 0, total_vert, &p);
-    hipError_t e = run_batch_elem(p, conn, segs, n_mesh, total_vert, row_ptr, cols, cols_capacity, workspace,
-                                  (hipStream_t)stream);
-    return e == hipSuccess ? MESH_OK : MESH_ERR_HIP;
+    if (!plan_batch_elem(total_slots, total_vert, o, &p)) return MESH_ERR_OVERFLOW;
+    if ((total_slots > 0 && (!conn || !segs)) || !outputs_ok(row_ptr, cols, cols_capacity))
+        return MESH_ERR_INVALID_ARG;
+    st = workspace_ok(workspace, workspace_bytes, p.total);
+    if (st != MESH_OK) return st;
+    return hip_status(run_batch_elem(p, conn, segs, n_mesh, total_vert, row_ptr, cols, cols_capacity, workspace,
+                                     (hipStream_t)stream));
 }
+
+static size_t batch_both_bytes(const BatchPlans& bp) {
+    if (bp.node.mode == NS_ELEM_ROWS) return bp.node.total;
+    return bp.node.total > bp.elem.total ? bp.node.total : bp.elem.total;
+}
+
+mesh_status mesh_batch_neighbors_query(int32_t n_mesh, int64_t total_pairs, int64_t total_slots,
+                                       int32_t total_vert, int32_t max_vert, const mesh_options* opts,
+                                       size_t* workspace_bytes, int64_t* node_cols_capacity,
+                                       int64_t* elem_cols_capacity) {
+    if (!workspace_bytes || !node_cols_capacity || !elem_cols_capacity) return MESH_ERR_INVALID_ARG;
+    BatchPlans bp;
+    mesh_status st = plan_batch_call(n_mesh, total_pairs, total_slots, total_vert, max_vert, opts, false, &bp);
+    if (st != MESH_OK) return st;
+    *workspace_bytes = batch_both_bytes(bp);
+    *node_cols_capacity = total_pairs;
+    *elem_cols_capacity = total_slots;
+    return MESH_OK;
+}
+
+mesh_status mesh_batch_neighbors(const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
+                                 int64_t total_pairs, int64_t total_slots, int32_t total_vert, int32_t max_vert,
+                                 int32_t* node_row_ptr, int32_t* node_cols, int64_t node_cols_capacity,
+                                 int32_t* elem_row_ptr, int32_t* elem_cols, int64_t elem_cols_capacity,
+                                 const mesh_options* opts, void* workspace, size_t workspace_bytes, void* stream) {
+    BatchPlans bp;
+    mesh_status st = plan_batch_call(n_mesh, total_pairs, total_slots, total_vert, max_vert, opts, false, &bp);
+    if (st != MESH_OK) return st;
+    if (((total_pairs > 0 || total_slots > 0) && (!conn || !segs)) ||
+        !outputs_ok(node_row_ptr, node_cols, node_cols_capacity) ||
+        !outputs_ok(elem_row_ptr, elem_cols, elem_cols_capacity))
+        return MESH_ERR_INVALID_ARG;
+    st = workspace_ok(workspace, workspace_bytes, batch_both_bytes(bp));
+    if (st != MESH_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t lo = batch_node_lo_bits(max_vert);
+    if (bp.node.mode == NS_ELEM_ROWS)
+        return hip_status(run_batch_node(bp.node, conn, segs, n_mesh, lo, total_vert, node_row_ptr, node_cols,
+                                         node_cols_capacity, workspace, s, false, elem_row_ptr, elem_cols,
+                                         elem_cols_capacity));
+    hipError_t e = run_batch_elem(bp.elem, conn, segs, n_mesh, total_vert, elem_row_ptr, elem_cols,
+                                  elem_cols_capacity, workspace, s);
+    if (e == hipSuccess)
+        e = run_batch_node(bp.node, conn, segs, n_mesh, lo, total_vert, node_row_ptr, node_cols, node_cols_capacity,
+                           workspace, s, /*keep_err=*/true);
+    return hip_status(e);
+}
+
+// ---- tuning information and diagnostics ---------------------------------------------
 
 int32_t mesh_radix_shape_count(void) { return N_RADIX_SHAPES; }
 
@@ -237,22 +457,20 @@ mesh_status mesh_radix_shape_info(int32_t shape, int32_t* block, int32_t* items)
     return MESH_OK;
 }
 
-mesh_status mesh_set_radix_shape(int32_t shape) {
-    if (shape < -1 || shape >= N_RADIX_SHAPES) return MESH_ERR_INVALID_ARG;
-    g_radix_shape.store(shape < 0 ? DEFAULT_RADIX_SHAPE : shape, std::memory_order_relaxed);
+mesh_status mesh_radix_launch_shape(int32_t shape, int32_t digit_bits, int64_t n_keys, int32_t* block,
+                                    int32_t* items, int32_t* bits) {
+    if (!block || !items || !bits || n_keys < 0) return MESH_ERR_INVALID_ARG;
+    mesh_options o = mesh_default_options();
+    o.radix_shape = shape;
+    o.digit_bits = digit_bits;
+    Opts r;
+    if (!resolve_options(&o, &r)) return MESH_ERR_INVALID_ARG;
+    const int eff = radix_effective_shape(r.shape, n_keys);
+    *block = RADIX_SHAPES[eff].block;
+    *items = RADIX_SHAPES[eff].items;
+    *bits = RBITS;
     return MESH_OK;
 }
-
-int32_t mesh_get_radix_shape(void) { return g_radix_shape.load(std::memory_order_relaxed); }
-
-mesh_status mesh_set_node_sort(int32_t mode) {
-    if (mode != MESH_NODE_SORT_FULL_KEY && mode != MESH_NODE_SORT_VERTEX_ROWS && mode != MESH_NODE_SORT_EDGE_ROWS)
-        return MESH_ERR_INVALID_ARG;
-    g_node_sort.store(mode, std::memory_order_relaxed);
-    return MESH_OK;
-}
-
-int32_t mesh_get_node_sort(void) { return g_node_sort.load(std::memory_order_relaxed); }
 
 mesh_status mesh_check(const void* workspace, void* stream) {
     if (!workspace) return MESH_ERR_INVALID_ARG;

@@ -16,6 +16,7 @@
 #include "launch.hpp"
 #include "radix.hpp"
 #include "edges.hpp"
+#include "erows.hpp"
 #include "rows.hpp"
 
 namespace mnb {
@@ -216,6 +217,7 @@ struct BatchNodeKeySrc {
     const int32_t* __restrict__ lut;  // over pair positions
     const TileRec* __restrict__ tiles;  // built for the tile size of the launch
     uint32_t lo_bits;
+    int32_t total_vert;
     static constexpr bool kSkipNone = false;
     static constexpr int PAIR_SCALE = CANON ? 2 : 1;  // pair positions per key
     static constexpr int TABLE_KIND = CANON ? 2 : 1;  // tile_table_kernel<KIND>
@@ -233,7 +235,9 @@ struct BatchNodeKeySrc {
     }
     __device__ __forceinline__ uint64_t key_of(int32_t x, int32_t y, int dir, int32_t n_vert, int32_t vert_off,
                                                bool* bad) const {
-        const bool ok = (uint32_t)x < (uint32_t)n_vert && (uint32_t)y < (uint32_t)n_vert;
+        // the mesh's vertex range must lie inside the batch's
+        const bool ok = (uint32_t)x < (uint32_t)n_vert && (uint32_t)y < (uint32_t)n_vert && vert_off >= 0 &&
+                        (int64_t)vert_off + n_vert <= (int64_t)total_vert;
         *bad = !ok;
         if (!ok || x == y) return KEY_NONE;
         int32_t u, w;
@@ -261,9 +265,7 @@ struct BatchNodeKeySrc {
         }
         uint32_t e;
         int pa, pb, dir;
-        if (et == TRI3) locate<TRI3>((uint32_t)loc, &e, &pa, &pb, &dir);
-        else if (et == TET4) locate<TET4>((uint32_t)loc, &e, &pa, &pb, &dir);
-        else locate<HEX8>((uint32_t)loc, &e, &pa, &pb, &dir);
+        with_type(et, [&](auto t) { locate<decltype(t)::value>((uint32_t)loc, &e, &pa, &pb, &dir); });
         const int32_t* el = conn + sg.conn_off + (int64_t)e * npe;
         return key_of(el[pa], el[pb], dir, sg.n_vert, sg.vert_off, bad);
     }
@@ -357,15 +359,16 @@ struct BatchNodeKeySrc {
         if (h.multi) {
             const int32_t* q = find_seg_record(s + h.n_vert, h.etype, i);
             const uint32_t loc = (uint32_t)(i - (int64_t)(((uint64_t)(uint32_t)q[7] << 32) | (uint32_t)q[6]));
-            if (q[0] == TRI3) return staged_key<TRI3>(ids, q[4], loc, q[1], q[2], bad);
-            if (q[0] == TET4) return staged_key<TET4>(ids, q[4], loc, q[1], q[2], bad);
-            return staged_key<HEX8>(ids, q[4], loc, q[1], q[2], bad);
+            return with_type(q[0], [&](auto t) {
+                return staged_key<decltype(t)::value>(ids, q[4], loc, q[1], q[2], bad);
+            });
         }
         const uint32_t loc = (uint32_t)(i - h.off);
         const int32_t e0 = (int32_t)h.e0;  // staged ids start at element e0
-        if (h.etype == TRI3) return staged_key<TRI3>(ids, -3 * e0, loc, h.n_vert, h.vert_off, bad);
-        if (h.etype == TET4) return staged_key<TET4>(ids, -4 * e0, loc, h.n_vert, h.vert_off, bad);
-        return staged_key<HEX8>(ids, -8 * e0, loc, h.n_vert, h.vert_off, bad);
+        return with_type(h.etype, [&](auto t) {
+            constexpr int ET = decltype(t)::value;
+            return staged_key<ET>(ids, -Elem<ET>::NPE * e0, loc, h.n_vert, h.vert_off, bad);
+        });
     }
     __device__ __forceinline__ uint64_t load_staged(const Header& h, int64_t i, int64_t tile_base,
                                                     const int32_t* s) const {
@@ -407,9 +410,7 @@ struct BatchNodeKeySrc {
         const TileRec r = tiles[t0 / TILE];
         if (r.etype < 0) return false;
         const int64_t hi = tmin<int64_t>(t0 + TILE, n);
-        if (r.etype == TRI3) elem_keys<TRI3, BLOCK>(r, t0, hi, tid, add, bad);
-        else if (r.etype == TET4) elem_keys<TET4, BLOCK>(r, t0, hi, tid, add, bad);
-        else elem_keys<HEX8, BLOCK>(r, t0, hi, tid, add, bad);
+        with_type(r.etype, [&](auto t) { elem_keys<decltype(t)::value, BLOCK>(r, t0, hi, tid, add, bad); });
         return true;
     }
 };
@@ -422,7 +423,13 @@ struct BatchElemPairSrc {
     const mesh_segment* __restrict__ segs;
     const int32_t* __restrict__ lut;
     const TileRec* __restrict__ tiles;  // built for the tile size of the launch
+    int32_t total_vert;
     static constexpr bool kSkipNone = true;
+    // the mesh's vertex range must lie inside the batch's (row_ptr entries
+    // are offered at vert_off + v)
+    __device__ __forceinline__ bool range_ok(int32_t vert_off, int32_t n_vert) const {
+        return vert_off >= 0 && n_vert >= 0 && (int64_t)vert_off + n_vert <= (int64_t)total_vert;
+    }
     static constexpr int TABLE_KIND = 0;  // tile_table_kernel<KIND>
 
     __device__ __forceinline__ uint64_t make(int64_t s, bool* bad) const {
@@ -430,7 +437,7 @@ struct BatchElemPairSrc {
         const mesh_segment& sg = segs[m];
         const int npe = nodes_per_elem(sg.etype);
         const int64_t loc = s - sg.slot_off;
-        if (npe == 0 || loc < 0 || loc >= npe * sg.n_elem) {
+        if (npe == 0 || loc < 0 || loc >= npe * sg.n_elem || !range_ok(sg.vert_off, sg.n_vert)) {
             *bad = true;
             return KEY_NONE;
         }
@@ -442,7 +449,7 @@ struct BatchElemPairSrc {
         }
         *bad = false;
         const uint32_t l32 = (uint32_t)loc;
-        const uint32_t e = npe == 3 ? l32 / 3u : npe == 4 ? l32 >> 2 : l32 >> 3;
+        const uint32_t e = slot_elem(l32, npe);
         const int j = (int)(l32 - e * (uint32_t)npe);
         const int32_t* first = el + (int64_t)e * npe;
         for (int jj = 0; jj < j; ++jj)
@@ -521,13 +528,13 @@ struct BatchElemPairSrc {
     }
     // key of local slot loc of a mesh whose element 0 is staged at rel
     // (negative when the staged ids start past it)
-    __device__ __forceinline__ static uint64_t staged_key(const int32_t* ids, int32_t rel, int npe, uint32_t loc,
-                                                          int32_t n_vert, int32_t vert_off, bool* bad) {
-        const uint32_t e = npe == 3 ? loc / 3u : npe == 4 ? loc >> 2 : loc >> 3;
+    __device__ __forceinline__ uint64_t staged_key(const int32_t* ids, int32_t rel, int npe, uint32_t loc,
+                                                   int32_t n_vert, int32_t vert_off, bool* bad) const {
+        const uint32_t e = slot_elem(loc, npe);
         const int j = (int)(loc - e * (uint32_t)npe);
         const int32_t* el = ids + (rel + (int32_t)e * npe);
         const int32_t v = el[j];
-        if ((uint32_t)v >= (uint32_t)n_vert) {
+        if ((uint32_t)v >= (uint32_t)n_vert || !range_ok(vert_off, n_vert)) {
             *bad = true;
             return KEY_NONE;
         }
@@ -577,7 +584,7 @@ struct BatchElemPairSrc {
                 const int64_t pos = pos0 + j;
                 if (pos < lo || pos >= hi) continue;
                 const int32_t v = id[j];
-                if ((uint32_t)v >= (uint32_t)r.n_vert) {
+                if ((uint32_t)v >= (uint32_t)r.n_vert || !range_ok(r.vert_off, r.n_vert)) {
                     bad = true;
                     continue;
                 }
@@ -594,9 +601,7 @@ struct BatchElemPairSrc {
         const TileRec r = tiles[t0 / TILE];
         if (r.etype < 0) return false;
         const int64_t hi = tmin<int64_t>(t0 + TILE, n);
-        if (r.etype == TRI3) elem_keys<3, BLOCK>(r, t0, hi, tid, add, bad);
-        else if (r.etype == TET4) elem_keys<4, BLOCK>(r, t0, hi, tid, add, bad);
-        else elem_keys<8, BLOCK>(r, t0, hi, tid, add, bad);
+        with_type(r.etype, [&](auto t) { elem_keys<Elem<decltype(t)::value>::NPE, BLOCK>(r, t0, hi, tid, add, bad); });
         return true;
     }
 };
@@ -666,24 +671,23 @@ __global__ __launch_bounds__(BH_BLOCK) void batch_hist_kernel(Src src, int64_t n
 // Host side
 // ---------------------------------------------------------------------------
 
-static uint32_t bits_for(int64_t n) {
-    uint32_t b = 1;
-    while (b < 31 && ((int64_t)1 << b) < n) ++b;
-    return b;
-}
-
-bool plan_batch(int64_t n_keys, uint32_t digit_bits, int32_t rows_vert, int32_t total_vert, BatchPlan* p) {
+bool plan_batch_sort(int64_t n_keys, uint32_t digit_bits, int32_t rows_vert, int32_t total_vert, const Opts& o,
+                     BatchPlan* p) {
     if (n_keys < 0 || digit_bits == 0 || digit_bits > 62 || rows_vert < 0 || total_vert < 0) return false;
+    *p = BatchPlan{};
+    p->opts = o;
     p->n_keys = n_keys;
-    p->n_pass = (int)ceil_div(digit_bits, RBITS);
-    if (p->n_pass > B_MAX_PASS) return false;
+    p->pp = plan_passes(digit_bits, o.digit_bits);
+    if (p->pp.n_pass > B_MAX_PASS) return false;
     p->digit_bits = digit_bits;
     p->n_tiles = ceil_div(n_keys, min_radix_tile());
     p->n_utiles = ceil_div(n_keys, UNIQ_TILE);
     p->rows_vert = rows_vert;
     p->long_cap = rows_vert > 0 ? n_keys / (ROW_SHORT + 1) + 1 : 0;
     const int64_t scan_tiles = rows_vert > 0 ? ceil_div((int64_t)rows_vert + 1, SCAN_TILE) : 0;
-    const bool two_bufs = p->n_pass > 1 || rows_vert > 0;  // the rows stage writes into the free key buffer
+    // the rows stages write into the key buffer the sort did not end in, and
+    // edge-rows hands the second look-back array to its transposed passes
+    const bool two = p->pp.n_pass > 1 || rows_vert > 0;
     size_t off = HEADER_BYTES;
     p->off_hist = off;
     off += align_up(B_MAX_PASS * RADIX * sizeof(uint32_t));
@@ -695,11 +699,11 @@ bool plan_batch(int64_t n_keys, uint32_t digit_bits, int32_t rows_vert, int32_t 
     off += align_up((size_t)p->n_tiles * RADIX * sizeof(uint64_t));
     p->zero_bytes = off;
     p->off_lb1 = off;
-    off += p->n_pass > 1 ? align_up((size_t)p->n_tiles * RADIX * sizeof(uint64_t)) : 0;
+    off += two ? align_up((size_t)p->n_tiles * RADIX * sizeof(uint64_t)) : 0;
     p->off_keys0 = off;
     off += align_up((size_t)n_keys * sizeof(uint64_t));
     p->off_keys1 = off;
-    off += two_bufs ? align_up((size_t)n_keys * sizeof(uint64_t)) : 0;
+    off += two ? align_up((size_t)n_keys * sizeof(uint64_t)) : 0;
     p->off_deg = off;
     off += align_up((size_t)rows_vert * sizeof(int32_t));
     p->off_src = off;
@@ -721,11 +725,43 @@ bool plan_batch(int64_t n_keys, uint32_t digit_bits, int32_t rows_vert, int32_t 
     return true;
 }
 
-uint32_t batch_node_lo_bits(int32_t max_vert) { return bits_for(max_vert); }
-uint32_t batch_hi_bits(int32_t total_vert) { return bits_for(total_vert); }
+uint32_t batch_node_lo_bits(int32_t max_vert) { return id_bits_for(max_vert); }
+
+bool plan_batch_elem(int64_t total_slots, int32_t total_vert, const Opts& o, BatchPlan* p, size_t) {
+    return plan_batch_sort(total_slots, id_bits_for(total_vert), 0, total_vert, o, p);
+}
+
+bool plan_batch_node(int64_t total_pairs, int64_t total_slots, int32_t total_vert, int32_t max_vert, const Opts& o,
+                     bool internal_elem, BatchNodePlan* p) {
+    *p = BatchNodePlan{};
+    p->mode = o.node_sort;
+    if (p->mode == NS_ELEM_ROWS) {
+        if (!plan_batch_elem(total_slots, total_vert, o, &p->bp)) return false;
+        size_t off = p->bp.total;
+        p->internal_elem = internal_elem;
+        if (internal_elem) {
+            p->off_erp = off;
+            off += align_up(((size_t)total_vert + 1) * sizeof(int32_t));
+            p->off_ecols = off;
+            off += align_up((size_t)total_slots * sizeof(int32_t));
+        }
+        off = plan_erows(total_slots, MAX_NPE - 1, total_vert, off, p->bp.off_keys0, p->bp.off_bmin - p->bp.off_keys0,
+                         &p->er);
+        p->total = off;
+        return true;
+    }
+    // full key: the global vertex bits above the local neighbour bits; the
+    // rows algorithms: the global vertex bits only, with room for KEY_NONE
+    const uint32_t bits = p->mode == NS_FULL_KEY ? id_bits_for(total_vert) + batch_node_lo_bits(max_vert)
+                                                 : bits_for_count((int64_t)total_vert + 1);
+    if (!plan_batch_sort(total_pairs, bits, p->mode == NS_FULL_KEY ? 0 : total_vert, total_vert, o, &p->bp))
+        return false;
+    p->total = p->bp.total;
+    return true;
+}
 
 template <class Src>
-static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, uint32_t shift0, uint32_t csr_lo_bits,
+static hipError_t batch_pipeline(const BatchPlan& p, Src src, uint32_t shift0, uint32_t csr_lo_bits,
                                  int32_t total_vert, int32_t* row_ptr, int32_t* cols, int64_t cols_cap, char* w,
                                  const mesh_segment* segs, int32_t n_mesh, int rows, hipStream_t s) {
     // rows: 0 unique + CSR, 1 vertex-rows stage, 2 edge-rows (src gives
@@ -737,14 +773,16 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
     uint64_t* ulb = (uint64_t*)(w + p.off_ulb);
     uint64_t* lb[2] = {(uint64_t*)(w + p.off_lb0), (uint64_t*)(w + p.off_lb1)};
     uint64_t* kb[2] = {(uint64_t*)(w + p.off_keys0), (uint64_t*)(w + p.off_keys1)};
-    const int shape = radix_shape();
+    const int shape = p.opts.shape;
     const bool node = !Src::kSkipNone;
+    const int n_pass = p.pp.n_pass;
 
-    const RadixShape sh = RADIX_SHAPES[shape >= 0 && shape < N_RADIX_SHAPES ? shape : DEFAULT_RADIX_SHAPE];
-    const int64_t tile = (int64_t)sh.block * sh.items;  // the tile launch_radix_pass uses for `shape`
+    // the tile size every pass of this call launches with: the tile table,
+    // the histogram tiling and the staged id capacity follow it
+    const int64_t tile = radix_tile_keys(shape, p.n_keys);
     const int64_t n_tiles = ceil_div(p.n_keys, tile);
     const int grid = (int)tmin<int64_t>(n_tiles, BH_GRID_MAX);
-    const uint32_t last_bits = p.digit_bits - (uint32_t)(p.n_pass - 1) * RBITS;
+    const uint32_t last_bits = p.pp.width[n_pass - 1];
     const dim3 lut_grid((unsigned)ceil_div(p.n_lut, LUT_BLOCK));
     const int64_t lut_n = rows == 2 ? 2 * p.n_keys : p.n_keys;  // the table is over pair positions
     hipError_t e =
@@ -761,29 +799,37 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
     if (e == hipSuccess) {
         const dim3 g(grid), b(BH_BLOCK);
         // at most 32 KB of counters: 8 copies up to 4 passes, 4 beyond
-        const uint32_t copies = p.n_pass <= 4 ? BH_COPIES : BH_COPIES / 2;
-        const size_t shm = (size_t)p.n_pass * RADIX * copies * sizeof(uint32_t);
-        if (tile == 6144)
-            e = launch_shm(hname, batch_hist_kernel<Src, 12>, g, b, shm, s, src, p.n_keys, shift0, p.n_pass, last_bits,
-                           copies, hist, count, err);
-        else if (tile == 12288)
-            e = launch_shm(hname, batch_hist_kernel<Src, 24>, g, b, shm, s, src, p.n_keys, shift0, p.n_pass, last_bits,
-                           copies, hist, count, err);
-        else if (tile == 4096)
-            e = launch_shm(hname, batch_hist_kernel<Src, 8>, g, b, shm, s, src, p.n_keys, shift0, p.n_pass, last_bits,
-                           copies, hist, count, err);
-        else
-            e = launch_shm(hname, batch_hist_kernel<Src, 16>, g, b, shm, s, src, p.n_keys, shift0, p.n_pass, last_bits,
-                           copies, hist, count, err);
+        const uint32_t copies = n_pass <= 4 ? BH_COPIES : BH_COPIES / 2;
+        const size_t shm = (size_t)n_pass * RADIX * copies * sizeof(uint32_t);
+        if (tile != (int64_t)BH_BLOCK * (tile / BH_BLOCK)) return hipErrorInvalidValue;
+        switch (tile / BH_BLOCK) {
+            case 12:
+                e = launch_shm(hname, batch_hist_kernel<Src, 12>, g, b, shm, s, src, p.n_keys, shift0, n_pass,
+                               last_bits, copies, hist, count, err);
+                break;
+            case 24:
+                e = launch_shm(hname, batch_hist_kernel<Src, 24>, g, b, shm, s, src, p.n_keys, shift0, n_pass,
+                               last_bits, copies, hist, count, err);
+                break;
+            case 8:
+                e = launch_shm(hname, batch_hist_kernel<Src, 8>, g, b, shm, s, src, p.n_keys, shift0, n_pass,
+                               last_bits, copies, hist, count, err);
+                break;
+            case 16:
+                e = launch_shm(hname, batch_hist_kernel<Src, 16>, g, b, shm, s, src, p.n_keys, shift0, n_pass,
+                               last_bits, copies, hist, count, err);
+                break;
+            default: return hipErrorInvalidValue;  // a tile size the table was not built for
+        }
     }
     // element relation: the last pass writes cols and offers row starts
     const CsrOut csr{cols, row_ptr, cols ? cols_cap : 0, 32u, 0xffffffffull};  // row_ptr set to INT32_MAX by the caller
-    for (int q = 0; q < p.n_pass && e == hipSuccess; ++q) {
-        const uint32_t shift = shift0 + (uint32_t)q * RBITS;
-        const uint32_t bits = tmin<uint32_t>(RBITS, p.digit_bits - (uint32_t)q * RBITS);
+    for (int q = 0; q < n_pass && e == hipSuccess; ++q) {
+        const uint32_t shift = shift0 + p.pp.shift[q];
+        const uint32_t bits = p.pp.width[q];
         uint64_t* out = kb[q & 1];
-        uint64_t* lb_next = q + 1 < p.n_pass || rows == 2 ? lb[(q + 1) & 1] : nullptr;
-        const bool last_elem = !node && q + 1 == p.n_pass;
+        uint64_t* lb_next = q + 1 < n_pass || rows == 2 ? lb[(q + 1) & 1] : nullptr;
+        const bool last_elem = !node && q + 1 == n_pass;
         if (q == 0 && last_elem)
             e = launch_radix_pass("batch_elem_radix_first", shape, src, csr, p.n_keys, shift, bits, hist, lb[0],
                                   lb_next, hdr + HDR_TICKET0, err, s);
@@ -803,10 +849,9 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
     if (e != hipSuccess) return e;
     if (!node)
         return launch_rowptr_fill("batch_elem_row_fill", row_ptr, total_vert, count, (int32_t*)(w + p.off_bmin), s);
-    (void)tag;
     if (rows) {
-        RowsStage r{kb[(p.n_pass - 1) & 1], p.n_keys, csr_lo_bits, total_vert, (int32_t*)(w + p.off_deg),
-                    (int64_t*)(w + p.off_src), (int32_t*)kb[p.n_pass & 1], (int64_t*)(w + p.off_long), p.long_cap,
+        RowsStage r{kb[(n_pass - 1) & 1], p.n_keys, csr_lo_bits, total_vert, (int32_t*)(w + p.off_deg),
+                    (int64_t*)(w + p.off_src), (int32_t*)kb[n_pass & 1], (int64_t*)(w + p.off_long), p.long_cap,
                     hdr + HDR_LONG_COUNT, ulb, hdr + HDR_TICKET0 + TK_BCSR, err};
         if (rows == 1) return launch_rows_stage(true, r, row_ptr, cols, cols_cap, s);
         // edge-rows: each vertex's higher neighbours and their scan, then the
@@ -815,60 +860,73 @@ static hipError_t batch_pipeline(const BatchPlan& p, const char* tag, Src src, u
         e = launch_rows_dedup(r, up_ptr, s, true);
         if (e != hipSuccess) return e;
         EdgeStage g{up_ptr, r.deg, r.src, r.temp, total_vert, csr_lo_bits, segs, n_mesh, p.n_keys,
-                    {kb[(p.n_pass - 1) & 1], kb[(p.n_pass - 1) & 1] + p.n_keys}, (int32_t*)kb[p.n_pass & 1] + p.n_keys,
-                    (uint32_t*)(w + p.off_hist2), {lb[0], lb[1]}, p.n_pass & 1, hdr + HDR_TICKET0 + 8, shape,
-                    p.n_pass, p.digit_bits, (int32_t*)(w + p.off_low), (int32_t*)(w + p.off_bmin), err};
+                    {kb[(n_pass - 1) & 1], kb[(n_pass - 1) & 1] + p.n_keys}, (int32_t*)kb[n_pass & 1] + p.n_keys,
+                    (uint32_t*)(w + p.off_hist2), {lb[0], lb[1]}, n_pass & 1, hdr + HDR_TICKET0 + 8, shape,
+                    p.pp, (int32_t*)(w + p.off_low), (int32_t*)(w + p.off_bmin), err};
         return launch_edge_stage(g, row_ptr, cols, cols_cap, s);
     }
-    return launch_unique_csr("batch_node_csr", kb[(p.n_pass - 1) & 1], p.n_keys, (const uint32_t*)nullptr,
+    return launch_unique_csr("batch_node_csr", kb[(n_pass - 1) & 1], p.n_keys, (const uint32_t*)nullptr,
                              csr_lo_bits, total_vert, cols, cols_cap, row_ptr, ulb, hdr + HDR_TICKET0 + TK_BCSR, err,
                              s);
 }
 
-hipError_t run_batch_node(const BatchPlan& p, const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
-                          uint32_t lo_bits, int32_t total_vert, int32_t* row_ptr, int32_t* cols, int64_t cols_cap,
-                          void* ws, hipStream_t s) {
-    const int mode = node_sort_mode();
-    const bool empty = p.n_keys == 0 || n_mesh == 0;
-    char* w = (char*)ws;
-    FillRegion fill[3] = {{ws, (int64_t)(p.zero_bytes / 4), 0u}};
-    int n_fill = 1;
-    if (!empty && mode != 0) fill[n_fill++] = {w + p.off_deg, total_vert, 0u};
-    if (!empty && mode == 2) fill[n_fill++] = {w + p.off_low, (int64_t)total_vert + 1, (uint32_t)INT32_MAX};
-    hipError_t e = fill_regions(fill, n_fill, s);
-    if (e != hipSuccess) return e;
-    if (empty) return fill_i32(row_ptr, (int64_t)total_vert + 1, 0, s);
-    const int32_t* lut = (const int32_t*)((char*)ws + p.off_lut);
-    const TileRec* tiles = (const TileRec*)((char*)ws + p.off_tiles);
-    if (mode != 0) {
-        // vertex-rows and edge-rows: radix passes over the global-vertex bits
-        // only (the all-ones value stays free for KEY_NONE), then per-row dedup
-        BatchPlan q = p;
-        q.digit_bits = bits_for((int64_t)total_vert + 1);
-        q.n_pass = (int)ceil_div(q.digit_bits, RBITS);
-        if (mode == 1)
-            return batch_pipeline(q, "node", BatchNodePairSrc{conn, segs, lut, tiles, lo_bits}, lo_bits, lo_bits,
-                                  total_vert, row_ptr, cols, cols_cap, (char*)ws, segs, n_mesh, 1, s);
-        q.n_keys = p.n_keys / 2;  // one canonical key per edge
-        return batch_pipeline(q, "node", BatchEdgeSrc{conn, segs, lut, tiles, lo_bits}, lo_bits, lo_bits, total_vert,
-                              row_ptr, cols, cols_cap, (char*)ws, segs, n_mesh, 2, s);
-    }
-    return batch_pipeline(p, "node", BatchNodePairSrc{conn, segs, lut, tiles, lo_bits}, 0u, lo_bits, total_vert, row_ptr,
-                          cols, cols_cap, (char*)ws, segs, n_mesh, 0, s);
-}
-
 hipError_t run_batch_elem(const BatchPlan& p, const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
                           int32_t total_vert, int32_t* row_ptr, int32_t* cols, int64_t cols_cap, void* ws,
-                          hipStream_t s) {
+                          hipStream_t s, bool keep_err, const FillRegion* extra) {
     const bool empty = p.n_keys == 0 || n_mesh == 0;
-    const FillRegion fill[2] = {{ws, (int64_t)(p.zero_bytes / 4), 0u},
-                                {row_ptr, (int64_t)total_vert + 1, empty ? 0u : (uint32_t)INT32_MAX}};
-    hipError_t e = fill_regions(fill, 2, s);
+    FillRegion fill[3] = {header_fill(ws, p.zero_bytes, keep_err),
+                          {row_ptr, (int64_t)total_vert + 1, empty ? 0u : (uint32_t)INT32_MAX}};
+    int n_fill = 2;
+    if (extra) fill[n_fill++] = *extra;
+    hipError_t e = fill_regions(fill, n_fill, s);
     if (e != hipSuccess || empty) return e;
     const int32_t* lut = (const int32_t*)((char*)ws + p.off_lut);
     const TileRec* tiles = (const TileRec*)((char*)ws + p.off_tiles);
-    return batch_pipeline(p, "elem", BatchElemPairSrc{conn, segs, lut, tiles}, 32u, 32u, total_vert, row_ptr, cols,
-                          cols_cap, (char*)ws, segs, n_mesh, 0, s);
+    return batch_pipeline(p, BatchElemPairSrc{conn, segs, lut, tiles, total_vert}, 32u, 32u, total_vert, row_ptr,
+                          cols, cols_cap, (char*)ws, segs, n_mesh, 0, s);
+}
+
+hipError_t run_batch_node(const BatchNodePlan& bn, const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
+                          uint32_t lo_bits, int32_t total_vert, int32_t* row_ptr, int32_t* cols, int64_t cols_cap,
+                          void* ws, hipStream_t s, bool keep_err, const int32_t* elem_row_ptr,
+                          const int32_t* elem_cols, int64_t elem_cap) {
+    const BatchPlan& p = bn.bp;
+    const int mode = bn.mode;
+    char* w = (char*)ws;
+    if (mode == NS_ELEM_ROWS) {
+        int32_t* erp = bn.internal_elem ? (int32_t*)(w + bn.off_erp) : const_cast<int32_t*>(elem_row_ptr);
+        int32_t* ecols = bn.internal_elem ? (int32_t*)(w + bn.off_ecols) : const_cast<int32_t*>(elem_cols);
+        const int64_t ecap = bn.internal_elem ? p.n_keys : elem_cap;
+        const FillRegion extra{w + bn.er.off_lb, (int64_t)bn.er.n_tiles * 2, 0u};
+        hipError_t e = run_batch_elem(p, conn, segs, n_mesh, total_vert, erp, ecols, ecap, ws, s, keep_err, &extra);
+        if (e != hipSuccess) return e;
+        if (p.n_keys == 0 || n_mesh == 0) return fill_i32(row_ptr, (int64_t)total_vert + 1, 0, s);
+        uint32_t* hdr = (uint32_t*)w;
+        const ErowsBufs b = erows_bufs(bn.er, w, hdr + HDR_ERR, hdr + HDR_TICKET0 + TK_EROWS);
+        return launch_erows("batch_node", BatchRows{conn, segs, n_mesh}, erp, ecols, ecap, total_vert, p.n_keys,
+                            row_ptr, cols, cols_cap, b, s);
+    }
+    const bool empty = p.n_keys == 0 || n_mesh == 0;
+    FillRegion fill[3] = {header_fill(ws, p.zero_bytes, keep_err)};
+    int n_fill = 1;
+    if (!empty && mode != NS_FULL_KEY) fill[n_fill++] = {w + p.off_deg, total_vert, 0u};
+    if (!empty && mode == NS_EDGE_ROWS) fill[n_fill++] = {w + p.off_low, (int64_t)total_vert + 1, (uint32_t)INT32_MAX};
+    hipError_t e = fill_regions(fill, n_fill, s);
+    if (e != hipSuccess) return e;
+    if (empty) return fill_i32(row_ptr, (int64_t)total_vert + 1, 0, s);
+    const int32_t* lut = (const int32_t*)(w + p.off_lut);
+    const TileRec* tiles = (const TileRec*)(w + p.off_tiles);
+    if (mode == NS_VERTEX_ROWS)
+        return batch_pipeline(p, BatchNodePairSrc{conn, segs, lut, tiles, lo_bits, total_vert}, lo_bits, lo_bits,
+                              total_vert, row_ptr, cols, cols_cap, w, segs, n_mesh, 1, s);
+    if (mode == NS_EDGE_ROWS) {
+        BatchPlan q = p;
+        q.n_keys = p.n_keys / 2;  // one canonical key per edge (the plan is sized for the pairs)
+        return batch_pipeline(q, BatchEdgeSrc{conn, segs, lut, tiles, lo_bits, total_vert}, lo_bits, lo_bits,
+                              total_vert, row_ptr, cols, cols_cap, w, segs, n_mesh, 2, s);
+    }
+    return batch_pipeline(p, BatchNodePairSrc{conn, segs, lut, tiles, lo_bits, total_vert}, 0u, lo_bits, total_vert,
+                          row_ptr, cols, cols_cap, w, segs, n_mesh, 0, s);
 }
 
 }  // namespace mnb

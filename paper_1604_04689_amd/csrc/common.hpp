@@ -200,4 +200,9 @@ __host__ __device__ constexpr T tmin(T a, T b) {
     return a < b ? a : b;
 }
 
+template <typename T>
+__host__ __device__ constexpr T tmax(T a, T b) {
+    return a < b ? b : a;
+}
+
 }  // namespace mnb

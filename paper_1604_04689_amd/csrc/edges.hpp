@@ -18,6 +18,7 @@
 #include "common.hpp"
 #include "launch.hpp"
 #include "csr.hpp"
+#include "internal.hpp"
 #include "radix.hpp"
 
 namespace mnb {
@@ -183,8 +184,8 @@ struct EdgeStage {
     uint64_t* lb[2];
     int l0;
     uint32_t* tickets;
-    int shape, n_pass;
-    uint32_t hi_bits;
+    int shape;
+    PassPlan pp;  // passes over the vertex bits of the transposed keys
     int32_t* low_ptr;
     int32_t* block_min;
     uint32_t* err;
@@ -195,7 +196,8 @@ static inline hipError_t launch_edge_stage(const EdgeStage& g, int32_t* row_ptr,
     const bool batch = g.segs != nullptr;
     const int32_t* E = g.up_ptr + g.n_vert;
     const unsigned vgrid = (unsigned)ceil_div((int64_t)g.n_vert, EDGE_BLOCK);
-    const uint32_t last_bits = g.hi_bits - (uint32_t)(g.n_pass - 1) * RBITS;
+    const int n_pass = g.pp.n_pass;
+    const uint32_t last_bits = g.pp.width[n_pass - 1];
     hipError_t e =
         batch ? launch("batch_node_edge_transpose", edge_transpose_kernel<true>, dim3(vgrid), dim3(EDGE_BLOCK), s,
                        g.up_ptr, g.deg, g.src, g.temp, g.n_vert, g.b, g.segs, g.n_mesh, g.keys[0], g.up_cols)
@@ -204,17 +206,17 @@ static inline hipError_t launch_edge_stage(const EdgeStage& g, int32_t* row_ptr,
     if (e == hipSuccess)
         e = launch(batch ? "batch_node_edge_hist" : "node_edge_hist", key_hist_kernel,
                    dim3((unsigned)tmin<int64_t>(ceil_div(g.n_edges, KH_BLOCK), KH_GRID_MAX)), dim3(KH_BLOCK), s,
-                   (const uint64_t*)g.keys[0], E, g.b, g.n_pass, last_bits, g.hist2);
+                   (const uint64_t*)g.keys[0], E, g.b, n_pass, last_bits, g.hist2);
     // the last pass writes the lower neighbours (low bits) and offers the
     // start of each vertex's group
     const CsrOut low{g.temp, g.low_ptr, g.n_edges, g.b, (1ull << g.b) - 1};
     const char* rname = batch ? "batch_node_edge_radix" : "node_edge_radix";
-    for (int q = 0; q < g.n_pass && e == hipSuccess; ++q) {
-        const uint32_t shift = g.b + (uint32_t)q * RBITS;
-        const uint32_t bits = tmin<uint32_t>(RBITS, g.hi_bits - (uint32_t)q * RBITS);
+    for (int q = 0; q < n_pass && e == hipSuccess; ++q) {
+        const uint32_t shift = g.b + g.pp.shift[q];
+        const uint32_t bits = g.pp.width[q];
         const int l = g.l0 ^ (q & 1);  // look-back array, cleared by the previous pass
         const CountedKeySrc src{g.keys[q & 1], (const uint32_t*)E};
-        if (q + 1 < g.n_pass)
+        if (q + 1 < n_pass)
             e = launch_radix_pass(rname, g.shape, src, g.keys[(q + 1) & 1], g.n_edges, shift, bits,
                                   g.hist2 + q * RADIX, g.lb[l], g.lb[l ^ 1], g.tickets + q, g.err, s);
         else

@@ -4,180 +4,37 @@
 // sorts the pairs by node.  Here each pair is the 64-bit key (v << 32) | e,
 // generated straight from the connectivity by the first pass, and the keys
 // are sorted by the bits of v only: a stable LSD radix sort over those bits,
-// i.e. one counting sort per 8-bit digit of the vertex id.  Pairs enter in
-// element order and every pass is stable, so each vertex's elements come out
+// i.e. one counting sort per digit of the vertex id.  Pairs enter in element
+// order and every pass is stable, so each vertex's elements come out
 // ascending without a per-row sort.  A repeated id inside an element (a
-// degenerate element) yields its pair once.  The CSR pass then writes
-// cols = e and the row starts.
+// degenerate element) yields its pair once.  The last pass writes cols = e
+// and offers each row start to row_ptr with an atomic minimum; a suffix
+// minimum gives empty rows the next row's start.
 //
 // (A counting sort with one global atomic counter per vertex was measured
 // first: on this GPU each device-scope atomic is a memory-side transaction,
 // and the atomic count + scatter of a 25M-pair mesh took 3.5 ms.)
 //
-//   elem_hist        conn -> histograms of the vertex digits of every pass
-//   radix_pass x q   (v << 32 | e) keys, stable, by the digits of v
-//   unique_csr       sorted keys -> row_ptr, cols
-#include "common.hpp"
-#include "csr.hpp"
-#include "elements.hpp"
-#include "internal.hpp"
-#include "launch.hpp"
-#include "radix.hpp"
+//   elem_hist        conn -> histograms of the vertex digits of every pass,
+//                    and the number of pairs that take part
+//   radix_pass x q   (v << 32 | e) keys, stable, by the digits of v; the last
+//                    one writes cols and the row starts (CsrOut)
+//   rowptr_fill      row starts of empty rows
+#include "elem.hpp"
 
 namespace mnb {
-
-constexpr int HIST_BLOCK = 512;
-constexpr int HIST_GRID_MAX = 1024;
-constexpr int HIST_UNROLL = 4;
-constexpr int MAX_EPASS = 4;  // 31 vertex bits
-
-// Ticket slots in the workspace header.
-constexpr int TK_PASS0 = 0;  // passes 0..3
-
-// The element holding slot s contains vertex v = conn[s] for the first time
-// (set semantics for degenerate elements: a repeated id counts once).
-template <int NPE>
-__device__ __forceinline__ bool first_occurrence(const int32_t* __restrict__ conn, uint32_t e, int j, int32_t v) {
-    bool first = true;
-    const int32_t* el = conn + (size_t)e * NPE;
-#pragma unroll
-    for (int jj = 0; jj < NPE - 1; ++jj)
-        if (jj < j) first &= el[jj] != v;
-    return first;
-}
-
-// (vertex, element) pair of connectivity slot s as the key (v << 32) | e, or
-// KEY_NONE when the slot repeats an id of its element or is out of range.
-template <int ET>
-struct ElemPairSrc {
-    const int32_t* __restrict__ conn;
-    int32_t n_vert;
-    static constexpr bool kSkipNone = true;
-    static constexpr bool kStaged = true;
-    static constexpr int NPE = Elem<ET>::NPE;
-
-    // ids of the tile's whole elements to s[0 ..): at most TILE + 2 * NPE words
-    template <int BLOCK, int TILE>
-    __device__ __forceinline__ void stage(int64_t tile_base, int64_t n, int32_t* s, int tid) const {
-        constexpr int MAXC = TILE + 2 * NPE;
-        constexpr int PER = (MAXC + BLOCK - 1) / BLOCK;
-        static_assert(MAXC <= 2 * TILE, "staged ids fit the key staging area");
-        const uint32_t e0 = (uint32_t)tile_base / NPE;
-        const uint32_t e1 = ((uint32_t)tmin<int64_t>(tile_base + TILE, n) - 1u) / NPE;
-        const int cnt = (int)(e1 - e0 + 1u) * NPE;
-        const int32_t* src = conn + (size_t)e0 * NPE;
-        int32_t v[PER];
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int i = q * BLOCK + tid;
-            v[q] = i < cnt ? src[i] : 0;
-        }
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int i = q * BLOCK + tid;
-            if (i < cnt) s[i] = v[q];
-        }
-    }
-    struct Header {};
-    __device__ __forceinline__ bool staged(const int32_t*) const { return true; }
-    __device__ __forceinline__ Header header(const int32_t*) const { return {}; }
-    __device__ __forceinline__ uint64_t load_staged(Header, int64_t s, int64_t tile_base, const int32_t* st) const {
-        const uint32_t ss = (uint32_t)s;
-        const uint32_t e = ss / NPE;
-        const int32_t* el = st + (e - (uint32_t)tile_base / NPE) * NPE;
-        const int j = (int)(ss - e * NPE);
-        const int32_t v = el[j];
-        if ((uint32_t)v >= (uint32_t)n_vert) return KEY_NONE;
-        bool first = true;
-#pragma unroll
-        for (int jj = 0; jj < NPE - 1; ++jj)
-            if (jj < j) first &= el[jj] != v;
-        return first ? ((uint64_t)(uint32_t)v << 32) | (uint64_t)e : KEY_NONE;
-    }
-
-    __device__ __forceinline__ uint64_t load(int64_t s) const {
-        const int32_t v = conn[s];
-        if ((uint32_t)v >= (uint32_t)n_vert) return KEY_NONE;
-        const uint32_t ss = (uint32_t)s;  // slot indices stay below 2^31
-        const uint32_t e = ss / NPE;
-        const int j = (int)(ss - e * NPE);
-        if (!first_occurrence<NPE>(conn, e, j, v)) return KEY_NONE;
-        return ((uint64_t)(uint32_t)v << 32) | (uint64_t)e;
-    }
-};
-
-// Histograms of the 8-bit digits of v over the pairs that take part, and
-// their number.  A thread takes whole elements, HIST_UNROLL of them in
-// flight; a repeated id inside an element counts once.  Raises
-// ERR_INDEX_RANGE.
-template <int ET>
-__global__ __launch_bounds__(HIST_BLOCK) void elem_hist_kernel(const int32_t* __restrict__ conn, int64_t n_elem,
-                                                              int32_t n_vert, int n_pass, uint32_t last_bits,
-                                                              uint32_t* __restrict__ hist, uint32_t* pair_count,
-                                                              uint32_t* err) {
-    constexpr int NPE = Elem<ET>::NPE;
-    __shared__ uint32_t s_hist[MAX_EPASS * RADIX];
-    __shared__ uint32_t s_pairs;
-    const int tid = threadIdx.x;
-    if (tid == 0) s_pairs = 0;
-    for (int i = tid; i < n_pass * RADIX; i += HIST_BLOCK) s_hist[i] = 0;
-    __syncthreads();
-    bool bad = false;
-    uint32_t pairs = 0;
-    const int64_t stride = (int64_t)gridDim.x * HIST_BLOCK;
-    for (int64_t e0 = (int64_t)blockIdx.x * HIST_BLOCK + tid; e0 < n_elem; e0 += stride * HIST_UNROLL) {
-        int32_t id[HIST_UNROLL][NPE];
-#pragma unroll
-        for (int u = 0; u < HIST_UNROLL; ++u) {  // all loads in flight first
-            const int64_t e = e0 + u * stride;
-            if (e < n_elem) load_elem_ids<ET>(conn, e, id[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < HIST_UNROLL; ++u) {
-            if (e0 + u * stride >= n_elem) continue;
-#pragma unroll
-            for (int j = 0; j < NPE; ++j) {
-                const int32_t v = id[u][j];
-                bool take = (uint32_t)v < (uint32_t)n_vert;
-                bad |= !take;
-#pragma unroll
-                for (int jj = 0; jj < j; ++jj) take &= id[u][jj] != v;
-                if (!take) continue;
-                ++pairs;
-                for (int p = 0; p < n_pass; ++p) {
-                    const uint32_t mask = p == n_pass - 1 ? (1u << last_bits) - 1 : RADIX - 1;
-                    atomicAdd(&s_hist[p * RADIX + (((uint32_t)v >> (p * RBITS)) & mask)], 1u);
-                }
-            }
-        }
-    }
-    if (bad) set_error(err, ERR_INDEX_RANGE);
-    if (pairs) atomicAdd(&s_pairs, pairs);
-    __syncthreads();
-    if (tid == 0 && s_pairs) atomicAdd(pair_count, s_pairs);
-    for (int i = tid; i < n_pass * RADIX; i += HIST_BLOCK)
-        if (s_hist[i]) atomicAdd(&hist[i], s_hist[i]);
-}
 
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 
-static uint32_t id_bits_of(int32_t n_vert) {
-    uint32_t b = 1;
-    while (b < 31 && ((int64_t)1 << b) < (int64_t)n_vert) ++b;
-    return b;
-}
-
-bool plan_elem(int64_t n_elem, int32_t etype, int32_t n_vert, ElemPlan* p) {
-    const int npe = nodes_per_elem(etype);
-    if (npe == 0 || n_elem < 0 || n_vert < 0) return false;
-    p->n_elem = n_elem;
-    p->etype = etype;
+bool plan_elem_slots(int64_t n_slots, int32_t n_vert, const Opts& o, ElemPlan* p) {
+    if (n_slots < 0 || n_vert < 0) return false;
+    p->opts = o;
     p->n_vert = n_vert;
-    p->n_slots = (int64_t)npe * n_elem;
-    p->id_bits = id_bits_of(n_vert);
-    p->n_pass = (int)ceil_div(p->id_bits, RBITS);
+    p->n_slots = n_slots;
+    p->id_bits = id_bits_for(n_vert);
+    p->pp = plan_passes(p->id_bits, o.digit_bits);
     p->n_tiles = ceil_div(p->n_slots, min_radix_tile());
     size_t off = HEADER_BYTES;
     p->off_hist = off;
@@ -186,14 +43,24 @@ bool plan_elem(int64_t n_elem, int32_t etype, int32_t n_vert, ElemPlan* p) {
     off += align_up((size_t)p->n_tiles * RADIX * sizeof(uint64_t));
     p->zero_bytes = off;  // header, histograms, pass-0 look-back
     p->off_lb1 = off;
-    off += p->n_pass > 1 ? align_up((size_t)p->n_tiles * RADIX * sizeof(uint64_t)) : 0;
+    off += p->pp.n_pass > 1 ? align_up((size_t)p->n_tiles * RADIX * sizeof(uint64_t)) : 0;
     p->off_keys0 = off;
     off += align_up((size_t)p->n_slots * sizeof(uint64_t));
     p->off_keys1 = off;
-    off += p->n_pass > 1 ? align_up((size_t)p->n_slots * sizeof(uint64_t)) : 0;
+    off += p->pp.n_pass > 1 ? align_up((size_t)p->n_slots * sizeof(uint64_t)) : 0;
     p->off_bmin = off;
     off += align_up((size_t)ceil_div((int64_t)n_vert + 1, (int64_t)RF_TILE) * sizeof(int32_t));
     p->total = off;
+    return true;
+}
+
+bool plan_elem(int64_t n_elem, int32_t etype, int32_t n_vert, const Opts& o, ElemPlan* p, size_t) {
+    const int npe = nodes_per_elem(etype);
+    if (npe == 0 || n_elem < 0 || n_vert < 0) return false;
+    *p = ElemPlan{};
+    if (!plan_elem_slots((int64_t)npe * n_elem, n_vert, o, p)) return false;
+    p->n_elem = n_elem;
+    p->etype = etype;
     return true;
 }
 
@@ -201,54 +68,26 @@ template <int ET>
 static hipError_t elem_pipeline(const ElemPlan& p, const int32_t* conn, int32_t* row_ptr, int32_t* cols,
                                 int64_t cols_cap, char* w, hipStream_t s) {
     uint32_t* hdr = (uint32_t*)w;
-    uint32_t* err = hdr + HDR_ERR;
-    uint32_t* count = hdr + HDR_KEY_COUNT;
-    uint32_t* hist = (uint32_t*)(w + p.off_hist);
-    uint64_t* lb[2] = {(uint64_t*)(w + p.off_lb0), (uint64_t*)(w + p.off_lb1)};
-    uint64_t* kb[2] = {(uint64_t*)(w + p.off_keys0), (uint64_t*)(w + p.off_keys1)};
-    const int shape = radix_shape();
-
     const int grid = (int)tmin<int64_t>(ceil_div(p.n_elem, HIST_BLOCK), HIST_GRID_MAX);
-    const uint32_t last_bits = p.id_bits - (uint32_t)(p.n_pass - 1) * RBITS;
-    // the last pass (CsrOut) offers every row start: unset entries hold
-    // INT32_MAX (set by the caller)
-    hipError_t e = launch("elem_hist", elem_hist_kernel<ET>, dim3(grid), dim3(HIST_BLOCK), s, conn, p.n_elem, p.n_vert,
-                   p.n_pass, last_bits, hist, count, err);
-    const CsrOut csr{cols, row_ptr, cols ? cols_cap : 0, 32u, 0xffffffffull};
-    for (int q = 0; q < p.n_pass && e == hipSuccess; ++q) {
-        const uint32_t shift = 32 + (uint32_t)q * RBITS;
-        const uint32_t bits = tmin<uint32_t>(RBITS, p.id_bits - (uint32_t)q * RBITS);
-        const bool last = q + 1 == p.n_pass;
-        uint64_t* out = kb[q & 1];
-        uint64_t* lb_next = last ? nullptr : lb[(q + 1) & 1];
-        const ElemPairSrc<ET> first{conn, p.n_vert};
-        const CountedKeySrc later{kb[(q - 1) & 1], count};
-        uint32_t* ticket = hdr + HDR_TICKET0 + TK_PASS0 + q;
-        const uint32_t* hq = hist + q * RADIX;
-        if (q == 0 && last) e = launch_radix_pass("elem_radix_first", shape, first, csr, p.n_slots, shift, bits, hq,
-                                                  lb[0], lb_next, ticket, err, s);
-        else if (q == 0) e = launch_radix_pass("elem_radix_first", shape, first, out, p.n_slots, shift, bits, hq,
-                                               lb[0], lb_next, ticket, err, s);
-        else if (last) e = launch_radix_pass("elem_radix", shape, later, csr, p.n_slots, shift, bits, hq, lb[q & 1],
-                                             lb_next, ticket, err, s);
-        else e = launch_radix_pass("elem_radix", shape, later, out, p.n_slots, shift, bits, hq, lb[q & 1], lb_next,
-                                   ticket, err, s);
-    }
+    const uint32_t last_bits = p.pp.width[p.pp.n_pass - 1];
+    hipError_t e = launch("elem_hist", elem_hist_kernel<ET>, dim3(grid), dim3(HIST_BLOCK), s, conn, p.n_elem,
+                          p.n_vert, p.pp.n_pass, last_bits, (uint32_t*)(w + p.off_hist), hdr + HDR_KEY_COUNT,
+                          hdr + HDR_ERR);
     if (e != hipSuccess) return e;
-    return launch_rowptr_fill("elem_row_fill", row_ptr, p.n_vert, count, (int32_t*)(w + p.off_bmin), s);
+    return elem_passes(p, ElemPairSrc<ET>{conn, p.n_vert}, row_ptr, cols, cols_cap, w, s);
 }
 
 hipError_t run_elem(const ElemPlan& p, const int32_t* conn, int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
-                    void* ws, hipStream_t s) {
-    const FillRegion fill[2] = {{ws, (int64_t)(p.zero_bytes / 4), 0u},
-                                {row_ptr, (int64_t)p.n_vert + 1, p.n_slots == 0 ? 0u : (uint32_t)INT32_MAX}};
-    hipError_t e = fill_regions(fill, 2, s);
+                    void* ws, hipStream_t s, bool keep_err, const FillRegion* extra) {
+    FillRegion fill[3] = {header_fill(ws, p.zero_bytes, keep_err),
+                          {row_ptr, (int64_t)p.n_vert + 1, p.n_slots == 0 ? 0u : (uint32_t)INT32_MAX}};
+    int n_fill = 2;
+    if (extra) fill[n_fill++] = *extra;
+    hipError_t e = fill_regions(fill, n_fill, s);
     if (e != hipSuccess || p.n_slots == 0) return e;
-    switch (p.etype) {
-        case TRI3: return elem_pipeline<TRI3>(p, conn, row_ptr, cols, cols_capacity, (char*)ws, s);
-        case TET4: return elem_pipeline<TET4>(p, conn, row_ptr, cols, cols_capacity, (char*)ws, s);
-        default: return elem_pipeline<HEX8>(p, conn, row_ptr, cols, cols_capacity, (char*)ws, s);
-    }
+    return with_type(p.etype, [&](auto et) {
+        return elem_pipeline<decltype(et)::value>(p, conn, row_ptr, cols, cols_capacity, (char*)ws, s);
+    });
 }
 
 }  // namespace mnb

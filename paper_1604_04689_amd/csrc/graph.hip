@@ -57,40 +57,67 @@ mesh_status capture(mesh_graph* out, F&& call) {
 extern "C" {
 
 mesh_status mesh_graph_node_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
-                                      int32_t* row_ptr, int32_t* cols, int64_t cols_capacity, void* workspace,
-                                      size_t workspace_bytes, mesh_graph* graph) {
+                                      int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
+                                      const mesh_options* opts, void* workspace, size_t workspace_bytes,
+                                      mesh_graph* graph) {
     return capture(graph, [&](void* s) {
-        return mesh_node_neighbors(conn, n_elem, etype, n_vert, row_ptr, cols, cols_capacity, workspace,
+        return mesh_node_neighbors(conn, n_elem, etype, n_vert, row_ptr, cols, cols_capacity, opts, workspace,
                                    workspace_bytes, s);
     });
 }
 
 mesh_status mesh_graph_elem_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
-                                      int32_t* row_ptr, int32_t* cols, int64_t cols_capacity, void* workspace,
-                                      size_t workspace_bytes, mesh_graph* graph) {
+                                      int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
+                                      const mesh_options* opts, void* workspace, size_t workspace_bytes,
+                                      mesh_graph* graph) {
     return capture(graph, [&](void* s) {
-        return mesh_elem_neighbors(conn, n_elem, etype, n_vert, row_ptr, cols, cols_capacity, workspace,
+        return mesh_elem_neighbors(conn, n_elem, etype, n_vert, row_ptr, cols, cols_capacity, opts, workspace,
                                    workspace_bytes, s);
     });
 }
 
-mesh_status mesh_graph_batch_node_neighbors(const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
-                                            int64_t total_pairs, int32_t total_vert, int32_t max_vert,
-                                            int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
-                                            void* workspace, size_t workspace_bytes, mesh_graph* graph) {
+mesh_status mesh_graph_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
+                                 int32_t* node_row_ptr, int32_t* node_cols, int64_t node_cols_capacity,
+                                 int32_t* elem_row_ptr, int32_t* elem_cols, int64_t elem_cols_capacity,
+                                 const mesh_options* opts, void* workspace, size_t workspace_bytes,
+                                 mesh_graph* graph) {
     return capture(graph, [&](void* s) {
-        return mesh_batch_node_neighbors(conn, segs, n_mesh, total_pairs, total_vert, max_vert, row_ptr, cols,
-                                         cols_capacity, workspace, workspace_bytes, s);
+        return mesh_neighbors(conn, n_elem, etype, n_vert, node_row_ptr, node_cols, node_cols_capacity, elem_row_ptr,
+                              elem_cols, elem_cols_capacity, opts, workspace, workspace_bytes, s);
+    });
+}
+
+mesh_status mesh_graph_batch_node_neighbors(const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
+                                            int64_t total_pairs, int64_t total_slots, int32_t total_vert,
+                                            int32_t max_vert, int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
+                                            const mesh_options* opts, void* workspace, size_t workspace_bytes,
+                                            mesh_graph* graph) {
+    return capture(graph, [&](void* s) {
+        return mesh_batch_node_neighbors(conn, segs, n_mesh, total_pairs, total_slots, total_vert, max_vert, row_ptr,
+                                         cols, cols_capacity, opts, workspace, workspace_bytes, s);
     });
 }
 
 mesh_status mesh_graph_batch_elem_neighbors(const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
                                             int64_t total_slots, int32_t total_vert, int32_t* row_ptr,
-                                            int32_t* cols, int64_t cols_capacity, void* workspace,
-                                            size_t workspace_bytes, mesh_graph* graph) {
+                                            int32_t* cols, int64_t cols_capacity, const mesh_options* opts,
+                                            void* workspace, size_t workspace_bytes, mesh_graph* graph) {
     return capture(graph, [&](void* s) {
-        return mesh_batch_elem_neighbors(conn, segs, n_mesh, total_slots, total_vert, row_ptr, cols,
-                                         cols_capacity, workspace, workspace_bytes, s);
+        return mesh_batch_elem_neighbors(conn, segs, n_mesh, total_slots, total_vert, row_ptr, cols, cols_capacity,
+                                         opts, workspace, workspace_bytes, s);
+    });
+}
+
+mesh_status mesh_graph_batch_neighbors(const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
+                                       int64_t total_pairs, int64_t total_slots, int32_t total_vert, int32_t max_vert,
+                                       int32_t* node_row_ptr, int32_t* node_cols, int64_t node_cols_capacity,
+                                       int32_t* elem_row_ptr, int32_t* elem_cols, int64_t elem_cols_capacity,
+                                       const mesh_options* opts, void* workspace, size_t workspace_bytes,
+                                       mesh_graph* graph) {
+    return capture(graph, [&](void* s) {
+        return mesh_batch_neighbors(conn, segs, n_mesh, total_pairs, total_slots, total_vert, max_vert, node_row_ptr,
+                                    node_cols, node_cols_capacity, elem_row_ptr, elem_cols, elem_cols_capacity, opts,
+                                    workspace, workspace_bytes, s);
     });
 }
 

@@ -2,23 +2,29 @@
 //
 // The paper forms two integer pairs per triangle edge (both directions), sorts
 // the pairs by their first entry, and derives per vertex the count and first
-// index of its neighbors by segmented reduction and scan.  Here each directed
-// pair (u, w) is packed into one 64-bit key (u << b) | w, b = bits of a vertex
-// id, and the whole key is sorted, so rows come out ascending and a repeated
-// edge (shared by several elements) lands next to its copy; one pass then
-// drops repeats, writes cols and the row starts.
+// index of its neighbors by segmented reduction and scan.  Four algorithms
+// with identical output (mesh_node_sort):
 //
-//   node_hist      conn -> digit histograms of every radix pass
-//   radix_pass x p keys -> keys (stable, one 8-bit digit per pass, onesweep:
-//                  ranks within a tile, decoupled look-back across tiles); the
-//                  first pass generates the pair keys from conn itself
-//   unique_csr     keys -> cols, row_ptr
+//   FULL_KEY     each directed pair (u, w) packed into one 64-bit key
+//                (u << b) | w, b = bits of a vertex id, the whole key sorted
+//                (node_hist, radix_pass x p, the first pass generating the
+//                keys from conn), then unique_csr drops repeats and writes
+//                cols and the row starts;
+//   VERTEX_ROWS  the same keys sorted by u only, rows deduplicated in LDS
+//                (rows.hpp);
+//   EDGE_ROWS    each element edge once as (min << b) | max sorted by min,
+//                rows deduplicated, unique edges transposed and sorted by max,
+//                lower and higher neighbours merged (edges.hpp);
+//   ELEM_ROWS    the element relation (elem_path.hip), then each node row
+//                gathered from the elements of the vertex's element row and
+//                deduplicated in LDS (erows.hpp).
 #include "common.hpp"
 #include "elements.hpp"
 #include "internal.hpp"
 #include "launch.hpp"
 #include "csr.hpp"
 #include "edges.hpp"
+#include "erows.hpp"
 #include "radix.hpp"
 #include "rows.hpp"
 
@@ -194,70 +200,94 @@ __global__ __launch_bounds__(NH_BLOCK) void node_hist_kernel(const int32_t* __re
 // Host side
 // ---------------------------------------------------------------------------
 
-static uint32_t id_bits_for(int32_t n_vert) {
-    uint32_t b = 1;
-    while (b < 31 && ((int64_t)1 << b) < (int64_t)n_vert) ++b;
-    return b;
-}
-
-static uint32_t bits_for_count(int64_t n) {  // smallest b >= 1 with 2^b >= n
-    uint32_t b = 1;
-    while (b < 31 && ((int64_t)1 << b) < n) ++b;
-    return b;
-}
-
-bool plan_node(int64_t n_elem, int32_t etype, int32_t n_vert, NodePlan* p) {
+bool plan_node(int64_t n_elem, int32_t etype, int32_t n_vert, const Opts& o, bool internal_elem, NodePlan* p) {
     const int ne = edges_per_elem(etype);
     if (ne == 0 || n_elem < 0 || n_vert < 0) return false;
+    *p = NodePlan{};
+    p->opts = o;
+    p->mode = o.node_sort;
     p->n_elem = n_elem;
     p->etype = etype;
     p->n_vert = n_vert;
     p->n_pairs = 2 * (int64_t)ne * n_elem;
-    p->id_bits = id_bits_for(n_vert);
-    p->n_pass = (int)ceil_div(2 * p->id_bits, RBITS);
-    // vertex-rows mode sorts the high part only; its bits leave the all-ones
-    // value free for KEY_NONE so that no real key ties with it
-    p->hi_bits = bits_for_count((int64_t)n_vert + 1);
-    p->n_pass_rows = (int)ceil_div(p->hi_bits, RBITS);
-    p->n_tiles = ceil_div(p->n_pairs, min_radix_tile());  // look-back room for any tile shape
-    p->n_utiles = ceil_div(p->n_pairs, UNIQ_TILE);
-    p->long_cap = p->n_pairs / (ROW_SHORT + 1) + 1;
     p->n_edges = (int64_t)ne * n_elem;
+    p->id_bits = id_bits_for(n_vert);
+    if (p->mode == NS_ELEM_ROWS) {
+        // the element relation first (its own plan from offset 0, header
+        // included); its key buffers are dead once it has run, and hold the
+        // long rows' candidates when they are large enough
+        if (!plan_elem(n_elem, etype, n_vert, o, &p->ep)) return false;
+        size_t off = p->ep.total;
+        p->internal_elem = internal_elem;
+        if (internal_elem) {
+            p->off_erp = off;
+            off += align_up(((size_t)n_vert + 1) * sizeof(int32_t));
+            p->off_ecols = off;
+            off += align_up((size_t)p->ep.n_slots * sizeof(int32_t));
+        }
+        off = plan_erows(p->ep.n_slots, nodes_per_elem(etype) - 1, n_vert, off, p->ep.off_keys0,
+                         p->ep.off_bmin - p->ep.off_keys0, &p->er);
+        p->zero_bytes = p->ep.zero_bytes;
+        p->total = off;
+        return true;
+    }
+    const bool full = p->mode == NS_FULL_KEY, edges = p->mode == NS_EDGE_ROWS;
+    // full-key: passes over all 2b key bits; vertex-rows and edge-rows: over
+    // the bits of the high part (a vertex id) above the low b bits, one more
+    // than a vertex id needs when n_vert is a power of two, so that KEY_NONE
+    // (all ones, still taking part in these sorts) ties with no real vertex
+    p->sort_bits = full ? 2 * p->id_bits : bits_for_count((int64_t)n_vert + 1);
+    p->pp = plan_passes(p->sort_bits, o.digit_bits);
+    p->n_keys = edges ? p->n_edges : p->n_pairs;
+    p->n_tiles = ceil_div(p->n_keys, min_radix_tile());  // look-back room for any tile shape
+    p->n_utiles = ceil_div(p->n_pairs, UNIQ_TILE);
+    p->long_cap = p->n_keys / (ROW_SHORT + 1) + 1;
     size_t off = HEADER_BYTES;
     p->off_hist = off;
     off += align_up(MAX_PASS * RADIX * sizeof(uint32_t));
-    p->off_hist2 = off;
-    off += align_up(MAX_KH_PASS * RADIX * sizeof(uint32_t));
-    p->off_ulb = off;
-    off += align_up((size_t)tmin<int64_t>(p->n_utiles + ceil_div((int64_t)n_vert + 1, SCAN_TILE), INT64_MAX) *
-                    sizeof(uint64_t));
+    if (edges) {
+        p->off_hist2 = off;
+        off += align_up(MAX_KH_PASS * RADIX * sizeof(uint32_t));
+    }
+    p->off_ulb = off;  // unique/CSR look-back (full key) or the row-count scan's (rows)
+    off += align_up((size_t)(full ? p->n_utiles : ceil_div((int64_t)n_vert + 1, SCAN_TILE)) * sizeof(uint64_t));
     p->off_lb0 = off;
     off += align_up((size_t)p->n_tiles * RADIX * sizeof(uint64_t));
     p->zero_bytes = off;  // header, histograms, CSR/scan look-back, pass-0 look-back
     p->off_lb1 = off;
     off += align_up((size_t)p->n_tiles * RADIX * sizeof(uint64_t));
+    // key buffers: the sort ping-pongs n_keys keys.  Edge-rows then needs,
+    // in the buffer the sort ended in, room for the transposed edges'
+    // ping-pong (2 x n_edges keys); the other one holds the row values and
+    // the higher neighbours (2 x n_edges ints).
+    const size_t kb = align_up((size_t)p->n_keys * sizeof(uint64_t));
+    const bool sorted_in_1 = ((p->pp.n_pass - 1) & 1) != 0;
     p->off_keys0 = off;
-    off += align_up((size_t)p->n_pairs * sizeof(uint64_t));
+    off += edges && !sorted_in_1 ? 2 * kb : kb;
     p->off_keys1 = off;
-    off += align_up((size_t)p->n_pairs * sizeof(uint64_t));
-    p->off_deg = off;  // vertex-rows mode: distinct neighbors per vertex
-    off += align_up((size_t)n_vert * sizeof(int32_t));
-    p->off_src = off;  // vertex-rows mode: first key index of each row
-    off += align_up((size_t)n_vert * sizeof(int64_t));
-    p->off_long = off;
-    off += align_up((size_t)p->long_cap * sizeof(int64_t));
-    p->off_up = off;
-    off += align_up(((size_t)n_vert + 1) * sizeof(int32_t));
-    p->off_low = off;
-    off += align_up(((size_t)n_vert + 1) * sizeof(int32_t));
-    p->off_bmin = off;  // edge-rows mode: block minima of the lower-group fill
-    off += align_up((size_t)ceil_div((int64_t)n_vert + 1, (int64_t)RF_TILE) * sizeof(int32_t));
+    off += edges && sorted_in_1 ? 2 * kb : kb;
+    if (!full) {
+        p->off_deg = off;  // distinct neighbors per vertex
+        off += align_up((size_t)n_vert * sizeof(int32_t));
+        p->off_src = off;  // first key index of each row
+        off += align_up((size_t)n_vert * sizeof(int64_t));
+        p->off_long = off;
+        off += align_up((size_t)p->long_cap * sizeof(int64_t));
+    }
+    if (edges) {
+        p->off_up = off;
+        off += align_up(((size_t)n_vert + 1) * sizeof(int32_t));
+        p->off_low = off;
+        off += align_up(((size_t)n_vert + 1) * sizeof(int32_t));
+        p->off_bmin = off;  // block minima of the lower-group fill
+        off += align_up((size_t)ceil_div((int64_t)n_vert + 1, (int64_t)RF_TILE) * sizeof(int32_t));
+    }
     p->total = off;
     return true;
 }
 
 template <int ET>
-static hipError_t node_pipeline(const NodePlan& p, int mode, const int32_t* conn, int32_t* row_ptr, int32_t* cols,
+static hipError_t node_pipeline(const NodePlan& p, const int32_t* conn, int32_t* row_ptr, int32_t* cols,
                                 int64_t cols_capacity, char* w, hipStream_t s) {
     uint32_t* hdr = (uint32_t*)w;
     uint32_t* err = hdr + HDR_ERR;
@@ -266,18 +296,14 @@ static hipError_t node_pipeline(const NodePlan& p, int mode, const int32_t* conn
     uint64_t* ulb = (uint64_t*)(w + p.off_ulb);
     uint64_t* lb[2] = {(uint64_t*)(w + p.off_lb0), (uint64_t*)(w + p.off_lb1)};
     uint64_t* kb[2] = {(uint64_t*)(w + p.off_keys0), (uint64_t*)(w + p.off_keys1)};
-    const int shape = radix_shape();
-    const bool rows = mode == 1, edges = mode == 2;
-
-    // full-key mode: passes over all 2b key bits; vertex-rows and edge-rows
-    // modes: over the hi_bits above the low b bits.  Edge-rows sorts one
-    // canonical key per element edge instead of two directed pairs.
+    const int shape = p.opts.shape;
+    const bool rows = p.mode == NS_VERTEX_ROWS, edges = p.mode == NS_EDGE_ROWS;
+    const PassPlan& pp = p.pp;
+    const int n_pass = pp.n_pass;
     const uint32_t shift0 = rows || edges ? p.id_bits : 0;
-    const uint32_t sort_bits = rows || edges ? p.hi_bits : 2 * p.id_bits;
-    const int n_pass = rows || edges ? p.n_pass_rows : p.n_pass;
-    const int64_t n_keys = edges ? p.n_edges : p.n_pairs;
+    const int64_t n_keys = p.n_keys;
     const int grid = (int)tmin<int64_t>(ceil_div(p.n_elem, NH_BLOCK), NH_GRID_MAX);
-    const uint32_t last_bits = sort_bits - (uint32_t)(n_pass - 1) * RBITS;
+    const uint32_t last_bits = pp.width[n_pass - 1];
     // (the caller has cleared the row degrees and, for edge-rows, set the
     // lower-group starts to INT32_MAX, with the workspace header)
     hipError_t e = edges ? launch("node_hist", node_hist_kernel<ET, true>, dim3(grid), dim3(NH_BLOCK), s, conn, p.n_elem,
@@ -287,8 +313,8 @@ static hipError_t node_pipeline(const NodePlan& p, int mode, const int32_t* conn
     if (e != hipSuccess) return e;
     if ((rows || edges) && p.n_vert == 0) return fill_i32(row_ptr, 1, 0, s);  // every id is out of range
     for (int pass = 0; pass < n_pass && e == hipSuccess; ++pass) {
-        const uint32_t shift = shift0 + (uint32_t)pass * RBITS;
-        const uint32_t bits = tmin<uint32_t>(RBITS, sort_bits - (uint32_t)pass * RBITS);
+        const uint32_t shift = shift0 + pp.shift[pass];
+        const uint32_t bits = pp.width[pass];
         uint64_t* out = kb[pass & 1];
         // edge-rows: the last pass also clears the look-back slots of the
         // first pass over the transposed edges
@@ -320,31 +346,44 @@ static hipError_t node_pipeline(const NodePlan& p, int mode, const int32_t* conn
     e = launch_rows_dedup(r, up_ptr, s);
     if (e != hipSuccess) return e;
     // transposed edges (w << b) | v: ping-pong halves of the sorted buffer (free
-    // now); w alone after the row values in the other buffer
+    // now, sized for 2 x n_edges keys); w alone after the row values in the
+    // other buffer
     EdgeStage g{up_ptr, r.deg, r.src, r.temp, p.n_vert, p.id_bits, nullptr, 0, p.n_edges,
                 {kb[(n_pass - 1) & 1], kb[(n_pass - 1) & 1] + p.n_edges}, (int32_t*)kb[n_pass & 1] + p.n_edges,
-                (uint32_t*)(w + p.off_hist2), {lb[0], lb[1]}, n_pass & 1, tickets + 8, shape, n_pass, p.hi_bits,
+                (uint32_t*)(w + p.off_hist2), {lb[0], lb[1]}, n_pass & 1, tickets + 8, shape, pp,
                 low_ptr, (int32_t*)(w + p.off_bmin), err};
     e = launch_edge_stage(g, row_ptr, cols, cols_capacity, s);
     return e;
 }
 
 hipError_t run_node(const NodePlan& p, const int32_t* conn, int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
-                    void* ws, hipStream_t s) {
-    const int mode = node_sort_mode();
+                    void* ws, hipStream_t s, bool keep_err, const int32_t* elem_row_ptr, const int32_t* elem_cols,
+                    int64_t elem_cap) {
     char* w = (char*)ws;
-    FillRegion fill[3] = {{ws, (int64_t)(p.zero_bytes / 4), 0u}};
+    if (p.mode == NS_ELEM_ROWS) {
+        // the element relation into the caller's outputs, or the workspace
+        int32_t* erp = p.internal_elem ? (int32_t*)(w + p.off_erp) : const_cast<int32_t*>(elem_row_ptr);
+        int32_t* ecols = p.internal_elem ? (int32_t*)(w + p.off_ecols) : const_cast<int32_t*>(elem_cols);
+        const int64_t ecap = p.internal_elem ? p.ep.n_slots : elem_cap;
+        const FillRegion extra{w + p.er.off_lb, (int64_t)(p.er.n_tiles * 2), 0u};
+        hipError_t e = run_elem(p.ep, conn, erp, ecols, ecap, ws, s, keep_err, &extra);
+        if (e != hipSuccess) return e;
+        if (p.ep.n_slots == 0) return fill_i32(row_ptr, (int64_t)p.n_vert + 1, 0, s);
+        uint32_t* hdr = (uint32_t*)w;
+        return run_erows_uniform(p.etype, p.er, conn, p.n_elem, p.n_vert, erp, ecols, ecap, row_ptr, cols,
+                                 cols_capacity, w, hdr + HDR_ERR, hdr + HDR_TICKET0 + TK_EROWS, s);
+    }
+    const int mode = p.mode;
+    FillRegion fill[3] = {header_fill(ws, p.zero_bytes, keep_err)};
     int n_fill = 1;
-    if (p.n_pairs > 0 && mode != 0) fill[n_fill++] = {w + p.off_deg, p.n_vert, 0u};
-    if (p.n_pairs > 0 && mode == 2) fill[n_fill++] = {w + p.off_low, (int64_t)p.n_vert + 1, (uint32_t)INT32_MAX};
+    if (p.n_pairs > 0 && mode != NS_FULL_KEY) fill[n_fill++] = {w + p.off_deg, p.n_vert, 0u};
+    if (p.n_pairs > 0 && mode == NS_EDGE_ROWS) fill[n_fill++] = {w + p.off_low, (int64_t)p.n_vert + 1, (uint32_t)INT32_MAX};
     hipError_t e = fill_regions(fill, n_fill, s);
     if (e != hipSuccess) return e;
     if (p.n_pairs == 0) return fill_i32(row_ptr, (int64_t)p.n_vert + 1, 0, s);
-    switch (p.etype) {
-        case TRI3: return node_pipeline<TRI3>(p, mode, conn, row_ptr, cols, cols_capacity, w, s);
-        case TET4: return node_pipeline<TET4>(p, mode, conn, row_ptr, cols, cols_capacity, w, s);
-        default: return node_pipeline<HEX8>(p, mode, conn, row_ptr, cols, cols_capacity, w, s);
-    }
+    return with_type(p.etype, [&](auto et) {
+        return node_pipeline<decltype(et)::value>(p, conn, row_ptr, cols, cols_capacity, w, s);
+    });
 }
 
 }  // namespace mnb

@@ -222,11 +222,10 @@ void radix_pass_kernel(Src src, Out out, int64_t n, uint32_t shift, uint32_t bit
     // peers = valid lanes whose digit equals this lane's, kept as two 32-bit
     // halves: per digit bit, m is all ones where the bit is set, and a lane
     // keeps the voters that agree with it, peers &= ~(vote ^ m), one
-    // three-input bitwise instruction per half.  Every lane of a digit holds
-    // the same peers, so all of them read the wave's counter and store the
-    // same new value: no leader, no branch, and the items' rank chains can
-    // overlap.  (Invalid lanes carry a digit in range and store what their
-    // digit's valid lanes store, or the unchanged count.)
+    // three-input bitwise instruction per half.  The lowest lane of each
+    // digit group (the leader) reads and bumps the wave's counter for that
+    // digit; the others take the old count from it by a shuffle and add their
+    // rank among the group.
     const uint64_t lt_mask = (1ull << lane) - 1;
     // ranks are below TILE <= 2^16: two per register
     static_assert(TILE <= 65536, "16-bit ranks");
@@ -300,8 +299,23 @@ hipError_t launch_radix_shape(const char* name, Src src, Out out, int64_t n, uin
                   out, n, shift, bits, hist, reinterpret_cast<W*>(lb), reinterpret_cast<W*>(lb_next), ticket, err);
 }
 
-// Launches one radix pass with tile shape RADIX_SHAPES[shape].  The look-back
-// arrays need room for ceil(n / min_radix_tile()) tiles.
+// The tile shape a pass over n keys launches with when `shape` is asked
+// for: passes over LB32_MAX_KEYS keys or more use 64-bit look-back words and
+// only the default shape; an unknown shape is the default.  Every table sized
+// by the tiles of a pass (batch tile records, histogram tiling, staged ids)
+// takes its tile size from here.
+inline int radix_effective_shape(int shape, int64_t n) {
+    if (n >= LB32_MAX_KEYS || shape < 0 || shape >= N_RADIX_SHAPES) return DEFAULT_RADIX_SHAPE;
+    return shape;
+}
+inline int64_t radix_tile_keys(int shape, int64_t n) {
+    const RadixShape sh = RADIX_SHAPES[radix_effective_shape(shape, n)];
+    return (int64_t)sh.block * sh.items;
+}
+
+// Launches one radix pass with tile shape RADIX_SHAPES[radix_effective_shape(
+// shape, n)].  The look-back arrays need room for ceil(n / min_radix_tile())
+// tiles.
 template <class Src, class Out>
 hipError_t launch_radix_pass(const char* name, int shape, Src src, Out out, int64_t n, uint32_t shift, uint32_t bits,
                              const uint32_t* hist, uint64_t* lb, uint64_t* lb_next, uint32_t* ticket, uint32_t* err,
@@ -309,11 +323,11 @@ hipError_t launch_radix_pass(const char* name, int shape, Src src, Out out, int6
     // The status arrays hold 64-bit words; passes over fewer than
     // LB32_MAX_KEYS keys use them as 32-bit words (every pass of one
     // pipeline has the same n, so a pass and the next agree on the width of
-    // the slots they hand over).  Larger passes take the default tile shape.
+    // the slots they hand over).
     if (n >= LB32_MAX_KEYS)
         return launch_radix_shape<512, 16, Src, Out, uint64_t>(name, src, out, n, shift, bits, hist, lb, lb_next,
                                                                ticket, err, s);
-    switch (shape) {
+    switch (radix_effective_shape(shape, n)) {
         case 1: return launch_radix_shape<256, 32>(name, src, out, n, shift, bits, hist, lb, lb_next, ticket, err, s);
         case 2: return launch_radix_shape<512, 12>(name, src, out, n, shift, bits, hist, lb, lb_next, ticket, err, s);
         case 3: return launch_radix_shape<512, 24>(name, src, out, n, shift, bits, hist, lb, lb_next, ticket, err, s);
@@ -337,8 +351,5 @@ constexpr int min_radix_tile() {
         if (RADIX_SHAPES[i].block * RADIX_SHAPES[i].items < m) m = RADIX_SHAPES[i].block * RADIX_SHAPES[i].items;
     return m;
 }
-
-// Process-wide tile shape used by every radix pass (mesh_set_radix_shape).
-int radix_shape();
 
 }  // namespace mnb

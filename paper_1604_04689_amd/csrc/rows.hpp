@@ -253,11 +253,73 @@ static __global__ __launch_bounds__(ROW_BLOCK) void row_unique_kernel(const uint
     if (bad) set_error(err, ERR_INTERNAL);
 }
 
-// Rows longer than ROW_SHORT: one block per listed row.  The lo values are
-// copied to the row's temp range, sorted (bitonic, in LDS up to LONG_LDS
-// entries, else in place in global memory with every comparator putting the
+// Sorts x[0 .. len) ascending in place (bitonic: in LDS through s when
+// len <= LONG_LDS, else in global memory with every comparator putting the
 // smaller value at the lower index, so virtual INT_MAX padding never moves),
-// then compacted to their distinct values.
+// then compacts it to its distinct values other than INT_MAX (the marker of
+// an absent value).  Returns the distinct count (the same on every thread).
+// Every thread of the block calls it; s_wcnt needs LONG_BLOCK / 64 words.
+__device__ inline int64_t block_sort_unique(int32_t* x, int64_t len, int32_t* s, uint32_t* s_wcnt) {
+    const int tid = threadIdx.x;
+    int64_t n2 = 1;
+    while (n2 < len) n2 <<= 1;
+    if (len <= LONG_LDS) {
+        for (int64_t i = tid; i < n2; i += LONG_BLOCK) s[i] = i < len ? x[i] : INT_MAX;
+        __syncthreads();
+        for (int64_t k = 2; k <= n2; k <<= 1)
+            for (int64_t j = k >> 1; j > 0; j >>= 1) {
+                for (int64_t i = tid; i < n2; i += LONG_BLOCK) {
+                    const int64_t p = i ^ j;
+                    if (p > i) {
+                        const int32_t a = s[i], c = s[p];
+                        if ((a > c) == ((i & k) == 0)) {
+                            s[i] = c;
+                            s[p] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        for (int64_t i = tid; i < len; i += LONG_BLOCK) x[i] = s[i];
+    } else {
+        for (int64_t k = 2; k <= n2; k <<= 1)
+            for (int64_t j = k >> 1; j > 0; j >>= 1) {
+                for (int64_t i = tid; i < len; i += LONG_BLOCK) {
+                    const int64_t p = (j == (k >> 1)) ? (i ^ (k - 1)) : (i ^ j);
+                    if (p > i && p < len) {
+                        const int32_t a = x[i], c = x[p];
+                        if (a > c) {
+                            x[i] = c;
+                            x[p] = a;
+                        }
+                    }
+                }
+                __threadfence_block();
+                __syncthreads();
+            }
+    }
+    __threadfence_block();
+    __syncthreads();
+    // compact the sorted values to their distinct ones, chunk by chunk in order
+    int64_t out = 0;
+    for (int64_t c0 = 0; c0 < len; c0 += LONG_BLOCK) {
+        const int64_t i = c0 + tid;
+        const int32_t v = i < len ? x[i] : 0;
+        const bool keep = i < len && v != INT_MAX && (i == 0 || x[i - 1] != v);
+        __syncthreads();  // every read of this chunk precedes any write to it
+        uint32_t total;
+        const uint32_t at = block_exclusive_sum<LONG_BLOCK>((uint32_t)keep, s_wcnt, &total);
+        if (keep) x[out + at] = v;
+        out += total;
+        __threadfence_block();
+        __syncthreads();
+    }
+    return out;
+}
+
+// Rows longer than ROW_SHORT: one block per listed row.  The lo values are
+// copied to the row's temp range, then sorted and compacted to their
+// distinct values there (block_sort_unique).
 static __global__ __launch_bounds__(LONG_BLOCK) void long_rows_kernel(const uint64_t* __restrict__ keys, int64_t n,
                                                               uint32_t b, int32_t n_vert, int32_t* __restrict__ deg,
                                                               int64_t* __restrict__ src, int32_t* temp,
@@ -285,63 +347,11 @@ static __global__ __launch_bounds__(LONG_BLOCK) void long_rows_kernel(const uint
         }
         __syncthreads();
         const int64_t len = s_len;
-        int64_t n2 = 1;
-        while (n2 < len) n2 <<= 1;
         int32_t* x = temp + rs;
-        if (len <= LONG_LDS) {
-            for (int64_t i = tid; i < n2; i += LONG_BLOCK) s[i] = i < len ? (int32_t)(keys[rs + i] & lo_mask) : INT_MAX;
-            __syncthreads();
-            for (int64_t k = 2; k <= n2; k <<= 1)
-                for (int64_t j = k >> 1; j > 0; j >>= 1) {
-                    for (int64_t i = tid; i < n2; i += LONG_BLOCK) {
-                        const int64_t p = i ^ j;
-                        if (p > i) {
-                            const int32_t a = s[i], c = s[p];
-                            if ((a > c) == ((i & k) == 0)) {
-                                s[i] = c;
-                                s[p] = a;
-                            }
-                        }
-                    }
-                    __syncthreads();
-                }
-            for (int64_t i = tid; i < len; i += LONG_BLOCK) x[i] = s[i];
-        } else {
-            for (int64_t i = tid; i < len; i += LONG_BLOCK) x[i] = (int32_t)(keys[rs + i] & lo_mask);
-            __threadfence_block();
-            __syncthreads();
-            for (int64_t k = 2; k <= n2; k <<= 1)
-                for (int64_t j = k >> 1; j > 0; j >>= 1) {
-                    for (int64_t i = tid; i < len; i += LONG_BLOCK) {
-                        const int64_t p = (j == (k >> 1)) ? (i ^ (k - 1)) : (i ^ j);
-                        if (p > i && p < len) {
-                            const int32_t a = x[i], c = x[p];
-                            if (a > c) {
-                                x[i] = c;
-                                x[p] = a;
-                            }
-                        }
-                    }
-                    __threadfence_block();
-                    __syncthreads();
-                }
-        }
+        for (int64_t i = tid; i < len; i += LONG_BLOCK) x[i] = (int32_t)(keys[rs + i] & lo_mask);
         __threadfence_block();
         __syncthreads();
-        // compact the sorted values to their distinct ones, chunk by chunk in order
-        int64_t out = 0;
-        for (int64_t c0 = 0; c0 < len; c0 += LONG_BLOCK) {
-            const int64_t i = c0 + tid;
-            const int32_t v = i < len ? x[i] : 0;
-            const bool keep = i < len && (i == 0 || x[i - 1] != v);
-            __syncthreads();  // every read of this chunk precedes any write to it
-            uint32_t total;
-            const uint32_t at = block_exclusive_sum<LONG_BLOCK>((uint32_t)keep, s_wcnt, &total);
-            if (keep) x[out + at] = v;
-            out += total;
-            __threadfence_block();
-            __syncthreads();
-        }
+        const int64_t out = block_sort_unique(x, len, s, s_wcnt);
         if (tid == 0) {
             if ((int64_t)hi < n_vert) {
                 deg[hi] = (int32_t)out;

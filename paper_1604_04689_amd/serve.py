@@ -54,12 +54,13 @@ class Request:
 
 
 def reserve_bytes(n_elem: int, etype: int, n_vert: int) -> int:
-    """Device bytes one request holds while in flight: both relations'
-    workspaces and outputs plus its connectivity (the library's own sizing)."""
-    ws_n, cap_n = _b.query_node(n_elem, etype, n_vert)
-    ws_e, cap_e = _b.query_elem(n_elem, etype, n_vert)
+    """Device bytes one request holds while in flight: the workspace of one
+    call building both relations, both outputs, and its connectivity (the
+    library's own sizing, under the tuned options of a mesh of its size)."""
+    from . import autotune
+    ws, cap_n, cap_e = _b.query("both", n_elem, etype, n_vert, autotune.options_for("both", etype, n_elem))
     npe = _b.NODES_PER_ELEM[etype]
-    return ws_n + ws_e + 4 * (cap_n + cap_e) + 8 * (n_vert + 1) + 4 * npe * n_elem
+    return ws + 4 * (cap_n + cap_e) + 8 * (n_vert + 1) + 4 * npe * n_elem
 
 
 class BudgetError(ValueError):
@@ -165,7 +166,7 @@ class GpuExecutor:
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(self.device) for _ in range(n_slots)]
         self.upload = torch.cuda.Stream(self.device)
-        self.slot_state = [dict(node=None, elem=None) for _ in range(n_slots)]
+        self.slot_state = [None] * n_slots  # each slot's BatchBuild of both relations
         self.arena = Arena(arena_ids)
         self.arena_buf = torch.empty(arena_ids, dtype=torch.int32, device=self.device)
         self.pin = torch.empty(arena_ids, dtype=torch.int32, pin_memory=True)
@@ -231,17 +232,15 @@ class GpuExecutor:
             s.wait_event(r.prep[2])
             offs.append(r.prep[0])
         with torch.cuda.stream(s):
-            if st["node"] is None:
-                st["node"] = _b.BatchBuild("node", desc, self.device, conn_offs=offs)
-                st["elem"] = _b.BatchBuild("elem", desc, self.device, conn_offs=offs)
+            if st is None:
+                st = self.slot_state[batch.slot] = _b.BatchBuild("both", desc, self.device, conn_offs=offs,
+                                                                 options="tuned")
             else:
-                st["node"].reset(desc, s, conn_offs=offs)
-                st["elem"].reset(desc, s, conn_offs=offs)
-            st["node"].launch(self.arena_buf, s, tuned=True)
-            st["elem"].launch(self.arena_buf, s, tuned=True)
+                st.reset(desc, s, conn_offs=offs)
+            st.launch(self.arena_buf, s)
             ev = torch.cuda.Event()
             ev.record(s)
-        batch.payload = {"node": st["node"], "elem": st["elem"], "event": ev}
+        batch.payload = {"build": st, "event": ev}
 
     def done(self, batch: BatchHandle) -> bool:
         return batch.payload["event"].query()
@@ -254,11 +253,10 @@ class GpuExecutor:
         p = batch.payload
         s = self.streams[batch.slot]
         out = []
-        node_rp, node_cols = p["node"].result(s)
-        elem_rp, elem_cols = p["elem"].result(s)
+        (node_rp, node_cols), (elem_rp, elem_cols) = p["build"].result(s)
         nrp, ncol = node_rp.cpu().numpy(), node_cols.cpu().numpy()
         erp, ecol = elem_rp.cpu().numpy(), elem_cols.cpu().numpy()
-        for seg in p["node"].seg_host:
+        for seg in p["build"].seg_host:
             v0, nv = int(seg["vert_off"]), int(seg["n_vert"])
             a, b = int(nrp[v0]), int(nrp[v0 + nv])
             c, d = int(erp[v0]), int(erp[v0 + nv])
@@ -266,9 +264,7 @@ class GpuExecutor:
         return out
 
     def check(self, batch: BatchHandle):
-        s = self.streams[batch.slot]
-        batch.payload["node"].check(s)
-        batch.payload["elem"].check(s)
+        batch.payload["build"].check(self.streams[batch.slot])
 
     def release(self, batch: BatchHandle):
         # the batch has completed, so the arena ranges it read are free again

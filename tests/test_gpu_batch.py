@@ -18,74 +18,102 @@ def _nb():
     return nb
 
 
-@pytest.fixture(autouse=True, params=[0, 1, 2], ids=["full_key", "vertex_rows", "edge_rows"])
-def node_sort(request):
-    """Every batch test runs under every node algorithm (process-wide)."""
-    nb = _nb()
-    nb.set_node_sort(request.param)
-    yield request.param
-    nb.set_node_sort(0)
+@pytest.fixture(params=[0, 1, 2, 3], ids=["full_key", "vertex_rows", "edge_rows", "elem_rows"])
+def opts(request):
+    """Every batch test runs under every node algorithm (per-call options)."""
+    return {"node_sort": request.param}
 
 
-def run_batch(meshes):
-    nb = _nb()
-    desc = [(m.n_elem, m.etype, m.n_vert) for m in meshes]
-    conn = torch.as_tensor(nb.concat_conn([m.conn for m in meshes])).to(DEV)
-    out = {}
-    for kind in ("node", "elem"):
-        b = nb.BatchBuild(kind, desc, DEV)
-        b.launch(conn)
-        rp, cols = b.result()
-        rp_h = rp.cpu().numpy()
-        cols_h = cols.cpu().numpy()
-        slices = []
-        for i, seg in enumerate(b.seg_host):
-            v0, nv = int(seg["vert_off"]), int(seg["n_vert"])
-            a, c = int(rp_h[v0]), int(rp_h[v0 + nv])
-            slices.append((rp_h[v0:v0 + nv + 1] - a, cols_h[a:c]))
-        out[kind] = slices
+def _slices(b, rp_h, cols_h):
+    out = []
+    for seg in b.seg_host:
+        v0, nv = int(seg["vert_off"]), int(seg["n_vert"])
+        a, c = int(rp_h[v0]), int(rp_h[v0 + nv])
+        out.append((rp_h[v0:v0 + nv + 1] - a, cols_h[a:c]))
     return out
 
 
-def check_slices(oracle_mod, meshes, got, only=None):
+def run_batch(meshes, opts, conn_offs=None, conn=None):
+    """Slices of every mesh under the node call, the element call and the
+    call building both: {"node": [...], "elem": [...], "both_node": [...],
+    "both_elem": [...]}."""
+    nb = _nb()
+    desc = [(m.n_elem, m.etype, m.n_vert) for m in meshes]
+    if conn is None:
+        conn = torch.as_tensor(nb.concat_conn([m.conn for m in meshes])).to(DEV)
+    out = {}
+    for kind in ("node", "elem", "both"):
+        b = nb.BatchBuild(kind, desc, DEV, conn_offs=conn_offs, options=opts)
+        b.launch(conn)
+        res = b.result()
+        if kind == "both":
+            (nr, nc), (er, ec) = res
+            out["both_node"] = _slices(b, nr.cpu().numpy(), nc.cpu().numpy())
+            out["both_elem"] = _slices(b, er.cpu().numpy(), ec.cpu().numpy())
+        else:
+            out[kind] = _slices(b, res[0].cpu().numpy(), res[1].cpu().numpy())
+    return out
+
+
+def check_slices(oracle_mod, meshes, got, only=None, reference=None):
+    """Every slice of every call kind against the oracle (or `reference`,
+    a function mesh -> (node_csr, elem_csr))."""
     for i, m in enumerate(meshes):
         if only is not None and i not in only:
             continue
-        for kind, fn in (("node", oracle_mod.node_neighbors), ("elem", oracle_mod.elem_neighbors)):
-            wr, wc = fn(m.conn, m.etype, m.n_vert)
+        if reference is None:
+            want = {"node": oracle_mod.node_neighbors(m.conn, m.etype, m.n_vert),
+                    "elem": oracle_mod.elem_neighbors(m.conn, m.etype, m.n_vert)}
+        else:
+            want = dict(zip(("node", "elem"), reference(m)))
+        for kind in got:
+            wr, wc = want["elem" if kind.endswith("elem") else "node"]
             gr, gc = got[kind][i]
             assert np.array_equal(gr, wr), f"mesh {i} ({m.name}) {kind} row_ptr"
             assert np.array_equal(gc, wc), f"mesh {i} ({m.name}) {kind} cols"
 
 
-def test_mixed_random_batch(oracle_mod):
+def test_mixed_random_batch(oracle_mod, opts):
     rng = np.random.default_rng(77)
     meshes = []
     for i in range(40):
-        et = int(rng.integers(0, 3))
+        et = int(rng.integers(0, 6))
         nv = int(rng.integers(1, 3000))
         ne = int(rng.integers(0, 4000)) if i % 9 else 0  # some empty meshes
         meshes.append(mg.random_mesh(ne, nv, et, seed=100 + i))
-    got = run_batch(meshes)
+    got = run_batch(meshes, opts)
     check_slices(oracle_mod, meshes, got)
 
 
-def test_structured_small_batch(oracle_mod):
+def test_structured_small_batch(oracle_mod, opts):
     specs = mg.batch_specs(n_mesh=48, seed=5, tri_range=(4, 60), cell_range=(1, 9))
-    meshes = [s.build() for s in specs]
-    got = run_batch(meshes)
+    meshes = [s.build() for s in specs] + [mg.quad_grid(9, 1), mg.wedge_grid(5, 3, 2), mg.pyramid_grid(3, 3)]
+    got = run_batch(meshes, opts)
     check_slices(oracle_mod, meshes, got)
 
 
-def test_batch_with_long_rows(oracle_mod):
+def test_batch_with_long_rows(oracle_mod, opts):
     # few vertices, many elements: rows of hundreds to thousands of pairs
     meshes = [mg.random_mesh(3000, 40, 1, seed=51), mg.tri_grid(30, "coin", 52),
-              mg.random_mesh(9000, 7, 2, seed=53), mg.random_mesh(400, 300, 0, seed=54)]
-    got = run_batch(meshes)
+              mg.random_mesh(9000, 7, 2, seed=53), mg.random_mesh(400, 300, 0, seed=54),
+              mg.random_mesh(2000, 9, 5, seed=55)]
+    got = run_batch(meshes, opts)
     check_slices(oracle_mod, meshes, got)
 
 
-def test_batch_with_gapped_and_reordered_conn(oracle_mod):
+def test_batch_tiny_vertex_range_many_edges(oracle_mod, opts):
+    """Repeated elements over at most 16 vertices: the sort covers at most 8
+    bits, yet more edges than one radix tile (the edge-rows transposed pass
+    needs its own look-back array then)."""
+    rng = np.random.default_rng(61)
+    meshes = [mg.random_mesh(6000, 4, 1, seed=62), mg.random_mesh(5000, 3, 0, seed=63)]
+    for m in meshes:
+        m.conn[:] = m.conn[rng.integers(0, 8, size=m.n_elem)]  # few distinct elements, many copies
+    got = run_batch(meshes, opts)
+    check_slices(oracle_mod, meshes, got)
+
+
+def test_batch_with_gapped_and_reordered_conn(oracle_mod, opts):
     """Meshes placed in the connectivity with gaps and out of order: tiles
     across meshes whose ids are not contiguous must take the per-key path,
     the contiguous ones the staged path, and both give the oracle's rows."""
@@ -107,80 +135,98 @@ def test_batch_with_gapped_and_reordered_conn(oracle_mod):
         parts.append(meshes[i].conn.reshape(-1))
         pos += meshes[i].conn.size
     conn = torch.as_tensor(np.concatenate(parts).astype(np.int32)).to(DEV)
-    desc = [(m.n_elem, m.etype, m.n_vert) for m in meshes]
-    got = {}
-    for kind in ("node", "elem"):
-        b = nb.BatchBuild(kind, desc, DEV, conn_offs=offs)
-        b.launch(conn)
-        rp, cols = b.result()
-        rp_h, cols_h = rp.cpu().numpy(), cols.cpu().numpy()
-        got[kind] = []
-        for seg in b.seg_host:
-            v0, nv = int(seg["vert_off"]), int(seg["n_vert"])
-            a, c = int(rp_h[v0]), int(rp_h[v0 + nv])
-            got[kind].append((rp_h[v0:v0 + nv + 1] - a, cols_h[a:c]))
+    got = run_batch(meshes, opts, conn_offs=offs, conn=conn)
     check_slices(oracle_mod, meshes, got)
 
 
-def test_batch_every_radix_shape_same_result(oracle_mod):
+def test_batch_every_radix_shape_same_result(oracle_mod, opts):
     """Every tile shape (each has its own tile table and histogram tiling)
     gives the same bytes as the default one, and the oracle's rows."""
-    nb = _nb()
     specs = mg.batch_specs(n_mesh=24, seed=11, tri_range=(4, 90), cell_range=(1, 12))
     meshes = [s.build() for s in specs]
-    ref = run_batch(meshes)
+    ref = run_batch(meshes, opts)
     check_slices(oracle_mod, meshes, ref)
-    try:
-        for shape in range(1, len(nb.radix_shapes())):
-            nb.set_radix_shape(shape)
-            got = run_batch(meshes)
-            for kind in ("node", "elem"):
-                for i in range(len(meshes)):
-                    assert np.array_equal(got[kind][i][0], ref[kind][i][0]), (shape, kind, i)
-                    assert np.array_equal(got[kind][i][1], ref[kind][i][1]), (shape, kind, i)
-    finally:
-        nb.set_radix_shape(0)
+    for shape in range(1, 7):
+        got = run_batch(meshes, {**opts, "radix_shape": shape})
+        for kind in got:
+            for i in range(len(meshes)):
+                assert np.array_equal(got[kind][i][0], ref[kind][i][0]), (shape, kind, i)
+                assert np.array_equal(got[kind][i][1], ref[kind][i][1]), (shape, kind, i)
 
 
-def test_single_mesh_batch_equals_single_call(oracle_mod):
+def test_single_mesh_batch_equals_single_call(oracle_mod, opts):
     m = mg.kuhn_tet_grid(9, 3)
-    got = run_batch([m])
+    got = run_batch([m], opts)
     check_slices(oracle_mod, [m], got)
 
 
-def test_batch_bad_id_is_reported():
+def test_batch_bad_id_is_reported(opts):
     nb = _nb()
     a = mg.tri_grid(5, "main", 1)
     bad = mg.tri_grid(4, "main", 2)
     bad.conn[3, 1] = bad.n_vert  # outside its own mesh (valid in the batch's global range)
     desc = [(a.n_elem, 0, a.n_vert), (bad.n_elem, 0, bad.n_vert)]
     conn = torch.as_tensor(nb.concat_conn([a.conn, bad.conn])).to(DEV)
-    for kind in ("node", "elem"):
-        b = nb.BatchBuild(kind, desc, DEV)
+    for kind in ("node", "elem", "both"):
+        b = nb.BatchBuild(kind, desc, DEV, options=opts)
         b.launch(conn)
         with pytest.raises(nb.MeshError) as e:
             b.result()
         assert e.value.status == nb.Status.INDEX_RANGE
 
 
-@pytest.mark.slow
-def test_full_batch_512(oracle_mod):
+def test_batch_record_outside_vertex_range_is_reported(opts):
+    """A segment record whose vertex range leaves [0, total_vert) (here:
+    vert_off 5 past its place, so its rows would run past the end) is
+    reported as INDEX_RANGE and its pairs are dropped: the guard words after
+    row_ptr stay untouched."""
     nb = _nb()
-    specs = mg.batch_specs()
-    meshes = [s.build() for s in specs]
-    got = run_batch(meshes)
-    # every slice equals the single-mesh GPU call; a sample also the oracle
-    for i in range(0, len(meshes), 37):
-        m = meshes[i]
-        c = torch.as_tensor(m.conn).to(DEV)
-        for kind, fn in (("node", nb.node_neighbors), ("elem", nb.elem_neighbors)):
-            r, cc = fn(c, m.etype, m.n_vert)
-            assert np.array_equal(got[kind][i][0], r.cpu().numpy()), (i, kind)
-            assert np.array_equal(got[kind][i][1], cc.cpu().numpy()), (i, kind)
-    sample = set(range(0, len(meshes), 23))
-    small = {i for i in sample if meshes[i].n_elem < 400000}
-    check_slices(oracle_mod, meshes, got, only=small)
-    # totals: every mesh of the batch, by closed form
+    a, c = mg.tri_grid(6, "main", 1), mg.kuhn_tet_grid(2, 2)
+    desc = [(a.n_elem, 0, a.n_vert), (c.n_elem, 1, c.n_vert)]
+    conn = torch.as_tensor(nb.concat_conn([a.conn, c.conn])).to(DEV)
+    n_rows = a.n_vert + c.n_vert + 1
+    for kind in ("node", "elem", "both"):
+        b = nb.BatchBuild(kind, desc, DEV, options=opts)
+        guarded = torch.full((n_rows + 256,), 7, dtype=torch.int32, device=DEV)
+        b._rp, b.row_ptr = guarded, guarded[:n_rows]
+        if kind == "both":
+            eguard = torch.full((n_rows + 256,), 7, dtype=torch.int32, device=DEV)
+            b._erp, b.elem_row_ptr = eguard, eguard[:n_rows]
+        seg = b.seg_host.copy()
+        seg[1]["vert_off"] = a.n_vert + 5
+        b.segs[:seg.nbytes].copy_(torch.as_tensor(seg.view("u1")).to(DEV))
+        b.launch(conn)
+        with pytest.raises(nb.MeshError) as e:
+            b.result()
+        assert e.value.status == nb.Status.INDEX_RANGE, kind
+        assert int((guarded[n_rows:] != 7).sum().item()) == 0, kind
+        if kind == "both":
+            assert int((eguard[n_rows:] != 7).sum().item()) == 0, kind
+
+
+@pytest.fixture(scope="module")
+def batch512():
+    """The 512-mesh batch and each mesh's (node_csr, elem_csr) by sparse
+    assembly, a route pinned against the oracle on the CPU
+    (tests/test_oracle_pins.py)."""
+    meshes = [s.build() for s in mg.batch_specs()]
+    print(f"[batch512] {len(meshes)} meshes, {sum(m.n_elem for m in meshes)} elements: reference rows ...",
+          flush=True)
+    return meshes, [pins.scipy_csr(m.conn, m.etype, m.n_vert) for m in meshes]
+
+
+@pytest.mark.slow
+def test_full_batch_512(oracle_mod, opts, batch512):
+    """The 512-mesh batch: every slice of every call kind, element by
+    element, against sparse assembly; a sample also against the oracle;
+    the nnz of every mesh against its closed form."""
+    meshes, refs = batch512
+    print(f"[batch512] options {opts}", flush=True)
+    got = run_batch(meshes, opts)
+    ref = {id(m): r for m, r in zip(meshes, refs)}
+    check_slices(oracle_mod, meshes, got, reference=lambda m: ref[id(m)])
+    sample = {i for i in range(0, len(meshes), 64) if meshes[i].n_elem < 200000}
+    check_slices(oracle_mod, meshes, got, only=sample)
     for kind in ("node", "elem"):
         for i, m in enumerate(meshes):
             nnz = got[kind][i][1].shape[0]

@@ -20,12 +20,17 @@ def _nb():
     return nb
 
 
-def gpu_csr(kind, conn, etype, n_vert, stream=None):
+def gpu_csr(kind, conn, etype, n_vert, stream=None, options=None):
+    """The CSR of one relation ("node", "elem"), or of both from one call
+    ("both": a pair of CSRs), as host arrays."""
     nb = _nb()
     npe = pins.NPE[etype]
     c = torch.as_tensor(np.ascontiguousarray(conn, dtype=np.int32).reshape(-1, npe)).to(DEV)
+    if kind == "both":
+        (nr, nc), (er, ec) = nb.neighbors(c, etype, n_vert, stream=stream, options=options)
+        return (nr.cpu().numpy(), nc.cpu().numpy()), (er.cpu().numpy(), ec.cpu().numpy())
     fn = nb.node_neighbors if kind == "node" else nb.elem_neighbors
-    row_ptr, cols = fn(c, etype, n_vert, stream=stream)
+    row_ptr, cols = fn(c, etype, n_vert, stream=stream, options=options)
     return row_ptr.cpu().numpy(), cols.cpu().numpy()
 
 
@@ -38,26 +43,46 @@ def assert_same(got, want, what=""):
     assert np.array_equal(gc, wc), f"{what}: cols differ at {np.flatnonzero(gc != wc)[:10]}"
 
 
-def check_both(oracle_mod, conn, etype, n_vert, what=""):
+def check_both(oracle_mod, conn, etype, n_vert, what="", options=None):
+    """Node call, element call and the call building both, against the oracle."""
     print(f"[parity] {what} etype={etype} n_elem={np.asarray(conn).reshape(-1, pins.NPE[etype]).shape[0]} "
-          f"n_vert={n_vert}", flush=True)
-    assert_same(gpu_csr("node", conn, etype, n_vert), oracle_mod.node_neighbors(conn, etype, n_vert), what + " node")
-    assert_same(gpu_csr("elem", conn, etype, n_vert), oracle_mod.elem_neighbors(conn, etype, n_vert), what + " elem")
+          f"n_vert={n_vert} options={options}", flush=True)
+    wn = oracle_mod.node_neighbors(conn, etype, n_vert)
+    we = oracle_mod.elem_neighbors(conn, etype, n_vert)
+    assert_same(gpu_csr("node", conn, etype, n_vert, options=options), wn, what + " node")
+    assert_same(gpu_csr("elem", conn, etype, n_vert, options=options), we, what + " elem")
+    gn, ge = gpu_csr("both", conn, etype, n_vert, options=options)
+    assert_same(gn, wn, what + " both/node")
+    assert_same(ge, we, what + " both/elem")
 
 
+# the node algorithms of the parity suites here: the full-key sort and the
+# rows gathered through the element relation (the row-based sorts have their
+# own suite)
+NODE_SORTS = [{"node_sort": 0}, {"node_sort": 3}]
+SORT_IDS = ["full_key", "elem_rows"]
+
+
+@pytest.mark.parametrize("opts", [None] + NODE_SORTS, ids=["default"] + SORT_IDS)
 @pytest.mark.parametrize("case", pins.read_golden(), ids=lambda c: c["name"])
-def test_golden(case):
+def test_golden(case, opts):
     conn = case["conn"].reshape(-1, pins.NPE[case["etype"]])
-    assert_same(gpu_csr("node", conn, case["etype"], case["n_vert"]), (case["node_row_ptr"], case["node_cols"]))
-    assert_same(gpu_csr("elem", conn, case["etype"], case["n_vert"]), (case["elem_row_ptr"], case["elem_cols"]))
+    want_n = (case["node_row_ptr"], case["node_cols"])
+    want_e = (case["elem_row_ptr"], case["elem_cols"])
+    assert_same(gpu_csr("node", conn, case["etype"], case["n_vert"], options=opts), want_n)
+    assert_same(gpu_csr("elem", conn, case["etype"], case["n_vert"], options=opts), want_e)
+    gn, ge = gpu_csr("both", conn, case["etype"], case["n_vert"], options=opts)
+    assert_same(gn, want_n)
+    assert_same(ge, want_e)
 
 
-@pytest.mark.parametrize("etype", [0, 1, 2])
+@pytest.mark.parametrize("opts", NODE_SORTS, ids=SORT_IDS)
+@pytest.mark.parametrize("etype", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("size", [(1, 1), (7, 5), (300, 90), (5000, 4000), (60000, 9000), (20000, 2 ** 20 + 7)])
-def test_random_meshes(oracle_mod, etype, size):
+def test_random_meshes(oracle_mod, etype, size, opts):
     n_elem, n_vert = size
     m = mg.random_mesh(n_elem, n_vert, etype, seed=n_elem + 7 * etype)
-    check_both(oracle_mod, m.conn, etype, n_vert, m.name)
+    check_both(oracle_mod, m.conn, etype, n_vert, m.name, opts)
 
 
 @pytest.mark.parametrize("maker", [lambda: mg.tri64(), lambda: mg.tri_grid(300, "coin", 3),
@@ -65,83 +90,99 @@ def test_random_meshes(oracle_mod, etype, size):
                                    lambda: mg.tri_grid(2, "main", 1), lambda: mg.kuhn_tet_grid(1, 2),
                                    lambda: mg.hex_grid(1, 3)],
                          ids=["tri64", "tri300coin", "kuhn20", "hex16", "tri2", "kuhn1", "hex1"])
-def test_structured(oracle_mod, maker):
+@pytest.mark.parametrize("opts", NODE_SORTS, ids=SORT_IDS)
+def test_structured(oracle_mod, maker, opts):
     m = maker()
-    check_both(oracle_mod, m.conn, m.etype, m.n_vert, m.name)
+    check_both(oracle_mod, m.conn, m.etype, m.n_vert, m.name, opts)
 
 
-def test_large_ids_many_passes(oracle_mod):
+@pytest.mark.parametrize("opts", NODE_SORTS, ids=SORT_IDS)
+def test_large_ids_many_passes(oracle_mod, opts):
     # ids up to 2^25: 50 key bits, 7 radix passes
     m = mg.random_mesh(30000, 2 ** 25 - 3, 1, seed=3)
-    check_both(oracle_mod, m.conn, 1, m.n_vert, "ids 2^25")
+    check_both(oracle_mod, m.conn, 1, m.n_vert, "ids 2^25", opts)
 
 
-def test_fans_long_element_rows(oracle_mod):
+@pytest.mark.parametrize("opts", NODE_SORTS, ids=SORT_IDS)
+def test_fans_long_element_rows(oracle_mod, opts):
     # vertex 0 lies in n triangles: element rows of 100 (long-row list),
     # 5000 (LDS bitonic) and 9000 (in-place bitonic in global memory)
     for n in (100, 5000, 9000):
         rim = np.arange(1, n + 2, dtype=np.int32)
         conn = np.stack([np.zeros(n, np.int32), rim[:-1], rim[1:]], 1)
         conn = conn[np.random.default_rng(n).permutation(n)]
-        check_both(oracle_mod, conn, 0, n + 2, f"fan{n}")
+        check_both(oracle_mod, conn, 0, n + 2, f"fan{n}", opts)
 
 
-def test_degenerate_and_duplicate_elements(oracle_mod):
+@pytest.mark.parametrize("opts", NODE_SORTS, ids=SORT_IDS)
+def test_degenerate_and_duplicate_elements(oracle_mod, opts):
     rng = np.random.default_rng(9)
     conn = rng.integers(0, 6, size=(4000, 4)).astype(np.int32)  # many repeats per tet
     conn[::7] = conn[1::7][: conn[::7].shape[0]]                   # duplicate rows
     conn[::11, 1] = conn[::11, 0]                                   # explicit repeated ids
-    check_both(oracle_mod, conn, 1, 8, "degenerate")
-    check_both(oracle_mod, np.zeros((50, 3), np.int32), 0, 1, "all-self tri")
+    check_both(oracle_mod, conn, 1, 8, "degenerate", opts)
+    check_both(oracle_mod, np.zeros((50, 3), np.int32), 0, 1, "all-self tri", opts)
+    # a vertex repeated at positions that share no edge: hexahedra with 2-3
+    # distinct ids, and wedges and pyramids with few distinct ids
+    for etype, nv in ((2, 3), (4, 3), (5, 2), (3, 2)):
+        conn = rng.integers(0, nv, size=(3000, pins.NPE[etype])).astype(np.int32)
+        check_both(oracle_mod, conn, etype, nv + 1, f"degenerate type {etype}", opts)
 
 
-def test_empty_and_no_vertices():
+@pytest.mark.parametrize("opts", [None] + NODE_SORTS)
+def test_empty_and_no_vertices(opts):
     for kind in ("node", "elem"):
-        r, c = gpu_csr(kind, np.zeros((0, 3), np.int32), 0, 5)
+        r, c = gpu_csr(kind, np.zeros((0, 3), np.int32), 0, 5, options=opts)
         assert r.tolist() == [0] * 6 and c.shape == (0,)
-        r, c = gpu_csr(kind, np.zeros((0, 4), np.int32), 1, 0)
+        r, c = gpu_csr(kind, np.zeros((0, 4), np.int32), 1, 0, options=opts)
         assert r.tolist() == [0] and c.shape == (0,)
+    (nr, nc), (er, ec) = gpu_csr("both", np.zeros((0, 4), np.int32), 1, 3, options=opts)
+    assert nr.tolist() == er.tolist() == [0] * 4 and nc.shape == ec.shape == (0,)
 
 
-def test_index_range_error():
+@pytest.mark.parametrize("opts", NODE_SORTS, ids=SORT_IDS)
+def test_index_range_error(opts):
     nb = _nb()
-    for kind in ("node", "elem"):
+    for kind in ("node", "elem", "both"):
         with pytest.raises(nb.MeshError) as e:
-            gpu_csr(kind, np.array([[0, 1, 2], [1, 2, 9]], np.int32), 0, 4)
+            gpu_csr(kind, np.array([[0, 1, 2], [1, 2, 9]], np.int32), 0, 4, options=opts)
         assert e.value.status == nb.Status.INDEX_RANGE
         with pytest.raises(nb.MeshError) as e:
-            gpu_csr(kind, np.array([[0, -1, 2]], np.int32), 0, 4)
+            gpu_csr(kind, np.array([[0, -1, 2]], np.int32), 0, 4, options=opts)
         assert e.value.status == nb.Status.INDEX_RANGE
 
 
-def test_capacity_error():
+@pytest.mark.parametrize("opts", NODE_SORTS, ids=SORT_IDS)
+def test_capacity_error(opts):
     nb = _nb()
     m = mg.tri_grid(20, "main", 1)
     for kind in ("node", "elem"):
-        b = nb.NeighborBuild(kind, m.n_elem, m.etype, m.n_vert, DEV, cols_capacity=100)
+        b = nb.NeighborBuild(kind, m.n_elem, m.etype, m.n_vert, DEV, cols_capacity=100, options=opts)
         b.launch(torch.as_tensor(m.conn).to(DEV))
         with pytest.raises(nb.MeshError) as e:
             b.result()
         assert e.value.status == nb.Status.CAPACITY
 
 
-def test_exact_capacity_is_enough(oracle_mod):
+@pytest.mark.parametrize("opts", NODE_SORTS, ids=SORT_IDS)
+def test_exact_capacity_is_enough(oracle_mod, opts):
     nb = _nb()
     m = mg.kuhn_tet_grid(6, 2)
     for kind, ref in (("node", oracle_mod.node_neighbors), ("elem", oracle_mod.elem_neighbors)):
         want = ref(m.conn, m.etype, m.n_vert)
-        b = nb.NeighborBuild(kind, m.n_elem, m.etype, m.n_vert, DEV, cols_capacity=want[1].shape[0])
+        b = nb.NeighborBuild(kind, m.n_elem, m.etype, m.n_vert, DEV, cols_capacity=want[1].shape[0], options=opts)
         b.launch(torch.as_tensor(m.conn).to(DEV))
         r, c = b.result()
         assert_same((r.cpu().numpy(), c.cpu().numpy()), want, kind)
 
 
-def test_deterministic_and_workspace_reuse():
+@pytest.mark.parametrize("opts", NODE_SORTS, ids=SORT_IDS)
+def test_deterministic_and_workspace_reuse(opts):
     nb = _nb()
     m = mg.kuhn_tet_grid(12, 8)
     conn = torch.as_tensor(m.conn).to(DEV)
     for kind in ("node", "elem"):
-        b = nb.NeighborBuild(kind, m.n_elem, m.etype, m.n_vert, DEV)
+        b = nb.NeighborBuild(kind, m.n_elem, m.etype, m.n_vert, DEV, options=opts)
         outs = []
         for _ in range(3):  # the same workspace, reused without clearing
             b.launch(conn)
@@ -172,15 +213,17 @@ def kuhn96_mesh():
 
 
 @pytest.mark.slow
-def test_full_tri2048_vs_oracle(oracle_mod, tri2048_mesh):
+@pytest.mark.parametrize("opts", NODE_SORTS, ids=SORT_IDS)
+def test_full_tri2048_vs_oracle(oracle_mod, tri2048_mesh, opts):
     m = tri2048_mesh
-    check_both(oracle_mod, m.conn, m.etype, m.n_vert, "tri2048 coin")
+    check_both(oracle_mod, m.conn, m.etype, m.n_vert, "tri2048 coin", opts)
 
 
 @pytest.mark.slow
-def test_full_kuhn96_vs_oracle(oracle_mod, kuhn96_mesh):
+@pytest.mark.parametrize("opts", NODE_SORTS, ids=SORT_IDS)
+def test_full_kuhn96_vs_oracle(oracle_mod, kuhn96_mesh, opts):
     m = kuhn96_mesh
-    check_both(oracle_mod, m.conn, m.etype, m.n_vert, "kuhn96")
+    check_both(oracle_mod, m.conn, m.etype, m.n_vert, "kuhn96", opts)
 
 
 @pytest.mark.slow
@@ -188,19 +231,18 @@ def test_full_kuhn96_lattice_rows(kuhn96_mesh):
     # closed-form check without the oracle: every row from lattice offsets
     m = kuhn96_mesh
     want = pins.lattice_node_csr(m.dims, pins.KUHN_STEPS, m.perm)
-    assert_same(gpu_csr("node", m.conn, m.etype, m.n_vert), want, "kuhn96 lattice")
+    for opts in NODE_SORTS:
+        assert_same(gpu_csr("node", m.conn, m.etype, m.n_vert, options=opts), want, f"kuhn96 lattice {opts}")
 
 
 def test_every_radix_shape_same_result(oracle_mod):
     nb = _nb()
     cases = [mg.kuhn_tet_grid(14, 3), mg.random_mesh(33333, 5000, 2, 4), mg.random_mesh(20001, 2 ** 25 - 3, 0, 5)]
-    try:
-        for shape in range(len(nb.radix_shapes())):
-            nb.set_radix_shape(shape)
-            for m in cases:
-                check_both(oracle_mod, m.conn, m.etype, m.n_vert, f"{m.name} shape {nb.radix_shapes()[shape]}")
-    finally:
-        nb.set_radix_shape(-1)
+    for shape in range(len(nb.radix_shapes())):
+        for m in cases:
+            for ns in (0, 3):
+                check_both(oracle_mod, m.conn, m.etype, m.n_vert, f"{m.name} shape {nb.radix_shapes()[shape]}",
+                           {"radix_shape": shape, "node_sort": ns})
 
 
 @pytest.mark.slow
@@ -222,9 +264,10 @@ def test_huge_vertex_count_sparse_use(oracle_mod):
         counts[used] = np.diff(lr)
         want_r = np.zeros(n_vert + 1, dtype=np.int64)
         np.cumsum(counts, out=want_r[1:])
-        gr, gc = gpu_csr(kind, conn, 1, n_vert)
-        assert np.array_equal(gr.astype(np.int64), want_r), kind
-        assert np.array_equal(gc, lc), kind
+        for opts in NODE_SORTS:
+            gr, gc = gpu_csr(kind, conn, 1, n_vert, options=opts)
+            assert np.array_equal(gr.astype(np.int64), want_r), (kind, opts)
+            assert np.array_equal(gc, lc), (kind, opts)
 
 
 @pytest.mark.slow

@@ -60,3 +60,34 @@ def test_served_with_small_arena(oracle_mod):
         (gnr, gnc), (ger, gec) = got[r.rid]
         assert np.array_equal(gnr, wn[0]) and np.array_equal(gnc, wn[1]), r.rid
         assert np.array_equal(ger, we[0]) and np.array_equal(gec, we[1]), r.rid
+
+
+@pytest.mark.slow
+def test_served_full_distribution_equals_alone(oracle_mod):
+    """Requests drawn from the full size distribution of the batch workload
+    (triangle grids up to 512^2 vertices, Kuhn and hex cubes up to 48^3
+    cells, three of them forced to 48^3 Kuhn), served with continuous
+    batching: every result equals the oracle's, element by element."""
+    from paper_1604_04689_amd import serve
+    reqs = make_requests(40, rate=2000.0, seed=21, small=False)
+    for i in (3, 17, 29):
+        m = mg.kuhn_tet_grid(48, 100 + i)
+        reqs[i] = serve.Request(i, reqs[i].arrival, m.conn, m.etype, m.n_vert)
+    print(f"[serve] {len(reqs)} requests, {sum(r.n_elem for r in reqs)} elements", flush=True)
+    got = {}
+
+    def on_complete(batch, ex):
+        ex.check(batch)
+        for r, res in zip(batch.requests, ex.results(batch)):
+            got[r.rid] = res
+
+    srv = serve.Server(serve.GpuExecutor(4), serve.RealClock(), n_slots=4, budget_bytes=64 << 30, max_batch=16,
+                       on_complete=on_complete)
+    srv.run(reqs)
+    assert len(got) == len(reqs) and srv.batches < len(reqs)
+    for r in reqs:
+        wn = oracle_mod.node_neighbors(r.conn, r.etype, r.n_vert)
+        we = oracle_mod.elem_neighbors(r.conn, r.etype, r.n_vert)
+        (gnr, gnc), (ger, gec) = got[r.rid]
+        assert np.array_equal(gnr, wn[0]) and np.array_equal(gnc, wn[1]), r.rid
+        assert np.array_equal(ger, we[0]) and np.array_equal(gec, we[1]), r.rid
