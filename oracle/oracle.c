@@ -100,7 +100,7 @@ static int64_t emit_csr(const ordered_set* sets, int32_t n_vert, int32_t* row_pt
     int64_t at = 0;
     row_ptr[0] = 0;
     for (int32_t v = 0; v < n_vert; ++v) {
-        memcpy(cols + at, sets[v].v, (size_t)sets[v].n * sizeof(int32_t));
+        if (sets[v].n > 0) memcpy(cols + at, sets[v].v, (size_t)sets[v].n * sizeof(int32_t));
         at += sets[v].n;
         row_ptr[v + 1] = (int32_t)at;
     }
