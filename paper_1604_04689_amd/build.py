@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmeshnbr.so")
 SOURCES = ["api.hip", "node_path.hip", "elem_path.hip", "elem_rows.hip", "mixed_path.hip", "batch_path.hip",
-           "graph.hip", "timing.hip"]
+           "graph.hip", "timing.hip", "noalloc.hip"]
 ARCH = os.environ.get("MESHNBR_ARCH", "gfx950")
 
 
@@ -44,19 +44,31 @@ def command(out: str = LIB):
     return [hipcc(), *compile_flags(), "-shared", *[os.path.join(CSRC, s) for s in SOURCES], "-o", out]
 
 
-def _compile(src: str) -> tuple:
+def _headers_mtime() -> float:
+    hdrs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    hdrs += [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
+    return max(os.path.getmtime(h) for h in hdrs)
+
+
+def _compile(src: str, skip_newer_than: float = -1.0) -> tuple:
     obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
     cmd = [hipcc(), *compile_flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+    if skip_newer_than >= 0 and os.path.exists(obj) and \
+            os.path.getmtime(obj) > max(skip_newer_than, os.path.getmtime(os.path.join(CSRC, src))):
+        return src, obj, subprocess.CompletedProcess(cmd, 0, "", ""), ["# up to date:", *cmd]
     r = subprocess.run(cmd, capture_output=True, text=True)
     return src, obj, r, cmd
 
 
-def build(verbose: bool = False, jobs: int = 0) -> str:
+def build(verbose: bool = False, jobs: int = 0, incremental: bool = False) -> str:
+    """Compile every source and link.  incremental=True (a development
+    convenience) reuses objects newer than their source and every header."""
     os.makedirs(OBJ, exist_ok=True)
     jobs = jobs or min(len(SOURCES), max(1, min(16, os.cpu_count() or 1)))
     objs = []
+    skip = _headers_mtime() if incremental else -1.0
     with concurrent.futures.ThreadPoolExecutor(jobs) as pool:
-        for src, obj, r, cmd in pool.map(_compile, SOURCES):
+        for src, obj, r, cmd in pool.map(lambda x: _compile(x, skip), SOURCES):
             if verbose:
                 print(" ".join(cmd), flush=True)
             if r.returncode != 0:
@@ -76,4 +88,4 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

@@ -15,6 +15,14 @@
 namespace mnb {
 
 bool timing_enabled();
+// While an UntimedScope lives on the calling thread, its launches run untimed
+// (no event is created or taken from the pool).
+struct UntimedScope {
+    UntimedScope();
+    ~UntimedScope();
+    UntimedScope(const UntimedScope&) = delete;
+    UntimedScope& operator=(const UntimedScope&) = delete;
+};
 // Hands out an event pair for one timed launch; false when timing is off or
 // the record is full (the launch then runs untimed).
 bool timing_begin(hipEvent_t* start, hipEvent_t* stop);

@@ -17,7 +17,7 @@ namespace {
 constexpr size_t MAX_PENDING = 1 << 16;
 
 struct Pending {
-    const char* name;
+    std::string name;  // copied: launch names may live in the caller's stack buffer
     hipEvent_t start, stop;
 };
 
@@ -25,10 +25,15 @@ std::mutex g_mu;
 bool g_enabled = false;
 std::vector<hipEvent_t> g_pool;
 std::vector<Pending> g_pending;
+thread_local int t_untimed = 0;
 
 }  // namespace
 
+UntimedScope::UntimedScope() { ++t_untimed; }
+UntimedScope::~UntimedScope() { --t_untimed; }
+
 bool timing_enabled() {
+    if (t_untimed) return false;
     std::lock_guard<std::mutex> lk(g_mu);
     return g_enabled;
 }
@@ -81,10 +86,10 @@ int32_t mesh_timing_read(mesh_kernel_time* out, int32_t max_entries) {
         if (hipEventSynchronize(p.stop) != hipSuccess || hipEventElapsedTime(&ms, p.start, p.stop) != hipSuccess)
             status = -1;
         size_t k = 0;
-        while (k < agg.size() && std::string(agg[k].name) != p.name) ++k;
+        while (k < agg.size() && std::string(agg[k].name) != p.name.substr(0, sizeof(agg[k].name) - 1)) ++k;
         if (k == agg.size()) {
             mesh_kernel_time t{};
-            std::snprintf(t.name, sizeof(t.name), "%s", p.name);
+            std::snprintf(t.name, sizeof(t.name), "%s", p.name.c_str());
             t.min_ms = 1e300;
             agg.push_back(t);
         }
