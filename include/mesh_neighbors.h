@@ -37,7 +37,8 @@
  *    Vertices used by no element get empty rows.  nnz = row_ptr[n_vert].
  *  - Every data pointer (conn, row_ptr, cols, workspace, the batched and
  *    mixed descriptor arrays) is a DEVICE pointer owned by the caller; the
- *    library allocates nothing and keeps no state between calls.  `opts`
+ *    library allocates nothing and keeps no state between calls (apart from
+ *    the fixed scratch array of mesh_neighbors_noalloc).  `opts`
  *    (host pointer, may be NULL) selects speed-only choices for that call
  *    alone.  `stream` is a hipStream_t (NULL = the null stream).  Calls are
  *    asynchronous and stream-ordered; none synchronises the host except
@@ -77,7 +78,9 @@ typedef enum {
     MESH_ERR_OVERFLOW = 5,         /* sizes beyond the int32 / pair-count range*/
     MESH_ERR_INDEX_RANGE = 6,      /* a connectivity id outside [0, n_vert)    */
     MESH_ERR_HIP = 7,              /* a HIP runtime call or launch failed       */
-    MESH_ERR_INTERNAL = 8          /* a device-side consistency guard tripped   */
+    MESH_ERR_INTERNAL = 8,         /* a device-side consistency guard tripped   */
+    MESH_ERR_SCRATCH_LIMIT = 9     /* mesh_neighbors_noalloc: the mesh needs more
+                                      scratch than MESH_NOALLOC_SCRATCH_BYTES      */
 } mesh_status;
 
 /* ------------------------------------------------------------------------ */
@@ -186,6 +189,39 @@ mesh_status mesh_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, i
                            int32_t* node_row_ptr, int32_t* node_cols, int64_t node_cols_capacity,
                            int32_t* elem_row_ptr, int32_t* elem_cols, int64_t elem_cols_capacity,
                            const mesh_options* opts, void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Both relations without a workspace argument.                             */
+/* ------------------------------------------------------------------------ */
+
+/* Size of the library's fixed device scratch array (64 MiB): enough for any
+ * mesh whose mesh_neighbors_query workspace is at most this size, e.g. up to
+ * about 1.2 M triangles or 0.97 M tetrahedra under the default options. */
+#define MESH_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code being captured into a
+ * HIP graph, tight serving loops, harnesses that forbid hipMalloc):
+ * mesh_neighbors with the same arguments, results and argument checks, but
+ * without a workspace.  Its scratch is a device array of
+ * MESH_NOALLOC_SCRATCH_BYTES owned by the library: each GPU the library runs
+ * on holds its own copy until the process ends.  The caller still passes the
+ * inputs and the outputs (device memory it owns).  Nothing is allocated: no
+ * hipMalloc, hipFree or allocating library routine is called, and launches
+ * are never timed (mesh_timing_enable does not apply).  The first call on a
+ * device looks up that device's copy of the array, with the device current.
+ *   - A mesh whose workspace (mesh_neighbors_query with the same options)
+ *     exceeds MESH_NOALLOC_SCRATCH_BYTES is refused with
+ *     MESH_ERR_SCRATCH_LIMIT before anything is launched.
+ *   - Every call on one GPU shares that GPU's array, which keeps the last
+ *     call's contents (each call sets everything that must start at a fixed
+ *     value itself).  Calls that overlap on one GPU (other streams, other
+ *     host threads) RACE on the array and give wrong results: serialise them.
+ *   - mesh_check(NULL, stream) reports the data error of the last call on
+ *     the current device, as mesh_check does for a workspace. */
+mesh_status mesh_neighbors_noalloc(const int32_t* conn, int64_t n_elem, int32_t etype, int32_t n_vert,
+                                   int32_t* node_row_ptr, int32_t* node_cols, int64_t node_cols_capacity,
+                                   int32_t* elem_row_ptr, int32_t* elem_cols, int64_t elem_cols_capacity,
+                                   const mesh_options* opts, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Meshes with several element types.                                       */
@@ -340,7 +376,9 @@ mesh_status mesh_graph_destroy(mesh_graph graph);
 
 /* Synchronises `stream`, then returns the data error recorded in `workspace`
  * by the last call that used it: MESH_OK, MESH_ERR_INDEX_RANGE,
- * MESH_ERR_CAPACITY or MESH_ERR_INTERNAL (MESH_ERR_HIP if the sync fails). */
+ * MESH_ERR_CAPACITY or MESH_ERR_INTERNAL (MESH_ERR_HIP if the sync fails).
+ * workspace = NULL reads the fixed scratch of mesh_neighbors_noalloc on the
+ * current device. */
 mesh_status mesh_check(const void* workspace, void* stream);
 
 /* Static, human-readable name of a status code. */

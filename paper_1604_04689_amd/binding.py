@@ -28,6 +28,7 @@ class Status(enum.IntEnum):
     INDEX_RANGE = 6
     HIP = 7
     INTERNAL = 8
+    SCRATCH_LIMIT = 9
 
 
 class MeshError(RuntimeError):
@@ -90,6 +91,8 @@ SIGNATURES = {
     "mesh_elem_neighbors": (_c_i32, _ONE + [_c_p]),
     "mesh_neighbors_query": (_c_i32, [_c_i64, _c_i32, _c_i32, _P_OPT, _P_SZ, _P_I64, _P_I64]),
     "mesh_neighbors": (_c_i32, _BOTH + [_c_p]),
+    "mesh_neighbors_noalloc": (_c_i32, [_c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64, _c_p, _c_p, _c_i64, _P_OPT,
+                                        _c_p]),
     "mesh_mixed_neighbors_query": (_c_i32, [_c_i64, _c_i64, _c_i64, _c_i32, _P_OPT, _P_SZ, _P_I64, _P_I64]),
     "mesh_mixed_neighbors": (_c_i32, [_c_p, _c_p, _c_p, _c_i64, _c_i64, _c_i64, _c_i32, _c_p, _c_p, _c_i64, _c_p,
                                       _c_p, _c_i64, _P_OPT, _c_p, _c_sz, _c_p]),
@@ -381,6 +384,41 @@ def neighbors(conn, etype, n_vert, stream=None, options=None):
     b = NeighborBuild("both", _n_elem(conn, etype), etype, n_vert, conn.device, options=options)
     b.launch(conn, stream)
     return b.result(stream)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # MESH_NOALLOC_SCRATCH_BYTES
+
+
+def neighbors_noalloc(conn, etype, n_vert, out, stream=None, options=None, check=True):
+    """Both relations through mesh_neighbors_noalloc: no workspace, the
+    library's fixed scratch array instead.  ``out`` = (node_row_ptr,
+    node_cols, elem_row_ptr, elem_cols), int32 tensors on conn's device that
+    the caller owns (row_ptr n_vert + 1 entries; cols capacities from
+    ``query("both", ...)``).  With check=True the device error word is read
+    (mesh_check(NULL)) and ((node row_ptr, cols[:nnz]), (elem row_ptr,
+    cols[:nnz])) returned; else nothing is synchronised and None returned."""
+    import torch
+
+    _check_conn(torch, conn, conn.device)
+    n_elem = _n_elem(conn, etype)
+    nrp, ncols, erp, ecols = out
+    for t in out:
+        if t.device != conn.device or t.dtype != torch.int32 or not t.is_contiguous():
+            raise ValueError("outputs must be contiguous int32 tensors on conn's device")
+    if nrp.numel() != int(n_vert) + 1 or erp.numel() != int(n_vert) + 1:
+        raise ValueError("row_ptr outputs need n_vert + 1 entries")
+    o = make_options(options)
+    h = _stream_handle(stream, conn.device)
+    with _device_guard(conn.device):
+        _check(lib().mesh_neighbors_noalloc(_ptr(conn), int(n_elem), int(etype), int(n_vert), _ptr(nrp),
+                                            _ptr(ncols) if ncols.numel() else ctypes.c_void_p(0), ncols.numel(),
+                                            _ptr(erp), _ptr(ecols) if ecols.numel() else ctypes.c_void_p(0),
+                                            ecols.numel(), ctypes.byref(o), h), "mesh_neighbors_noalloc")
+        if not check:
+            return None
+        _check(lib().mesh_check(None, h), "mesh_check")
+    nnz, enz = int(nrp[-1].item()), int(erp[-1].item())
+    return (nrp, ncols[:nnz]), (erp, ecols[:enz])
 
 
 # ---------------------------------------------------------------------------

@@ -150,7 +150,7 @@ static mesh_status hip_status(hipError_t e) { return e == hipSuccess ? MESH_OK :
 
 extern "C" {
 
-int32_t mesh_abi_version(void) { return (2 << 16) | 0; }
+int32_t mesh_abi_version(void) { return (2 << 16) | 1; }
 
 mesh_options mesh_default_options(void) {
     mesh_options o;
@@ -172,6 +172,7 @@ const char* mesh_status_string(mesh_status s) {
         case MESH_ERR_INDEX_RANGE: return "vertex id outside [0, n_vert)";
         case MESH_ERR_HIP: return "HIP runtime error";
         case MESH_ERR_INTERNAL: return "internal device check failed";
+        case MESH_ERR_SCRATCH_LIMIT: return "mesh needs more scratch than the fixed no-allocation array holds";
     }
     return "unknown status";
 }
@@ -473,7 +474,11 @@ mesh_status mesh_radix_launch_shape(int32_t shape, int32_t digit_bits, int64_t n
 }
 
 mesh_status mesh_check(const void* workspace, void* stream) {
-    if (!workspace) return MESH_ERR_INVALID_ARG;
+    if (!workspace) {  // the fixed scratch of mesh_neighbors_noalloc on the current device
+        void* p = nullptr;
+        if (noalloc_scratch(&p) != hipSuccess) return MESH_ERR_HIP;
+        workspace = p;
+    }
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return MESH_ERR_HIP;
     uint32_t err = 0;
     if (hipMemcpy(&err, workspace, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) return MESH_ERR_HIP;

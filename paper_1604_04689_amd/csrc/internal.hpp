@@ -204,6 +204,10 @@ struct FillRegion {  // (declared above)
 };
 hipError_t fill_regions(const FillRegion* r, int count, hipStream_t stream);
 
+// Device address of the fixed scratch array of mesh_neighbors_noalloc on the
+// current device (looked up once per device).
+hipError_t noalloc_scratch(void** out);
+
 // The workspace's first word is the error word; keep_err leaves it (and only
 // it) untouched when the header is cleared, for a second pipeline in the same
 // call.

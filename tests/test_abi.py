@@ -196,8 +196,13 @@ def test_mixed_argument_checks():
     assert lib.mesh_mixed_neighbors(*a) == S.WORKSPACE
 
 
-def test_check_null_workspace():
-    assert binding.lib().mesh_check(None, None) == binding.Status.INVALID_ARG
+def test_check_null_workspace_without_a_device():
+    """mesh_check(NULL) reads the fixed scratch of mesh_neighbors_noalloc on
+    the current device; with no device there is none, and it says so."""
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    assert binding.lib().mesh_check(None, None) == binding.Status.HIP
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
@@ -263,3 +268,21 @@ def test_tuning_table_lookup(tmp_path, monkeypatch):
     monkeypatch.setenv("MESHNBR_TUNING", "off")
     assert autotune.options_for("node", 0, 174763) is None
     monkeypatch.setattr(autotune, "_table_cache", None)
+
+
+def test_noalloc_refuses_past_its_scratch_without_a_gpu():
+    """mesh_neighbors_noalloc sizes the mesh with the plain query and refuses
+    one whose workspace exceeds the fixed scratch before touching the device
+    (so this runs without a GPU); bad arguments fail the same way as in
+    mesh_neighbors."""
+    lib = binding.lib()
+    n_elem, n_vert = 3_000_000, 1_600_000
+    ws, ncap, ecap = binding.query("both", n_elem, 0, n_vert)
+    assert ws > binding.NOALLOC_SCRATCH_BYTES
+    st = lib.mesh_neighbors_noalloc(ctypes.c_void_p(16), n_elem, 0, n_vert, ctypes.c_void_p(256), ctypes.c_void_p(256),
+                                    ncap, ctypes.c_void_p(256), ctypes.c_void_p(256), ecap, None, None)
+    assert st == binding.Status.SCRATCH_LIMIT
+    assert lib.mesh_neighbors_noalloc(None, 10, 9, 10, None, None, 0, None, None, 0, None,
+                                      None) == binding.Status.UNSUPPORTED_TYPE
+    assert lib.mesh_neighbors_noalloc(None, -1, 0, 10, None, None, 0, None, None, 0, None,
+                                      None) == binding.Status.INVALID_ARG
