@@ -677,7 +677,7 @@ bool plan_batch_sort(int64_t n_keys, uint32_t digit_bits, int32_t rows_vert, int
     *p = BatchPlan{};
     p->opts = o;
     p->n_keys = n_keys;
-    p->pp = plan_passes(digit_bits, o.digit_bits);
+    p->pp = plan_passes(digit_bits, RBITS);  // batch sorts take 8-bit digits
     if (p->pp.n_pass > B_MAX_PASS) return false;
     p->digit_bits = digit_bits;
     p->n_tiles = ceil_div(n_keys, min_radix_tile());
@@ -897,7 +897,7 @@ hipError_t run_batch_node(const BatchNodePlan& bn, const int32_t* conn, const me
         int32_t* erp = bn.internal_elem ? (int32_t*)(w + bn.off_erp) : const_cast<int32_t*>(elem_row_ptr);
         int32_t* ecols = bn.internal_elem ? (int32_t*)(w + bn.off_ecols) : const_cast<int32_t*>(elem_cols);
         const int64_t ecap = bn.internal_elem ? p.n_keys : elem_cap;
-        const FillRegion extra{w + bn.er.off_lb, (int64_t)bn.er.n_tiles * 2, 0u};
+        const FillRegion extra{w + bn.er.off_lb, bn.er.lb_words, 0u};
         hipError_t e = run_batch_elem(p, conn, segs, n_mesh, total_vert, erp, ecols, ecap, ws, s, keep_err, &extra);
         if (e != hipSuccess) return e;
         if (p.n_keys == 0 || n_mesh == 0) return fill_i32(row_ptr, (int64_t)total_vert + 1, 0, s);

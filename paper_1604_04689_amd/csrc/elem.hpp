@@ -92,21 +92,78 @@ struct ElemPairSrc {
     }
 };
 
-// Histograms of the 8-bit digits of v over the pairs that take part, and
+// The digits of every pass of a sort over the vertex bits (shift and mask of
+// the vertex id per pass), as the histogram kernels take them.
+struct DigitPlan {
+    int n_pass;
+    uint32_t shift[MAX_EPASS];
+    uint32_t mask[MAX_EPASS];
+};
+inline DigitPlan digit_plan(const PassPlan& pp) {
+    DigitPlan d{};
+    d.n_pass = pp.n_pass;
+    for (int q = 0; q < pp.n_pass && q < MAX_EPASS; ++q) {
+        d.shift[q] = pp.shift[q];
+        d.mask[q] = (1u << pp.width[q]) - 1;
+    }
+    return d;
+}
+// Passes whose histograms one block keeps in LDS, per digit width.
+constexpr int hist_passes(int radix) { return radix > RADIX ? 3 : MAX_EPASS; }
+
+// Block histograms go to the global ones.  8-bit digits: added with global
+// atomics.  Wider digits (HR = 2048 values per pass) would take eight times as
+// many atomics, each a memory-side operation on this GPU, so every block
+// stores its partial histograms whole at part + blockIdx.x * n_pass * HR and
+// hist_sum_kernel adds them up.
+template <int HR>
+__device__ __forceinline__ void flush_hist(const uint32_t* s_hist, int n_words, uint32_t* __restrict__ hist,
+                                           int tid, int nthreads) {
+    if constexpr (HR > RADIX) {
+        uint32_t* part = hist + (int64_t)blockIdx.x * n_words;
+        for (int i = tid; i < n_words; i += nthreads) part[i] = s_hist[i];
+    } else {
+        for (int i = tid; i < n_words; i += nthreads)
+            if (s_hist[i]) atomicAdd(&hist[i], s_hist[i]);
+    }
+}
+
+// hist[i] = sum over the G blocks' partials part[b * n_words + i].
+constexpr int HSUM_BLOCK = 256;
+static __global__ __launch_bounds__(HSUM_BLOCK) void hist_sum_kernel(const uint32_t* __restrict__ part, int blocks,
+                                                                    int n_words, uint32_t* __restrict__ hist) {
+    const int i = blockIdx.x * HSUM_BLOCK + threadIdx.x;
+    if (i >= n_words) return;
+    uint32_t acc[4] = {0, 0, 0, 0};
+    int b = 0;
+    for (; b + 4 <= blocks; b += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += part[(int64_t)(b + u) * n_words + i];
+    }
+    for (; b < blocks; ++b) acc[0] += part[(int64_t)b * n_words + i];
+    hist[i] = acc[0] + acc[1] + acc[2] + acc[3];
+}
+
+// Grid of a wide histogram kernel (one partial per block).
+constexpr int HIST_GRID_WIDE = 256;
+
+// Histograms of the digits of v over the pairs that take part (pass q's digit
+// values at hist[q * HR ..], or the block partials, see flush_hist), and
 // their number.  A thread takes whole elements, HIST_UNROLL of them in
 // flight; a repeated id inside an element counts once.  Raises
 // ERR_INDEX_RANGE.
-template <int ET>
+template <int ET, int HR>
 __global__ __launch_bounds__(HIST_BLOCK) void elem_hist_kernel(const int32_t* __restrict__ conn, int64_t n_elem,
-                                                              int32_t n_vert, int n_pass, uint32_t last_bits,
+                                                              int32_t n_vert, DigitPlan dp,
                                                               uint32_t* __restrict__ hist, uint32_t* pair_count,
                                                               uint32_t* err) {
     constexpr int NPE = Elem<ET>::NPE;
-    __shared__ uint32_t s_hist[MAX_EPASS * RADIX];
+    __shared__ uint32_t s_hist[hist_passes(HR) * HR];
     __shared__ uint32_t s_pairs;
     const int tid = threadIdx.x;
+    const int n_pass = dp.n_pass;
     if (tid == 0) s_pairs = 0;
-    for (int i = tid; i < n_pass * RADIX; i += HIST_BLOCK) s_hist[i] = 0;
+    for (int i = tid; i < n_pass * HR; i += HIST_BLOCK) s_hist[i] = 0;
     __syncthreads();
     bool bad = false;
     uint32_t pairs = 0;
@@ -130,10 +187,8 @@ __global__ __launch_bounds__(HIST_BLOCK) void elem_hist_kernel(const int32_t* __
                 for (int jj = 0; jj < j; ++jj) take &= id[u][jj] != v;
                 if (!take) continue;
                 ++pairs;
-                for (int p = 0; p < n_pass; ++p) {
-                    const uint32_t mask = p == n_pass - 1 ? (1u << last_bits) - 1 : RADIX - 1;
-                    atomicAdd(&s_hist[p * RADIX + (((uint32_t)v >> (p * RBITS)) & mask)], 1u);
-                }
+                for (int p = 0; p < n_pass; ++p)
+                    atomicAdd(&s_hist[p * HR + (((uint32_t)v >> dp.shift[p]) & dp.mask[p])], 1u);
             }
         }
     }
@@ -141,8 +196,7 @@ __global__ __launch_bounds__(HIST_BLOCK) void elem_hist_kernel(const int32_t* __
     if (pairs) atomicAdd(&s_pairs, pairs);
     __syncthreads();
     if (tid == 0 && s_pairs) atomicAdd(pair_count, s_pairs);
-    for (int i = tid; i < n_pass * RADIX; i += HIST_BLOCK)
-        if (s_hist[i]) atomicAdd(&hist[i], s_hist[i]);
+    flush_hist<HR>(s_hist, n_pass * HR, hist, tid, HIST_BLOCK);
 }
 
 // The radix passes of the element relation over keys from `first` (the
@@ -163,23 +217,26 @@ inline hipError_t elem_passes(const ElemPlan& p, First first, int32_t* row_ptr, 
     // INT32_MAX (set by the caller)
     const CsrOut csr{cols, row_ptr, cols ? cols_cap : 0, 32u, 0xffffffffull};
     hipError_t e = hipSuccess;
-    for (int q = 0; q < n_pass && e == hipSuccess; ++q) {
+    const uint32_t hs = p.pp.hist_stride();
+    auto pass = [&](const char* name, auto src, auto out, int q) {
         const uint32_t shift = 32 + p.pp.shift[q];
         const uint32_t bits = p.pp.width[q];
-        const bool last = q + 1 == n_pass;
-        uint64_t* out = kb[q & 1];
-        uint64_t* lb_next = last ? nullptr : lb[(q + 1) & 1];
-        const CountedKeySrc later{kb[(q - 1) & 1], count};
+        uint64_t* lb_next = q + 1 == n_pass ? nullptr : lb[(q + 1) & 1];
         uint32_t* ticket = hdr + HDR_TICKET0 + TK_PASS0 + q;
-        const uint32_t* hq = hist + q * RADIX;
-        if (q == 0 && last) e = launch_radix_pass("elem_radix_first", shape, first, csr, p.n_slots, shift, bits, hq,
-                                                  lb[0], lb_next, ticket, err, s);
-        else if (q == 0) e = launch_radix_pass("elem_radix_first", shape, first, out, p.n_slots, shift, bits, hq,
-                                               lb[0], lb_next, ticket, err, s);
-        else if (last) e = launch_radix_pass("elem_radix", shape, later, csr, p.n_slots, shift, bits, hq, lb[q & 1],
-                                             lb_next, ticket, err, s);
-        else e = launch_radix_pass("elem_radix", shape, later, out, p.n_slots, shift, bits, hq, lb[q & 1], lb_next,
-                                   ticket, err, s);
+        const uint32_t* hq = hist + q * hs;
+        if (p.pp.wide)
+            return launch_radix_wide(name, src, out, p.n_slots, shift, bits, hq, lb[q & 1], lb_next, ticket, err, s);
+        return launch_radix_pass(name, shape, src, out, p.n_slots, shift, bits, hq, lb[q & 1], lb_next, ticket, err,
+                                 s);
+    };
+    for (int q = 0; q < n_pass && e == hipSuccess; ++q) {
+        const bool last = q + 1 == n_pass;
+        const KeyOut out{kb[q & 1]};
+        const CountedKeySrc later{kb[(q - 1) & 1], count};
+        if (q == 0 && last) e = pass("elem_radix_first", first, csr, q);
+        else if (q == 0) e = pass("elem_radix_first", first, out, q);
+        else if (last) e = pass("elem_radix", later, csr, q);
+        else e = pass("elem_radix", later, out, q);
     }
     if (e != hipSuccess) return e;
     return launch_rowptr_fill("elem_row_fill", row_ptr, p.n_vert, count, (int32_t*)(w + p.off_bmin), s);

@@ -34,22 +34,29 @@ bool plan_elem_slots(int64_t n_slots, int32_t n_vert, const Opts& o, ElemPlan* p
     p->n_vert = n_vert;
     p->n_slots = n_slots;
     p->id_bits = id_bits_for(n_vert);
-    p->pp = plan_passes(p->id_bits, o.digit_bits);
+    int db = o.digit_bits < 0 ? default_elem_digit_bits(p->id_bits, n_slots) : o.digit_bits;
+    if (n_slots >= LB32_MAX_KEYS) db = RBITS;  // the wide pass has 32-bit look-back words only
+    p->pp = plan_passes(p->id_bits, db);
     p->n_tiles = ceil_div(p->n_slots, min_radix_tile());
+    const size_t lb_bytes = align_up(radix_lookback_bytes(p->n_slots, p->pp.wide));
     size_t off = HEADER_BYTES;
     p->off_hist = off;
-    off += align_up(MAX_EPASS * RADIX * sizeof(uint32_t));
+    off += align_up((size_t)MAX_EPASS * p->pp.hist_stride() * sizeof(uint32_t));
     p->off_lb0 = off;
-    off += align_up((size_t)p->n_tiles * RADIX * sizeof(uint64_t));
+    off += lb_bytes;
     p->zero_bytes = off;  // header, histograms, pass-0 look-back
     p->off_lb1 = off;
-    off += p->pp.n_pass > 1 ? align_up((size_t)p->n_tiles * RADIX * sizeof(uint64_t)) : 0;
+    off += p->pp.n_pass > 1 ? lb_bytes : 0;
     p->off_keys0 = off;
     off += align_up((size_t)p->n_slots * sizeof(uint64_t));
     p->off_keys1 = off;
     off += p->pp.n_pass > 1 ? align_up((size_t)p->n_slots * sizeof(uint64_t)) : 0;
     p->off_bmin = off;
     off += align_up((size_t)ceil_div((int64_t)n_vert + 1, (int64_t)RF_TILE) * sizeof(int32_t));
+    if (p->pp.wide) {  // block partials of the wide histograms
+        p->off_part = off;
+        off += align_up((size_t)HIST_GRID_WIDE * p->pp.n_pass * WRADIX * sizeof(uint32_t));
+    }
     p->total = off;
     return true;
 }
@@ -69,10 +76,21 @@ static hipError_t elem_pipeline(const ElemPlan& p, const int32_t* conn, int32_t*
                                 int64_t cols_cap, char* w, hipStream_t s) {
     uint32_t* hdr = (uint32_t*)w;
     const int grid = (int)tmin<int64_t>(ceil_div(p.n_elem, HIST_BLOCK), HIST_GRID_MAX);
-    const uint32_t last_bits = p.pp.width[p.pp.n_pass - 1];
-    hipError_t e = launch("elem_hist", elem_hist_kernel<ET>, dim3(grid), dim3(HIST_BLOCK), s, conn, p.n_elem,
-                          p.n_vert, p.pp.n_pass, last_bits, (uint32_t*)(w + p.off_hist), hdr + HDR_KEY_COUNT,
-                          hdr + HDR_ERR);
+    const DigitPlan dp = digit_plan(p.pp);
+    hipError_t e;
+    if (p.pp.wide) {
+        const int n_words = dp.n_pass * WRADIX;
+        const int wgrid = (int)tmin<int64_t>(grid, HIST_GRID_WIDE);
+        uint32_t* part = (uint32_t*)(w + p.off_part);
+        e = launch("elem_hist", elem_hist_kernel<ET, WRADIX>, dim3(wgrid), dim3(HIST_BLOCK), s, conn, p.n_elem, p.n_vert,
+                   dp, part, hdr + HDR_KEY_COUNT, hdr + HDR_ERR);
+        if (e == hipSuccess)
+            e = launch("hist_sum", hist_sum_kernel, dim3((unsigned)ceil_div(n_words, HSUM_BLOCK)), dim3(HSUM_BLOCK), s,
+                       (const uint32_t*)part, wgrid, n_words, (uint32_t*)(w + p.off_hist));
+    } else {
+        e = launch("elem_hist", elem_hist_kernel<ET, RADIX>, dim3(grid), dim3(HIST_BLOCK), s, conn, p.n_elem, p.n_vert,
+                   dp, (uint32_t*)(w + p.off_hist), hdr + HDR_KEY_COUNT, hdr + HDR_ERR);
+    }
     if (e != hipSuccess) return e;
     return elem_passes(p, ElemPairSrc<ET>{conn, p.n_vert}, row_ptr, cols, cols_cap, w, s);
 }

@@ -13,13 +13,14 @@ size_t plan_erows(int64_t n_entries, int slots, int32_t n_vert, size_t off, size
     p->n_tiles = erows_tiles_bound(n_entries);
     p->long_cap = erows_long_cap(n_entries);
     p->off_lb = off;
-    off += align_up((size_t)p->n_tiles * sizeof(uint64_t));
+    p->lb_words = erows_scan_tiles(n_vert) * 2;
+    off += align_up((size_t)p->lb_words * sizeof(uint32_t));
     p->off_tf = off;
     off += align_up(((size_t)p->n_tiles + 1) * sizeof(int32_t));
     p->off_list = off;
     off += align_up((size_t)p->long_cap * sizeof(int32_t));
     p->off_deg = off;
-    off += align_up((size_t)n_vert * sizeof(int32_t));
+    off += align_up(((size_t)n_vert + 1) * sizeof(int32_t));
     p->temp_bytes = (size_t)slots * (size_t)n_entries * sizeof(int32_t);
     if (p->temp_bytes <= alias_bytes) {
         p->off_temp = alias_off;  // dead by the time the stage runs
@@ -32,9 +33,9 @@ size_t plan_erows(int64_t n_entries, int slots, int32_t n_vert, size_t off, size
 
 ErowsBufs erows_bufs(const ErowsPlan& er, char* ws, uint32_t* err, uint32_t* ticket) {
     uint32_t* hdr = (uint32_t*)ws;
-    return ErowsBufs{(uint64_t*)(ws + er.off_lb), (int32_t*)(ws + er.off_tf),   (int32_t*)(ws + er.off_list),
-                     er.long_cap,                 hdr + HDR_LONG_COUNT,          (int32_t*)(ws + er.off_deg),
-                     (int32_t*)(ws + er.off_temp), ticket,                       err};
+    return ErowsBufs{(int32_t*)(ws + er.off_tf),   (int32_t*)(ws + er.off_list), er.long_cap,
+                     hdr + HDR_LONG_COUNT,          (int32_t*)(ws + er.off_deg),  (int32_t*)(ws + er.off_temp),
+                     (uint64_t*)(ws + er.off_lb),   ticket,                       err};
 }
 
 hipError_t run_erows_uniform(int32_t etype, const ErowsPlan& er, const int32_t* conn, int64_t n_elem,

@@ -8,19 +8,21 @@
 // row's candidates (the edge-neighbors of v inside each of its elements,
 // gathered from the connectivity) are deduplicated and ordered in LDS, which
 // gives the ascending, duplicate-free rows of our reading of the serial
-// solution (Sec. 3.2.2); counts become row starts by a decoupled look-back
-// across tiles.
+// solution (Sec. 3.2.2).  Every tile works alone: each row's distinct values
+// are staged at the row's own candidate slots with its count, the counts are
+// scanned into row_ptr, and the staged values gathered into cols.
 //
-//   erows_prep   per vertex: the first vertex whose element row starts in
-//                each tile of ER_TILE element-CSR entries; rows longer than
-//                ER_ROW_MAX entries listed
-//   erows_long   one block per listed row: candidates to global memory,
-//                sorted and deduplicated there (block_sort_unique)
-//   erows_tile   one block per tile, in tile order by ticket: the rows that
-//                start in the tile, candidates into LDS hash tables spanning
-//                each row's own candidate slots, distinct values compacted,
-//                counts scanned (long rows' counts from erows_long), tile
-//                offset by look-back, rows written to cols
+//   erows_prep    per vertex: the first vertex whose element row starts in
+//                 each tile of ER_TILE element-CSR entries; rows longer than
+//                 ER_ROW_MAX entries listed
+//   erows_long    one block per listed row: candidates to the stage, sorted
+//                 and deduplicated there (block_sort_unique), count written
+//   erows_tile    one block per tile: the rows that start in the tile,
+//                 candidates into LDS hash tables spanning each row's own
+//                 candidate slots, distinct values compacted and ordered by
+//                 counting, written to the stage with the row counts
+//   erows_scan    counts -> row_ptr (decoupled look-back scan)
+//   erows_gather  stage -> cols, coalesced
 #pragma once
 
 #include <climits>
@@ -29,6 +31,7 @@
 #include "../../include/mesh_neighbors.h"
 #include "common.hpp"
 #include "elements.hpp"
+#include "internal.hpp"
 #include "launch.hpp"
 #include "rows.hpp"
 
@@ -71,83 +74,141 @@ __device__ __forceinline__ bool elem_cands(const int32_t (&ids)[NPE], int npe, u
     return vmask != 0;
 }
 
-// Element access of a mesh of one type: element e's ids at conn + e * NPE.
+// Element access.  The candidates of one element-CSR entry (row vertex v,
+// element e) come in three steps, so that a thread can issue the loads of all
+// its entries before it waits for any of them (the gathers from conn are
+// random accesses; one round trip per entry would leave the kernel waiting on
+// memory latency):
+//   locate(ctx, v, e, in) -> Loc   where e's ids are and its type (loads only
+//                                  what that needs: nothing for one element
+//                                  type, the offsets for mixed types, the
+//                                  segment record for a batch)
+//   fetch(loc, ids)                the ids (loads only where loc.ok)
+//   cands(loc, ids, v, c, bad)     the candidates; *bad when the entry is in a
+//                                  row but e is not an element or v not in it
+// `in` is false for positions outside every short row: no loads, no
+// candidates, no error.
+
+// A mesh of one type: element e's ids at conn + e * NPE.
 template <int ET>
 struct UniformRows {
     static constexpr int NPE = Elem<ET>::NPE;
     static constexpr int S = NPE - 1;
+    static constexpr int IDS = NPE;
     static constexpr bool kCtx = false;
     const int32_t* __restrict__ conn;
     int64_t n_elem;
     int32_t n_vert;
+    struct Loc {
+        uint32_t e;
+        bool ok, bad;
+    };
     __device__ __forceinline__ int32_t ctx(int32_t) const { return 0; }
-    // candidates of row vertex v in element e (as listed in v's element row);
-    // *bad: e is not an element, or v is not in it
-    __device__ __forceinline__ void cands(int32_t, int32_t v, int32_t e, uint32_t (&c)[S], bool* bad) const {
-        if ((uint64_t)(uint32_t)e >= (uint64_t)n_elem) {
+    __device__ __forceinline__ Loc locate(int32_t, int32_t, int32_t e, bool in) const {
+        const bool valid = (uint64_t)(uint32_t)e < (uint64_t)n_elem;
+        return Loc{(uint32_t)e, in && valid, in && !valid};
+    }
+    __device__ __forceinline__ void fetch(const Loc& l, int32_t (&ids)[IDS]) const {
+        if (l.ok) {
+            const int32_t* el = conn + (size_t)l.e * NPE;
+#pragma unroll
+            for (int j = 0; j < NPE; ++j) ids[j] = el[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < NPE; ++j) ids[j] = -1;
+        }
+    }
+    __device__ __forceinline__ void cands(const Loc& l, const int32_t (&ids)[IDS], int32_t v, uint32_t (&c)[S],
+                                          bool* bad) const {
+        *bad |= l.bad;
+        if (!l.ok) {
 #pragma unroll
             for (int s = 0; s < S; ++s) c[s] = CAND_NONE;
-            *bad = true;
             return;
         }
-        int32_t ids[NPE];
-        const int32_t* el = conn + (int64_t)e * NPE;
-#pragma unroll
-        for (int j = 0; j < NPE; ++j) ids[j] = el[j];
         *bad |= !elem_cands<NPE>(ids, NPE, adjacency_word<ET>(), v, n_vert, c);
     }
 };
 
-// Up to 8 ids of an element of runtime type `et` at el, and the candidates.
-__device__ __forceinline__ bool runtime_cands(const int32_t* __restrict__ el, int32_t et, int32_t v, int32_t n_vert,
+// Candidates from up to MAX_NPE ids of an element of runtime type et.
+__device__ __forceinline__ bool runtime_cands(const int32_t (&ids)[MAX_NPE], int32_t et, int32_t v, int32_t n_vert,
                                               uint32_t (&c)[MAX_NPE - 1]) {
-    const int npe = nodes_per_elem(et);
-    int32_t ids[MAX_NPE];
-#pragma unroll
-    for (int j = 0; j < MAX_NPE; ++j) ids[j] = j < npe ? el[j] : -1;
-    return elem_cands<MAX_NPE>(ids, npe, adjacency_of(et), v, n_vert, c);
+    return elem_cands<MAX_NPE>(ids, nodes_per_elem(et), adjacency_of(et), v, n_vert, c);
 }
 
-// Element access of a mesh whose elements carry their own types:
-// element e has type etypes[e] and ids conn[elem_off[e] .. elem_off[e+1]).
+// Up to MAX_NPE ids at el, the first npe of them loaded (the rest -1).
+__device__ __forceinline__ void fetch_runtime(const int32_t* __restrict__ el, int npe, bool ok,
+                                              int32_t (&ids)[MAX_NPE]) {
+#pragma unroll
+    for (int j = 0; j < MAX_NPE; ++j) ids[j] = -1;
+    if (ok) {
+#pragma unroll
+        for (int j = 0; j < MAX_NPE; ++j)
+            if (j < npe) ids[j] = el[j];
+    }
+}
+
+// A mesh whose elements carry their own types: element e has type etypes[e]
+// and ids conn[elem_off[e] .. elem_off[e+1]).
 struct MixedRows {
     static constexpr int S = MAX_NPE - 1;
+    static constexpr int IDS = MAX_NPE;
     static constexpr bool kCtx = false;
     const int32_t* __restrict__ conn;
     const int32_t* __restrict__ elem_off;
     const uint8_t* __restrict__ etypes;
     int64_t n_elem, n_ids;
     int32_t n_vert;
+    struct Loc {
+        int32_t a, et;
+        bool ok, bad;
+    };
     __device__ __forceinline__ int32_t ctx(int32_t) const { return 0; }
-    __device__ __forceinline__ void cands(int32_t, int32_t v, int32_t e, uint32_t (&c)[S], bool* bad) const {
+    __device__ __forceinline__ Loc locate(int32_t, int32_t, int32_t e, bool in) const {
+        Loc l{0, 0, false, false};
+        if (!in) return l;
         bool ok = (uint64_t)(uint32_t)e < (uint64_t)n_elem;
-        int32_t a = 0, et = 0;
         if (ok) {
-            a = elem_off[e];
+            l.a = elem_off[e];
             const int32_t b = elem_off[e + 1];
-            et = etypes[e];
-            const int npe = nodes_per_elem(et);
-            ok = npe > 0 && a >= 0 && b - a == npe && (int64_t)b <= n_ids;
+            l.et = etypes[e];
+            const int npe = nodes_per_elem(l.et);
+            ok = npe > 0 && l.a >= 0 && b - l.a == npe && (int64_t)b <= n_ids;
         }
-        if (!ok) {
+        l.ok = ok;
+        l.bad = !ok;
+        return l;
+    }
+    __device__ __forceinline__ void fetch(const Loc& l, int32_t (&ids)[IDS]) const {
+        fetch_runtime(conn + (l.ok ? l.a : 0), nodes_per_elem(l.et), l.ok, ids);
+    }
+    __device__ __forceinline__ void cands(const Loc& l, const int32_t (&ids)[IDS], int32_t v, uint32_t (&c)[S],
+                                          bool* bad) const {
+        *bad |= l.bad;
+        if (!l.ok) {
 #pragma unroll
             for (int s = 0; s < S; ++s) c[s] = CAND_NONE;
-            *bad = true;
             return;
         }
-        *bad |= !runtime_cands(conn + a, et, v, n_vert, c);
+        *bad |= !runtime_cands(ids, l.et, v, n_vert, c);
     }
 };
 
-// Element access of a batch: row vertex v is global; its mesh is the last
-// segment with vert_off <= v (vert_off non-decreasing), its element ids are
-// local to that mesh and so are the candidates.  ctx(v) is the mesh index.
+// A batch: row vertex v is global; its mesh is the last segment with
+// vert_off <= v (vert_off non-decreasing), its element ids are local to that
+// mesh and so are the candidates.  ctx(v) is the mesh index.
 struct BatchRows {
     static constexpr int S = MAX_NPE - 1;
+    static constexpr int IDS = MAX_NPE;
     static constexpr bool kCtx = true;
     const int32_t* __restrict__ conn;
     const mesh_segment* __restrict__ segs;
     int32_t n_mesh;
+    struct Loc {
+        int64_t off;  // first id of the element in conn
+        int32_t et, vl, nv;
+        bool ok, bad;
+    };
     __device__ __forceinline__ int32_t ctx(int32_t v) const {
         int lo = 0, hi = n_mesh - 1;
         while (lo < hi) {
@@ -157,19 +218,43 @@ struct BatchRows {
         }
         return lo;
     }
-    __device__ __forceinline__ void cands(int32_t m, int32_t v, int32_t e, uint32_t (&c)[S], bool* bad) const {
+    __device__ __forceinline__ Loc locate(int32_t m, int32_t v, int32_t e, bool in) const {
+        Loc l{0, 0, 0, 0, false, false};
+        if (!in) return l;
         const mesh_segment& sg = segs[m];
         const int npe = nodes_per_elem(sg.etype);
-        const int32_t vl = v - sg.vert_off;
-        if (npe == 0 || (uint64_t)(uint32_t)e >= (uint64_t)sg.n_elem || vl < 0 || vl >= sg.n_vert) {
+        l.et = sg.etype;
+        l.vl = v - sg.vert_off;
+        l.nv = sg.n_vert;
+        l.ok = npe > 0 && (uint64_t)(uint32_t)e < (uint64_t)sg.n_elem && l.vl >= 0 && l.vl < sg.n_vert;
+        l.bad = !l.ok;
+        l.off = l.ok ? sg.conn_off + (int64_t)e * npe : 0;
+        return l;
+    }
+    __device__ __forceinline__ void fetch(const Loc& l, int32_t (&ids)[IDS]) const {
+        fetch_runtime(conn + l.off, nodes_per_elem(l.et), l.ok, ids);
+    }
+    __device__ __forceinline__ void cands(const Loc& l, const int32_t (&ids)[IDS], int32_t, uint32_t (&c)[S],
+                                          bool* bad) const {
+        *bad |= l.bad;
+        if (!l.ok) {
 #pragma unroll
             for (int s = 0; s < S; ++s) c[s] = CAND_NONE;
-            *bad = true;
             return;
         }
-        *bad |= !runtime_cands(conn + sg.conn_off + (int64_t)e * npe, sg.etype, vl, sg.n_vert, c);
+        *bad |= !runtime_cands(ids, l.et, l.vl, l.nv, c);
     }
 };
+
+// All three steps for one entry (long rows, one entry per thread at a time).
+template <class Acc>
+__device__ __forceinline__ void entry_cands(const Acc& acc, int32_t cx, int32_t v, int32_t e, bool in,
+                                            uint32_t (&c)[Acc::S], bool* bad) {
+    const typename Acc::Loc l = acc.locate(cx, v, e, in);
+    int32_t ids[Acc::IDS];
+    acc.fetch(l, ids);
+    acc.cands(l, ids, v, c, bad);
+}
 
 // Element row length of vertex v, 0 (and *bad) when the row pointers are not
 // a valid CSR there.
@@ -256,12 +341,7 @@ __global__ __launch_bounds__(ER_BLOCK) void erows_long_kernel(Acc acc, const int
         for (int64_t i = tid; i < len; i += ER_BLOCK) {
             const int64_t p = a + i;
             uint32_t c[S];
-            if (p < qe) {
-                acc.cands(cx, v, ecols[p], c, &bad);
-            } else {
-#pragma unroll
-                for (int k = 0; k < S; ++k) c[k] = CAND_NONE;
-            }
+            entry_cands(acc, cx, v, p < qe ? ecols[p] : 0, p < qe, c, &bad);
 #pragma unroll
             for (int k = 0; k < S; ++k) x[S * i + k] = c[k] == CAND_NONE ? INT_MAX : (int32_t)c[k];
         }
@@ -274,71 +354,87 @@ __global__ __launch_bounds__(ER_BLOCK) void erows_long_kernel(Acc acc, const int
     if (bad) set_error(err, ERR_INTERNAL);
 }
 
-// The node CSR from the element CSR, one tile of ER_TILE entries per block.
-// A block owns the vertices whose element row starts in its tile (tiles are
-// taken by ticket, in order, for the look-back).  Entry position r of the
-// tile (0 <= r < ER_SPAN, entry base + r) sits in register slot r / ER_BLOCK
-// of thread r % ER_BLOCK, with its S candidates.
+// The node rows from the element CSR, one tile of ER_TILE entries per block,
+// independently of every other tile.  A block owns the vertices whose element
+// row starts in its tile.  Entry position r of the tile (0 <= r < ER_SPAN,
+// entry base + r) sits in register slot r / ER_BLOCK of thread r % ER_BLOCK,
+// with its S candidates.  Row v's distinct values go, ascending, to
+// stage[S * a .. S * a + cnt[v]) (a = the row's first entry: its S candidate
+// slots per entry always have room), and cnt[v] is written for every owned
+// vertex except the long rows (erows_long writes theirs).
+//
+// The work of a tile is a chain of memory round trips and barriers, kept
+// short: the element ids of the first ER_TILE + WAVE positions are loaded,
+// and for an accessor that needs no row context their connectivity gathered,
+// while the owned rows are being listed; every candidate is offered to its
+// row's table in one round of LDS atomics (the few that collide probe on).
+// With no offset to wait for, no tile waits for another.
 template <class Acc>
 __global__ __launch_bounds__(ER_BLOCK) void erows_tile_kernel(Acc acc, const int32_t* __restrict__ erp,
                                                              const int32_t* __restrict__ ecols, int32_t n_vert,
                                                              int64_t q_bound, int64_t ecap,
                                                              const int32_t* __restrict__ tile_first,
-                                                             const int32_t* __restrict__ ldeg,
-                                                             const int32_t* __restrict__ temp,
-                                                             int32_t* __restrict__ row_ptr,
-                                                             int32_t* __restrict__ cols, int64_t cols_cap,
-                                                             uint64_t* lookback, uint32_t* ticket, uint32_t* err) {
+                                                             int32_t* __restrict__ cnt, int32_t* __restrict__ stage,
+                                                             uint32_t* err) {
     constexpr int S = Acc::S;
     constexpr int CAP = ER_SPAN * S;
     constexpr int WAVES = ER_BLOCK / WAVE;
-    constexpr int MAX_LONG = 64;  // long rows copied per chunk of owned vertices
+    constexpr bool kEarly = !Acc::kCtx;  // ids gathered before the rows are known
     static_assert(CAP < INT16_MAX, "16-bit dense indices");
     // per-row hash tables over each row's own candidate slots; once every
     // insertion is done, the same words hold the distinct values, dense, in
-    // slot order (each row's values contiguous)
-    __shared__ uint32_t s_tab[CAP];
+    // slot order (each row's values contiguous); 4 words of padding for the
+    // unrolled rank loop
+    __shared__ uint32_t s_tab[CAP + 4];
     __shared__ int16_t s_ra[ER_TILE];    // short row k: first entry, relative to the tile base
     __shared__ int16_t s_rlen[ER_TILE];  // entries
     __shared__ int16_t s_rds[ER_TILE];   // dense range of its distinct values
     __shared__ int16_t s_rde[ER_TILE];
     __shared__ int32_t s_rv[ER_TILE];    // vertex
-    __shared__ int32_t s_roff[ER_TILE];  // offset of the row in the tile's output
     __shared__ int32_t s_rctx[Acc::kCtx ? ER_TILE : 1];
     __shared__ uint32_t s_wtot[ER_EPT][WAVES];
     __shared__ uint32_t s_tmp[WAVES];
-    __shared__ int64_t s_tmp64[WAVES];
-    __shared__ int32_t s_lv[MAX_LONG];   // long rows of a chunk: vertex, count, output offset
-    __shared__ int64_t s_lcnt[MAX_LONG];
-    __shared__ int64_t s_loff[MAX_LONG];
-    __shared__ uint32_t s_nlong;
-    __shared__ uint32_t s_tile;
-    __shared__ unsigned long long s_longsum;
-    __shared__ uint64_t s_prefix;
 
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
     const int64_t q = erow_total(erp, n_vert, q_bound);
     const int64_t n_tiles = q / ER_TILE + 1;
-    if ((int64_t)blockIdx.x >= n_tiles) return;  // owns nothing: takes no ticket
-    if (tid == 0) {
-        s_tile = atomicAdd(ticket, 1u);
-        s_longsum = 0;
-    }
-    for (int i = tid; i < CAP; i += ER_BLOCK) s_tab[i] = SLOT_EMPTY;
-    __syncthreads();
-    const int64_t t = s_tile;
+    const int64_t t = blockIdx.x;
+    if (t >= n_tiles) return;  // owns nothing
+    for (int i = tid; i < CAP + 4; i += ER_BLOCK) s_tab[i] = SLOT_EMPTY;
     const int64_t base = t * ER_TILE;
     const bool last_tile = t == n_tiles - 1;
     const int64_t qe = tmin<int64_t>(q, ecap);
     const int64_t in_end = tmin<int64_t>(qe - base, ER_SPAN);  // entry positions that can be read
+    bool bad = false;
+
+    // ---- element ids of every readable position; for the positions below
+    // ER_TILE + WAVE (the first halo slots hold the rest of the tile's last
+    // row, which almost always runs past ER_TILE and is seldom longer than a
+    // wave's worth of entries) their elements' ids too, owned row or not
+    int32_t ent[ER_EPT];
+#pragma unroll
+    for (int i = 0; i < ER_EPT; ++i) {
+        const int r = i * ER_BLOCK + tid;
+        ent[i] = r < in_end ? ecols[base + r] : 0;
+    }
     int32_t v_first = tile_first[t];
     int32_t v_end = last_tile ? n_vert : tile_first[t + 1];
     v_first = tmin<int32_t>(tmax<int32_t>(v_first, 0), n_vert);
     v_end = tmin<int32_t>(tmax<int32_t>(v_end, v_first), n_vert);
-    bool bad = false;
+    auto early = [&](int i) { return kEarly && i * ER_BLOCK + tid < ER_TILE + WAVE; };
+    typename Acc::Loc loc[ER_EPT];
+    int32_t ids[ER_EPT][Acc::IDS];
+#pragma unroll
+    for (int i = 0; i < ER_EPT; ++i) {
+        if (early(i)) {
+            const int r = i * ER_BLOCK + tid;
+            loc[i] = acc.locate(0, 0, ent[i], r < in_end);
+            acc.fetch(loc[i], ids[i]);
+        }
+    }
 
-    // ---- the owned vertices' rows: short non-empty rows listed in LDS;
-    // long rows' distinct counts summed
+    // ---- the owned vertices' rows: short non-empty rows listed in LDS; empty
+    // rows get their count (0) here
     int32_t nrows = 0;
     for (int32_t c0 = v_first; c0 < v_end; c0 += ER_BLOCK) {
         const int32_t v = c0 + tid;
@@ -348,8 +444,8 @@ __global__ __launch_bounds__(ER_BLOCK) void erows_tile_kernel(Acc acc, const int
             bad = true;
             len = 0;
         }
+        if (v < v_end && len == 0) cnt[v] = 0;
         const bool is_short = len > 0 && len <= ER_ROW_MAX;
-        if (len > ER_ROW_MAX) atomicAdd(&s_longsum, (unsigned long long)long_count(ldeg, v, len, S));
         uint32_t total;
         const uint32_t k = (uint32_t)nrows + block_exclusive_sum<ER_BLOCK>((uint32_t)is_short, s_tmp, &total);
         if (is_short && k < (uint32_t)ER_TILE) {
@@ -368,15 +464,14 @@ __global__ __launch_bounds__(ER_BLOCK) void erows_tile_kernel(Acc acc, const int
     }
     __syncthreads();
 
-    // ---- candidates of every entry of a short row (element ids first, all
-    // loads in flight, then the gathers)
+    // ---- the row of every position (the last short row starting at or
+    // before it), then the ids not gathered yet, then the candidates
     uint32_t cand[ER_EPT][S];
     int32_t rowk[ER_EPT];
-    int32_t ent[ER_EPT];
 #pragma unroll
     for (int i = 0; i < ER_EPT; ++i) {
         const int r = i * ER_BLOCK + tid;
-        int lo = 0, hi = nrows - 1;  // last short row starting at or before r
+        int lo = 0, hi = nrows - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (s_ra[mid] <= r) lo = mid;
@@ -384,42 +479,70 @@ __global__ __launch_bounds__(ER_BLOCK) void erows_tile_kernel(Acc acc, const int
         }
         const bool in = nrows > 0 && s_ra[lo] <= r && r < s_ra[lo] + s_rlen[lo] && r < in_end;
         rowk[i] = in ? lo : -1;
-        ent[i] = in ? ecols[base + r] : 0;
     }
+    int32_t rv[ER_EPT];
 #pragma unroll
     for (int i = 0; i < ER_EPT; ++i) {
-        if (rowk[i] >= 0) {
-            const int k = rowk[i];
-            acc.cands(Acc::kCtx ? s_rctx[k] : 0, s_rv[k], ent[i], cand[i], &bad);
-        } else {
+        const int k = rowk[i] >= 0 ? rowk[i] : 0;
+        rv[i] = s_rv[k];
+        if (!early(i)) loc[i] = acc.locate(Acc::kCtx ? s_rctx[k] : 0, rv[i], ent[i], rowk[i] >= 0);
+    }
 #pragma unroll
-            for (int s = 0; s < S; ++s) cand[i][s] = CAND_NONE;
-        }
+    for (int i = 0; i < ER_EPT; ++i)
+        if (!early(i)) acc.fetch(loc[i], ids[i]);
+#pragma unroll
+    for (int i = 0; i < ER_EPT; ++i) {
+        // a position outside every owned row contributes nothing (its early
+        // gather, if any, is dropped; a bad element there is not ours to report)
+        if (rowk[i] < 0) loc[i] = acc.locate(0, 0, 0, false);
+        acc.cands(loc[i], ids[i], rv[i], cand[i], &bad);
     }
 
-    // ---- insert every candidate into its row's table (linear probing over
-    // the row's own slots); the insertion that fills an empty slot keeps the
-    // value
+    // ---- offer every candidate to its row's table (open addressing over the
+    // row's own slots): one round of atomics for all of them, then linear
+    // probing for the few whose first slot held another value.  The insertion
+    // that fills an empty slot keeps the value.
     uint64_t kept = 0;
+    {
+        uint32_t old[ER_EPT][S];
 #pragma unroll
-    for (int i = 0; i < ER_EPT; ++i) {
-        if (rowk[i] < 0) continue;
-        const int k = rowk[i];
-        const uint32_t t0 = (uint32_t)S * (uint32_t)s_ra[k];
-        const uint32_t len = (uint32_t)S * (uint32_t)s_rlen[k];
+        for (int i = 0; i < ER_EPT; ++i) {
+            const int k = rowk[i] >= 0 ? rowk[i] : 0;
+            const uint32_t t0 = (uint32_t)S * (uint32_t)s_ra[k];
+            const uint32_t len = (uint32_t)S * (uint32_t)s_rlen[k];
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const uint32_t w = cand[i][s];
-            if (w == CAND_NONE) continue;
-            uint32_t h = (uint32_t)(((uint64_t)(w * 2654435761u) * len) >> 32);
-            for (uint32_t probe = 0; probe < len; ++probe) {
-                const uint32_t old = atomicCAS(&s_tab[t0 + h], SLOT_EMPTY, w);
-                if (old == SLOT_EMPTY) {
+            for (int s = 0; s < S; ++s) {
+                const uint32_t w = cand[i][s];
+                old[i][s] = w;  // settled unless offered below
+                if (rowk[i] >= 0 && w != CAND_NONE)
+                    old[i][s] = atomicCAS(&s_tab[t0 + (uint32_t)(((uint64_t)(w * 2654435761u) * len) >> 32)],
+                                          SLOT_EMPTY, w);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < ER_EPT; ++i) {
+            const int k = rowk[i] >= 0 ? rowk[i] : 0;
+            const uint32_t t0 = (uint32_t)S * (uint32_t)s_ra[k];
+            const uint32_t len = (uint32_t)S * (uint32_t)s_rlen[k];
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const uint32_t w = cand[i][s];
+                if (rowk[i] < 0 || w == CAND_NONE) continue;
+                if (old[i][s] == SLOT_EMPTY) {
                     kept |= 1ull << (i * S + s);
-                    break;
+                    continue;
                 }
-                if (old == w) break;
-                h = h + 1 == len ? 0 : h + 1;
+                if (old[i][s] == w) continue;
+                uint32_t h = (uint32_t)(((uint64_t)(w * 2654435761u) * len) >> 32);
+                for (uint32_t probe = 1; probe < len; ++probe) {
+                    h = h + 1 == len ? 0 : h + 1;
+                    const uint32_t o = atomicCAS(&s_tab[t0 + h], SLOT_EMPTY, w);
+                    if (o == SLOT_EMPTY) {
+                        kept |= 1ull << (i * S + s);
+                        break;
+                    }
+                    if (o == w) break;
+                }
             }
         }
     }
@@ -458,114 +581,116 @@ __global__ __launch_bounds__(ER_BLOCK) void erows_tile_kernel(Acc acc, const int
     }
     __syncthreads();
 
-    // ---- the tile's output count, its offset by look-back
-    int64_t mine = 0;
-    for (int k = tid; k < nrows; k += ER_BLOCK) mine += tmax<int32_t>(s_rde[k] - s_rds[k], 0);
-    int64_t tile_total;
-    (void)block_exclusive_sum<ER_BLOCK, int64_t>(mine, s_tmp64, &tile_total);
-    tile_total += (int64_t)s_longsum;
-    if (wid == 0) {
-        if (lane == 0) lb_store(lookback + t, (t == 0 ? LB_INC : LB_AGG) | (uint64_t)tile_total);
-        const uint64_t before = wave_lookback_prefix(lookback, (uint32_t)t, (uint64_t)tile_total, err);
-        if (lane == 0) s_prefix = before;
-    }
-    __syncthreads();
-    const int64_t g0 = (int64_t)s_prefix;
-    if (last_tile && tid == 0) row_ptr[n_vert] = (int32_t)(g0 + tile_total);
-
-    // ---- row starts of the owned vertices; long rows copied from temp
-    int64_t carry = 0;
-    int32_t kk = 0;
-    for (int32_t c0 = v_first; c0 < v_end; c0 += ER_BLOCK) {
-        const int32_t v = c0 + tid;
-        int32_t a = 0, len = 0;
-        if (v < v_end) len = erow_len(erp, v, q, &a, &bad);
-        if (len > 0 && (a < base || a >= base + ER_TILE)) len = 0;
-        const bool is_short = len > 0 && len <= ER_ROW_MAX;
-        const bool is_long = len > ER_ROW_MAX;
-        uint32_t n_short;
-        const uint32_t k = (uint32_t)kk + block_exclusive_sum<ER_BLOCK>((uint32_t)is_short, s_tmp, &n_short);
-        int64_t cnt = 0;
-        if (is_short && k < (uint32_t)ER_TILE) cnt = tmax<int32_t>(s_rde[k] - s_rds[k], 0);
-        if (is_long) cnt = long_count(ldeg, v, len, S);
-        int64_t chunk_total;
-        const int64_t off = carry + block_exclusive_sum<ER_BLOCK, int64_t>(cnt, s_tmp64, &chunk_total);
-        if (tid == 0) s_nlong = 0;
-        __syncthreads();
-        if (v < v_end) row_ptr[v] = (int32_t)(g0 + off);
-        if (is_short && k < (uint32_t)ER_TILE) s_roff[k] = (int32_t)off;
-        if (is_long) {
-            const uint32_t slot = atomicAdd(&s_nlong, 1u);
-            if (slot < (uint32_t)MAX_LONG) {
-                s_lv[slot] = v;
-                s_lcnt[slot] = cnt;
-                s_loff[slot] = off;
-            }
-        }
-        __syncthreads();
-        const int n_long = (int)tmin<uint32_t>(s_nlong, (uint32_t)MAX_LONG);
-        if (s_nlong > (uint32_t)MAX_LONG) bad = true;  // only on an invalid CSR
-        for (int li = 0; li < n_long; ++li) {
-            const int32_t lv = s_lv[li];
-            const int64_t dst = g0 + s_loff[li];
-            const int64_t n = s_lcnt[li];  // at most the row's candidate slots
-            const int32_t* src = temp + (int64_t)S * erp[lv];
-            if (dst + n > cols_cap) {
-                if (tid == 0) set_error(err, ERR_CAPACITY);
-                continue;
-            }
-            for (int64_t x = tid; x < n; x += ER_BLOCK) cols[dst + x] = src[x];
-        }
-        carry += chunk_total;
-        kk += (int32_t)n_short;
-        __syncthreads();
-    }
-
-    // ---- short rows' values: a value's place is the number of its row's
-    // distinct values below it
-    bool full = false;
+    // ---- counts of the short rows, and each kept value to its place: the
+    // number of its row's distinct values below it
+    for (int k = tid; k < nrows; k += ER_BLOCK) cnt[s_rv[k]] = tmax<int32_t>(s_rde[k] - s_rds[k], 0);
 #pragma unroll
     for (int i = 0; i < ER_EPT; ++i) {
+        if (rowk[i] < 0) continue;
         const int k = rowk[i];
-        if (k < 0) continue;
         const int ds = s_rds[k], de = s_rde[k];
-        const int64_t row0 = g0 + s_roff[k];
+        int32_t* row = stage + (int64_t)S * (base + s_ra[k]);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             if (!((kept >> (i * S + s)) & 1ull)) continue;
             const uint32_t w = cand[i][s];
-            int below = 0;
-            for (int x = ds; x < de; ++x) below += s_tab[x] < w ? 1 : 0;
-            const int64_t dst = row0 + below;
-            if (dst < cols_cap) cols[dst] = (int32_t)w;
-            else full = true;
+            int n = 0;
+            for (int x = ds; x < de; x += 4) {  // padding past de reads SLOT_EMPTY or other rows' values
+                const uint32_t a0 = s_tab[x], a1 = s_tab[x + 1], a2 = s_tab[x + 2], a3 = s_tab[x + 3];
+                n += (a0 < w) + (x + 1 < de && a1 < w) + (x + 2 < de && a2 < w) + (x + 3 < de && a3 < w);
+            }
+            row[n] = (int32_t)w;  // n < distinct count <= S * (row entries)
         }
     }
-    if (full) set_error(err, ERR_CAPACITY);
     if (bad) set_error(err, ERR_INTERNAL);
 }
 
-// Buffers of the stage (inside the workspace): n_tiles_bound look-back words
-// (zero on entry), tile_first (n_tiles_bound + 1 ints), the long-row list and
-// its counter (zero on entry), ldeg (n_vert ints), temp (S * q_bound ints,
-// free memory: it may alias dead buffers).
+// cols[row_ptr[v] + i] = stage[S * erp[v] + i] for i < cnt[v] = row_ptr[v+1] -
+// row_ptr[v].  A block covers EG_BLOCK consecutive vertices; their output
+// range is contiguous, so consecutive threads take consecutive outputs
+// (coalesced writes), each finding its row by a fixed-step binary search over
+// the block's row starts in LDS, four outputs per thread at a time.
+constexpr int EG_BLOCK = 256;
+constexpr int EG_UNROLL = 4;
+
+static __global__ __launch_bounds__(EG_BLOCK) void erows_gather_kernel(const int32_t* __restrict__ row_ptr,
+                                                                      const int32_t* __restrict__ erp, int slots,
+                                                                      const int32_t* __restrict__ stage,
+                                                                      int32_t n_vert, int64_t q_bound,
+                                                                      int32_t* __restrict__ cols, int64_t cols_cap,
+                                                                      uint32_t* err) {
+    __shared__ int32_t s_start[EG_BLOCK + 1];
+    __shared__ int64_t s_src[EG_BLOCK];
+    const int tid = threadIdx.x;
+    const int64_t v0 = (int64_t)blockIdx.x * EG_BLOCK;
+    const int nv = (int)tmin<int64_t>(EG_BLOCK, (int64_t)n_vert - v0);
+    bool bad = false;
+    if (tid < nv) {
+        const int32_t a = erp[v0 + tid], b = erp[v0 + tid + 1];
+        const int32_t r0 = row_ptr[v0 + tid], r1 = row_ptr[v0 + tid + 1];
+        // a row holds at most its candidate slots, inside the element CSR
+        const bool ok = a >= 0 && b >= a && (int64_t)b <= q_bound && r1 - r0 >= 0 &&
+                        (int64_t)(r1 - r0) <= (int64_t)slots * (b - a);
+        bad |= !ok;
+        s_start[tid] = r0;
+        s_src[tid] = ok ? (int64_t)slots * a : -1;
+    }
+    if (tid == 0) s_start[nv] = row_ptr[v0 + nv];
+    for (int i = nv + 1 + tid; i <= EG_BLOCK; i += EG_BLOCK) s_start[i] = INT32_MAX;  // past the last row
+    __syncthreads();
+    const int64_t a = s_start[0], e = s_start[nv];
+    if (e > cols_cap || e < a) {
+        if (tid == 0) set_error(err, e > cols_cap ? ERR_CAPACITY : ERR_INTERNAL);
+        return;
+    }
+    for (int64_t i0 = a + tid; i0 < e; i0 += (int64_t)EG_BLOCK * EG_UNROLL) {
+        int lo[EG_UNROLL];
+#pragma unroll
+        for (int u = 0; u < EG_UNROLL; ++u) lo[u] = 0;
+#pragma unroll
+        for (int step = EG_BLOCK / 2; step >= 1; step >>= 1)  // last row whose start <= i
+#pragma unroll
+            for (int u = 0; u < EG_UNROLL; ++u) {
+                const int64_t i = i0 + (int64_t)u * EG_BLOCK;
+                if ((int64_t)s_start[lo[u] + step] <= i) lo[u] += step;
+            }
+#pragma unroll
+        for (int u = 0; u < EG_UNROLL; ++u) {
+            const int64_t i = i0 + (int64_t)u * EG_BLOCK;
+            if (i < e) {
+                const int64_t src = s_src[lo[u]];
+                if (src >= 0) cols[i] = stage[src + (i - s_start[lo[u]])];
+            }
+        }
+    }
+    if (bad) set_error(err, ERR_INTERNAL);
+}
+
+// Buffers of the stage (inside the workspace): tile_first (n_tiles_bound + 1
+// ints), the long-row list and its counter (zero on entry), cnt (n_vert + 1
+// ints: each row's distinct count, then the scan's input), stage (S *
+// q_bound ints, free memory: it may alias dead buffers), the scan's look-back
+// words (zero on entry) and ticket.
 struct ErowsBufs {
-    uint64_t* lookback;
     int32_t* tile_first;
     int32_t* long_list;
     int64_t long_cap;
     uint32_t* long_count;
-    int32_t* ldeg;
-    int32_t* temp;
-    uint32_t* ticket;
+    int32_t* cnt;
+    int32_t* stage;
+    uint64_t* scan_lb;
+    uint32_t* scan_ticket;
     uint32_t* err;
 };
 
 inline int64_t erows_tiles_bound(int64_t q_bound) { return q_bound / ER_TILE + 1; }
+inline int64_t erows_scan_tiles(int32_t n_vert) { return ceil_div((int64_t)n_vert + 1, SCAN_TILE); }
 struct ErowsPlan;
 ErowsBufs erows_bufs(const ErowsPlan& er, char* ws, uint32_t* err, uint32_t* ticket);
 inline int64_t erows_long_cap(int64_t q_bound) { return q_bound / (ER_ROW_MAX + 1) + 1; }
 
+// The stage: rows' counts and values (prep, long rows, tiles), counts scanned
+// into row_ptr, values gathered into cols.
 template <class Acc>
 hipError_t launch_erows(const char* tag, const Acc& acc, const int32_t* erp, const int32_t* ecols, int64_t ecap,
                         int32_t n_vert, int64_t q_bound, int32_t* row_ptr, int32_t* cols, int64_t cols_cap,
@@ -580,13 +705,24 @@ hipError_t launch_erows(const char* tag, const Acc& acc, const int32_t* erp, con
         snprintf(name, sizeof name, "%s_erows_long", tag);
         e = launch(name, erows_long_kernel<Acc>, dim3(ER_LONG_GRID), dim3(ER_BLOCK), s, acc, erp, ecols, n_vert,
                    q_bound, ecap, (const int32_t*)b.long_list, erows_long_cap(q_bound), (const uint32_t*)b.long_count,
-                   b.ldeg, b.temp, b.err);
+                   b.cnt, b.stage, b.err);
     }
     if (e == hipSuccess) {
         snprintf(name, sizeof name, "%s_erows", tag);
         e = launch(name, erows_tile_kernel<Acc>, dim3((unsigned)n_tiles), dim3(ER_BLOCK), s, acc, erp, ecols,
-                   n_vert, q_bound, ecap, (const int32_t*)b.tile_first, (const int32_t*)b.ldeg,
-                   (const int32_t*)b.temp, row_ptr, cols, cols_cap, b.lookback, b.ticket, b.err);
+                   n_vert, q_bound, ecap, (const int32_t*)b.tile_first, b.cnt, b.stage, b.err);
+    }
+    if (e == hipSuccess && n_vert == 0) e = fill_i32(row_ptr, 1, 0, s);
+    if (e == hipSuccess) {
+        snprintf(name, sizeof name, "%s_erows_scan", tag);
+        e = launch(name, scan_i32_kernel, dim3((unsigned)ceil_div((int64_t)n_vert, SCAN_TILE)), dim3(SCAN_BLOCK), s,
+                   (const int32_t*)b.cnt, (int64_t)n_vert, row_ptr, b.scan_lb, b.scan_ticket, b.err);
+    }
+    if (e == hipSuccess) {
+        snprintf(name, sizeof name, "%s_erows_gather", tag);
+        e = launch(name, erows_gather_kernel, dim3((unsigned)ceil_div((int64_t)n_vert, EG_BLOCK)), dim3(EG_BLOCK), s,
+                   (const int32_t*)row_ptr, erp, Acc::S, (const int32_t*)b.stage, n_vert, q_bound, cols, cols_cap,
+                   b.err);
     }
     return e;
 }

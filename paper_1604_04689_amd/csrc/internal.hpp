@@ -19,7 +19,7 @@ enum NodeSort : int { NS_FULL_KEY = 0, NS_VERTEX_ROWS = 1, NS_EDGE_ROWS = 2, NS_
 struct Opts {
     int node_sort = NS_ELEM_ROWS;
     int shape = 0;       // requested radix tile shape
-    int digit_bits = 8;  // requested radix digit width
+    int digit_bits = -1;  // requested radix digit width (-1: the rule for the sort at hand)
 };
 
 // false: an option out of range (MESH_ERR_INVALID_ARG).
@@ -31,14 +31,23 @@ uint32_t bits_for_count(int64_t n);
 uint32_t id_bits_for(int32_t n_vert);
 
 // ---- sort plan shared by the radix pipelines ---------------------------------
-// Digit passes over `bits` key bits with the requested digit width: the
-// widths of each pass, low digit first.
+// Digit passes over `bits` key bits: the widths of each pass, low digit
+// first.  8-bit passes (radix_pass), or, when `wide`, passes of up to 11 bits
+// (radix_wide_pass) with the bits split as evenly as the pass count allows.
 struct PassPlan {
     int n_pass = 0;
+    bool wide = false;
     uint32_t width[8] = {};  // digit width of each pass
     uint32_t shift[8] = {};  // first key bit of each pass, relative to the sorted field
+    // histogram words per pass (the digit values of the widest pass)
+    uint32_t hist_stride() const { return wide ? 2048u : 256u; }
 };
+// digit_bits 8: 8-bit passes; 11: passes of up to 11 bits when that takes
+// fewer passes than 8-bit ones (else 8-bit passes).
 PassPlan plan_passes(uint32_t bits, int digit_bits);
+// The element sort's digit width when the options leave it open (8: the
+// wide pass is slower on every mesh measured; it stays selectable).
+int default_elem_digit_bits(uint32_t id_bits, int64_t n_keys);
 
 // ---- element pipeline --------------------------------------------------------
 struct ElemPlan {
@@ -51,6 +60,7 @@ struct ElemPlan {
     int64_t n_tiles = 0;      // radix tiles (room for any tile shape)
     size_t off_hist = 0, off_lb0 = 0, off_lb1 = 0, off_keys0 = 0, off_keys1 = 0;
     size_t off_bmin = 0;      // block minima of the row-start fill
+    size_t off_part = 0;      // wide passes: block partials of the histograms
     size_t zero_bytes = 0;
     size_t total = 0;
     Opts opts;
@@ -67,18 +77,19 @@ hipError_t run_elem(const ElemPlan& p, const int32_t* conn, int32_t* row_ptr, in
 
 // ---- node relation through the element rows (ELEM_ROWS) ------------------------
 // Work of the gather/dedup stage after the element relation: tiles of
-// ER_TILE element-CSR entries, a look-back word per tile, the distinct
-// counts of long rows, and room for long rows' candidates (S per entry).
+// ER_TILE element-CSR entries, each row's distinct count, the rows' values
+// staged at S slots per entry, and the look-back words of the count scan.
 struct ErowsPlan {
     int64_t n_entries = 0;    // upper bound of element-relation entries
     int slots = 0;            // candidate slots per entry (S)
     int64_t n_tiles = 0;
     int64_t long_cap = 0;
-    size_t off_lb = 0;        // look-back words, one per tile (cleared by the call's fill)
+    size_t off_lb = 0;        // count scan look-back words (cleared by the call's fill)
+    int64_t lb_words = 0;     // their size in 32-bit words
     size_t off_tf = 0;        // first owned vertex of every tile
     size_t off_list = 0;      // long rows
-    size_t off_deg = 0;       // long rows' distinct counts
-    size_t off_temp = 0;      // long rows' candidates: S * n_entries ints
+    size_t off_deg = 0;       // distinct count of every row (n_vert + 1 ints)
+    size_t off_temp = 0;      // staged values: S * n_entries ints
     size_t temp_bytes = 0;
 };
 // Sizes the stage at `off` onward; temp may alias a dead region of `alias_bytes`

@@ -66,15 +66,18 @@ struct MixedElemPairSrc {
     }
 };
 
-// Digit histograms of v over the pairs that take part, and their number.
-static __global__ __launch_bounds__(MX_BLOCK) void mixed_hist_kernel(MixedElemPairSrc src, int64_t n_ids, int n_pass,
-                                                                    uint32_t last_bits, uint32_t* __restrict__ hist,
-                                                                    uint32_t* pair_count, uint32_t* err) {
-    __shared__ uint32_t s_hist[MAX_EPASS * RADIX];
+// Digit histograms of v over the pairs that take part (pass q at
+// hist[q * HR ..]), and their number.
+template <int HR>
+static __global__ __launch_bounds__(MX_BLOCK) void mixed_hist_kernel(MixedElemPairSrc src, int64_t n_ids, DigitPlan dp,
+                                                                    uint32_t* __restrict__ hist, uint32_t* pair_count,
+                                                                    uint32_t* err) {
+    __shared__ uint32_t s_hist[hist_passes(HR) * HR];
     __shared__ uint32_t s_pairs;
     const int tid = threadIdx.x;
+    const int n_pass = dp.n_pass;
     if (tid == 0) s_pairs = 0;
-    for (int i = tid; i < n_pass * RADIX; i += MX_BLOCK) s_hist[i] = 0;
+    for (int i = tid; i < n_pass * HR; i += MX_BLOCK) s_hist[i] = 0;
     __syncthreads();
     bool bad = false;
     uint32_t pairs = 0;
@@ -83,17 +86,13 @@ static __global__ __launch_bounds__(MX_BLOCK) void mixed_hist_kernel(MixedElemPa
         if (k == KEY_NONE) continue;
         ++pairs;
         const uint32_t v = (uint32_t)(k >> 32);
-        for (int p = 0; p < n_pass; ++p) {
-            const uint32_t mask = p == n_pass - 1 ? (1u << last_bits) - 1 : RADIX - 1;
-            atomicAdd(&s_hist[p * RADIX + ((v >> (p * RBITS)) & mask)], 1u);
-        }
+        for (int p = 0; p < n_pass; ++p) atomicAdd(&s_hist[p * HR + ((v >> dp.shift[p]) & dp.mask[p])], 1u);
     }
     if (bad) set_error(err, ERR_INDEX_RANGE);
     if (pairs) atomicAdd(&s_pairs, pairs);
     __syncthreads();
     if (tid == 0 && s_pairs) atomicAdd(pair_count, s_pairs);
-    for (int i = tid; i < n_pass * RADIX; i += MX_BLOCK)
-        if (s_hist[i]) atomicAdd(&hist[i], s_hist[i]);
+    flush_hist<HR>(s_hist, n_pass * HR, hist, tid, MX_BLOCK);
 }
 
 bool plan_mixed(int64_t n_elem, int64_t n_ids, int64_t n_pairs, int32_t n_vert, const Opts& o, MixedPlan* p) {
@@ -123,7 +122,7 @@ hipError_t run_mixed(const MixedPlan& p, const int32_t* conn, const int32_t* ele
     int32_t* map = (int32_t*)(w + p.off_map);
     const FillRegion fill[4] = {{ws, (int64_t)(p.zero_bytes / 4), 0u},
                                 {elem_row_ptr, (int64_t)p.n_vert + 1, p.n_ids == 0 ? 0u : (uint32_t)INT32_MAX},
-                                {w + p.er.off_lb, (int64_t)p.er.n_tiles * 2, 0u},
+                                {w + p.er.off_lb, p.er.lb_words, 0u},
                                 {map, p.n_ids, 0xffffffffu}};
     hipError_t e = fill_regions(fill, 4, s);
     if (e != hipSuccess) return e;
@@ -135,10 +134,21 @@ hipError_t run_mixed(const MixedPlan& p, const int32_t* conn, const int32_t* ele
     e = launch("mixed_map", mixed_map_kernel, dim3((unsigned)ceil_div(p.n_elem, MX_BLOCK)), dim3(MX_BLOCK), s,
                elem_off, etypes, p.n_elem, p.n_ids, map, err);
     const MixedElemPairSrc src{conn, map, elem_off, p.n_vert};
-    if (e == hipSuccess)
-        e = launch("mixed_hist", mixed_hist_kernel, dim3((unsigned)tmin<int64_t>(ceil_div(p.n_ids, MX_BLOCK), MX_GRID_MAX)),
-                   dim3(MX_BLOCK), s, src, p.n_ids, p.ep.pp.n_pass, p.ep.pp.width[p.ep.pp.n_pass - 1],
-                   (uint32_t*)(w + p.ep.off_hist), hdr + HDR_KEY_COUNT, err);
+    const DigitPlan dp = digit_plan(p.ep.pp);
+    if (e == hipSuccess && p.ep.pp.wide) {
+        const int n_words = dp.n_pass * WRADIX;
+        const int grid = (int)tmin<int64_t>(ceil_div(p.n_ids, MX_BLOCK), HIST_GRID_WIDE);
+        uint32_t* part = (uint32_t*)(w + p.ep.off_part);
+        e = launch("mixed_hist", mixed_hist_kernel<WRADIX>, dim3(grid), dim3(MX_BLOCK), s, src, p.n_ids, dp, part,
+                   hdr + HDR_KEY_COUNT, err);
+        if (e == hipSuccess)
+            e = launch("hist_sum", hist_sum_kernel, dim3((unsigned)ceil_div(n_words, HSUM_BLOCK)), dim3(HSUM_BLOCK), s,
+                       (const uint32_t*)part, grid, n_words, (uint32_t*)(w + p.ep.off_hist));
+    } else if (e == hipSuccess) {
+        e = launch("mixed_hist", mixed_hist_kernel<RADIX>,
+                   dim3((unsigned)tmin<int64_t>(ceil_div(p.n_ids, MX_BLOCK), MX_GRID_MAX)), dim3(MX_BLOCK), s, src,
+                   p.n_ids, dp, (uint32_t*)(w + p.ep.off_hist), hdr + HDR_KEY_COUNT, err);
+    }
     if (e == hipSuccess) e = elem_passes(p.ep, src, elem_row_ptr, elem_cols, elem_cap, w, s);
     if (e != hipSuccess) return e;
     const ErowsBufs b = erows_bufs(p.er, w, err, hdr + HDR_TICKET0 + TK_EROWS);

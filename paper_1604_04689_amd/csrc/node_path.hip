@@ -237,7 +237,7 @@ bool plan_node(int64_t n_elem, int32_t etype, int32_t n_vert, const Opts& o, boo
     // than a vertex id needs when n_vert is a power of two, so that KEY_NONE
     // (all ones, still taking part in these sorts) ties with no real vertex
     p->sort_bits = full ? 2 * p->id_bits : bits_for_count((int64_t)n_vert + 1);
-    p->pp = plan_passes(p->sort_bits, o.digit_bits);
+    p->pp = plan_passes(p->sort_bits, RBITS);  // the node sorts take 8-bit digits
     p->n_keys = edges ? p->n_edges : p->n_pairs;
     p->n_tiles = ceil_div(p->n_keys, min_radix_tile());  // look-back room for any tile shape
     p->n_utiles = ceil_div(p->n_pairs, UNIQ_TILE);
@@ -365,7 +365,7 @@ hipError_t run_node(const NodePlan& p, const int32_t* conn, int32_t* row_ptr, in
         int32_t* erp = p.internal_elem ? (int32_t*)(w + p.off_erp) : const_cast<int32_t*>(elem_row_ptr);
         int32_t* ecols = p.internal_elem ? (int32_t*)(w + p.off_ecols) : const_cast<int32_t*>(elem_cols);
         const int64_t ecap = p.internal_elem ? p.ep.n_slots : elem_cap;
-        const FillRegion extra{w + p.er.off_lb, (int64_t)(p.er.n_tiles * 2), 0u};
+        const FillRegion extra{w + p.er.off_lb, p.er.lb_words, 0u};
         hipError_t e = run_elem(p.ep, conn, erp, ecols, ecap, ws, s, keep_err, &extra);
         if (e != hipSuccess) return e;
         if (p.ep.n_slots == 0) return fill_i32(row_ptr, (int64_t)p.n_vert + 1, 0, s);

@@ -1,4 +1,5 @@
-// One stable LSD radix pass over 64-bit keys (8-bit digit), onesweep style:
+// One stable LSD radix pass over 64-bit keys (8-bit digit, or up to 11 bits in
+// the wide pass below), onesweep style:
 // tiles ranked in LDS, decoupled look-back across tiles, keys staged in digit
 // order in LDS and written out in coalesced runs.  The key source is a
 // template parameter, so the first pass of a pipeline can generate its keys
@@ -350,6 +351,286 @@ constexpr int min_radix_tile() {
     for (int i = 1; i < N_RADIX_SHAPES; ++i)
         if (RADIX_SHAPES[i].block * RADIX_SHAPES[i].items < m) m = RADIX_SHAPES[i].block * RADIX_SHAPES[i].items;
     return m;
+}
+
+// ---------------------------------------------------------------------------
+// radix_wide_pass: the same stable pass with digits of up to WBITS = 11 bits
+// (2048 digit values), so that the vertex bits of the largest meshes here
+// (20 to 22 bits) are sorted in two passes instead of three.
+//
+// The tile keeps the 8-bit pass's order of work; what changes is where the
+// digit counters live.  Per-wave counters for 2048 digits would not fit beside
+// the key staging area, so they are 16-bit and sit INSIDE the staging area,
+// which is idle until the keys are staged: after ranking, every key's place in
+// the tile is computed into registers, and only then are the keys written
+// over the counters.  The tile's digit counts (later its digit offsets) are
+// 16-bit pairs in one word, counted with 32-bit LDS atomics (a count never
+// carries into its neighbour: a tile holds at most 2^16 - 1 keys); global
+// offsets are 32-bit (passes of this width cover fewer than 2^30 keys).  Each
+// thread owns DPT = 2048 / BLOCK consecutive digits for the look-back, walked
+// together.
+// ---------------------------------------------------------------------------
+constexpr int WBITS = 11;
+constexpr int WRADIX = 1 << WBITS;
+
+// Exclusive prefix of the running counts of ND consecutive digits (status
+// words of digit j of tile t at status[t * WRADIX + j]), walked together by
+// one thread: every round requests LB_BATCH predecessors of every unfinished
+// digit at once.  Publishes LB_INC | (prefix + agg) for each.
+template <int ND, class W>
+__device__ __forceinline__ void lookback_prefix_n(W* status, uint32_t tile, const uint32_t (&agg)[ND],
+                                                  uint32_t (&prefix)[ND], uint32_t* err) {
+    using L = LbWord<W>;
+    constexpr int B = 2;  // predecessors per digit per round (registers are the limit here)
+    int32_t t[ND];        // next tile to read; -1 once the walk is done
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        prefix[d] = 0;
+        t[d] = (int32_t)tile - 1;
+    }
+    uint32_t spins = 0;
+    while (true) {
+        W s[ND][B];
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+                s[d][k] = t[d] - k >= 0 ? lb_load(status + (int64_t)(t[d] - k) * WRADIX + d) : L::INC;
+        bool stalled = false, all = true;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            bool stop = t[d] < 0;
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                if (stop) continue;
+                const W f = s[d][k] & L::FLAG;
+                if (f == 0) {  // resume this digit's walk at this tile
+                    stop = true;
+                    stalled = true;
+                    continue;
+                }
+                prefix[d] += (uint32_t)(s[d][k] & L::VAL);
+                t[d] = f == L::INC ? -1 : t[d] - 1;
+                stop = t[d] < 0;
+            }
+            all &= t[d] < 0;
+        }
+        if (all) break;
+        if (stalled) {
+            if (lookback_give_up(++spins, err)) {
+                set_error(err, ERR_INTERNAL);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < ND; ++d) lb_store(status + (int64_t)tile * WRADIX + d, (W)(L::INC | (W)(prefix[d] + agg[d])));
+}
+
+template <int BLOCK, int ITEMS, class Src, class Out>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(radix_waves_per_eu(BLOCK, ITEMS))))
+void radix_wide_kernel(Src src, Out out, int64_t n, uint32_t shift, uint32_t bits, const uint32_t* __restrict__ hist,
+                       uint32_t* lookback, uint32_t* lookback_next, uint32_t* ticket, uint32_t* err) {
+    constexpr int WAVES = BLOCK / WAVE;
+    constexpr int TILE = BLOCK * ITEMS;
+    constexpr int DPT = WRADIX / BLOCK;  // digits per thread
+    static_assert(WRADIX % BLOCK == 0 && DPT % 2 == 0, "whole digit pairs per thread");
+    static_assert(WAVES * WRADIX * 2 <= TILE * 8, "16-bit wave counters fit the staging area");
+    static_assert(TILE < 65536, "16-bit counts and places");
+    using L = LbWord<uint32_t>;
+    __shared__ uint64_t s_keys[TILE];
+    __shared__ uint32_t s_cnt2[WRADIX / 2];  // 16-bit digit counts, then digit offsets, two per word
+    __shared__ int32_t s_glob[WRADIX];
+    __shared__ uint32_t s_tmp[WAVES];
+    __shared__ uint32_t s_tile;
+    uint16_t* s_wc = reinterpret_cast<uint16_t*>(s_keys);  // [WAVES][WRADIX] while ranking
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const int wid = tid / WAVE;
+    const int64_t limit_n = source_limit(src, n);
+    if ((int64_t)blockIdx.x * TILE >= limit_n) return;
+    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+    for (int i = tid; i < WRADIX / 2; i += BLOCK) s_cnt2[i] = 0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const int64_t tile_base = (int64_t)tile * TILE;
+    const uint32_t dmask = (1u << bits) - 1;
+
+    // ---- 1. load, count ---------------------------------------------------------
+    const int64_t wbase = tile_base + (int64_t)wid * WAVE * ITEMS + lane;
+    if (tile_base >= limit_n) return;
+    uint64_t key[ITEMS];
+    uint32_t valid_bits = 0;
+    bool direct = true;
+    if constexpr (is_staged<Src>::value) {
+        int32_t* s_stage = reinterpret_cast<int32_t*>(s_keys);
+        src.template stage<BLOCK, TILE>(tile_base, n, s_stage, tid);
+        __syncthreads();
+        if (src.staged(s_stage)) {
+            direct = false;
+            const auto hdr = src.header(s_stage);
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const int64_t idx = wbase + j * WAVE;
+                key[j] = idx < n ? src.load_staged(hdr, idx, tile_base, s_stage) : KEY_NONE;
+                const bool valid = idx < limit_n && !(Src::kSkipNone && key[j] == KEY_NONE);
+                valid_bits |= (uint32_t)valid << j;
+            }
+        }
+        __syncthreads();  // the staged ids are read: the area takes the wave counters
+    }
+    if (direct) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int64_t idx = wbase + j * WAVE;
+            key[j] = idx < n ? src.load(idx) : KEY_NONE;
+            const bool valid = idx < limit_n && !(Src::kSkipNone && key[j] == KEY_NONE);
+            valid_bits |= (uint32_t)valid << j;
+        }
+    }
+    {
+        uint32_t* w32 = reinterpret_cast<uint32_t*>(s_wc);
+        for (int i = tid; i < WAVES * WRADIX / 2; i += BLOCK) w32[i] = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        if ((valid_bits >> j) & 1u) {
+            const uint32_t dg = (uint32_t)(key[j] >> shift) & dmask;
+            atomicAdd(&s_cnt2[dg >> 1], 1u << (16 * (dg & 1)));
+        }
+    }
+    __syncthreads();
+
+    // ---- 2. publish, tile offsets, look-back -----------------------------------
+    // thread tid owns digits d0 .. d0 + DPT - 1
+    const int d0 = tid * DPT;
+    uint32_t cnt[DPT], hq[DPT];
+    uint32_t mine = 0, gmine = 0;
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        cnt[j] = (s_cnt2[(d0 + j) >> 1] >> (16 * ((d0 + j) & 1))) & 0xffffu;
+        lb_store(lookback + (int64_t)tile * WRADIX + d0 + j, (uint32_t)((tile == 0 ? L::INC : L::AGG) | cnt[j]));
+        hq[j] = hist[d0 + j];
+        mine += cnt[j];
+        gmine += hq[j];
+    }
+    uint32_t tile_total, hist_total;
+    uint32_t toff = block_exclusive_sum<BLOCK>(mine, s_tmp, &tile_total);
+    uint32_t gstart = block_exclusive_sum<BLOCK>(gmine, s_tmp, &hist_total);
+    uint32_t before[DPT];
+    lookback_prefix_n<DPT>(lookback + d0, tile, cnt, before, err);
+#pragma unroll
+    for (int j = 0; j < DPT; j += 2) {  // this thread's own words of s_cnt2: no other thread reads them yet
+        s_cnt2[(d0 + j) >> 1] = toff | ((toff + cnt[j]) << 16);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            s_glob[d0 + j + h] = (int32_t)(gstart + before[j + h]) - (int32_t)toff;
+            toff += cnt[j + h];
+            gstart += hq[j + h];
+        }
+        if (lookback_next) {
+            lookback_next[(int64_t)tile * WRADIX + d0 + j] = 0;
+            lookback_next[(int64_t)tile * WRADIX + d0 + j + 1] = 0;
+        }
+    }
+
+    // ---- 3. rank within the wave (as in radix_pass, over WBITS digit bits),
+    // the wave counters 16-bit in the staging area --------------------------------
+    const uint64_t lt_mask = (1ull << lane) - 1;
+    uint32_t rank2[(ITEMS + 1) / 2] = {};
+    uint16_t* wc = s_wc + wid * WRADIX;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const bool valid = (valid_bits >> j) & 1u;
+        const uint32_t dg = (uint32_t)(key[j] >> shift) & dmask;
+        const uint64_t vv = __ballot(valid);
+        uint32_t plo = (uint32_t)vv, phi = (uint32_t)(vv >> 32);
+#pragma unroll
+        for (int bit = 0; bit < WBITS; ++bit) {
+            uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int32_t)dg, bit, 1);
+            asm("" : "+v"(m));
+            const uint64_t vote = __ballot(m != 0);
+            plo &= ~((uint32_t)vote ^ m);
+            phi &= ~((uint32_t)(vote >> 32) ^ m);
+            asm("" : "+v"(plo), "+v"(phi));
+        }
+        const uint64_t peers = ((uint64_t)phi << 32) | plo;
+        const uint32_t below = __popcll(peers & lt_mask);
+        const int leader = __ffsll((unsigned long long)peers) - 1;
+        uint32_t base = 0;
+        if (valid && below == 0) {
+            base = wc[dg];
+            wc[dg] = (uint16_t)(base + (uint32_t)__popcll(peers));
+        }
+        base = __shfl(base, leader & (WAVE - 1), WAVE);
+        rank2[j / 2] |= (base + below) << (16 * (j & 1));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {  // wave counts of each digit scanned in wave order (stability)
+        uint32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            const uint32_t c = s_wc[w * WRADIX + d0 + j];
+            s_wc[w * WRADIX + d0 + j] = (uint16_t)run;
+            run += c;
+        }
+    }
+    __syncthreads();
+
+    // ---- 4. places in the tile, then the keys staged in digit order over the
+    // counters, then written out ------------------------------------------------
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {  // rank -> place, in the same 16 bits
+        if ((valid_bits >> j) & 1u) {
+            const uint32_t dg = (uint32_t)(key[j] >> shift) & dmask;
+            const uint32_t off = (s_cnt2[dg >> 1] >> (16 * (dg & 1))) & 0xffffu;
+            rank2[j / 2] += (off + (uint32_t)wc[dg]) << (16 * (j & 1));
+        }
+    }
+    __syncthreads();  // every counter is read: the area takes the keys
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+        if ((valid_bits >> j) & 1u) s_keys[(rank2[j / 2] >> (16 * (j & 1))) & 0xffffu] = key[j];
+    __syncthreads();
+    const int64_t limit = hist_total;  // participating keys of the pass = output size
+    bool bad = false, full = false;
+    for (int i = tid; i < (int)tile_total; i += BLOCK) {
+        const uint64_t k = s_keys[i];
+        const uint32_t dg = (uint32_t)(k >> shift) & dmask;
+        const int64_t dst = (int64_t)s_glob[dg] + i;
+        const int run_first = (int)((s_cnt2[dg >> 1] >> (16 * (dg & 1))) & 0xffffu);
+        if ((uint64_t)dst < (uint64_t)limit) full |= !out.put(k, dst, i, run_first, s_keys);
+        else bad = true;
+    }
+    if (bad) set_error(err, ERR_INTERNAL);
+    if (full) set_error(err, ERR_CAPACITY);
+}
+
+constexpr int WIDE_BLOCK = 512, WIDE_ITEMS = 16;
+constexpr int WIDE_TILE = WIDE_BLOCK * WIDE_ITEMS;
+
+// Launches one wide pass (bits <= WBITS) over n < LB32_MAX_KEYS keys.  The
+// look-back arrays need room for ceil(n / WIDE_TILE) * WRADIX 32-bit words;
+// the histogram holds WRADIX words.
+template <class Src, class Out>
+hipError_t launch_radix_wide(const char* name, Src src, Out out, int64_t n, uint32_t shift, uint32_t bits,
+                             const uint32_t* hist, uint64_t* lb, uint64_t* lb_next, uint32_t* ticket, uint32_t* err,
+                             hipStream_t s) {
+    if (n >= LB32_MAX_KEYS || bits > (uint32_t)WBITS) return hipErrorInvalidValue;
+    return launch(name, radix_wide_kernel<WIDE_BLOCK, WIDE_ITEMS, Src, Out>, dim3((unsigned)ceil_div(n, WIDE_TILE)),
+                  dim3(WIDE_BLOCK), s, src, out, n, shift, bits, hist, reinterpret_cast<uint32_t*>(lb),
+                  reinterpret_cast<uint32_t*>(lb_next), ticket, err);
+}
+
+// Look-back bytes per array of a sort over n keys with either pass width.
+inline size_t radix_lookback_bytes(int64_t n, bool wide) {
+    const size_t narrow = (size_t)ceil_div(n, (int64_t)min_radix_tile()) * RADIX * sizeof(uint64_t);
+    if (!wide) return narrow;
+    const size_t w = (size_t)ceil_div(n, (int64_t)WIDE_TILE) * WRADIX * sizeof(uint32_t);
+    return w > narrow ? w : narrow;
 }
 
 }  // namespace mnb
