@@ -74,7 +74,9 @@ def kernel_bytes(m, nnz_node, nnz_elem, node_sort):
     element sort's last pass reads keys and writes cols and the row starts
     instead of keys, so elem_radix is the mean over its middle passes and that
     last one.  node_erows (rows gathered through the element relation) reads
-    the element CSR and conn once and writes the node CSR."""
+    the element CSR and conn once and writes each row's distinct values and
+    count; node_erows_scan turns the counts into row_ptr and
+    node_erows_gather moves the values into cols."""
     f, v, k, npe = m.n_elem, m.n_vert, EDGES[m.etype], NPE[m.etype]
     p_pairs, q_pairs, u = 2 * k * f, nnz_elem, nnz_node
     keys = k * f if node_sort == 2 else p_pairs
@@ -100,7 +102,10 @@ def kernel_bytes(m, nnz_node, nnz_elem, node_sort):
         "node_edge_merge": 8 * e + 8 * (v + 1) + 4 * u + 4 * (v + 1),
         "node_erows_prep": 4 * (v + 1),                     # element row starts in; tile table (small) out
         "node_erows_long": 0,                               # long rows only; data-dependent
-        "node_erows": 4 * (v + 1) + 4 * q_pairs + conn + 4 * (v + 1) + 4 * u,
+        "node_erows": 4 * (v + 1) + 4 * q_pairs + conn + 4 * v + 4 * u,
+        "node_erows_scan": 4 * v + 4 * (v + 1),
+        "node_erows_gather": 8 * (v + 1) + 4 * u + 4 * u,
+        "hist_sum": 0,
         "elem_hist": conn,
         "elem_radix_first": conn + (8 * q_pairs if elem_passes > 1 else csr_out),
         "elem_radix": sum(later) // len(later) if elem_passes > 1 else 0,

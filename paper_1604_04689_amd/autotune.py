@@ -6,7 +6,7 @@ deduplication; each edge once by its lower vertex, deduplicated per row, then
 transposed; or rows gathered through the element relation), the radix tile
 shape (threads per block x keys per thread, which also sets the waves per
 block and, through the LDS a tile needs, the blocks and so waves per CU) and
-the radix digit width.  For each workload it times every combination on the
+the radix digit width (8 or 11 bits, for the element sort).  For each workload it times every combination on the
 GPU, checks that all of them produce byte-identical CSR output, and records
 the fastest per (relation, element type, size bucket) in ``tuning.json`` next
 to this file.
@@ -36,7 +36,9 @@ MAX_BUCKET_GAP = 2
 # the tile shapes the tuner times (the others never won a sweep over all of
 # them on MI355X; they stay selectable through mesh_options)
 TUNED_SHAPES = (0, 2, 4, 5)
-DIGIT_WIDTHS = (8,)
+# 11-bit digits apply to the element sort (the element relation, and the node
+# relation under the element-rows algorithm); the wide pass has one tile shape
+WIDE_SHAPE = 0
 
 
 def size_bucket(n_keys: int) -> int:
@@ -122,10 +124,17 @@ def _time(torch, build, conn, steps):
     return ms, digest
 
 
-def candidates(kind):
+def candidates(kind, batch=False):
+    """Every (node algorithm, tile shape, digit width) timed for a relation:
+    8-bit digits under every tuned shape, 11-bit digits (the element sort
+    only; batches sort with 8-bit digits) under the wide pass's shape."""
     modes = (0, 1, 2, 3) if kind != "elem" else (-1,)
-    return [{"node_sort": m, "radix_shape": s, "digit_bits": d} for m in modes for s in TUNED_SHAPES
-            for d in DIGIT_WIDTHS]
+    out = []
+    for m in modes:
+        out += [{"node_sort": m, "radix_shape": s, "digit_bits": 8} for s in TUNED_SHAPES]
+        if not batch and (kind != "node" or m == 3):
+            out.append({"node_sort": m, "radix_shape": WIDE_SHAPE, "digit_bits": 11})
+    return out
 
 
 def _entry(relation, etype, n_keys, results, workload):
@@ -162,7 +171,7 @@ def tune(meshes, steps=5, log=print, batches=()):
         _, tot = _b.segment_table(desc)
         for kind in ("node", "elem", "both"):
             results = []
-            for o in candidates(kind):
+            for o in candidates(kind, batch=True):
                 b = _b.BatchBuild(kind, desc, dev, options=o)
                 ms, dg = _time(torch, b, conn, max(2, steps // 2))
                 del b
