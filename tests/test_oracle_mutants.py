@@ -68,7 +68,10 @@ def _call(fn, conn, etype, n_vert):
 
 
 def _call_mixed(fn, conn, etypes, n_vert):
-    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    # a mutant that takes the wrong node count for an element reads up to 7
+    # ids past its end: pad with valid ids (0) so that such a read stays in
+    # bounds and the mutant shows as a wrong result, not a crash
+    conn = np.concatenate([np.asarray(conn, dtype=np.int32).reshape(-1), np.zeros(8, dtype=np.int32)])
     etypes = np.ascontiguousarray(etypes, dtype=np.int32)
     off = np.zeros(etypes.shape[0] + 1, dtype=np.int64)
     np.cumsum([pins.NPE[int(t)] for t in etypes], out=off[1:])
