@@ -386,13 +386,16 @@ def run_batched(steps, warmup, torch, nb, per_mesh_steps=2):
 
 
 def run_serving(meshes, torch, nb, rate_elems=None, n_req=5000, warm=500, slots=4, max_batch=64,
-                budget=64 << 30):
+                budget=64 << 30, device_inputs=False):
     """Requests drawn from the batch's meshes, admitted by a device-memory
     budget, continuous batching over `slots` streams.  Inputs start in
     pageable host memory; staging and upload are part of latency.  Arrivals
     are Poisson at `rate_elems` elements/s offered, or all at t = 0
-    (saturation: sustained throughput) when rate_elems is None.  Every
-    retired batch's device error word is checked; any error fails the run."""
+    (saturation: sustained throughput) when rate_elems is None.  With
+    device_inputs every request's connectivity is already a device tensor
+    (no host staging or upload), which isolates the device side of serving.
+    Every retired batch's device error word is checked; any error fails the
+    run."""
     import numpy as np
     from paper_1604_04689_amd import meshgen as mg
     from paper_1604_04689_amd import serve
@@ -408,7 +411,12 @@ def run_serving(meshes, torch, nb, rate_elems=None, n_req=5000, warm=500, slots=
     def on_complete(batch, executor):
         executor.check(batch)  # raises MeshError on any device error
 
-    reqs = [serve.Request(i, float(t), meshes[j].conn, meshes[j].etype, meshes[j].n_vert)
+    src = {}
+    if device_inputs:
+        for j in set(int(x) for x in pick):
+            src[j] = torch.as_tensor(meshes[j].conn).to("cuda:0")
+        torch.cuda.synchronize()
+    reqs = [serve.Request(i, float(t), src.get(int(j), meshes[j].conn), meshes[j].etype, meshes[j].n_vert)
             for i, (j, t) in enumerate(zip(pick, arr))]
     srv = serve.Server(ex, serve.RealClock(), n_slots=slots, budget_bytes=budget, max_batch=max_batch,
                        on_complete=on_complete)
@@ -420,8 +428,12 @@ def run_serving(meshes, torch, nb, rate_elems=None, n_req=5000, warm=500, slots=
     summ.update({"offered_elements_per_s": rate_elems, "arrivals": "poisson" if rate_elems else "all at t=0",
                  "slots": slots, "max_batch": max_batch, "budget_bytes": budget, "batches": srv.batches,
                  "mean_batch": float(np.mean(srv.batch_sizes)), "peak_reserved_bytes": srv.peak_in_use,
-                 "wall_s": wall, "warmup_requests": warm, "errors_checked": True})
+                 "wall_s": wall, "warmup_requests": warm, "errors_checked": True,
+                 "inputs": "device tensors" if device_inputs else "pageable host arrays (staged and uploaded)",
+                 "input_GBs": sum(4 * meshes[pick[r.rid]].conn.size for r in measured) / summ["span_s"] / 1e9})
     what = f"offered {rate_elems / 1e9:.2f} G elem/s" if rate_elems else "saturation"
+    if device_inputs:
+        what += ", device inputs"
     log(f"[bench] serve ({what}): {summ['requests']} requests: p50 {summ['p50_ms']:.2f} ms, "
         f"p99 {summ['p99_ms']:.2f} ms, {summ['elements_per_s'] / 1e9:.2f} G elem/s sustained, "
         f"{srv.batches} batches")
@@ -517,6 +529,9 @@ def main():
         meshes, others["batch512"] = run_batched(max(3, args.steps // 4), 1, torch, nb)
         sat = run_serving(meshes, torch, nb, rate_elems=None, n_req=args.serve_requests, warm=args.serve_warmup)
         others["serve_saturation"] = sat
+        others["serve_saturation_device_inputs"] = run_serving(meshes, torch, nb, rate_elems=None,
+                                                               n_req=args.serve_requests, warm=args.serve_warmup,
+                                                               device_inputs=True)
         capacity = sat["elements_per_s"]
         others["serve"] = {f"rho_{rho}": run_serving(meshes, torch, nb, rate_elems=rho * capacity,
                                                      n_req=args.serve_requests, warm=args.serve_warmup)

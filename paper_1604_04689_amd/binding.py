@@ -556,11 +556,12 @@ class BatchBuild:
         self._seg_pinned = self._seg_event = None
         self.reset(meshes, conn_offs=conn_offs)
 
-    def reset(self, meshes, stream=None, conn_offs=None):
+    def reset(self, meshes, stream=None, conn_offs=None, outputs=True):
         """Re-target at another batch.  The segment table is uploaded
         asynchronously on ``stream`` (default: the current stream), so reset
         and launch must use the same stream.  ``conn_offs`` places each mesh's
-        ids in the connectivity passed to launch (default: back to back)."""
+        ids in the connectivity passed to launch (default: back to back).
+        outputs=False leaves the outputs to the caller (set_outputs)."""
         import contextlib
 
         import torch
@@ -597,16 +598,18 @@ class BatchBuild:
             return buf
 
         self._ws_raw, self.workspace = _workspace(torch, self.ws_bytes, self.device, self._ws_raw)
-        self._rp = grow(self._rp, tot["vert"] + 1, torch.int32)
-        self.row_ptr = self._rp[:tot["vert"] + 1]
-        self._cols = grow(self._cols, self.cols_capacity, torch.int32)
-        self.cols = self._cols
         if self.kind == "both":
             self.elem_capacity = int(cap2.value)
-            self._erp = grow(self._erp, tot["vert"] + 1, torch.int32)
-            self.elem_row_ptr = self._erp[:tot["vert"] + 1]
-            self._ecols = grow(self._ecols, self.elem_capacity, torch.int32)
-            self.elem_cols = self._ecols
+        if outputs:
+            self._rp = grow(self._rp, tot["vert"] + 1, torch.int32)
+            self.row_ptr = self._rp[:tot["vert"] + 1]
+            self._cols = grow(self._cols, self.cols_capacity, torch.int32)
+            self.cols = self._cols
+            if self.kind == "both":
+                self._erp = grow(self._erp, tot["vert"] + 1, torch.int32)
+                self.elem_row_ptr = self._erp[:tot["vert"] + 1]
+                self._ecols = grow(self._ecols, self.elem_capacity, torch.int32)
+                self.elem_cols = self._ecols
         nbytes = 48 * len(meshes)
         self._segs = grow(self._segs, max(nbytes, 1), torch.uint8)
         if nbytes:
@@ -622,6 +625,30 @@ class BatchBuild:
                 self._seg_event = torch.cuda.Event()
                 self._seg_event.record()
         self.segs = self._segs
+
+    def output_sizes(self):
+        """Entries the current batch needs in each output: (row_ptr, cols)
+        or, building both, (row_ptr, cols, elem row_ptr, elem cols)."""
+        n = self.totals["vert"] + 1
+        if self.kind == "both":
+            return n, max(self.cols_capacity, 1), n, max(self.elem_capacity, 1)
+        return n, max(self.cols_capacity, 1)
+
+    def set_outputs(self, bufs):
+        """Write the next launches into the caller's int32 device tensors
+        (at least output_sizes() entries each), so that the previous
+        launch's results stay valid for whoever still holds them; returns the
+        views in use."""
+        sizes = self.output_sizes()
+        if len(bufs) != len(sizes) or any(b.numel() < n for b, n in zip(bufs, sizes)):
+            raise ValueError("output buffers smaller than the batch needs")
+        self._rp, self._cols = bufs[0], bufs[1]
+        self.row_ptr, self.cols = bufs[0][:sizes[0]], bufs[1]
+        if self.kind == "both":
+            self._erp, self._ecols = bufs[2], bufs[3]
+            self.elem_row_ptr, self.elem_cols = bufs[2][:sizes[2]], bufs[3]
+            return self.row_ptr, self.cols, self.elem_row_ptr, self.elem_cols
+        return self.row_ptr, self.cols
 
     def _args(self, conn):
         t = self.totals

@@ -17,6 +17,8 @@ size_t plan_erows(int64_t n_entries, int slots, int32_t n_vert, size_t off, size
     off += align_up((size_t)p->lb_words * sizeof(uint32_t));
     p->off_tf = off;
     off += align_up(((size_t)p->n_tiles + 1) * sizeof(int32_t));
+    p->off_tc = off;
+    off += align_up(((size_t)p->n_tiles + 1) * sizeof(int32_t));
     p->off_list = off;
     off += align_up((size_t)p->long_cap * sizeof(int32_t));
     p->off_deg = off;
@@ -33,7 +35,8 @@ size_t plan_erows(int64_t n_entries, int slots, int32_t n_vert, size_t off, size
 
 ErowsBufs erows_bufs(const ErowsPlan& er, char* ws, uint32_t* err, uint32_t* ticket) {
     uint32_t* hdr = (uint32_t*)ws;
-    return ErowsBufs{(int32_t*)(ws + er.off_tf),   (int32_t*)(ws + er.off_list), er.long_cap,
+    return ErowsBufs{(int32_t*)(ws + er.off_tf),   (int32_t*)(ws + er.off_tc),   (int32_t*)(ws + er.off_list),
+                     er.long_cap,
                      hdr + HDR_LONG_COUNT,          (int32_t*)(ws + er.off_deg),  (int32_t*)(ws + er.off_temp),
                      (uint64_t*)(ws + er.off_lb),   ticket,                       err};
 }

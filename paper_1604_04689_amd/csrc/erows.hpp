@@ -104,6 +104,7 @@ struct UniformRows {
         bool ok, bad;
     };
     __device__ __forceinline__ int32_t ctx(int32_t) const { return 0; }
+    __device__ __forceinline__ int32_t ctx_from(int32_t, int32_t) const { return 0; }
     __device__ __forceinline__ Loc locate(int32_t, int32_t, int32_t e, bool in) const {
         const bool valid = (uint64_t)(uint32_t)e < (uint64_t)n_elem;
         return Loc{(uint32_t)e, in && valid, in && !valid};
@@ -164,6 +165,7 @@ struct MixedRows {
         bool ok, bad;
     };
     __device__ __forceinline__ int32_t ctx(int32_t) const { return 0; }
+    __device__ __forceinline__ int32_t ctx_from(int32_t, int32_t) const { return 0; }
     __device__ __forceinline__ Loc locate(int32_t, int32_t, int32_t e, bool in) const {
         Loc l{0, 0, false, false};
         if (!in) return l;
@@ -217,6 +219,13 @@ struct BatchRows {
             else hi = mid - 1;
         }
         return lo;
+    }
+    // The mesh of v >= the first vertex of mesh m0: walk forward from m0 (a
+    // tile's rows span few meshes, so this is a step or two, not a search).
+    __device__ __forceinline__ int32_t ctx_from(int32_t m0, int32_t v) const {
+        int32_t m = m0 < 0 ? 0 : m0;
+        while (m + 1 < n_mesh && segs[m + 1].vert_off <= v) ++m;
+        return m;
     }
     __device__ __forceinline__ Loc locate(int32_t m, int32_t v, int32_t e, bool in) const {
         Loc l{0, 0, 0, 0, false, false};
@@ -283,11 +292,15 @@ __device__ __forceinline__ int64_t erow_total(const int32_t* __restrict__ erp, i
 }
 
 // tile_first[t] = first vertex v (in [0, n_vert], n_vert standing for "none")
+// whose element row starts at or after t * ER_TILE, and tile_ctx[t] its
+// accessor context (the mesh of v in a batch; found once per tile here)
 // whose element row starts at or after t * ER_TILE; rows longer than
 // ER_ROW_MAX entries go to the long list.  One thread per v in [0, n_vert].
-static __global__ __launch_bounds__(ER_PREP_BLOCK) void erows_prep_kernel(const int32_t* __restrict__ erp,
+template <class Acc>
+__global__ __launch_bounds__(ER_PREP_BLOCK) void erows_prep_kernel(Acc acc, const int32_t* __restrict__ erp,
                                                                          int32_t n_vert, int64_t q_bound,
                                                                          int32_t* __restrict__ tile_first,
+                                                                         int32_t* __restrict__ tile_ctx,
                                                                          int64_t n_tiles_bound,
                                                                          int32_t* __restrict__ long_list,
                                                                          int64_t long_cap, uint32_t* long_count,
@@ -299,7 +312,13 @@ static __global__ __launch_bounds__(ER_PREP_BLOCK) void erows_prep_kernel(const 
     const int64_t cur = v < n_vert ? tmin<int64_t>(tmax<int64_t>(erp[v], 0), q) : q;
     // tiles t with prev < t * ER_TILE <= cur
     const int64_t t0 = (prev + ER_TILE) / ER_TILE, t1 = tmin<int64_t>(cur / ER_TILE, n_tiles_bound - 1);
-    for (int64_t t = t0; t <= t1; ++t) tile_first[t] = (int32_t)v;
+    if (t0 <= t1) {
+        const int32_t cx = Acc::kCtx && v < n_vert ? acc.ctx((int32_t)v) : 0;
+        for (int64_t t = t0; t <= t1; ++t) {
+            tile_first[t] = (int32_t)v;
+            tile_ctx[t] = cx;
+        }
+    }
     if (v < n_vert) {
         int32_t a;
         bool bad = false;
@@ -374,6 +393,7 @@ __global__ __launch_bounds__(ER_BLOCK) void erows_tile_kernel(Acc acc, const int
                                                              const int32_t* __restrict__ ecols, int32_t n_vert,
                                                              int64_t q_bound, int64_t ecap,
                                                              const int32_t* __restrict__ tile_first,
+                                                             const int32_t* __restrict__ tile_ctx,
                                                              int32_t* __restrict__ cnt, int32_t* __restrict__ stage,
                                                              uint32_t* err) {
     constexpr int S = Acc::S;
@@ -421,6 +441,7 @@ __global__ __launch_bounds__(ER_BLOCK) void erows_tile_kernel(Acc acc, const int
     int32_t v_end = last_tile ? n_vert : tile_first[t + 1];
     v_first = tmin<int32_t>(tmax<int32_t>(v_first, 0), n_vert);
     v_end = tmin<int32_t>(tmax<int32_t>(v_end, v_first), n_vert);
+    const int32_t ctx0 = Acc::kCtx ? tile_ctx[t] : 0;
     auto early = [&](int i) { return kEarly && i * ER_BLOCK + tid < ER_TILE + WAVE; };
     typename Acc::Loc loc[ER_EPT];
     int32_t ids[ER_EPT][Acc::IDS];
@@ -454,7 +475,7 @@ __global__ __launch_bounds__(ER_BLOCK) void erows_tile_kernel(Acc acc, const int
             s_rv[k] = v;
             s_rds[k] = 0;
             s_rde[k] = 0;
-            if constexpr (Acc::kCtx) s_rctx[k] = acc.ctx(v);
+            if constexpr (Acc::kCtx) s_rctx[k] = acc.ctx_from(ctx0, v);
         }
         nrows += (int32_t)total;
     }
@@ -666,13 +687,14 @@ static __global__ __launch_bounds__(EG_BLOCK) void erows_gather_kernel(const int
     if (bad) set_error(err, ERR_INTERNAL);
 }
 
-// Buffers of the stage (inside the workspace): tile_first (n_tiles_bound + 1
-// ints), the long-row list and its counter (zero on entry), cnt (n_vert + 1
+// Buffers of the stage (inside the workspace): tile_first and tile_ctx
+// (n_tiles_bound + 1 ints each), the long-row list and its counter (zero on entry), cnt (n_vert + 1
 // ints: each row's distinct count, then the scan's input), stage (S *
 // q_bound ints, free memory: it may alias dead buffers), the scan's look-back
 // words (zero on entry) and ticket.
 struct ErowsBufs {
     int32_t* tile_first;
+    int32_t* tile_ctx;
     int32_t* long_list;
     int64_t long_cap;
     uint32_t* long_count;
@@ -698,8 +720,9 @@ hipError_t launch_erows(const char* tag, const Acc& acc, const int32_t* erp, con
     const int64_t n_tiles = erows_tiles_bound(q_bound);
     char name[48];
     snprintf(name, sizeof name, "%s_erows_prep", tag);
-    hipError_t e = launch(name, erows_prep_kernel, dim3((unsigned)ceil_div((int64_t)n_vert + 1, ER_PREP_BLOCK)),
-                          dim3(ER_PREP_BLOCK), s, erp, n_vert, q_bound, b.tile_first, n_tiles, b.long_list,
+    hipError_t e = launch(name, erows_prep_kernel<Acc>, dim3((unsigned)ceil_div((int64_t)n_vert + 1, ER_PREP_BLOCK)),
+                          dim3(ER_PREP_BLOCK), s, acc, erp, n_vert, q_bound, b.tile_first, b.tile_ctx, n_tiles,
+                          b.long_list,
                           erows_long_cap(q_bound), b.long_count, b.err);
     if (e == hipSuccess) {
         snprintf(name, sizeof name, "%s_erows_long", tag);
@@ -710,7 +733,8 @@ hipError_t launch_erows(const char* tag, const Acc& acc, const int32_t* erp, con
     if (e == hipSuccess) {
         snprintf(name, sizeof name, "%s_erows", tag);
         e = launch(name, erows_tile_kernel<Acc>, dim3((unsigned)n_tiles), dim3(ER_BLOCK), s, acc, erp, ecols,
-                   n_vert, q_bound, ecap, (const int32_t*)b.tile_first, b.cnt, b.stage, b.err);
+                   n_vert, q_bound, ecap, (const int32_t*)b.tile_first, (const int32_t*)b.tile_ctx, b.cnt, b.stage,
+                   b.err);
     }
     if (e == hipSuccess && n_vert == 0) e = fill_i32(row_ptr, 1, 0, s);
     if (e == hipSuccess) {

@@ -87,6 +87,7 @@ struct ErowsPlan {
     size_t off_lb = 0;        // count scan look-back words (cleared by the call's fill)
     int64_t lb_words = 0;     // their size in 32-bit words
     size_t off_tf = 0;        // first owned vertex of every tile
+    size_t off_tc = 0;        // accessor context (mesh in a batch) of that vertex
     size_t off_list = 0;      // long rows
     size_t off_deg = 0;       // distinct count of every row (n_vert + 1 ints)
     size_t off_temp = 0;      // staged values: S * n_entries ints

@@ -6,8 +6,15 @@ that have arrived and are waiting are admitted in arrival order while their
 reserved device memory fits the budget (the pair/key buffers dominate), and
 go out together as one batched launch on that slot; launches on different
 slots overlap on the device.  A request that arrives while others run waits
-only for the next free slot and for memory.  Results stay resident on the
-device until released; latency = completion - arrival.
+only for the next free slot and for memory; latency = completion - arrival.
+
+Results stay resident on the device: when its batch completes, every request
+gets a ``ResultHandle`` (``request.result``) over its slices of the batch's
+output tensors, which no later batch overwrites.  The budget keeps counting a
+result's bytes until the client calls ``release()`` on it, so results the
+client holds on to make later requests wait for memory.  With
+``keep_results=False`` (the default) the server releases each result right
+after the completion callback has seen it.
 
 The executor is pluggable:
 
@@ -22,6 +29,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import functools
 import heapq
 import math
 import time
@@ -36,35 +44,101 @@ from . import binding as _b
 class Request:
     rid: int
     arrival: float          # seconds on the server clock
-    conn: np.ndarray        # int32 [n_elem, npe], local ids
+    conn: np.ndarray        # int32 [n_elem, npe], local ids (host array, or a torch device tensor)
     etype: int
     n_vert: int
     reserve: int = 0        # device bytes reserved while in flight (set by the server)
+    resident: int = 0       # of which held after completion until the result is released
     admitted: float = math.nan
     completed: float = math.nan
     prep: object = None     # executor state once the upload has started
+    result: object = None   # ResultHandle once completed
 
     @property
     def n_elem(self) -> int:
-        return int(self.conn.shape[0])
+        return int(self.conn.shape[0])  # numpy array, or a device tensor of the same shape
 
     @property
     def latency(self) -> float:
         return self.completed - self.arrival
 
 
+@functools.lru_cache(maxsize=1 << 16)
+def output_bytes(n_elem: int, etype: int, n_vert: int) -> int:
+    """Device bytes of one request's results (both CSRs at their worst-case
+    capacity), held from its launch until the client releases them."""
+    npe, k = _b.NODES_PER_ELEM[etype], _b.EDGES_PER_ELEM[etype]
+    return 4 * (2 * k * n_elem + npe * n_elem) + 8 * (n_vert + 1)
+
+
+@functools.lru_cache(maxsize=1 << 16)
 def reserve_bytes(n_elem: int, etype: int, n_vert: int) -> int:
     """Device bytes one request holds while in flight: the workspace of one
     call building both relations, both outputs, and its connectivity (the
-    library's own sizing, under the tuned options of a mesh of its size)."""
+    library's own sizing, under the tuned options of a mesh of its size).
+    The outputs (output_bytes) stay held after completion until released."""
     from . import autotune
-    ws, cap_n, cap_e = _b.query("both", n_elem, etype, n_vert, autotune.options_for("both", etype, n_elem))
+    ws, _, _ = _b.query("both", n_elem, etype, n_vert, autotune.options_for("both", etype, n_elem))
     npe = _b.NODES_PER_ELEM[etype]
-    return ws + 4 * (cap_n + cap_e) + 8 * (n_vert + 1) + 4 * npe * n_elem
+    return ws + output_bytes(n_elem, etype, n_vert) + 4 * npe * n_elem
 
 
 class BudgetError(ValueError):
     pass
+
+
+class ResultHandle:
+    """One served request's node and element CSRs, resident where the
+    executor left them (device tensors for the GPU executor) until
+    ``release()``.  ``node()`` / ``elem()`` give (row_ptr, cols) views of
+    the batch's output (row_ptr still holding the batch's offsets; subtract
+    ``node_base`` / ``elem_base``, or use ``node_csr()`` / ``elem_csr()``
+    which do); ``to_host()`` copies both CSRs, rebased, to numpy arrays."""
+
+    def __init__(self, node, elem, node_base, elem_base, on_release):
+        self._node, self._elem = node, elem
+        self.node_base, self.elem_base = node_base, elem_base
+        self._on_release = on_release
+
+    @property
+    def released(self) -> bool:
+        return self._node is None
+
+    def _live(self):
+        if self._node is None:
+            raise ValueError("result was released")
+
+    def node(self):
+        self._live()
+        return self._node
+
+    def elem(self):
+        self._live()
+        return self._elem
+
+    def node_csr(self):
+        rp, cols = self.node()
+        return rp - self.node_base, cols
+
+    def elem_csr(self):
+        rp, cols = self.elem()
+        return rp - self.elem_base, cols
+
+    def to_host(self):
+        """((node row_ptr, cols), (elem row_ptr, cols)) as numpy arrays."""
+        def host(x):
+            return x.cpu().numpy() if hasattr(x, "cpu") else np.asarray(x)
+        (nr, nc), (er, ec) = self.node_csr(), self.elem_csr()
+        return (host(nr), host(nc)), (host(er), host(ec))
+
+    def release(self):
+        """Give the result's memory back (idempotent)."""
+        if self._node is None:
+            return
+        self._node = self._elem = None
+        cb, self._on_release = self._on_release, None
+        if cb is not None:
+            cb()
 
 
 @dataclasses.dataclass
@@ -98,6 +172,15 @@ class FakeExecutor:
 
     def results(self, batch: BatchHandle):
         return batch.payload
+
+    def handles(self, batch: BatchHandle, on_release):
+        """One ResultHandle per request over the computed host arrays (None
+        entries when there is no compute function)."""
+        out = []
+        for i, r in enumerate(batch.requests):
+            res = batch.payload[i] if batch.payload is not None else ((None, None), (None, None))
+            out.append(ResultHandle(res[0], res[1], 0, 0, (lambda r=r: on_release(r))))
+        return out
 
     def release(self, batch: BatchHandle):
         self.finish.pop(id(batch), None)
@@ -143,6 +226,14 @@ class Arena:
         return sum(self.used.values())
 
 
+def _n_ids(conn) -> int:
+    return int(conn.numel()) if hasattr(conn, "numel") else int(conn.size)
+
+
+def _on_device(conn) -> bool:
+    return hasattr(conn, "is_cuda") and conn.is_cuda
+
+
 class GpuExecutor:
     """Runs each batch on its slot's stream through the batched C entry points.
 
@@ -154,8 +245,12 @@ class GpuExecutor:
     separate upload stream, so uploads overlap the batches already running.
     A batch only writes its segment records (which point into the arena) and
     launches; its slot stream waits for its requests' uploads.  A range is
-    free again once its batch has completed.  Each slot keeps its device
-    buffers across batches (they only grow)."""
+    free again once its batch has completed.  Each slot keeps its workspace
+    across batches (it only grows); a batch's outputs come from a pool of
+    output sets and go back to it when every result of the batch has been
+    released, so steady serving allocates nothing."""
+
+    COPY_TASK_IDS = 1 << 20  # ids one host-copy task copies at least (fewer, larger tasks)
 
     def __init__(self, n_slots: int, device="cuda:0", copy_threads: int = 8, arena_ids: int = 1 << 28):
         import concurrent.futures
@@ -173,6 +268,8 @@ class GpuExecutor:
         self.pin_np = self.pin.numpy()
         self.staging = collections.deque()  # prepared, upload not yet issued, in prepare order
         self.pool = concurrent.futures.ThreadPoolExecutor(max(copy_threads, 1))
+        self.free_outs = []  # output sets whose results were all released
+        self.dev_pending, self.host_pending = [], []  # prepared, upload not started
 
     def _copy_in(self, conn: np.ndarray, off: int):
         flat = conn.reshape(-1)
@@ -209,16 +306,54 @@ class GpuExecutor:
             r.prep[2] = ev
 
     def prepare(self, r: Request) -> bool:
-        """Start staging and uploading r; False if the arena is full now."""
-        if r.conn.size > self.arena.capacity:
-            raise BudgetError(f"request {r.rid} has {r.conn.size} ids, the arena holds {self.arena.capacity}")
-        off = self.arena.alloc(r.conn.size)
+        """Give r an arena range and queue its upload (started by commit());
+        False if the arena is full now.  A request whose connectivity is
+        already a device tensor is copied into the arena on the upload stream
+        (no host staging)."""
+        n = _n_ids(r.conn)
+        if n > self.arena.capacity:
+            raise BudgetError(f"request {r.rid} has {n} ids, the arena holds {self.arena.capacity}")
+        off = self.arena.alloc(n)
         if off is None:
             return False
-        r.prep = [off, self.pool.submit(self._copy_in, r.conn, off), None]  # range, host copy, upload event
-        self.staging.append(r)
-        self._flush()
+        r.prep = [off, None, None]  # range, host copy, upload event
+        (self.dev_pending if _on_device(r.conn) else self.host_pending).append(r)
         return True
+
+    def commit(self):
+        """Start the uploads of every request prepared since the last commit:
+        device inputs as copies on the upload stream behind one event, host
+        inputs as a few worker tasks (each copying several requests into the
+        pinned twin), uploaded as their copies finish."""
+        torch = self.torch
+        if self.dev_pending:
+            self.upload.wait_stream(torch.cuda.current_stream(self.device))  # the tensors' producers
+            with torch.cuda.stream(self.upload):
+                for r in self.dev_pending:
+                    off = r.prep[0]
+                    self.arena_buf[off:off + _n_ids(r.conn)].copy_(r.conn.reshape(-1), non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(self.upload)
+            for r in self.dev_pending:
+                r.prep[2] = ev
+            self.dev_pending = []
+        if self.host_pending:
+            group, ids = [], 0
+            for i, r in enumerate(self.host_pending):
+                group.append(r)
+                ids += r.conn.size
+                if ids >= self.COPY_TASK_IDS or i + 1 == len(self.host_pending):
+                    fut = self.pool.submit(self._copy_group, [(x.conn, x.prep[0]) for x in group])
+                    for x in group:
+                        x.prep[1] = fut
+                        self.staging.append(x)
+                    group, ids = [], 0
+            self.host_pending = []
+            self._flush()
+
+    def _copy_group(self, items):
+        for conn, off in items:
+            self._copy_in(conn, off)
 
     def submit(self, batch: BatchHandle):
         torch = self.torch
@@ -226,6 +361,7 @@ class GpuExecutor:
         s = self.streams[batch.slot]
         desc = [(r.n_elem, r.etype, r.n_vert) for r in batch.requests]
         offs = []
+        self.commit()
         for r in batch.requests:
             if r.prep[2] is None:
                 self._flush(until=r)
@@ -236,11 +372,31 @@ class GpuExecutor:
                 st = self.slot_state[batch.slot] = _b.BatchBuild("both", desc, self.device, conn_offs=offs,
                                                                  options="tuned")
             else:
-                st.reset(desc, s, conn_offs=offs)
+                st.reset(desc, s, conn_offs=offs, outputs=False)
+            oset = self._take_outputs(st.output_sizes())
+            outs = st.set_outputs(oset["bufs"])  # this batch's results outlive the slot's next batch
             st.launch(self.arena_buf, s)
             ev = torch.cuda.Event()
             ev.record(s)
-        batch.payload = {"build": st, "event": ev}
+        oset["refs"] = len(batch.requests)
+        batch.payload = {"build": st, "event": ev, "outs": outs, "seg": st.seg_host, "oset": oset}
+
+    def _take_outputs(self, sizes):
+        """An output set (node row_ptr, cols, elem row_ptr, cols) holding at
+        least `sizes` entries: a released one when one is large enough, else a
+        new one with some headroom.  A set returns to the pool once every
+        result handle of its batch is released."""
+        for i, o in enumerate(self.free_outs):
+            if all(b.numel() >= n for b, n in zip(o["bufs"], sizes)):
+                return self.free_outs.pop(i)
+        torch = self.torch
+        bufs = [torch.empty(int(n * 1.25) + 64, dtype=torch.int32, device=self.device) for n in sizes]
+        return {"bufs": bufs, "refs": 0}
+
+    def _put_outputs(self, oset):
+        oset["refs"] -= 1
+        if oset["refs"] == 0:
+            self.free_outs.append(oset)
 
     def done(self, batch: BatchHandle) -> bool:
         return batch.payload["event"].query()
@@ -248,26 +404,55 @@ class GpuExecutor:
     def next_completion(self, batch: BatchHandle) -> float:
         return math.nan
 
+    def _bounds(self, batch: BatchHandle):
+        """Row starts of every request's slices (one device-to-host copy of
+        2 x (requests + 1) entries of the completed batch's row pointers)."""
+        p = batch.payload
+        if "bounds" not in p:
+            torch = self.torch
+            idx = torch.as_tensor(np.append(p["seg"]["vert_off"], p["build"].totals["vert"]).astype(np.int64),
+                                  device=self.device)
+            nrp, erp = p["outs"][0], p["outs"][2]
+            both = torch.stack([nrp.index_select(0, idx), erp.index_select(0, idx)])
+            p["bounds"] = both.cpu().numpy()
+        return p["bounds"]
+
+    def handles(self, batch: BatchHandle, on_release):
+        """One ResultHandle per request: device views into the batch's own
+        output tensors, which stay allocated while any handle holds them."""
+        p = batch.payload
+        b = self._bounds(batch)
+        nrp, ncol, erp, ecol = p["outs"]
+        out = []
+        for i, seg in enumerate(p["seg"]):
+            v0, nv = int(seg["vert_off"]), int(seg["n_vert"])
+            a, bb, c, d = int(b[0, i]), int(b[0, i + 1]), int(b[1, i]), int(b[1, i + 1])
+            r = batch.requests[i]
+
+            def done(r=r, oset=p["oset"]):
+                on_release(r)
+                self._put_outputs(oset)
+            out.append(ResultHandle((nrp[v0:v0 + nv + 1], ncol[a:bb]), (erp[v0:v0 + nv + 1], ecol[c:d]), a, c, done))
+        return out
+
     def results(self, batch: BatchHandle):
         """Per request: ((node row_ptr, cols), (elem row_ptr, cols)) as host arrays."""
         p = batch.payload
-        s = self.streams[batch.slot]
+        nrp, ncol, erp, ecol = (x.cpu().numpy() for x in p["outs"])
+        b = self._bounds(batch)
         out = []
-        (node_rp, node_cols), (elem_rp, elem_cols) = p["build"].result(s)
-        nrp, ncol = node_rp.cpu().numpy(), node_cols.cpu().numpy()
-        erp, ecol = elem_rp.cpu().numpy(), elem_cols.cpu().numpy()
-        for seg in p["build"].seg_host:
+        for i, seg in enumerate(p["seg"]):
             v0, nv = int(seg["vert_off"]), int(seg["n_vert"])
-            a, b = int(nrp[v0]), int(nrp[v0 + nv])
-            c, d = int(erp[v0]), int(erp[v0 + nv])
-            out.append(((nrp[v0:v0 + nv + 1] - a, ncol[a:b]), (erp[v0:v0 + nv + 1] - c, ecol[c:d])))
+            a, bb, c, d = int(b[0, i]), int(b[0, i + 1]), int(b[1, i]), int(b[1, i + 1])
+            out.append(((nrp[v0:v0 + nv + 1] - a, ncol[a:bb]), (erp[v0:v0 + nv + 1] - c, ecol[c:d])))
         return out
 
     def check(self, batch: BatchHandle):
         batch.payload["build"].check(self.streams[batch.slot])
 
     def release(self, batch: BatchHandle):
-        # the batch has completed, so the arena ranges it read are free again
+        # the batch has completed, so the arena ranges it read are free again;
+        # its outputs live on in the result handles that still reference them
         for r in batch.requests:
             if getattr(r, "prep", None) is not None:
                 self.arena.release(r.prep[0])
@@ -302,7 +487,8 @@ class Server:
     """Continuous batching over ``n_slots`` slots under ``budget_bytes``."""
 
     def __init__(self, executor, clock, n_slots=4, budget_bytes=64 << 30, max_batch=64,
-                 on_complete: Optional[Callable] = None, reserve: Callable = reserve_bytes, max_staged=64):
+                 on_complete: Optional[Callable] = None, reserve: Callable = reserve_bytes, max_staged=None,
+                 keep_results: bool = False, resident: Callable = output_bytes):
         self.ex = executor
         self.clock = clock
         self.n_slots = n_slots
@@ -310,9 +496,14 @@ class Server:
         self.max_batch = max_batch
         self.on_complete = on_complete
         self.reserve = reserve
-        self.max_staged = max_staged  # uploads started ahead of admission, at most
+        # uploads started ahead of admission, at most (default: enough to fill every slot twice)
+        self.max_staged = max_staged if max_staged is not None else 2 * n_slots * max_batch
+        self.keep_results = keep_results
+        self.resident_fn = resident
         self.admitted = 0
-        self.in_use = 0
+        self.in_use = 0           # reserved bytes: in-flight requests and unreleased results
+        self.resident_bytes = 0   # of which held by completed, unreleased results
+        self.unreleased = 0
         self.peak_in_use = 0
         self.batches = 0
         self.batch_sizes = []
@@ -344,26 +535,39 @@ class Server:
         self.batch_sizes.append(len(take))
         return b
 
+    def _release_result(self, r: Request):
+        self.in_use -= r.resident
+        self.resident_bytes -= r.resident
+        self.unreleased -= 1
+
     def _retire(self, slot: int):
         b = self.running.pop(slot)
         now = self.clock.now()
         for r in b.requests:
             r.completed = now
+            self.in_use -= r.reserve - r.resident  # the workspace and inputs are free; results stay
+            self.resident_bytes += r.resident
+            self.unreleased += 1
+        for r, h in zip(b.requests, self.ex.handles(b, self._release_result)):
+            r.result = h
         if self.on_complete is not None:
             self.on_complete(b, self.ex)
-        for r in b.requests:
-            self.in_use -= r.reserve
         self.ex.release(b)
+        if not self.keep_results:
+            for r in b.requests:
+                r.result.release()
 
     def run(self, requests: List[Request]) -> List[Request]:
         """Serve the requests (sorted by arrival) to completion."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         for r in reqs:
             r.reserve = self.reserve(r.n_elem, r.etype, r.n_vert)
+            r.resident = min(self.resident_fn(r.n_elem, r.etype, r.n_vert), r.reserve)
             if r.reserve > self.budget:
                 raise BudgetError(f"request {r.rid} needs {r.reserve} bytes, budget is {self.budget}")
         self.waiting.extend(reqs)
         prepare = getattr(self.ex, "prepare", None)
+        commit = getattr(self.ex, "commit", None)
         next_prep = 0  # requests are prepared in arrival order as they arrive
         first = self.admitted
         while self.waiting or self.running:
@@ -375,6 +579,8 @@ class Server:
                     if not prepare(reqs[next_prep]):
                         break  # arena full: retry once a batch has released its ranges
                     next_prep += 1
+                if commit is not None:
+                    commit()
             for slot in list(self.running):
                 if self.ex.done(self.running[slot]):
                     self._retire(slot)
@@ -391,6 +597,11 @@ class Server:
                 nxt.append(self.waiting[0].arrival)
             if nxt:
                 self.clock.wait_until(min(nxt))
+            elif not self.running and self.waiting and self.in_use + self.waiting[0].reserve > self.budget:
+                # nothing runs, and unreleased results hold the memory the next request needs
+                raise BudgetError(f"request {self.waiting[0].rid} waits for {self.waiting[0].reserve} bytes, but "
+                                  f"{self.resident_bytes} bytes of the {self.budget}-byte budget are held by "
+                                  f"{self.unreleased} unreleased results")
         return reqs
 
 

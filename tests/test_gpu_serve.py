@@ -91,3 +91,26 @@ def test_served_full_distribution_equals_alone(oracle_mod):
         (gnr, gnc), (ger, gec) = got[r.rid]
         assert np.array_equal(gnr, wn[0]) and np.array_equal(gnc, wn[1]), r.rid
         assert np.array_equal(ger, we[0]) and np.array_equal(gec, we[1]), r.rid
+
+
+def test_served_results_stay_resident_until_released(oracle_mod):
+    """keep_results: each request's CSRs stay in device memory, untouched by
+    the later batches that reuse its slot, until the client releases them;
+    every one equals the oracle's, element by element."""
+    from paper_1604_04689_amd import serve
+    reqs = make_requests(30, rate=20000.0, seed=13)
+    srv = serve.Server(serve.GpuExecutor(2), serve.RealClock(), n_slots=2, budget_bytes=1 << 34, max_batch=4,
+                       keep_results=True, on_complete=lambda b, ex: ex.check(b))
+    done = srv.run(reqs)
+    assert srv.batches > 2 and srv.unreleased == len(reqs)  # slots were reused while results were held
+    for r in done:
+        rp, cols = r.result.node()
+        assert rp.device.type == "cuda" and cols.device.type == "cuda"
+        wn = oracle_mod.node_neighbors(r.conn, r.etype, r.n_vert)
+        we = oracle_mod.elem_neighbors(r.conn, r.etype, r.n_vert)
+        (gnr, gnc), (ger, gec) = r.result.to_host()
+        assert np.array_equal(gnr, wn[0]) and np.array_equal(gnc, wn[1]), r.rid
+        assert np.array_equal(ger, we[0]) and np.array_equal(gec, we[1]), r.rid
+    for r in done:
+        r.result.release()
+    assert srv.resident_bytes == 0 and srv.in_use == 0

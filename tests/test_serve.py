@@ -139,3 +139,51 @@ def test_staged_executor_admits_only_prepared():
     # one arena room: the requests run one at a time, one second each
     assert sorted(r.completed for r in done) == [1.0, 2.0, 3.0]
     assert srv.batches == 3
+
+
+def test_results_resident_until_released(oracle_mod):
+    """keep_results: every request's result handle stays valid after later
+    batches ran, holds its bytes in the budget until released, and equals
+    the request computed alone."""
+    reqs = make_requests(20, rate=5000.0, seed=31)
+
+    def compute(r):
+        return (oracle_mod.node_neighbors(r.conn, r.etype, r.n_vert),
+                oracle_mod.elem_neighbors(r.conn, r.etype, r.n_vert))
+
+    srv, done = run(reqs, n_slots=2, budget_bytes=1 << 40, max_batch=4, compute=compute, keep_results=True)
+    held = sum(serve.output_bytes(r.n_elem, r.etype, r.n_vert) for r in reqs)
+    assert srv.resident_bytes == held and srv.in_use == held and srv.unreleased == len(reqs)
+    for r in done:
+        (nr, nc), (er, ec) = r.result.to_host()
+        (wnr, wnc), (wer, wec) = compute(r)
+        assert np.array_equal(nr, wnr) and np.array_equal(nc, wnc)
+        assert np.array_equal(er, wer) and np.array_equal(ec, wec)
+    for r in done:
+        r.result.release()
+        r.result.release()  # idempotent
+    assert srv.resident_bytes == 0 and srv.in_use == 0 and srv.unreleased == 0
+    with pytest.raises(ValueError):
+        done[0].result.node()
+
+
+def test_unreleased_results_hold_the_budget():
+    """A client that keeps its last two results: later requests are admitted
+    only as older results are released; one that keeps everything under a
+    budget too small for that is told why the server cannot go on.  Sizes
+    are set by hand: 10 bytes in flight, of which 4 stay with the result."""
+    sizes = dict(reserve=lambda *a: 10, resident=lambda *a: 4)
+    budget = 10 + 2 * 4  # one request in flight beside two kept results
+    kept = []
+
+    def keep_two(batch, ex):
+        kept.extend(r.result for r in batch.requests)
+        while len(kept) > 2:
+            kept.pop(0).release()
+
+    srv, done = run(make_requests(16, rate=1e6, seed=32), n_slots=2, budget_bytes=budget, max_batch=1,
+                    keep_results=True, on_complete=keep_two, **sizes)
+    assert len(done) == 16 and srv.peak_in_use <= budget and srv.unreleased == 2 and srv.in_use == 8
+    with pytest.raises(serve.BudgetError, match="unreleased results"):
+        run(make_requests(16, rate=1e6, seed=32), n_slots=2, budget_bytes=budget, max_batch=1, keep_results=True,
+            **sizes)
