@@ -418,6 +418,7 @@ def run_serving(meshes, torch, nb, rate_elems=None, n_req=5000, warm=500, slots=
         torch.cuda.synchronize()
     reqs = [serve.Request(i, float(t), src.get(int(j), meshes[j].conn), meshes[j].etype, meshes[j].n_vert)
             for i, (j, t) in enumerate(zip(pick, arr))]
+    ex.warm(reqs, max_batch)  # device buffers sized up front: no allocation while serving
     srv = serve.Server(ex, serve.RealClock(), n_slots=slots, budget_bytes=budget, max_batch=max_batch,
                        on_complete=on_complete)
     t0 = time.perf_counter()

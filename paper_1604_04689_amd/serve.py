@@ -381,6 +381,25 @@ class GpuExecutor:
         oset["refs"] = len(batch.requests)
         batch.payload = {"build": st, "event": ev, "outs": outs, "seg": st.seg_host, "oset": oset}
 
+    def warm(self, requests: List[Request], max_batch: int):
+        """Size every slot for the largest batch these requests can form (the
+        max_batch largest by directed pairs), and give each slot an output
+        set of that size, so that no device allocation happens while
+        serving.  Call before the server's clock starts."""
+        torch = self.torch
+        if not requests:
+            return
+        big = sorted(requests, key=lambda r: -_b.EDGES_PER_ELEM[r.etype] * r.n_elem)[:max_batch]
+        desc = [(r.n_elem, r.etype, r.n_vert) for r in big]
+        for i, s in enumerate(self.streams):
+            with torch.cuda.stream(s):
+                if self.slot_state[i] is None:
+                    self.slot_state[i] = _b.BatchBuild("both", desc, self.device, options="tuned")
+                else:
+                    self.slot_state[i].reset(desc, s, outputs=False)
+            self.free_outs.append(self._take_outputs(self.slot_state[i].output_sizes()))
+        torch.cuda.synchronize(self.device)
+
     def _take_outputs(self, sizes):
         """An output set (node row_ptr, cols, elem row_ptr, cols) holding at
         least `sizes` entries: a released one when one is large enough, else a
