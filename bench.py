@@ -48,6 +48,8 @@ WORKLOADS = {
 }
 
 SERVE_RHO = (0.5, 0.8, 0.95)
+# pair budgets of the bounded-memory build timed on the main workload
+CHUNK_BUDGETS = (1 << 20, 1 << 23)
 
 
 def log(*a):
@@ -195,7 +197,36 @@ def time_e2e(torch, nb, m, build, steps):
     return sec, bytes_moved
 
 
-def run_workload(name, steps, warmup, torch, nb, compare_sorts=True, e2e=True):
+def run_chunked(torch, nb, m, conn, build, stream, steps, budgets):
+    """The bounded-memory build (chunk_keys) of both relations at each pair
+    budget: time per step (one wait on the stream per call included),
+    workspace against the whole-mesh build's, ranges per call, and byte
+    equality with the whole-mesh result."""
+    ref = _snapshot(build)
+    out = {"whole_mesh_workspace_bytes": build.ws_bytes}
+    for cap in budgets:
+        b = nb.NeighborBuild("both", m.n_elem, m.etype, m.n_vert, conn.device, options={"chunk_keys": cap})
+        b.launch(conn, stream)
+        b.check(stream)
+        if not _same_as(b, ref):
+            raise RuntimeError(f"bounded-memory build (chunk_keys={cap}) differs from the whole-mesh result")
+        nb.timing_read()
+        nb.timing_enable(True)
+        n = max(3, steps // 2)
+        sec = _sync_time(torch, lambda: b.launch(conn, stream), n)
+        nb.timing_enable(False)
+        kt = nb.timing_read()
+        ranges = kt["chunk_elem_hist"][0] / n if "chunk_elem_hist" in kt else 0
+        out[f"chunk_keys_{cap}"] = {"ms_per_step": sec * 1e3, "elements_per_s": m.n_elem / sec,
+                                    "workspace_bytes": b.ws_bytes, "ranges_per_call": ranges}
+        log(f"[bench] {m.name} chunk_keys={cap}: {sec * 1e3:.3f} ms/step, {ranges:.0f} ranges, "
+            f"workspace {b.ws_bytes / 1e6:.1f} MB (whole mesh {build.ws_bytes / 1e6:.0f} MB)")
+        del b
+        torch.cuda.empty_cache()
+    return out
+
+
+def run_workload(name, steps, warmup, torch, nb, compare_sorts=True, e2e=True, chunk_budgets=()):
     log(f"[bench] generating {name} ...")
     t = time.time()
     m = make_mesh(name)
@@ -289,6 +320,8 @@ def run_workload(name, steps, warmup, torch, nb, compare_sorts=True, e2e=True):
             del b
             torch.cuda.empty_cache()
         res["by_node_sort"] = by_sort
+    if chunk_budgets:
+        res["chunked"] = run_chunked(torch, nb, m, conn, build, stream, steps, chunk_budgets)
     if e2e:
         s, nbytes = time_e2e(torch, nb, m, build, max(3, steps // 2))
         res["with_transfers"] = {"ms_per_step": s * 1e3, "elements_per_s": m.n_elem / s, "pcie_bytes": nbytes,
@@ -520,7 +553,8 @@ def main():
     if args.copy_calibration:
         copy_calibration(torch)
 
-    m, main_res = run_workload(args.workload, args.steps, args.warmup, torch, nb, compare_sorts=not args.no_compare)
+    m, main_res = run_workload(args.workload, args.steps, args.warmup, torch, nb, compare_sorts=not args.no_compare,
+                               chunk_budgets=CHUNK_BUDGETS if not args.no_compare else ())
     others = {}
     for w in [x for x in args.also.split(",") if x and x != args.workload]:
         _, others[w] = run_workload(w, args.steps, args.warmup, torch, nb, compare_sorts=not args.no_compare)

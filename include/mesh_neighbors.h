@@ -42,7 +42,8 @@
  *    (host pointer, may be NULL) selects speed-only choices for that call
  *    alone.  `stream` is a hipStream_t (NULL = the null stream).  Calls are
  *    asynchronous and stream-ordered; none synchronises the host except
- *    mesh_check.
+ *    mesh_check and a bounded-memory build (chunk_keys, below), which waits
+ *    once on its stream.
  *  - Argument errors are returned synchronously before anything is launched.
  *    Data errors found on the device (a vertex id outside [0, n_vert), more
  *    nnz than cols_capacity) are recorded in the workspace: the output is then
@@ -79,8 +80,10 @@ typedef enum {
     MESH_ERR_INDEX_RANGE = 6,      /* a connectivity id outside [0, n_vert)    */
     MESH_ERR_HIP = 7,              /* a HIP runtime call or launch failed       */
     MESH_ERR_INTERNAL = 8,         /* a device-side consistency guard tripped   */
-    MESH_ERR_SCRATCH_LIMIT = 9     /* mesh_neighbors_noalloc: the mesh needs more
+    MESH_ERR_SCRATCH_LIMIT = 9,    /* mesh_neighbors_noalloc: the mesh needs more
                                       scratch than MESH_NOALLOC_SCRATCH_BYTES      */
+    MESH_ERR_CHUNK = 10            /* bounded-memory build: one vertex bin holds
+                                      more pairs than chunk_keys               */
 } mesh_status;
 
 /* ------------------------------------------------------------------------ */
@@ -120,8 +123,32 @@ typedef struct {
     int32_t node_sort;    /* mesh_node_sort, or -1                               */
     int32_t radix_shape;  /* radix tile shape 0 .. mesh_radix_shape_count()-1, or -1 */
     int32_t digit_bits;   /* radix digit width: 8 or 11 bits per pass, or -1      */
-    int32_t reserved[5];  /* 0                                                    */
+    int32_t chunk_keys;   /* bounded-memory build: most pairs sorted at once, or
+                             -1 / 0 for the whole mesh at once (see below)     */
+    int32_t reserved[4];  /* 0                                                    */
 } mesh_options;
+
+/* Bounded-memory build (chunk_keys > 0).  The paper names the device memory
+ * its pair arrays take as the limit of its method and leaves a leaner
+ * variant to future work (Sec. 3.2.2, Sec. 4).  With chunk_keys set, a call
+ * builds the relations one vertex range at a time: a histogram of the
+ * (vertex, element) pairs over the top 11 bits of the vertex id is read back
+ * (the call waits on its stream once, so it cannot be captured into a
+ * graph), the host cuts [0, n_vert) at bin boundaries into ranges of at most
+ * chunk_keys pairs and chunk_keys vertices, and each range sorts only its own
+ * pairs (every range reads the whole connectivity) and writes its element
+ * rows, then derives its node rows, straight into the outputs.  The
+ * workspace holds O(chunk_keys) words plus a quarter byte per connectivity
+ * slot (the look-back status of the first radix pass, which reads every
+ * slot; half a byte from 2^30 slots on), where a whole-mesh build takes 17
+ * to 50 bytes per slot.  Results are identical.
+ * Applies to mesh_node_neighbors, mesh_elem_neighbors, mesh_neighbors (and
+ * their queries and mesh_neighbors_noalloc) under the ELEM_ROWS node
+ * algorithm with 8-bit digits; other entry points, node algorithms or
+ * digit_bits = 11 return MESH_ERR_INVALID_ARG, as does chunk_keys below
+ * 4096 or below the vertices of one bin (2^(bits of n_vert - 1) / 2^11).  A
+ * bin of more than chunk_keys pairs returns MESH_ERR_CHUNK (synchronously,
+ * after the histogram; the outputs are then unspecified). */
 
 /* Options with every field set to -1 (the library defaults). */
 mesh_options mesh_default_options(void);

@@ -29,6 +29,7 @@ class Status(enum.IntEnum):
     HIP = 7
     INTERNAL = 8
     SCRATCH_LIMIT = 9
+    CHUNK = 10
 
 
 class MeshError(RuntimeError):
@@ -47,23 +48,29 @@ NODE_SORT_NAMES = {0: "full_key", 1: "vertex_rows", 2: "edge_rows", 3: "elem_row
 
 
 class Options(ctypes.Structure):
-    """mesh_options: per-call speed-only choices (-1 = library default)."""
+    """mesh_options: per-call choices that never change results (-1 =
+    library default): node algorithm, radix tile shape, digit width, and
+    chunk_keys, the pair budget of a bounded-memory build (-1 or 0: the whole
+    mesh at once)."""
     _fields_ = [("node_sort", ctypes.c_int32), ("radix_shape", ctypes.c_int32), ("digit_bits", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("chunk_keys", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
     def as_dict(self):
         return {"node_sort": int(self.node_sort), "radix_shape": int(self.radix_shape),
-                "digit_bits": int(self.digit_bits)}
+                "digit_bits": int(self.digit_bits), "chunk_keys": int(self.chunk_keys)}
+
+
+OPTION_KEYS = ("node_sort", "radix_shape", "digit_bits", "chunk_keys")
 
 
 def make_options(options=None) -> Options:
     """Options from None (defaults), an Options, or a dict with any of
-    node_sort, radix_shape, digit_bits."""
+    node_sort, radix_shape, digit_bits, chunk_keys."""
     if isinstance(options, Options):
         return options
-    o = Options(-1, -1, -1)
+    o = Options(-1, -1, -1, -1)
     for k, v in (options or {}).items():
-        if k not in ("node_sort", "radix_shape", "digit_bits"):
+        if k not in OPTION_KEYS:
             raise ValueError(f"unknown option {k}")
         setattr(o, k, -1 if v is None else int(v))
     return o

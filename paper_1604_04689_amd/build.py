@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmeshnbr.so")
 SOURCES = ["api.hip", "node_path.hip", "elem_path.hip", "elem_rows.hip", "mixed_path.hip", "batch_path.hip",
-           "graph.hip", "timing.hip", "noalloc.hip"]
+           "graph.hip", "timing.hip", "noalloc.hip", "chunk_path.hip"]
 ARCH = os.environ.get("MESHNBR_ARCH", "gfx950")
 
 

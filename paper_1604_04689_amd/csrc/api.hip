@@ -67,15 +67,18 @@ hipError_t fill_regions(const FillRegion* r, int count, hipStream_t s) {
     return launch("fill", fill_set_kernel, dim3(grid), dim3(FILL_BLOCK), s, f);
 }
 
-bool resolve_options(const mesh_options* o, Opts* out) {
+bool resolve_options(const mesh_options* o, Opts* out, bool allow_chunk) {
     Opts r;
     if (o) {
         if (o->node_sort < -1 || o->node_sort > NS_ELEM_ROWS) return false;
         if (o->radix_shape < -1 || o->radix_shape >= N_RADIX_SHAPES) return false;
         if (o->digit_bits != -1 && o->digit_bits != 8 && o->digit_bits != 11) return false;
+        if (o->chunk_keys < -1 || (o->chunk_keys > 0 && (!allow_chunk || o->chunk_keys < CHUNK_MIN_KEYS)))
+            return false;
         if (o->node_sort >= 0) r.node_sort = o->node_sort;
         if (o->radix_shape >= 0) r.shape = o->radix_shape;
         r.digit_bits = o->digit_bits;
+        r.chunk_keys = o->chunk_keys > 0 ? o->chunk_keys : 0;
     }
     *out = r;
     return true;
@@ -153,6 +156,8 @@ struct SinglePlans {
     Opts o;
     NodePlan node;
     ElemPlan elem;
+    bool chunked = false;  // bounded-memory build (chunk_keys): `chunk` runs the call
+    ChunkPlan chunk;
 };
 
 enum Relations { REL_NODE = 1, REL_ELEM = 2, REL_BOTH = 3 };
@@ -161,7 +166,7 @@ static mesh_status plan_single(int64_t n_elem, int32_t etype, int32_t n_vert, co
                                int relations, bool node_internal_elem, SinglePlans* sp) {
     mesh_status st = check_sizes(n_elem, etype, n_vert);
     if (st != MESH_OK) return st;
-    if (!resolve_options(opts, &sp->o)) return MESH_ERR_INVALID_ARG;
+    if (!resolve_options(opts, &sp->o, /*allow_chunk=*/true)) return MESH_ERR_INVALID_ARG;
     // the relation's keys below 2^31: directed pairs for the node relation
     // (the larger count), node slots for the element relation alone
     if ((relations & REL_NODE) && n_elem > INT32_MAX / (2 * edges_per_elem(etype))) return MESH_ERR_OVERFLOW;
@@ -169,6 +174,12 @@ static mesh_status plan_single(int64_t n_elem, int32_t etype, int32_t n_vert, co
     if ((relations & REL_NODE) && !plan_node(n_elem, etype, n_vert, sp->o, node_internal_elem, &sp->node))
         return MESH_ERR_INVALID_ARG;
     if (!plan_elem(n_elem, etype, n_vert, sp->o, &sp->elem)) return MESH_ERR_INVALID_ARG;
+    if (sp->o.chunk_keys > 0) {
+        sp->chunked = true;
+        if (!plan_chunked(n_elem, etype, n_vert, sp->o, (relations & REL_NODE) != 0, (relations & REL_ELEM) != 0,
+                          &sp->chunk))
+            return MESH_ERR_INVALID_ARG;
+    }
     return MESH_OK;
 }
 
@@ -176,14 +187,15 @@ static mesh_status hip_status(hipError_t e) { return e == hipSuccess ? MESH_OK :
 
 extern "C" {
 
-int32_t mesh_abi_version(void) { return (2 << 16) | 1; }
+int32_t mesh_abi_version(void) { return (2 << 16) | 2; }
 
 mesh_options mesh_default_options(void) {
     mesh_options o;
     o.node_sort = -1;
     o.radix_shape = -1;
     o.digit_bits = -1;
-    for (int i = 0; i < 5; ++i) o.reserved[i] = 0;
+    o.chunk_keys = -1;
+    for (int i = 0; i < 4; ++i) o.reserved[i] = 0;
     return o;
 }
 
@@ -199,6 +211,7 @@ const char* mesh_status_string(mesh_status s) {
         case MESH_ERR_HIP: return "HIP runtime error";
         case MESH_ERR_INTERNAL: return "internal device check failed";
         case MESH_ERR_SCRATCH_LIMIT: return "mesh needs more scratch than the fixed no-allocation array holds";
+        case MESH_ERR_CHUNK: return "a vertex bin holds more pairs than chunk_keys";
     }
     return "unknown status";
 }
@@ -211,7 +224,7 @@ mesh_status mesh_node_neighbors_query(int64_t n_elem, int32_t etype, int32_t n_v
     SinglePlans sp;
     mesh_status st = plan_single(n_elem, etype, n_vert, opts, REL_NODE, true, &sp);
     if (st != MESH_OK) return st;
-    *workspace_bytes = sp.node.total;
+    *workspace_bytes = sp.chunked ? sp.chunk.total : sp.node.total;
     *cols_capacity = sp.node.n_pairs;
     return MESH_OK;
 }
@@ -223,8 +236,11 @@ mesh_status mesh_node_neighbors(const int32_t* conn, int64_t n_elem, int32_t ety
     mesh_status st = plan_single(n_elem, etype, n_vert, opts, REL_NODE, true, &sp);
     if (st != MESH_OK) return st;
     if ((n_elem > 0 && !conn) || !outputs_ok(row_ptr, cols, cols_capacity)) return MESH_ERR_INVALID_ARG;
-    st = workspace_ok(workspace, workspace_bytes, sp.node.total);
+    st = workspace_ok(workspace, workspace_bytes, sp.chunked ? sp.chunk.total : sp.node.total);
     if (st != MESH_OK) return st;
+    if (sp.chunked)
+        return run_chunked(sp.chunk, conn, row_ptr, cols, cols_capacity, nullptr, nullptr, 0, workspace,
+                           (hipStream_t)stream);
     return hip_status(run_node(sp.node, conn, row_ptr, cols, cols_capacity, workspace, (hipStream_t)stream));
 }
 
@@ -234,7 +250,7 @@ mesh_status mesh_elem_neighbors_query(int64_t n_elem, int32_t etype, int32_t n_v
     SinglePlans sp;
     mesh_status st = plan_single(n_elem, etype, n_vert, opts, REL_ELEM, true, &sp);
     if (st != MESH_OK) return st;
-    *workspace_bytes = sp.elem.total;
+    *workspace_bytes = sp.chunked ? sp.chunk.total : sp.elem.total;
     *cols_capacity = sp.elem.n_slots;
     return MESH_OK;
 }
@@ -246,8 +262,11 @@ mesh_status mesh_elem_neighbors(const int32_t* conn, int64_t n_elem, int32_t ety
     mesh_status st = plan_single(n_elem, etype, n_vert, opts, REL_ELEM, true, &sp);
     if (st != MESH_OK) return st;
     if ((n_elem > 0 && !conn) || !outputs_ok(row_ptr, cols, cols_capacity)) return MESH_ERR_INVALID_ARG;
-    st = workspace_ok(workspace, workspace_bytes, sp.elem.total);
+    st = workspace_ok(workspace, workspace_bytes, sp.chunked ? sp.chunk.total : sp.elem.total);
     if (st != MESH_OK) return st;
+    if (sp.chunked)
+        return run_chunked(sp.chunk, conn, nullptr, nullptr, 0, row_ptr, cols, cols_capacity, workspace,
+                           (hipStream_t)stream);
     return hip_status(run_elem(sp.elem, conn, row_ptr, cols, cols_capacity, workspace, (hipStream_t)stream));
 }
 
@@ -255,6 +274,7 @@ mesh_status mesh_elem_neighbors(const int32_t* conn, int64_t n_elem, int32_t ety
 // sort (the element CSR goes to the caller's outputs); otherwise the two
 // pipelines share one workspace, one after the other.
 static size_t both_bytes(const SinglePlans& sp) {
+    if (sp.chunked) return sp.chunk.total;
     if (sp.node.mode == NS_ELEM_ROWS) return sp.node.total;
     return sp.node.total > sp.elem.total ? sp.node.total : sp.elem.total;
 }
@@ -285,6 +305,9 @@ mesh_status mesh_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, i
     st = workspace_ok(workspace, workspace_bytes, both_bytes(sp));
     if (st != MESH_OK) return st;
     hipStream_t s = (hipStream_t)stream;
+    if (sp.chunked)
+        return run_chunked(sp.chunk, conn, node_row_ptr, node_cols, node_cols_capacity, elem_row_ptr, elem_cols,
+                           elem_cols_capacity, workspace, s);
     if (sp.node.mode == NS_ELEM_ROWS)
         return hip_status(run_node(sp.node, conn, node_row_ptr, node_cols, node_cols_capacity, workspace, s, false,
                                    elem_row_ptr, elem_cols, elem_cols_capacity));

@@ -1,0 +1,309 @@
+// Bounded-memory build: the relations of one mesh one vertex range at a time.
+//
+// The paper's method keeps every pair of the mesh in device memory at once,
+// and the paper names that footprint as its limit, leaving a leaner design to
+// future work (Sec. 3.2.2, Sec. 4).  Here the vertices are cut into ranges
+// whose pairs fit a fixed budget, and each range runs the element sort of
+// Sec. 2.2.2 on its own pairs only: rows of different vertices never share a
+// pair, so a range's rows are final as soon as its sort ends, and the ranges
+// are written one after the other at their place in the outputs.
+//
+//   fill            header, the first row start of each output
+//   chunk_coarse    conn -> pairs per bin of the top vertex bits (block
+//                   partials, then summed); read back with one wait
+//   (host)          ranges of whole bins, at most cap pairs and cap vertices
+//   per range [v0, v1), its pairs starting at element-CSR entry ebase:
+//     fill            header (error word kept), histograms, look-back words,
+//                     the range's row starts
+//     elem_hist       digit histograms of u = v - v0 over the range's pairs
+//     radix passes    the first reads the whole connectivity and keeps the
+//                     range's pairs ((u << 32) | e); the last writes the
+//                     element columns at ebase and the range's row starts
+//     rowptr_fill     row starts of the range's empty rows
+//     chunk_rows      element row starts + ebase -> the caller's row_ptr
+//     erows stage     the range's node rows from its element rows (the
+//                     ELEM_ROWS stage), their starts continuing the previous
+//                     range's last one on the device
+#include <vector>
+
+#include "elem.hpp"
+#include "erows.hpp"
+
+namespace mnb {
+
+// dst[i] = src[i] + add for i < n.
+constexpr int CR_BLOCK = 256;
+static __global__ __launch_bounds__(CR_BLOCK) void chunk_rows_kernel(int32_t* __restrict__ dst,
+                                                                    const int32_t* __restrict__ src, int64_t n,
+                                                                    int32_t add) {
+    const int64_t i = (int64_t)blockIdx.x * CR_BLOCK + threadIdx.x;
+    if (i < n) dst[i] = src[i] + add;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+bool plan_chunked(int64_t n_elem, int32_t etype, int32_t n_vert, const Opts& o, bool node, bool elem_out,
+                  ChunkPlan* p) {
+    const int npe = nodes_per_elem(etype);
+    if (npe == 0 || n_elem < 0 || n_vert < 0 || o.chunk_keys < CHUNK_MIN_KEYS) return false;
+    // the node relation through the element rows only, 8-bit digits only
+    if (node && o.node_sort != NS_ELEM_ROWS) return false;
+    if (o.digit_bits == WBITS) return false;
+    *p = ChunkPlan{};
+    p->opts = o;
+    p->n_elem = n_elem;
+    p->etype = etype;
+    p->n_vert = n_vert;
+    p->n_slots = (int64_t)npe * n_elem;
+    p->cap = o.chunk_keys;
+    p->node = node;
+    p->elem_out = elem_out;
+    const uint32_t id_bits = id_bits_for(n_vert);
+    p->coarse_bits = id_bits < (uint32_t)WBITS ? id_bits : (uint32_t)WBITS;
+    p->coarse_shift = id_bits - p->coarse_bits;
+    if (((int64_t)1 << p->coarse_shift) > p->cap) return false;  // one bin's vertices fit a range
+    const int64_t cap = p->cap;
+
+    size_t off = HEADER_BYTES;
+    p->off_hist = off;
+    off += align_up((size_t)MAX_EPASS * RADIX * sizeof(uint32_t));
+    if (node) {  // the node stage's scan look-back: cleared with the header
+        p->er.n_entries = cap;
+        p->er.slots = npe - 1;
+        p->er.n_tiles = erows_tiles_bound(cap);
+        p->er.long_cap = erows_long_cap(cap);
+        p->er.off_lb = off;
+        p->er.lb_words = erows_scan_tiles((int32_t)cap) * 2;
+        off += align_up((size_t)p->er.lb_words * sizeof(uint32_t));
+    }
+    p->zero_bytes = off;
+    // look-back words: the first pass runs over every slot (32-bit words below
+    // LB32_MAX_KEYS slots, which take half the room), later ones over the
+    // range's keys
+    p->off_lb0 = off;
+    const size_t lb0 = radix_lookback_bytes(p->n_slots, false);
+    off += align_up(p->n_slots < LB32_MAX_KEYS ? lb0 / 2 : lb0);
+    p->off_lb1 = off;
+    off += align_up(radix_lookback_bytes(cap, false));
+    p->lb_end = off;
+    p->off_keys0 = off;
+    off += align_up((size_t)cap * sizeof(uint64_t));
+    p->off_keys1 = off;
+    off += align_up((size_t)cap * sizeof(uint64_t));
+    const size_t keys_end = off;
+    p->off_bmin = off;
+    off += align_up((size_t)ceil_div(cap + 1, (int64_t)RF_TILE) * sizeof(int32_t));
+    p->off_erp = off;
+    off += align_up(((size_t)cap + 1) * sizeof(int32_t));
+    if (node && !elem_out) {
+        p->off_ecols = off;
+        off += align_up((size_t)cap * sizeof(int32_t));
+    }
+    p->off_bins = off;
+    off += align_up((size_t)WRADIX * sizeof(uint32_t));
+    // the coarse histogram's block partials are dead before the first range:
+    // they share the key buffers when those are large enough
+    const size_t part_bytes = (size_t)HIST_GRID_WIDE * WRADIX * sizeof(uint32_t);
+    if (part_bytes <= keys_end - p->off_keys0) {
+        p->off_part = p->off_keys0;
+    } else {
+        p->off_part = off;
+        off += align_up(part_bytes);
+    }
+    if (node) {
+        ErowsPlan& er = p->er;
+        er.off_tf = off;
+        off += align_up(((size_t)er.n_tiles + 1) * sizeof(int32_t));
+        er.off_tc = off;
+        off += align_up(((size_t)er.n_tiles + 1) * sizeof(int32_t));
+        er.off_list = off;
+        off += align_up((size_t)er.long_cap * sizeof(int32_t));
+        er.off_deg = off;
+        off += align_up(((size_t)cap + 1) * sizeof(int32_t));
+        er.temp_bytes = (size_t)er.slots * (size_t)cap * sizeof(int32_t);
+        if (er.temp_bytes <= keys_end - p->off_keys0) {  // the keys are dead once a range's rows are written
+            er.off_temp = p->off_keys0;
+        } else {
+            er.off_temp = off;
+            off += align_up(er.temp_bytes);
+        }
+    }
+    p->total = off;
+    return true;
+}
+
+namespace {
+
+struct Range {
+    int32_t v0, v1;
+    int64_t ebase, count;
+};
+
+// Ranges of whole bins (bin b holds the vertices [b << shift, (b + 1) << shift)),
+// each of at most cap pairs and cap vertices, covering [0, n_vert).  false:
+// one bin holds more than cap pairs.
+bool cut_ranges(const uint32_t* bins, uint32_t coarse_bits, uint32_t shift, int32_t n_vert, int64_t cap,
+                std::vector<Range>* out) {
+    out->clear();
+    const int64_t width = (int64_t)1 << shift;
+    const int64_t n_bins = (int64_t)1 << coarse_bits;
+    int64_t v0 = 0, count = 0, ebase = 0;
+    for (int64_t b = 0; b < n_bins && b * width < n_vert; ++b) {
+        const int64_t bv0 = b * width, bv1 = bv0 + width < n_vert ? bv0 + width : n_vert;
+        const int64_t c = bins[b];
+        if (c > cap) return false;
+        if (bv0 > v0 && (count + c > cap || bv1 - v0 > cap)) {
+            out->push_back(Range{(int32_t)v0, (int32_t)bv0, ebase, count});
+            ebase += count;
+            v0 = bv0;
+            count = 0;
+        }
+        count += c;
+    }
+    if (v0 < n_vert) out->push_back(Range{(int32_t)v0, n_vert, ebase, count});
+    return true;
+}
+
+template <int ET>
+hipError_t run_range(const ChunkPlan& p, const Range& r, const int32_t* conn, int32_t* node_row_ptr,
+                     int32_t* node_cols, int64_t node_cap, int32_t* elem_row_ptr, int32_t* elem_cols,
+                     int64_t elem_cap, char* w, hipStream_t s) {
+    uint32_t* hdr = (uint32_t*)w;
+    uint32_t* err = hdr + HDR_ERR;
+    uint32_t* count = hdr + HDR_KEY_COUNT;
+    uint32_t* hist = (uint32_t*)(w + p.off_hist);
+    const int32_t nv = r.v1 - r.v0;
+    int32_t* erp = (int32_t*)(w + p.off_erp);
+    const FillRegion fill[3] = {header_fill(w, p.zero_bytes, /*keep_err=*/true),
+                                {w + p.off_lb0, (int64_t)((p.lb_end - p.off_lb0) / 4), 0u},
+                                {erp, (int64_t)nv + 1, r.count == 0 ? 0u : (uint32_t)INT32_MAX}};
+    hipError_t e = fill_regions(fill, 3, s);
+    if (e != hipSuccess) return e;
+
+    // the range's element columns: in the caller's output at ebase, or in the
+    // workspace for a node-only call
+    int32_t* ecols;
+    int64_t ecap;
+    if (p.elem_out) {
+        ecols = elem_cols ? elem_cols + r.ebase : nullptr;
+        ecap = elem_cols && elem_cap > r.ebase ? elem_cap - r.ebase : 0;
+    } else {
+        ecols = (int32_t*)(w + p.off_ecols);
+        ecap = r.count;
+    }
+    if (r.count > 0) {
+        const PassPlan pp = plan_passes(id_bits_for(nv), RBITS);
+        const DigitPlan dp = digit_plan(pp);
+        const int grid = (int)tmin<int64_t>(ceil_div(p.n_elem, HIST_BLOCK), HIST_GRID_MAX);
+        e = launch("chunk_elem_hist", elem_hist_kernel<ET, RADIX>, dim3(grid), dim3(HIST_BLOCK), s, conn, p.n_elem,
+                   p.n_vert, r.v0, nv, dp, hist, count, err);
+        uint64_t* lb[2] = {(uint64_t*)(w + p.off_lb0), (uint64_t*)(w + p.off_lb1)};
+        uint64_t* kb[2] = {(uint64_t*)(w + p.off_keys0), (uint64_t*)(w + p.off_keys1)};
+        const CsrOut csr{ecols, erp, ecols ? ecap : 0, 32u, 0xffffffffull};
+        const ElemPairSrc<ET> first{conn, nv, r.v0};
+        for (int q = 0; q < pp.n_pass && e == hipSuccess; ++q) {
+            const bool last = q + 1 == pp.n_pass;
+            const uint32_t shift = 32 + pp.shift[q], bits = pp.width[q];
+            const uint32_t* hq = hist + q * RADIX;
+            uint32_t* ticket = hdr + HDR_TICKET0 + TK_PASS0 + q;
+            // the first pass runs over every slot and the later ones over the
+            // range's keys, with look-back words of their own widths: the
+            // first hands no status slots on (the fill cleared lb[1]); later
+            // passes hand them on as usual
+            uint64_t* lb_next = q == 0 || last ? nullptr : lb[(q + 1) & 1];
+            const CountedKeySrc later{kb[(q - 1) & 1], count};
+            const KeyOut out{kb[q & 1]};
+            if (q == 0 && last)
+                e = launch_radix_pass("chunk_elem_radix_first", p.opts.shape, first, csr, p.n_slots, shift, bits, hq,
+                                      lb[0], nullptr, ticket, err, s);
+            else if (q == 0)
+                e = launch_radix_pass("chunk_elem_radix_first", p.opts.shape, first, out, p.n_slots, shift, bits, hq,
+                                      lb[0], nullptr, ticket, err, s);
+            else if (last)
+                e = launch_radix_pass("chunk_elem_radix", p.opts.shape, later, csr, r.count, shift, bits, hq,
+                                      lb[q & 1], lb_next, ticket, err, s);
+            else
+                e = launch_radix_pass("chunk_elem_radix", p.opts.shape, later, out, r.count, shift, bits, hq,
+                                      lb[q & 1], lb_next, ticket, err, s);
+        }
+        if (e == hipSuccess)
+            e = launch_rowptr_fill("chunk_elem_row_fill", erp, nv, count, (int32_t*)(w + p.off_bmin), s);
+        if (e != hipSuccess) return e;
+    }
+    if (p.elem_out) {
+        e = launch("chunk_rows", chunk_rows_kernel, dim3((unsigned)ceil_div((int64_t)nv + 1, CR_BLOCK)),
+                   dim3(CR_BLOCK), s, elem_row_ptr + r.v0, (const int32_t*)erp, (int64_t)nv + 1, (int32_t)r.ebase);
+        if (e != hipSuccess) return e;
+    }
+    if (!p.node) return hipSuccess;
+    const ErowsBufs b = erows_bufs(p.er, w, err, hdr + HDR_TICKET0 + TK_EROWS);
+    int32_t* rp = node_row_ptr + r.v0;  // rp[0]: the previous range's end, the base of this one's starts
+    return launch_erows("chunk_node", UniformRows<ET>{conn, p.n_elem, p.n_vert, r.v0}, erp, ecols,
+                        ecols ? ecap : 0, nv, r.count, rp, node_cols, node_cap, b, s, rp);
+}
+
+}  // namespace
+
+mesh_status run_chunked(const ChunkPlan& p, const int32_t* conn, int32_t* node_row_ptr, int32_t* node_cols,
+                        int64_t node_cap, int32_t* elem_row_ptr, int32_t* elem_cols, int64_t elem_cap, void* ws,
+                        hipStream_t s) {
+    char* w = (char*)ws;
+    uint32_t* hdr = (uint32_t*)w;
+    if (p.n_slots == 0) {  // no pairs: every row empty
+        hipError_t e = zero_words(ws, HEADER_BYTES, s);
+        if (e == hipSuccess && p.node) e = fill_i32(node_row_ptr, (int64_t)p.n_vert + 1, 0, s);
+        if (e == hipSuccess && p.elem_out) e = fill_i32(elem_row_ptr, (int64_t)p.n_vert + 1, 0, s);
+        return e == hipSuccess ? MESH_OK : MESH_ERR_HIP;
+    }
+    FillRegion fill[3] = {header_fill(ws, HEADER_BYTES, false)};
+    int n_fill = 1;
+    if (p.node) fill[n_fill++] = {node_row_ptr, 1, 0u};
+    if (p.elem_out) fill[n_fill++] = {elem_row_ptr, 1, 0u};
+    hipError_t e = fill_regions(fill, n_fill, s);
+    if (e != hipSuccess) return MESH_ERR_HIP;
+
+    // pairs per bin of the top vertex bits
+    uint32_t* bins = (uint32_t*)(w + p.off_bins);
+    e = with_type(p.etype, [&](auto et) {
+        constexpr int ET = decltype(et)::value;
+        DigitPlan dp{};
+        dp.n_pass = 1;
+        dp.shift[0] = p.coarse_shift;
+        dp.mask[0] = (1u << p.coarse_bits) - 1;
+        const int grid = (int)tmin<int64_t>(ceil_div(p.n_elem, HIST_BLOCK), HIST_GRID_WIDE);
+        hipError_t x = launch("chunk_coarse", elem_hist_kernel<ET, WRADIX>, dim3(grid), dim3(HIST_BLOCK), s, conn,
+                              p.n_elem, p.n_vert, 0, p.n_vert, dp, (uint32_t*)(w + p.off_part),
+                              hdr + HDR_KEY_COUNT, hdr + HDR_ERR);
+        if (x == hipSuccess)
+            x = launch("chunk_coarse_sum", hist_sum_kernel, dim3((unsigned)ceil_div(WRADIX, HSUM_BLOCK)),
+                       dim3(HSUM_BLOCK), s, (const uint32_t*)(w + p.off_part), grid, WRADIX, bins);
+        return x;
+    });
+    if (e != hipSuccess) return MESH_ERR_HIP;
+    const int64_t n_bins = (int64_t)1 << p.coarse_bits;
+    std::vector<uint32_t> h_bins((size_t)n_bins);
+    uint32_t h_hdr[HDR_KEY_COUNT + 1];
+    e = hipMemcpyAsync(h_bins.data(), bins, (size_t)n_bins * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_hdr, hdr, sizeof h_hdr, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return MESH_ERR_HIP;
+    uint64_t total = 0;
+    for (uint32_t c : h_bins) total += c;
+    if (total != h_hdr[HDR_KEY_COUNT]) return MESH_ERR_INTERNAL;
+
+    std::vector<Range> ranges;
+    if (!cut_ranges(h_bins.data(), p.coarse_bits, p.coarse_shift, p.n_vert, p.cap, &ranges)) return MESH_ERR_CHUNK;
+    e = with_type(p.etype, [&](auto et) {
+        constexpr int ET = decltype(et)::value;
+        hipError_t x = hipSuccess;
+        for (size_t i = 0; i < ranges.size() && x == hipSuccess; ++i)
+            x = run_range<ET>(p, ranges[i], conn, node_row_ptr, node_cols, node_cap, elem_row_ptr, elem_cols,
+                              elem_cap, w, s);
+        return x;
+    });
+    return e == hipSuccess ? MESH_OK : MESH_ERR_HIP;
+}
+
+}  // namespace mnb

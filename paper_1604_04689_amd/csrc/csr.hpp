@@ -151,15 +151,18 @@ inline hipError_t launch_unique_csr(const char* name, const uint64_t* keys, int6
                   dim3(UNIQ_BLOCK), s, keys, n_host, n_dev, b, n_vert, cols, cols_cap, row_ptr, lookback, ticket, err);
 }
 
-// Exclusive scan of n int32 counts: out[i] = sum of in[0..i), out[n] = total.
-// Tiles by ticket, one wave-wide look-back per tile.
+// Exclusive scan of n int32 counts: out[i] = B + sum of in[0..i), out[n] =
+// B + total, where B = *base read on the device (0 for a null base).  base
+// may point at out[0]: the value written there is the one read.  Tiles by
+// ticket, one wave-wide look-back per tile.
 constexpr int SCAN_BLOCK = 1024;
 constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
 
 static __global__ __launch_bounds__(SCAN_BLOCK) void scan_i32_kernel(const int32_t* __restrict__ in, int64_t n,
-                                                             int32_t* __restrict__ out, uint64_t* lookback,
-                                                             uint32_t* ticket, uint32_t* err) {
+                                                             int32_t* out, uint64_t* lookback,
+                                                             uint32_t* ticket, uint32_t* err,
+                                                             const int32_t* base) {
     constexpr int WAVES = SCAN_BLOCK / WAVE;
     constexpr int PARTS = SCAN_ITEMS * WAVES;  // one sum per (item, wave), in element order
     static_assert(PARTS % WAVE == 0, "the partial sums fill whole waves");
@@ -170,11 +173,11 @@ static __global__ __launch_bounds__(SCAN_BLOCK) void scan_i32_kernel(const int32
     if (tid == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
-    const int64_t base = (int64_t)tile * SCAN_TILE;
+    const int64_t first = (int64_t)tile * SCAN_TILE;
     uint32_t c[SCAN_ITEMS], ex[SCAN_ITEMS];
 #pragma unroll
     for (int j = 0; j < SCAN_ITEMS; ++j) {
-        const int64_t i = base + j * SCAN_BLOCK + wid * WAVE + lane;
+        const int64_t i = first + j * SCAN_BLOCK + wid * WAVE + lane;
         c[j] = i < n ? (uint32_t)in[i] : 0u;
     }
 #pragma unroll
@@ -200,10 +203,10 @@ static __global__ __launch_bounds__(SCAN_BLOCK) void scan_i32_kernel(const int32
         if (lane == 0) s_prefix = before;
     }
     __syncthreads();
-    const uint64_t prefix = s_prefix;
+    const uint64_t prefix = s_prefix + (base ? (uint64_t)(uint32_t)*base : 0u);
 #pragma unroll
     for (int j = 0; j < SCAN_ITEMS; ++j) {
-        const int64_t i = base + j * SCAN_BLOCK + wid * WAVE + lane;
+        const int64_t i = first + j * SCAN_BLOCK + wid * WAVE + lane;
         if (i < n) {
             const uint64_t start = prefix + s_sum[j * WAVES + wid] + ex[j];
             out[i] = (int32_t)start;

@@ -32,12 +32,15 @@ __device__ __forceinline__ bool first_occurrence(const int32_t* __restrict__ con
     return first;
 }
 
-// (vertex, element) pair of connectivity slot s as the key (v << 32) | e, or
-// KEY_NONE when the slot repeats an id of its element or is out of range.
+// (vertex, element) pair of connectivity slot s as the key (u << 32) | e
+// with u = v - v_lo, or KEY_NONE when the slot repeats an id of its element
+// or v lies outside the window [v_lo, v_lo + n_vert) (the whole mesh unless a
+// bounded-memory build sorts one vertex range at a time).
 template <int ET>
 struct ElemPairSrc {
     const int32_t* __restrict__ conn;
     int32_t n_vert;
+    int32_t v_lo = 0;
     static constexpr bool kSkipNone = true;
     static constexpr bool kStaged = true;
     static constexpr int NPE = Elem<ET>::NPE;
@@ -73,22 +76,24 @@ struct ElemPairSrc {
         const int32_t* el = st + (e - (uint32_t)tile_base / NPE) * NPE;
         const int j = (int)(ss - e * NPE);
         const int32_t v = el[j];
-        if ((uint32_t)v >= (uint32_t)n_vert) return KEY_NONE;
+        const uint32_t u = (uint32_t)(v - v_lo);
+        if (u >= (uint32_t)n_vert) return KEY_NONE;
         bool first = true;
 #pragma unroll
         for (int jj = 0; jj < NPE - 1; ++jj)
             if (jj < j) first &= el[jj] != v;
-        return first ? ((uint64_t)(uint32_t)v << 32) | (uint64_t)e : KEY_NONE;
+        return first ? ((uint64_t)u << 32) | (uint64_t)e : KEY_NONE;
     }
 
     __device__ __forceinline__ uint64_t load(int64_t s) const {
         const int32_t v = conn[s];
-        if ((uint32_t)v >= (uint32_t)n_vert) return KEY_NONE;
+        const uint32_t u = (uint32_t)(v - v_lo);
+        if (u >= (uint32_t)n_vert) return KEY_NONE;
         const uint32_t ss = (uint32_t)s;  // slot indices stay below 2^31
         const uint32_t e = ss / NPE;
         const int j = (int)(ss - e * NPE);
         if (!first_occurrence<NPE>(conn, e, j, v)) return KEY_NONE;
-        return ((uint64_t)(uint32_t)v << 32) | (uint64_t)e;
+        return ((uint64_t)u << 32) | (uint64_t)e;
     }
 };
 
@@ -147,16 +152,17 @@ static __global__ __launch_bounds__(HSUM_BLOCK) void hist_sum_kernel(const uint3
 // Grid of a wide histogram kernel (one partial per block).
 constexpr int HIST_GRID_WIDE = 256;
 
-// Histograms of the digits of v over the pairs that take part (pass q's digit
-// values at hist[q * HR ..], or the block partials, see flush_hist), and
-// their number.  A thread takes whole elements, HIST_UNROLL of them in
-// flight; a repeated id inside an element counts once.  Raises
-// ERR_INDEX_RANGE.
+// Histograms of the digits of u = v - v_lo over the pairs whose vertex lies
+// in the window [v_lo, v_lo + n_win) (pass q's digit values at hist[q * HR
+// ..], or the block partials, see flush_hist), and their number.  A thread
+// takes whole elements, HIST_UNROLL of them in flight; a repeated id inside
+// an element counts once.  Raises ERR_INDEX_RANGE for an id outside
+// [0, n_vert).
 template <int ET, int HR>
 __global__ __launch_bounds__(HIST_BLOCK) void elem_hist_kernel(const int32_t* __restrict__ conn, int64_t n_elem,
-                                                              int32_t n_vert, DigitPlan dp,
-                                                              uint32_t* __restrict__ hist, uint32_t* pair_count,
-                                                              uint32_t* err) {
+                                                              int32_t n_vert, int32_t v_lo, int32_t n_win,
+                                                              DigitPlan dp, uint32_t* __restrict__ hist,
+                                                              uint32_t* pair_count, uint32_t* err) {
     constexpr int NPE = Elem<ET>::NPE;
     __shared__ uint32_t s_hist[hist_passes(HR) * HR];
     __shared__ uint32_t s_pairs;
@@ -181,14 +187,15 @@ __global__ __launch_bounds__(HIST_BLOCK) void elem_hist_kernel(const int32_t* __
 #pragma unroll
             for (int j = 0; j < NPE; ++j) {
                 const int32_t v = id[u][j];
-                bool take = (uint32_t)v < (uint32_t)n_vert;
-                bad |= !take;
+                const uint32_t w = (uint32_t)(v - v_lo);
+                bad |= (uint32_t)v >= (uint32_t)n_vert;
+                bool take = w < (uint32_t)n_win;
 #pragma unroll
                 for (int jj = 0; jj < j; ++jj) take &= id[u][jj] != v;
                 if (!take) continue;
                 ++pairs;
                 for (int p = 0; p < n_pass; ++p)
-                    atomicAdd(&s_hist[p * HR + (((uint32_t)v >> dp.shift[p]) & dp.mask[p])], 1u);
+                    atomicAdd(&s_hist[p * HR + ((w >> dp.shift[p]) & dp.mask[p])], 1u);
             }
         }
     }

@@ -83,13 +83,13 @@ static hipError_t elem_pipeline(const ElemPlan& p, const int32_t* conn, int32_t*
         const int wgrid = (int)tmin<int64_t>(grid, HIST_GRID_WIDE);
         uint32_t* part = (uint32_t*)(w + p.off_part);
         e = launch("elem_hist", elem_hist_kernel<ET, WRADIX>, dim3(wgrid), dim3(HIST_BLOCK), s, conn, p.n_elem, p.n_vert,
-                   dp, part, hdr + HDR_KEY_COUNT, hdr + HDR_ERR);
+                   0, p.n_vert, dp, part, hdr + HDR_KEY_COUNT, hdr + HDR_ERR);
         if (e == hipSuccess)
             e = launch("hist_sum", hist_sum_kernel, dim3((unsigned)ceil_div(n_words, HSUM_BLOCK)), dim3(HSUM_BLOCK), s,
                        (const uint32_t*)part, wgrid, n_words, (uint32_t*)(w + p.off_hist));
     } else {
         e = launch("elem_hist", elem_hist_kernel<ET, RADIX>, dim3(grid), dim3(HIST_BLOCK), s, conn, p.n_elem, p.n_vert,
-                   dp, (uint32_t*)(w + p.off_hist), hdr + HDR_KEY_COUNT, hdr + HDR_ERR);
+                   0, p.n_vert, dp, (uint32_t*)(w + p.off_hist), hdr + HDR_KEY_COUNT, hdr + HDR_ERR);
     }
     if (e != hipSuccess) return e;
     return elem_passes(p, ElemPairSrc<ET>{conn, p.n_vert}, row_ptr, cols, cols_cap, w, s);

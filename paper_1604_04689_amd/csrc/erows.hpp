@@ -89,7 +89,9 @@ __device__ __forceinline__ bool elem_cands(const int32_t (&ids)[NPE], int npe, u
 // `in` is false for positions outside every short row: no loads, no
 // candidates, no error.
 
-// A mesh of one type: element e's ids at conn + e * NPE.
+// A mesh of one type: element e's ids at conn + e * NPE.  Row index r stands
+// for vertex r + v0 (v0 = 0 unless the rows are one vertex range of a
+// bounded-memory build).
 template <int ET>
 struct UniformRows {
     static constexpr int NPE = Elem<ET>::NPE;
@@ -99,6 +101,7 @@ struct UniformRows {
     const int32_t* __restrict__ conn;
     int64_t n_elem;
     int32_t n_vert;
+    int32_t v0 = 0;
     struct Loc {
         uint32_t e;
         bool ok, bad;
@@ -127,7 +130,7 @@ struct UniformRows {
             for (int s = 0; s < S; ++s) c[s] = CAND_NONE;
             return;
         }
-        *bad |= !elem_cands<NPE>(ids, NPE, adjacency_word<ET>(), v, n_vert, c);
+        *bad |= !elem_cands<NPE>(ids, NPE, adjacency_word<ET>(), v + v0, n_vert, c);
     }
 };
 
@@ -713,10 +716,12 @@ inline int64_t erows_long_cap(int64_t q_bound) { return q_bound / (ER_ROW_MAX + 
 
 // The stage: rows' counts and values (prep, long rows, tiles), counts scanned
 // into row_ptr, values gathered into cols.
+// scan_base: the row starts are offset by *scan_base (read on the device;
+// null: none), for rows that continue a CSR written by earlier calls.
 template <class Acc>
 hipError_t launch_erows(const char* tag, const Acc& acc, const int32_t* erp, const int32_t* ecols, int64_t ecap,
                         int32_t n_vert, int64_t q_bound, int32_t* row_ptr, int32_t* cols, int64_t cols_cap,
-                        const ErowsBufs& b, hipStream_t s) {
+                        const ErowsBufs& b, hipStream_t s, const int32_t* scan_base = nullptr) {
     const int64_t n_tiles = erows_tiles_bound(q_bound);
     char name[48];
     snprintf(name, sizeof name, "%s_erows_prep", tag);
@@ -740,7 +745,7 @@ hipError_t launch_erows(const char* tag, const Acc& acc, const int32_t* erp, con
     if (e == hipSuccess) {
         snprintf(name, sizeof name, "%s_erows_scan", tag);
         e = launch(name, scan_i32_kernel, dim3((unsigned)ceil_div((int64_t)n_vert, SCAN_TILE)), dim3(SCAN_BLOCK), s,
-                   (const int32_t*)b.cnt, (int64_t)n_vert, row_ptr, b.scan_lb, b.scan_ticket, b.err);
+                   (const int32_t*)b.cnt, (int64_t)n_vert, row_ptr, b.scan_lb, b.scan_ticket, b.err, scan_base);
     }
     if (e == hipSuccess) {
         snprintf(name, sizeof name, "%s_erows_gather", tag);

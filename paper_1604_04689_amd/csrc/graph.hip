@@ -17,6 +17,10 @@ struct mesh_graph_s {
 
 namespace {
 
+// A bounded-memory build waits on its stream for a histogram, which a capture
+// cannot hold: such options are refused before capturing.
+bool chunked(const mesh_options* o) { return o && o->chunk_keys > 0; }
+
 template <typename F>
 mesh_status capture(mesh_graph* out, F&& call) {
     if (!out) return MESH_ERR_INVALID_ARG;
@@ -60,6 +64,10 @@ mesh_status mesh_graph_node_neighbors(const int32_t* conn, int64_t n_elem, int32
                                       int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
                                       const mesh_options* opts, void* workspace, size_t workspace_bytes,
                                       mesh_graph* graph) {
+    if (chunked(opts)) {
+        if (graph) *graph = nullptr;
+        return MESH_ERR_INVALID_ARG;
+    }
     return capture(graph, [&](void* s) {
         return mesh_node_neighbors(conn, n_elem, etype, n_vert, row_ptr, cols, cols_capacity, opts, workspace,
                                    workspace_bytes, s);
@@ -70,6 +78,10 @@ mesh_status mesh_graph_elem_neighbors(const int32_t* conn, int64_t n_elem, int32
                                       int32_t* row_ptr, int32_t* cols, int64_t cols_capacity,
                                       const mesh_options* opts, void* workspace, size_t workspace_bytes,
                                       mesh_graph* graph) {
+    if (chunked(opts)) {
+        if (graph) *graph = nullptr;
+        return MESH_ERR_INVALID_ARG;
+    }
     return capture(graph, [&](void* s) {
         return mesh_elem_neighbors(conn, n_elem, etype, n_vert, row_ptr, cols, cols_capacity, opts, workspace,
                                    workspace_bytes, s);
@@ -81,6 +93,10 @@ mesh_status mesh_graph_neighbors(const int32_t* conn, int64_t n_elem, int32_t et
                                  int32_t* elem_row_ptr, int32_t* elem_cols, int64_t elem_cols_capacity,
                                  const mesh_options* opts, void* workspace, size_t workspace_bytes,
                                  mesh_graph* graph) {
+    if (chunked(opts)) {
+        if (graph) *graph = nullptr;
+        return MESH_ERR_INVALID_ARG;
+    }
     return capture(graph, [&](void* s) {
         return mesh_neighbors(conn, n_elem, etype, n_vert, node_row_ptr, node_cols, node_cols_capacity, elem_row_ptr,
                               elem_cols, elem_cols_capacity, opts, workspace, workspace_bytes, s);

@@ -20,10 +20,12 @@ struct Opts {
     int node_sort = NS_ELEM_ROWS;
     int shape = 0;       // requested radix tile shape
     int digit_bits = -1;  // requested radix digit width (-1: the rule for the sort at hand)
+    int64_t chunk_keys = 0;  // bounded-memory build: pairs sorted at once (0: the whole mesh)
 };
 
-// false: an option out of range (MESH_ERR_INVALID_ARG).
-bool resolve_options(const mesh_options* o, Opts* out);
+// false: an option out of range (MESH_ERR_INVALID_ARG).  chunk_keys > 0 is an
+// option only where allow_chunk is set (single-mesh calls).
+bool resolve_options(const mesh_options* o, Opts* out, bool allow_chunk = false);
 
 // Smallest b >= 1 with 2^b >= n.
 uint32_t bits_for_count(int64_t n);
@@ -142,6 +144,46 @@ hipError_t run_erows_uniform(int32_t etype, const ErowsPlan& er, const int32_t* 
                              int32_t n_vert, const int32_t* erp, const int32_t* ecols, int64_t ecap,
                              int32_t* row_ptr, int32_t* cols, int64_t cols_cap, char* ws, uint32_t* err,
                              uint32_t* ticket, hipStream_t s);
+
+// ---- bounded-memory build (chunk_keys) ------------------------------------------
+// The relations of one mesh of one type, one vertex range at a time: a
+// histogram over the top vertex bits (coarse bins) is read back, the host cuts
+// the vertices into ranges of at most `cap` pairs and `cap` vertices, and each
+// range sorts its own pairs and writes its rows.  Workspace: the header and
+// the per-range histograms (cleared per range, with the node stage's scan
+// look-back), the look-back words of the first pass (over every connectivity
+// slot) and of later passes (over at most cap keys), two key buffers of cap
+// keys, the range's element row starts (and, for a node-only call, its
+// element columns), the coarse bins and their block partials, and the node
+// stage's buffers for cap entries.
+constexpr int64_t CHUNK_MIN_KEYS = 4096;
+struct ChunkPlan {
+    int64_t n_elem = 0;
+    int32_t etype = 0;
+    int32_t n_vert = 0;
+    int64_t n_slots = 0;
+    int64_t cap = 0;
+    uint32_t coarse_bits = 0;  // vertex bits of a bin index (the top ones)
+    uint32_t coarse_shift = 0; // low vertex bits inside a bin
+    bool node = false;         // the node relation is written
+    bool elem_out = false;     // the element relation goes to the caller
+    size_t off_hist = 0, zero_bytes = 0;  // [0, zero_bytes): cleared per range (error word kept)
+    size_t off_lb0 = 0, off_lb1 = 0, lb_end = 0;
+    size_t off_keys0 = 0, off_keys1 = 0, off_bmin = 0, off_erp = 0, off_ecols = 0;
+    size_t off_bins = 0, off_part = 0;
+    ErowsPlan er;
+    size_t total = 0;
+    Opts opts;
+};
+// false: the options do not allow a bounded-memory build of these sizes
+// (MESH_ERR_INVALID_ARG).
+bool plan_chunked(int64_t n_elem, int32_t etype, int32_t n_vert, const Opts& o, bool node, bool elem_out,
+                  ChunkPlan* p);
+// Waits on the stream once (the coarse histogram).  The element outputs may
+// be null when !p.elem_out, the node outputs when !p.node.
+mesh_status run_chunked(const ChunkPlan& p, const int32_t* conn, int32_t* node_row_ptr, int32_t* node_cols,
+                        int64_t node_cap, int32_t* elem_row_ptr, int32_t* elem_cols, int64_t elem_cap, void* ws,
+                        hipStream_t s);
 
 // ---- meshes of several element types -----------------------------------------
 struct MixedPlan {

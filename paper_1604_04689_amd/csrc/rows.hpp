@@ -436,7 +436,7 @@ static inline hipError_t launch_rows_dedup(const RowsStage& r, int32_t* row_ptr,
     if (e == hipSuccess)
         e = launch(batch ? "batch_node_row_scan" : "node_row_scan", scan_i32_kernel,
                    dim3((unsigned)ceil_div((int64_t)r.n_vert, SCAN_TILE)), dim3(SCAN_BLOCK), s, (const int32_t*)r.deg,
-                   (int64_t)r.n_vert, row_ptr, r.scan_lb, r.scan_ticket, r.err);
+                   (int64_t)r.n_vert, row_ptr, r.scan_lb, r.scan_ticket, r.err, (const int32_t*)nullptr);
     return e;
 }
 

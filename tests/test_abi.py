@@ -104,7 +104,7 @@ def test_bad_options_refused(bad):
 
 def test_default_options():
     o = binding.lib().mesh_default_options()
-    assert o.as_dict() == {"node_sort": -1, "radix_shape": -1, "digit_bits": -1}
+    assert o.as_dict() == {"node_sort": -1, "radix_shape": -1, "digit_bits": -1, "chunk_keys": -1}
     # NULL options and all-default options size the same workspace
     w, c = ctypes.c_size_t(0), ctypes.c_int64(0)
     assert binding.lib().mesh_node_neighbors_query(5000, 1, 3000, None, ctypes.byref(w), ctypes.byref(c)) == 0
@@ -263,7 +263,7 @@ def test_tuning_table_lookup(tmp_path, monkeypatch):
     assert autotune.batch_options_for("both", 2 ** 24, 10) is None
     # a build's options come from the table, nothing process-wide changes
     o = binding._resolve("node", 0, 174763, "tuned")
-    assert o.as_dict() == {"node_sort": 1, "radix_shape": 2, "digit_bits": 8}
+    assert o.as_dict() == {"node_sort": 1, "radix_shape": 2, "digit_bits": 8, "chunk_keys": -1}
     monkeypatch.setattr(autotune, "_table_cache", None)
     monkeypatch.setenv("MESHNBR_TUNING", "off")
     assert autotune.options_for("node", 0, 174763) is None
@@ -286,3 +286,80 @@ def test_noalloc_refuses_past_its_scratch_without_a_gpu():
                                       None) == binding.Status.UNSUPPORTED_TYPE
     assert lib.mesh_neighbors_noalloc(None, -1, 0, 10, None, None, 0, None, None, 0, None,
                                       None) == binding.Status.INVALID_ARG
+
+
+# ---- bounded-memory build (mesh_options.chunk_keys) --------------------------
+
+@pytest.mark.parametrize("bad", [{"chunk_keys": 4095}, {"chunk_keys": 1}, {"chunk_keys": -2},
+                                 {"chunk_keys": 4096, "node_sort": 0}, {"chunk_keys": 4096, "node_sort": 2},
+                                 {"chunk_keys": 4096, "digit_bits": 11}])
+def test_chunk_options_refused(bad):
+    """A budget below 4096 pairs, a node algorithm other than ELEM_ROWS for a
+    call that builds the node relation, or 11-bit digits."""
+    for kind in ("node", "both"):
+        with pytest.raises(binding.MeshError) as e:
+            binding.query(kind, 1000, 0, 600, bad)
+        assert e.value.status == binding.Status.INVALID_ARG
+
+
+def test_chunk_options_accepted():
+    # the element relation alone ignores the node algorithm
+    assert binding.query("elem", 1000, 0, 600, {"chunk_keys": 4096, "node_sort": 0})[1] == 3000
+    # -1 and 0 mean the whole mesh: the same workspace as no option
+    for k in (-1, 0):
+        assert binding.query("node", 5000, 1, 3000, {"chunk_keys": k}) == binding.query("node", 5000, 1, 3000)
+    # capacities do not depend on the budget
+    assert binding.query("both", 5000, 1, 3000, {"chunk_keys": 8192})[1:] == binding.query("both", 5000, 1, 3000)[1:]
+
+
+def test_chunk_budget_covers_one_bin():
+    """Ranges are cut at bins of the top 11 vertex bits: a budget below one
+    bin's vertices (2^20 of them for 31-bit ids) is refused."""
+    with pytest.raises(binding.MeshError) as e:
+        binding.query("node", 1000, 0, 2 ** 31 - 1, {"chunk_keys": (1 << 20) - 1})
+    assert e.value.status == binding.Status.INVALID_ARG
+    binding.query("node", 1000, 0, 2 ** 31 - 1, {"chunk_keys": 1 << 20})
+    binding.query("node", 1000, 0, 1 << 15, {"chunk_keys": 4096})   # bins of 16 vertices
+
+
+@pytest.mark.parametrize("etype", [0, 1, 2])
+def test_chunk_workspace_is_bounded(etype):
+    """The whole-mesh build takes 17 to 50 bytes per connectivity slot; the
+    bounded build takes O(chunk_keys) plus a quarter byte per slot (the first
+    radix pass's look-back status)."""
+    npe = binding.NODES_PER_ELEM[etype]
+    n_elem, n_vert, cap = 4_000_000, 1_500_000, 1 << 20
+    for kind in ("node", "elem", "both"):
+        whole = binding.query(kind, n_elem, etype, n_vert)[0]
+        a = binding.query(kind, n_elem, etype, n_vert, {"chunk_keys": cap})[0]
+        b = binding.query(kind, 2 * n_elem, etype, n_vert, {"chunk_keys": cap})[0]
+        assert whole >= 17 * npe * n_elem
+        assert a < whole / 4
+        assert abs((b - a) - npe * n_elem / 4) < 4096           # a quarter byte per added slot
+        assert a < 80 * cap + npe * n_elem / 4 + (4 << 20)       # O(cap) otherwise
+
+
+def test_chunk_refused_for_batches_mixed_and_graphs():
+    lib = binding.lib()
+    o = binding.make_options({"chunk_keys": 8192})
+    w, c, c2 = ctypes.c_size_t(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    assert lib.mesh_batch_node_neighbors_query(3, 1000, 450, 500, 200, ctypes.byref(o), ctypes.byref(w),
+                                               ctypes.byref(c)) == binding.Status.INVALID_ARG
+    assert lib.mesh_batch_elem_neighbors_query(3, 800, 500, ctypes.byref(o), ctypes.byref(w),
+                                               ctypes.byref(c)) == binding.Status.INVALID_ARG
+    assert lib.mesh_mixed_neighbors_query(100, 400, 800, 300, ctypes.byref(o), ctypes.byref(w), ctypes.byref(c),
+                                          ctypes.byref(c2)) == binding.Status.INVALID_ARG
+    # a capture cannot hold the histogram read-back: refused before capturing
+    # (so without a device), and the handle cleared
+    g = ctypes.c_void_p(1)
+    st = lib.mesh_graph_node_neighbors(ctypes.c_void_p(256), 10, 0, 10, ctypes.c_void_p(256), ctypes.c_void_p(256),
+                                       60, ctypes.byref(o), ctypes.c_void_p(256), 1 << 20, ctypes.byref(g))
+    assert st == binding.Status.INVALID_ARG and not g.value
+
+
+def test_chunk_lets_noalloc_take_larger_meshes():
+    """The no-allocation entry sizes with the plain query: a mesh past its
+    scratch as a whole fits it under a pair budget."""
+    n_elem, n_vert = 3_000_000, 1_600_000
+    assert binding.query("both", n_elem, 0, n_vert)[0] > binding.NOALLOC_SCRATCH_BYTES
+    assert binding.query("both", n_elem, 0, n_vert, {"chunk_keys": 1 << 20})[0] < binding.NOALLOC_SCRATCH_BYTES
