@@ -23,6 +23,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import subprocess
 import sys
 import time
@@ -116,12 +117,35 @@ def kernel_bytes(m, nnz_node, nnz_elem, node_sort):
     }
 
 
-def source_hash():
-    """Hash of every kernel source: a traffic record taken on other source is stale."""
+# the translation unit that launches each profiled kernel
+KERNEL_UNITS = {"node_erows": "elem_rows.hip"}
+
+
+def _include_closure(path):
+    """path and every file it includes with #include "...", transitively."""
+    seen, todo = [], [os.path.normpath(path)]
+    while todo:
+        f = todo.pop()
+        if f in seen:
+            continue
+        seen.append(f)
+        with open(f) as fh:
+            for line in fh:
+                m = re.match(r'\s*#\s*include\s+"([^"]+)"', line)
+                if m:
+                    todo.append(os.path.normpath(os.path.join(os.path.dirname(f), m.group(1))))
+    return sorted(seen)
+
+
+def source_hash(kernel="node_erows"):
+    """Hash of the sources the kernel is built from (its launching unit and
+    every header it includes): a traffic record taken on other source is
+    stale."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1604_04689_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
+    unit = os.path.join(ROOT, "paper_1604_04689_amd", "csrc", KERNEL_UNITS[kernel])
+    for f in _include_closure(unit):
+        h.update(os.path.relpath(f, ROOT).encode())
+        with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -135,7 +159,7 @@ def load_traffic(kernel, workload, node_sort):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("source_sha") != source_hash() or t.get("node_sort") != node_sort:
+    if kernel not in KERNEL_UNITS or t.get("source_sha") != source_hash(kernel) or t.get("node_sort") != node_sort:
         return None
     return t.get("bytes_per_launch")
 
@@ -210,13 +234,13 @@ def run_chunked(torch, nb, m, conn, build, stream, steps, budgets):
         b.check(stream)
         if not _same_as(b, ref):
             raise RuntimeError(f"bounded-memory build (chunk_keys={cap}) differs from the whole-mesh result")
+        sec = _sync_time(torch, lambda: b.launch(conn, stream), max(3, steps // 2))
         nb.timing_read()
-        nb.timing_enable(True)
-        n = max(3, steps // 2)
-        sec = _sync_time(torch, lambda: b.launch(conn, stream), n)
+        nb.timing_enable(True)  # one more call, timed per kernel, to count its ranges
+        b.launch(conn, stream)
+        torch.cuda.synchronize()
         nb.timing_enable(False)
-        kt = nb.timing_read()
-        ranges = kt["chunk_elem_hist"][0] / n if "chunk_elem_hist" in kt else 0
+        ranges = nb.timing_read().get("chunk_compact", (0,))[0]
         out[f"chunk_keys_{cap}"] = {"ms_per_step": sec * 1e3, "elements_per_s": m.n_elem / sec,
                                     "workspace_bytes": b.ws_bytes, "ranges_per_call": ranges}
         log(f"[bench] {m.name} chunk_keys={cap}: {sec * 1e3:.3f} ms/step, {ranges:.0f} ranges, "
@@ -452,11 +476,12 @@ def run_serving(meshes, torch, nb, rate_elems=None, n_req=5000, warm=500, slots=
     reqs = [serve.Request(i, float(t), src.get(int(j), meshes[j].conn), meshes[j].etype, meshes[j].n_vert)
             for i, (j, t) in enumerate(zip(pick, arr))]
     ex.warm(reqs, max_batch)  # device buffers sized up front: no allocation while serving
-    srv = serve.Server(ex, serve.RealClock(), n_slots=slots, budget_bytes=budget, max_batch=max_batch,
-                       on_complete=on_complete)
-    t0 = time.perf_counter()
-    done = srv.run(reqs)
-    wall = time.perf_counter() - t0
+    with serve.frozen_gc():  # no full collector pass inside the serving loop
+        srv = serve.Server(ex, serve.RealClock(), n_slots=slots, budget_bytes=budget, max_batch=max_batch,
+                           on_complete=on_complete)
+        t0 = time.perf_counter()
+        done = srv.run(reqs)
+        wall = time.perf_counter() - t0
     measured = sorted(done, key=lambda r: r.rid)[warm:]  # the first `warm` arrivals are warm-up
     summ = serve.latency_summary(measured)
     summ.update({"offered_elements_per_s": rate_elems, "arrivals": "poisson" if rate_elems else "all at t=0",

@@ -135,13 +135,12 @@ typedef struct {
  * (vertex, element) pairs over the top 11 bits of the vertex id is read back
  * (the call waits on its stream once, so it cannot be captured into a
  * graph), the host cuts [0, n_vert) at bin boundaries into ranges of at most
- * chunk_keys pairs and chunk_keys vertices, and each range sorts only its own
- * pairs (every range reads the whole connectivity) and writes its element
- * rows, then derives its node rows, straight into the outputs.  The
- * workspace holds O(chunk_keys) words plus a quarter byte per connectivity
- * slot (the look-back status of the first radix pass, which reads every
- * slot; half a byte from 2^30 slots on), where a whole-mesh build takes 17
- * to 50 bytes per slot.  Results are identical.
+ * chunk_keys pairs and chunk_keys vertices, and each range compacts its own
+ * pairs out of the connectivity (every range reads all of it), sorts them,
+ * and writes its element rows, then derives its node rows, straight into the
+ * outputs.  The workspace holds O(chunk_keys) words plus one 8-byte word per
+ * 8192 connectivity slots, where a whole-mesh build takes 17 to 50 bytes per
+ * slot.  Results are identical.
  * Applies to mesh_node_neighbors, mesh_elem_neighbors, mesh_neighbors (and
  * their queries and mesh_neighbors_noalloc) under the ELEM_ROWS node
  * algorithm with 8-bit digits; other entry points, node algorithms or

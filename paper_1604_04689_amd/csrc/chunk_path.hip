@@ -15,9 +15,11 @@
 //   per range [v0, v1), its pairs starting at element-CSR entry ebase:
 //     fill            header (error word kept), histograms, look-back words,
 //                     the range's row starts
-//     elem_hist       digit histograms of u = v - v0 over the range's pairs
-//     radix passes    the first reads the whole connectivity and keeps the
-//                     range's pairs ((u << 32) | e); the last writes the
+//     chunk_compact   conn -> the range's (u << 32) | e keys, u = v - v0, in
+//                     connectivity order (a stable compaction: tile offsets
+//                     by a decoupled look-back over one count)
+//     chunk_hist      digit histograms of the range's passes over its keys
+//     radix passes    stable, by the digits of u; the last writes the
 //                     element columns at ebase and the range's row starts
 //     rowptr_fill     row starts of the range's empty rows
 //     chunk_rows      element row starts + ebase -> the caller's row_ptr
@@ -26,10 +28,85 @@
 //                     range's last one on the device
 #include <vector>
 
+#include "edges.hpp"
 #include "elem.hpp"
 #include "erows.hpp"
 
 namespace mnb {
+
+// Stable compaction of one range's keys.  Tile t (by ticket) covers
+// connectivity slots [t * CC_TILE, (t + 1) * CC_TILE); item j of thread x is
+// slot t * CC_TILE + j * CC_BLOCK + x, so (item, wave, lane) order is slot
+// order.  A key's place is the number of the range's keys in earlier slots:
+// the tile's own by ballots and a scan of the per-(item, wave) counts, the
+// earlier tiles' by a decoupled look-back over one running count.  Their
+// number goes to *pair_count.  (Counting the digit histograms here too was
+// measured slower: every tile adding its few hundred digit counts to the same
+// global words queued those atomics behind each other.)
+constexpr int CC_BLOCK = 512;
+constexpr int CC_ITEMS = 16;
+constexpr int CC_TILE = CC_BLOCK * CC_ITEMS;
+constexpr int TK_COMPACT = 4;  // ticket slot in the workspace header (after the passes')
+constexpr int CHUNK_HIST_GRID = 128;  // blocks of the range's histogram kernel (each adds its counts once)
+
+template <int ET>
+__global__ __launch_bounds__(CC_BLOCK) void chunk_compact_kernel(ElemPairSrc<ET> src, int64_t n_slots,
+                                                                 uint64_t* __restrict__ keys, int64_t keys_cap,
+                                                                 uint64_t* lookback, uint32_t* ticket,
+                                                                 uint32_t* pair_count, uint32_t* err) {
+    constexpr int WAVES = CC_BLOCK / WAVE;
+    constexpr int PARTS = CC_ITEMS * WAVES;
+    static_assert(PARTS == 2 * WAVE, "two (item, wave) counts per lane of the scanning wave");
+    __shared__ uint32_t s_cnt[PARTS];  // count of (item j, wave w) at j * WAVES + w, then its offset
+    __shared__ uint32_t s_tile, s_total;
+    __shared__ uint64_t s_prefix;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
+    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const int64_t first = (int64_t)tile * CC_TILE;
+    uint64_t key[CC_ITEMS];
+#pragma unroll
+    for (int j = 0; j < CC_ITEMS; ++j) {
+        const int64_t i = first + j * CC_BLOCK + tid;
+        key[j] = i < n_slots ? src.load(i) : KEY_NONE;
+    }
+    const uint64_t lt = (1ull << lane) - 1;
+    uint32_t rank[CC_ITEMS];
+#pragma unroll
+    for (int j = 0; j < CC_ITEMS; ++j) {
+        const bool valid = key[j] != KEY_NONE;
+        const uint64_t b = __ballot(valid);
+        rank[j] = (uint32_t)__popcll(b & lt);
+        if (lane == 0) s_cnt[j * WAVES + wid] = (uint32_t)__popcll(b);
+    }
+    __syncthreads();
+    if (wid == 0) {
+        const uint32_t a = s_cnt[2 * lane], b = s_cnt[2 * lane + 1];
+        const uint32_t incl = wave_inclusive_sum(a + b);
+        s_cnt[2 * lane] = incl - a - b;
+        s_cnt[2 * lane + 1] = incl - b;
+        const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+        if (lane == 0) lb_store(lookback + tile, (tile == 0 ? LB_INC : LB_AGG) | (uint64_t)total);
+        const uint64_t before = wave_lookback_prefix(lookback, tile, total, err);
+        if (lane == 0) {
+            s_prefix = before;
+            s_total = total;
+        }
+    }
+    __syncthreads();
+    const uint64_t prefix = s_prefix;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < CC_ITEMS; ++j) {
+        if (key[j] == KEY_NONE) continue;
+        const uint64_t dst = prefix + s_cnt[j * WAVES + wid] + rank[j];
+        if (dst < (uint64_t)keys_cap) keys[dst] = key[j];
+        else bad = true;
+    }
+    if (bad) set_error(err, ERR_INTERNAL);
+    if (tid == 0 && s_total) atomicAdd(pair_count, s_total);
+}
 
 // dst[i] = src[i] + add for i < n.
 constexpr int CR_BLOCK = 256;
@@ -78,16 +155,16 @@ bool plan_chunked(int64_t n_elem, int32_t etype, int32_t n_vert, const Opts& o, 
         p->er.lb_words = erows_scan_tiles((int32_t)cap) * 2;
         off += align_up((size_t)p->er.lb_words * sizeof(uint32_t));
     }
-    p->zero_bytes = off;
-    // look-back words: the first pass runs over every slot (32-bit words below
-    // LB32_MAX_KEYS slots, which take half the room), later ones over the
-    // range's keys
+    // the compaction's look-back (one word per tile of CC_TILE slots) and
+    // the first pass's, both cleared per range with the header; every pass
+    // clears the next one's
+    p->off_clb = off;
+    off += align_up((size_t)ceil_div(p->n_slots, (int64_t)CC_TILE) * sizeof(uint64_t));
     p->off_lb0 = off;
-    const size_t lb0 = radix_lookback_bytes(p->n_slots, false);
-    off += align_up(p->n_slots < LB32_MAX_KEYS ? lb0 / 2 : lb0);
+    off += align_up(radix_lookback_bytes(cap, false));
+    p->zero_bytes = off;
     p->off_lb1 = off;
     off += align_up(radix_lookback_bytes(cap, false));
-    p->lb_end = off;
     p->off_keys0 = off;
     off += align_up((size_t)cap * sizeof(uint64_t));
     p->off_keys1 = off;
@@ -176,10 +253,9 @@ hipError_t run_range(const ChunkPlan& p, const Range& r, const int32_t* conn, in
     uint32_t* hist = (uint32_t*)(w + p.off_hist);
     const int32_t nv = r.v1 - r.v0;
     int32_t* erp = (int32_t*)(w + p.off_erp);
-    const FillRegion fill[3] = {header_fill(w, p.zero_bytes, /*keep_err=*/true),
-                                {w + p.off_lb0, (int64_t)((p.lb_end - p.off_lb0) / 4), 0u},
+    const FillRegion fill[2] = {header_fill(w, p.zero_bytes, /*keep_err=*/true),
                                 {erp, (int64_t)nv + 1, r.count == 0 ? 0u : (uint32_t)INT32_MAX}};
-    hipError_t e = fill_regions(fill, 3, s);
+    hipError_t e = fill_regions(fill, 2, s);
     if (e != hipSuccess) return e;
 
     // the range's element columns: in the caller's output at ebase, or in the
@@ -195,38 +271,30 @@ hipError_t run_range(const ChunkPlan& p, const Range& r, const int32_t* conn, in
     }
     if (r.count > 0) {
         const PassPlan pp = plan_passes(id_bits_for(nv), RBITS);
-        const DigitPlan dp = digit_plan(pp);
-        const int grid = (int)tmin<int64_t>(ceil_div(p.n_elem, HIST_BLOCK), HIST_GRID_MAX);
-        e = launch("chunk_elem_hist", elem_hist_kernel<ET, RADIX>, dim3(grid), dim3(HIST_BLOCK), s, conn, p.n_elem,
-                   p.n_vert, r.v0, nv, dp, hist, count, err);
         uint64_t* lb[2] = {(uint64_t*)(w + p.off_lb0), (uint64_t*)(w + p.off_lb1)};
         uint64_t* kb[2] = {(uint64_t*)(w + p.off_keys0), (uint64_t*)(w + p.off_keys1)};
+        e = launch("chunk_compact", chunk_compact_kernel<ET>, dim3((unsigned)ceil_div(p.n_slots, CC_TILE)),
+                   dim3(CC_BLOCK), s, ElemPairSrc<ET>{conn, nv, r.v0}, p.n_slots, kb[0], p.cap,
+                   (uint64_t*)(w + p.off_clb), hdr + HDR_TICKET0 + TK_COMPACT, count, err);
+        if (e == hipSuccess)
+            e = launch("chunk_hist", key_hist_kernel,
+                       dim3((unsigned)tmin<int64_t>(ceil_div(r.count, 4 * KH_BLOCK), CHUNK_HIST_GRID)), dim3(KH_BLOCK),
+                       s, (const uint64_t*)kb[0], (const int32_t*)count, 32u, pp.n_pass, pp.width[pp.n_pass - 1],
+                       hist);
+        // every pass over the range's keys: pass q reads kb[q & 1] and clears
+        // the look-back words of pass q + 1; the last writes the CSR
         const CsrOut csr{ecols, erp, ecols ? ecap : 0, 32u, 0xffffffffull};
-        const ElemPairSrc<ET> first{conn, nv, r.v0};
         for (int q = 0; q < pp.n_pass && e == hipSuccess; ++q) {
             const bool last = q + 1 == pp.n_pass;
             const uint32_t shift = 32 + pp.shift[q], bits = pp.width[q];
-            const uint32_t* hq = hist + q * RADIX;
+            const CountedKeySrc src{kb[q & 1], count};
             uint32_t* ticket = hdr + HDR_TICKET0 + TK_PASS0 + q;
-            // the first pass runs over every slot and the later ones over the
-            // range's keys, with look-back words of their own widths: the
-            // first hands no status slots on (the fill cleared lb[1]); later
-            // passes hand them on as usual
-            uint64_t* lb_next = q == 0 || last ? nullptr : lb[(q + 1) & 1];
-            const CountedKeySrc later{kb[(q - 1) & 1], count};
-            const KeyOut out{kb[q & 1]};
-            if (q == 0 && last)
-                e = launch_radix_pass("chunk_elem_radix_first", p.opts.shape, first, csr, p.n_slots, shift, bits, hq,
-                                      lb[0], nullptr, ticket, err, s);
-            else if (q == 0)
-                e = launch_radix_pass("chunk_elem_radix_first", p.opts.shape, first, out, p.n_slots, shift, bits, hq,
-                                      lb[0], nullptr, ticket, err, s);
-            else if (last)
-                e = launch_radix_pass("chunk_elem_radix", p.opts.shape, later, csr, r.count, shift, bits, hq,
-                                      lb[q & 1], lb_next, ticket, err, s);
+            if (last)
+                e = launch_radix_pass("chunk_elem_radix", p.opts.shape, src, csr, r.count, shift, bits,
+                                      hist + q * RADIX, lb[q & 1], nullptr, ticket, err, s);
             else
-                e = launch_radix_pass("chunk_elem_radix", p.opts.shape, later, out, r.count, shift, bits, hq,
-                                      lb[q & 1], lb_next, ticket, err, s);
+                e = launch_radix_pass("chunk_elem_radix", p.opts.shape, src, KeyOut{kb[(q + 1) & 1]}, r.count,
+                                      shift, bits, hist + q * RADIX, lb[q & 1], lb[(q + 1) & 1], ticket, err, s);
         }
         if (e == hipSuccess)
             e = launch_rowptr_fill("chunk_elem_row_fill", erp, nv, count, (int32_t*)(w + p.off_bmin), s);

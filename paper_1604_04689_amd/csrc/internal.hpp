@@ -149,13 +149,14 @@ hipError_t run_erows_uniform(int32_t etype, const ErowsPlan& er, const int32_t* 
 // The relations of one mesh of one type, one vertex range at a time: a
 // histogram over the top vertex bits (coarse bins) is read back, the host cuts
 // the vertices into ranges of at most `cap` pairs and `cap` vertices, and each
-// range sorts its own pairs and writes its rows.  Workspace: the header and
-// the per-range histograms (cleared per range, with the node stage's scan
-// look-back), the look-back words of the first pass (over every connectivity
-// slot) and of later passes (over at most cap keys), two key buffers of cap
-// keys, the range's element row starts (and, for a node-only call, its
-// element columns), the coarse bins and their block partials, and the node
-// stage's buffers for cap entries.
+// range compacts its own pairs out of the connectivity, sorts them and writes
+// its rows.  Workspace: the header, the per-range histograms, the node
+// stage's scan look-back, the compaction's look-back (one word per 8192
+// connectivity slots) and the first pass's (all cleared per range), the
+// other passes' look-back and two key buffers of cap keys, the range's
+// element row starts (and, for a node-only call, its element columns), the
+// coarse bins and their block partials, and the node stage's buffers for cap
+// entries.
 constexpr int64_t CHUNK_MIN_KEYS = 4096;
 struct ChunkPlan {
     int64_t n_elem = 0;
@@ -168,7 +169,8 @@ struct ChunkPlan {
     bool node = false;         // the node relation is written
     bool elem_out = false;     // the element relation goes to the caller
     size_t off_hist = 0, zero_bytes = 0;  // [0, zero_bytes): cleared per range (error word kept)
-    size_t off_lb0 = 0, off_lb1 = 0, lb_end = 0;
+    size_t off_clb = 0;        // look-back words of the compaction (one per tile of slots)
+    size_t off_lb0 = 0, off_lb1 = 0;
     size_t off_keys0 = 0, off_keys1 = 0, off_bmin = 0, off_erp = 0, off_ecols = 0;
     size_t off_bins = 0, off_part = 0;
     ErowsPlan er;

@@ -28,8 +28,10 @@ The executor is pluggable:
 from __future__ import annotations
 
 import collections
+import contextlib
 import dataclasses
 import functools
+import gc
 import heapq
 import math
 import time
@@ -479,6 +481,21 @@ class GpuExecutor:
         batch.payload = None
 
 
+@contextlib.contextmanager
+def frozen_gc():
+    """Collect once, then keep every object alive now out of the cyclic
+    collector's passes until the block ends.  A full pass over all the
+    objects a serving process holds (meshes, tensors, requests) takes tens of
+    milliseconds and, inside the serving loop, shows as a latency outlier;
+    enter this before the clock starts."""
+    gc.collect()
+    gc.freeze()
+    try:
+        yield
+    finally:
+        gc.unfreeze()
+
+
 class RealClock:
     def __init__(self):
         self.t0 = time.perf_counter()
@@ -626,8 +643,12 @@ class Server:
 
 def latency_summary(reqs: List[Request]):
     lat = np.array([r.latency for r in reqs])
+    arr = np.array([r.arrival for r in reqs])
     elems = sum(r.n_elem for r in reqs)
-    span = max(r.completed for r in reqs) - min(r.arrival for r in reqs)
-    return {"requests": len(reqs), "p50_ms": float(np.percentile(lat, 50) * 1e3),
-            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+    span = max(r.completed for r in reqs) - arr.min()
+    p99 = float(np.percentile(lat, 99))
+    tail = arr[lat >= p99] - arr.min()  # when the slowest 1% arrived (a stall shows as a narrow window)
+    return {"requests": len(reqs), "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": p99 * 1e3,
+            "max_ms": float(lat.max() * 1e3), "mean_ms": float(lat.mean() * 1e3),
+            "p99_tail_arrivals_s": [float(tail.min()), float(tail.max())],
             "elements": int(elems), "span_s": float(span), "elements_per_s": float(elems / span)}

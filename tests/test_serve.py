@@ -187,3 +187,12 @@ def test_unreleased_results_hold_the_budget():
     with pytest.raises(serve.BudgetError, match="unreleased results"):
         run(make_requests(16, rate=1e6, seed=32), n_slots=2, budget_bytes=budget, max_batch=1, keep_results=True,
             **sizes)
+
+
+def test_frozen_gc_restores_the_collector():
+    import gc
+    from paper_1604_04689_amd import serve
+    before = gc.get_freeze_count()
+    with serve.frozen_gc():
+        assert gc.get_freeze_count() > before
+    assert gc.get_freeze_count() == before
