@@ -44,7 +44,10 @@ namespace mnb {
 // measured slower: every tile adding its few hundred digit counts to the same
 // global words queued those atomics behind each other.)
 constexpr int CC_BLOCK = 512;
-constexpr int CC_ITEMS = 16;
+// Tiles are large: the tiles' look-back is a chain that passes one status
+// word from tile to tile, and with 8192-slot tiles that chain, not the reads,
+// set the kernel's time (about 30 ns per tile on MI355X).
+constexpr int CC_ITEMS = 48;
 constexpr int CC_TILE = CC_BLOCK * CC_ITEMS;
 constexpr int TK_COMPACT = 4;  // ticket slot in the workspace header (after the passes')
 constexpr int CHUNK_HIST_GRID = 128;  // blocks of the range's histogram kernel (each adds its counts once)
@@ -54,9 +57,11 @@ __global__ __launch_bounds__(CC_BLOCK) void chunk_compact_kernel(ElemPairSrc<ET>
                                                                  uint64_t* __restrict__ keys, int64_t keys_cap,
                                                                  uint64_t* lookback, uint32_t* ticket,
                                                                  uint32_t* pair_count, uint32_t* err) {
+    constexpr int NPE = ElemPairSrc<ET>::NPE;
     constexpr int WAVES = CC_BLOCK / WAVE;
     constexpr int PARTS = CC_ITEMS * WAVES;
-    static_assert(PARTS == 2 * WAVE, "two (item, wave) counts per lane of the scanning wave");
+    constexpr int PER_LANE = PARTS / WAVE;  // (item, wave) counts each lane of the scanning wave takes
+    static_assert(PARTS % WAVE == 0 && CC_ITEMS <= 64, "whole counts per lane; one mask bit per item");
     __shared__ uint32_t s_cnt[PARTS];  // count of (item j, wave w) at j * WAVES + w, then its offset
     __shared__ uint32_t s_tile, s_total;
     __shared__ uint64_t s_prefix;
@@ -65,27 +70,44 @@ __global__ __launch_bounds__(CC_BLOCK) void chunk_compact_kernel(ElemPairSrc<ET>
     __syncthreads();
     const uint32_t tile = s_tile;
     const int64_t first = (int64_t)tile * CC_TILE;
-    uint64_t key[CC_ITEMS];
+    // every slot's id first (all loads in flight); a slot takes part when its
+    // id lies in the window and first occurs there in its element (the few
+    // such slots read their element's earlier ids)
+    int32_t id[CC_ITEMS];
 #pragma unroll
     for (int j = 0; j < CC_ITEMS; ++j) {
         const int64_t i = first + j * CC_BLOCK + tid;
-        key[j] = i < n_slots ? src.load(i) : KEY_NONE;
+        id[j] = i < n_slots ? src.conn[i] : src.v_lo - 1;
     }
-    const uint64_t lt = (1ull << lane) - 1;
-    uint32_t rank[CC_ITEMS];
+    uint64_t valid = 0;
 #pragma unroll
     for (int j = 0; j < CC_ITEMS; ++j) {
-        const bool valid = key[j] != KEY_NONE;
-        const uint64_t b = __ballot(valid);
-        rank[j] = (uint32_t)__popcll(b & lt);
+        if ((uint32_t)(id[j] - src.v_lo) < (uint32_t)src.n_vert) {
+            const uint32_t s = (uint32_t)(first + j * CC_BLOCK + tid);  // slot indices stay below 2^31
+            const uint32_t e = s / NPE;
+            if (first_occurrence<NPE>(src.conn, e, (int)(s - e * NPE), id[j])) valid |= 1ull << j;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < CC_ITEMS; ++j) {
+        const uint64_t b = __ballot((valid >> j) & 1ull);
         if (lane == 0) s_cnt[j * WAVES + wid] = (uint32_t)__popcll(b);
     }
     __syncthreads();
     if (wid == 0) {
-        const uint32_t a = s_cnt[2 * lane], b = s_cnt[2 * lane + 1];
-        const uint32_t incl = wave_inclusive_sum(a + b);
-        s_cnt[2 * lane] = incl - a - b;
-        s_cnt[2 * lane + 1] = incl - b;
+        uint32_t c[PER_LANE], sum = 0;
+#pragma unroll
+        for (int k = 0; k < PER_LANE; ++k) {
+            c[k] = s_cnt[PER_LANE * lane + k];
+            sum += c[k];
+        }
+        const uint32_t incl = wave_inclusive_sum(sum);
+        uint32_t run = incl - sum;
+#pragma unroll
+        for (int k = 0; k < PER_LANE; ++k) {
+            s_cnt[PER_LANE * lane + k] = run;
+            run += c[k];
+        }
         const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
         if (lane == 0) lb_store(lookback + tile, (tile == 0 ? LB_INC : LB_AGG) | (uint64_t)total);
         const uint64_t before = wave_lookback_prefix(lookback, tile, total, err);
@@ -96,12 +118,15 @@ __global__ __launch_bounds__(CC_BLOCK) void chunk_compact_kernel(ElemPairSrc<ET>
     }
     __syncthreads();
     const uint64_t prefix = s_prefix;
+    const uint64_t lt = (1ull << lane) - 1;
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < CC_ITEMS; ++j) {
-        if (key[j] == KEY_NONE) continue;
-        const uint64_t dst = prefix + s_cnt[j * WAVES + wid] + rank[j];
-        if (dst < (uint64_t)keys_cap) keys[dst] = key[j];
+        const uint64_t b = __ballot((valid >> j) & 1ull);
+        if (!((valid >> j) & 1ull)) continue;
+        const uint64_t dst = prefix + s_cnt[j * WAVES + wid] + (uint64_t)__popcll(b & lt);
+        const uint32_t e = (uint32_t)(first + j * CC_BLOCK + tid) / NPE;
+        if (dst < (uint64_t)keys_cap) keys[dst] = ((uint64_t)(uint32_t)(id[j] - src.v_lo) << 32) | (uint64_t)e;
         else bad = true;
     }
     if (bad) set_error(err, ERR_INTERNAL);

@@ -400,6 +400,13 @@ class GpuExecutor:
                 else:
                     self.slot_state[i].reset(desc, s, outputs=False)
             self.free_outs.append(self._take_outputs(self.slot_state[i].output_sizes()))
+        # the first use of a torch kernel loads its code (up to about 0.1 s,
+        # measured inside the serving loop on MI355X): run the row gathers of
+        # every batch size once now (torch picks different kernels for few
+        # and for many indices)
+        nrp, erp = self.free_outs[0]["bufs"][0], self.free_outs[0]["bufs"][2]
+        for n in range(1, max_batch + 2):
+            self._gather_rows(nrp, erp, np.zeros(n, dtype=np.int64))
         torch.cuda.synchronize(self.device)
 
     def _take_outputs(self, sizes):
@@ -430,13 +437,15 @@ class GpuExecutor:
         2 x (requests + 1) entries of the completed batch's row pointers)."""
         p = batch.payload
         if "bounds" not in p:
-            torch = self.torch
-            idx = torch.as_tensor(np.append(p["seg"]["vert_off"], p["build"].totals["vert"]).astype(np.int64),
-                                  device=self.device)
-            nrp, erp = p["outs"][0], p["outs"][2]
-            both = torch.stack([nrp.index_select(0, idx), erp.index_select(0, idx)])
-            p["bounds"] = both.cpu().numpy()
+            p["bounds"] = self._gather_rows(p["outs"][0], p["outs"][2],
+                                            np.append(p["seg"]["vert_off"], p["build"].totals["vert"]))
         return p["bounds"]
+
+    def _gather_rows(self, nrp, erp, rows):
+        """nrp[rows] and erp[rows] as one (2, len(rows)) host array."""
+        torch = self.torch
+        idx = torch.as_tensor(np.asarray(rows, dtype=np.int64), device=self.device)
+        return torch.stack([nrp.index_select(0, idx), erp.index_select(0, idx)]).cpu().numpy()
 
     def handles(self, batch: BatchHandle, on_release):
         """One ResultHandle per request: device views into the batch's own
