@@ -139,7 +139,7 @@ typedef struct {
  * pairs out of the connectivity (every range reads all of it), sorts them,
  * and writes its element rows, then derives its node rows, straight into the
  * outputs.  The workspace holds O(chunk_keys) words plus one 8-byte word per
- * 8192 connectivity slots, where a whole-mesh build takes 17 to 50 bytes per
+ * 24576 connectivity slots, where a whole-mesh build takes 17 to 50 bytes per
  * slot.  Results are identical.
  * Applies to mesh_node_neighbors, mesh_elem_neighbors, mesh_neighbors (and
  * their queries and mesh_neighbors_noalloc) under the ELEM_ROWS node

@@ -151,7 +151,7 @@ hipError_t run_erows_uniform(int32_t etype, const ErowsPlan& er, const int32_t* 
 // the vertices into ranges of at most `cap` pairs and `cap` vertices, and each
 // range compacts its own pairs out of the connectivity, sorts them and writes
 // its rows.  Workspace: the header, the per-range histograms, the node
-// stage's scan look-back, the compaction's look-back (one word per 8192
+// stage's scan look-back, the compaction's look-back (one word per 24576
 // connectivity slots) and the first pass's (all cleared per range), the
 // other passes' look-back and two key buffers of cap keys, the range's
 // element row starts (and, for a node-only call, its element columns), the

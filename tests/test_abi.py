@@ -325,8 +325,8 @@ def test_chunk_budget_covers_one_bin():
 @pytest.mark.parametrize("etype", [0, 1, 2])
 def test_chunk_workspace_is_bounded(etype):
     """The whole-mesh build takes 17 to 50 bytes per connectivity slot; the
-    bounded build takes O(chunk_keys) plus one 8-byte look-back word per 8192
-    slots (the compaction's)."""
+    bounded build takes O(chunk_keys) plus one 8-byte look-back word per 24576
+    slots (the compaction's tiles)."""
     npe = binding.NODES_PER_ELEM[etype]
     n_elem, n_vert, cap = 4_000_000, 1_500_000, 1 << 20
     for kind in ("node", "elem", "both"):
@@ -335,7 +335,7 @@ def test_chunk_workspace_is_bounded(etype):
         b = binding.query(kind, 2 * n_elem, etype, n_vert, {"chunk_keys": cap})[0]
         assert whole >= 17 * npe * n_elem
         assert a < whole / 4
-        assert abs((b - a) - npe * n_elem / 1024) < 512         # 8 bytes per 8192 added slots
+        assert abs((b - a) - npe * n_elem * 8 / 24576) < 512    # 8 bytes per 24576 added slots
         assert a < 80 * cap + (4 << 20)                          # O(cap) otherwise
 
 
