@@ -747,6 +747,9 @@ bool plan_batch_node(int64_t total_pairs, int64_t total_slots, int32_t total_ver
         }
         off = plan_erows(total_slots, MAX_NPE - 1, total_vert, off, p->bp.off_keys0, p->bp.off_bmin - p->bp.off_keys0,
                          &p->er);
+        p->tlist_stride = p->er.n_tiles + 1;
+        p->off_tlists = off;
+        off += align_up((size_t)ER_LISTS * (size_t)p->tlist_stride * sizeof(int32_t));
         p->total = off;
         return true;
     }
@@ -903,8 +906,10 @@ hipError_t run_batch_node(const BatchNodePlan& bn, const int32_t* conn, const me
         if (p.n_keys == 0 || n_mesh == 0) return fill_i32(row_ptr, (int64_t)total_vert + 1, 0, s);
         uint32_t* hdr = (uint32_t*)w;
         const ErowsBufs b = erows_bufs(bn.er, w, hdr + HDR_ERR, hdr + HDR_TICKET0 + TK_EROWS);
-        return launch_erows("batch_node", BatchRows{conn, segs, n_mesh}, erp, ecols, ecap, total_vert, p.n_keys,
-                            row_ptr, cols, cols_cap, b, s);
+        static_assert(HDR_TILE_LISTS + ER_LISTS <= (int)(HEADER_BYTES / 4), "tile-list counts inside the header");
+        return launch_erows_batch("batch_node", conn, segs, n_mesh, erp, ecols, ecap, total_vert, p.n_keys, row_ptr,
+                                  cols, cols_cap, b, (int32_t*)(w + bn.off_tlists), bn.tlist_stride,
+                                  hdr + HDR_TILE_LISTS, s);
     }
     const bool empty = p.n_keys == 0 || n_mesh == 0;
     FillRegion fill[3] = {header_fill(ws, p.zero_bytes, keep_err)};

@@ -25,6 +25,7 @@ constexpr int HDR_TICKET0 = 4;      // u32 index of the first tile ticket
 constexpr int N_TICKETS = 16;
 constexpr int HDR_LONG_COUNT = 32;  // u32 index of the long-row counter
 constexpr int HDR_KEY_COUNT = 33;   // u32 index of a device-side key count
+constexpr int HDR_TILE_LISTS = 40;  // u32 index of the batch stage's tile-list counts (7 words)
 
 // Decoupled look-back status word: 2 flag bits over a 62-bit value.
 constexpr uint64_t LB_AGG = 1ull << 62;  // value = this tile's own count

@@ -199,9 +199,29 @@ struct MixedRows {
     }
 };
 
+// The mesh of global vertex v in a batch: the last segment with vert_off <=
+// v (vert_off non-decreasing), by binary search.
+__device__ __forceinline__ int32_t batch_mesh_of(const mesh_segment* __restrict__ segs, int32_t n_mesh, int32_t v) {
+    int lo = 0, hi = n_mesh - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].vert_off <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+// The mesh of v >= the first vertex of mesh m0: walk forward from m0 (a
+// tile's rows span few meshes, so this is a step or two, not a search).
+__device__ __forceinline__ int32_t batch_mesh_from(const mesh_segment* __restrict__ segs, int32_t n_mesh, int32_t m0,
+                                                   int32_t v) {
+    int32_t m = m0 < 0 ? 0 : m0;
+    while (m + 1 < n_mesh && segs[m + 1].vert_off <= v) ++m;
+    return m;
+}
+
 // A batch: row vertex v is global; its mesh is the last segment with
-// vert_off <= v (vert_off non-decreasing), its element ids are local to that
-// mesh and so are the candidates.  ctx(v) is the mesh index.
+// vert_off <= v, its element ids are local to that mesh and so are the
+// candidates.  ctx(v) is the mesh index.  Any element type per mesh.
 struct BatchRows {
     static constexpr int S = MAX_NPE - 1;
     static constexpr int IDS = MAX_NPE;
@@ -214,21 +234,9 @@ struct BatchRows {
         int32_t et, vl, nv;
         bool ok, bad;
     };
-    __device__ __forceinline__ int32_t ctx(int32_t v) const {
-        int lo = 0, hi = n_mesh - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (segs[mid].vert_off <= v) lo = mid;
-            else hi = mid - 1;
-        }
-        return lo;
-    }
-    // The mesh of v >= the first vertex of mesh m0: walk forward from m0 (a
-    // tile's rows span few meshes, so this is a step or two, not a search).
+    __device__ __forceinline__ int32_t ctx(int32_t v) const { return batch_mesh_of(segs, n_mesh, v); }
     __device__ __forceinline__ int32_t ctx_from(int32_t m0, int32_t v) const {
-        int32_t m = m0 < 0 ? 0 : m0;
-        while (m + 1 < n_mesh && segs[m + 1].vert_off <= v) ++m;
-        return m;
+        return batch_mesh_from(segs, n_mesh, m0, v);
     }
     __device__ __forceinline__ Loc locate(int32_t m, int32_t v, int32_t e, bool in) const {
         Loc l{0, 0, 0, 0, false, false};
@@ -255,6 +263,62 @@ struct BatchRows {
             return;
         }
         *bad |= !runtime_cands(ids, l.et, l.vl, l.nv, c);
+    }
+};
+
+// A batch whose rows (those of one tile) all belong to meshes of element type
+// ET: the same access as BatchRows with the type's own candidate slots (S =
+// npe - 1 instead of the largest type's), so a tile of triangles or
+// tetrahedra keeps its registers and LDS tables to its own size.  An entry of
+// a mesh of another type is an error (the tile lists never send one here).
+template <int ET>
+struct BatchTypedRows {
+    static constexpr int NPE = Elem<ET>::NPE;
+    static constexpr int S = NPE - 1;
+    static constexpr int IDS = NPE;
+    static constexpr bool kCtx = true;
+    const int32_t* __restrict__ conn;
+    const mesh_segment* __restrict__ segs;
+    int32_t n_mesh;
+    struct Loc {
+        int64_t off;
+        int32_t vl, nv;
+        bool ok, bad;
+    };
+    __device__ __forceinline__ int32_t ctx(int32_t v) const { return batch_mesh_of(segs, n_mesh, v); }
+    __device__ __forceinline__ int32_t ctx_from(int32_t m0, int32_t v) const {
+        return batch_mesh_from(segs, n_mesh, m0, v);
+    }
+    __device__ __forceinline__ Loc locate(int32_t m, int32_t v, int32_t e, bool in) const {
+        Loc l{0, 0, 0, false, false};
+        if (!in) return l;
+        const mesh_segment& sg = segs[m];
+        l.vl = v - sg.vert_off;
+        l.nv = sg.n_vert;
+        l.ok = sg.etype == ET && (uint64_t)(uint32_t)e < (uint64_t)sg.n_elem && l.vl >= 0 && l.vl < sg.n_vert;
+        l.bad = !l.ok;
+        l.off = l.ok ? sg.conn_off + (int64_t)e * NPE : 0;
+        return l;
+    }
+    __device__ __forceinline__ void fetch(const Loc& l, int32_t (&ids)[IDS]) const {
+        if (l.ok) {
+            const int32_t* el = conn + l.off;
+#pragma unroll
+            for (int j = 0; j < NPE; ++j) ids[j] = el[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < NPE; ++j) ids[j] = -1;
+        }
+    }
+    __device__ __forceinline__ void cands(const Loc& l, const int32_t (&ids)[IDS], int32_t, uint32_t (&c)[S],
+                                          bool* bad) const {
+        *bad |= l.bad;
+        if (!l.ok) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) c[s] = CAND_NONE;
+            return;
+        }
+        *bad |= !elem_cands<NPE>(ids, NPE, adjacency_word<ET>(), l.vl, l.nv, c);
     }
 };
 
@@ -381,8 +445,8 @@ __global__ __launch_bounds__(ER_BLOCK) void erows_long_kernel(Acc acc, const int
 // row starts in its tile.  Entry position r of the tile (0 <= r < ER_SPAN,
 // entry base + r) sits in register slot r / ER_BLOCK of thread r % ER_BLOCK,
 // with its S candidates.  Row v's distinct values go, ascending, to
-// stage[S * a .. S * a + cnt[v]) (a = the row's first entry: its S candidate
-// slots per entry always have room), and cnt[v] is written for every owned
+// stage[P * a .. P * a + cnt[v]) (a = the row's first entry, P = stage_slots
+// >= S: the S candidate slots per entry always have room), and cnt[v] is written for every owned
 // vertex except the long rows (erows_long writes theirs).
 //
 // The work of a tile is a chain of memory round trips and barriers, kept
@@ -392,13 +456,12 @@ __global__ __launch_bounds__(ER_BLOCK) void erows_long_kernel(Acc acc, const int
 // row's table in one round of LDS atomics (the few that collide probe on).
 // With no offset to wait for, no tile waits for another.
 template <class Acc>
-__global__ __launch_bounds__(ER_BLOCK) void erows_tile_kernel(Acc acc, const int32_t* __restrict__ erp,
-                                                             const int32_t* __restrict__ ecols, int32_t n_vert,
-                                                             int64_t q_bound, int64_t ecap,
-                                                             const int32_t* __restrict__ tile_first,
-                                                             const int32_t* __restrict__ tile_ctx,
-                                                             int32_t* __restrict__ cnt, int32_t* __restrict__ stage,
-                                                             uint32_t* err) {
+__device__ __forceinline__ void erows_tile_body(const Acc& acc, const int32_t* __restrict__ erp,
+                                                const int32_t* __restrict__ ecols, int32_t n_vert, int64_t q_bound,
+                                                int64_t ecap, const int32_t* __restrict__ tile_first,
+                                                const int32_t* __restrict__ tile_ctx, int32_t* __restrict__ cnt,
+                                                int32_t* __restrict__ stage, int stage_slots, uint32_t* err,
+                                                int64_t t) {
     constexpr int S = Acc::S;
     constexpr int CAP = ER_SPAN * S;
     constexpr int WAVES = ER_BLOCK / WAVE;
@@ -421,7 +484,6 @@ __global__ __launch_bounds__(ER_BLOCK) void erows_tile_kernel(Acc acc, const int
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
     const int64_t q = erow_total(erp, n_vert, q_bound);
     const int64_t n_tiles = q / ER_TILE + 1;
-    const int64_t t = blockIdx.x;
     if (t >= n_tiles) return;  // owns nothing
     for (int i = tid; i < CAP + 4; i += ER_BLOCK) s_tab[i] = SLOT_EMPTY;
     const int64_t base = t * ER_TILE;
@@ -613,7 +675,7 @@ __global__ __launch_bounds__(ER_BLOCK) void erows_tile_kernel(Acc acc, const int
         if (rowk[i] < 0) continue;
         const int k = rowk[i];
         const int ds = s_rds[k], de = s_rde[k];
-        int32_t* row = stage + (int64_t)S * (base + s_ra[k]);
+        int32_t* row = stage + (int64_t)stage_slots * (base + s_ra[k]);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             if (!((kept >> (i * S + s)) & 1ull)) continue;
@@ -627,6 +689,38 @@ __global__ __launch_bounds__(ER_BLOCK) void erows_tile_kernel(Acc acc, const int
         }
     }
     if (bad) set_error(err, ERR_INTERNAL);
+}
+
+// One tile per block: tile blockIdx.x.
+template <class Acc>
+__global__ __launch_bounds__(ER_BLOCK) void erows_tile_kernel(Acc acc, const int32_t* __restrict__ erp,
+                                                             const int32_t* __restrict__ ecols, int32_t n_vert,
+                                                             int64_t q_bound, int64_t ecap,
+                                                             const int32_t* __restrict__ tile_first,
+                                                             const int32_t* __restrict__ tile_ctx,
+                                                             int32_t* __restrict__ cnt, int32_t* __restrict__ stage,
+                                                             uint32_t* err) {
+    erows_tile_body(acc, erp, ecols, n_vert, q_bound, ecap, tile_first, tile_ctx, cnt, stage, Acc::S, err,
+                    (int64_t)blockIdx.x);
+}
+
+// The tiles of a list (list[0 .. *count)), the blocks taking them in turn.
+template <class Acc>
+__global__ __launch_bounds__(ER_BLOCK) void erows_tile_list_kernel(Acc acc, const int32_t* __restrict__ erp,
+                                                                  const int32_t* __restrict__ ecols, int32_t n_vert,
+                                                                  int64_t q_bound, int64_t ecap,
+                                                                  const int32_t* __restrict__ tile_first,
+                                                                  const int32_t* __restrict__ tile_ctx,
+                                                                  int32_t* __restrict__ cnt,
+                                                                  int32_t* __restrict__ stage, int stage_slots,
+                                                                  uint32_t* err, const int32_t* __restrict__ list,
+                                                                  const uint32_t* count) {
+    const uint32_t n = *count;
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        erows_tile_body(acc, erp, ecols, n_vert, q_bound, ecap, tile_first, tile_ctx, cnt, stage, stage_slots, err,
+                        (int64_t)list[i]);
+        __syncthreads();  // the next tile rewrites the LDS tables
+    }
 }
 
 // cols[row_ptr[v] + i] = stage[S * erp[v] + i] for i < cnt[v] = row_ptr[v+1] -
@@ -752,6 +846,113 @@ hipError_t launch_erows(const char* tag, const Acc& acc, const int32_t* erp, con
         e = launch(name, erows_gather_kernel, dim3((unsigned)ceil_div((int64_t)n_vert, EG_BLOCK)), dim3(EG_BLOCK), s,
                    (const int32_t*)row_ptr, erp, Acc::S, (const int32_t*)b.stage, n_vert, q_bound, cols, cols_cap,
                    b.err);
+    }
+    return e;
+}
+
+// Tile lists of a batch by element type: list k (k < N_ELEM_TYPES) holds the
+// tiles whose owned rows all belong to meshes of type k, list N_ELEM_TYPES
+// the rest (rows of several types, or a segment record with an unknown
+// type).  Tiles that own no row are left out (their block would write
+// nothing).  One thread per tile; lists[k * stride + i], counts[k].
+constexpr int ER_LISTS = N_ELEM_TYPES + 1;
+constexpr int ER_CLASSIFY_BLOCK = 256;
+constexpr int ER_LIST_GRID = 2048;  // blocks of each list launch (each takes tiles in turn)
+static __global__ __launch_bounds__(ER_CLASSIFY_BLOCK) void erows_classify_kernel(
+    const int32_t* __restrict__ erp, int32_t n_vert, int64_t q_bound, const int32_t* __restrict__ tile_first,
+    const int32_t* __restrict__ tile_ctx, const mesh_segment* __restrict__ segs, int32_t n_mesh,
+    int32_t* __restrict__ lists, int64_t stride, uint32_t* counts) {
+    const int64_t t = (int64_t)blockIdx.x * ER_CLASSIFY_BLOCK + threadIdx.x;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t n_tiles = erow_total(erp, n_vert, q_bound) / ER_TILE + 1;
+    int k = -1;  // the tile's list, -1 for none
+    if (t < n_tiles && n_mesh > 0) {
+        // the owned vertices, clamped as erows_tile_body clamps them
+        int32_t v_first = tile_first[t];
+        int32_t v_end = t == n_tiles - 1 ? n_vert : tile_first[t + 1];
+        v_first = tmin<int32_t>(tmax<int32_t>(v_first, 0), n_vert);
+        v_end = tmin<int32_t>(tmax<int32_t>(v_end, v_first), n_vert);
+        if (v_end > v_first) {
+            const int32_t m0 = tmin<int32_t>(tmax<int32_t>(tile_ctx[t], 0), n_mesh - 1);
+            const int32_t m1 = batch_mesh_from(segs, n_mesh, m0, v_end - 1);
+            k = segs[m0].etype;
+            for (int32_t m = m0 + 1; m <= m1 && k < N_ELEM_TYPES; ++m)
+                if (segs[m].etype != k) k = N_ELEM_TYPES;
+            if (k < 0 || k > N_ELEM_TYPES) k = N_ELEM_TYPES;
+        }
+    }
+    // one counter atomic per (wave, list): most tiles go to one or two lists,
+    // and one atomic per tile on the same word queues them all behind it
+    const uint64_t lt = (1ull << lane) - 1;
+    for (int kk = 0; kk < ER_LISTS; ++kk) {
+        const uint64_t m = __ballot(k == kk);
+        if (!m) continue;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&counts[kk], (uint32_t)__popcll(m));
+        base = __shfl(base, leader, WAVE);
+        if (k == kk) {
+            const uint32_t i = base + (uint32_t)__popcll(m & lt);
+            if ((int64_t)i < stride) lists[kk * stride + i] = (int32_t)t;
+        }
+    }
+}
+
+// The stage for a batch: as launch_erows, with the tiles sorted into lists by
+// the element type of their rows' meshes and each list run with that type's
+// accessor (the rest with BatchRows).  lists: ER_LISTS * stride ints
+// (stride >= the tile bound); counts: ER_LISTS words, zero on entry.
+inline hipError_t launch_erows_batch(const char* tag, const int32_t* conn, const mesh_segment* segs, int32_t n_mesh,
+                                     const int32_t* erp, const int32_t* ecols, int64_t ecap, int32_t n_vert,
+                                     int64_t q_bound, int32_t* row_ptr, int32_t* cols, int64_t cols_cap,
+                                     const ErowsBufs& b, int32_t* lists, int64_t stride, uint32_t* counts,
+                                     hipStream_t s) {
+    const BatchRows any{conn, segs, n_mesh};
+    const int64_t n_tiles = erows_tiles_bound(q_bound);
+    if (stride < n_tiles) return hipErrorInvalidValue;
+    char name[48];
+    snprintf(name, sizeof name, "%s_erows_prep", tag);
+    hipError_t e = launch(name, erows_prep_kernel<BatchRows>,
+                          dim3((unsigned)ceil_div((int64_t)n_vert + 1, ER_PREP_BLOCK)), dim3(ER_PREP_BLOCK), s, any,
+                          erp, n_vert, q_bound, b.tile_first, b.tile_ctx, n_tiles, b.long_list,
+                          erows_long_cap(q_bound), b.long_count, b.err);
+    if (e == hipSuccess) {
+        snprintf(name, sizeof name, "%s_erows_long", tag);
+        e = launch(name, erows_long_kernel<BatchRows>, dim3(ER_LONG_GRID), dim3(ER_BLOCK), s, any, erp, ecols, n_vert,
+                   q_bound, ecap, (const int32_t*)b.long_list, erows_long_cap(q_bound), (const uint32_t*)b.long_count,
+                   b.cnt, b.stage, b.err);
+    }
+    if (e == hipSuccess) {
+        snprintf(name, sizeof name, "%s_erows_classify", tag);
+        e = launch(name, erows_classify_kernel, dim3((unsigned)ceil_div(n_tiles, ER_CLASSIFY_BLOCK)),
+                   dim3(ER_CLASSIFY_BLOCK), s, erp, n_vert, q_bound, (const int32_t*)b.tile_first,
+                   (const int32_t*)b.tile_ctx, segs, n_mesh, lists, stride, counts);
+    }
+    snprintf(name, sizeof name, "%s_erows", tag);
+    const dim3 grid((unsigned)tmin<int64_t>(n_tiles, ER_LIST_GRID));
+    auto run_list = [&](auto acc, int k) {
+        return launch(name, erows_tile_list_kernel<decltype(acc)>, grid, dim3(ER_BLOCK), s, acc, erp, ecols, n_vert,
+                      q_bound, ecap, (const int32_t*)b.tile_first, (const int32_t*)b.tile_ctx, b.cnt, b.stage,
+                      (int)BatchRows::S, b.err, (const int32_t*)(lists + k * stride), (const uint32_t*)(counts + k));
+    };
+    for (int k = 0; k < N_ELEM_TYPES && e == hipSuccess; ++k)
+        e = with_type(k, [&](auto et) {
+            constexpr int ET = decltype(et)::value;
+            return run_list(BatchTypedRows<ET>{conn, segs, n_mesh}, ET);
+        });
+    if (e == hipSuccess) e = run_list(any, N_ELEM_TYPES);
+    if (e == hipSuccess && n_vert == 0) e = fill_i32(row_ptr, 1, 0, s);
+    if (e == hipSuccess) {
+        snprintf(name, sizeof name, "%s_erows_scan", tag);
+        e = launch(name, scan_i32_kernel, dim3((unsigned)ceil_div((int64_t)n_vert, SCAN_TILE)), dim3(SCAN_BLOCK), s,
+                   (const int32_t*)b.cnt, (int64_t)n_vert, row_ptr, b.scan_lb, b.scan_ticket, b.err,
+                   (const int32_t*)nullptr);
+    }
+    if (e == hipSuccess) {
+        snprintf(name, sizeof name, "%s_erows_gather", tag);
+        e = launch(name, erows_gather_kernel, dim3((unsigned)ceil_div((int64_t)n_vert, EG_BLOCK)), dim3(EG_BLOCK), s,
+                   (const int32_t*)row_ptr, erp, (int)BatchRows::S, (const int32_t*)b.stage, n_vert, q_bound, cols,
+                   cols_cap, b.err);
     }
     return e;
 }

@@ -230,6 +230,8 @@ struct BatchNodePlan {
     bool internal_elem = false;
     size_t off_erp = 0, off_ecols = 0;
     ErowsPlan er;
+    size_t off_tlists = 0;    // ELEM_ROWS: the stage's tile lists by element type
+    int64_t tlist_stride = 0; // entries per list
     size_t total = 0;
 };
 bool plan_batch_sort(int64_t n_keys, uint32_t digit_bits, int32_t rows_vert, int32_t total_vert, const Opts& o,
