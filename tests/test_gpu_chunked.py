@@ -111,3 +111,22 @@ def test_chunked_noalloc(oracle_mod):
         assert_same((er.cpu().numpy(), ec.cpu().numpy()), whole[1], "noalloc chunked elem")
         if n == 300:
             assert_same(whole[0], oracle_mod.node_neighbors(m.conn, 0, m.n_vert), "noalloc chunked vs oracle")
+
+
+def test_chunked_unaligned_connectivity(oracle_mod):
+    """A connectivity that starts 4 bytes past an aligned address (a view of
+    a larger buffer) gives the oracle's rows under a pair budget."""
+    from paper_1604_04689_amd import binding as nb
+    dev = torch.device("cuda:0")
+    m = mg.random_mesh(30_011, 9_000, 0, seed=77)
+    flat = torch.as_tensor(np.ascontiguousarray(m.conn, dtype=np.int32).reshape(-1))
+    buf = torch.zeros(flat.numel() + 1, dtype=torch.int32, device=dev)
+    buf[1:] = flat.to(dev)
+    c = buf[1:].view(-1, 3)
+    assert c.data_ptr() % 16 == 4
+    print("[chunked] unaligned conn", flush=True)
+    got = nb.neighbors(c, 0, m.n_vert, options={"chunk_keys": 4096})
+    want_n = oracle_mod.node_neighbors(m.conn, 0, m.n_vert)
+    want_e = oracle_mod.elem_neighbors(m.conn, 0, m.n_vert)
+    assert_same((got[0][0].cpu().numpy(), got[0][1].cpu().numpy()), want_n, "unaligned chunked node")
+    assert_same((got[1][0].cpu().numpy(), got[1][1].cpu().numpy()), want_e, "unaligned chunked elem")
