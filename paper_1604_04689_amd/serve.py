@@ -98,24 +98,32 @@ class ResultHandle:
     which do); ``to_host()`` copies both CSRs, rebased, to numpy arrays."""
 
     def __init__(self, node, elem, node_base, elem_base, on_release):
+        # node / elem: (row_ptr, cols), or a callable that makes them on first
+        # use (the GPU executor's views cost microseconds per request, which a
+        # client that only releases never pays)
         self._node, self._elem = node, elem
         self.node_base, self.elem_base = node_base, elem_base
         self._on_release = on_release
+        self._released = False
 
     @property
     def released(self) -> bool:
-        return self._node is None
+        return self._released
 
     def _live(self):
-        if self._node is None:
+        if self._released:
             raise ValueError("result was released")
 
     def node(self):
         self._live()
+        if callable(self._node):
+            self._node = self._node()
         return self._node
 
     def elem(self):
         self._live()
+        if callable(self._elem):
+            self._elem = self._elem()
         return self._elem
 
     def node_csr(self):
@@ -135,8 +143,9 @@ class ResultHandle:
 
     def release(self):
         """Give the result's memory back (idempotent)."""
-        if self._node is None:
+        if self._released:
             return
+        self._released = True
         self._node = self._elem = None
         cb, self._on_release = self._on_release, None
         if cb is not None:
@@ -462,7 +471,8 @@ class GpuExecutor:
             def done(r=r, oset=p["oset"]):
                 on_release(r)
                 self._put_outputs(oset)
-            out.append(ResultHandle((nrp[v0:v0 + nv + 1], ncol[a:bb]), (erp[v0:v0 + nv + 1], ecol[c:d]), a, c, done))
+            out.append(ResultHandle(lambda v0=v0, nv=nv, a=a, bb=bb: (nrp[v0:v0 + nv + 1], ncol[a:bb]),
+                                    lambda v0=v0, nv=nv, c=c, d=d: (erp[v0:v0 + nv + 1], ecol[c:d]), a, c, done))
         return out
 
     def results(self, batch: BatchHandle):
