@@ -224,6 +224,8 @@ bool plan_chunked(int64_t n_elem, int32_t etype, int32_t n_vert, const Opts& o, 
         off += align_up((size_t)er.long_cap * sizeof(int32_t));
         er.off_deg = off;
         off += align_up(((size_t)cap + 1) * sizeof(int32_t));
+        er.off_soff = off;
+        off += align_up(((size_t)cap + 1) * sizeof(int16_t));
         er.temp_bytes = (size_t)er.slots * (size_t)cap * sizeof(int32_t);
         if (er.temp_bytes <= keys_end - p->off_keys0) {  // the keys are dead once a range's rows are written
             er.off_temp = p->off_keys0;

@@ -23,6 +23,8 @@ size_t plan_erows(int64_t n_entries, int slots, int32_t n_vert, size_t off, size
     off += align_up((size_t)p->long_cap * sizeof(int32_t));
     p->off_deg = off;
     off += align_up(((size_t)n_vert + 1) * sizeof(int32_t));
+    p->off_soff = off;
+    off += align_up(((size_t)n_vert + 1) * sizeof(int16_t));
     p->temp_bytes = (size_t)slots * (size_t)n_entries * sizeof(int32_t);
     if (p->temp_bytes <= alias_bytes) {
         p->off_temp = alias_off;  // dead by the time the stage runs
@@ -37,8 +39,9 @@ ErowsBufs erows_bufs(const ErowsPlan& er, char* ws, uint32_t* err, uint32_t* tic
     uint32_t* hdr = (uint32_t*)ws;
     return ErowsBufs{(int32_t*)(ws + er.off_tf),   (int32_t*)(ws + er.off_tc),   (int32_t*)(ws + er.off_list),
                      er.long_cap,
-                     hdr + HDR_LONG_COUNT,          (int32_t*)(ws + er.off_deg),  (int32_t*)(ws + er.off_temp),
-                     (uint64_t*)(ws + er.off_lb),   ticket,                       err};
+                     hdr + HDR_LONG_COUNT,          (int32_t*)(ws + er.off_deg),  (int16_t*)(ws + er.off_soff),
+                     (int32_t*)(ws + er.off_temp),  (uint64_t*)(ws + er.off_lb),  ticket,
+                     err};
 }
 
 hipError_t run_erows_uniform(int32_t etype, const ErowsPlan& er, const int32_t* conn, int64_t n_elem,

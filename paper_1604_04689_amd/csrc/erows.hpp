@@ -408,7 +408,8 @@ __global__ __launch_bounds__(ER_BLOCK) void erows_long_kernel(Acc acc, const int
                                                              int64_t q_bound, int64_t ecap,
                                                              const int32_t* __restrict__ long_list,
                                                              int64_t long_cap, const uint32_t* long_count,
-                                                             int32_t* __restrict__ ldeg, int32_t* temp,
+                                                             int32_t* __restrict__ ldeg,
+                                                             int16_t* __restrict__ soff, int32_t* temp,
                                                              uint32_t* err) {
     constexpr int S = Acc::S;
     __shared__ int32_t s[LONG_LDS];
@@ -434,7 +435,10 @@ __global__ __launch_bounds__(ER_BLOCK) void erows_long_kernel(Acc acc, const int
         __threadfence_block();
         __syncthreads();
         const int64_t cnt = block_sort_unique(x, (int64_t)S * len, s, s_wcnt);
-        if (tid == 0) ldeg[v] = (int32_t)cnt;
+        if (tid == 0) {
+            ldeg[v] = (int32_t)cnt;
+            soff[v] = 0;
+        }
         __syncthreads();
     }
     if (bad) set_error(err, ERR_INTERNAL);
@@ -460,8 +464,8 @@ __device__ __forceinline__ void erows_tile_body(const Acc& acc, const int32_t* _
                                                 const int32_t* __restrict__ ecols, int32_t n_vert, int64_t q_bound,
                                                 int64_t ecap, const int32_t* __restrict__ tile_first,
                                                 const int32_t* __restrict__ tile_ctx, int32_t* __restrict__ cnt,
-                                                int32_t* __restrict__ stage, int stage_slots, uint32_t* err,
-                                                int64_t t) {
+                                                int16_t* __restrict__ soff, int32_t* __restrict__ stage,
+                                                int stage_slots, uint32_t* err, int64_t t) {
     constexpr int S = Acc::S;
     constexpr int CAP = ER_SPAN * S;
     constexpr int WAVES = ER_BLOCK / WAVE;
@@ -530,7 +534,10 @@ __device__ __forceinline__ void erows_tile_body(const Acc& acc, const int32_t* _
             bad = true;
             len = 0;
         }
-        if (v < v_end && len == 0) cnt[v] = 0;
+        if (v < v_end && len == 0) {
+            cnt[v] = 0;
+            soff[v] = 0;
+        }
         const bool is_short = len > 0 && len <= ER_ROW_MAX;
         uint32_t total;
         const uint32_t k = (uint32_t)nrows + block_exclusive_sum<ER_BLOCK>((uint32_t)is_short, s_tmp, &total);
@@ -549,6 +556,12 @@ __device__ __forceinline__ void erows_tile_body(const Acc& acc, const int32_t* _
         nrows = ER_TILE;
     }
     __syncthreads();
+    // the short rows' values go to the stage back to back from the first
+    // short row's slots on (the gather then reads them densely), unless a
+    // long row lies between two of them (its values take its own slots)
+    bool gap = false;
+    for (int k = 1 + tid; k < nrows; k += ER_BLOCK) gap |= s_ra[k - 1] + s_rlen[k - 1] != s_ra[k];
+    const bool dense = !__syncthreads_or(gap);
 
     // ---- the row of every position (the last short row starting at or
     // before it), then the ids not gathered yet, then the candidates
@@ -669,13 +682,20 @@ __device__ __forceinline__ void erows_tile_body(const Acc& acc, const int32_t* _
 
     // ---- counts of the short rows, and each kept value to its place: the
     // number of its row's distinct values below it
-    for (int k = tid; k < nrows; k += ER_BLOCK) cnt[s_rv[k]] = tmax<int32_t>(s_rde[k] - s_rds[k], 0);
+    // (dense: row k's values at P * (base + s_ra[0]) + s_rds[k], P =
+    // stage_slots; soff[v] = that minus P * (row start), the gather's offset;
+    // the rows' values fit the rows' own slots, S <= P per entry)
+    for (int k = tid; k < nrows; k += ER_BLOCK) {
+        cnt[s_rv[k]] = tmax<int32_t>(s_rde[k] - s_rds[k], 0);
+        soff[s_rv[k]] = dense ? (int16_t)(s_rds[k] - stage_slots * (s_ra[k] - s_ra[0])) : (int16_t)0;
+    }
 #pragma unroll
     for (int i = 0; i < ER_EPT; ++i) {
         if (rowk[i] < 0) continue;
         const int k = rowk[i];
         const int ds = s_rds[k], de = s_rde[k];
-        int32_t* row = stage + (int64_t)stage_slots * (base + s_ra[k]);
+        int32_t* row = dense ? stage + (int64_t)stage_slots * (base + s_ra[0]) + ds
+                             : stage + (int64_t)stage_slots * (base + s_ra[k]);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             if (!((kept >> (i * S + s)) & 1ull)) continue;
@@ -698,9 +718,9 @@ __global__ __launch_bounds__(ER_BLOCK) void erows_tile_kernel(Acc acc, const int
                                                              int64_t q_bound, int64_t ecap,
                                                              const int32_t* __restrict__ tile_first,
                                                              const int32_t* __restrict__ tile_ctx,
-                                                             int32_t* __restrict__ cnt, int32_t* __restrict__ stage,
-                                                             uint32_t* err) {
-    erows_tile_body(acc, erp, ecols, n_vert, q_bound, ecap, tile_first, tile_ctx, cnt, stage, Acc::S, err,
+                                                             int32_t* __restrict__ cnt, int16_t* __restrict__ soff,
+                                                             int32_t* __restrict__ stage, uint32_t* err) {
+    erows_tile_body(acc, erp, ecols, n_vert, q_bound, ecap, tile_first, tile_ctx, cnt, soff, stage, Acc::S, err,
                     (int64_t)blockIdx.x);
 }
 
@@ -712,27 +732,29 @@ __global__ __launch_bounds__(ER_BLOCK) void erows_tile_list_kernel(Acc acc, cons
                                                                   const int32_t* __restrict__ tile_first,
                                                                   const int32_t* __restrict__ tile_ctx,
                                                                   int32_t* __restrict__ cnt,
+                                                                  int16_t* __restrict__ soff,
                                                                   int32_t* __restrict__ stage, int stage_slots,
                                                                   uint32_t* err, const int32_t* __restrict__ list,
                                                                   const uint32_t* count) {
     const uint32_t n = *count;
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-        erows_tile_body(acc, erp, ecols, n_vert, q_bound, ecap, tile_first, tile_ctx, cnt, stage, stage_slots, err,
-                        (int64_t)list[i]);
+        erows_tile_body(acc, erp, ecols, n_vert, q_bound, ecap, tile_first, tile_ctx, cnt, soff, stage, stage_slots,
+                        err, (int64_t)list[i]);
         __syncthreads();  // the next tile rewrites the LDS tables
     }
 }
 
-// cols[row_ptr[v] + i] = stage[S * erp[v] + i] for i < cnt[v] = row_ptr[v+1] -
-// row_ptr[v].  A block covers EG_BLOCK consecutive vertices; their output
-// range is contiguous, so consecutive threads take consecutive outputs
+// cols[row_ptr[v] + i] = stage[S * erp[v] + soff[v] + i] for i < cnt[v] =
+// row_ptr[v+1] - row_ptr[v].  A block covers EG_BLOCK consecutive vertices;
+// their output range is contiguous, so consecutive threads take consecutive outputs
 // (coalesced writes), each finding its row by a fixed-step binary search over
 // the block's row starts in LDS, four outputs per thread at a time.
 constexpr int EG_BLOCK = 256;
 constexpr int EG_UNROLL = 4;
 
 static __global__ __launch_bounds__(EG_BLOCK) void erows_gather_kernel(const int32_t* __restrict__ row_ptr,
-                                                                      const int32_t* __restrict__ erp, int slots,
+                                                                      const int32_t* __restrict__ erp,
+                                                                      const int16_t* __restrict__ soff, int slots,
                                                                       const int32_t* __restrict__ stage,
                                                                       int32_t n_vert, int64_t q_bound,
                                                                       int32_t* __restrict__ cols, int64_t cols_cap,
@@ -746,12 +768,14 @@ static __global__ __launch_bounds__(EG_BLOCK) void erows_gather_kernel(const int
     if (tid < nv) {
         const int32_t a = erp[v0 + tid], b = erp[v0 + tid + 1];
         const int32_t r0 = row_ptr[v0 + tid], r1 = row_ptr[v0 + tid + 1];
-        // a row holds at most its candidate slots, inside the element CSR
+        const int32_t so = soff[v0 + tid];
+        // a row holds at most its candidate slots, inside the element CSR;
+        // its values start at or before its own slots (packed rows move down)
         const bool ok = a >= 0 && b >= a && (int64_t)b <= q_bound && r1 - r0 >= 0 &&
-                        (int64_t)(r1 - r0) <= (int64_t)slots * (b - a);
+                        (int64_t)(r1 - r0) <= (int64_t)slots * (b - a) && so <= 0 && (int64_t)slots * a + so >= 0;
         bad |= !ok;
         s_start[tid] = r0;
-        s_src[tid] = ok ? (int64_t)slots * a : -1;
+        s_src[tid] = ok ? (int64_t)slots * a + so : -1;
     }
     if (tid == 0) s_start[nv] = row_ptr[v0 + nv];
     for (int i = nv + 1 + tid; i <= EG_BLOCK; i += EG_BLOCK) s_start[i] = INT32_MAX;  // past the last row
@@ -785,10 +809,11 @@ static __global__ __launch_bounds__(EG_BLOCK) void erows_gather_kernel(const int
 }
 
 // Buffers of the stage (inside the workspace): tile_first and tile_ctx
-// (n_tiles_bound + 1 ints each), the long-row list and its counter (zero on entry), cnt (n_vert + 1
-// ints: each row's distinct count, then the scan's input), stage (S *
-// q_bound ints, free memory: it may alias dead buffers), the scan's look-back
-// words (zero on entry) and ticket.
+// (n_tiles_bound + 1 ints each), the long-row list and its counter (zero on
+// entry), cnt (n_vert + 1 ints: each row's distinct count, then the scan's
+// input), soff (n_vert + 1 int16: where each row's values start in the stage,
+// relative to its own slots), stage (S * q_bound ints, free memory: it may
+// alias dead buffers), the scan's look-back words (zero on entry) and ticket.
 struct ErowsBufs {
     int32_t* tile_first;
     int32_t* tile_ctx;
@@ -796,6 +821,7 @@ struct ErowsBufs {
     int64_t long_cap;
     uint32_t* long_count;
     int32_t* cnt;
+    int16_t* soff;  // per row: where its values start in the stage, relative to stage_slots * (row start)
     int32_t* stage;
     uint64_t* scan_lb;
     uint32_t* scan_ticket;
@@ -827,13 +853,13 @@ hipError_t launch_erows(const char* tag, const Acc& acc, const int32_t* erp, con
         snprintf(name, sizeof name, "%s_erows_long", tag);
         e = launch(name, erows_long_kernel<Acc>, dim3(ER_LONG_GRID), dim3(ER_BLOCK), s, acc, erp, ecols, n_vert,
                    q_bound, ecap, (const int32_t*)b.long_list, erows_long_cap(q_bound), (const uint32_t*)b.long_count,
-                   b.cnt, b.stage, b.err);
+                   b.cnt, b.soff, b.stage, b.err);
     }
     if (e == hipSuccess) {
         snprintf(name, sizeof name, "%s_erows", tag);
         e = launch(name, erows_tile_kernel<Acc>, dim3((unsigned)n_tiles), dim3(ER_BLOCK), s, acc, erp, ecols,
-                   n_vert, q_bound, ecap, (const int32_t*)b.tile_first, (const int32_t*)b.tile_ctx, b.cnt, b.stage,
-                   b.err);
+                   n_vert, q_bound, ecap, (const int32_t*)b.tile_first, (const int32_t*)b.tile_ctx, b.cnt, b.soff,
+                   b.stage, b.err);
     }
     if (e == hipSuccess && n_vert == 0) e = fill_i32(row_ptr, 1, 0, s);
     if (e == hipSuccess) {
@@ -844,8 +870,8 @@ hipError_t launch_erows(const char* tag, const Acc& acc, const int32_t* erp, con
     if (e == hipSuccess) {
         snprintf(name, sizeof name, "%s_erows_gather", tag);
         e = launch(name, erows_gather_kernel, dim3((unsigned)ceil_div((int64_t)n_vert, EG_BLOCK)), dim3(EG_BLOCK), s,
-                   (const int32_t*)row_ptr, erp, Acc::S, (const int32_t*)b.stage, n_vert, q_bound, cols, cols_cap,
-                   b.err);
+                   (const int32_t*)row_ptr, erp, (const int16_t*)b.soff, Acc::S, (const int32_t*)b.stage, n_vert,
+                   q_bound, cols, cols_cap, b.err);
     }
     return e;
 }
@@ -920,7 +946,7 @@ inline hipError_t launch_erows_batch(const char* tag, const int32_t* conn, const
         snprintf(name, sizeof name, "%s_erows_long", tag);
         e = launch(name, erows_long_kernel<BatchRows>, dim3(ER_LONG_GRID), dim3(ER_BLOCK), s, any, erp, ecols, n_vert,
                    q_bound, ecap, (const int32_t*)b.long_list, erows_long_cap(q_bound), (const uint32_t*)b.long_count,
-                   b.cnt, b.stage, b.err);
+                   b.cnt, b.soff, b.stage, b.err);
     }
     if (e == hipSuccess) {
         snprintf(name, sizeof name, "%s_erows_classify", tag);
@@ -932,8 +958,8 @@ inline hipError_t launch_erows_batch(const char* tag, const int32_t* conn, const
     const dim3 grid((unsigned)tmin<int64_t>(n_tiles, ER_LIST_GRID));
     auto run_list = [&](auto acc, int k) {
         return launch(name, erows_tile_list_kernel<decltype(acc)>, grid, dim3(ER_BLOCK), s, acc, erp, ecols, n_vert,
-                      q_bound, ecap, (const int32_t*)b.tile_first, (const int32_t*)b.tile_ctx, b.cnt, b.stage,
-                      (int)BatchRows::S, b.err, (const int32_t*)(lists + k * stride), (const uint32_t*)(counts + k));
+                      q_bound, ecap, (const int32_t*)b.tile_first, (const int32_t*)b.tile_ctx, b.cnt, b.soff,
+                      b.stage, (int)BatchRows::S, b.err, (const int32_t*)(lists + k * stride), (const uint32_t*)(counts + k));
     };
     for (int k = 0; k < N_ELEM_TYPES && e == hipSuccess; ++k)
         e = with_type(k, [&](auto et) {
@@ -951,8 +977,8 @@ inline hipError_t launch_erows_batch(const char* tag, const int32_t* conn, const
     if (e == hipSuccess) {
         snprintf(name, sizeof name, "%s_erows_gather", tag);
         e = launch(name, erows_gather_kernel, dim3((unsigned)ceil_div((int64_t)n_vert, EG_BLOCK)), dim3(EG_BLOCK), s,
-                   (const int32_t*)row_ptr, erp, (int)BatchRows::S, (const int32_t*)b.stage, n_vert, q_bound, cols,
-                   cols_cap, b.err);
+                   (const int32_t*)row_ptr, erp, (const int16_t*)b.soff, (int)BatchRows::S, (const int32_t*)b.stage,
+                   n_vert, q_bound, cols, cols_cap, b.err);
     }
     return e;
 }

@@ -92,6 +92,7 @@ struct ErowsPlan {
     size_t off_tc = 0;        // accessor context (mesh in a batch) of that vertex
     size_t off_list = 0;      // long rows
     size_t off_deg = 0;       // distinct count of every row (n_vert + 1 ints)
+    size_t off_soff = 0;      // stage offset of every row (n_vert + 1 int16)
     size_t off_temp = 0;      // staged values: S * n_entries ints
     size_t temp_bytes = 0;
 };
