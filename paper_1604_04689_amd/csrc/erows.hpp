@@ -8,9 +8,10 @@
 // row's candidates (the edge-neighbors of v inside each of its elements,
 // gathered from the connectivity) are deduplicated and ordered in LDS, which
 // gives the ascending, duplicate-free rows of our reading of the serial
-// solution (Sec. 3.2.2).  Every tile works alone: each row's distinct values
-// are staged at the row's own candidate slots with its count, the counts are
-// scanned into row_ptr, and the staged values gathered into cols.
+// solution (Sec. 3.2.2).  Every tile works alone: its rows' distinct values
+// are staged within the rows' own candidate slots (packed back to back) with
+// each row's count and offset, the counts are scanned into row_ptr, and the
+// staged values gathered into cols.
 //
 //   erows_prep    per vertex: the first vertex whose element row starts in
 //                 each tile of ER_TILE element-CSR entries; rows longer than
@@ -20,7 +21,9 @@
 //   erows_tile    one block per tile: the rows that start in the tile,
 //                 candidates into LDS hash tables spanning each row's own
 //                 candidate slots, distinct values compacted and ordered by
-//                 counting, written to the stage with the row counts
+//                 counting, written to the stage with the row counts and
+//                 offsets (a batch: tiles sorted into lists by element type
+//                 first, erows_classify, each list with its type's access)
 //   erows_scan    counts -> row_ptr (decoupled look-back scan)
 //   erows_gather  stage -> cols, coalesced
 #pragma once
