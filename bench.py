@@ -49,6 +49,13 @@ WORKLOADS = {
 }
 
 SERVE_RHO = (0.5, 0.8, 0.95)
+# Table 1 of the paper, per row: vertices and triangles of the scanned mesh,
+# and its GPU times for the node and the element relation (ms, on a GT640).
+# A coin-flip triangle grid of n x n vertices has about the same sizes
+# (n^2 vertices, 2 (n-1)^2 triangles); those grids stand in for the meshes.
+PAPER_TABLE1 = ((417, "172k", "346k", 50.0, 22.1), (488, "237k", "474k", 66.7, 29.4),
+                (573, "327k", "655k", 89.1, 38.3), (661, "437k", "871k", 112.7, 48.5),
+                (739, "543k", "1088k", 138.5, 60.6), (940, "882k", "1765k", 221.3, 93.3))
 # pair budgets of the bounded-memory build timed on the main workload
 CHUNK_BUDGETS = (1 << 20, 1 << 23)
 
@@ -357,6 +364,37 @@ def run_workload(name, steps, warmup, torch, nb, compare_sorts=True, e2e=True, c
     return m, res
 
 
+def run_paper_scale(torch, nb, steps=20):
+    """Grids sized like the rows of the paper's Table 1: node relation,
+    element relation and both, each alone per step (context only: other
+    meshes, other hardware)."""
+    from paper_1604_04689_amd import meshgen as mg
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    rows = []
+    for i, (n, pv, pf, p_node, p_elem) in enumerate(PAPER_TABLE1):
+        m = mg.tri_grid(n, "coin", mg.BASE_SEED + 100 + i)
+        conn = torch.as_tensor(m.conn).to(dev)
+        t = {}
+        for kind in ("node", "elem", "both"):
+            b = nb.NeighborBuild(kind, m.n_elem, m.etype, m.n_vert, dev, options="tuned")
+            for _ in range(3):
+                b.launch(conn, stream)
+            b.check(stream)
+            t[kind] = _sync_time(torch, lambda: b.launch(conn, stream), steps) * 1e3
+            del b
+        rows.append({"table1_row": i + 1, "paper_vertices": pv, "paper_triangles": pf, "grid_side": n,
+                     "n_vert": m.n_vert, "n_elem": m.n_elem, "node_ms": t["node"], "elem_ms": t["elem"],
+                     "both_ms": t["both"], "paper_gpu_node_ms": p_node, "paper_gpu_elem_ms": p_elem,
+                     "node_speedup_vs_paper_gpu": p_node / t["node"], "elem_speedup_vs_paper_gpu": p_elem / t["elem"]})
+        log(f"[bench] Table 1 row {i + 1} size ({m.n_elem} tris): node {t['node']:.3f} ms, elem {t['elem']:.3f} ms, "
+            f"both {t['both']:.3f} ms (paper GT640: {p_node} / {p_elem} ms)")
+        del conn
+    torch.cuda.empty_cache()
+    return {"note": "coin-flip triangle grids sized like the rows of the paper's Table 1 (its scanned meshes are "
+                    "not used); the paper's times are on a GT640 with Thrust (context only)", "rows": rows}
+
+
 def run_tiny(torch, nb, steps=200):
     """The 64 x 64 grid: microseconds per step, eager and graph replay."""
     m = make_mesh("tri64")
@@ -556,6 +594,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-mesh batch and the serving stream")
     ap.add_argument("--no-compare", action="store_true", help="skip the node-algorithm comparison")
+    ap.add_argument("--no-paper-scale", action="store_true", help="skip the grids sized like the paper's Table 1")
     ap.add_argument("--serve-requests", type=int, default=5000)
     ap.add_argument("--serve-warmup", type=int, default=500)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -584,6 +623,8 @@ def main():
     for w in [x for x in args.also.split(",") if x and x != args.workload]:
         _, others[w] = run_workload(w, args.steps, args.warmup, torch, nb, compare_sorts=not args.no_compare)
     others["tri64"] = run_tiny(torch, nb)
+    if not args.no_paper_scale:
+        others["paper_scale"] = run_paper_scale(torch, nb)
 
     if not args.no_batch:
         meshes, others["batch512"] = run_batched(max(3, args.steps // 4), 1, torch, nb)
