@@ -196,9 +196,9 @@ def main():
         meshes = [mg.tri_grid(256, "coin", 1), mg.kuhn_tet_grid(16, 2), mg.hex_grid(16, 3)]
         batches = [("batch64", [s.build() for s in mg.batch_specs(64, seed=7)])]
     else:
-        meshes = [mg.tri64(), mg.tri_grid(256, "coin", 1), mg.tri_grid(1024, "coin", 2), mg.tri2048(),
-                  mg.kuhn_tet_grid(24, 3), mg.kuhn_tet_grid(48, 4), mg.kuhn96(),
-                  mg.hex_grid(24, 5), mg.hex_grid(64, 6)]
+        meshes = [mg.tri64(), mg.tri_grid(256, "coin", 1), mg.tri_grid(512, "coin", 7), mg.tri_grid(1024, "coin", 2),
+                  mg.tri2048(), mg.kuhn_tet_grid(24, 3), mg.kuhn_tet_grid(34, 8), mg.kuhn_tet_grid(48, 4), mg.kuhn96(),
+                  mg.hex_grid(24, 5), mg.hex_grid(40, 9), mg.hex_grid(64, 6)]
         batches = [("batch64", [s.build() for s in mg.batch_specs(64, seed=7)]),
                    ("batch512", [s.build() for s in mg.batch_specs()])]
     table = tune(meshes, batches=batches)
