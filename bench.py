@@ -144,16 +144,24 @@ def _include_closure(path):
     return sorted(seen)
 
 
+def _code_only(text):
+    """Source text without comments and blank space (a comment changes no
+    kernel)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def source_hash(kernel="node_erows"):
-    """Hash of the sources the kernel is built from (its launching unit and
-    every header it includes): a traffic record taken on other source is
-    stale."""
+    """Hash of the code the kernel is built from (its launching unit and
+    every header it includes, comments left out): a traffic record taken on
+    other code is stale."""
     h = hashlib.sha256()
     unit = os.path.join(ROOT, "paper_1604_04689_amd", "csrc", KERNEL_UNITS[kernel])
     for f in _include_closure(unit):
         h.update(os.path.relpath(f, ROOT).encode())
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f) as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -143,11 +143,13 @@ typedef struct {
  * slot.  Results are identical.
  * Applies to mesh_node_neighbors, mesh_elem_neighbors, mesh_neighbors (and
  * their queries and mesh_neighbors_noalloc) under the ELEM_ROWS node
- * algorithm with 8-bit digits; other entry points, node algorithms or
- * digit_bits = 11 return MESH_ERR_INVALID_ARG, as does chunk_keys below
- * 4096 or below the vertices of one bin (2^(bits of n_vert - 1) / 2^11).  A
- * bin of more than chunk_keys pairs returns MESH_ERR_CHUNK (synchronously,
- * after the histogram; the outputs are then unspecified). */
+ * algorithm (mesh_elem_neighbors takes any node_sort) with 8-bit digits;
+ * other entry points (batches, mixed meshes, graph captures), other node
+ * algorithms or digit_bits = 11 return MESH_ERR_INVALID_ARG, as does
+ * chunk_keys below 4096 or below the vertices of one bin
+ * (2^(bits of n_vert - 1) / 2^11).  A bin of more than chunk_keys pairs
+ * returns MESH_ERR_CHUNK (synchronously, after the histogram; the outputs
+ * are then unspecified). */
 
 /* Options with every field set to -1 (the library defaults). */
 mesh_options mesh_default_options(void);
