@@ -239,7 +239,10 @@ mesh_status mesh_neighbors(const int32_t* conn, int64_t n_elem, int32_t etype, i
  * device looks up that device's copy of the array, with the device current.
  *   - A mesh whose workspace (mesh_neighbors_query with the same options)
  *     exceeds MESH_NOALLOC_SCRATCH_BYTES is refused with
- *     MESH_ERR_SCRATCH_LIMIT before anything is launched.
+ *     MESH_ERR_SCRATCH_LIMIT before anything is launched.  Under a pair
+ *     budget (mesh_options.chunk_keys) the workspace no longer grows with
+ *     the mesh, so much larger meshes fit; such a call waits on its stream
+ *     once and so cannot be captured into a graph.
  *   - Every call on one GPU shares that GPU's array, which keeps the last
  *     call's contents (each call sets everything that must start at a fixed
  *     value itself).  Calls that overlap on one GPU (other streams, other
