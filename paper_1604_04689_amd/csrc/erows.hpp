@@ -50,6 +50,7 @@ constexpr int ER_PREP_BLOCK = 256;
 constexpr uint32_t CAND_NONE = SLOT_EMPTY;
 constexpr int TK_EROWS = 12;  // ticket slot of erows_tile in the workspace header
 static_assert(ER_SPAN % ER_BLOCK == 0, "whole positions per thread");
+static_assert(ER_TILE % 32 == 0 && ER_TILE / 32 <= WAVE, "row-start bitmap words, scanned by one wave");
 static_assert(ER_BLOCK == LONG_BLOCK, "long rows share block_sort_unique");
 
 // The edge-neighbors of vertex v inside one element with ids[0 .. npe) and
@@ -487,12 +488,16 @@ __device__ __forceinline__ void erows_tile_body(const Acc& acc, const int32_t* _
     __shared__ int32_t s_rctx[Acc::kCtx ? ER_TILE : 1];
     __shared__ uint32_t s_wtot[ER_EPT][WAVES];
     __shared__ uint32_t s_tmp[WAVES];
+    // row starts as a bitmap: bit j of word w (.x) set where a short row
+    // starts at entry 32w + j; .y the short rows starting in earlier words
+    __shared__ uint2 s_rmap[ER_TILE / 32];
 
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
     const int64_t q = erow_total(erp, n_vert, q_bound);
     const int64_t n_tiles = q / ER_TILE + 1;
     if (t >= n_tiles) return;  // owns nothing
     for (int i = tid; i < CAP + 4; i += ER_BLOCK) s_tab[i] = SLOT_EMPTY;
+    for (int i = tid; i < ER_TILE / 32; i += ER_BLOCK) s_rmap[i].x = 0;
     const int64_t base = t * ER_TILE;
     const bool last_tile = t == n_tiles - 1;
     const int64_t qe = tmin<int64_t>(q, ecap);
@@ -548,6 +553,7 @@ __device__ __forceinline__ void erows_tile_body(const Acc& acc, const int32_t* _
             s_ra[k] = (int16_t)(a - base);
             s_rlen[k] = (int16_t)len;
             s_rv[k] = v;
+            atomicOr(&s_rmap[(a - base) >> 5].x, 1u << ((a - base) & 31));
             s_rds[k] = 0;
             s_rde[k] = 0;
             if constexpr (Acc::kCtx) s_rctx[k] = acc.ctx_from(ctx0, v);
@@ -559,6 +565,11 @@ __device__ __forceinline__ void erows_tile_body(const Acc& acc, const int32_t* _
         nrows = ER_TILE;
     }
     __syncthreads();
+    if (tid < WAVE) {
+        const uint32_t c = lane < ER_TILE / 32 ? (uint32_t)__popc(s_rmap[lane].x) : 0u;
+        const uint32_t inc = wave_inclusive_sum(c);
+        if (lane < ER_TILE / 32) s_rmap[lane].y = inc - c;
+    }
     // the short rows' values go to the stage back to back from the first
     // short row's slots on (the gather then reads them densely), unless a
     // long row lies between two of them (its values take its own slots)
@@ -567,19 +578,20 @@ __device__ __forceinline__ void erows_tile_body(const Acc& acc, const int32_t* _
     const bool dense = !__syncthreads_or(gap);
 
     // ---- the row of every position (the last short row starting at or
-    // before it), then the ids not gathered yet, then the candidates
+    // before it: the row starts counted in the bitmap up to it; past the
+    // tile, the last row), then the ids not gathered yet, then the candidates
     uint32_t cand[ER_EPT][S];
     int32_t rowk[ER_EPT];
 #pragma unroll
     for (int i = 0; i < ER_EPT; ++i) {
         const int r = i * ER_BLOCK + tid;
-        int lo = 0, hi = nrows - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_ra[mid] <= r) lo = mid;
-            else hi = mid - 1;
+        int lo = nrows - 1;
+        if (r < ER_TILE) {
+            const uint2 m = s_rmap[r >> 5];
+            lo = tmin<int>((int)m.y + __popc(m.x & (0xffffffffu >> (31 - (r & 31)))) - 1, lo);
         }
-        const bool in = nrows > 0 && s_ra[lo] <= r && r < s_ra[lo] + s_rlen[lo] && r < in_end;
+        const int lk = lo < 0 ? 0 : lo;
+        const bool in = lo >= 0 && s_ra[lk] <= r && r < s_ra[lk] + s_rlen[lk] && r < in_end;
         rowk[i] = in ? lo : -1;
     }
     int32_t rv[ER_EPT];
