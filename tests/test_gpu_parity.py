@@ -114,6 +114,52 @@ def test_fans_long_element_rows(oracle_mod, opts):
         check_both(oracle_mod, conn, 0, n + 2, f"fan{n}", opts)
 
 
+def star_mesh(lengths, etype, n_unused_block, seed):
+    """Stars: hub k lies in lengths[k] elements (triangles (hub, r_i, r_i+1)
+    or tetrahedra (hub, r_i, r_i+1, cap) around a path of fresh rim
+    vertices), so the hubs' element rows have exactly those lengths and the
+    rim and cap rows are short.  Vertex ids are a random subset of a larger
+    range with one block of n_unused_block unused ids in its middle (runs of
+    empty rows), elements shuffled."""
+    rng = np.random.default_rng(seed)
+    elems, nv = [], 0
+    for L in lengths:
+        hub, rim = nv, np.arange(nv + 1, nv + L + 2)
+        nv += L + 2
+        if etype == 0:
+            elems.append(np.stack([np.full(L, hub), rim[:-1], rim[1:]], 1))
+        else:
+            cap = nv
+            nv += 1
+            elems.append(np.stack([np.full(L, hub), rim[:-1], rim[1:], np.full(L, cap)], 1))
+    conn = np.concatenate(elems)
+    n_ids = nv + nv // 4 + n_unused_block
+    lo = rng.choice(n_ids // 2 - n_unused_block // 2, size=nv // 2, replace=False)
+    hi = n_ids // 2 + n_unused_block // 2 + rng.choice(n_ids - n_ids // 2 - n_unused_block // 2, size=nv - nv // 2,
+                                                       replace=False)
+    ids = rng.permutation(np.concatenate([lo, hi]))
+    conn = ids[conn][rng.permutation(conn.shape[0])]
+    return np.ascontiguousarray(conn, dtype=np.int32), int(n_ids)
+
+
+@pytest.mark.parametrize("opts", [None] + NODE_SORTS, ids=["default"] + SORT_IDS)
+@pytest.mark.parametrize("etype", [0, 1])
+def test_node_rows_tile_layouts(oracle_mod, opts, etype):
+    """Element rows of every length class the node stage treats apart, mixed
+    over many tiles of element-CSR entries: short rows of 1 to 60 entries,
+    rows of exactly the longest length kept in LDS (256) and one more,
+    long rows of a few hundred between short ones, and a run of 1500 empty
+    rows inside one tile."""
+    rng = np.random.default_rng(11 + etype)
+    lengths = list(rng.integers(1, 7, size=3000)) + list(rng.integers(7, 61, size=120)) + [256, 257, 255, 300, 600]
+    lengths += list(rng.integers(258, 420, size=6))
+    lengths = [int(x) for x in rng.permutation(np.array(lengths))]
+    conn, n_vert = star_mesh(lengths, etype, 1500, seed=5 + etype)
+    counts = np.bincount(conn.ravel(), minlength=n_vert)
+    assert counts.max() == 600 and (counts == 256).any() and (counts == 257).any()
+    check_both(oracle_mod, conn, etype, n_vert, f"star layouts type {etype}", opts)
+
+
 @pytest.mark.parametrize("opts", NODE_SORTS, ids=SORT_IDS)
 def test_degenerate_and_duplicate_elements(oracle_mod, opts):
     rng = np.random.default_rng(9)
