@@ -450,11 +450,21 @@ typedef struct {
 } mesh_kernel_time;
 
 /* While enabled (a process-wide diagnostics switch that changes no result),
- * every kernel the library launches is bracketed by HIP events recorded by
- * the launch itself on the launch's own stream (hipExtLaunchKernel), on the
- * device current when the events were first created.  Up to 65536 launches
- * are recorded between reads; later ones run untimed.  Always MESH_OK. */
+ * every kernel the library launches (or each one mesh_timing_select names)
+ * is bracketed by HIP events recorded by the launch itself on the launch's
+ * own stream (hipExtLaunchKernel), on the device current when the events
+ * were first created.  Up to 65536 launches are recorded between reads;
+ * later ones run untimed.  Always MESH_OK. */
 mesh_status mesh_timing_enable(int32_t enable);
+
+/* Restricts timing to the launches named in `names`, a comma-separated list
+ * of launch names as mesh_timing_read reports them (e.g. "node_erows");
+ * NULL or "" times every launch again.  Each timed launch costs the stream
+ * a few microseconds (the events it records), so a caller timing a whole
+ * step can time only the kernels it needs.  Process-wide, like
+ * mesh_timing_enable.  MESH_ERR_INVALID_ARG if the list is longer than 1024
+ * characters or holds more than 32 names (the selection is then unchanged). */
+mesh_status mesh_timing_select(const char* names);
 
 /* Waits for the recorded launches to finish, aggregates their durations per
  * kernel name into out[0 .. min(n, max_entries)) and clears the record.

@@ -126,6 +126,7 @@ SIGNATURES = {
     "mesh_radix_launch_shape": (_c_i32, [_c_i32, _c_i32, _c_i64, _P_I32, _P_I32, _P_I32]),
     "mesh_timing_enable": (_c_i32, [_c_i32]),
     "mesh_timing_read": (_c_i32, [ctypes.POINTER(KernelTime), _c_i32]),
+    "mesh_timing_select": (_c_i32, [ctypes.c_char_p]),
 }
 
 
@@ -173,6 +174,13 @@ def radix_launch_shape(shape, digit_bits, n_keys):
 def timing_enable(on: bool = True):
     """Record HIP-event durations of every library kernel launched from now on."""
     lib().mesh_timing_enable(1 if on else 0)
+
+
+def timing_select(names=None):
+    """Time only the launches with these names (an iterable of launch names
+    as timing_read reports them); None or empty: every launch."""
+    s = ",".join(names) if names else ""
+    _check(lib().mesh_timing_select(s.encode()), "mesh_timing_select")
 
 
 def timing_read():

@@ -187,7 +187,7 @@ static mesh_status hip_status(hipError_t e) { return e == hipSuccess ? MESH_OK :
 
 extern "C" {
 
-int32_t mesh_abi_version(void) { return (2 << 16) | 2; }
+int32_t mesh_abi_version(void) { return (2 << 16) | 3; }
 
 mesh_options mesh_default_options(void) {
     mesh_options o;

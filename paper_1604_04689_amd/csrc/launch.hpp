@@ -14,7 +14,9 @@
 
 namespace mnb {
 
-bool timing_enabled();
+// True when launches of kernel `name` are being timed (timing on, and the
+// name selected, or no selection).
+bool timing_enabled(const char* name);
 // While an UntimedScope lives on the calling thread, its launches run untimed
 // (no event is created or taken from the pool).
 struct UntimedScope {
@@ -55,7 +57,7 @@ hipError_t launch_shm(const char* name, void (*kernel)(P...), dim3 grid, dim3 bl
     hipEvent_t e0, e1;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     // launches recorded into a graph run untimed
-    if (timing_enabled() && hipStreamIsCapturing(stream, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone &&
+    if (timing_enabled(name) && hipStreamIsCapturing(stream, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone &&
         timing_begin(&e0, &e1)) {
         hipError_t e = hipExtLaunchKernel((const void*)kernel, grid, block, args, shm, stream, e0, e1, 0);
         if (e == hipSuccess) timing_commit(name, e0, e1);

@@ -3,6 +3,7 @@
 // mesh_timing_read.  Guarded by a mutex; events are created lazily on the
 // device current at the time and reused.
 #include <cstdio>
+#include <cstring>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -25,17 +26,24 @@ std::mutex g_mu;
 bool g_enabled = false;
 std::vector<hipEvent_t> g_pool;
 std::vector<Pending> g_pending;
+std::vector<std::string> g_select;  // launch names timed; empty: all
 thread_local int t_untimed = 0;
+constexpr size_t MAX_SELECT_CHARS = 1024;
+constexpr size_t MAX_SELECT_NAMES = 32;
 
 }  // namespace
 
 UntimedScope::UntimedScope() { ++t_untimed; }
 UntimedScope::~UntimedScope() { --t_untimed; }
 
-bool timing_enabled() {
+bool timing_enabled(const char* name) {
     if (t_untimed) return false;
     std::lock_guard<std::mutex> lk(g_mu);
-    return g_enabled;
+    if (!g_enabled) return false;
+    if (g_select.empty()) return true;
+    for (const std::string& s : g_select)
+        if (s == name) return true;
+    return false;
 }
 
 bool timing_begin(hipEvent_t* start, hipEvent_t* stop) {
@@ -70,6 +78,25 @@ extern "C" {
 mesh_status mesh_timing_enable(int32_t enable) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_enabled = enable != 0;
+    return MESH_OK;
+}
+
+mesh_status mesh_timing_select(const char* names) {
+    std::vector<std::string> sel;
+    if (names) {
+        const size_t n = std::strlen(names);
+        if (n > MAX_SELECT_CHARS) return MESH_ERR_INVALID_ARG;
+        size_t a = 0;
+        while (a <= n) {
+            size_t b = a;
+            while (b < n && names[b] != ',') ++b;
+            if (b > a) sel.emplace_back(names + a, b - a);
+            a = b + 1;
+        }
+        if (sel.size() > MAX_SELECT_NAMES) return MESH_ERR_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_select.swap(sel);
     return MESH_OK;
 }
 

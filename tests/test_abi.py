@@ -45,6 +45,25 @@ def test_version_and_status_strings():
     assert binding.status_string(99) == "unknown status"
 
 
+def test_timing_selection_arguments():
+    """The timing selection is host state only: lists of launch names are
+    taken, too long a list or too many names are refused and leave the
+    selection as it was."""
+    lib = binding.lib()
+    ok, bad = binding.Status.OK, binding.Status.INVALID_ARG
+    assert lib.mesh_timing_select(None) == ok
+    assert lib.mesh_timing_select(b"") == ok
+    assert lib.mesh_timing_select(b"node_erows") == ok
+    assert lib.mesh_timing_select(b"node_erows,elem_radix,,fill") == ok
+    assert lib.mesh_timing_select(b"x" * 1025) == bad
+    assert lib.mesh_timing_select(",".join(f"k{i}" for i in range(33)).encode()) == bad
+    assert lib.mesh_timing_select(",".join(f"k{i}" for i in range(32)).encode()) == ok
+    binding.timing_select(["node_erows", "fill"])
+    binding.timing_select(None)
+    with pytest.raises(binding.MeshError):
+        binding.timing_select(["y" * 1100])
+
+
 TYPES = [(0, 3, 3), (1, 6, 4), (2, 12, 8), (3, 4, 4), (4, 9, 6), (5, 8, 5)]
 
 

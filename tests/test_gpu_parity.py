@@ -238,6 +238,29 @@ def test_deterministic_and_workspace_reuse(opts):
             assert_same(o, outs[0], kind)
 
 
+def test_kernel_timing_selection(oracle_mod):
+    """With timing on and a selection, only the selected launches are timed
+    (and the result is the same as untimed)."""
+    nb = _nb()
+    m = mg.tri_grid(300, "coin", 3)
+    want = oracle_mod.node_neighbors(m.conn, m.etype, m.n_vert)
+    nb.timing_read()
+    try:
+        nb.timing_enable(True)
+        nb.timing_select(["node_erows", "node_erows_gather"])
+        got = gpu_csr("node", m.conn, m.etype, m.n_vert, options={"node_sort": 3})
+        sel = nb.timing_read()
+        nb.timing_select(None)
+        gpu_csr("node", m.conn, m.etype, m.n_vert, options={"node_sort": 3})
+        every = nb.timing_read()
+    finally:
+        nb.timing_enable(False)
+        nb.timing_select(None)
+    assert_same(got, want, "timed")
+    assert set(sel) == {"node_erows", "node_erows_gather"} and sel["node_erows"][0] == 1
+    assert {"node_erows", "node_erows_gather", "node_erows_prep", "node_erows_scan"} <= set(every)
+
+
 def test_side_stream(oracle_mod):
     m = mg.hex_grid(9, 4)
     s = torch.cuda.Stream(DEV)
