@@ -1,7 +1,8 @@
 // Per-kernel timing: a process-wide record of (kernel name, start, stop)
-// event pairs filled by launch() while enabled, and read back by
-// mesh_timing_read.  Guarded by a mutex; events are created lazily on the
-// device current at the time and reused.
+// event pairs filled by launch() while enabled (for every launch, or for the
+// launch names mesh_timing_select lists), and read back by mesh_timing_read.
+// Guarded by a mutex; events are created lazily on the device current at the
+// time and reused.
 #include <cstdio>
 #include <cstring>
 #include <mutex>
