@@ -275,6 +275,7 @@ class GpuExecutor:
         self.slot_state = [None] * n_slots  # each slot's BatchBuild of both relations
         self.arena = Arena(arena_ids)
         self.arena_buf = torch.empty(arena_ids, dtype=torch.int32, device=self.device)
+        self._pad = torch.zeros(self.arena.align, dtype=torch.int32, device=self.device)  # fills alignment gaps
         self.pin = torch.empty(arena_ids, dtype=torch.int32, pin_memory=True)
         self.pin_np = self.pin.numpy()
         self.staging = collections.deque()  # prepared, upload not yet issued, in prepare order
@@ -340,9 +341,30 @@ class GpuExecutor:
         if self.dev_pending:
             self.upload.wait_stream(torch.cuda.current_stream(self.device))  # the tensors' producers
             with torch.cuda.stream(self.upload):
-                for r in self.dev_pending:
-                    off = r.prep[0]
-                    self.arena_buf[off:off + _n_ids(r.conn)].copy_(r.conn.reshape(-1), non_blocking=True)
+                # requests whose arena ranges follow each other go in one
+                # concatenation (one launch instead of one copy each); the
+                # alignment padding between ranges is filled from a zero
+                # buffer and never read
+                run, end = [], None
+                for r in self.dev_pending + [None]:
+                    if r is not None and r.prep[0] == end:
+                        run.append(r)
+                        end += self.arena.used[r.prep[0]]
+                        continue
+                    if len(run) > 1 and all(x.conn.dtype == torch.int32 for x in run):
+                        parts = []
+                        for x in run:
+                            parts.append(x.conn.reshape(-1))
+                            pad = self.arena.used[x.prep[0]] - _n_ids(x.conn)
+                            if pad:
+                                parts.append(self._pad[:pad])
+                        torch.cat(parts, out=self.arena_buf[run[0].prep[0]:end])
+                    else:
+                        for x in run:
+                            off = x.prep[0]
+                            self.arena_buf[off:off + _n_ids(x.conn)].copy_(x.conn.reshape(-1), non_blocking=True)
+                    if r is not None:
+                        run, end = [r], r.prep[0] + self.arena.used[r.prep[0]]
                 ev = torch.cuda.Event()
                 ev.record(self.upload)
             for r in self.dev_pending:
@@ -373,10 +395,13 @@ class GpuExecutor:
         desc = [(r.n_elem, r.etype, r.n_vert) for r in batch.requests]
         offs = []
         self.commit()
+        waited = set()
         for r in batch.requests:
             if r.prep[2] is None:
                 self._flush(until=r)
-            s.wait_event(r.prep[2])
+            if id(r.prep[2]) not in waited:  # requests uploaded together share one event
+                waited.add(id(r.prep[2]))
+                s.wait_event(r.prep[2])
             offs.append(r.prep[0])
         with torch.cuda.stream(s):
             if st is None:

@@ -36,6 +36,35 @@ def test_served_equals_alone(oracle_mod):
     print("served:", s, "batches:", srv.batches, flush=True)
 
 
+def test_served_device_inputs_equal_alone(oracle_mod):
+    """Requests whose connectivity is already a device tensor (copied into
+    the arena on the upload stream, runs of adjacent ranges in one
+    concatenation) give the same results as the oracle."""
+    from paper_1604_04689_amd import serve
+    reqs = make_requests(40, rate=20000.0, seed=13)
+    host = {r.rid: r.conn for r in reqs}
+    for r in reqs:
+        r.conn = torch.as_tensor(r.conn).to("cuda:0")
+    got = {}
+
+    def on_complete(batch, ex):
+        ex.check(batch)
+        for r, res in zip(batch.requests, ex.results(batch)):
+            got[r.rid] = res
+
+    srv = serve.Server(serve.GpuExecutor(3), serve.RealClock(), n_slots=3, budget_bytes=1 << 34, max_batch=8,
+                       on_complete=on_complete)
+    srv.run(reqs)
+    assert len(got) == len(reqs) and srv.batches < len(reqs)
+    for r in reqs:
+        conn = host[r.rid]
+        wn = oracle_mod.node_neighbors(conn, r.etype, r.n_vert)
+        we = oracle_mod.elem_neighbors(conn, r.etype, r.n_vert)
+        (gnr, gnc), (ger, gec) = got[r.rid]
+        assert np.array_equal(gnr, wn[0]) and np.array_equal(gnc, wn[1]), r.rid
+        assert np.array_equal(ger, we[0]) and np.array_equal(gec, we[1]), r.rid
+
+
 def test_served_with_small_arena(oracle_mod):
     """A connectivity arena that holds only two requests at a time: uploads
     wait for batches to release their ranges, results stay exact."""
